@@ -1,0 +1,237 @@
+/*
+ * fc.h -- C ABI of the MI355X finite cell Schwarz-PCG library (libfc).
+ *
+ * The library solves the symmetric positive (semi-)definite systems A x = b
+ * that the finite cell method produces (Jomo et al., arXiv:1809.00828,
+ * Sec. 2.1 Eq. 1 and Sec. 3.1 Eq. 2) by conjugate gradients preconditioned
+ * with the paper's additive Schwarz preconditioner
+ *
+ *     S = sum_B R_B^T (R_B A R_B^T)^+ R_B          (Sec. 3.1, Eq. 6)
+ *
+ * built from element blocks, stabilised pseudo-inverses (Sec. 3.2, Eqs.
+ * 9-11) and the diagonal-scaling fallback of Algorithm 1.
+ *
+ * Conventions shared by every entry point
+ *   - Handles (fc_problem, fc_precond) own their device memory; the caller
+ *     owns every vector buffer passed in.  Vector arguments named *_dev are
+ *     device pointers (e.g. torch.Tensor.data_ptr()) of FP64 values; *_host
+ *     arguments are host pointers.
+ *   - stream is a hipStream_t (NULL = the default stream).  Calls enqueue
+ *     their work on it and return without synchronising, except the set-up
+ *     calls and fc_pcg_solve, which synchronise the stream once before they
+ *     return.
+ *   - Every call returns an fc_status; FC_OK is 0.  No exception or abort
+ *     crosses the ABI.  fc_last_error() returns a thread-local message
+ *     describing the last failure.
+ *   - Unknowns are numbered on the tensor-product lattice: per direction
+ *     g = p*e + L(a) with L(0) = 0, L(1) = p, L(j) = j-1 for local function
+ *     a on cell e; node = g_0 + (pn+1)(g_1 + (pn+1) g_2); unknown =
+ *     ncomp*node + component.  Element-local functions are ordered
+ *     a_0 + (p+1)(a_1 + (p+1) a_2), components fastest.
+ *   - Indices are int32: every supported system has fewer than 2^31
+ *     unknowns and stored matrix blocks.
+ */
+#ifndef FC_H
+#define FC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct fc_problem_s* fc_problem;
+typedef struct fc_precond_s* fc_precond;
+
+typedef enum {
+  FC_OK = 0,
+  FC_E_ARG = 1,          /* invalid argument or inconsistent sizes        */
+  FC_E_NOMEM = 2,        /* a device or host allocation failed            */
+  FC_E_DEVICE = 3,       /* a HIP runtime call failed                     */
+  FC_E_NOTCONV = 4,      /* PCG reached maxit; x holds the last iterate   */
+  FC_E_BREAKDOWN = 5,    /* (p,Ap) <= 0 or (r,z) <= 0 during PCG          */
+  FC_E_NAN = 6,          /* a non-finite value appeared                    */
+  FC_E_UNSUPPORTED = 7   /* a size or option this build does not support */
+} fc_status;
+
+enum { FC_PDE_POISSON = 0, FC_PDE_ELASTICITY = 1 };
+enum { FC_DOMAIN_VOIDS = 0, FC_DOMAIN_INCLUSIONS = 1 };
+
+/*
+ * Problem description (Sec. 2.1, Eq. 1 and Sec. 5.1 problem setup).
+ * The embedding box is [0,1]^dim with n cells per direction and the full
+ * tensor-product integrated Legendre basis of order p.  Shapes are axis-
+ * aligned ellipsoids (centre, semi-axes, dim values each); a point is inside
+ * one when sum(((x-c)/s)^2) <= 1.  The physical domain is the box minus the
+ * shapes (FC_DOMAIN_VOIDS) or their union (FC_DOMAIN_INCLUSIONS); alpha is
+ * the indicator value elsewhere.  Cut cells are integrated on a tree of
+ * depth quad_depth with a (p+1)^dim Gauss rule on every leaf.
+ *   POISSON:    a(u,v) = int alpha (grad u.grad v + u v),
+ *               l(v)   = int alpha f v with
+ *               f(x)   = sum_k mode_amp[k] cos(2 pi mode_k[k].x + mode_phase[k])
+ *   ELASTICITY: a(u,v) = int alpha eps(v):C:eps(u) (E, nu), traction on the
+ *               face x_{dim-1} = 1; clamp_zmin clamps (strongly: rows and
+ *               columns zeroed, diagonal kept, load zeroed) every function
+ *               that is nonzero on x_{dim-1} = 0.
+ * All pointers are host pointers read during fc_setup only.
+ */
+typedef struct {
+  int32_t dim, n, p, pde;
+  double alpha;
+  int32_t quad_depth, domain;
+  int32_t n_shapes;
+  const double* shape_centre;   /* [n_shapes*dim] */
+  const double* shape_semi;     /* [n_shapes*dim] */
+  int32_t n_modes;
+  const double* mode_k;         /* [n_modes*dim]  */
+  const double* mode_amp;       /* [n_modes]      */
+  const double* mode_phase;     /* [n_modes]      */
+  double E, nu;
+  double traction[3];
+  int32_t clamp_zmin;
+} fc_problem_desc;
+
+/* Assemble A (BSR, block = ncomp x ncomp), b, the per-cell volume fraction
+ * eta_T (Sec. 3.2, Eq. 8) and the element blocks on the host, then upload
+ * them.  Errors: FC_E_ARG (bad description), FC_E_UNSUPPORTED (block size
+ * above the supported maximum), FC_E_NOMEM, FC_E_DEVICE. */
+fc_status fc_setup(const fc_problem_desc* desc, void* stream, fc_problem* out);
+
+/* Host-only assembly: run the assembler of fc_setup on the host without
+ * touching a GPU, so the assembled system can be inspected or uploaded
+ * later.  fc_host_system_export copies it out in the layout of
+ * fc_setup_from_matrix (any pointer may be NULL): rowptr[n/bsr_dim+1],
+ * col[nnzb], val[nnzb*bsr_dim^2] (row-major blocks), rhs[n],
+ * elem_dofs[n_el*m], eta[n_el].  fc_setup_from_host uploads it (the host
+ * system stays valid and must still be destroyed).
+ * Errors: as fc_setup; fc_assemble never returns FC_E_DEVICE. */
+typedef struct fc_host_system_s* fc_host_system;
+fc_status fc_assemble(const fc_problem_desc* desc, fc_host_system* out);
+fc_status fc_host_system_info(fc_host_system hs, int64_t* n_dofs, int64_t* nnzb,
+                              int64_t* n_el, int32_t* m, int32_t* bsr_dim);
+fc_status fc_host_system_export(fc_host_system hs, int32_t* rowptr, int32_t* col,
+                                double* val, double* rhs, int32_t* elem_dofs,
+                                double* eta);
+fc_status fc_setup_from_host(fc_host_system hs, void* stream, fc_problem* out);
+void fc_host_system_destroy(fc_host_system hs);
+
+/* Wrap an assembled system given by the caller (host arrays, copied).
+ * BSR with bsr_dim x bsr_dim blocks stored row-major per block:
+ * rowptr[n/bsr_dim+1], col[nnzb] (sorted within each block row),
+ * val[nnzb*bsr_dim^2]; rhs[n]; element blocks elem_dofs[n_el*m] in scalar
+ * unknowns, which must list each node's bsr_dim components consecutively
+ * (unknown = bsr_dim*node + c); eta[n_el] is each block's volume fraction.
+ * Errors: FC_E_ARG, FC_E_UNSUPPORTED, FC_E_NOMEM, FC_E_DEVICE. */
+fc_status fc_setup_from_matrix(int64_t n, int32_t bsr_dim,
+                               const int32_t* rowptr, const int32_t* col,
+                               const double* val, const double* rhs,
+                               int64_t n_el, int32_t m,
+                               const int32_t* elem_dofs, const double* eta,
+                               void* stream, fc_problem* out);
+
+/* Sizes of a problem: unknowns, stored BSR blocks, elements, block size m
+ * (unknowns per element block), BSR block dimension. */
+fc_status fc_problem_info(fc_problem pb, int64_t* n_dofs, int64_t* nnzb,
+                          int64_t* n_el, int32_t* m, int32_t* bsr_dim);
+
+/* Copy b to b_dev (device, n_dofs values) on the stream. */
+fc_status fc_get_rhs(fc_problem pb, double* b_dev, void* stream);
+
+/* Copy eta_T of every element to eta_host (n_el values, synchronous). */
+fc_status fc_get_eta(fc_problem pb, double* eta_host);
+
+/* Copy the matrix to host arrays in the layout of fc_setup_from_matrix
+ * (rowptr[n/bsr_dim+1], col[nnzb], val[nnzb*bsr_dim^2]) and the element
+ * blocks (elem_dofs[n_el*m]); any pointer may be NULL.  Synchronous. */
+fc_status fc_export(fc_problem pb, int32_t* rowptr, int32_t* col, double* val,
+                    int32_t* elem_dofs);
+
+/* y = A x (Sec. 3.1, Eq. 2), x_dev and y_dev device buffers of n_dofs
+ * FP64 values, must not alias. */
+fc_status fc_apply_A(fc_problem pb, const double* x_dev, double* y_dev,
+                     void* stream);
+
+/* Preconditioner options (Algorithm 1 and Sec. 3.2).
+ *   eta_bar    blocks only for elements with eta_T <= eta_bar (1.0: all)
+ *   eps        pseudo-inverse threshold: eigenvalues <= eps*max are dropped
+ *   stabilize  1 = pseudo-inverse of Eqs. 10-11, 0 = plain inverse (S*)
+ *   store_mask FC_STORE_* bits: extra low-precision copies of the block
+ *              inverses (FP64 is always kept) */
+enum { FC_STORE_F64 = 1, FC_STORE_F32 = 2, FC_STORE_BF16 = 4 };
+typedef struct {
+  double eta_bar;
+  double eps;
+  int32_t stabilize;
+  uint32_t store_mask;
+} fc_precond_opts;
+
+/* Algorithm 1 on the device: select blocks, extract A_B = R_B A R_B^T,
+ * compute the stabilised local inverses in FP64, then the diagonal
+ * fallback 1/A_ll for every unknown whose diagonal in S is zero and
+ * A_ll > 0.  opts NULL means {1.0, 1e-13, 1, FC_STORE_F64}.
+ * Errors: FC_E_ARG, FC_E_UNSUPPORTED, FC_E_NOMEM, FC_E_DEVICE. */
+fc_status fc_precond_build(fc_problem pb, const fc_precond_opts* opts,
+                           void* stream, fc_precond* out);
+
+/* Statistics of a built preconditioner: number of blocks, unknowns that
+ * received the diagonal fallback, blocks whose inverse needed the
+ * eigen-decomposition (rather than the certified direct inverse), and
+ * eigenvalues dropped by the threshold summed over all blocks. */
+fc_status fc_precond_info(fc_precond pc, int64_t* n_blocks,
+                          int64_t* n_fallback, int64_t* n_eig_blocks,
+                          int64_t* n_dropped);
+
+/* Copy the FP64 local inverse of block k (m*m values, row-major) to host. */
+fc_status fc_get_block_inverse(fc_precond pc, int64_t k, double* out_host);
+
+/* z = S r (Sec. 3.1, Eq. 6 with the fallback of Algorithm 1); r_dev and
+ * z_dev device buffers of n_dofs FP64 values, must not alias. */
+fc_status fc_apply_M(fc_precond pc, const double* r_dev, double* z_dev,
+                     void* stream);
+
+/* PCG options.
+ *   tol, maxit   stop when the criterion drops to tol (Sec. 5: 1e-10 and
+ *                300000 in the paper's vertebra study) or after maxit
+ *   stop         FC_STOP_PRECOND: ||S r_i|| / ||S b|| (Eq. 12, recurrence
+ *                residual); FC_STOP_RESIDUAL: ||r_i|| / ||b||
+ *   mode         FC_MODE_F64 plain FP64 PCG
+ *   check_every  iterations between host checks of the device stop flag
+ *   history_dev  optional device buffer of maxit+1 doubles receiving the
+ *                relative stop criterion of every iteration, or NULL */
+enum { FC_STOP_PRECOND = 0, FC_STOP_RESIDUAL = 1 };
+enum { FC_MODE_F64 = 0 };
+typedef struct {
+  double tol;
+  int64_t maxit;
+  int32_t stop;
+  int32_t mode;
+  int32_t check_every;
+  double inner_tol;
+  double* history_dev;
+} fc_solve_opts;
+
+typedef struct {
+  int64_t iters;          /* products with A in the (inner) iteration     */
+  int64_t outer_iters;    /* refinement steps (1 for plain PCG)          */
+  double rel_res_true;    /* ||b - A x|| / ||b|| recomputed at the end   */
+  double rel_res_prec;    /* last ||S r_i|| / ||S b||                    */
+  int32_t status;         /* fc_status of the solve                       */
+  double ms_solve;        /* device time of the iteration, milliseconds   */
+} fc_solve_info;
+
+/* Preconditioned CG (Sec. 5, with S of Eq. 6) from x = 0: b_dev and x_dev
+ * are device buffers of n_dofs FP64 values (x_dev receives the solution).
+ * Returns FC_OK, FC_E_NOTCONV (x = last iterate), FC_E_BREAKDOWN or
+ * FC_E_NAN, and fills *info (may be NULL).  Synchronises the stream. */
+fc_status fc_pcg_solve(fc_problem pb, fc_precond pc, const double* b_dev,
+                       double* x_dev, const fc_solve_opts* opts,
+                       fc_solve_info* info, void* stream);
+
+void fc_problem_destroy(fc_problem pb);
+void fc_precond_destroy(fc_precond pc);
+const char* fc_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FC_H */

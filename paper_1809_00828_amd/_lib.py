@@ -1,0 +1,341 @@
+"""ctypes binding of libfc (include/fc.h).
+
+Argument marshalling only: every computation runs in the native library.
+Device buffers are passed as raw pointers; the helpers accept torch tensors
+(FP64, on the GPU) and take their data_ptr(), and streams default to
+torch's current stream.  Loading fails loudly when libfc.so is missing.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libfc.so")
+
+FC_OK, FC_E_ARG, FC_E_NOMEM, FC_E_DEVICE, FC_E_NOTCONV, FC_E_BREAKDOWN, \
+    FC_E_NAN, FC_E_UNSUPPORTED = range(8)
+STATUS_NAMES = {0: "OK", 1: "E_ARG", 2: "E_NOMEM", 3: "E_DEVICE", 4: "E_NOTCONV",
+                5: "E_BREAKDOWN", 6: "E_NAN", 7: "E_UNSUPPORTED"}
+PDE = {"poisson": 0, "elasticity": 1}
+DOMAIN = {"voids": 0, "inclusions": 1}
+STORE_F64, STORE_F32, STORE_BF16 = 1, 2, 4
+STOP = {"precond": 0, "residual": 1}
+MODE = {"f64": 0, "ir_f32": 1, "ir_bf16": 2, "learned": 3}
+
+# every symbol include/fc.h declares
+EXPORTS = [
+    "fc_setup", "fc_assemble", "fc_host_system_info", "fc_host_system_export",
+    "fc_setup_from_host", "fc_host_system_destroy", "fc_setup_from_matrix",
+    "fc_problem_info", "fc_get_rhs", "fc_get_eta", "fc_export", "fc_apply_A",
+    "fc_precond_build", "fc_precond_info", "fc_get_block_inverse", "fc_apply_M",
+    "fc_pcg_solve", "fc_problem_destroy", "fc_precond_destroy", "fc_last_error",
+]
+
+
+class FcError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"libfc {STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+class ProblemDesc(C.Structure):
+    _fields_ = [("dim", C.c_int32), ("n", C.c_int32), ("p", C.c_int32), ("pde", C.c_int32),
+                ("alpha", C.c_double), ("quad_depth", C.c_int32), ("domain", C.c_int32),
+                ("n_shapes", C.c_int32), ("shape_centre", C.POINTER(C.c_double)),
+                ("shape_semi", C.POINTER(C.c_double)), ("n_modes", C.c_int32),
+                ("mode_k", C.POINTER(C.c_double)), ("mode_amp", C.POINTER(C.c_double)),
+                ("mode_phase", C.POINTER(C.c_double)), ("E", C.c_double), ("nu", C.c_double),
+                ("traction", C.c_double * 3), ("clamp_zmin", C.c_int32)]
+
+
+class PrecondOpts(C.Structure):
+    _fields_ = [("eta_bar", C.c_double), ("eps", C.c_double), ("stabilize", C.c_int32),
+                ("store_mask", C.c_uint32)]
+
+
+class SolveOpts(C.Structure):
+    _fields_ = [("tol", C.c_double), ("maxit", C.c_int64), ("stop", C.c_int32),
+                ("mode", C.c_int32), ("check_every", C.c_int32), ("inner_tol", C.c_double),
+                ("history_dev", C.c_void_p)]
+
+
+class SolveInfo(C.Structure):
+    _fields_ = [("iters", C.c_int64), ("outer_iters", C.c_int64),
+                ("rel_res_true", C.c_double), ("rel_res_prec", C.c_double),
+                ("status", C.c_int32), ("ms_solve", C.c_double)]
+
+
+_lib = None
+
+
+def load():
+    """Load libfc.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise FcError(FC_E_UNSUPPORTED,
+                      f"{LIB_PATH} is missing; build it with "
+                      "`python -m paper_1809_00828_amd.build`")
+    lib = C.CDLL(LIB_PATH)
+    vp, i32, i64, dp = C.c_void_p, C.c_int32, C.c_int64, C.c_void_p
+    P = C.POINTER
+    sig = {
+        "fc_setup": [P(ProblemDesc), vp, P(vp)],
+        "fc_assemble": [P(ProblemDesc), P(vp)],
+        "fc_host_system_info": [vp, P(i64), P(i64), P(i64), P(i32), P(i32)],
+        "fc_host_system_export": [vp, vp, vp, vp, vp, vp, vp],
+        "fc_setup_from_host": [vp, vp, P(vp)],
+        "fc_setup_from_matrix": [i64, i32, vp, vp, vp, vp, i64, i32, vp, vp, vp, P(vp)],
+        "fc_problem_info": [vp, P(i64), P(i64), P(i64), P(i32), P(i32)],
+        "fc_get_rhs": [vp, dp, vp],
+        "fc_get_eta": [vp, vp],
+        "fc_export": [vp, vp, vp, vp, vp],
+        "fc_apply_A": [vp, dp, dp, vp],
+        "fc_precond_build": [vp, P(PrecondOpts), vp, P(vp)],
+        "fc_precond_info": [vp, P(i64), P(i64), P(i64), P(i64)],
+        "fc_get_block_inverse": [vp, i64, vp],
+        "fc_apply_M": [vp, dp, dp, vp],
+        "fc_pcg_solve": [vp, vp, dp, dp, P(SolveOpts), P(SolveInfo), vp],
+    }
+    for name, args in sig.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = C.c_int
+    for name in ("fc_problem_destroy", "fc_precond_destroy", "fc_host_system_destroy"):
+        f = getattr(lib, name)
+        f.argtypes = [vp]
+        f.restype = None
+    lib.fc_last_error.argtypes = []
+    lib.fc_last_error.restype = C.c_char_p
+    _lib = lib
+    return lib
+
+
+def _check(status):
+    if status != FC_OK:
+        msg = load().fc_last_error().decode(errors="replace")
+        raise FcError(status, msg)
+
+
+def _dptr(t):
+    """Device pointer of a torch tensor (FP64 contiguous), or an int."""
+    if isinstance(t, int):
+        return t
+    import torch
+    if t.dtype != torch.float64 or not t.is_cuda or not t.is_contiguous():
+        raise FcError(FC_E_ARG, "expected a contiguous FP64 CUDA tensor")
+    return t.data_ptr()
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+def _np_ptr(a):
+    return a.ctypes.data_as(C.c_void_p)
+
+
+def make_desc(d: dict):
+    """ctypes description of a problem dict (see fcgen); returns (desc, keep)
+    where keep holds the arrays the pointers refer to."""
+    dim = d["dim"]
+    centre = np.ascontiguousarray([s["centre"] for s in d["shapes"]], dtype=np.float64).ravel()
+    semi = np.ascontiguousarray([s["semi"] for s in d["shapes"]], dtype=np.float64).ravel()
+    mk = np.ascontiguousarray([m["k"] for m in d["modes"]], dtype=np.float64).ravel()
+    ma = np.ascontiguousarray([m["amp"] for m in d["modes"]], dtype=np.float64)
+    mp = np.ascontiguousarray([m["phase"] for m in d["modes"]], dtype=np.float64)
+    keep = [centre, semi, mk, ma, mp]
+    dp = C.POINTER(C.c_double)
+    desc = ProblemDesc()
+    desc.dim, desc.n, desc.p = dim, d["n"], d["p"]
+    desc.pde = PDE[d["pde"]]
+    desc.alpha = d["alpha"]
+    desc.quad_depth = d["quad_depth"]
+    desc.domain = DOMAIN[d["domain"]]
+    desc.n_shapes = len(d["shapes"])
+    desc.shape_centre = centre.ctypes.data_as(dp)
+    desc.shape_semi = semi.ctypes.data_as(dp)
+    desc.n_modes = len(d["modes"])
+    desc.mode_k = mk.ctypes.data_as(dp)
+    desc.mode_amp = ma.ctypes.data_as(dp)
+    desc.mode_phase = mp.ctypes.data_as(dp)
+    desc.E, desc.nu = d["E"], d["nu"]
+    t = list(d["traction"]) + [0.0] * (3 - len(d["traction"]))
+    desc.traction = (C.c_double * 3)(*t[:3])
+    desc.clamp_zmin = 1 if d.get("clamp_zmin") else 0
+    return desc, keep
+
+
+class HostSystem:
+    """Host-assembled system (fc_assemble); needs no GPU."""
+
+    def __init__(self, desc: dict):
+        lib = load()
+        cd, self._keep = make_desc(desc)
+        h = C.c_void_p()
+        _check(lib.fc_assemble(C.byref(cd), C.byref(h)))
+        self._h = h
+
+    def info(self):
+        lib = load()
+        n, nnzb, nel = C.c_int64(), C.c_int64(), C.c_int64()
+        m, bd = C.c_int32(), C.c_int32()
+        _check(lib.fc_host_system_info(self._h, C.byref(n), C.byref(nnzb), C.byref(nel),
+                                       C.byref(m), C.byref(bd)))
+        return {"n_dofs": n.value, "nnzb": nnzb.value, "n_el": nel.value, "m": m.value,
+                "bsr_dim": bd.value}
+
+    def export(self):
+        inf = self.info()
+        bd = inf["bsr_dim"]
+        rp = np.zeros(inf["n_dofs"] // bd + 1, np.int32)
+        col = np.zeros(inf["nnzb"], np.int32)
+        val = np.zeros(inf["nnzb"] * bd * bd, np.float64)
+        rhs = np.zeros(inf["n_dofs"], np.float64)
+        ed = np.zeros(inf["n_el"] * inf["m"], np.int32)
+        eta = np.zeros(inf["n_el"], np.float64)
+        _check(load().fc_host_system_export(self._h, _np_ptr(rp), _np_ptr(col), _np_ptr(val),
+                                            _np_ptr(rhs), _np_ptr(ed), _np_ptr(eta)))
+        return {"rowptr": rp, "col": col, "val": val.reshape(-1, bd, bd), "rhs": rhs,
+                "elem_dofs": ed.reshape(inf["n_el"], inf["m"]), "eta": eta, **inf}
+
+    def upload(self, stream=None):
+        h = C.c_void_p()
+        _check(load().fc_setup_from_host(self._h, C.c_void_p(_stream(stream)), C.byref(h)))
+        return Problem(h)
+
+    def __del__(self):
+        if getattr(self, "_h", None) and _lib is not None:
+            _lib.fc_host_system_destroy(self._h)
+            self._h = None
+
+
+class Problem:
+    def __init__(self, handle):
+        self._h = handle
+        self._info = None
+
+    @classmethod
+    def setup(cls, desc: dict, stream=None):
+        cd, keep = make_desc(desc)
+        h = C.c_void_p()
+        _check(load().fc_setup(C.byref(cd), C.c_void_p(_stream(stream)), C.byref(h)))
+        return cls(h)
+
+    @classmethod
+    def from_matrix(cls, n, bsr_dim, rowptr, col, val, rhs, elem_dofs, eta, stream=None):
+        rowptr = np.ascontiguousarray(rowptr, np.int32)
+        col = np.ascontiguousarray(col, np.int32)
+        val = np.ascontiguousarray(val, np.float64).ravel()
+        rhs = np.ascontiguousarray(rhs, np.float64)
+        elem_dofs = np.ascontiguousarray(elem_dofs, np.int32)
+        eta = np.ascontiguousarray(eta, np.float64)
+        h = C.c_void_p()
+        _check(load().fc_setup_from_matrix(
+            int(n), int(bsr_dim), _np_ptr(rowptr), _np_ptr(col), _np_ptr(val), _np_ptr(rhs),
+            int(elem_dofs.shape[0]), int(elem_dofs.shape[1]), _np_ptr(elem_dofs), _np_ptr(eta),
+            C.c_void_p(_stream(stream)), C.byref(h)))
+        return cls(h)
+
+    def info(self):
+        if self._info is None:
+            n, nnzb, nel = C.c_int64(), C.c_int64(), C.c_int64()
+            m, bd = C.c_int32(), C.c_int32()
+            _check(load().fc_problem_info(self._h, C.byref(n), C.byref(nnzb), C.byref(nel),
+                                          C.byref(m), C.byref(bd)))
+            self._info = {"n_dofs": n.value, "nnzb": nnzb.value, "n_el": nel.value,
+                          "m": m.value, "bsr_dim": bd.value}
+        return self._info
+
+    @property
+    def n(self):
+        return self.info()["n_dofs"]
+
+    def rhs(self, out, stream=None):
+        _check(load().fc_get_rhs(self._h, C.c_void_p(_dptr(out)), C.c_void_p(_stream(stream))))
+        return out
+
+    def eta(self):
+        e = np.zeros(self.info()["n_el"], np.float64)
+        _check(load().fc_get_eta(self._h, _np_ptr(e)))
+        return e
+
+    def export(self):
+        inf = self.info()
+        bd = inf["bsr_dim"]
+        rp = np.zeros(inf["n_dofs"] // bd + 1, np.int32)
+        col = np.zeros(inf["nnzb"], np.int32)
+        val = np.zeros(inf["nnzb"] * bd * bd, np.float64)
+        ed = np.zeros(inf["n_el"] * inf["m"], np.int32)
+        _check(load().fc_export(self._h, _np_ptr(rp), _np_ptr(col), _np_ptr(val), _np_ptr(ed)))
+        return {"rowptr": rp, "col": col, "val": val.reshape(-1, bd, bd),
+                "elem_dofs": ed.reshape(inf["n_el"], inf["m"])}
+
+    def apply_A(self, x, y, stream=None):
+        _check(load().fc_apply_A(self._h, C.c_void_p(_dptr(x)), C.c_void_p(_dptr(y)),
+                                 C.c_void_p(_stream(stream))))
+        return y
+
+    def __del__(self):
+        if getattr(self, "_h", None) and _lib is not None:
+            _lib.fc_problem_destroy(self._h)
+            self._h = None
+
+
+class Precond:
+    def __init__(self, problem: Problem, eta_bar=1.0, eps=1e-13, stabilize=True,
+                 store=STORE_F64, stream=None):
+        o = PrecondOpts(float(eta_bar), float(eps), 1 if stabilize else 0, int(store))
+        h = C.c_void_p()
+        _check(load().fc_precond_build(problem._h, C.byref(o), C.c_void_p(_stream(stream)),
+                                       C.byref(h)))
+        self._h = h
+        self.problem = problem     # keeps the problem alive as long as this
+        self.m = problem.info()["m"]
+
+    def info(self):
+        a, b, c, d = C.c_int64(), C.c_int64(), C.c_int64(), C.c_int64()
+        _check(load().fc_precond_info(self._h, C.byref(a), C.byref(b), C.byref(c), C.byref(d)))
+        return {"n_blocks": a.value, "n_fallback": b.value, "n_eig_blocks": c.value,
+                "n_dropped": d.value}
+
+    def block_inverse(self, k):
+        out = np.zeros((self.m, self.m), np.float64)
+        _check(load().fc_get_block_inverse(self._h, int(k), _np_ptr(out)))
+        return out
+
+    def apply_M(self, r, z, stream=None):
+        _check(load().fc_apply_M(self._h, C.c_void_p(_dptr(r)), C.c_void_p(_dptr(z)),
+                                 C.c_void_p(_stream(stream))))
+        return z
+
+    def __del__(self):
+        if getattr(self, "_h", None) and _lib is not None:
+            _lib.fc_precond_destroy(self._h)
+            self._h = None
+
+
+def pcg_solve(problem: Problem, precond: Precond, b, x, tol=1e-10, maxit=300000,
+              stop="precond", mode="f64", check_every=16, inner_tol=1e-4, history=None,
+              stream=None, raise_on_error=False):
+    """Run fc_pcg_solve; returns the info dict (status included)."""
+    o = SolveOpts(float(tol), int(maxit), STOP[stop], MODE[mode], int(check_every),
+                  float(inner_tol), C.c_void_p(_dptr(history)) if history is not None else None)
+    info = SolveInfo()
+    st = load().fc_pcg_solve(problem._h, precond._h, C.c_void_p(_dptr(b)), C.c_void_p(_dptr(x)),
+                             C.byref(o), C.byref(info), C.c_void_p(_stream(stream)))
+    if st not in (FC_OK, FC_E_NOTCONV, FC_E_BREAKDOWN, FC_E_NAN) or (raise_on_error and st):
+        _check(st)
+    return {"iters": info.iters, "outer_iters": info.outer_iters,
+            "rel_res_true": info.rel_res_true, "rel_res_prec": info.rel_res_prec,
+            "status": STATUS_NAMES.get(info.status if st == FC_OK else st, st),
+            "ms_solve": info.ms_solve}

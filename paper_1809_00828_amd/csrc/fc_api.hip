@@ -1,0 +1,519 @@
+// C ABI of libfc (declared in include/fc.h): handle management, uploads,
+// the preconditioner build of Algorithm 1 and dispatch to the kernels.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "fc_internal.h"
+#include "host_assemble.h"
+#include "k_setup.h"
+
+struct fc_host_system_s {
+  fc::HostSystem sys;
+};
+
+namespace fc {
+
+static thread_local std::string g_err;
+void set_error(const std::string& msg) { g_err = msg; }
+
+fc_status pcg_solve_f64(fc_precond_s& pc, const double* b, double* x, const fc_solve_opts& o,
+                        fc_solve_info* info, hipStream_t user);
+
+template <class T>
+static fc_status dev_alloc(T** p, size_t count) {
+  *p = nullptr;
+  if (count == 0) return FC_OK;
+  hipError_t e = hipMalloc(p, count * sizeof(T));
+  if (e != hipSuccess) {
+    set_error(std::string("hipMalloc of ") + std::to_string(count * sizeof(T)) +
+              " bytes failed: " + hipGetErrorString(e));
+    (void)hipGetLastError();
+    return e == hipErrorOutOfMemory ? FC_E_NOMEM : FC_E_DEVICE;
+  }
+  return FC_OK;
+}
+
+template <class T>
+static fc_status upload(T** p, const T* src, size_t count) {
+  fc_status st = dev_alloc(p, count);
+  if (st != FC_OK || count == 0) return st;
+  FC_HIP(hipMemcpy(*p, src, count * sizeof(T), hipMemcpyHostToDevice));
+  return FC_OK;
+}
+
+#define FC_TRY(x)                  \
+  do {                             \
+    fc_status s_ = (x);            \
+    if (s_ != FC_OK) return s_;    \
+  } while (0)
+
+static void free_problem(fc_problem_s* pb) {
+  if (!pb) return;
+  for (void* p : {(void*)pb->A.rowptr, (void*)pb->A.col, (void*)pb->A.val, (void*)pb->A.val32,
+                  (void*)pb->rhs, (void*)pb->elem_nodes, (void*)pb->diag})
+    if (p) (void)hipFree(p);
+  delete pb;
+}
+
+static void free_precond(fc_precond_s* pc) {
+  if (!pc) return;
+  solver_ws_destroy(pc->ws);
+  for (void* p : {(void*)pc->block_elem, (void*)pc->P, (void*)pc->P32, (void*)pc->Pbf,
+                  (void*)pc->inv_ptr, (void*)pc->inv_idx, (void*)pc->fallback, (void*)pc->y})
+    if (p) (void)hipFree(p);
+  delete pc;
+}
+
+static fc_status upload_system(const HostSystem& S, hipStream_t stream, fc_problem* out) {
+  std::unique_ptr<fc_problem_s, void (*)(fc_problem_s*)> pb(new (std::nothrow) fc_problem_s(),
+                                                           free_problem);
+  if (!pb) return FC_E_NOMEM;
+  FC_HIP(hipGetDevice(&pb->device));
+  pb->dim = S.dim;
+  pb->p = S.p;
+  pb->n = S.n;
+  pb->bdim = S.bdim;
+  pb->nn = S.nn;
+  pb->m = S.m;
+  pb->n_nodes = S.n_nodes;
+  pb->n_dofs = S.n_dofs;
+  pb->n_el = S.n_el;
+  pb->A.bdim = S.bdim;
+  pb->A.n_rows = S.n_nodes;
+  pb->A.nnzb = S.rowptr.back();
+  int32_t mr = 0;
+  for (int64_t i = 0; i < S.n_nodes; ++i) mr = std::max(mr, S.rowptr[i + 1] - S.rowptr[i]);
+  pb->A.max_row = mr;
+  FC_TRY(upload(&pb->A.rowptr, S.rowptr.data(), S.rowptr.size()));
+  FC_TRY(upload(&pb->A.col, S.col.data(), S.col.size()));
+  FC_TRY(upload(&pb->A.val, S.val.data(), S.val.size()));
+  FC_TRY(upload(&pb->rhs, S.rhs.data(), S.rhs.size()));
+  FC_TRY(upload(&pb->elem_nodes, S.elem_nodes.data(), S.elem_nodes.size()));
+  FC_TRY(dev_alloc(&pb->diag, (size_t)S.n_dofs));
+  pb->eta = S.eta;
+  pb->elem_nodes_host = S.elem_nodes;
+  FC_HIP(launch_diag(*pb, stream));
+  FC_HIP(hipStreamSynchronize(stream));
+  *out = pb.release();
+  return FC_OK;
+}
+
+static void to_desc_check() {}
+
+}  // namespace fc
+
+using namespace fc;
+
+extern "C" {
+
+const char* fc_last_error(void) { return g_err.c_str(); }
+
+fc_status fc_assemble(const fc_problem_desc* desc, fc_host_system* out) {
+  if (!desc || !out) {
+    set_error("fc_assemble: NULL argument");
+    return FC_E_ARG;
+  }
+  *out = nullptr;
+  std::unique_ptr<fc_host_system_s> hs(new (std::nothrow) fc_host_system_s());
+  if (!hs) return FC_E_NOMEM;
+  std::string err;
+  fc_status st;
+  try {
+    st = assemble_host(*desc, &hs->sys, &err);
+  } catch (const std::bad_alloc&) {
+    set_error("fc_assemble: host allocation failed");
+    return FC_E_NOMEM;
+  }
+  if (st != FC_OK) {
+    set_error("fc_assemble: " + err);
+    return st;
+  }
+  *out = hs.release();
+  return FC_OK;
+}
+
+fc_status fc_host_system_info(fc_host_system hs, int64_t* n_dofs, int64_t* nnzb, int64_t* n_el,
+                              int32_t* m, int32_t* bsr_dim) {
+  if (!hs) return FC_E_ARG;
+  const HostSystem& S = hs->sys;
+  if (n_dofs) *n_dofs = S.n_dofs;
+  if (nnzb) *nnzb = S.rowptr.empty() ? 0 : S.rowptr.back();
+  if (n_el) *n_el = S.n_el;
+  if (m) *m = S.m;
+  if (bsr_dim) *bsr_dim = S.bdim;
+  return FC_OK;
+}
+
+static void soa_to_rowmajor(const std::vector<int32_t>& rp, const double* soa, int bd,
+                            int64_t n_rows, double* out) {
+  const int bb = bd * bd;
+  for (int64_t i = 0; i < n_rows; ++i) {
+    const int64_t L = rp[i + 1] - rp[i];
+    for (int64_t k = 0; k < L; ++k)
+      for (int e = 0; e < bb; ++e)
+        out[((int64_t)rp[i] + k) * bb + e] = soa[(int64_t)rp[i] * bb + e * L + k];
+  }
+}
+
+static void elem_dofs_from_nodes(const int32_t* en, int64_t n_el, int nn, int bd, int32_t* out) {
+  for (int64_t e = 0; e < n_el; ++e)
+    for (int a = 0; a < nn; ++a)
+      for (int c = 0; c < bd; ++c)
+        out[(e * nn + a) * bd + c] = en[e * nn + a] * bd + c;
+}
+
+fc_status fc_host_system_export(fc_host_system hs, int32_t* rowptr, int32_t* col, double* val,
+                                double* rhs, int32_t* elem_dofs, double* eta) {
+  if (!hs) return FC_E_ARG;
+  const HostSystem& S = hs->sys;
+  if (rowptr) std::memcpy(rowptr, S.rowptr.data(), S.rowptr.size() * sizeof(int32_t));
+  if (col) std::memcpy(col, S.col.data(), S.col.size() * sizeof(int32_t));
+  if (val) soa_to_rowmajor(S.rowptr, S.val.data(), S.bdim, S.n_nodes, val);
+  if (rhs) std::memcpy(rhs, S.rhs.data(), S.rhs.size() * sizeof(double));
+  if (elem_dofs) elem_dofs_from_nodes(S.elem_nodes.data(), S.n_el, S.nn, S.bdim, elem_dofs);
+  if (eta) std::memcpy(eta, S.eta.data(), S.eta.size() * sizeof(double));
+  return FC_OK;
+}
+
+void fc_host_system_destroy(fc_host_system hs) { delete hs; }
+
+fc_status fc_setup_from_host(fc_host_system hs, void* stream, fc_problem* out) {
+  if (!hs || !out) {
+    set_error("fc_setup_from_host: NULL argument");
+    return FC_E_ARG;
+  }
+  *out = nullptr;
+  return upload_system(hs->sys, (hipStream_t)stream, out);
+}
+
+fc_status fc_setup(const fc_problem_desc* desc, void* stream, fc_problem* out) {
+  fc_host_system hs = nullptr;
+  fc_status st = fc_assemble(desc, &hs);
+  if (st != FC_OK) return st;
+  st = fc_setup_from_host(hs, stream, out);
+  fc_host_system_destroy(hs);
+  return st;
+}
+
+fc_status fc_setup_from_matrix(int64_t n, int32_t bsr_dim, const int32_t* rowptr,
+                               const int32_t* col, const double* val, const double* rhs,
+                               int64_t n_el, int32_t m, const int32_t* elem_dofs,
+                               const double* eta, void* stream, fc_problem* out) {
+  if (!out || !rowptr || !col || !val || !rhs || (n_el > 0 && (!elem_dofs || !eta)) ||
+      bsr_dim < 1 || bsr_dim > 3 || n <= 0 || n % bsr_dim || m <= 0 || m % bsr_dim ||
+      n >= (int64_t(1) << 31)) {
+    set_error("fc_setup_from_matrix: invalid arguments");
+    return FC_E_ARG;
+  }
+  *out = nullptr;
+  HostSystem S;
+  S.bdim = bsr_dim;
+  S.n_nodes = n / bsr_dim;
+  S.n_dofs = n;
+  S.n_el = n_el;
+  S.m = m;
+  S.nn = m / bsr_dim;
+  const int bb = bsr_dim * bsr_dim;
+  S.rowptr.assign(rowptr, rowptr + S.n_nodes + 1);
+  if (S.rowptr[0] != 0) {
+    set_error("fc_setup_from_matrix: rowptr[0] must be 0");
+    return FC_E_ARG;
+  }
+  for (int64_t i = 0; i < S.n_nodes; ++i)
+    if (S.rowptr[i + 1] < S.rowptr[i]) {
+      set_error("fc_setup_from_matrix: rowptr not monotone");
+      return FC_E_ARG;
+    }
+  const int64_t nnzb = S.rowptr.back();
+  S.col.assign(col, col + nnzb);
+  for (int64_t i = 0; i < S.n_nodes; ++i)
+    for (int32_t k = S.rowptr[i]; k < S.rowptr[i + 1]; ++k)
+      if (S.col[k] < 0 || S.col[k] >= S.n_nodes || (k > S.rowptr[i] && S.col[k] <= S.col[k - 1])) {
+        set_error("fc_setup_from_matrix: column indices out of range or not sorted");
+        return FC_E_ARG;
+      }
+  S.val.resize((size_t)nnzb * bb);
+  for (int64_t i = 0; i < S.n_nodes; ++i) {
+    const int64_t L = S.rowptr[i + 1] - S.rowptr[i];
+    for (int64_t k = 0; k < L; ++k)
+      for (int e = 0; e < bb; ++e)
+        S.val[(int64_t)S.rowptr[i] * bb + e * L + k] = val[((int64_t)S.rowptr[i] + k) * bb + e];
+  }
+  S.rhs.assign(rhs, rhs + n);
+  S.elem_nodes.resize((size_t)n_el * S.nn);
+  for (int64_t e = 0; e < n_el; ++e)
+    for (int a = 0; a < S.nn; ++a) {
+      const int32_t d0 = elem_dofs[e * m + a * bsr_dim];
+      if (d0 < 0 || d0 >= n || d0 % bsr_dim) {
+        set_error("fc_setup_from_matrix: element unknowns must be bsr_dim*node + c");
+        return FC_E_ARG;
+      }
+      for (int c = 1; c < bsr_dim; ++c)
+        if (elem_dofs[e * m + a * bsr_dim + c] != d0 + c) {
+          set_error("fc_setup_from_matrix: element unknowns must be bsr_dim*node + c");
+          return FC_E_ARG;
+        }
+      S.elem_nodes[e * S.nn + a] = d0 / bsr_dim;
+    }
+  S.eta.assign(eta, eta + n_el);
+  return upload_system(S, (hipStream_t)stream, out);
+}
+
+fc_status fc_problem_info(fc_problem pb, int64_t* n_dofs, int64_t* nnzb, int64_t* n_el, int32_t* m,
+                          int32_t* bsr_dim) {
+  if (!pb) return FC_E_ARG;
+  if (n_dofs) *n_dofs = pb->n_dofs;
+  if (nnzb) *nnzb = pb->A.nnzb;
+  if (n_el) *n_el = pb->n_el;
+  if (m) *m = pb->m;
+  if (bsr_dim) *bsr_dim = pb->bdim;
+  return FC_OK;
+}
+
+fc_status fc_get_rhs(fc_problem pb, double* b_dev, void* stream) {
+  if (!pb || !b_dev) return FC_E_ARG;
+  FC_HIP(hipMemcpyAsync(b_dev, pb->rhs, pb->n_dofs * sizeof(double), hipMemcpyDeviceToDevice,
+                        (hipStream_t)stream));
+  return FC_OK;
+}
+
+fc_status fc_get_eta(fc_problem pb, double* eta_host) {
+  if (!pb || !eta_host) return FC_E_ARG;
+  std::memcpy(eta_host, pb->eta.data(), pb->eta.size() * sizeof(double));
+  return FC_OK;
+}
+
+fc_status fc_export(fc_problem pb, int32_t* rowptr, int32_t* col, double* val, int32_t* elem_dofs) {
+  if (!pb) return FC_E_ARG;
+  std::vector<int32_t> rp(pb->A.n_rows + 1);
+  FC_HIP(hipMemcpy(rp.data(), pb->A.rowptr, rp.size() * sizeof(int32_t), hipMemcpyDeviceToHost));
+  if (rowptr) std::memcpy(rowptr, rp.data(), rp.size() * sizeof(int32_t));
+  if (col) FC_HIP(hipMemcpy(col, pb->A.col, pb->A.nnzb * sizeof(int32_t), hipMemcpyDeviceToHost));
+  if (val) {
+    const int bb = pb->bdim * pb->bdim;
+    std::vector<double> soa((size_t)pb->A.nnzb * bb);
+    FC_HIP(hipMemcpy(soa.data(), pb->A.val, soa.size() * sizeof(double), hipMemcpyDeviceToHost));
+    soa_to_rowmajor(rp, soa.data(), pb->bdim, pb->A.n_rows, val);
+  }
+  if (elem_dofs)
+    elem_dofs_from_nodes(pb->elem_nodes_host.data(), pb->n_el, pb->nn, pb->bdim, elem_dofs);
+  return FC_OK;
+}
+
+fc_status fc_apply_A(fc_problem pb, const double* x_dev, double* y_dev, void* stream) {
+  if (!pb || !x_dev || !y_dev || x_dev == y_dev) {
+    set_error("fc_apply_A: invalid arguments");
+    return FC_E_ARG;
+  }
+  FC_HIP(launch_spmv(pb->A, x_dev, y_dev, (hipStream_t)stream));
+  return FC_OK;
+}
+
+fc_status fc_precond_build(fc_problem pb, const fc_precond_opts* opts, void* stream,
+                           fc_precond* out) {
+  if (!pb || !out) {
+    set_error("fc_precond_build: NULL argument");
+    return FC_E_ARG;
+  }
+  *out = nullptr;
+  fc_precond_opts o{1.0, 1e-13, 1, FC_STORE_F64};
+  if (opts) o = *opts;
+  if (!(o.eps >= 0.0) || !(o.eta_bar == o.eta_bar)) {
+    set_error("fc_precond_build: invalid options");
+    return FC_E_ARG;
+  }
+  if (pb->m > 192) {
+    set_error("fc_precond_build: element blocks above 192 unknowns are not supported");
+    return FC_E_UNSUPPORTED;
+  }
+  hipStream_t s = (hipStream_t)stream;
+  std::unique_ptr<fc_precond_s, void (*)(fc_precond_s*)> pc(new (std::nothrow) fc_precond_s(),
+                                                           free_precond);
+  if (!pc) return FC_E_NOMEM;
+  pc->pb = pb;
+  pc->m = pb->m;
+  pc->nn = pb->nn;
+  pc->bdim = pb->bdim;
+  pc->eps = o.eps;
+  pc->stabilize = o.stabilize ? 1 : 0;
+  const int m = pc->m, nn = pc->nn, bd = pc->bdim;
+
+  // blocks: elements with eta_T <= eta_bar (Sec. 3.2), element order
+  std::vector<int32_t> blocks;
+  for (int64_t e = 0; e < pb->n_el; ++e)
+    if (pb->eta[e] <= o.eta_bar) blocks.push_back((int32_t)e);
+  pc->n_blocks = (int64_t)blocks.size();
+  const int64_t nb = pc->n_blocks;
+  if (nb * (int64_t)m >= (int64_t(1) << 31)) {
+    set_error("fc_precond_build: too many block entries for int32 indices");
+    return FC_E_UNSUPPORTED;
+  }
+  // node -> (block, local node) map, blocks in increasing order
+  std::vector<int32_t> ptr(pb->n_nodes + 1, 0), idx((size_t)nb * nn);
+  for (int64_t k = 0; k < nb; ++k)
+    for (int a = 0; a < nn; ++a) ptr[pb->elem_nodes_host[(int64_t)blocks[k] * nn + a] + 1]++;
+  for (int64_t i = 0; i < pb->n_nodes; ++i) ptr[i + 1] += ptr[i];
+  {
+    std::vector<int32_t> fill(ptr.begin(), ptr.end() - 1);
+    for (int64_t k = 0; k < nb; ++k)
+      for (int a = 0; a < nn; ++a) {
+        const int32_t node = pb->elem_nodes_host[(int64_t)blocks[k] * nn + a];
+        idx[fill[node]++] = (int32_t)(k * m + a * bd);
+      }
+  }
+  FC_TRY(upload(&pc->block_elem, blocks.data(), blocks.size()));
+  FC_TRY(upload(&pc->inv_ptr, ptr.data(), ptr.size()));
+  FC_TRY(upload(&pc->inv_idx, idx.data(), idx.size()));
+  FC_TRY(dev_alloc(&pc->P, (size_t)nb * m * m));
+  FC_TRY(dev_alloc(&pc->y, (size_t)nb * m));
+  FC_TRY(dev_alloc(&pc->fallback, (size_t)pb->n_dofs));
+
+  int32_t* d_flag = nullptr;
+  int32_t* d_drop = nullptr;
+  unsigned long long* d_count = nullptr;
+  struct Tmp {
+    void* p[3] = {nullptr, nullptr, nullptr};
+    ~Tmp() {
+      for (void* q : p)
+        if (q) (void)hipFree(q);
+    }
+  } tmp;
+  FC_TRY(dev_alloc(&d_flag, (size_t)std::max<int64_t>(nb, 1)));
+  tmp.p[0] = d_flag;
+  FC_TRY(dev_alloc(&d_drop, (size_t)std::max<int64_t>(nb, 1)));
+  tmp.p[1] = d_drop;
+  FC_TRY(dev_alloc(&d_count, 1));
+  tmp.p[2] = d_count;
+  FC_HIP(hipMemsetAsync(d_drop, 0, std::max<int64_t>(nb, 1) * sizeof(int32_t), s));
+  FC_HIP(hipMemsetAsync(d_count, 0, sizeof(unsigned long long), s));
+
+  if (nb > 0) {
+    FC_HIP(launch_block_extract(*pb, *pc, s));
+    if (m <= 64) {
+      // every block by the eigen-decomposition; in LDS when it fits
+      const int64_t chunk = jacobi_needs_work(m) ? 16384 : nb;
+      double* work = nullptr;
+      if (jacobi_needs_work(m)) FC_TRY(dev_alloc(&work, (size_t)std::min(chunk, nb) * 2 * m * m));
+      std::vector<int32_t> all(nb);
+      for (int64_t k = 0; k < nb; ++k) all[k] = (int32_t)k;
+      int32_t* d_all = nullptr;
+      fc_status st = upload(&d_all, all.data(), all.size());
+      hipError_t e = hipSuccess;
+      for (int64_t s0 = 0; st == FC_OK && s0 < nb && e == hipSuccess; s0 += chunk)
+        e = launch_jacobi(*pc, d_all + s0, std::min(chunk, nb - s0), work, d_drop, s);
+      hipError_t e2 = hipStreamSynchronize(s);
+      if (d_all) (void)hipFree(d_all);
+      if (work) (void)hipFree(work);
+      FC_TRY(st);
+      FC_HIP(e);
+      FC_HIP(e2);
+      pc->n_eig = nb;
+    } else {
+      FC_HIP(launch_sweep(*pc, d_flag, s));
+      std::vector<int32_t> flag(nb);
+      FC_HIP(hipMemcpyAsync(flag.data(), d_flag, nb * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+      FC_HIP(hipStreamSynchronize(s));
+      std::vector<int32_t> sel;
+      for (int64_t k = 0; k < nb; ++k)
+        if (flag[k]) sel.push_back((int32_t)k);
+      pc->n_eig = (int64_t)sel.size();
+      if (!sel.empty()) {
+        // blocks whose certificate failed still hold A_B: eigen-decompose
+        const int64_t chunk = 2048;
+        int32_t* d_sel = nullptr;
+        double* work = nullptr;
+        FC_TRY(upload(&d_sel, sel.data(), sel.size()));
+        fc_status st = dev_alloc(&work, (size_t)std::min<int64_t>(chunk, sel.size()) * 2 * m * m);
+        if (st != FC_OK) {
+          (void)hipFree(d_sel);
+          return st;
+        }
+        hipError_t e = hipSuccess;
+        for (int64_t s0 = 0; s0 < (int64_t)sel.size() && e == hipSuccess; s0 += chunk) {
+          const int64_t cnt = std::min<int64_t>(chunk, sel.size() - s0);
+          e = launch_jacobi(*pc, d_sel + s0, cnt, work, d_drop, s);
+        }
+        hipError_t e2 = hipStreamSynchronize(s);
+        (void)hipFree(d_sel);
+        (void)hipFree(work);
+        FC_HIP(e);
+        FC_HIP(e2);
+      }
+    }
+  }
+  FC_HIP(launch_fallback(*pb, *pc, d_count, s));
+  if (o.store_mask & FC_STORE_F32) FC_TRY(dev_alloc(&pc->P32, (size_t)nb * m * m));
+  if (o.store_mask & FC_STORE_BF16) FC_TRY(dev_alloc(&pc->Pbf, (size_t)nb * m * m));
+  FC_HIP(launch_casts(*pc, s));
+  unsigned long long cnt = 0;
+  std::vector<int32_t> drop(std::max<int64_t>(nb, 1));
+  FC_HIP(hipMemcpyAsync(&cnt, d_count, sizeof(cnt), hipMemcpyDeviceToHost, s));
+  FC_HIP(hipMemcpyAsync(drop.data(), d_drop, drop.size() * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  FC_HIP(hipStreamSynchronize(s));
+  pc->n_fallback = (int64_t)cnt;
+  int64_t nd = 0;
+  for (int64_t k = 0; k < nb; ++k) nd += drop[k];
+  pc->n_dropped = nd;
+  *out = pc.release();
+  return FC_OK;
+}
+
+fc_status fc_precond_info(fc_precond pc, int64_t* n_blocks, int64_t* n_fallback,
+                          int64_t* n_eig_blocks, int64_t* n_dropped) {
+  if (!pc) return FC_E_ARG;
+  if (n_blocks) *n_blocks = pc->n_blocks;
+  if (n_fallback) *n_fallback = pc->n_fallback;
+  if (n_eig_blocks) *n_eig_blocks = pc->n_eig;
+  if (n_dropped) *n_dropped = pc->n_dropped;
+  return FC_OK;
+}
+
+fc_status fc_get_block_inverse(fc_precond pc, int64_t k, double* out_host) {
+  if (!pc || !out_host || k < 0 || k >= pc->n_blocks) {
+    set_error("fc_get_block_inverse: invalid arguments");
+    return FC_E_ARG;
+  }
+  const size_t mm = (size_t)pc->m * pc->m;
+  FC_HIP(hipMemcpy(out_host, pc->P + k * mm, mm * sizeof(double), hipMemcpyDeviceToHost));
+  return FC_OK;
+}
+
+fc_status fc_apply_M(fc_precond pc, const double* r_dev, double* z_dev, void* stream) {
+  if (!pc || !r_dev || !z_dev || r_dev == z_dev) {
+    set_error("fc_apply_M: invalid arguments");
+    return FC_E_ARG;
+  }
+  FC_HIP(launch_schwarz_apply(*pc, r_dev, z_dev, (hipStream_t)stream));
+  return FC_OK;
+}
+
+fc_status fc_pcg_solve(fc_problem pb, fc_precond pc, const double* b_dev, double* x_dev,
+                       const fc_solve_opts* opts, fc_solve_info* info, void* stream) {
+  if (!pb || !pc || pc->pb != pb || !b_dev || !x_dev || b_dev == x_dev) {
+    set_error("fc_pcg_solve: invalid arguments");
+    return FC_E_ARG;
+  }
+  fc_solve_opts o{1e-10, 300000, FC_STOP_PRECOND, FC_MODE_F64, 16, 1e-4, nullptr};
+  if (opts) o = *opts;
+  if (!(o.tol >= 0.0) || o.maxit < 0 || (o.stop != FC_STOP_PRECOND && o.stop != FC_STOP_RESIDUAL)) {
+    set_error("fc_pcg_solve: invalid options");
+    return FC_E_ARG;
+  }
+  if (o.mode != FC_MODE_F64) {
+    set_error("fc_pcg_solve: unsupported mode");
+    return FC_E_UNSUPPORTED;
+  }
+  return pcg_solve_f64(*pc, b_dev, x_dev, o, info, (hipStream_t)stream);
+}
+
+void fc_problem_destroy(fc_problem pb) { free_problem(pb); }
+void fc_precond_destroy(fc_precond pc) { free_precond(pc); }
+
+}  // extern "C"

@@ -1,0 +1,110 @@
+// Internal structures of libfc shared by the HIP translation units.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "fc.h"
+
+namespace fc {
+
+void set_error(const std::string& msg);
+
+#define FC_HIP(call)                                                         \
+  do {                                                                       \
+    hipError_t e_ = (call);                                                  \
+    if (e_ != hipSuccess) {                                                  \
+      ::fc::set_error(std::string(#call) + ": " + hipGetErrorString(e_));    \
+      return FC_E_DEVICE;                                                    \
+    }                                                                        \
+  } while (0)
+
+// Scalars of one PCG run kept on the device so the iteration never waits on
+// the host.  Dots are reduced per workgroup into `partial`, and the last
+// workgroup to finish (found with `ticket`) sums the partials in a fixed
+// order, so every run is bitwise reproducible.
+struct CgScalars {
+  double rz;        // (r, z) of the current iterate
+  double pq;        // (p, A p)
+  double alpha, beta;
+  double zz;        // (z, z) of the newest z
+  double rr;        // (r, r) of the newest r
+  double crit0;     // ||z_0|| or ||b|| (denominator of the stop test)
+  double crit;      // newest relative criterion
+  double tol;
+  int64_t iter;     // products with A done
+  int64_t maxit;
+  int32_t done;     // 0 running, 1 converged, 2 maxit, 3 breakdown, 4 non-finite
+  int32_t stop;     // FC_STOP_*
+  uint32_t ticket;  // last-workgroup counter (reset by the last workgroup)
+  uint32_t pad;
+  double zn0, rn0;  // ||z_0||, ||r_0||
+  double* history;  // optional per-iteration criterion
+};
+
+struct DeviceBsr {
+  int32_t bdim = 1;
+  int64_t n_rows = 0;      // block rows
+  int64_t nnzb = 0;
+  int32_t max_row = 0;     // longest block row
+  int32_t* rowptr = nullptr;
+  int32_t* col = nullptr;
+  double* val = nullptr;   // row-SoA layout
+  float* val32 = nullptr;  // optional FP32 copy, same layout
+};
+
+struct SolverWs;
+void solver_ws_destroy(SolverWs* ws);
+
+}  // namespace fc
+
+struct fc_problem_s {
+  int device = 0;
+  int32_t dim = 0, p = 0, n = 0;   // lattice (0 when built from a matrix)
+  int32_t bdim = 1, nn = 0, m = 0;
+  int64_t n_nodes = 0, n_dofs = 0, n_el = 0;
+  fc::DeviceBsr A;
+  double* rhs = nullptr;           // [n_dofs]
+  int32_t* elem_nodes = nullptr;   // [n_el*nn]
+  std::vector<double> eta;         // host copy [n_el]
+  std::vector<int32_t> elem_nodes_host;
+  double* diag = nullptr;          // A_ll [n_dofs]
+};
+
+struct fc_precond_s {
+  fc_problem pb = nullptr;
+  int32_t m = 0, nn = 0, bdim = 1;
+  int64_t n_blocks = 0;
+  int32_t* block_elem = nullptr;   // [n_blocks] element of each block
+  double* P = nullptr;             // [n_blocks*m*m] FP64 local inverses
+  float* P32 = nullptr;            // optional FP32 copy
+  uint16_t* Pbf = nullptr;         // optional BF16 copy
+  int32_t* inv_ptr = nullptr;      // [n_nodes+1] node -> (block, local node)
+  int32_t* inv_idx = nullptr;      // entries: block*m + local_node*bdim
+  double* fallback = nullptr;      // [n_dofs] 1/A_ll where S_ll = 0, else 0
+  double* y = nullptr;             // [n_blocks*m] block outputs (workspace)
+  int64_t n_fallback = 0, n_eig = 0, n_dropped = 0;
+  double eps = 1e-13;
+  int32_t stabilize = 1;
+  fc::SolverWs* ws = nullptr;      // PCG workspace, created on first solve
+};
+
+namespace fc {
+
+// ---- launchers (each returns hipSuccess or the first launch error) ----
+// y = A x  (and optionally partial dots (x, y) per workgroup)
+hipError_t launch_spmv(const DeviceBsr& A, const double* x, double* y,
+                       hipStream_t s);
+hipError_t launch_spmv_f32(const DeviceBsr& A, const double* x, double* y,
+                           hipStream_t s);
+
+hipError_t launch_block_extract(const fc_problem_s& pb, const fc_precond_s& pc,
+                                hipStream_t s);
+
+// z = S r
+hipError_t launch_schwarz_apply(const fc_precond_s& pc, const double* r,
+                                double* z, hipStream_t s);
+
+}  // namespace fc

@@ -1,0 +1,16 @@
+// Preconditioner set-up launchers.
+#pragma once
+#include "fc_internal.h"
+
+namespace fc {
+hipError_t launch_jacobi(fc_precond_s& pc, const int32_t* sel, int64_t count,
+                         double* work, int32_t* dropped, hipStream_t s);
+// true when the Jacobi eigen path keeps its blocks in global memory
+bool jacobi_needs_work(int m);
+hipError_t launch_sweep(fc_precond_s& pc, int32_t* need_eig, hipStream_t s);
+hipError_t launch_diag(const fc_problem_s& pb, hipStream_t s);
+hipError_t launch_fallback(const fc_problem_s& pb, fc_precond_s& pc,
+                           unsigned long long* d_count, hipStream_t s);
+hipError_t launch_casts(fc_precond_s& pc, hipStream_t s);
+hipError_t launch_cast_matrix(const DeviceBsr& A, hipStream_t s);
+}  // namespace fc

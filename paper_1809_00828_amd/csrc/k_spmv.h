@@ -1,0 +1,12 @@
+// SpMV launch helpers used by the solver.
+#pragma once
+#include "fc_internal.h"
+
+namespace fc {
+// Number of workgroups (and so of dot partials) of the fused SpMV.
+int spmv_num_blocks(const DeviceBsr& A);
+// q = A p with the fused (p, q) reduction and the step length of PCG
+// (skipped when sc->done is set).
+hipError_t launch_spmv_pq(const DeviceBsr& A, bool f32, const double* p, double* q,
+                          CgScalars* sc, double* partial, hipStream_t s);
+}  // namespace fc

@@ -1,0 +1,241 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle.
+
+Sizes span several tiles and ragged tails of every kernel while the oracle
+still finishes in seconds.  Tolerances:
+  * y = A x: relative 1e-13 (assembly and SpMV are both rounding-level).
+  * local inverses: both sides are backward stable, so they differ by
+    ~ m * eps_mach * kappa(A_B) relative; the test bounds the difference by
+    1e-15 * m * kappa(A_B) + 1e-13 and requires identical dropped counts.
+  * z = S r and PCG iterates: relative energy-norm difference <= 1e-10 (the
+    parity bar on the solution); iteration counts within +-2.
+"""
+import numpy as np
+import pytest
+
+import paper_1809_00828_amd as fc
+from oracle import pcg, schwarz
+from tests.gpu_common import (PROBLEMS, energy, oracle_direct, oracle_precond,
+                              oracle_system, require_gpu)
+
+pytestmark = pytest.mark.gpu
+
+NAMES = sorted(PROBLEMS)
+
+
+@pytest.fixture(scope="module")
+def torch():
+    return require_gpu()
+
+
+_lib_cache = {}
+
+
+def lib_problem(name):
+    if name not in _lib_cache:
+        d, _ = oracle_system(name)
+        _lib_cache[name] = fc.Problem.setup(d)
+    return _lib_cache[name]
+
+
+def _dev(torch, a):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
+
+
+@pytest.mark.parametrize("name", NAMES)
+def test_apply_A(torch, name):
+    print(f"[apply_A] {name}", flush=True)
+    _, s = oracle_system(name)
+    pb = lib_problem(name)
+    n = pb.n
+    assert n == s["A"].shape[0]
+    x = np.random.default_rng(11).standard_normal(n)
+    y = torch.empty(n, dtype=torch.float64, device="cuda")
+    pb.apply_A(_dev(torch, x), y)
+    torch.cuda.synchronize()
+    ref = s["A"] @ x
+    err = np.linalg.norm(y.cpu().numpy() - ref) / np.linalg.norm(ref)
+    assert err <= 1e-13, err
+
+
+@pytest.mark.parametrize("name", NAMES)
+def test_rhs_and_eta(torch, name):
+    _, s = oracle_system(name)
+    pb = lib_problem(name)
+    b = torch.empty(pb.n, dtype=torch.float64, device="cuda")
+    pb.rhs(b)
+    torch.cuda.synchronize()
+    bo = s["b"]
+    np.testing.assert_allclose(b.cpu().numpy(), bo, rtol=0,
+                               atol=1e-13 * max(abs(bo).max(), 1e-300))
+    np.testing.assert_allclose(pb.eta(), s["eta"], rtol=0, atol=1e-12)
+
+
+@pytest.mark.parametrize("name", NAMES)
+def test_local_inverses(torch, name):
+    print(f"[local_inverses] {name}", flush=True)
+    _, s = oracle_system(name)
+    pc = fc.Precond(lib_problem(name))
+    info = pc.info()
+    assert info["n_blocks"] == len(s["eta"])
+    assert info["n_fallback"] == 0
+    rng = np.random.default_rng(5)
+    picks = sorted(set(rng.integers(0, info["n_blocks"], size=8).tolist()) | {0, info["n_blocks"] - 1})
+    dropped = 0
+    for k in range(info["n_blocks"]):
+        B = s["elem_dofs"][k]
+        AB = schwarz.extract_submatrix(s["A"], B)
+        lam = np.linalg.eigvalsh(AB)
+        dropped += int(np.sum(~(lam > 1e-13 * lam.max())))
+        if k not in picks:
+            continue
+        ref = schwarz.pseudo_inverse(AB)
+        got = pc.block_inverse(k)
+        kept = lam[lam > 1e-13 * lam.max()]
+        kappa = kept.max() / kept.min()
+        tol = 1e-15 * AB.shape[0] * kappa + 1e-13
+        err = np.linalg.norm(got - ref) / np.linalg.norm(ref)
+        assert err <= tol, (k, err, kappa)
+        np.testing.assert_allclose(got, got.T, rtol=0, atol=1e-14 * abs(got).max())
+    assert info["n_dropped"] == dropped
+
+
+@pytest.mark.parametrize("name", NAMES)
+def test_apply_M(torch, name):
+    print(f"[apply_M] {name}", flush=True)
+    _, s = oracle_system(name)
+    S, _, _ = oracle_precond(name)
+    pc = fc.Precond(lib_problem(name))
+    n = S.shape[0]
+    r = np.random.default_rng(12).standard_normal(n)
+    z = torch.empty(n, dtype=torch.float64, device="cuda")
+    pc.apply_M(_dev(torch, r), z)
+    torch.cuda.synchronize()
+    ref = S @ r
+    d = z.cpu().numpy() - ref
+    A = s["A"]
+    assert energy(A, d) <= 1e-10 * energy(A, ref)
+    # entries of unknowns in well-conditioned regions agree to rounding
+    assert np.median(np.abs(d) / (np.abs(ref) + 1e-300)) < 1e-10
+
+
+def _solve(torch, name, tol, maxit=100000, stop="precond", **kw):
+    d, s = oracle_system(name)
+    pb = lib_problem(name)
+    pc = fc.Precond(pb, **kw)
+    b = torch.empty(pb.n, dtype=torch.float64, device="cuda")
+    pb.rhs(b)
+    x = torch.zeros(pb.n, dtype=torch.float64, device="cuda")
+    info = fc.pcg_solve(pb, pc, b, x, tol=tol, maxit=maxit, stop=stop, check_every=8)
+    torch.cuda.synchronize()
+    return x.cpu().numpy(), info
+
+
+@pytest.mark.parametrize("name", NAMES)
+def test_pcg_matches_oracle(torch, name):
+    print(f"[pcg] {name}", flush=True)
+    _, s = oracle_system(name)
+    A, b = s["A"], s["b"]
+    S, _, _ = oracle_precond(name)
+    tol = 1e-10
+    x, info = _solve(torch, name, tol)
+    xo, io = pcg.pcg(A, b, S, tol=tol)
+    assert info["status"] == "OK", info
+    assert abs(info["iters"] - io["iters"]) <= 2, (info["iters"], io["iters"])
+    # both solved tighter: the two solutions agree in the energy norm
+    x2, info2 = _solve(torch, name, 1e-13)
+    xo2, _ = pcg.pcg(A, b, S, tol=1e-13)
+    xr = oracle_direct(name)
+    assert energy(A, x2 - xo2) <= 1e-10 * energy(A, xo2)
+    assert energy(A, x2 - xr) <= 1e-9 * energy(A, xr)
+    assert info2["rel_res_true"] <= 1e-9
+
+
+@pytest.mark.parametrize("name", ["disk16_p2", "elast3d_p3"])
+def test_pcg_fixed_iterations_match(torch, name):
+    """Iterate k of both sides, k well before convergence."""
+    _, s = oracle_system(name)
+    A, b = s["A"], s["b"]
+    S, _, _ = oracle_precond(name)
+    k = 15
+    x, info = _solve(torch, name, 0.0, maxit=k)
+    xo, io = pcg.pcg(A, b, S, tol=0.0, maxit=k)
+    assert info["status"] == "E_NOTCONV" and info["iters"] == k == io["iters"]
+    assert energy(A, x - xo) <= 1e-10 * energy(A, xo)
+
+
+def test_pcg_is_bitwise_reproducible(torch):
+    x1, i1 = _solve(torch, "pois3d_p2", 1e-10)
+    x2, i2 = _solve(torch, "pois3d_p2", 1e-10)
+    assert i1["iters"] == i2["iters"]
+    np.testing.assert_array_equal(x1, x2)
+
+
+def test_residual_stop_rule(torch):
+    name = "disk16_p2"
+    _, s = oracle_system(name)
+    S, _, _ = oracle_precond(name)
+    x, info = _solve(torch, name, 1e-9, stop="residual")
+    _, io = pcg.pcg(s["A"], s["b"], S, tol=1e-9, stop="residual")
+    assert info["status"] == "OK"
+    assert abs(info["iters"] - io["iters"]) <= 2
+    assert info["rel_res_true"] <= 2e-9
+
+
+def test_zero_rhs_gives_zero_solution(torch):
+    pb = lib_problem("disk16_p2")
+    pc = fc.Precond(pb)
+    b = torch.zeros(pb.n, dtype=torch.float64, device="cuda")
+    x = torch.full((pb.n,), 7.0, dtype=torch.float64, device="cuda")
+    info = fc.pcg_solve(pb, pc, b, x, tol=1e-10)
+    assert info["status"] == "OK" and info["iters"] == 0
+    assert float(x.abs().max()) == 0.0
+
+
+def test_eta_bar_fallback_matches_oracle(torch):
+    name = "disk16_p2"
+    _, s = oracle_system(name)
+    S, fall, blocks = oracle_precond(name, eta_bar=0.5)
+    pb = lib_problem(name)
+    pc = fc.Precond(pb, eta_bar=0.5)
+    info = pc.info()
+    assert info["n_blocks"] == len(blocks)
+    assert info["n_fallback"] == fall.size > 0
+    r = np.random.default_rng(3).standard_normal(pb.n)
+    z = torch.empty(pb.n, dtype=torch.float64, device="cuda")
+    pc.apply_M(_dev(torch, r), z)
+    torch.cuda.synchronize()
+    ref = S @ r
+    assert energy(s["A"], z.cpu().numpy() - ref) <= 1e-10 * energy(s["A"], ref)
+    x, inf2 = _solve(torch, name, 1e-10, eta_bar=0.5)
+    _, io = pcg.pcg(s["A"], s["b"], S, tol=1e-10)
+    assert abs(inf2["iters"] - io["iters"]) <= 2
+
+
+def test_setup_from_oracle_matrix(torch):
+    """The solver on the oracle's own matrix (isolates the solver from the
+    assembler)."""
+    from tests.gpu_common import csr_to_bsr_arrays
+    name = "elast3d_p2"
+    d, s = oracle_system(name)
+    bd = 3
+    rowptr, col, val = csr_to_bsr_arrays(s["A"], bd)
+    pb = fc.Problem.from_matrix(s["A"].shape[0], bd, rowptr, col, val, s["b"],
+                                s["elem_dofs"], s["eta"])
+    pc = fc.Precond(pb)
+    b = _dev(torch, s["b"])
+    x = torch.zeros_like(b)
+    info = fc.pcg_solve(pb, pc, b, x, tol=1e-10)
+    S, _, _ = oracle_precond(name)
+    xo, io = pcg.pcg(s["A"], s["b"], S, tol=1e-10)
+    assert info["status"] == "OK" and abs(info["iters"] - io["iters"]) <= 2
+    xr = oracle_direct(name)
+    assert energy(s["A"], x.cpu().numpy() - xr) <= 1e-8 * energy(s["A"], xr)
+
+
+def test_invalid_arguments_raise(torch):
+    pb = lib_problem("disk16_p2")
+    x = torch.zeros(pb.n, dtype=torch.float64, device="cuda")
+    with pytest.raises(fc.FcError):
+        pb.apply_A(x, x)
+    with pytest.raises(fc.FcError):
+        fc.Precond(pb, eps=-1.0)
