@@ -197,7 +197,11 @@ fc_status fc_apply_M(fc_precond pc, const double* r_dev, double* z_dev,
  *   mode         FC_MODE_F64 plain FP64 PCG
  *   check_every  iterations between host checks of the device stop flag
  *   history_dev  optional device buffer of maxit+1 doubles receiving the
- *                relative stop criterion of every iteration, or NULL */
+ *                relative stop criterion of every iteration, or NULL
+ *   timing       nonzero: launch the iteration without a captured graph and
+ *                bracket every SpMV and Schwarz block-product kernel with
+ *                events on the solver stream (fc_solve_info.ms_spmv,
+ *                ms_schwarz); costs a few microseconds per iteration */
 enum { FC_STOP_PRECOND = 0, FC_STOP_RESIDUAL = 1 };
 enum { FC_MODE_F64 = 0 };
 typedef struct {
@@ -208,6 +212,7 @@ typedef struct {
   int32_t check_every;
   double inner_tol;
   double* history_dev;
+  int32_t timing;
 } fc_solve_opts;
 
 typedef struct {
@@ -217,6 +222,9 @@ typedef struct {
   double rel_res_prec;    /* last ||S r_i|| / ||S b||                    */
   int32_t status;         /* fc_status of the solve                       */
   double ms_solve;        /* device time of the iteration, milliseconds   */
+  double ms_spmv;         /* timing mode: summed SpMV kernel time          */
+  double ms_schwarz;      /* timing mode: summed block-product kernel time */
+  int64_t n_timed;        /* timing mode: iterations those sums cover      */
 } fc_solve_info;
 
 /* Preconditioned CG (Sec. 5, with S of Eq. 6) from x = 0: b_dev and x_dev

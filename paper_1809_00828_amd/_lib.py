@@ -59,13 +59,14 @@ class PrecondOpts(C.Structure):
 class SolveOpts(C.Structure):
     _fields_ = [("tol", C.c_double), ("maxit", C.c_int64), ("stop", C.c_int32),
                 ("mode", C.c_int32), ("check_every", C.c_int32), ("inner_tol", C.c_double),
-                ("history_dev", C.c_void_p)]
+                ("history_dev", C.c_void_p), ("timing", C.c_int32)]
 
 
 class SolveInfo(C.Structure):
     _fields_ = [("iters", C.c_int64), ("outer_iters", C.c_int64),
                 ("rel_res_true", C.c_double), ("rel_res_prec", C.c_double),
-                ("status", C.c_int32), ("ms_solve", C.c_double)]
+                ("status", C.c_int32), ("ms_solve", C.c_double), ("ms_spmv", C.c_double),
+                ("ms_schwarz", C.c_double), ("n_timed", C.c_int64)]
 
 
 _lib = None
@@ -326,10 +327,11 @@ class Precond:
 
 def pcg_solve(problem: Problem, precond: Precond, b, x, tol=1e-10, maxit=300000,
               stop="precond", mode="f64", check_every=16, inner_tol=1e-4, history=None,
-              stream=None, raise_on_error=False):
+              timing=False, stream=None, raise_on_error=False):
     """Run fc_pcg_solve; returns the info dict (status included)."""
     o = SolveOpts(float(tol), int(maxit), STOP[stop], MODE[mode], int(check_every),
-                  float(inner_tol), C.c_void_p(_dptr(history)) if history is not None else None)
+                  float(inner_tol), C.c_void_p(_dptr(history)) if history is not None else None,
+                  1 if timing else 0)
     info = SolveInfo()
     st = load().fc_pcg_solve(problem._h, precond._h, C.c_void_p(_dptr(b)), C.c_void_p(_dptr(x)),
                              C.byref(o), C.byref(info), C.c_void_p(_stream(stream)))
@@ -338,4 +340,5 @@ def pcg_solve(problem: Problem, precond: Precond, b, x, tol=1e-10, maxit=300000,
     return {"iters": info.iters, "outer_iters": info.outer_iters,
             "rel_res_true": info.rel_res_true, "rel_res_prec": info.rel_res_prec,
             "status": STATUS_NAMES.get(info.status if st == FC_OK else st, st),
-            "ms_solve": info.ms_solve}
+            "ms_solve": info.ms_solve, "ms_spmv": info.ms_spmv,
+            "ms_schwarz": info.ms_schwarz, "n_timed": info.n_timed}

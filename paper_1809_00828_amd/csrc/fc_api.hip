@@ -500,7 +500,7 @@ fc_status fc_pcg_solve(fc_problem pb, fc_precond pc, const double* b_dev, double
     set_error("fc_pcg_solve: invalid arguments");
     return FC_E_ARG;
   }
-  fc_solve_opts o{1e-10, 300000, FC_STOP_PRECOND, FC_MODE_F64, 16, 1e-4, nullptr};
+  fc_solve_opts o{1e-10, 300000, FC_STOP_PRECOND, FC_MODE_F64, 16, 1e-4, nullptr, 0};
   if (opts) o = *opts;
   if (!(o.tol >= 0.0) || o.maxit < 0 || (o.stop != FC_STOP_PRECOND && o.stop != FC_STOP_RESIDUAL)) {
     set_error("fc_pcg_solve: invalid options");

@@ -4,14 +4,16 @@
 // Recurrences (x_0 = 0):  r_0 = b, z_0 = S r_0, p_0 = z_0, then per step
 //   q = A p;  alpha = (r,z)/(p,q);  x += alpha p;  r -= alpha q;
 //   z = S r;  beta = (r,z)_new/(r,z);  p = z + beta p.
-// One step is four kernels, all reading their scalars from device memory:
-//   1. SpMV q = A p with the fused (p,q) reduction; the last workgroup
-//      computes alpha and counts the step (k_spmv.hip)
-//   2. Schwarz phase 1 on the gathered r - alpha q (k_schwarz.hip)
-//   3. pull z = sum_B R_B^T y_B + fallback, fused with the x and r updates
-//      and the (r,z), (z,z), (r,r) reductions; the last workgroup evaluates
-//      the stop test and beta
-//   4. p = z + beta p
+// One step is six kernels, all reading their scalars from device memory:
+//   1. SpMV q = A p with per-workgroup (p,q) partials (k_spmv.hip)
+//   2. one workgroup sums them in a fixed order: alpha, step count
+//   3. Schwarz phase 1 on the gathered r - alpha q (k_schwarz.hip)
+//   4. pull z = sum_B R_B^T y_B + fallback, fused with the x and r updates
+//      and per-workgroup (r,z), (z,z), (r,r) partials
+//   5. one workgroup: stop test and beta
+//   6. p = z + beta p
+// The reductions stay atomic-free: a same-address atomic per workgroup
+// serialises in L2 and costs more than the SpMV itself at this size.
 // Every kernel returns at once when the stop flag is set, so a captured
 // chunk of steps can be replayed without the host and the iterate stays the
 // one at which the test fired.  The host checks the flag between chunks.
@@ -19,6 +21,7 @@
 
 #include <chrono>
 #include <cmath>
+#include <vector>
 
 #include "dev_common.h"
 #include "k_schwarz.h"
@@ -39,6 +42,7 @@ struct SolverWs {
   hipGraph_t graph = nullptr;
   const void* key[4] = {nullptr, nullptr, nullptr, nullptr};
   int key_chunk = 0, key_prec = -1;
+  std::vector<hipEvent_t> tev;  // timing mode: 4 events per step of a chunk
 };
 
 void solver_ws_destroy(SolverWs* w) {
@@ -49,6 +53,7 @@ void solver_ws_destroy(SolverWs* w) {
   if (w->sc) (void)hipFree(w->sc);
   if (w->host) (void)hipHostFree(w->host);
   for (auto& e : w->ev) if (e) (void)hipEventDestroy(e);
+  for (auto& e : w->tev) if (e) (void)hipEventDestroy(e);
   if (w->stream) (void)hipStreamDestroy(w->stream);
   delete w;
 }
@@ -99,21 +104,42 @@ __global__ __launch_bounds__(256) void k_cg_start(const double* __restrict__ r,
   }
 }
 
+// Step length: sum the per-workgroup (p, A p) partials of the SpMV in a
+// fixed order (one workgroup), count the step and check for breakdown.
+__global__ __launch_bounds__(1024) void k_cg_alpha(const double* __restrict__ partial, int np,
+                                                   CgScalars* sc) {
+  __shared__ double lds[16];
+  if (sc->done) return;
+  double t = 0.0;
+  for (int i = threadIdx.x; i < np; i += blockDim.x) t += partial[i];
+  const double pq = block_sum(t, lds);
+  if (threadIdx.x == 0) {
+    sc->pq = pq;
+    sc->iter += 1;
+    const double rz = sc->rz;
+    if (!(pq > 0.0) || !(rz > 0.0)) {
+      sc->done = (pq != pq || rz != rz) ? 4 : 3;
+    } else {
+      sc->alpha = rz / pq;
+    }
+  }
+}
+
 // Pull of the Schwarz apply fused with x += alpha p, r -= alpha q and the
-// reductions of the new r and z.
+// reductions of the new r and z (one partial triple per workgroup; the
+// grid loops over the unknowns).
 __global__ __launch_bounds__(256) void k_cg_pull(
     const double* __restrict__ y, const int32_t* __restrict__ inv_ptr,
     const int32_t* __restrict__ inv_idx, const double* __restrict__ fb, int bd, int64_t n,
     double* __restrict__ x, double* __restrict__ r, const double* __restrict__ p,
     const double* __restrict__ q, double* __restrict__ z, double* __restrict__ partial,
-    CgScalars* sc) {
+    const CgScalars* __restrict__ sc) {
   __shared__ double lds[16];
-  __shared__ int flag;
   if (sc->done) return;
   const double alpha = sc->alpha;
   double a = 0.0, b = 0.0, c = 0.0;
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
     const int64_t node = i / bd;
     const int cc = (int)(i - node * bd);
     double s = 0.0;
@@ -123,9 +149,9 @@ __global__ __launch_bounds__(256) void k_cg_pull(
     r[i] = ri;
     const double zi = fma(fb[i], ri, s);
     z[i] = zi;
-    a = ri * zi;
-    b = zi * zi;
-    c = ri * ri;
+    a = fma(ri, zi, a);
+    b = fma(zi, zi, b);
+    c = fma(ri, ri, c);
   }
   a = block_sum(a, lds);
   b = block_sum(b, lds);
@@ -135,10 +161,23 @@ __global__ __launch_bounds__(256) void k_cg_pull(
     partial[gridDim.x + blockIdx.x] = b;
     partial[2 * gridDim.x + blockIdx.x] = c;
   }
-  if (!last_block(&sc->ticket, gridDim.x, &flag)) return;
-  const double rz = sum_partials(partial, gridDim.x, lds);
-  const double zz = sum_partials(partial + gridDim.x, gridDim.x, lds);
-  const double rr = sum_partials(partial + 2 * gridDim.x, gridDim.x, lds);
+}
+
+// Stop test (Eq. 12 or the plain residual) and beta from the pull's
+// partials, summed in a fixed order by one workgroup.
+__global__ __launch_bounds__(1024) void k_cg_beta(const double* __restrict__ partial, int np,
+                                                  CgScalars* sc) {
+  __shared__ double lds[16];
+  if (sc->done) return;
+  double ta = 0.0, tb = 0.0, tc = 0.0;
+  for (int i = threadIdx.x; i < np; i += blockDim.x) {
+    ta += partial[i];
+    tb += partial[np + i];
+    tc += partial[2 * np + i];
+  }
+  const double rz = block_sum(ta, lds);
+  const double zz = block_sum(tb, lds);
+  const double rr = block_sum(tc, lds);
   if (threadIdx.x == 0) {
     const double crit = (sc->stop == FC_STOP_PRECOND ? sqrt(zz) : sqrt(rr)) / sc->crit0;
     sc->zz = zz;
@@ -208,6 +247,8 @@ __global__ __launch_bounds__(256) void k_resid(const double* __restrict__ b,
 
 static inline unsigned nblk(int64_t n) { return (unsigned)((n + kVecThreads - 1) / kVecThreads); }
 static constexpr unsigned kRedBlocks = 1024;
+// grid of the fused pull: enough workgroups to fill the chip, few partials
+static inline unsigned pull_grid(int64_t n) { return std::min<unsigned>(nblk(n), 2048u); }
 
 // ----------------------------------------------------------- host side
 static fc_status ensure_ws(fc_precond_s& pc, SolverWs** out) {
@@ -237,19 +278,28 @@ static fc_status ensure_ws(fc_precond_s& pc, SolverWs** out) {
   return FC_OK;
 }
 
-// Enqueue `chunk` PCG steps on stream s.
+// Enqueue `chunk` PCG steps on stream s (with timing events when tev).
 static hipError_t enqueue_steps(fc_precond_s& pc, SolverWs& w, double* x, int chunk,
-                                int prec, hipStream_t s) {
+                                int prec, hipStream_t s, hipEvent_t* tev = nullptr) {
   fc_problem_s& pb = *pc.pb;
   const int64_t n = pb.n_dofs;
   for (int it = 0; it < chunk; ++it) {
-    hipError_t e = launch_spmv_pq(pb.A, false, w.p, w.q, w.sc, w.partial, s);
+    hipError_t e;
+    if (tev && (e = hipEventRecord(tev[4 * it + 0], s)) != hipSuccess) return e;
+    e = launch_spmv_pq(pb.A, false, w.p, w.q, w.sc, w.partial, s);
     if (e != hipSuccess) return e;
+    if (tev && (e = hipEventRecord(tev[4 * it + 1], s)) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_cg_alpha, dim3(1), dim3(1024), 0, s, w.partial, spmv_num_blocks(pb.A),
+                       w.sc);
+    if (tev && (e = hipEventRecord(tev[4 * it + 2], s)) != hipSuccess) return e;
     e = launch_schwarz_phase1(pc, prec, w.r, w.q, w.sc, s);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_cg_pull, dim3(nblk(n)), dim3(kVecThreads), 0, s, pc.y, pc.inv_ptr,
+    if (tev && (e = hipEventRecord(tev[4 * it + 3], s)) != hipSuccess) return e;
+    const unsigned pg = pull_grid(n);
+    hipLaunchKernelGGL(k_cg_pull, dim3(pg), dim3(kVecThreads), 0, s, pc.y, pc.inv_ptr,
                        pc.inv_idx, pc.fallback, pc.bdim, n, x, w.r, w.p, w.q, w.z, w.partial,
                        w.sc);
+    hipLaunchKernelGGL(k_cg_beta, dim3(1), dim3(1024), 0, s, w.partial, (int)pg, w.sc);
     hipLaunchKernelGGL(k_cg_p, dim3(nblk(n)), dim3(kVecThreads), 0, s, w.z, w.p, n, w.sc);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
@@ -288,36 +338,66 @@ fc_status pcg_solve_f64(fc_precond_s& pc, const double* b, double* x, const fc_s
 
   const int chunk = o.check_every > 0 ? o.check_every : 16;
   const int prec = 0;
-  // (re)capture the chunk when the buffers or the chunk length change
-  if (!w.exec || w.key[0] != x || w.key_chunk != chunk || w.key_prec != prec) {
-    if (w.exec) {
-      FC_HIP(hipGraphExecDestroy(w.exec));
-      w.exec = nullptr;
+  double t_spmv = 0.0, t_schw = 0.0;
+  int64_t n_timed = 0;
+  if (o.timing) {
+    // direct launches with events around the two streaming kernels
+    if ((int)w.tev.size() < 4 * chunk) {
+      size_t old = w.tev.size();
+      w.tev.resize(4 * chunk, nullptr);
+      for (size_t i = old; i < w.tev.size(); ++i) FC_HIP(hipEventCreate(&w.tev[i]));
     }
-    if (w.graph) {
-      FC_HIP(hipGraphDestroy(w.graph));
-      w.graph = nullptr;
+    int64_t iter_before = 0, launched = 0;
+    const int64_t max_chunks = (o.maxit + chunk - 1) / chunk + 1;
+    for (;;) {
+      FC_HIP(enqueue_steps(pc, w, x, chunk, prec, s, w.tev.data()));
+      ++launched;
+      FC_HIP(hipMemcpyAsync(w.host, w.sc, sizeof(CgScalars), hipMemcpyDeviceToHost, s));
+      FC_HIP(hipStreamSynchronize(s));
+      const int64_t ran = std::min<int64_t>(chunk, w.host->iter - iter_before);
+      iter_before = w.host->iter;
+      for (int64_t it = 0; it < ran; ++it) {
+        float a = 0.f, b = 0.f;
+        FC_HIP(hipEventElapsedTime(&a, w.tev[4 * it + 0], w.tev[4 * it + 1]));
+        FC_HIP(hipEventElapsedTime(&b, w.tev[4 * it + 2], w.tev[4 * it + 3]));
+        t_spmv += a;
+        t_schw += b;
+      }
+      n_timed += ran;
+      if (w.host->done != 0 || launched > max_chunks) break;
     }
-    FC_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-    hipError_t e = enqueue_steps(pc, w, x, chunk, prec, s);
-    hipGraph_t g = nullptr;
-    hipError_t e2 = hipStreamEndCapture(s, &g);
-    if (e != hipSuccess) FC_HIP(e);
-    FC_HIP(e2);
-    w.graph = g;
-    FC_HIP(hipGraphInstantiate(&w.exec, g, nullptr, nullptr, 0));
-    w.key[0] = x;
-    w.key_chunk = chunk;
-    w.key_prec = prec;
-  }
-  int64_t launched = 0;
-  const int64_t max_chunks = (o.maxit + chunk - 1) / chunk + 1;
-  for (;;) {
-    FC_HIP(hipGraphLaunch(w.exec, s));
-    ++launched;
-    FC_HIP(hipMemcpyAsync(w.host, w.sc, sizeof(CgScalars), hipMemcpyDeviceToHost, s));
-    FC_HIP(hipStreamSynchronize(s));
-    if (w.host->done != 0 || launched > max_chunks) break;
+  } else {
+    // (re)capture the chunk when the buffers or the chunk length change
+    if (!w.exec || w.key[0] != x || w.key_chunk != chunk || w.key_prec != prec) {
+      if (w.exec) {
+        FC_HIP(hipGraphExecDestroy(w.exec));
+        w.exec = nullptr;
+      }
+      if (w.graph) {
+        FC_HIP(hipGraphDestroy(w.graph));
+        w.graph = nullptr;
+      }
+      FC_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+      hipError_t e = enqueue_steps(pc, w, x, chunk, prec, s);
+      hipGraph_t g = nullptr;
+      hipError_t e2 = hipStreamEndCapture(s, &g);
+      if (e != hipSuccess) FC_HIP(e);
+      FC_HIP(e2);
+      w.graph = g;
+      FC_HIP(hipGraphInstantiate(&w.exec, g, nullptr, nullptr, 0));
+      w.key[0] = x;
+      w.key_chunk = chunk;
+      w.key_prec = prec;
+    }
+    int64_t launched = 0;
+    const int64_t max_chunks = (o.maxit + chunk - 1) / chunk + 1;
+    for (;;) {
+      FC_HIP(hipGraphLaunch(w.exec, s));
+      ++launched;
+      FC_HIP(hipMemcpyAsync(w.host, w.sc, sizeof(CgScalars), hipMemcpyDeviceToHost, s));
+      FC_HIP(hipStreamSynchronize(s));
+      if (w.host->done != 0 || launched > max_chunks) break;
+    }
   }
   FC_HIP(hipEventRecord(w.ev[2], s));
   // true residual ||b - A x|| / ||b||
@@ -350,6 +430,9 @@ fc_status pcg_solve_f64(fc_precond_s& pc, const double* b, double* x, const fc_s
     info->rel_res_prec = h.zn0 > 0 ? std::sqrt(h.zz) / h.zn0 : 0.0;
     info->status = result;
     info->ms_solve = ms;
+    info->ms_spmv = t_spmv;
+    info->ms_schwarz = t_schw;
+    info->n_timed = n_timed;
   }
   return result;
 }

@@ -5,7 +5,7 @@
 namespace fc {
 // Number of workgroups (and so of dot partials) of the fused SpMV.
 int spmv_num_blocks(const DeviceBsr& A);
-// q = A p with the fused (p, q) reduction and the step length of PCG
+// q = A p leaving one partial (p, q) per workgroup in partial[0..nb)
 // (skipped when sc->done is set).
 hipError_t launch_spmv_pq(const DeviceBsr& A, bool f32, const double* p, double* q,
                           CgScalars* sc, double* partial, hipStream_t s);

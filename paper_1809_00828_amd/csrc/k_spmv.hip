@@ -11,6 +11,12 @@
 // once per product and streamed with non-temporal loads, which leaves the
 // cache to the gathered x entries (neighbouring rows of the lattice share
 // most of their columns).
+//
+// Tiles of 256/G rows are dealt out so that the workgroups resident on one
+// XCD (hardware ids congruent mod 8) walk one contiguous range of rows and
+// share that XCD's L2 for x.  The PCG variant runs a bounded grid that
+// loops over its tiles and leaves one partial (x, y) per workgroup; a
+// one-workgroup kernel of the solver sums them in a fixed order.
 #include "dev_common.h"
 #include "k_spmv.h"
 
@@ -20,24 +26,27 @@ template <int B, int G, typename T>
 __global__ __launch_bounds__(256) void k_spmv_bsr(
     const int32_t* __restrict__ rowptr, const int32_t* __restrict__ col,
     const T* __restrict__ val, const double* __restrict__ x,
-    double* __restrict__ y, int64_t n_rows, const CgScalars* sc,
-    double* __restrict__ partial, CgScalars* scw) {
+    double* __restrict__ y, int64_t n_rows, const CgScalars* __restrict__ sc,
+    double* __restrict__ partial) {
   constexpr int BB = B * B;
-  constexpr int RPW = 256 / G;   // rows per workgroup
+  constexpr int RPW = 256 / G;   // rows per tile
   __shared__ double lds[16];
-  __shared__ int flag;
-  const bool fused = partial != nullptr;
-  if (fused && sc->done) return;
-  const uint32_t tile = xcd_remap(blockIdx.x, gridDim.x);
-  const int64_t row = (int64_t)tile * RPW + threadIdx.x / G;
+  if (sc && sc->done) return;
+  const int64_t ntiles = (n_rows + RPW - 1) / RPW;
+  // XCD-contiguous tile ranges
+  const uint32_t nwg = gridDim.x, xcd = blockIdx.x % kNumXcd, j = blockIdx.x / kNumXcd;
+  const uint32_t per = nwg / kNumXcd + (xcd < nwg % kNumXcd ? 1u : 0u);
+  const int64_t t0 = ntiles * xcd / kNumXcd, t1 = ntiles * (xcd + 1) / kNumXcd;
   const int lane = threadIdx.x % G;
   double dot = 0.0;
-  if (row < n_rows) {
+  for (int64_t tile = t0 + j; tile < t1; tile += per) {
+    const int64_t row = tile * RPW + threadIdx.x / G;
+    if (row >= n_rows) continue;
     const int64_t base = rowptr[row];
     const int L = rowptr[row + 1] - (int32_t)base;
     const T* v = val + base * BB;
-    float accf[B];
     double acc[B];
+    float accf[B];
 #pragma unroll
     for (int i = 0; i < B; ++i) {
       acc[i] = 0.0;
@@ -47,72 +56,66 @@ __global__ __launch_bounds__(256) void k_spmv_bsr(
       const int c = __builtin_nontemporal_load(col + base + k);
       double xv[B];
 #pragma unroll
-      for (int j = 0; j < B; ++j) xv[j] = x[(int64_t)c * B + j];
+      for (int jj = 0; jj < B; ++jj) xv[jj] = x[(int64_t)c * B + jj];
 #pragma unroll
       for (int i = 0; i < B; ++i)
 #pragma unroll
-        for (int j = 0; j < B; ++j) {
-          const T a = __builtin_nontemporal_load(v + (int64_t)(i * B + j) * L + k);
+        for (int jj = 0; jj < B; ++jj) {
+          const T a = __builtin_nontemporal_load(v + (int64_t)(i * B + jj) * L + k);
           if constexpr (sizeof(T) == 8)
-            acc[i] = fma((double)a, xv[j], acc[i]);
+            acc[i] = fma((double)a, xv[jj], acc[i]);
           else
-            accf[i] = fmaf((float)a, (float)xv[j], accf[i]);
+            accf[i] = fmaf((float)a, (float)xv[jj], accf[i]);
         }
     }
 #pragma unroll
     for (int i = 0; i < B; ++i) {
-      double t = (sizeof(T) == 8) ? acc[i] : (double)accf[i];
       if constexpr (sizeof(T) == 8)
-        t = group_sum<G>(t);
+        acc[i] = group_sum<G>(acc[i]);
       else
-        t = (double)group_sum<G>((float)t);
-      acc[i] = t;
+        acc[i] = (double)group_sum<G>(accf[i]);
     }
     if (lane == 0) {
 #pragma unroll
       for (int i = 0; i < B; ++i) {
         y[row * B + i] = acc[i];
-        if (fused) dot = fma(x[row * B + i], acc[i], dot);
+        if (partial) dot = fma(x[row * B + i], acc[i], dot);
       }
     }
   }
-  if (!fused) return;
-  // fused (p, A p) for PCG: per-workgroup partial, last workgroup finalises
+  if (!partial) return;
   dot = block_sum(dot, lds);
   if (threadIdx.x == 0) partial[blockIdx.x] = dot;
-  if (!last_block(&scw->ticket, gridDim.x, &flag)) return;
-  const double pq = sum_partials(partial, gridDim.x, lds);
-  if (threadIdx.x == 0) {
-    scw->pq = pq;
-    scw->iter += 1;
-    const double rz = scw->rz;
-    if (!(pq > 0.0) || !(rz > 0.0)) {
-      scw->done = (pq != pq || rz != rz) ? 4 : 3;
-    } else {
-      scw->alpha = rz / pq;
-    }
-  }
 }
+
+static int group_width(const DeviceBsr& A) {
+  const double mean = A.n_rows ? double(A.nnzb) / double(A.n_rows) : 1.0;
+  if (mean < 12) return 8;
+  if (mean < 24) return 16;
+  if (mean < 48) return 32;
+  return 64;
+}
+
+static int64_t num_tiles(const DeviceBsr& A) {
+  const int rpw = 256 / group_width(A);
+  return (A.n_rows + rpw - 1) / rpw;
+}
+
+constexpr int64_t kFusedGrid = 2048;   // 8 workgroups of 4 waves per CU
 
 template <int B, typename T>
 static hipError_t spmv_dispatch(const DeviceBsr& A, const T* val, const double* x,
                                 double* y, hipStream_t s, const CgScalars* sc,
-                                double* partial, CgScalars* scw, int* nblocks_out) {
-  // group width from the mean row length
-  const double mean = A.n_rows ? double(A.nnzb) / double(A.n_rows) : 1.0;
-  int G = 64;
-  if (mean < 12) G = 8;
-  else if (mean < 24) G = 16;
-  else if (mean < 48) G = 32;
-  const int rpw = 256 / G;
-  const int64_t nb = (A.n_rows + rpw - 1) / rpw;
-  if (nblocks_out) *nblocks_out = (int)nb;
-  if (nb == 0) return hipSuccess;
+                                double* partial) {
+  const int G = group_width(A);
+  const int64_t nt = num_tiles(A);
+  if (nt == 0) return hipSuccess;
+  const int64_t nb = partial ? std::min(nt, kFusedGrid) : nt;
   dim3 grid((unsigned)nb), block(256);
 #define FC_SPMV_CASE(GG)                                                           \
   case GG:                                                                         \
     hipLaunchKernelGGL((k_spmv_bsr<B, GG, T>), grid, block, 0, s, A.rowptr, A.col, \
-                       val, x, y, A.n_rows, sc, partial, scw);                    \
+                       val, x, y, A.n_rows, sc, partial);                         \
     break;
   switch (G) {
     FC_SPMV_CASE(8)
@@ -125,41 +128,32 @@ static hipError_t spmv_dispatch(const DeviceBsr& A, const T* val, const double* 
 }
 
 template <typename T>
-static hipError_t spmv_any(const DeviceBsr& A, const T* val, const double* x,
-                           double* y, hipStream_t s, const CgScalars* sc,
-                           double* partial, CgScalars* scw, int* nb) {
+static hipError_t spmv_any(const DeviceBsr& A, const T* val, const double* x, double* y,
+                           hipStream_t s, const CgScalars* sc, double* partial) {
   switch (A.bdim) {
-    case 1: return spmv_dispatch<1, T>(A, val, x, y, s, sc, partial, scw, nb);
-    case 2: return spmv_dispatch<2, T>(A, val, x, y, s, sc, partial, scw, nb);
-    case 3: return spmv_dispatch<3, T>(A, val, x, y, s, sc, partial, scw, nb);
+    case 1: return spmv_dispatch<1, T>(A, val, x, y, s, sc, partial);
+    case 2: return spmv_dispatch<2, T>(A, val, x, y, s, sc, partial);
+    case 3: return spmv_dispatch<3, T>(A, val, x, y, s, sc, partial);
   }
   return hipErrorInvalidValue;
 }
 
 hipError_t launch_spmv(const DeviceBsr& A, const double* x, double* y, hipStream_t s) {
-  return spmv_any<double>(A, A.val, x, y, s, nullptr, nullptr, nullptr, nullptr);
+  return spmv_any<double>(A, A.val, x, y, s, nullptr, nullptr);
 }
 
-hipError_t launch_spmv_f32(const DeviceBsr& A, const double* x, double* y,
-                           hipStream_t s) {
-  return spmv_any<float>(A, A.val32, x, y, s, nullptr, nullptr, nullptr, nullptr);
+hipError_t launch_spmv_f32(const DeviceBsr& A, const double* x, double* y, hipStream_t s) {
+  return spmv_any<float>(A, A.val32, x, y, s, nullptr, nullptr);
 }
 
 int spmv_num_blocks(const DeviceBsr& A) {
-  int nb = 0;
-  const double mean = A.n_rows ? double(A.nnzb) / double(A.n_rows) : 1.0;
-  int G = 64;
-  if (mean < 12) G = 8;
-  else if (mean < 24) G = 16;
-  else if (mean < 48) G = 32;
-  nb = (int)((A.n_rows + 256 / G - 1) / (256 / G));
-  return nb;
+  return (int)std::min(num_tiles(A), kFusedGrid);
 }
 
 hipError_t launch_spmv_pq(const DeviceBsr& A, bool f32, const double* p, double* q,
                           CgScalars* sc, double* partial, hipStream_t s) {
-  if (f32) return spmv_any<float>(A, A.val32, p, q, s, sc, partial, sc, nullptr);
-  return spmv_any<double>(A, A.val, p, q, s, sc, partial, sc, nullptr);
+  if (f32) return spmv_any<float>(A, A.val32, p, q, s, sc, partial);
+  return spmv_any<double>(A, A.val, p, q, s, sc, partial);
 }
 
 }  // namespace fc

@@ -81,3 +81,26 @@ def csr_to_bsr_arrays(A, bd):
     for r, c, v in zip(coo.row, coo.col, coo.data):
         val[pos[int((r // bd) * nb + c // bd)], r % bd, c % bd] += v
     return rowptr, bcol, val
+
+
+@functools.lru_cache(maxsize=None)
+def max_block_kappa(name, eta_bar=1.0):
+    """Largest condition number (over kept eigenvalues) of the element
+    blocks.  Above ~1e10 the smallest kept eigenpairs, and so the local
+    pseudo-inverses, are fixed by FP64 data only to ~eps * kappa: two
+    backward-stable eigensolvers (or two assemblers that differ by rounding)
+    then give preconditioners whose PCG iteration counts differ by more
+    than rounding."""
+    _, s = oracle_system(name)
+    _, _, blocks = oracle_precond(name, eta_bar)
+    worst = 1.0
+    for B in blocks:
+        lam = np.linalg.eigvalsh(schwarz.extract_submatrix(s["A"], B))
+        if lam.max() <= 0:
+            continue
+        kept = lam[lam > 1e-13 * lam.max()]
+        worst = max(worst, kept.max() / kept.min())
+    return worst
+
+
+WELL_DETERMINED_KAPPA = 1e10
