@@ -44,8 +44,9 @@ def algorithmic_bytes(info, m, n_blocks, nn):
     bd = info["bsr_dim"]
     nnzb = info["nnzb"]
     spmv = nnzb * (bd * bd * 8 + 4) + (n // bd + 1) * 4 + 2 * n * 8
-    # P_B once, element node lists, gathered r and q once, y_B written
-    schwarz = n_blocks * m * m * 8 + n_blocks * nn * 4 + 2 * n * 8 + n_blocks * m * 8
+    # stored half of each symmetric P_B once ((m/2+1)*m wrapped diagonals),
+    # element node lists, gathered r and q once, y_B written
+    schwarz = n_blocks * (m // 2 + 1) * m * 8 + n_blocks * nn * 4 + 2 * n * 8 + n_blocks * m * 8
     return spmv, schwarz
 
 
@@ -159,6 +160,15 @@ def main():
     gbs_schw = schw_b / (ms_schw * 1e-3) / 1e9
     gbs_spmv = spmv_b / (ms_spmv * 1e-3) / 1e9
     total_dof_iters = n * sum(iters)
+    k_spmv = {"bound": "hbm", "kernel": "k_spmv_bsr<3,64,double> (SpMV q = A p)",
+              "achieved": gbs_spmv, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+              "frac": gbs_spmv / HBM_PEAK_GBS, "traffic": None,
+              "bytes_per_launch": spmv_b, "avg_ms": ms_spmv}
+    k_schw = {"bound": "hbm", "kernel": "k_schwarz_sym_staged<double> (block products)",
+              "achieved": gbs_schw, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+              "frac": gbs_schw / HBM_PEAK_GBS, "traffic": None,
+              "bytes_per_launch": schw_b, "avg_ms": ms_schw}
+    dominant, other = (k_spmv, k_schw) if ms_spmv >= ms_schw else (k_schw, k_spmv)
     out = {
         "metric": METRIC,
         "value": total_dof_iters / wall,
@@ -170,14 +180,8 @@ def main():
         "config": {"workload": wl, "n_dofs": n, "nnz_blocks": info["nnzb"],
                    "blocks": pinfo["n_blocks"], "block_size": m, "tol": args.tol,
                    "stop": "relative residual ||b-Ax||/||b||", "form": "fp64"},
-        "roofline": {"bound": "hbm", "kernel": "k_schwarz_large<double> (block products)",
-                     "achieved": gbs_schw, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": gbs_schw / HBM_PEAK_GBS, "traffic": None,
-                     "bytes_per_launch": schw_b, "avg_ms": ms_schw},
-        "roofline_spmv": {"bound": "hbm", "kernel": "k_spmv_bsr<3,64,double>",
-                          "achieved": gbs_spmv, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                          "frac": gbs_spmv / HBM_PEAK_GBS, "bytes_per_launch": spmv_b,
-                          "avg_ms": ms_spmv},
+        "roofline": dominant,
+        "roofline_other": other,
         "iters": iters, "status": status,
         "time_to_tol_ms": [bd + sv for bd, sv in zip(builds, solves)],
         "build_ms": builds, "solve_ms": solves,

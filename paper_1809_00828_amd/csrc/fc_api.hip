@@ -12,6 +12,7 @@
 
 #include "fc_internal.h"
 #include "host_assemble.h"
+#include "k_schwarz.h"
 #include "k_setup.h"
 
 struct fc_host_system_s {
@@ -65,7 +66,7 @@ static void free_problem(fc_problem_s* pb) {
 static void free_precond(fc_precond_s* pc) {
   if (!pc) return;
   solver_ws_destroy(pc->ws);
-  for (void* p : {(void*)pc->block_elem, (void*)pc->P, (void*)pc->P32, (void*)pc->Pbf,
+  for (void* p : {(void*)pc->block_elem, (void*)pc->P, (void*)pc->Q, (void*)pc->Q32, (void*)pc->Qbf,
                   (void*)pc->inv_ptr, (void*)pc->inv_idx, (void*)pc->fallback, (void*)pc->y})
     if (p) (void)hipFree(p);
   delete pc;
@@ -449,9 +450,18 @@ fc_status fc_precond_build(fc_problem pb, const fc_precond_opts* opts, void* str
     }
   }
   FC_HIP(launch_fallback(*pb, *pc, d_count, s));
-  if (o.store_mask & FC_STORE_F32) FC_TRY(dev_alloc(&pc->P32, (size_t)nb * m * m));
-  if (o.store_mask & FC_STORE_BF16) FC_TRY(dev_alloc(&pc->Pbf, (size_t)nb * m * m));
-  FC_HIP(launch_casts(*pc, s));
+  // wrapped-diagonal symmetric copies streamed by the block products
+  const size_t qn = (size_t)nb * sym_block_stride(m);
+  FC_TRY(dev_alloc(&pc->Q, qn));
+  FC_HIP(launch_pack_sym(pc->P, pc->Q, 0, m, nb, s));
+  if (o.store_mask & FC_STORE_F32) {
+    FC_TRY(dev_alloc(&pc->Q32, qn));
+    FC_HIP(launch_pack_sym(pc->P, pc->Q32, 1, m, nb, s));
+  }
+  if (o.store_mask & FC_STORE_BF16) {
+    FC_TRY(dev_alloc(&pc->Qbf, qn));
+    FC_HIP(launch_pack_sym(pc->P, pc->Qbf, 2, m, nb, s));
+  }
   unsigned long long cnt = 0;
   std::vector<int32_t> drop(std::max<int64_t>(nb, 1));
   FC_HIP(hipMemcpyAsync(&cnt, d_count, sizeof(cnt), hipMemcpyDeviceToHost, s));

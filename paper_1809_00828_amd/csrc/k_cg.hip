@@ -110,9 +110,16 @@ __global__ __launch_bounds__(1024) void k_cg_alpha(const double* __restrict__ pa
                                                    CgScalars* sc) {
   __shared__ double lds[16];
   if (sc->done) return;
-  double t = 0.0;
-  for (int i = threadIdx.x; i < np; i += blockDim.x) t += partial[i];
-  const double pq = block_sum(t, lds);
+  double t0 = 0.0, t1 = 0.0, t2 = 0.0, t3 = 0.0;
+  int i = threadIdx.x;
+  for (; i + 3 * (int)blockDim.x < np; i += 4 * blockDim.x) {
+    t0 += partial[i];
+    t1 += partial[i + blockDim.x];
+    t2 += partial[i + 2 * blockDim.x];
+    t3 += partial[i + 3 * blockDim.x];
+  }
+  for (; i < np; i += blockDim.x) t0 += partial[i];
+  const double pq = block_sum((t0 + t1) + (t2 + t3), lds);
   if (threadIdx.x == 0) {
     sc->pq = pq;
     sc->iter += 1;

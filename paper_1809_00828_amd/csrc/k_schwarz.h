@@ -8,4 +8,13 @@ namespace fc {
 // the local inverses.  Skipped when sc->done is set (sc may be NULL).
 hipError_t launch_schwarz_phase1(const fc_precond_s& pc, int precision, const double* r,
                                  const double* q, const CgScalars* sc, hipStream_t s);
+// Phase 2 only: z = sum_B R_B^T y_B + fallback * r.
+hipError_t launch_schwarz_pull(const fc_precond_s& pc, const double* r, double* z,
+                               hipStream_t s);
+// Elements per block of the wrapped-diagonal symmetric layout, (m/2+1)*m.
+int64_t sym_block_stride(int m);
+// Q = wrapped-diagonal copy of the dense FP64 local inverses P in FP64 (0),
+// FP32 (1) or BF16 (2).
+hipError_t launch_pack_sym(const double* P, void* Q, int precision, int m, int64_t n_blocks,
+                           hipStream_t s);
 }  // namespace fc

@@ -11,6 +11,5 @@ hipError_t launch_sweep(fc_precond_s& pc, int32_t* need_eig, hipStream_t s);
 hipError_t launch_diag(const fc_problem_s& pb, hipStream_t s);
 hipError_t launch_fallback(const fc_problem_s& pb, fc_precond_s& pc,
                            unsigned long long* d_count, hipStream_t s);
-hipError_t launch_casts(fc_precond_s& pc, hipStream_t s);
 hipError_t launch_cast_matrix(const DeviceBsr& A, hipStream_t s);
 }  // namespace fc

@@ -343,18 +343,6 @@ __global__ void k_cast_f32(const double* __restrict__ in, float* __restrict__ ou
     out[i] = (float)in[i];
 }
 
-// FP64 -> BF16, round to nearest even (through FP32).
-__global__ void k_cast_bf16(const double* __restrict__ in, uint16_t* __restrict__ out, int64_t n) {
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-       i += (int64_t)gridDim.x * blockDim.x) {
-    float f = (float)in[i];
-    uint32_t u = __float_as_uint(f);
-    uint32_t lsb = (u >> 16) & 1u;
-    u += 0x7fffu + lsb;
-    out[i] = (uint16_t)(u >> 16);
-  }
-}
-
 // ---------------------------------------------------------- launchers
 hipError_t launch_block_extract(const fc_problem_s& pb, const fc_precond_s& pc,
                                 hipStream_t s) {
@@ -427,14 +415,6 @@ hipError_t launch_fallback(const fc_problem_s& pb, fc_precond_s& pc,
   hipLaunchKernelGGL(k_fallback, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s,
                      pc.P, pc.inv_ptr, pc.inv_idx, pb.diag, pc.m, pc.bdim, n,
                      pc.fallback, d_count);
-  return hipGetLastError();
-}
-
-hipError_t launch_casts(fc_precond_s& pc, hipStream_t s) {
-  const int64_t n = pc.n_blocks * (int64_t)pc.m * pc.m;
-  if (n == 0) return hipSuccess;
-  if (pc.P32) hipLaunchKernelGGL(k_cast_f32, dim3(4096), dim3(256), 0, s, pc.P, pc.P32, n);
-  if (pc.Pbf) hipLaunchKernelGGL(k_cast_bf16, dim3(4096), dim3(256), 0, s, pc.P, pc.Pbf, n);
   return hipGetLastError();
 }
 

@@ -14,9 +14,11 @@
 //
 // Tiles of 256/G rows are dealt out so that the workgroups resident on one
 // XCD (hardware ids congruent mod 8) walk one contiguous range of rows and
-// share that XCD's L2 for x.  The PCG variant runs a bounded grid that
-// loops over its tiles and leaves one partial (x, y) per workgroup; a
-// one-workgroup kernel of the solver sums them in a fixed order.
+// share that XCD's L2 for x.  The PCG variant leaves one partial (x, y)
+// per workgroup; a one-workgroup kernel of the solver sums them in a fixed
+// order (no atomics).
+#include <cstdlib>
+
 #include "dev_common.h"
 #include "k_spmv.h"
 
@@ -52,20 +54,35 @@ __global__ __launch_bounds__(256) void k_spmv_bsr(
       acc[i] = 0.0;
       accf[i] = 0.0f;
     }
-    for (int k = lane; k < L; k += G) {
+    // two blocks per lane per pass: twice the loads in flight
+    for (int k = lane; k < L; k += 2 * G) {
+      const int k2 = k + G;
+      const bool two = k2 < L;
       const int c = __builtin_nontemporal_load(col + base + k);
-      double xv[B];
+      const int c2 = two ? __builtin_nontemporal_load(col + base + k2) : c;
+      T a1[BB], a2[BB];
 #pragma unroll
-      for (int jj = 0; jj < B; ++jj) xv[jj] = x[(int64_t)c * B + jj];
+      for (int e = 0; e < BB; ++e) {
+        a1[e] = __builtin_nontemporal_load(v + (int64_t)e * L + k);
+        a2[e] = two ? __builtin_nontemporal_load(v + (int64_t)e * L + k2) : T(0);
+      }
+      double xv[B], xv2[B];
+#pragma unroll
+      for (int jj = 0; jj < B; ++jj) {
+        xv[jj] = x[(int64_t)c * B + jj];
+        xv2[jj] = x[(int64_t)c2 * B + jj];
+      }
 #pragma unroll
       for (int i = 0; i < B; ++i)
 #pragma unroll
         for (int jj = 0; jj < B; ++jj) {
-          const T a = __builtin_nontemporal_load(v + (int64_t)(i * B + jj) * L + k);
-          if constexpr (sizeof(T) == 8)
-            acc[i] = fma((double)a, xv[jj], acc[i]);
-          else
-            accf[i] = fmaf((float)a, (float)xv[jj], accf[i]);
+          if constexpr (sizeof(T) == 8) {
+            acc[i] = fma((double)a1[i * B + jj], xv[jj], acc[i]);
+            acc[i] = fma((double)a2[i * B + jj], xv2[jj], acc[i]);
+          } else {
+            accf[i] = fmaf((float)a1[i * B + jj], (float)xv[jj], accf[i]);
+            accf[i] = fmaf((float)a2[i * B + jj], (float)xv2[jj], accf[i]);
+          }
         }
     }
 #pragma unroll
@@ -88,7 +105,17 @@ __global__ __launch_bounds__(256) void k_spmv_bsr(
   if (threadIdx.x == 0) partial[blockIdx.x] = dot;
 }
 
+// Launch shape.  Group width from the mean row length (FC_SPMV_GROUP
+// overrides it); the PCG variant uses one tile per workgroup unless
+// FC_SPMV_FUSED_GRID caps the grid (then workgroups loop over tiles).
+static int env_int(const char* name, int dflt) {
+  const char* e = std::getenv(name);
+  return e ? std::atoi(e) : dflt;
+}
+
 static int group_width(const DeviceBsr& A) {
+  static const int forced = env_int("FC_SPMV_GROUP", 0);
+  if (forced == 8 || forced == 16 || forced == 32 || forced == 64) return forced;
   const double mean = A.n_rows ? double(A.nnzb) / double(A.n_rows) : 1.0;
   if (mean < 12) return 8;
   if (mean < 24) return 16;
@@ -101,7 +128,11 @@ static int64_t num_tiles(const DeviceBsr& A) {
   return (A.n_rows + rpw - 1) / rpw;
 }
 
-constexpr int64_t kFusedGrid = 2048;   // 8 workgroups of 4 waves per CU
+static int64_t fused_grid(const DeviceBsr& A) {
+  static const int cap = env_int("FC_SPMV_FUSED_GRID", 0);
+  const int64_t nt = num_tiles(A);
+  return cap > 0 ? std::min<int64_t>(nt, cap) : nt;
+}
 
 template <int B, typename T>
 static hipError_t spmv_dispatch(const DeviceBsr& A, const T* val, const double* x,
@@ -110,7 +141,7 @@ static hipError_t spmv_dispatch(const DeviceBsr& A, const T* val, const double* 
   const int G = group_width(A);
   const int64_t nt = num_tiles(A);
   if (nt == 0) return hipSuccess;
-  const int64_t nb = partial ? std::min(nt, kFusedGrid) : nt;
+  const int64_t nb = partial ? fused_grid(A) : nt;
   dim3 grid((unsigned)nb), block(256);
 #define FC_SPMV_CASE(GG)                                                           \
   case GG:                                                                         \
@@ -146,9 +177,7 @@ hipError_t launch_spmv_f32(const DeviceBsr& A, const double* x, double* y, hipSt
   return spmv_any<float>(A, A.val32, x, y, s, nullptr, nullptr);
 }
 
-int spmv_num_blocks(const DeviceBsr& A) {
-  return (int)std::min(num_tiles(A), kFusedGrid);
-}
+int spmv_num_blocks(const DeviceBsr& A) { return (int)fused_grid(A); }
 
 hipError_t launch_spmv_pq(const DeviceBsr& A, bool f32, const double* p, double* q,
                           CgScalars* sc, double* partial, hipStream_t s) {
