@@ -94,6 +94,33 @@ def cpu_baseline(seconds=10.0):
     }
 
 
+def forms(fc, pb, b, tol, t_f64, it_f64):
+    """Time-to-tolerance of the mixed-precision forms against plain FP64 on
+    the same problem: build (with the FP32/BF16 factored copies) + solve to
+    ||b - A x|| / ||b|| <= tol."""
+    import torch
+    x64 = torch.zeros_like(b)
+    res = {"fp64": {"time_to_tol_ms": t_f64, "iters": it_f64}}
+    tb = time.perf_counter()
+    pc = fc.Precond(pb, store=fc.STORE_F64 | fc.STORE_F32 | fc.STORE_BF16)
+    torch.cuda.synchronize()
+    build = (time.perf_counter() - tb) * 1e3
+    fc.pcg_solve(pb, pc, b, x64, tol=tol, stop="residual")
+    for mode in ("s_bf16", "s_f32", "ir_f32", "ir_bf16"):
+        x = torch.zeros_like(b)
+        r = fc.pcg_solve(pb, pc, b, x, tol=tol, stop="residual", mode=mode, inner_tol=1e-2,
+                         maxit=60000)
+        diff = float((x - x64).norm() / x64.norm())
+        res[mode] = {"time_to_tol_ms": build + r["ms_solve"], "solve_ms": r["ms_solve"],
+                     "build_ms": build, "iters": r["iters"], "outer": r["outer_iters"],
+                     "fallbacks": r["fallbacks"], "status": r["status"],
+                     "rel_res_true": r["rel_res_true"], "rel_diff_vs_fp64": diff,
+                     "speedup_vs_fp64": t_f64 / (build + r["ms_solve"])}
+        log(f"form {mode}: {r['iters']} iterations, {r['ms_solve']:.0f} ms, {r['status']}")
+    del pc
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -102,6 +129,8 @@ def main():
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--small", action="store_true", help="8^3-cell check run")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-forms", action="store_true",
+                    help="skip the mixed-precision forms comparison")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
@@ -190,6 +219,8 @@ def main():
         "rel_res_true": res[-1][1]["rel_res_true"],
         "precond": pinfo, "host_assembly_s": t_asm,
     }
+    if not args.no_forms:
+        out["forms"] = forms(fc, pb, b, args.tol, out["time_to_tol_ms"][-1], iters[-1])
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out), flush=True)

@@ -194,7 +194,21 @@ fc_status fc_apply_M(fc_precond pc, const double* r_dev, double* z_dev,
  *                300000 in the paper's vertebra study) or after maxit
  *   stop         FC_STOP_PRECOND: ||S r_i|| / ||S b|| (Eq. 12, recurrence
  *                residual); FC_STOP_RESIDUAL: ||r_i|| / ||b||
- *   mode         FC_MODE_F64 plain FP64 PCG
+ *   mode         FC_MODE_F64 plain FP64 PCG;
+ *                FC_MODE_IR_F32 / FC_MODE_IR_BF16: iterative refinement --
+ *                the FP64 residual b - A x is recomputed outside, and each
+ *                correction comes from a PCG run with the FP32 copy of A and
+ *                the FP32 / BF16 factored copy of the local inverses (built
+ *                with FC_STORE_F32 / FC_STORE_BF16), FP32 accumulation, FP64
+ *                vectors and scalars, stopped at inner_tol (relative to
+ *                its right-hand side) or at breakdown.  A correction that
+ *                does not reduce the FP64 residual by 10 % is undone and the
+ *                remaining inner runs use the FP64 matrix (counted in
+ *                fc_solve_info.fallbacks).  tol then applies to
+ *                ||b - A x|| / ||b|| whatever `stop` says;
+ *                FC_MODE_S_F32 / FC_MODE_S_BF16: one PCG run with the FP64
+ *                matrix and the FP32 / BF16 factored local inverses as the
+ *                preconditioner (positive semi-definite however rounded)
  *   check_every  iterations between host checks of the device stop flag
  *   history_dev  optional device buffer of maxit+1 doubles receiving the
  *                relative stop criterion of every iteration, or NULL
@@ -203,7 +217,8 @@ fc_status fc_apply_M(fc_precond pc, const double* r_dev, double* z_dev,
  *                events on the solver stream (fc_solve_info.ms_spmv,
  *                ms_schwarz); costs a few microseconds per iteration */
 enum { FC_STOP_PRECOND = 0, FC_STOP_RESIDUAL = 1 };
-enum { FC_MODE_F64 = 0 };
+enum { FC_MODE_F64 = 0, FC_MODE_IR_F32 = 1, FC_MODE_IR_BF16 = 2, FC_MODE_S_F32 = 3,
+       FC_MODE_S_BF16 = 4 };
 typedef struct {
   double tol;
   int64_t maxit;
@@ -216,7 +231,7 @@ typedef struct {
 } fc_solve_opts;
 
 typedef struct {
-  int64_t iters;          /* products with A in the (inner) iteration     */
+  int64_t iters;          /* products with A inside the PCG iterations    */
   int64_t outer_iters;    /* refinement steps (1 for plain PCG)          */
   double rel_res_true;    /* ||b - A x|| / ||b|| recomputed at the end   */
   double rel_res_prec;    /* last ||S r_i|| / ||S b||                    */
@@ -225,6 +240,7 @@ typedef struct {
   double ms_spmv;         /* timing mode: summed SpMV kernel time          */
   double ms_schwarz;      /* timing mode: summed block-product kernel time */
   int64_t n_timed;        /* timing mode: iterations those sums cover      */
+  int64_t fallbacks;      /* IR modes: switches to the FP64 matrix         */
 } fc_solve_info;
 
 /* Preconditioned CG (Sec. 5, with S of Eq. 6) from x = 0: b_dev and x_dev

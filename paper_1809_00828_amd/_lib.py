@@ -23,7 +23,7 @@ PDE = {"poisson": 0, "elasticity": 1}
 DOMAIN = {"voids": 0, "inclusions": 1}
 STORE_F64, STORE_F32, STORE_BF16 = 1, 2, 4
 STOP = {"precond": 0, "residual": 1}
-MODE = {"f64": 0, "ir_f32": 1, "ir_bf16": 2, "learned": 3}
+MODE = {"f64": 0, "ir_f32": 1, "ir_bf16": 2, "s_f32": 3, "s_bf16": 4}
 
 # every symbol include/fc.h declares
 EXPORTS = [
@@ -66,7 +66,7 @@ class SolveInfo(C.Structure):
     _fields_ = [("iters", C.c_int64), ("outer_iters", C.c_int64),
                 ("rel_res_true", C.c_double), ("rel_res_prec", C.c_double),
                 ("status", C.c_int32), ("ms_solve", C.c_double), ("ms_spmv", C.c_double),
-                ("ms_schwarz", C.c_double), ("n_timed", C.c_int64)]
+                ("ms_schwarz", C.c_double), ("n_timed", C.c_int64), ("fallbacks", C.c_int64)]
 
 
 _lib = None
@@ -341,4 +341,5 @@ def pcg_solve(problem: Problem, precond: Precond, b, x, tol=1e-10, maxit=300000,
             "rel_res_true": info.rel_res_true, "rel_res_prec": info.rel_res_prec,
             "status": STATUS_NAMES.get(info.status if st == FC_OK else st, st),
             "ms_solve": info.ms_solve, "ms_spmv": info.ms_spmv,
-            "ms_schwarz": info.ms_schwarz, "n_timed": info.n_timed}
+            "ms_schwarz": info.ms_schwarz, "n_timed": info.n_timed,
+            "fallbacks": info.fallbacks}

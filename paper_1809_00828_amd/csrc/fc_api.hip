@@ -24,8 +24,8 @@ namespace fc {
 static thread_local std::string g_err;
 void set_error(const std::string& msg) { g_err = msg; }
 
-fc_status pcg_solve_f64(fc_precond_s& pc, const double* b, double* x, const fc_solve_opts& o,
-                        fc_solve_info* info, hipStream_t user);
+fc_status pcg_solve(fc_precond_s& pc, const double* b, double* x, const fc_solve_opts& o,
+                    fc_solve_info* info, hipStream_t user);
 
 template <class T>
 static fc_status dev_alloc(T** p, size_t count) {
@@ -66,7 +66,7 @@ static void free_problem(fc_problem_s* pb) {
 static void free_precond(fc_precond_s* pc) {
   if (!pc) return;
   solver_ws_destroy(pc->ws);
-  for (void* p : {(void*)pc->block_elem, (void*)pc->P, (void*)pc->Q, (void*)pc->Q32, (void*)pc->Qbf,
+  for (void* p : {(void*)pc->block_elem, (void*)pc->P, (void*)pc->Q, (void*)pc->L32, (void*)pc->Lbf, (void*)pc->isd,
                   (void*)pc->inv_ptr, (void*)pc->inv_idx, (void*)pc->fallback, (void*)pc->y})
     if (p) (void)hipFree(p);
   delete pc;
@@ -453,15 +453,16 @@ fc_status fc_precond_build(fc_problem pb, const fc_precond_opts* opts, void* str
   // wrapped-diagonal symmetric copies streamed by the block products
   const size_t qn = (size_t)nb * sym_block_stride(m);
   FC_TRY(dev_alloc(&pc->Q, qn));
-  FC_HIP(launch_pack_sym(pc->P, pc->Q, 0, m, nb, s));
-  if (o.store_mask & FC_STORE_F32) {
-    FC_TRY(dev_alloc(&pc->Q32, qn));
-    FC_HIP(launch_pack_sym(pc->P, pc->Q32, 1, m, nb, s));
+  FC_HIP(launch_pack_sym(*pc, pc->Q, 0, s));
+  if (o.store_mask & (FC_STORE_F32 | FC_STORE_BF16)) {
+    FC_TRY(dev_alloc(&pc->isd, (size_t)pb->n_dofs));
+    FC_HIP(launch_inv_sqrt_diag(*pb, pc->isd, s));
   }
-  if (o.store_mask & FC_STORE_BF16) {
-    FC_TRY(dev_alloc(&pc->Qbf, qn));
-    FC_HIP(launch_pack_sym(pc->P, pc->Qbf, 2, m, nb, s));
-  }
+  // positive semi-definite low-precision copies: scaled Cholesky factors
+  const size_t ln = (size_t)nb * ((size_t)m * (m + 1) / 2);
+  if (o.store_mask & FC_STORE_F32) FC_TRY(dev_alloc(&pc->L32, ln));
+  if (o.store_mask & FC_STORE_BF16) FC_TRY(dev_alloc(&pc->Lbf, ln));
+  if (pc->L32 || pc->Lbf) FC_HIP(launch_chol_pack(*pc, s));
   unsigned long long cnt = 0;
   std::vector<int32_t> drop(std::max<int64_t>(nb, 1));
   FC_HIP(hipMemcpyAsync(&cnt, d_count, sizeof(cnt), hipMemcpyDeviceToHost, s));
@@ -516,11 +517,11 @@ fc_status fc_pcg_solve(fc_problem pb, fc_precond pc, const double* b_dev, double
     set_error("fc_pcg_solve: invalid options");
     return FC_E_ARG;
   }
-  if (o.mode != FC_MODE_F64) {
+  if (o.mode < FC_MODE_F64 || o.mode > FC_MODE_S_BF16) {
     set_error("fc_pcg_solve: unsupported mode");
     return FC_E_UNSUPPORTED;
   }
-  return pcg_solve_f64(*pc, b_dev, x_dev, o, info, (hipStream_t)stream);
+  return pcg_solve(*pc, b_dev, x_dev, o, info, (hipStream_t)stream);
 }
 
 void fc_problem_destroy(fc_problem pb) { free_problem(pb); }

@@ -80,8 +80,9 @@ struct fc_precond_s {
   int32_t* block_elem = nullptr;   // [n_blocks] element of each block
   double* P = nullptr;             // [n_blocks*m*m] FP64 local inverses (dense)
   double* Q = nullptr;             // wrapped-diagonal symmetric copy, FP64
-  float* Q32 = nullptr;            // optional FP32 wrapped-diagonal copy
-  uint16_t* Qbf = nullptr;         // optional BF16 wrapped-diagonal copy
+  float* L32 = nullptr;            // optional FP32 scaled Cholesky factors
+  uint16_t* Lbf = nullptr;         // optional BF16 scaled Cholesky factors
+  double* isd = nullptr;           // [n_dofs] 1/sqrt(A_ll), scaling of L32/Lbf
   int32_t* inv_ptr = nullptr;      // [n_nodes+1] node -> (block, local node)
   int32_t* inv_idx = nullptr;      // entries: block*m + local_node*bdim
   double* fallback = nullptr;      // [n_dofs] 1/A_ll where S_ll = 0, else 0

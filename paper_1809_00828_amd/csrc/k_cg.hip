@@ -25,13 +25,21 @@
 
 #include "dev_common.h"
 #include "k_schwarz.h"
+#include "k_setup.h"
 #include "k_spmv.h"
+
+#define FC_TRY_ST(x)               \
+  do {                             \
+    fc_status s_ = (x);            \
+    if (s_ != FC_OK) return s_;    \
+  } while (0)
 
 namespace fc {
 
 struct SolverWs {
   int64_t n = 0;
   double *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr, *t = nullptr;
+  double *d = nullptr, *ro = nullptr;   // refinement correction and outer residual
   double* partial = nullptr;
   int64_t partial_len = 0;
   CgScalars* sc = nullptr;
@@ -42,6 +50,7 @@ struct SolverWs {
   hipGraph_t graph = nullptr;
   const void* key[4] = {nullptr, nullptr, nullptr, nullptr};
   int key_chunk = 0, key_prec = -1;
+  const void* key_b = nullptr;
   std::vector<hipEvent_t> tev;  // timing mode: 4 events per step of a chunk
 };
 
@@ -49,7 +58,7 @@ void solver_ws_destroy(SolverWs* w) {
   if (!w) return;
   if (w->exec) (void)hipGraphExecDestroy(w->exec);
   if (w->graph) (void)hipGraphDestroy(w->graph);
-  for (auto* p : {w->r, w->z, w->p, w->q, w->t, w->partial}) if (p) (void)hipFree(p);
+  for (auto* p : {w->r, w->z, w->p, w->q, w->t, w->d, w->ro, w->partial}) if (p) (void)hipFree(p);
   if (w->sc) (void)hipFree(w->sc);
   if (w->host) (void)hipHostFree(w->host);
   for (auto& e : w->ev) if (e) (void)hipEventDestroy(e);
@@ -217,6 +226,21 @@ __global__ void k_copy(const double* __restrict__ a, double* __restrict__ b, int
     b[i] = a[i];
 }
 
+__global__ void k_axpy(double alpha, const double* __restrict__ a, double* __restrict__ b,
+                       int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    b[i] = fma(alpha, a[i], b[i]);
+}
+
+// c = a - b
+__global__ void k_sub(const double* __restrict__ a, const double* __restrict__ b,
+                      double* __restrict__ c, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    c[i] = a[i] - b[i];
+}
+
 __global__ void k_fill(double* __restrict__ a, double v, int64_t n) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x)
@@ -286,20 +310,22 @@ static fc_status ensure_ws(fc_precond_s& pc, SolverWs** out) {
 }
 
 // Enqueue `chunk` PCG steps on stream s (with timing events when tev).
-static hipError_t enqueue_steps(fc_precond_s& pc, SolverWs& w, double* x, int chunk,
-                                int prec, hipStream_t s, hipEvent_t* tev = nullptr) {
+// precA: 0 = FP64 matrix, 1 = FP32 copy; precS: 0/1/2 = FP64/FP32/BF16
+// local inverses.
+static hipError_t enqueue_steps(fc_precond_s& pc, SolverWs& w, double* x, int chunk, int precA,
+                                int precS, hipStream_t s, hipEvent_t* tev = nullptr) {
   fc_problem_s& pb = *pc.pb;
   const int64_t n = pb.n_dofs;
   for (int it = 0; it < chunk; ++it) {
     hipError_t e;
     if (tev && (e = hipEventRecord(tev[4 * it + 0], s)) != hipSuccess) return e;
-    e = launch_spmv_pq(pb.A, false, w.p, w.q, w.sc, w.partial, s);
+    e = launch_spmv_pq(pb.A, precA == 1, w.p, w.q, w.sc, w.partial, s);
     if (e != hipSuccess) return e;
     if (tev && (e = hipEventRecord(tev[4 * it + 1], s)) != hipSuccess) return e;
     hipLaunchKernelGGL(k_cg_alpha, dim3(1), dim3(1024), 0, s, w.partial, spmv_num_blocks(pb.A),
                        w.sc);
     if (tev && (e = hipEventRecord(tev[4 * it + 2], s)) != hipSuccess) return e;
-    e = launch_schwarz_phase1(pc, prec, w.r, w.q, w.sc, s);
+    e = launch_schwarz_phase1(pc, precS, w.r, w.q, w.sc, s);
     if (e != hipSuccess) return e;
     if (tev && (e = hipEventRecord(tev[4 * it + 3], s)) != hipSuccess) return e;
     const unsigned pg = pull_grid(n);
@@ -314,68 +340,75 @@ static hipError_t enqueue_steps(fc_precond_s& pc, SolverWs& w, double* x, int ch
   return hipSuccess;
 }
 
-fc_status pcg_solve_f64(fc_precond_s& pc, const double* b, double* x, const fc_solve_opts& o,
-                        fc_solve_info* info, hipStream_t user) {
+struct CoreArgs {
+  const double* b;
+  double* x;
+  double tol;
+  int64_t maxit;
+  int stop, precA, precS, timing, chunk;
+  double* history;
+};
+
+struct CoreResult {
+  int done = 0;
+  int64_t iters = 0;
+  double crit = 0, zz = 0, zn0 = 0;
+  double t_spmv = 0, t_schw = 0;
+  int64_t n_timed = 0;
+};
+
+// One PCG run from x = 0 on the solver stream s.
+static fc_status pcg_core(fc_precond_s& pc, SolverWs& w, const CoreArgs& a, CoreResult* res,
+                          hipStream_t s) {
   fc_problem_s& pb = *pc.pb;
   const int64_t n = pb.n_dofs;
-  SolverWs* wp = nullptr;
-  fc_status st = ensure_ws(pc, &wp);
-  if (st != FC_OK) return st;
-  SolverWs& w = *wp;
-  hipStream_t s = w.stream;
-  FC_HIP(hipEventRecord(w.ev[0], user));
-  FC_HIP(hipStreamWaitEvent(s, w.ev[0], 0));
-
   CgScalars init{};
-  init.tol = o.tol;
-  init.maxit = o.maxit;
-  init.stop = o.stop;
-  init.history = o.history_dev;
+  init.tol = a.tol;
+  init.maxit = a.maxit;
+  init.stop = a.stop;
+  init.history = a.history;
   FC_HIP(hipMemcpyAsync(w.sc, &init, sizeof(CgScalars), hipMemcpyHostToDevice, s));
-  FC_HIP(hipEventRecord(w.ev[1], s));
   // x = 0, r = b, z = S r, p = z
-  hipLaunchKernelGGL(k_fill, dim3(1024), dim3(256), 0, s, x, 0.0, n);
-  hipLaunchKernelGGL(k_copy, dim3(1024), dim3(256), 0, s, b, w.r, n);
+  hipLaunchKernelGGL(k_fill, dim3(1024), dim3(256), 0, s, a.x, 0.0, n);
+  hipLaunchKernelGGL(k_copy, dim3(1024), dim3(256), 0, s, a.b, w.r, n);
   FC_HIP(hipGetLastError());
-  FC_HIP(launch_schwarz_apply(pc, w.r, w.z, s));
+  FC_HIP(launch_schwarz_phase1(pc, a.precS, w.r, nullptr, nullptr, s));
+  FC_HIP(launch_schwarz_pull(pc, w.r, w.z, s));
   hipLaunchKernelGGL(k_copy, dim3(1024), dim3(256), 0, s, w.z, w.p, n);
   hipLaunchKernelGGL(k_cg_start, dim3(kRedBlocks), dim3(256), 0, s, w.r, w.z, n, w.partial,
                      w.sc);
   FC_HIP(hipGetLastError());
-
-  const int chunk = o.check_every > 0 ? o.check_every : 16;
-  const int prec = 0;
-  double t_spmv = 0.0, t_schw = 0.0;
-  int64_t n_timed = 0;
-  if (o.timing) {
-    // direct launches with events around the two streaming kernels
+  const int chunk = a.chunk > 0 ? a.chunk : 16;
+  const int prec = a.precA * 4 + a.precS;
+  const int64_t max_chunks = (a.maxit + chunk - 1) / chunk + 1;
+  int64_t launched = 0;
+  if (a.timing) {
     if ((int)w.tev.size() < 4 * chunk) {
       size_t old = w.tev.size();
       w.tev.resize(4 * chunk, nullptr);
       for (size_t i = old; i < w.tev.size(); ++i) FC_HIP(hipEventCreate(&w.tev[i]));
     }
-    int64_t iter_before = 0, launched = 0;
-    const int64_t max_chunks = (o.maxit + chunk - 1) / chunk + 1;
+    int64_t iter_before = 0;
     for (;;) {
-      FC_HIP(enqueue_steps(pc, w, x, chunk, prec, s, w.tev.data()));
+      FC_HIP(enqueue_steps(pc, w, a.x, chunk, a.precA, a.precS, s, w.tev.data()));
       ++launched;
       FC_HIP(hipMemcpyAsync(w.host, w.sc, sizeof(CgScalars), hipMemcpyDeviceToHost, s));
       FC_HIP(hipStreamSynchronize(s));
       const int64_t ran = std::min<int64_t>(chunk, w.host->iter - iter_before);
       iter_before = w.host->iter;
       for (int64_t it = 0; it < ran; ++it) {
-        float a = 0.f, b = 0.f;
-        FC_HIP(hipEventElapsedTime(&a, w.tev[4 * it + 0], w.tev[4 * it + 1]));
-        FC_HIP(hipEventElapsedTime(&b, w.tev[4 * it + 2], w.tev[4 * it + 3]));
-        t_spmv += a;
-        t_schw += b;
+        float t0 = 0.f, t1 = 0.f;
+        FC_HIP(hipEventElapsedTime(&t0, w.tev[4 * it + 0], w.tev[4 * it + 1]));
+        FC_HIP(hipEventElapsedTime(&t1, w.tev[4 * it + 2], w.tev[4 * it + 3]));
+        res->t_spmv += t0;
+        res->t_schw += t1;
       }
-      n_timed += ran;
+      res->n_timed += ran;
       if (w.host->done != 0 || launched > max_chunks) break;
     }
   } else {
-    // (re)capture the chunk when the buffers or the chunk length change
-    if (!w.exec || w.key[0] != x || w.key_chunk != chunk || w.key_prec != prec) {
+    // (re)capture the chunk when the buffers, precisions or length change
+    if (!w.exec || w.key[0] != a.x || w.key_chunk != chunk || w.key_prec != prec) {
       if (w.exec) {
         FC_HIP(hipGraphExecDestroy(w.exec));
         w.exec = nullptr;
@@ -385,19 +418,17 @@ fc_status pcg_solve_f64(fc_precond_s& pc, const double* b, double* x, const fc_s
         w.graph = nullptr;
       }
       FC_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-      hipError_t e = enqueue_steps(pc, w, x, chunk, prec, s);
+      hipError_t e = enqueue_steps(pc, w, a.x, chunk, a.precA, a.precS, s);
       hipGraph_t g = nullptr;
       hipError_t e2 = hipStreamEndCapture(s, &g);
       if (e != hipSuccess) FC_HIP(e);
       FC_HIP(e2);
       w.graph = g;
       FC_HIP(hipGraphInstantiate(&w.exec, g, nullptr, nullptr, 0));
-      w.key[0] = x;
+      w.key[0] = a.x;
       w.key_chunk = chunk;
       w.key_prec = prec;
     }
-    int64_t launched = 0;
-    const int64_t max_chunks = (o.maxit + chunk - 1) / chunk + 1;
     for (;;) {
       FC_HIP(hipGraphLaunch(w.exec, s));
       ++launched;
@@ -406,40 +437,144 @@ fc_status pcg_solve_f64(fc_precond_s& pc, const double* b, double* x, const fc_s
       if (w.host->done != 0 || launched > max_chunks) break;
     }
   }
-  FC_HIP(hipEventRecord(w.ev[2], s));
-  // true residual ||b - A x|| / ||b||
-  FC_HIP(launch_spmv(pb.A, x, w.t, s));
+  const CgScalars& h = *w.host;
+  res->done = h.done;
+  res->iters = h.iter;
+  res->crit = h.crit;
+  res->zz = h.zz;
+  res->zn0 = h.zn0;
+  return FC_OK;
+}
+
+// ||b - A x|| / ||b|| with the FP64 matrix; t receives A x.
+static fc_status true_residual(fc_precond_s& pc, SolverWs& w, const double* b, const double* x,
+                               double* t, hipStream_t s, double* rel, double* out_r = nullptr) {
+  fc_problem_s& pb = *pc.pb;
+  const int64_t n = pb.n_dofs;
+  FC_HIP(launch_spmv(pb.A, x, t, s));
+  if (out_r) hipLaunchKernelGGL(k_sub, dim3(1024), dim3(256), 0, s, b, t, out_r, n);
   double* out2 = w.partial + w.partial_len - 2;
-  hipLaunchKernelGGL(k_resid, dim3(kRedBlocks), dim3(256), 0, s, b, w.t, n, w.partial, w.sc,
-                     out2);
+  hipLaunchKernelGGL(k_resid, dim3(kRedBlocks), dim3(256), 0, s, b, t, n, w.partial, w.sc, out2);
   FC_HIP(hipGetLastError());
-  double res[2] = {0, 0};
-  FC_HIP(hipMemcpyAsync(res, out2, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
-  FC_HIP(hipMemcpyAsync(w.host, w.sc, sizeof(CgScalars), hipMemcpyDeviceToHost, s));
+  FC_HIP(hipMemcpyAsync(w.host, out2, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+  FC_HIP(hipStreamSynchronize(s));
+  const double* v = reinterpret_cast<const double*>(w.host);
+  *rel = v[1] > 0 ? std::sqrt(v[0] / v[1]) : 0.0;
+  return FC_OK;
+}
+
+static fc_status status_of(int done) {
+  switch (done) {
+    case 1: return FC_OK;
+    case 2: return FC_E_NOTCONV;
+    case 3: return FC_E_BREAKDOWN;
+    case 4: return FC_E_NAN;
+  }
+  return FC_E_NOTCONV;
+}
+
+fc_status pcg_solve(fc_precond_s& pc, const double* b, double* x, const fc_solve_opts& o,
+                    fc_solve_info* info, hipStream_t user) {
+  fc_problem_s& pb = *pc.pb;
+  const int64_t n = pb.n_dofs;
+  SolverWs* wp = nullptr;
+  fc_status st = ensure_ws(pc, &wp);
+  if (st != FC_OK) return st;
+  SolverWs& w = *wp;
+  hipStream_t s = w.stream;
+  FC_HIP(hipEventRecord(w.ev[0], user));
+  FC_HIP(hipStreamWaitEvent(s, w.ev[0], 0));
+  FC_HIP(hipEventRecord(w.ev[1], s));
+
+  fc_status result = FC_OK;
+  int64_t iters = 0, outer = 1;
+  double rel_true = 0.0, rel_prec = 0.0;
+  CoreResult acc;
+  int64_t fallbacks = 0;
+  const bool low_s = o.mode == FC_MODE_S_F32 || o.mode == FC_MODE_S_BF16 ||
+                     o.mode == FC_MODE_IR_F32 || o.mode == FC_MODE_IR_BF16;
+  const int precS = !low_s ? 0
+                    : (o.mode == FC_MODE_S_F32 || o.mode == FC_MODE_IR_F32) ? 1 : 2;
+  if ((precS == 1 && !pc.L32) || (precS == 2 && !pc.Lbf)) {
+    set_error("fc_pcg_solve: the preconditioner holds no copy in the requested precision");
+    return FC_E_ARG;
+  }
+  if (o.mode == FC_MODE_F64 || o.mode == FC_MODE_S_F32 || o.mode == FC_MODE_S_BF16) {
+    // one PCG run with the FP64 matrix (and a low-precision S if asked)
+    CoreArgs a{b, x, o.tol, o.maxit, o.stop, 0, precS, o.timing, o.check_every, o.history_dev};
+    FC_TRY_ST(pcg_core(pc, w, a, &acc, s));
+    iters = acc.iters;
+    rel_prec = acc.zn0 > 0 ? std::sqrt(acc.zz) / acc.zn0 : 0.0;
+    FC_HIP(hipEventRecord(w.ev[2], s));
+    FC_TRY_ST(true_residual(pc, w, b, x, w.t, s, &rel_true));
+    result = status_of(acc.done);
+  } else {
+    // iterative refinement: FP64 residual outside, low-precision PCG inside.
+    // A correction that does not reduce the FP64 residual is undone and the
+    // inner solves continue with the FP64 matrix (FP32 rounding can make
+    // the stored matrix indefinite on the low-energy fictitious modes).
+    int precA = 1;
+    if (!pb.A.val32) {
+      FC_HIP(hipMalloc(&pb.A.val32, pb.A.nnzb * pb.bdim * pb.bdim * sizeof(float)));
+      FC_HIP(launch_cast_matrix(pb.A, s));
+    }
+    if (!w.d) FC_HIP(hipMalloc(&w.d, n * sizeof(double)));
+    if (!w.ro) FC_HIP(hipMalloc(&w.ro, n * sizeof(double)));
+    hipLaunchKernelGGL(k_fill, dim3(1024), dim3(256), 0, s, x, 0.0, n);
+    hipLaunchKernelGGL(k_copy, dim3(1024), dim3(256), 0, s, b, w.ro, n);
+    FC_HIP(hipGetLastError());
+    const double inner_tol = o.inner_tol > 0 ? o.inner_tol : 1e-4;
+    result = FC_E_NOTCONV;
+    outer = 0;
+    double rel_prev = 1.0;
+    for (;;) {
+      ++outer;
+      CoreArgs a{w.ro, w.d, inner_tol, std::max<int64_t>(1, o.maxit - iters), FC_STOP_RESIDUAL,
+                 precA, precS, o.timing, o.check_every, nullptr};
+      CoreResult cr;
+      FC_TRY_ST(pcg_core(pc, w, a, &cr, s));
+      iters += cr.iters;
+      acc.t_spmv += cr.t_spmv;
+      acc.t_schw += cr.t_schw;
+      acc.n_timed += cr.n_timed;
+      hipLaunchKernelGGL(k_axpy, dim3(1024), dim3(256), 0, s, 1.0, w.d, x, n);
+      FC_HIP(hipGetLastError());
+      FC_TRY_ST(true_residual(pc, w, b, x, w.t, s, &rel_true, w.ro));
+      if (!(rel_true < 0.9 * rel_prev)) {
+        // undo the correction and restore the residual of the previous x
+        hipLaunchKernelGGL(k_axpy, dim3(1024), dim3(256), 0, s, -1.0, w.d, x, n);
+        FC_HIP(hipGetLastError());
+        FC_TRY_ST(true_residual(pc, w, b, x, w.t, s, &rel_true, w.ro));
+        if (precA == 0) break;    // no progress even with the FP64 matrix
+        precA = 0;
+        ++fallbacks;
+      } else {
+        rel_prev = rel_true;
+      }
+      if (rel_true <= o.tol) {
+        result = FC_OK;
+        break;
+      }
+      if (iters >= o.maxit || outer >= 1000) break;
+    }
+    FC_HIP(hipEventRecord(w.ev[2], s));
+  }
   FC_HIP(hipEventRecord(w.ev[3], s));
   FC_HIP(hipStreamSynchronize(s));
   FC_HIP(hipStreamWaitEvent(user, w.ev[3], 0));
   float ms = 0.f;
   FC_HIP(hipEventElapsedTime(&ms, w.ev[1], w.ev[2]));
-  const CgScalars& h = *w.host;
-  fc_status result = FC_OK;
-  switch (h.done) {
-    case 1: result = FC_OK; break;
-    case 2: result = FC_E_NOTCONV; break;
-    case 3: result = FC_E_BREAKDOWN; break;
-    case 4: result = FC_E_NAN; break;
-    default: result = FC_E_NOTCONV; break;
-  }
   if (info) {
-    info->iters = h.iter;
-    info->outer_iters = 1;
-    info->rel_res_true = res[1] > 0 ? std::sqrt(res[0] / res[1]) : 0.0;
-    info->rel_res_prec = h.zn0 > 0 ? std::sqrt(h.zz) / h.zn0 : 0.0;
+    info->iters = iters;
+    info->outer_iters = outer;
+    info->rel_res_true = rel_true;
+    info->rel_res_prec = rel_prec;
     info->status = result;
     info->ms_solve = ms;
-    info->ms_spmv = t_spmv;
-    info->ms_schwarz = t_schw;
-    info->n_timed = n_timed;
+    info->ms_spmv = acc.t_spmv;
+    info->ms_schwarz = acc.t_schw;
+    info->n_timed = acc.n_timed;
+    info->fallbacks = fallbacks;
   }
   return result;
 }

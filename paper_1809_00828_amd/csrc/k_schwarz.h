@@ -13,8 +13,9 @@ hipError_t launch_schwarz_pull(const fc_precond_s& pc, const double* r, double* 
                                hipStream_t s);
 // Elements per block of the wrapped-diagonal symmetric layout, (m/2+1)*m.
 int64_t sym_block_stride(int m);
-// Q = wrapped-diagonal copy of the dense FP64 local inverses P in FP64 (0),
-// FP32 (1) or BF16 (2).
-hipError_t launch_pack_sym(const double* P, void* Q, int precision, int m, int64_t n_blocks,
-                           hipStream_t s);
+// Q = wrapped-diagonal copy of the dense FP64 local inverses pc.P in FP64
+// (0), or diagonally scaled in FP32 (1) or BF16 (2) (needs pc.isd).
+hipError_t launch_pack_sym(const fc_precond_s& pc, void* Q, int precision, hipStream_t s);
+// isd = 1/sqrt(diag(A)) (1 where the diagonal is not positive).
+hipError_t launch_inv_sqrt_diag(const fc_problem_s& pb, double* isd, hipStream_t s);
 }  // namespace fc

@@ -22,6 +22,7 @@
 // Phase 2 (pull): every unknown sums the y_B entries of the blocks that
 // contain it, in a fixed order (no atomics, bitwise reproducible), and adds
 // its diagonal-scaling term.
+#include <algorithm>
 #include <cstdlib>
 
 #include "dev_common.h"
@@ -114,7 +115,7 @@ template <typename T, bool kSym>
 __global__ __launch_bounds__(256) void k_schwarz_large(
     const T* __restrict__ P, int64_t block_stride, const int32_t* __restrict__ elem_nodes,
     const int32_t* __restrict__ block_elem, int nn, int bd, int m,
-    const double* __restrict__ r, const double* __restrict__ q,
+    const double* __restrict__ r, const double* __restrict__ q, const double* __restrict__ isd,
     const CgScalars* __restrict__ sc, double* __restrict__ y, int64_t n_blocks) {
   __shared__ double rB[256];
   if (sc && sc->done) return;
@@ -123,14 +124,16 @@ __global__ __launch_bounds__(256) void k_schwarz_large(
   const double alpha = (sc && q) ? sc->alpha : 0.0;
   const int i = threadIdx.x;
   const int64_t e = block_elem[blk];
+  int64_t dof = 0;
   if (i < m) {
-    const int64_t dof = (int64_t)elem_nodes[e * nn + i / bd] * bd + (i % bd);
-    rB[i] = gather_r(r, q, alpha, dof);
+    dof = (int64_t)elem_nodes[e * nn + i / bd] * bd + (i % bd);
+    rB[i] = gather_r(r, q, alpha, dof) * (isd ? isd[dof] : 1.0);
   }
   __syncthreads();
   if (i >= m) return;
   const T* Pb = P + blk * block_stride;
-  y[blk * m + i] = kSym ? sym_row<T>(Pb, rB, m, i) : dense_row<T>(Pb, rB, m, i);
+  const double v = kSym ? sym_row<T>(Pb, rB, m, i) : dense_row<T>(Pb, rB, m, i);
+  y[blk * m + i] = isd ? v * isd[dof] : v;
 }
 
 // m > 64, symmetric layout staged through LDS: chunks of kRows stored rows
@@ -143,7 +146,7 @@ template <typename T>
 __global__ __launch_bounds__(256) void k_schwarz_sym_staged(
     const T* __restrict__ P, int64_t block_stride, const int32_t* __restrict__ elem_nodes,
     const int32_t* __restrict__ block_elem, int nn, int bd, int m,
-    const double* __restrict__ r, const double* __restrict__ q,
+    const double* __restrict__ r, const double* __restrict__ q, const double* __restrict__ isd,
     const CgScalars* __restrict__ sc, double* __restrict__ y, int64_t n_blocks) {
   using A = typename Acc<T>::type;
   __shared__ double rB[256];
@@ -155,9 +158,10 @@ __global__ __launch_bounds__(256) void k_schwarz_sym_staged(
   const int i = threadIdx.x;
   const bool act = i < m;
   const int64_t e = block_elem[blk];
+  int64_t dof = 0;
   if (act) {
-    const int64_t dof = (int64_t)elem_nodes[e * nn + i / bd] * bd + (i % bd);
-    rB[i] = gather_r(r, q, alpha, dof);
+    dof = (int64_t)elem_nodes[e * nn + i / bd] * bd + (i % bd);
+    rB[i] = gather_r(r, q, alpha, dof) * (isd ? isd[dof] : 1.0);
   }
   const T* Qb = P + blk * block_stride;
   const int h = m / 2;
@@ -191,7 +195,10 @@ __global__ __launch_bounds__(256) void k_schwarz_sym_staged(
       }
     }
   }
-  if (act) y[blk * m + i] = (double)acc0 + (double)acc1;
+  if (act) {
+    const double v = (double)acc0 + (double)acc1;
+    y[blk * m + i] = isd ? v * isd[dof] : v;
+  }
 }
 
 // m <= 64: each wave handles floor(64/m) blocks, one lane per output row.
@@ -199,7 +206,7 @@ template <typename T, bool kSym>
 __global__ __launch_bounds__(256) void k_schwarz_small(
     const T* __restrict__ P, int64_t block_stride, const int32_t* __restrict__ elem_nodes,
     const int32_t* __restrict__ block_elem, int nn, int bd, int m,
-    const double* __restrict__ r, const double* __restrict__ q,
+    const double* __restrict__ r, const double* __restrict__ q, const double* __restrict__ isd,
     const CgScalars* __restrict__ sc, double* __restrict__ y, int64_t n_blocks) {
   __shared__ double rB[4][64];
   if (sc && sc->done) return;
@@ -210,16 +217,180 @@ __global__ __launch_bounds__(256) void k_schwarz_small(
   const int64_t tile = xcd_remap(blockIdx.x, gridDim.x);
   const int64_t blk = (tile * 4 + w) * bpw + lb;
   const bool active = lb < bpw && blk < n_blocks;
+  int64_t dof = 0;
   if (active) {
     const int64_t e = block_elem[blk];
-    const int64_t dof = (int64_t)elem_nodes[e * nn + i / bd] * bd + (i % bd);
-    rB[w][l] = gather_r(r, q, alpha, dof);
+    dof = (int64_t)elem_nodes[e * nn + i / bd] * bd + (i % bd);
+    rB[w][l] = gather_r(r, q, alpha, dof) * (isd ? isd[dof] : 1.0);
   }
   __syncthreads();
   if (!active) return;
   const double* rb = &rB[w][lb * m];
   const T* Pb = P + blk * block_stride;
-  y[blk * m + i] = kSym ? sym_row<T>(Pb, rb, m, i) : dense_row<T>(Pb, rb, m, i);
+  const double v = kSym ? sym_row<T>(Pb, rb, m, i) : dense_row<T>(Pb, rb, m, i);
+  y[blk * m + i] = isd ? v * isd[dof] : v;
+}
+
+// Factored low-precision product y_B = D^{-1/2} Lt (Lt^T (D^{-1/2} r_B)) with
+// Lt packed by subdiagonals (k_setup.hip).  The whole packed factor of a
+// block is staged in LDS with 16-byte loads, then both triangular passes
+// read it from LDS:
+//   t_j = sum_d Lt[off_d + j] r_{j+d}        (lane j, d = 0 .. m-1-j)
+//   y_i = sum_d Lt[off_d + i - d] t_{i-d}    (lane i, d = 0 .. i)
+// Each pass reads consecutive LDS words across lanes.  FP32 accumulation.
+template <typename T>
+__device__ __forceinline__ void stage_packed(const T* __restrict__ src, T* dst, int64_t count,
+                                             int tid, int nt) {
+  // 16-byte chunks where the block start is 16-byte aligned, else scalar
+  const uintptr_t addr = reinterpret_cast<uintptr_t>(src);
+  constexpr int V = 16 / sizeof(T);
+  if ((addr % 16) == 0) {
+    const int64_t nv = count / V;
+    typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+    const u32x4* s4 = reinterpret_cast<const u32x4*>(src);
+    u32x4* d4 = reinterpret_cast<u32x4*>(dst);
+    for (int64_t c = tid; c < nv; c += nt) d4[c] = __builtin_nontemporal_load(s4 + c);
+    for (int64_t c = nv * V + tid; c < count; c += nt) dst[c] = src[c];
+  } else {
+    for (int64_t c = tid; c < count; c += nt) dst[c] = __builtin_nontemporal_load(src + c);
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ float ld_f32(const T* p) {
+  if constexpr (sizeof(T) == 4)
+    return *p;
+  else
+    return bf16_to_f32(*p);
+}
+
+// One block per workgroup (m > 64) or several per wave (m <= 64): the
+// caller sets up rb (scaled gathered residual) and the staged factor Lb.
+template <typename T>
+__device__ __forceinline__ float chol_pass1(const T* Lb, const float* rb, int m, int j) {
+  float t0 = 0.f, t1 = 0.f;
+  int64_t off = 0;
+  int d = 0;
+  for (; d + 1 <= m - 1 - j; d += 2) {
+    t0 = fmaf(ld_f32(Lb + off + j), rb[j + d], t0);
+    off += m - d;
+    t1 = fmaf(ld_f32(Lb + off + j), rb[j + d + 1], t1);
+    off += m - d - 1;
+  }
+  if (d <= m - 1 - j) t0 = fmaf(ld_f32(Lb + off + j), rb[j + d], t0);
+  return t0 + t1;
+}
+
+template <typename T>
+__device__ __forceinline__ float chol_pass2(const T* Lb, const float* tb, int m, int i) {
+  float y0 = 0.f, y1 = 0.f;
+  int64_t off = 0;
+  int d = 0;
+  for (; d + 1 <= i; d += 2) {
+    y0 = fmaf(ld_f32(Lb + off + i - d), tb[i - d], y0);
+    off += m - d;
+    y1 = fmaf(ld_f32(Lb + off + i - d - 1), tb[i - d - 1], y1);
+    off += m - d - 1;
+  }
+  if (d <= i) y0 = fmaf(ld_f32(Lb + off + i - d), tb[i - d], y0);
+  return y0 + y1;
+}
+
+constexpr int kCholLdsBytes = 75000;   // FP32 factor of m = 192: 74,112 bytes
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_schwarz_chol_large(
+    const T* __restrict__ L, const int32_t* __restrict__ elem_nodes,
+    const int32_t* __restrict__ block_elem, int nn, int bd, int m,
+    const double* __restrict__ r, const double* __restrict__ q, const double* __restrict__ isd,
+    const CgScalars* __restrict__ sc, double* __restrict__ y, int64_t n_blocks) {
+  extern __shared__ __align__(16) unsigned char dyn_lds[];
+  __shared__ float rb[256], tb[256];
+  if (sc && sc->done) return;
+  const int64_t blk = xcd_remap(blockIdx.x, gridDim.x);
+  if (blk >= n_blocks) return;
+  const double alpha = (sc && q) ? sc->alpha : 0.0;
+  const int i = threadIdx.x;
+  const int64_t per = (int64_t)m * (m + 1) / 2;
+  T* Lb = reinterpret_cast<T*>(dyn_lds);
+  stage_packed<T>(L + blk * per, Lb, per, i, blockDim.x);
+  const int64_t e = block_elem[blk];
+  int64_t dof = 0;
+  double s = 1.0;
+  if (i < m) {
+    dof = (int64_t)elem_nodes[e * nn + i / bd] * bd + (i % bd);
+    s = isd[dof];
+    rb[i] = (float)(gather_r(r, q, alpha, dof) * s);
+  }
+  __syncthreads();
+  if (i < m) tb[i] = chol_pass1<T>(Lb, rb, m, i);
+  __syncthreads();
+  if (i < m) y[blk * m + i] = (double)chol_pass2<T>(Lb, tb, m, i) * s;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_schwarz_chol_small(
+    const T* __restrict__ L, const int32_t* __restrict__ elem_nodes,
+    const int32_t* __restrict__ block_elem, int nn, int bd, int m,
+    const double* __restrict__ r, const double* __restrict__ q, const double* __restrict__ isd,
+    const CgScalars* __restrict__ sc, double* __restrict__ y, int64_t n_blocks) {
+  extern __shared__ __align__(16) unsigned char dyn_lds[];
+  __shared__ float rb[4][64], tb[4][64];
+  if (sc && sc->done) return;
+  const double alpha = (sc && q) ? sc->alpha : 0.0;
+  const int bpw = 64 / m;
+  const int w = threadIdx.x / 64, l = threadIdx.x % 64;
+  const int lb = l / m, i = l % m;
+  const int64_t tile = xcd_remap(blockIdx.x, gridDim.x);
+  const int64_t blk0 = tile * 4 * bpw;                 // first block of the workgroup
+  const int64_t nwb = std::min<int64_t>(4 * bpw, n_blocks - blk0);
+  const int64_t per = (int64_t)m * (m + 1) / 2;
+  T* Ls = reinterpret_cast<T*>(dyn_lds);
+  if (nwb > 0) stage_packed<T>(L + blk0 * per, Ls, nwb * per, threadIdx.x, blockDim.x);
+  const int64_t blk = (tile * 4 + w) * bpw + lb;
+  const bool active = lb < bpw && blk < n_blocks;
+  int64_t dof = 0;
+  double s = 1.0;
+  if (active) {
+    const int64_t e = block_elem[blk];
+    dof = (int64_t)elem_nodes[e * nn + i / bd] * bd + (i % bd);
+    s = isd[dof];
+    rb[w][l] = (float)(gather_r(r, q, alpha, dof) * s);
+  }
+  __syncthreads();
+  const T* Lb = Ls + (blk - blk0) * per;
+  if (active) tb[w][l] = chol_pass1<T>(Lb, &rb[w][lb * m], m, i);
+  __syncthreads();
+  if (active) y[blk * m + i] = (double)chol_pass2<T>(Lb, &tb[w][lb * m], m, i) * s;
+}
+
+template <typename T>
+static hipError_t phase1_chol(const fc_precond_s& pc, const T* L, const double* r,
+                              const double* q, const CgScalars* sc, hipStream_t s) {
+  const fc_problem_s& pb = *pc.pb;
+  if (pc.n_blocks == 0) return hipSuccess;
+  const int m = pc.m;
+  const int64_t per = (int64_t)m * (m + 1) / 2;
+  if (m > 64) {
+    const int threads = 64 * ((m + 63) / 64);
+    const size_t lds = (size_t)per * sizeof(T);
+    (void)hipFuncSetAttribute((const void*)k_schwarz_chol_large<T>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipLaunchKernelGGL(k_schwarz_chol_large<T>, dim3((unsigned)pc.n_blocks), dim3(threads), lds,
+                       s, L, pb.elem_nodes, pc.block_elem, pc.nn, pc.bdim, m, r, q, pc.isd, sc,
+                       pc.y, pc.n_blocks);
+  } else {
+    const int bpw = 64 / m;
+    const int64_t per_wg = 4 * (int64_t)bpw;
+    const int64_t nwg = (pc.n_blocks + per_wg - 1) / per_wg;
+    const size_t lds = (size_t)(per_wg * per) * sizeof(T);
+    (void)hipFuncSetAttribute((const void*)k_schwarz_chol_small<T>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipLaunchKernelGGL(k_schwarz_chol_small<T>, dim3((unsigned)nwg), dim3(256), lds, s, L,
+                       pb.elem_nodes, pc.block_elem, pc.nn, pc.bdim, m, r, q, pc.isd, sc, pc.y,
+                       pc.n_blocks);
+  }
+  return hipGetLastError();
 }
 
 // Phase 2: z_i = sum over blocks containing i of y_B[slot] + fb_i * r_i.
@@ -237,9 +408,15 @@ __global__ __launch_bounds__(256) void k_schwarz_pull(
 }
 
 // Wrapped-diagonal copy: Q[blk][k][i] = P[blk][i][(i+k) mod m], k <= m/2.
+// With isd (low-precision copies) the stored block is the diagonally
+// scaled D^{1/2} P_B D^{1/2} (D = diag(A) on the block's unknowns, isd =
+// D^{-1/2}), which removes the 1/alpha dynamic range of fictitious
+// functions before rounding; the apply undoes the scaling in FP64.
 template <typename T>
 __global__ void k_pack_sym(const double* __restrict__ P, T* __restrict__ Q, int m,
-                           int64_t n_blocks) {
+                           int64_t n_blocks, const double* __restrict__ isd,
+                           const int32_t* __restrict__ elem_nodes,
+                           const int32_t* __restrict__ block_elem, int nn, int bd) {
   const int h = m / 2;
   const int64_t per = (int64_t)(h + 1) * m;
   const int64_t total = per * n_blocks;
@@ -250,7 +427,13 @@ __global__ void k_pack_sym(const double* __restrict__ P, T* __restrict__ Q, int 
     const int k = (int)(rem / m), i = (int)(rem - (int64_t)k * m);
     int j = i + k;
     if (j >= m) j -= m;
-    const double v = P[blk * (int64_t)m * m + (int64_t)i * m + j];
+    double v = P[blk * (int64_t)m * m + (int64_t)i * m + j];
+    if (isd) {
+      const int64_t e = block_elem[blk];
+      const int64_t di = (int64_t)elem_nodes[e * nn + i / bd] * bd + (i % bd);
+      const int64_t dj = (int64_t)elem_nodes[e * nn + j / bd] * bd + (j % bd);
+      v = v / (isd[di] * isd[dj]);
+    }
     if constexpr (sizeof(T) == 8) {
       Q[t] = v;
     } else if constexpr (sizeof(T) == 4) {
@@ -266,22 +449,45 @@ __global__ void k_pack_sym(const double* __restrict__ P, T* __restrict__ Q, int 
 
 int64_t sym_block_stride(int m) { return (int64_t)(m / 2 + 1) * m; }
 
-hipError_t launch_pack_sym(const double* P, void* Q, int precision, int m, int64_t n_blocks,
-                           hipStream_t s) {
-  if (n_blocks == 0) return hipSuccess;
+hipError_t launch_pack_sym(const fc_precond_s& pc, void* Q, int precision, hipStream_t s) {
+  const int64_t nb = pc.n_blocks;
+  const int m = pc.m;
+  if (nb == 0) return hipSuccess;
   dim3 g(8192), b(256);
+  const int32_t* en = pc.pb->elem_nodes;
   switch (precision) {
-    case 0: hipLaunchKernelGGL(k_pack_sym<double>, g, b, 0, s, P, (double*)Q, m, n_blocks); break;
-    case 1: hipLaunchKernelGGL(k_pack_sym<float>, g, b, 0, s, P, (float*)Q, m, n_blocks); break;
-    case 2: hipLaunchKernelGGL(k_pack_sym<uint16_t>, g, b, 0, s, P, (uint16_t*)Q, m, n_blocks); break;
+    case 0:
+      hipLaunchKernelGGL(k_pack_sym<double>, g, b, 0, s, pc.P, (double*)Q, m, nb, nullptr, en,
+                         pc.block_elem, pc.nn, pc.bdim);
+      break;
+    case 1:
+      hipLaunchKernelGGL(k_pack_sym<float>, g, b, 0, s, pc.P, (float*)Q, m, nb, pc.isd, en,
+                         pc.block_elem, pc.nn, pc.bdim);
+      break;
+    case 2:
+      hipLaunchKernelGGL(k_pack_sym<uint16_t>, g, b, 0, s, pc.P, (uint16_t*)Q, m, nb, pc.isd, en,
+                         pc.block_elem, pc.nn, pc.bdim);
+      break;
     default: return hipErrorInvalidValue;
   }
+  return hipGetLastError();
+}
+
+__global__ void k_inv_sqrt_diag(const double* __restrict__ d, double* __restrict__ isd, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    isd[i] = d[i] > 0.0 ? 1.0 / sqrt(d[i]) : 1.0;
+}
+
+hipError_t launch_inv_sqrt_diag(const fc_problem_s& pb, double* isd, hipStream_t s) {
+  hipLaunchKernelGGL(k_inv_sqrt_diag, dim3(1024), dim3(256), 0, s, pb.diag, isd, pb.n_dofs);
   return hipGetLastError();
 }
 
 template <typename T, bool kSym>
 static hipError_t phase1(const fc_precond_s& pc, const T* P, const double* r, const double* q,
                          const CgScalars* sc, hipStream_t s) {
+  const double* isd = sizeof(T) == 8 ? nullptr : pc.isd;
   const fc_problem_s& pb = *pc.pb;
   if (pc.n_blocks == 0) return hipSuccess;
   const int64_t stride = kSym ? sym_block_stride(pc.m) : (int64_t)pc.m * pc.m;
@@ -294,17 +500,17 @@ static hipError_t phase1(const fc_precond_s& pc, const T* P, const double* r, co
     if (kSym && variant)
       hipLaunchKernelGGL((k_schwarz_sym_staged<T>), dim3((unsigned)pc.n_blocks), dim3(threads),
                          0, s, P, stride, pb.elem_nodes, pc.block_elem, pc.nn, pc.bdim, pc.m, r,
-                         q, sc, pc.y, pc.n_blocks);
+                         q, isd, sc, pc.y, pc.n_blocks);
     else
       hipLaunchKernelGGL((k_schwarz_large<T, kSym>), dim3((unsigned)pc.n_blocks), dim3(threads),
                          0, s, P, stride, pb.elem_nodes, pc.block_elem, pc.nn, pc.bdim, pc.m, r,
-                         q, sc, pc.y, pc.n_blocks);
+                         q, isd, sc, pc.y, pc.n_blocks);
   } else {
     const int bpw = 64 / pc.m;
     const int64_t per_wg = 4 * (int64_t)bpw;
     const int64_t nwg = (pc.n_blocks + per_wg - 1) / per_wg;
     hipLaunchKernelGGL((k_schwarz_small<T, kSym>), dim3((unsigned)nwg), dim3(256), 0, s, P, stride,
-                       pb.elem_nodes, pc.block_elem, pc.nn, pc.bdim, pc.m, r, q, sc, pc.y,
+                       pb.elem_nodes, pc.block_elem, pc.nn, pc.bdim, pc.m, r, q, isd, sc, pc.y,
                        pc.n_blocks);
   }
   return hipGetLastError();
@@ -317,11 +523,11 @@ hipError_t launch_schwarz_phase1(const fc_precond_s& pc, int precision, const do
       if (pc.Q) return phase1<double, true>(pc, pc.Q, r, q, sc, s);
       return phase1<double, false>(pc, pc.P, r, q, sc, s);
     case 1:
-      if (!pc.Q32) return hipErrorInvalidValue;
-      return phase1<float, true>(pc, pc.Q32, r, q, sc, s);
+      if (!pc.L32) return hipErrorInvalidValue;
+      return phase1_chol<float>(pc, pc.L32, r, q, sc, s);
     case 2:
-      if (!pc.Qbf) return hipErrorInvalidValue;
-      return phase1<uint16_t, true>(pc, pc.Qbf, r, q, sc, s);
+      if (!pc.Lbf) return hipErrorInvalidValue;
+      return phase1_chol<uint16_t>(pc, pc.Lbf, r, q, sc, s);
   }
   return hipErrorInvalidValue;
 }

@@ -291,6 +291,131 @@ __global__ __launch_bounds__(1024) void k_sweep_inverse(
   if (tid == 0) need_eig[blk] = 0;
 }
 
+// ------------------------------------------- factored low-precision copy
+// P_B = L L^T (lower Cholesky factor of the FP64 local inverse; a pivot at
+// or below 1e-14 * max diag(P_B) zeroes its column, which is exact for the
+// null modes of a pseudo-inverse).  The stored factor is the diagonally
+// scaled Lt = D^{1/2} L (D = diag(A) on the block, isd = D^{-1/2}), so
+// Lt Lt^T = D^{1/2} P_B D^{1/2}, packed by subdiagonals:
+//     diagonal d (i - j = d) at offset d*m - d*(d-1)/2, entry j.
+// However it is rounded, Lt Lt^T stays positive semi-definite, which is
+// what keeps CG with an FP32/BF16 preconditioner meaningful.
+// Thread (ti, tj) of a GRID x GRID grid holds the T x T tile at rows
+// ti*T.., columns tj*T..; the pivot row is broadcast through LDS.
+__device__ __forceinline__ uint16_t f32_to_bf16(float f) {
+  uint32_t u = __float_as_uint(f);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+
+template <int GRID, int T>
+__global__ __launch_bounds__(GRID * GRID) void k_chol_pack(
+    const double* __restrict__ P, int m, const double* __restrict__ isd,
+    const int32_t* __restrict__ elem_nodes, const int32_t* __restrict__ block_elem, int nn,
+    int bd, float* __restrict__ L32, uint16_t* __restrict__ Lbf) {
+  __shared__ double rowbuf[2][GRID * T];
+  __shared__ double red[16];
+  __shared__ double sc[GRID * T];
+  const int64_t blk = blockIdx.x;
+  const double* Pb = P + blk * (int64_t)m * m;
+  const int tid = threadIdx.x, ti = tid / GRID, tj = tid % GRID;
+  const int64_t e = block_elem[blk];
+  for (int i = tid; i < m; i += GRID * GRID) {
+    const int64_t dof = (int64_t)elem_nodes[e * nn + i / bd] * bd + (i % bd);
+    sc[i] = 1.0 / isd[dof];   // sqrt(A_ii)
+  }
+  double a[T][T];
+  double dmax = 0.0;
+#pragma unroll
+  for (int r = 0; r < T; ++r)
+#pragma unroll
+    for (int c = 0; c < T; ++c) {
+      const int i = ti * T + r, j = tj * T + c;
+      a[r][c] = (i < m && j < m) ? Pb[(int64_t)i * m + j] : 0.0;
+      if (i == j && i < m) dmax = fmax(dmax, a[r][c]);
+    }
+  {
+    double v = dmax;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+    if (tid % 64 == 0) red[tid / 64] = v;
+    __syncthreads();
+    v = 0.0;
+    for (int w = 0; w < (GRID * GRID + 63) / 64; ++w) v = fmax(v, red[w]);
+    dmax = v;
+  }
+  const double tiny = 1e-14 * dmax;
+  for (int k = 0; k < m; ++k) {
+    double* buf = rowbuf[k & 1];
+    if (ti == k / T) {
+      const int r = k % T;
+#pragma unroll
+      for (int rr = 0; rr < T; ++rr)
+        if (rr == r) {
+#pragma unroll
+          for (int c = 0; c < T; ++c) buf[tj * T + c] = a[rr][c];
+        }
+    }
+    __syncthreads();
+    const double d = buf[k];
+    const bool live = d > tiny;
+    const double lkk = live ? sqrt(d) : 0.0;
+    const double rl = live ? 1.0 / lkk : 0.0;
+#pragma unroll
+    for (int r = 0; r < T; ++r) {
+      const int i = ti * T + r;
+      if (i < k || i >= m) continue;
+      const double li = (i == k) ? lkk : buf[i] * rl;
+#pragma unroll
+      for (int c = 0; c < T; ++c) {
+        const int j = tj * T + c;
+        if (j < k || j >= m) continue;
+        if (j == k) {
+          a[r][c] = li;                       // L[i][k]
+        } else if (i > k) {
+          a[r][c] -= li * (buf[j] * rl);      // trailing update with L[j][k]
+        }
+      }
+    }
+  }
+  __syncthreads();
+  // write the scaled lower triangle by subdiagonals
+  const int64_t per = (int64_t)m * (m + 1) / 2;
+#pragma unroll
+  for (int r = 0; r < T; ++r)
+#pragma unroll
+    for (int c = 0; c < T; ++c) {
+      const int i = ti * T + r, j = tj * T + c;
+      if (i >= m || j > i) continue;
+      const int dg = i - j;
+      const int64_t pos = blk * per + (int64_t)dg * m - (int64_t)dg * (dg - 1) / 2 + j;
+      const double v = a[r][c] * sc[i];
+      if (L32) L32[pos] = (float)v;
+      if (Lbf) Lbf[pos] = f32_to_bf16((float)v);
+    }
+}
+
+hipError_t launch_chol_pack(fc_precond_s& pc, hipStream_t s) {
+  const int m = pc.m;
+  const int64_t nb = pc.n_blocks;
+  if (nb == 0) return hipSuccess;
+  dim3 g((unsigned)nb);
+  const fc_problem_s& pb = *pc.pb;
+#define FC_CHOL(GR, TT)                                                                     \
+  hipLaunchKernelGGL((k_chol_pack<GR, TT>), g, dim3(GR * GR), 0, s, pc.P, m, pc.isd,       \
+                     pb.elem_nodes, pc.block_elem, pc.nn, pc.bdim, pc.L32, pc.Lbf)
+  if (m <= 8) FC_CHOL(8, 1);
+  else if (m <= 16) FC_CHOL(8, 2);
+  else if (m <= 32) FC_CHOL(8, 4);
+  else if (m <= 64) FC_CHOL(8, 8);
+  else if (m <= 96) FC_CHOL(32, 3);
+  else if (m <= 128) FC_CHOL(32, 4);
+  else if (m <= 160) FC_CHOL(32, 5);
+  else FC_CHOL(32, 6);
+#undef FC_CHOL
+  return hipGetLastError();
+}
+
 // ---------------------------------------------------- diagonal / fallback
 __global__ void k_diag(const int32_t* __restrict__ rowptr, const int32_t* __restrict__ col,
                        const double* __restrict__ val, int bd, int64_t n_rows,

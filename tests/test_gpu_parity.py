@@ -274,3 +274,47 @@ def test_invalid_arguments_raise(torch):
         pb.apply_A(x, x)
     with pytest.raises(fc.FcError):
         fc.Precond(pb, eps=-1.0)
+
+
+# ------------------------------------------------------ precision forms
+FORMS = ["s_f32", "s_bf16", "ir_f32", "ir_bf16"]
+
+
+@pytest.mark.parametrize("name", ["disk16_p2", "elast3d_p3", "pois3d_p2"])
+@pytest.mark.parametrize("mode", FORMS)
+def test_precision_forms_reach_tolerance(torch, name, mode):
+    """Low-precision forms solve to the same FP64 residual; their error
+    against the oracle's direct solution is reported and must stay within
+    10x of what plain FP64 PCG reaches at the same tolerance."""
+    print(f"[form] {name} {mode}", flush=True)
+    _, s = oracle_system(name)
+    A = s["A"]
+    pb = lib_problem(name)
+    pc = fc.Precond(pb, store=fc.STORE_F64 | fc.STORE_F32 | fc.STORE_BF16)
+    b = torch.empty(pb.n, dtype=torch.float64, device="cuda")
+    pb.rhs(b)
+    tol = 1e-8
+    x64 = torch.zeros_like(b)
+    i64 = fc.pcg_solve(pb, pc, b, x64, tol=tol, stop="residual")
+    x = torch.zeros_like(b)
+    info = fc.pcg_solve(pb, pc, b, x, tol=tol, stop="residual", mode=mode, inner_tol=1e-2,
+                        maxit=200000)
+    assert info["status"] == "OK", info
+    assert info["rel_res_true"] <= tol
+    xr = oracle_direct(name)
+    e64 = energy(A, x64.cpu().numpy() - xr) / energy(A, xr)
+    e = energy(A, x.cpu().numpy() - xr) / energy(A, xr)
+    print(f"[form] {name} {mode}: iters {info['iters']} (fp64 {i64['iters']}), "
+          f"outer {info['outer_iters']}, fallbacks {info['fallbacks']}, "
+          f"energy error {e:.2e} (fp64 {e64:.2e})", flush=True)
+    assert e <= 10 * e64 + 1e-12
+
+
+def test_low_precision_copies_required(torch):
+    pb = lib_problem("disk16_p2")
+    pc = fc.Precond(pb)
+    b = torch.empty(pb.n, dtype=torch.float64, device="cuda")
+    pb.rhs(b)
+    x = torch.zeros_like(b)
+    with pytest.raises(fc.FcError):
+        fc.pcg_solve(pb, pc, b, x, mode="s_bf16", raise_on_error=True)
