@@ -251,6 +251,33 @@ fc_status fc_pcg_solve(fc_problem pb, fc_precond pc, const double* b_dev,
                        double* x_dev, const fc_solve_opts* opts,
                        fc_solve_info* info, void* stream);
 
+/* Batched solves (many independent problems, one set of launches).
+ * fc_batch_create groups nprob problems with their preconditioners (built
+ * by fc_precond_build, FP64) into one batch: shape classes, segmented work
+ * lists of (problem, tile), per-problem CG scalars.  With autotune != 0 it
+ * times the SpMV group widths and the block-product variants of every
+ * shape class on the batch's own data and keeps the fastest (the choices
+ * and timings are in the report of fc_batch_info).  The handles must
+ * outlive the batch.  Errors: FC_E_ARG, FC_E_NOMEM, FC_E_DEVICE.
+ * fc_pcg_solve_batch runs FP64 PCG (Sec. 5 with S of Eq. 6) on every
+ * problem from x = 0; b_dev and x_dev are host arrays of nprob device
+ * pointers (n_dofs of problem k each).  Every problem stops by its own
+ * test (opts->stop, opts->tol, opts->maxit); converged problems drop out of
+ * the work at once.  infos (may be NULL) receives one record per problem
+ * (rel_res_true holds the recurrence residual ||r_i||/||b||; ms_solve is
+ * the batch's time).  Returns FC_OK when every problem converged, else the
+ * first failure's status.  Synchronises the stream. */
+typedef struct fc_batch_s* fc_batch;
+fc_status fc_batch_create(int32_t nprob, const fc_problem* problems,
+                          const fc_precond* preconds, int32_t autotune,
+                          void* stream, fc_batch* out);
+fc_status fc_batch_info(fc_batch bt, int64_t* total_dofs, int32_t* n_spmv_classes,
+                        int32_t* n_schwarz_classes, char* report, int64_t report_len);
+fc_status fc_pcg_solve_batch(fc_batch bt, const double* const* b_dev,
+                             double* const* x_dev, const fc_solve_opts* opts,
+                             fc_solve_info* infos, void* stream);
+void fc_batch_destroy(fc_batch bt);
+
 void fc_problem_destroy(fc_problem pb);
 void fc_precond_destroy(fc_precond pc);
 const char* fc_last_error(void);

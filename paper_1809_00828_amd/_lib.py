@@ -32,6 +32,7 @@ EXPORTS = [
     "fc_problem_info", "fc_get_rhs", "fc_get_eta", "fc_export", "fc_apply_A",
     "fc_precond_build", "fc_precond_info", "fc_get_block_inverse", "fc_apply_M",
     "fc_pcg_solve", "fc_problem_destroy", "fc_precond_destroy", "fc_last_error",
+    "fc_batch_create", "fc_batch_info", "fc_pcg_solve_batch", "fc_batch_destroy",
 ]
 
 
@@ -101,12 +102,16 @@ def load():
         "fc_get_block_inverse": [vp, i64, vp],
         "fc_apply_M": [vp, dp, dp, vp],
         "fc_pcg_solve": [vp, vp, dp, dp, P(SolveOpts), P(SolveInfo), vp],
+        "fc_batch_create": [i32, vp, vp, i32, vp, P(vp)],
+        "fc_batch_info": [vp, P(i64), P(i32), P(i32), C.c_char_p, i64],
+        "fc_pcg_solve_batch": [vp, vp, vp, P(SolveOpts), vp, vp],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
         f.argtypes = args
         f.restype = C.c_int
-    for name in ("fc_problem_destroy", "fc_precond_destroy", "fc_host_system_destroy"):
+    for name in ("fc_problem_destroy", "fc_precond_destroy", "fc_host_system_destroy",
+                 "fc_batch_destroy"):
         f = getattr(lib, name)
         f.argtypes = [vp]
         f.restype = None
@@ -343,3 +348,48 @@ def pcg_solve(problem: Problem, precond: Precond, b, x, tol=1e-10, maxit=300000,
             "ms_solve": info.ms_solve, "ms_spmv": info.ms_spmv,
             "ms_schwarz": info.ms_schwarz, "n_timed": info.n_timed,
             "fallbacks": info.fallbacks}
+
+
+class Batch:
+    """Many problems solved together (fc_batch_create / fc_pcg_solve_batch)."""
+
+    def __init__(self, problems, preconds, autotune=True, stream=None):
+        if len(problems) != len(preconds) or not problems:
+            raise FcError(FC_E_ARG, "need one preconditioner per problem")
+        self.problems = list(problems)
+        self.preconds = list(preconds)
+        k = len(problems)
+        hp = (C.c_void_p * k)(*[p._h.value for p in problems])
+        hc = (C.c_void_p * k)(*[c._h.value for c in preconds])
+        h = C.c_void_p()
+        _check(load().fc_batch_create(k, hp, hc, 1 if autotune else 0,
+                                      C.c_void_p(_stream(stream)), C.byref(h)))
+        self._h = h
+
+    def info(self):
+        tot, a, b = C.c_int64(), C.c_int32(), C.c_int32()
+        buf = C.create_string_buffer(1 << 16)
+        _check(load().fc_batch_info(self._h, C.byref(tot), C.byref(a), C.byref(b), buf,
+                                    len(buf)))
+        return {"total_dofs": tot.value, "spmv_classes": a.value, "schwarz_classes": b.value,
+                "report": buf.value.decode()}
+
+    def solve(self, bs, xs, tol=1e-8, maxit=300000, stop="precond", check_every=16,
+              stream=None):
+        k = len(self.problems)
+        bp = (C.c_void_p * k)(*[_dptr(t) for t in bs])
+        xp = (C.c_void_p * k)(*[_dptr(t) for t in xs])
+        o = SolveOpts(float(tol), int(maxit), STOP[stop], 0, int(check_every), 1e-4, None, 0)
+        infos = (SolveInfo * k)()
+        st = load().fc_pcg_solve_batch(self._h, bp, xp, C.byref(o), infos,
+                                       C.c_void_p(_stream(stream)))
+        if st not in (FC_OK, FC_E_NOTCONV, FC_E_BREAKDOWN, FC_E_NAN):
+            _check(st)
+        return [{"iters": i.iters, "status": STATUS_NAMES.get(i.status, i.status),
+                 "rel_res_prec": i.rel_res_prec, "rel_res": i.rel_res_true,
+                 "ms_solve": i.ms_solve} for i in infos]
+
+    def __del__(self):
+        if getattr(self, "_h", None) and _lib is not None:
+            _lib.fc_batch_destroy(self._h)
+            self._h = None
