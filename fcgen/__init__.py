@@ -31,7 +31,7 @@ import numpy as np
 
 __all__ = [
     "disk_poisson_2d", "porous_elasticity_3d", "porous_poisson_3d",
-    "batch_poisson", "custom", "n_dofs",
+    "batch_poisson", "custom", "n_dofs", "unet_init",
 ]
 
 
@@ -165,3 +165,19 @@ def batch_poisson(seed: int = 0, count: int = 512, min_dofs: int = 50_000,
                           domain=domain, modes=modes,
                           seed=seed * 100003 + len(out)))
     return out
+
+
+def unet_init(ch=(8, 16, 32, 32), in_ch=2, seed=0):
+    """Seeded He-normal initial parameters of the coarse-correction U-Net
+    (flat vector: per convolution W[co][ci][27] then b[co], layer order
+    enc0a enc0b enc1a enc1b enc2a enc2b bota botb up2a up2b up1a up1b up0a
+    up0b head), float32; biases start at zero."""
+    c0, c1, c2, c3 = ch
+    io = [(in_ch, c0), (c0, c0), (c0, c1), (c1, c1), (c1, c2), (c2, c2), (c2, c3), (c3, c3),
+          (c3, c2), (c2, c2), (c2, c1), (c1, c1), (c1, c0), (c0, c0), (c0, 1)]
+    rng = np.random.default_rng(seed)
+    parts = []
+    for ci, co in io:
+        parts.append(rng.standard_normal(co * ci * 27) * math.sqrt(2.0 / (27 * ci)))
+        parts.append(np.zeros(co))
+    return np.concatenate(parts).astype(np.float32)
