@@ -121,6 +121,64 @@ def forms(fc, pb, b, tol, t_f64, it_f64):
     return res
 
 
+def batch_bench(fc, args):
+    """Uneven batch of 2-D/3-D Poisson problems (grids 8^2..128^2 and
+    8^3..24^3, p = 1..4, elliptical inclusions or voids, alpha = 1e-10,
+    50k-200k DOFs each) solved together to ||r||/||b|| <= 1e-8."""
+    import torch
+    import fcgen
+    descs = fcgen.batch_poisson(seed=0, count=args.batch)
+    pbs, pcs = [], []
+    t0 = time.perf_counter()
+    for k, d in enumerate(descs):
+        hs = fc.HostSystem(d)
+        pbs.append(hs.upload())
+        del hs
+        pcs.append(fc.Precond(pbs[-1]))
+        if k % 16 == 15 or k == len(descs) - 1:
+            log(f"batch: {k + 1}/{len(descs)} problems assembled and preconditioned "
+                f"({time.perf_counter() - t0:.0f} s)")
+    torch.cuda.synchronize()
+    t_setup = time.perf_counter() - t0
+    tb = time.perf_counter()
+    batch = fc.Batch(pbs, pcs, autotune=True)
+    t_tune = time.perf_counter() - tb
+    info = batch.info()
+    log("batch: autotuned\n" + info["report"])
+    bs, xs = [], []
+    for p in pbs:
+        b = torch.empty(p.n, dtype=torch.float64, device="cuda")
+        p.rhs(b)
+        bs.append(b)
+        xs.append(torch.zeros_like(b))
+    # the library reports converged members every 64 chunks of 32 steps
+    os.environ.setdefault("FC_BATCH_PROGRESS", "64")
+    for _ in range(args.warmup):
+        batch.solve(bs, xs, tol=args.tol, stop="residual", check_every=32)
+        log("batch: warmup solve done")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        res = batch.solve(bs, xs, tol=args.tol, stop="residual", check_every=32)
+        log(f"batch: timed solve {k + 1}/{args.steps} done")
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) / args.steps
+    dof_iters = sum(p.n * r["iters"] for p, r in zip(pbs, res))
+    return {
+        "metric": METRIC + " (batched form)", "value": dof_iters / wall, "unit": "DOF·iter/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": wall * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"{len(descs)} uneven 2D/3D finite cell Poisson problems, "
+                               f"p=1..4, alpha=1e-10, one batch",
+                   "total_dofs": info["total_dofs"], "tol": args.tol},
+        "converged": sum(r["status"] == "OK" for r in res),
+        "iters_min": min(r["iters"] for r in res), "iters_max": max(r["iters"] for r in res),
+        "setup_s": t_setup, "batch_create_autotune_s": t_tune,
+        "classes": {"spmv": info["spmv_classes"], "schwarz": info["schwarz_classes"]},
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -131,6 +189,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-forms", action="store_true",
                     help="skip the mixed-precision forms comparison")
+    ap.add_argument("--batch", type=int, default=0,
+                    help="instead: solve this many problems of the uneven batch "
+                         "generator together (512 = the full batch)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
@@ -141,6 +202,9 @@ def main():
     import paper_1809_00828_amd as fc
 
     torch.cuda.set_device(0)
+    if args.batch:
+        print(json.dumps(batch_bench(fc, args)), flush=True)
+        return
     desc, wl = workload(args.small)
     t0 = time.perf_counter()
     hs = fc.HostSystem(desc)

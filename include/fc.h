@@ -208,7 +208,11 @@ fc_status fc_apply_M(fc_precond pc, const double* r_dev, double* z_dev,
  *                ||b - A x|| / ||b|| whatever `stop` says;
  *                FC_MODE_S_F32 / FC_MODE_S_BF16: one PCG run with the FP64
  *                matrix and the FP32 / BF16 factored local inverses as the
- *                preconditioner (positive semi-definite however rounded)
+ *                preconditioner (positive semi-definite however rounded);
+ *                FC_MODE_LEARNED: flexible CG (beta = -(z_new, A p)/(p, A p))
+ *                with z = S r + gamma P_c y, y the network attached with
+ *                fc_learned_attach (see there); always the residual stop
+ *                ||r_i|| / ||b||
  *   check_every  iterations between host checks of the device stop flag
  *   history_dev  optional device buffer of maxit+1 doubles receiving the
  *                relative stop criterion of every iteration, or NULL
@@ -218,7 +222,7 @@ fc_status fc_apply_M(fc_precond pc, const double* r_dev, double* z_dev,
  *                ms_schwarz); costs a few microseconds per iteration */
 enum { FC_STOP_PRECOND = 0, FC_STOP_RESIDUAL = 1 };
 enum { FC_MODE_F64 = 0, FC_MODE_IR_F32 = 1, FC_MODE_IR_BF16 = 2, FC_MODE_S_F32 = 3,
-       FC_MODE_S_BF16 = 4 };
+       FC_MODE_S_BF16 = 4, FC_MODE_LEARNED = 5 };
 typedef struct {
   double tol;
   int64_t maxit;
@@ -277,6 +281,99 @@ fc_status fc_pcg_solve_batch(fc_batch bt, const double* const* b_dev,
                              double* const* x_dev, const fc_solve_opts* opts,
                              fc_solve_info* infos, void* stream);
 void fc_batch_destroy(fc_batch bt);
+
+/* Learned coarse correction (the coarse level the paper's outlook, Sec. 6,
+ * names as the extension of the one-level Schwarz method).  A 4-level 3-D
+ * U-Net on the coarse vertex grid: widths ch[0..3], in_ch input channels,
+ * 'same' 3x3x3 convolutions, ReLU, average pooling over existing children,
+ * nearest upsampling, additive skips, a 1-channel head.  Parameters are one
+ * flat FP32 vector: per convolution W[co][ci][27] (tap dz*9+dy*3+dx) then
+ * b[co], in the order enc0a enc0b enc1a enc1b enc2a enc2b bota botb up2a
+ * up2b up1a up1b up0a up0b head.  Convolutions use a BF16 copy of the
+ * weights with FP32 activations and accumulation.
+ * Tensors are device buffers of FP32, layout [batch][channel][z][y][x]
+ * with a cubic grid of `grid` points per direction. */
+typedef struct fc_model_s* fc_model;
+typedef struct {
+  int32_t epochs;   /* passes over the samples                         */
+  int32_t batch;    /* samples per Adam step (mini-batch)              */
+  float lr;         /* Adam step size (beta1 0.9, beta2 0.999, eps 1e-8) */
+} fc_train_opts;
+fc_status fc_model_param_count(const int32_t* ch, int32_t in_ch, int64_t* n);
+/* params: host FP32 initial parameters (copied). */
+fc_status fc_model_create(const int32_t* ch, int32_t in_ch, const float* params,
+                          fc_model* out);
+fc_status fc_model_get_params(fc_model m, float* params_host);
+fc_status fc_model_set_params(fc_model m, const float* params_host);
+/* y = network(x): x [batch][in_ch][grid^3], y [batch][1][grid^3]. */
+fc_status fc_model_forward(fc_model m, int32_t batch, int32_t grid, const float* x_dev,
+                           float* y_dev, void* stream);
+/* Mean squared error against t and its gradient (FP32, copied to
+ * grad_host if not NULL; loss to *loss).  Synchronises the stream. */
+fc_status fc_model_loss_grad(fc_model m, int32_t batch, int32_t grid, const float* x_dev,
+                             const float* t_dev, double* loss, float* grad_host,
+                             void* stream);
+/* Adam on mini-batches over n_samples pairs (x, t) held on the device;
+ * mini-batch j of epoch e holds samples (j + i*steps + e) mod n.
+ * history (may be NULL) receives the mean loss of every epoch. */
+fc_status fc_model_train(fc_model m, int64_t n_samples, int32_t grid, const float* x_dev,
+                         const float* t_dev, const fc_train_opts* opts, double* history,
+                         void* stream);
+void fc_model_destroy(fc_model m);
+
+/* Coarse level of the learned correction, for a scalar 3-D lattice
+ * problem with an even number n of cells per direction (else
+ * FC_E_UNSUPPORTED).  The coarse grid has G = n/2 + 1 vertices per
+ * direction, vertex (a, b, c) at fine vertex (2a, 2b, 2c), stored at
+ * a + G (b + G c).  The vertex functions of the basis (Sec. 2) are the Q1
+ * hats of the cells, so P_c, trilinear interpolation from the coarse
+ * vertices written into the vertex unknowns (all other unknowns zero),
+ * represents coarse trilinear functions exactly; restriction is P_c^T and
+ * A_c = P_c^T A P_c (27-point, built once by 27 products with A).
+ * The correction after z = S r is
+ *   y = network(channel 0: P_c^T r at unit RMS, channel 1: eta of the
+ *       coarse vertex = mean over the touching coarse cells of their fine
+ *       cells' eta_T),
+ *   gamma = (y . P_c^T r) / (y . A_c y), z += gamma P_c y,
+ * with gamma = 0 (network term dropped) when the quotient is not a
+ * positive finite number, so (z, r) > 0 whenever (S r, r) > 0.
+ * The coarse context lives with the preconditioner and is built on first
+ * use by any of these calls. */
+
+/* Attach model m (or detach with NULL) for FC_MODE_LEARNED.  The
+ * preconditioner keeps a reference: m must outlive its use there. */
+fc_status fc_learned_attach(fc_precond pc, fc_model m);
+/* G, the coarse vertices per direction. */
+fc_status fc_coarse_grid(fc_precond pc, int32_t* G);
+/* Device FP32 copies of the eta channel and of the material mask (1 where
+ * the vertex function touches a cell with eta_T > 0); either may be NULL. */
+fc_status fc_coarse_channels(fc_precond pc, float* eta_dev, float* mask_dev);
+/* rc = P_c^T r (FP64, G^3 values). */
+fc_status fc_coarse_restrict(fc_precond pc, const double* r_dev, double* rc_dev,
+                             void* stream);
+/* z += gamma P_c y (y FP32 G^3 values, z FP64 n_dofs values).
+ * Synchronises the stream. */
+fc_status fc_coarse_prolong(fc_precond pc, const float* y_dev, double gamma, double* z_dev,
+                            void* stream);
+/* v = A_c y; *gamma receives (y . rc) / (y . A_c y) for the rc of the last
+ * fc_coarse_restrict (0 when not positive finite).  Synchronises. */
+fc_status fc_coarse_apply(fc_precond pc, const float* y_dev, double* v_dev, double* gamma,
+                          void* stream);
+/* Corrections applied and dropped since fc_learned_attach. */
+fc_status fc_learned_stats(fc_precond pc, int64_t* n_apply, int64_t* n_drop);
+/* Training pairs from a running FP64 Schwarz-PCG solve of A x = b from
+ * x = 0: at every iteration listed in iters (ascending; 0 is the start) the
+ * network input of the residual r_k goes to xin_dev + i*2*G^3 and the
+ * target to t_dev + i*G^3:
+ *   kind 0: mask * (x_star - x_k - S r_k) at the coarse vertices,
+ *   kind 1: mask * (x_star - x_k),
+ * scaled to unit RMS (x_star: the converged solution, device).  Stops
+ * early at convergence to tol (relative residual); *n_taken receives the
+ * number of pairs written. */
+fc_status fc_learned_snapshots(fc_precond pc, const double* b_dev, const double* x_star_dev,
+                               int32_t n_snap, const int32_t* iters, int32_t kind,
+                               double tol, float* xin_dev, float* t_dev, int32_t* n_taken,
+                               void* stream);
 
 void fc_problem_destroy(fc_problem pb);
 void fc_precond_destroy(fc_precond pc);

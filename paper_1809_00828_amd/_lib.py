@@ -23,7 +23,7 @@ PDE = {"poisson": 0, "elasticity": 1}
 DOMAIN = {"voids": 0, "inclusions": 1}
 STORE_F64, STORE_F32, STORE_BF16 = 1, 2, 4
 STOP = {"precond": 0, "residual": 1}
-MODE = {"f64": 0, "ir_f32": 1, "ir_bf16": 2, "s_f32": 3, "s_bf16": 4}
+MODE = {"f64": 0, "ir_f32": 1, "ir_bf16": 2, "s_f32": 3, "s_bf16": 4, "learned": 5}
 
 # every symbol include/fc.h declares
 EXPORTS = [
@@ -33,6 +33,10 @@ EXPORTS = [
     "fc_precond_build", "fc_precond_info", "fc_get_block_inverse", "fc_apply_M",
     "fc_pcg_solve", "fc_problem_destroy", "fc_precond_destroy", "fc_last_error",
     "fc_batch_create", "fc_batch_info", "fc_pcg_solve_batch", "fc_batch_destroy",
+    "fc_model_param_count", "fc_model_create", "fc_model_get_params", "fc_model_set_params",
+    "fc_model_forward", "fc_model_loss_grad", "fc_model_train", "fc_model_destroy",
+    "fc_learned_attach", "fc_coarse_grid", "fc_coarse_channels", "fc_coarse_restrict",
+    "fc_coarse_prolong", "fc_coarse_apply", "fc_learned_stats", "fc_learned_snapshots",
 ]
 
 
@@ -61,6 +65,10 @@ class SolveOpts(C.Structure):
     _fields_ = [("tol", C.c_double), ("maxit", C.c_int64), ("stop", C.c_int32),
                 ("mode", C.c_int32), ("check_every", C.c_int32), ("inner_tol", C.c_double),
                 ("history_dev", C.c_void_p), ("timing", C.c_int32)]
+
+
+class TrainOpts(C.Structure):
+    _fields_ = [("epochs", C.c_int32), ("batch", C.c_int32), ("lr", C.c_float)]
 
 
 class SolveInfo(C.Structure):
@@ -105,13 +113,28 @@ def load():
         "fc_batch_create": [i32, vp, vp, i32, vp, P(vp)],
         "fc_batch_info": [vp, P(i64), P(i32), P(i32), C.c_char_p, i64],
         "fc_pcg_solve_batch": [vp, vp, vp, P(SolveOpts), vp, vp],
+        "fc_model_param_count": [vp, i32, P(i64)],
+        "fc_model_create": [vp, i32, vp, P(vp)],
+        "fc_model_get_params": [vp, vp],
+        "fc_model_set_params": [vp, vp],
+        "fc_model_forward": [vp, i32, i32, dp, dp, vp],
+        "fc_model_loss_grad": [vp, i32, i32, dp, dp, P(C.c_double), vp, vp],
+        "fc_model_train": [vp, i64, i32, dp, dp, P(TrainOpts), vp, vp],
+        "fc_learned_attach": [vp, vp],
+        "fc_coarse_grid": [vp, P(i32)],
+        "fc_coarse_channels": [vp, dp, dp],
+        "fc_coarse_restrict": [vp, dp, dp, vp],
+        "fc_coarse_prolong": [vp, dp, C.c_double, dp, vp],
+        "fc_coarse_apply": [vp, dp, dp, P(C.c_double), vp],
+        "fc_learned_stats": [vp, P(i64), P(i64)],
+        "fc_learned_snapshots": [vp, dp, dp, i32, vp, i32, C.c_double, dp, dp, P(i32), vp],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
         f.argtypes = args
         f.restype = C.c_int
     for name in ("fc_problem_destroy", "fc_precond_destroy", "fc_host_system_destroy",
-                 "fc_batch_destroy"):
+                 "fc_batch_destroy", "fc_model_destroy"):
         f = getattr(lib, name)
         f.argtypes = [vp]
         f.restype = None
@@ -324,6 +347,53 @@ class Precond:
                                  C.c_void_p(_stream(stream))))
         return z
 
+    # ---- learned coarse correction (fc_learned_* / fc_coarse_*)
+    def attach(self, model):
+        """Attach a Model for mode="learned" (None detaches)."""
+        _check(load().fc_learned_attach(self._h, model._h if model is not None else None))
+        self._model = model        # the library keeps a reference
+
+    def coarse_grid(self):
+        g = C.c_int32()
+        _check(load().fc_coarse_grid(self._h, C.byref(g)))
+        return g.value
+
+    def coarse_channels(self, eta, mask):
+        _check(load().fc_coarse_channels(self._h, C.c_void_p(_fptr(eta)),
+                                         C.c_void_p(_fptr(mask))))
+
+    def coarse_restrict(self, r, rc, stream=None):
+        _check(load().fc_coarse_restrict(self._h, C.c_void_p(_dptr(r)), C.c_void_p(_dptr(rc)),
+                                          C.c_void_p(_stream(stream))))
+        return rc
+
+    def coarse_prolong(self, y, gamma, z, stream=None):
+        _check(load().fc_coarse_prolong(self._h, C.c_void_p(_fptr(y)), float(gamma),
+                                         C.c_void_p(_dptr(z)), C.c_void_p(_stream(stream))))
+        return z
+
+    def coarse_apply(self, y, v, stream=None):
+        g = C.c_double()
+        _check(load().fc_coarse_apply(self._h, C.c_void_p(_fptr(y)), C.c_void_p(_dptr(v)),
+                                       C.byref(g), C.c_void_p(_stream(stream))))
+        return g.value
+
+    def learned_stats(self):
+        a, d = C.c_int64(), C.c_int64()
+        _check(load().fc_learned_stats(self._h, C.byref(a), C.byref(d)))
+        return {"applied": a.value, "dropped": d.value}
+
+    def snapshots(self, b, x_star, iters, xin, t, kind="e-Sr", tol=1e-8, stream=None):
+        """Training pairs at the listed iterations (fc_learned_snapshots);
+        returns how many were written."""
+        it = np.ascontiguousarray(iters, dtype=np.int32)
+        k = C.c_int32()
+        _check(load().fc_learned_snapshots(
+            self._h, C.c_void_p(_dptr(b)), C.c_void_p(_dptr(x_star)), int(it.size), _np_ptr(it),
+            {"e-Sr": 0, "e": 1}[kind], float(tol), C.c_void_p(_fptr(xin)), C.c_void_p(_fptr(t)),
+            C.byref(k), C.c_void_p(_stream(stream))))
+        return k.value
+
     def __del__(self):
         if getattr(self, "_h", None) and _lib is not None:
             _lib.fc_precond_destroy(self._h)
@@ -392,4 +462,67 @@ class Batch:
     def __del__(self):
         if getattr(self, "_h", None) and _lib is not None:
             _lib.fc_batch_destroy(self._h)
+            self._h = None
+
+
+def _fptr(t):
+    """Device pointer of a contiguous FP32 CUDA tensor."""
+    import torch
+    if t.dtype != torch.float32 or not t.is_cuda or not t.is_contiguous():
+        raise FcError(FC_E_ARG, "expected a contiguous FP32 CUDA tensor")
+    return t.data_ptr()
+
+
+class Model:
+    """The learned coarse-correction network (fc_model_*)."""
+
+    def __init__(self, params, ch=(8, 16, 32, 32), in_ch=2):
+        self.ch = tuple(int(c) for c in ch)
+        self.in_ch = int(in_ch)
+        arr = (C.c_int32 * 4)(*self.ch)
+        n = C.c_int64()
+        _check(load().fc_model_param_count(arr, self.in_ch, C.byref(n)))
+        self.n_params = n.value
+        p = np.ascontiguousarray(params, dtype=np.float32)
+        if p.size != self.n_params:
+            raise FcError(FC_E_ARG, f"expected {self.n_params} parameters, got {p.size}")
+        h = C.c_void_p()
+        _check(load().fc_model_create(arr, self.in_ch, _np_ptr(p), C.byref(h)))
+        self._h = h
+
+    def params(self):
+        out = np.zeros(self.n_params, np.float32)
+        _check(load().fc_model_get_params(self._h, _np_ptr(out)))
+        return out
+
+    def set_params(self, params):
+        p = np.ascontiguousarray(params, dtype=np.float32)
+        _check(load().fc_model_set_params(self._h, _np_ptr(p)))
+
+    def forward(self, x, y, stream=None):
+        B, _, g = x.shape[0], x.shape[1], x.shape[2]
+        _check(load().fc_model_forward(self._h, B, g, C.c_void_p(_fptr(x)),
+                                       C.c_void_p(_fptr(y)), C.c_void_p(_stream(stream))))
+        return y
+
+    def loss_grad(self, x, t, stream=None):
+        B, g = x.shape[0], x.shape[2]
+        loss = C.c_double()
+        grad = np.zeros(self.n_params, np.float32)
+        _check(load().fc_model_loss_grad(self._h, B, g, C.c_void_p(_fptr(x)),
+                                         C.c_void_p(_fptr(t)), C.byref(loss), _np_ptr(grad),
+                                         C.c_void_p(_stream(stream))))
+        return loss.value, grad
+
+    def train(self, x, t, epochs=10, batch=8, lr=1e-3, stream=None):
+        n, g = x.shape[0], x.shape[2]
+        hist = np.zeros(epochs, np.float64)
+        o = TrainOpts(int(epochs), int(batch), float(lr))
+        _check(load().fc_model_train(self._h, n, g, C.c_void_p(_fptr(x)), C.c_void_p(_fptr(t)),
+                                     C.byref(o), _np_ptr(hist), C.c_void_p(_stream(stream))))
+        return hist
+
+    def __del__(self):
+        if getattr(self, "_h", None) and _lib is not None:
+            _lib.fc_model_destroy(self._h)
             self._h = None

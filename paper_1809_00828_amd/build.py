@@ -21,7 +21,7 @@ BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libfc.so")
 
 HIP_SOURCES = ["fc_api.hip", "k_spmv.hip", "k_setup.hip", "k_schwarz.hip", "k_cg.hip",
-               "k_batch.hip"]
+               "k_batch.hip", "k_learned.hip", "fc_model.hip", "k_coarse.hip"]
 CXX_SOURCES = ["host_assemble.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

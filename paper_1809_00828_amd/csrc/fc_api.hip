@@ -66,6 +66,7 @@ static void free_problem(fc_problem_s* pb) {
 static void free_precond(fc_precond_s* pc) {
   if (!pc) return;
   solver_ws_destroy(pc->ws);
+  coarse_destroy(pc->coarse);
   for (void* p : {(void*)pc->block_elem, (void*)pc->P, (void*)pc->Q, (void*)pc->L32, (void*)pc->Lbf, (void*)pc->isd,
                   (void*)pc->inv_ptr, (void*)pc->inv_idx, (void*)pc->fallback, (void*)pc->y})
     if (p) (void)hipFree(p);
@@ -517,7 +518,7 @@ fc_status fc_pcg_solve(fc_problem pb, fc_precond pc, const double* b_dev, double
     set_error("fc_pcg_solve: invalid options");
     return FC_E_ARG;
   }
-  if (o.mode < FC_MODE_F64 || o.mode > FC_MODE_S_BF16) {
+  if (o.mode < FC_MODE_F64 || o.mode > FC_MODE_LEARNED) {
     set_error("fc_pcg_solve: unsupported mode");
     return FC_E_UNSUPPORTED;
   }

@@ -57,6 +57,8 @@ struct DeviceBsr {
 
 struct SolverWs;
 void solver_ws_destroy(SolverWs* ws);
+struct CoarseCtx;
+void coarse_destroy(CoarseCtx* c);
 
 }  // namespace fc
 
@@ -91,6 +93,7 @@ struct fc_precond_s {
   double eps = 1e-13;
   int32_t stabilize = 1;
   fc::SolverWs* ws = nullptr;      // PCG workspace, created on first solve
+  fc::CoarseCtx* coarse = nullptr; // learned coarse correction, when attached
 };
 
 namespace fc {
@@ -108,5 +111,8 @@ hipError_t launch_block_extract(const fc_problem_s& pb, const fc_precond_s& pc,
 // z = S r
 hipError_t launch_schwarz_apply(const fc_precond_s& pc, const double* r,
                                 double* z, hipStream_t s);
+
+// drop the captured solver chunk (its kernels hold buffers about to change)
+void solver_invalidate_graph(fc_precond_s& pc);
 
 }  // namespace fc

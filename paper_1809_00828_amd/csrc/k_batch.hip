@@ -13,6 +13,9 @@
 // product variants, keeping the fastest.
 #include <hip/hip_runtime.h>
 
+#include <cstdio>
+#include <cstdlib>
+
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -780,19 +783,24 @@ extern "C" fc_status fc_pcg_solve_batch(fc_batch bt, const double* const* b_dev,
     B.key_chunk = chunk;
   }
   const int64_t max_chunks = (o.maxit + chunk - 1) / chunk + 1;
+  // FC_BATCH_PROGRESS=k: report the number of converged members on stderr
+  // every k chunks (long uneven batches otherwise run silently for minutes)
+  const char* prog_env = std::getenv("FC_BATCH_PROGRESS");
+  const int64_t prog = prog_env ? std::max<int64_t>(0, std::atoll(prog_env)) : 0;
   int64_t launched = 0;
   for (;;) {
     FC_HIP(hipGraphLaunch(B.exec, s));
     ++launched;
     FC_HIP(hipMemcpyAsync(B.host_sc, B.sc, B.nprob * sizeof(CgScalars), hipMemcpyDeviceToHost, s));
     FC_HIP(hipStreamSynchronize(s));
-    bool all = true;
-    for (int k = 0; k < B.nprob; ++k)
-      if (!B.host_sc[k].done) {
-        all = false;
-        break;
-      }
-    if (all || launched > max_chunks) break;
+    int ndone = 0;
+    for (int k = 0; k < B.nprob; ++k) ndone += B.host_sc[k].done != 0;
+    if (prog && launched % prog == 0) {
+      std::fprintf(stderr, "[batch] %lld iterations: %d of %d members stopped\n",
+                   (long long)(launched * chunk), ndone, B.nprob);
+      std::fflush(stderr);
+    }
+    if (ndone == B.nprob || launched > max_chunks) break;
   }
   FC_HIP(hipEventRecord(B.ev[2], s));
   FC_HIP(hipStreamSynchronize(s));

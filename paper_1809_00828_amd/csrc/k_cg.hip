@@ -25,6 +25,7 @@
 
 #include "dev_common.h"
 #include "k_schwarz.h"
+#include "learned.h"
 #include "k_setup.h"
 #include "k_spmv.h"
 
@@ -143,7 +144,9 @@ __global__ __launch_bounds__(1024) void k_cg_alpha(const double* __restrict__ pa
 
 // Pull of the Schwarz apply fused with x += alpha p, r -= alpha q and the
 // reductions of the new r and z (one partial triple per workgroup; the
-// grid loops over the unknowns).
+// grid loops over the unknowns).  kFlex adds a fourth partial, (z, q),
+// for the flexible beta.
+template <bool kFlex>
 __global__ __launch_bounds__(256) void k_cg_pull(
     const double* __restrict__ y, const int32_t* __restrict__ inv_ptr,
     const int32_t* __restrict__ inv_idx, const double* __restrict__ fb, int bd, int64_t n,
@@ -153,14 +156,15 @@ __global__ __launch_bounds__(256) void k_cg_pull(
   __shared__ double lds[16];
   if (sc->done) return;
   const double alpha = sc->alpha;
-  double a = 0.0, b = 0.0, c = 0.0;
+  double a = 0.0, b = 0.0, c = 0.0, d = 0.0;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x) {
     const int64_t node = i / bd;
     const int cc = (int)(i - node * bd);
     double s = 0.0;
     for (int32_t e = inv_ptr[node]; e < inv_ptr[node + 1]; ++e) s += y[(int64_t)inv_idx[e] + cc];
-    const double ri = fma(-alpha, q[i], r[i]);
+    const double qi = q[i];
+    const double ri = fma(-alpha, qi, r[i]);
     x[i] = fma(alpha, p[i], x[i]);
     r[i] = ri;
     const double zi = fma(fb[i], ri, s);
@@ -168,14 +172,17 @@ __global__ __launch_bounds__(256) void k_cg_pull(
     a = fma(ri, zi, a);
     b = fma(zi, zi, b);
     c = fma(ri, ri, c);
+    if (kFlex) d = fma(zi, qi, d);
   }
   a = block_sum(a, lds);
   b = block_sum(b, lds);
   c = block_sum(c, lds);
+  if (kFlex) d = block_sum(d, lds);
   if (threadIdx.x == 0) {
     partial[blockIdx.x] = a;
     partial[gridDim.x + blockIdx.x] = b;
     partial[2 * gridDim.x + blockIdx.x] = c;
+    if (kFlex) partial[3 * gridDim.x + blockIdx.x] = d;
   }
 }
 
@@ -208,6 +215,49 @@ __global__ __launch_bounds__(1024) void k_cg_beta(const double* __restrict__ par
       sc->done = 2;
     }
     sc->beta = rz / sc->rz;
+    sc->rz = rz;
+  }
+}
+
+// Flexible variant (FCG(1)) for the learned correction z = S r + gamma w:
+// (r, z) and (z, q) are the pull's Schwarz parts plus the correction's
+// gamma (y . P_c^T r) and gamma (w . q); beta = -(z, q) / (p, q) keeps p
+// A-orthogonal to the previous direction.  (z, z) keeps the Schwarz part.
+__global__ __launch_bounds__(1024) void k_cg_beta_flex(const double* __restrict__ partial, int np,
+                                                       CgScalars* sc,
+                                                       const LearnScalars* __restrict__ ls) {
+  __shared__ double lds[16];
+  if (sc->done) return;
+  double ta = 0.0, tb = 0.0, tc = 0.0, td = 0.0;
+  for (int i = threadIdx.x; i < np; i += blockDim.x) {
+    ta += partial[i];
+    tb += partial[np + i];
+    tc += partial[2 * np + i];
+    td += partial[3 * np + i];
+  }
+  double rz = block_sum(ta, lds);
+  const double zz = block_sum(tb, lds);
+  const double rr = block_sum(tc, lds);
+  double zq = block_sum(td, lds);
+  if (threadIdx.x == 0) {
+    const double g = ls->gamma;
+    if (g != 0.0) {
+      rz += g * ls->yrc;
+      zq += g * ls->wq;
+    }
+    const double crit = sqrt(rr) / sc->crit0;
+    sc->zz = zz;
+    sc->rr = rr;
+    sc->crit = crit;
+    if (sc->history) sc->history[sc->iter] = crit;
+    if (!(crit == crit) || !(rz == rz) || isinf(rz) || !(zq == zq)) {
+      sc->done = 4;
+    } else if (crit <= sc->tol) {
+      sc->done = 1;
+    } else if (sc->iter >= sc->maxit) {
+      sc->done = 2;
+    }
+    sc->beta = -zq / sc->pq;
     sc->rz = rz;
   }
 }
@@ -297,7 +347,7 @@ static fc_status ensure_ws(fc_precond_s& pc, SolverWs** out) {
     FC_HIP(hipMalloc(&w->t, n * sizeof(double)));
     int64_t np = std::max<int64_t>({(int64_t)spmv_num_blocks(pb.A), (int64_t)nblk(n),
                                     (int64_t)kRedBlocks});
-    w->partial_len = 3 * np + 8;
+    w->partial_len = 4 * np + 8;
     FC_HIP(hipMalloc(&w->partial, w->partial_len * sizeof(double)));
     FC_HIP(hipMalloc(&w->sc, sizeof(CgScalars)));
     FC_HIP(hipMemset(w->sc, 0, sizeof(CgScalars)));
@@ -313,7 +363,8 @@ static fc_status ensure_ws(fc_precond_s& pc, SolverWs** out) {
 // precA: 0 = FP64 matrix, 1 = FP32 copy; precS: 0/1/2 = FP64/FP32/BF16
 // local inverses.
 static hipError_t enqueue_steps(fc_precond_s& pc, SolverWs& w, double* x, int chunk, int precA,
-                                int precS, hipStream_t s, hipEvent_t* tev = nullptr) {
+                                int precS, hipStream_t s, hipEvent_t* tev = nullptr,
+                                CoarseCtx* learn = nullptr) {
   fc_problem_s& pb = *pc.pb;
   const int64_t n = pb.n_dofs;
   for (int it = 0; it < chunk; ++it) {
@@ -329,10 +380,19 @@ static hipError_t enqueue_steps(fc_precond_s& pc, SolverWs& w, double* x, int ch
     if (e != hipSuccess) return e;
     if (tev && (e = hipEventRecord(tev[4 * it + 3], s)) != hipSuccess) return e;
     const unsigned pg = pull_grid(n);
-    hipLaunchKernelGGL(k_cg_pull, dim3(pg), dim3(kVecThreads), 0, s, pc.y, pc.inv_ptr,
-                       pc.inv_idx, pc.fallback, pc.bdim, n, x, w.r, w.p, w.q, w.z, w.partial,
-                       w.sc);
-    hipLaunchKernelGGL(k_cg_beta, dim3(1), dim3(1024), 0, s, w.partial, (int)pg, w.sc);
+    if (learn) {
+      hipLaunchKernelGGL(k_cg_pull<true>, dim3(pg), dim3(kVecThreads), 0, s, pc.y, pc.inv_ptr,
+                         pc.inv_idx, pc.fallback, pc.bdim, n, x, w.r, w.p, w.q, w.z, w.partial,
+                         w.sc);
+      if ((e = coarse_correct(*learn, w.r, w.z, w.q, w.sc, s)) != hipSuccess) return e;
+      hipLaunchKernelGGL(k_cg_beta_flex, dim3(1), dim3(1024), 0, s, w.partial, (int)pg, w.sc,
+                         learn->ls);
+    } else {
+      hipLaunchKernelGGL(k_cg_pull<false>, dim3(pg), dim3(kVecThreads), 0, s, pc.y, pc.inv_ptr,
+                         pc.inv_idx, pc.fallback, pc.bdim, n, x, w.r, w.p, w.q, w.z, w.partial,
+                         w.sc);
+      hipLaunchKernelGGL(k_cg_beta, dim3(1), dim3(1024), 0, s, w.partial, (int)pg, w.sc);
+    }
     hipLaunchKernelGGL(k_cg_p, dim3(nblk(n)), dim3(kVecThreads), 0, s, w.z, w.p, n, w.sc);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
@@ -347,6 +407,7 @@ struct CoreArgs {
   int64_t maxit;
   int stop, precA, precS, timing, chunk;
   double* history;
+  CoarseCtx* learn = nullptr;   // learned correction (flexible CG) when set
 };
 
 struct CoreResult {
@@ -374,12 +435,13 @@ static fc_status pcg_core(fc_precond_s& pc, SolverWs& w, const CoreArgs& a, Core
   FC_HIP(hipGetLastError());
   FC_HIP(launch_schwarz_phase1(pc, a.precS, w.r, nullptr, nullptr, s));
   FC_HIP(launch_schwarz_pull(pc, w.r, w.z, s));
+  if (a.learn) FC_HIP(coarse_correct(*a.learn, w.r, w.z, nullptr, w.sc, s));
   hipLaunchKernelGGL(k_copy, dim3(1024), dim3(256), 0, s, w.z, w.p, n);
   hipLaunchKernelGGL(k_cg_start, dim3(kRedBlocks), dim3(256), 0, s, w.r, w.z, n, w.partial,
                      w.sc);
   FC_HIP(hipGetLastError());
   const int chunk = a.chunk > 0 ? a.chunk : 16;
-  const int prec = a.precA * 4 + a.precS;
+  const int prec = a.precA * 4 + a.precS + (a.learn ? 16 : 0);
   const int64_t max_chunks = (a.maxit + chunk - 1) / chunk + 1;
   int64_t launched = 0;
   if (a.timing) {
@@ -390,7 +452,7 @@ static fc_status pcg_core(fc_precond_s& pc, SolverWs& w, const CoreArgs& a, Core
     }
     int64_t iter_before = 0;
     for (;;) {
-      FC_HIP(enqueue_steps(pc, w, a.x, chunk, a.precA, a.precS, s, w.tev.data()));
+      FC_HIP(enqueue_steps(pc, w, a.x, chunk, a.precA, a.precS, s, w.tev.data(), a.learn));
       ++launched;
       FC_HIP(hipMemcpyAsync(w.host, w.sc, sizeof(CgScalars), hipMemcpyDeviceToHost, s));
       FC_HIP(hipStreamSynchronize(s));
@@ -418,7 +480,7 @@ static fc_status pcg_core(fc_precond_s& pc, SolverWs& w, const CoreArgs& a, Core
         w.graph = nullptr;
       }
       FC_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-      hipError_t e = enqueue_steps(pc, w, a.x, chunk, a.precA, a.precS, s);
+      hipError_t e = enqueue_steps(pc, w, a.x, chunk, a.precA, a.precS, s, nullptr, a.learn);
       hipGraph_t g = nullptr;
       hipError_t e2 = hipStreamEndCapture(s, &g);
       if (e != hipSuccess) FC_HIP(e);
@@ -499,9 +561,19 @@ fc_status pcg_solve(fc_precond_s& pc, const double* b, double* x, const fc_solve
     set_error("fc_pcg_solve: the preconditioner holds no copy in the requested precision");
     return FC_E_ARG;
   }
-  if (o.mode == FC_MODE_F64 || o.mode == FC_MODE_S_F32 || o.mode == FC_MODE_S_BF16) {
-    // one PCG run with the FP64 matrix (and a low-precision S if asked)
-    CoreArgs a{b, x, o.tol, o.maxit, o.stop, 0, precS, o.timing, o.check_every, o.history_dev};
+  CoarseCtx* learn = nullptr;
+  if (o.mode == FC_MODE_LEARNED) {
+    if (!pc.coarse || !pc.coarse->model) {
+      set_error("fc_pcg_solve: FC_MODE_LEARNED needs a network attached with fc_learned_attach");
+      return FC_E_ARG;
+    }
+    learn = pc.coarse;
+  }
+  if (o.mode == FC_MODE_F64 || o.mode == FC_MODE_S_F32 || o.mode == FC_MODE_S_BF16 || learn) {
+    // one PCG run with the FP64 matrix (and a low-precision S if asked, or
+    // flexible CG with the learned correction)
+    CoreArgs a{b, x, o.tol, o.maxit, learn ? (int)FC_STOP_RESIDUAL : o.stop, 0, precS, o.timing,
+               o.check_every, o.history_dev, learn};
     FC_TRY_ST(pcg_core(pc, w, a, &acc, s));
     iters = acc.iters;
     rel_prec = acc.zn0 > 0 ? std::sqrt(acc.zz) / acc.zn0 : 0.0;
@@ -579,4 +651,84 @@ fc_status pcg_solve(fc_precond_s& pc, const double* b, double* x, const fc_solve
   return result;
 }
 
+void solver_invalidate_graph(fc_precond_s& pc) {
+  SolverWs* w = pc.ws;
+  if (!w) return;
+  if (w->exec) (void)hipGraphExecDestroy(w->exec);
+  if (w->graph) (void)hipGraphDestroy(w->graph);
+  w->exec = nullptr;
+  w->graph = nullptr;
+  w->key[0] = nullptr;
+  w->key_prec = -1;
+}
+
 }  // namespace fc
+
+using namespace fc;
+
+extern "C" fc_status fc_learned_snapshots(fc_precond pc, const double* b, const double* xs,
+                                          int32_t n_snap, const int32_t* iters, int32_t kind,
+                                          double tol, float* xin, float* t, int32_t* n_taken,
+                                          void* stream) {
+  if (!pc || !b || !xs || n_snap < 1 || !iters || !xin || !t || (kind != 0 && kind != 1)) {
+    set_error("fc_learned_snapshots: invalid arguments");
+    return FC_E_ARG;
+  }
+  for (int j = 0; j < n_snap; ++j)
+    if (iters[j] < 0 || (j > 0 && iters[j] <= iters[j - 1])) {
+      set_error("fc_learned_snapshots: iterations must be ascending and non-negative");
+      return FC_E_ARG;
+    }
+  if (n_taken) *n_taken = 0;
+  hipStream_t user = (hipStream_t)stream;
+  FC_TRY_ST(coarse_ensure(*pc, user));
+  CoarseCtx& c = *pc->coarse;
+  SolverWs* wp = nullptr;
+  FC_TRY_ST(ensure_ws(*pc, &wp));
+  SolverWs& w = *wp;
+  fc_problem_s& pb = *pc->pb;
+  const int64_t n = pb.n_dofs;
+  if (!w.d) FC_HIP(hipMalloc(&w.d, n * sizeof(double)));
+  double* x = w.d;
+  hipStream_t s = w.stream;
+  FC_HIP(hipEventRecord(w.ev[0], user));
+  FC_HIP(hipStreamWaitEvent(s, w.ev[0], 0));
+  CgScalars init{};
+  init.tol = tol;
+  init.maxit = (int64_t)iters[n_snap - 1] + 1;
+  init.stop = FC_STOP_RESIDUAL;
+  FC_HIP(hipMemcpyAsync(w.sc, &init, sizeof(CgScalars), hipMemcpyHostToDevice, s));
+  hipLaunchKernelGGL(k_fill, dim3(1024), dim3(256), 0, s, x, 0.0, n);
+  hipLaunchKernelGGL(k_copy, dim3(1024), dim3(256), 0, s, b, w.r, n);
+  FC_HIP(hipGetLastError());
+  FC_HIP(launch_schwarz_phase1(*pc, 0, w.r, nullptr, nullptr, s));
+  FC_HIP(launch_schwarz_pull(*pc, w.r, w.z, s));
+  hipLaunchKernelGGL(k_copy, dim3(1024), dim3(256), 0, s, w.z, w.p, n);
+  hipLaunchKernelGGL(k_cg_start, dim3(kRedBlocks), dim3(256), 0, s, w.r, w.z, n, w.partial,
+                     w.sc);
+  FC_HIP(hipGetLastError());
+  const int64_t nv = c.nvox;
+  int j = 0;
+  int64_t it = 0;
+  auto take = [&]() -> hipError_t {
+    hipError_t e = coarse_snapshot(c, w.r, xs, x, kind == 0 ? w.z : nullptr,
+                                   xin + (int64_t)j * 2 * nv, t + (int64_t)j * nv, s);
+    ++j;
+    return e;
+  };
+  if (iters[0] == 0) FC_HIP(take());
+  while (j < n_snap) {
+    FC_HIP(enqueue_steps(*pc, w, x, 1, 0, 0, s));
+    ++it;
+    FC_HIP(hipMemcpyAsync(w.host, w.sc, sizeof(CgScalars), hipMemcpyDeviceToHost, s));
+    FC_HIP(hipStreamSynchronize(s));
+    if (w.host->iter != it) break;   // stopped before this step (flag set earlier)
+    if (iters[j] == it) FC_HIP(take());
+    if (w.host->done != 0) break;
+  }
+  FC_HIP(hipEventRecord(w.ev[3], s));
+  FC_HIP(hipStreamWaitEvent(user, w.ev[3], 0));
+  FC_HIP(hipStreamSynchronize(s));
+  if (n_taken) *n_taken = j;
+  return FC_OK;
+}

@@ -1,0 +1,497 @@
+// Learned coarse correction: a small 3-D U-Net on the coarse vertex grid,
+// with its own forward, backward and Adam kernels, the transfers between
+// unknowns and the coarse grid, and training data taken from the solver.
+//
+// Network (4 levels, widths c0..c3, in_ch input channels): 'same' 3x3x3
+// convolutions with zero padding, ReLU, average pooling over the existing
+// children, nearest upsampling, additive skips:
+//   enc_l: h = relu(conv_b(relu(conv_a(x))))   (l = 0..2, pool after)
+//   bottom: relu(conv_b(relu(conv_a(.))))
+//   dec_l: h = relu(conv_a(up(h))) + s_l; h = relu(conv_b(h))  (l = 2,1,0)
+//   head:  conv(c0 -> 1)
+// Parameters: one flat FP32 master vector (per convolution W[co][ci][27]
+// then b[co]; tap = dz*9 + dy*3 + dx), a BF16 copy used by every
+// convolution, FP32 activations and FP32 accumulation.
+//
+// Convolution kernels: every thread owns one output voxel and 16 output
+// channels; the 16 x Ci x 27 BF16 weights of the chunk are staged in LDS.
+// The data gradient is the same kernel with the weights transposed and the
+// taps mirrored; the weight gradient is one workgroup per (co, ci) pair
+// reducing over voxels (fixed order, no atomics).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <vector>
+
+#include "dev_common.h"
+#include "learned.h"
+
+namespace fc {
+
+constexpr int kCoChunk = 16;
+
+__device__ __forceinline__ uint16_t f2bf(float f) {
+  uint32_t u = __float_as_uint(f);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+
+// y[b][o][v] = act(bias[o] + sum_{i,t} w(o,i,t) x[b][i][v + off_t])
+// kTrans: w(o,i,t) = W[i][o][26-t] (data gradient of a convolution with
+// Ci = Cout of the layer), no bias, no activation.
+template <bool kTrans>
+__global__ __launch_bounds__(256) void k_conv3d(const float* __restrict__ x, int Ci,
+                                                const uint16_t* __restrict__ W,
+                                                const float* __restrict__ bias,
+                                                float* __restrict__ y, int Co, int D, int H,
+                                                int Wd, int relu) {
+  extern __shared__ uint16_t wsh[];   // [kCoChunk][Ci][27]
+  const int V = D * H * Wd;
+  const int b = blockIdx.z;
+  const int o0 = blockIdx.y * kCoChunk;
+  const int nco = min(kCoChunk, Co - o0);
+  // stage weights of this output chunk
+  for (int t = threadIdx.x; t < nco * Ci * 27; t += blockDim.x) {
+    const int o = t / (Ci * 27), rem = t % (Ci * 27), i = rem / 27, k = rem % 27;
+    uint16_t v;
+    if (kTrans)
+      v = W[((int64_t)i * Co + (o0 + o)) * 27 + (26 - k)];   // layer W[co=i][ci=o0+o]
+    else
+      v = W[((int64_t)(o0 + o) * Ci + i) * 27 + k];
+    wsh[(o * Ci + i) * 27 + k] = v;
+  }
+  __syncthreads();
+  const int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= V) return;
+  const int xx = v % Wd, yy = (v / Wd) % H, zz = v / (Wd * H);
+  float acc[kCoChunk];
+#pragma unroll
+  for (int o = 0; o < kCoChunk; ++o) acc[o] = (!kTrans && bias && o < nco) ? bias[o0 + o] : 0.f;
+  const float* xb = x + (int64_t)b * Ci * V;
+  for (int i = 0; i < Ci; ++i) {
+    const float* xi = xb + (int64_t)i * V;
+    const uint16_t* wi = wsh + i * 27;
+#pragma unroll
+    for (int k = 0; k < 27; ++k) {
+      const int dz = k / 9 - 1, dy = (k / 3) % 3 - 1, dx = k % 3 - 1;
+      const int z2 = zz + dz, y2 = yy + dy, x2 = xx + dx;
+      const bool in = z2 >= 0 && z2 < D && y2 >= 0 && y2 < H && x2 >= 0 && x2 < Wd;
+      const float xv = in ? xi[(z2 * H + y2) * Wd + x2] : 0.f;
+#pragma unroll
+      for (int o = 0; o < kCoChunk; ++o)
+        acc[o] = fmaf(bf16_to_f32(wi[o * Ci * 27 + k]), xv, acc[o]);
+    }
+  }
+  float* yb = y + (int64_t)b * Co * V;
+#pragma unroll
+  for (int o = 0; o < kCoChunk; ++o)
+    if (o < nco) yb[(int64_t)(o0 + o) * V + v] = relu ? fmaxf(acc[o], 0.f) : acc[o];
+}
+
+// gw[co][ci][t] = sum_{b,v} g[b][co][v] x[b][ci][v + off_t];  gb[co] = sum g
+__global__ __launch_bounds__(256) void k_conv3d_wgrad(const float* __restrict__ x, int Ci,
+                                                      const float* __restrict__ g, int Co, int B,
+                                                      int D, int H, int Wd,
+                                                      float* __restrict__ gw,
+                                                      float* __restrict__ gb) {
+  __shared__ float red[16];
+  const int ci = blockIdx.x, co = blockIdx.y;
+  const int V = D * H * Wd;
+  float acc[27];
+#pragma unroll
+  for (int k = 0; k < 27; ++k) acc[k] = 0.f;
+  float accb = 0.f;
+  for (int64_t idx = threadIdx.x; idx < (int64_t)B * V; idx += blockDim.x) {
+    const int b = (int)(idx / V), v = (int)(idx % V);
+    const float gv = g[((int64_t)b * Co + co) * V + v];
+    accb += gv;
+    if (gv == 0.f) continue;
+    const int xx = v % Wd, yy = (v / Wd) % H, zz = v / (Wd * H);
+    const float* xi = x + ((int64_t)b * Ci + ci) * V;
+#pragma unroll
+    for (int k = 0; k < 27; ++k) {
+      const int dz = k / 9 - 1, dy = (k / 3) % 3 - 1, dx = k % 3 - 1;
+      const int z2 = zz + dz, y2 = yy + dy, x2 = xx + dx;
+      if (z2 >= 0 && z2 < D && y2 >= 0 && y2 < H && x2 >= 0 && x2 < Wd)
+        acc[k] = fmaf(gv, xi[(z2 * H + y2) * Wd + x2], acc[k]);
+    }
+  }
+  for (int k = 0; k < 27; ++k) {
+    const float s = block_sum(acc[k], red);
+    if (threadIdx.x == 0) gw[((int64_t)co * Ci + ci) * 27 + k] = s;
+  }
+  if (ci == 0) {
+    const float s = block_sum(accb, red);
+    if (threadIdx.x == 0) gb[co] = s;
+  }
+}
+
+// average over the existing children: (D,H,W) -> ceil halves
+__global__ void k_pool(const float* __restrict__ x, float* __restrict__ y, int BC, int D, int H,
+                       int Wd) {
+  const int d = (D + 1) / 2, h = (H + 1) / 2, w = (Wd + 1) / 2;
+  const int64_t total = (int64_t)BC * d * h * w;
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total;
+       t += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t bc = t / ((int64_t)d * h * w);
+    const int rem = (int)(t % ((int64_t)d * h * w));
+    const int X = rem % w, Y = (rem / w) % h, Z = rem / (w * h);
+    float s = 0.f;
+    int cnt = 0;
+    for (int a = 0; a < 2; ++a)
+      for (int b = 0; b < 2; ++b)
+        for (int c = 0; c < 2; ++c) {
+          const int z = 2 * Z + a, yy = 2 * Y + b, xx = 2 * X + c;
+          if (z < D && yy < H && xx < Wd) {
+            s += x[bc * D * H * Wd + ((int64_t)z * H + yy) * Wd + xx];
+            ++cnt;
+          }
+        }
+    y[t] = s / (float)cnt;
+  }
+}
+
+__global__ void k_pool_bwd(const float* __restrict__ gy, float* __restrict__ gx, int BC, int D,
+                           int H, int Wd) {
+  const int d = (D + 1) / 2, h = (H + 1) / 2, w = (Wd + 1) / 2;
+  const int64_t total = (int64_t)BC * D * H * Wd;
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total;
+       t += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t bc = t / ((int64_t)D * H * Wd);
+    const int rem = (int)(t % ((int64_t)D * H * Wd));
+    const int xx = rem % Wd, yy = (rem / Wd) % H, z = rem / (Wd * H);
+    const int X = xx / 2, Y = yy / 2, Z = z / 2;
+    const int cz = (2 * Z + 1 < D) ? 2 : 1, cy = (2 * Y + 1 < H) ? 2 : 1, cx = (2 * X + 1 < Wd) ? 2 : 1;
+    gx[t] = gy[bc * d * h * w + ((int64_t)Z * h + Y) * w + X] / (float)(cz * cy * cx);
+  }
+}
+
+// nearest upsampling (d,h,w) -> (D,H,W): y[i] = x[i/2]; with accumulate
+// into y (mode 1) for the additive use
+__global__ void k_upsample(const float* __restrict__ x, float* __restrict__ y, int BC, int D,
+                           int H, int Wd) {
+  const int d = (D + 1) / 2, h = (H + 1) / 2, w = (Wd + 1) / 2;
+  const int64_t total = (int64_t)BC * D * H * Wd;
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total;
+       t += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t bc = t / ((int64_t)D * H * Wd);
+    const int rem = (int)(t % ((int64_t)D * H * Wd));
+    const int xx = rem % Wd, yy = (rem / Wd) % H, z = rem / (Wd * H);
+    y[t] = x[bc * d * h * w + ((int64_t)(z / 2) * h + yy / 2) * w + xx / 2];
+  }
+}
+
+__global__ void k_upsample_bwd(const float* __restrict__ gy, float* __restrict__ gx, int BC,
+                               int D, int H, int Wd) {
+  const int d = (D + 1) / 2, h = (H + 1) / 2, w = (Wd + 1) / 2;
+  const int64_t total = (int64_t)BC * d * h * w;
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total;
+       t += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t bc = t / ((int64_t)d * h * w);
+    const int rem = (int)(t % ((int64_t)d * h * w));
+    const int X = rem % w, Y = (rem / w) % h, Z = rem / (w * h);
+    float s = 0.f;
+    for (int a = 0; a < 2; ++a)
+      for (int b = 0; b < 2; ++b)
+        for (int c = 0; c < 2; ++c) {
+          const int z = 2 * Z + a, yy = 2 * Y + b, xx = 2 * X + c;
+          if (z < D && yy < H && xx < Wd) s += gy[bc * D * H * Wd + ((int64_t)z * H + yy) * Wd + xx];
+        }
+    gx[t] = s;
+  }
+}
+
+// a = a + b
+__global__ void k_add(float* __restrict__ a, const float* __restrict__ b, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    a[i] += b[i];
+}
+
+// c = a + b
+__global__ void k_add3(float* __restrict__ c, const float* __restrict__ a,
+                       const float* __restrict__ b, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    c[i] = a[i] + b[i];
+}
+
+// g *= (act > 0)
+__global__ void k_relu_mask(float* __restrict__ g, const float* __restrict__ act, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    if (!(act[i] > 0.f)) g[i] = 0.f;
+}
+
+// mean squared error: per-workgroup partial sums and g = 2 (y - t) / n
+__global__ __launch_bounds__(256) void k_mse(const float* __restrict__ y,
+                                             const float* __restrict__ t, float* __restrict__ g,
+                                             int64_t n, double* __restrict__ partial) {
+  __shared__ double red[16];
+  double s = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const float d = y[i] - t[i];
+    s += (double)d * d;
+    g[i] = 2.f * d / (float)n;
+  }
+  s = block_sum(s, red);
+  if (threadIdx.x == 0) partial[blockIdx.x] = s;
+}
+
+__global__ void k_adam(float* __restrict__ p, const float* __restrict__ g, float* __restrict__ m,
+                       float* __restrict__ v, uint16_t* __restrict__ pb, int64_t n, float lr,
+                       float b1, float b2, float eps, float c1, float c2) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const float gi = g[i];
+    const float mi = b1 * m[i] + (1.f - b1) * gi;
+    const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    const float pi = p[i] - lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+    p[i] = pi;
+    pb[i] = f2bf(pi);
+  }
+}
+
+__global__ void k_to_bf16(const float* __restrict__ p, uint16_t* __restrict__ pb, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    pb[i] = f2bf(p[i]);
+}
+
+static inline dim3 grid1(int64_t n) {
+  return dim3((unsigned)std::min<int64_t>((n + 255) / 256, 8192));
+}
+
+// ------------------------------------------------------------ network
+static const int kLayerIO[15][2] = {{-1, 0}, {0, 0}, {0, 1}, {1, 1}, {1, 2}, {2, 2}, {2, 3},
+                                    {3, 3}, {3, 2}, {2, 2}, {2, 1}, {1, 1}, {1, 0}, {0, 0},
+                                    {0, -2}};
+
+void Net::init(const int32_t* c, int32_t in_channels) {
+  for (int i = 0; i < 4; ++i) ch[i] = c[i];
+  in_ch = in_channels;
+  int64_t off = 0;
+  for (int l = 0; l < 15; ++l) {
+    ci[l] = kLayerIO[l][0] == -1 ? in_ch : ch[kLayerIO[l][0]];
+    co[l] = kLayerIO[l][1] == -2 ? 1 : ch[kLayerIO[l][1]];
+    woff[l] = off;
+    off += (int64_t)ci[l] * co[l] * 27;
+    boff[l] = off;
+    off += co[l];
+  }
+  nparam = off;
+}
+
+int64_t net_param_count(const int32_t* c, int32_t in_channels) {
+  Net n;
+  n.init(c, in_channels);
+  return n.nparam;
+}
+
+static hipError_t conv_fwd(const Net& net, int l, const float* x, float* y, int B, int N, bool relu,
+                           hipStream_t s) {
+  const int Ci = net.ci[l], Co = net.co[l];
+  const int V = N * N * N;
+  dim3 g((V + 255) / 256, (Co + kCoChunk - 1) / kCoChunk, B);
+  const size_t lds = (size_t)kCoChunk * Ci * 27 * sizeof(uint16_t);
+  hipLaunchKernelGGL(k_conv3d<false>, g, dim3(256), lds, s, x, Ci, net.wbf + net.woff[l],
+                     net.p + net.boff[l], y, Co, N, N, N, relu ? 1 : 0);
+  return hipGetLastError();
+}
+
+// data gradient of layer l: gx (Ci channels) from gy (Co channels)
+static hipError_t conv_bwd_data(const Net& net, int l, const float* gy, float* gx, int B, int N,
+                                hipStream_t s) {
+  const int Ci = net.ci[l], Co = net.co[l];
+  const int V = N * N * N;
+  dim3 g((V + 255) / 256, (Ci + kCoChunk - 1) / kCoChunk, B);
+  const size_t lds = (size_t)kCoChunk * Co * 27 * sizeof(uint16_t);
+  hipLaunchKernelGGL(k_conv3d<true>, g, dim3(256), lds, s, gy, Co, net.wbf + net.woff[l], nullptr,
+                     gx, Ci, N, N, N, 0);
+  return hipGetLastError();
+}
+
+static hipError_t conv_bwd_weight(Net& net, int l, const float* x, const float* gy, int B, int N,
+                                  hipStream_t s) {
+  const int Ci = net.ci[l], Co = net.co[l];
+  hipLaunchKernelGGL(k_conv3d_wgrad, dim3(Ci, Co), dim3(256), 0, s, x, Ci, gy, Co, B, N, N, N,
+                     net.g + net.woff[l], net.g + net.boff[l]);
+  return hipGetLastError();
+}
+
+fc_status NetWs::ensure(const Net& net, int B_, int N0) {
+  if (B_ <= capB && N0 == N[0] && buf) return FC_OK;
+  release();
+  B = B_;
+  capB = B_;
+  N[0] = N0;
+  for (int l = 1; l < 4; ++l) N[l] = (N[l - 1] + 1) / 2;
+  // per-level tensor sizes (max channels of that level) for every saved
+  // activation and two gradient scratch tensors per level
+  int64_t total = 0;
+  auto vox = [&](int l) { return (int64_t)N[l] * N[l] * N[l]; };
+  for (int l = 0; l < 4; ++l) {
+    // widths present at level l: its own, the pooled input from above (or
+    // the network input) and the upsampled tensor from below
+    int64_t cmax = net.ch[l];
+    cmax = std::max<int64_t>(cmax, l == 0 ? net.in_ch : net.ch[l - 1]);
+    if (l < 3) cmax = std::max<int64_t>(cmax, net.ch[l + 1]);
+    for (int k = 0; k < kSlots; ++k) {
+      off[l][k] = total;
+      total += (int64_t)B * cmax * vox(l);
+    }
+  }
+  off_y = total;
+  total += 2 * (int64_t)B * vox(0);   // output and its gradient
+  hipError_t e = hipMalloc(&buf, total * sizeof(float));
+  if (e != hipSuccess) {
+    buf = nullptr;
+    set_error("network workspace allocation failed");
+    return FC_E_NOMEM;
+  }
+  if (hipMalloc(&partial, 1024 * sizeof(double)) != hipSuccess) return FC_E_NOMEM;
+  return FC_OK;
+}
+
+void NetWs::release() {
+  if (buf) (void)hipFree(buf);
+  if (partial) (void)hipFree(partial);
+  buf = nullptr;
+  partial = nullptr;
+  capB = 0;
+}
+
+// slots per level: 0 in, 1 a, 2 b (skip), 3 u (up), 4 da, 5 m, 6 db,
+// 7, 8 gradient scratch
+hipError_t net_forward(const Net& net, NetWs& ws, const float* x, int B, hipStream_t s) {
+  const int* N = ws.N;
+  hipError_t e;
+  const float* in = x;
+  for (int l = 0; l < 3; ++l) {
+    float* a = ws.t(l, 1);
+    float* b = ws.t(l, 2);
+    if ((e = conv_fwd(net, 2 * l, in, a, B, N[l], true, s)) != hipSuccess) return e;
+    if ((e = conv_fwd(net, 2 * l + 1, a, b, B, N[l], true, s)) != hipSuccess) return e;
+    float* nxt = ws.t(l + 1, 0);
+    const int64_t bc = (int64_t)B * net.ch[l];
+    hipLaunchKernelGGL(k_pool, grid1(bc * ws.vox(l + 1)), dim3(256), 0, s, b, nxt, (int)bc, N[l],
+                       N[l], N[l]);
+    in = nxt;
+  }
+  if ((e = conv_fwd(net, 6, in, ws.t(3, 1), B, N[3], true, s)) != hipSuccess) return e;
+  if ((e = conv_fwd(net, 7, ws.t(3, 1), ws.t(3, 2), B, N[3], true, s)) != hipSuccess) return e;
+  const float* h = ws.t(3, 2);
+  int hc = net.ch[3];
+  for (int l = 2; l >= 0; --l) {
+    float* u = ws.t(l, 3);
+    const int64_t bc = (int64_t)B * hc;
+    hipLaunchKernelGGL(k_upsample, grid1(bc * ws.vox(l)), dim3(256), 0, s, h, u, (int)bc, N[l],
+                       N[l], N[l]);
+    const int la = 8 + 2 * (2 - l), lb = la + 1;
+    float* da = ws.t(l, 4);
+    if ((e = conv_fwd(net, la, u, da, B, N[l], true, s)) != hipSuccess) return e;
+    float* m = ws.t(l, 5);
+    const int64_t n = (int64_t)B * net.ch[l] * ws.vox(l);
+    hipLaunchKernelGGL(k_add3, grid1(n), dim3(256), 0, s, m, da, ws.t(l, 2), n);
+    float* db = ws.t(l, 6);
+    if ((e = conv_fwd(net, lb, m, db, B, N[l], true, s)) != hipSuccess) return e;
+    h = db;
+    hc = net.ch[l];
+  }
+  return conv_fwd(net, 14, h, ws.y(), B, N[0], false, s);
+}
+
+// Backward from gy (B,1,N0^3) into net.g (parameters); x is the input.
+hipError_t net_backward(Net& net, NetWs& ws, const float* x, float* gy, int B, hipStream_t s) {
+  const int* N = ws.N;
+  hipError_t e;
+  // head
+  float* g = ws.t(0, 7);
+  if ((e = conv_bwd_weight(net, 14, ws.t(0, 6), gy, B, N[0], s)) != hipSuccess) return e;
+  if ((e = conv_bwd_data(net, 14, gy, g, B, N[0], s)) != hipSuccess) return e;
+  std::vector<float*> gskip(3, nullptr);
+  int gc = net.ch[0];
+  for (int l = 0; l < 3; ++l) {
+    const int la = 8 + 2 * (2 - l), lb = la + 1;
+    const int64_t n = (int64_t)B * net.ch[l] * ws.vox(l);
+    hipLaunchKernelGGL(k_relu_mask, grid1(n), dim3(256), 0, s, g, ws.t(l, 6), n);
+    if ((e = conv_bwd_weight(net, lb, ws.t(l, 5), g, B, N[l], s)) != hipSuccess) return e;
+    float* gm = ws.t(l, 8);
+    if ((e = conv_bwd_data(net, lb, g, gm, B, N[l], s)) != hipSuccess) return e;
+    // gm flows to the skip (kept in slot 8) and to da
+    float* gda = ws.t(l, 7);
+    (void)hipMemcpyAsync(gda, gm, n * sizeof(float), hipMemcpyDeviceToDevice, s);
+    gskip[l] = gm;
+    hipLaunchKernelGGL(k_relu_mask, grid1(n), dim3(256), 0, s, gda, ws.t(l, 4), n);
+    if ((e = conv_bwd_weight(net, la, ws.t(l, 3), gda, B, N[l], s)) != hipSuccess) return e;
+    // data gradient of up_a lands on the upsampled tensor (Ci = width below)
+    float* gu = ws.t(l, 3);   // the upsampled input is no longer needed
+    if ((e = conv_bwd_data(net, la, gda, gu, B, N[l], s)) != hipSuccess) return e;
+    const int cbelow = net.ci[la];
+    float* gnext = ws.t(l + 1, 7);
+    const int64_t bc = (int64_t)B * cbelow;
+    hipLaunchKernelGGL(k_upsample_bwd, grid1(bc * ws.vox(l + 1)), dim3(256), 0, s, gu, gnext,
+                       (int)bc, N[l], N[l], N[l]);
+    g = gnext;
+    gc = cbelow;
+  }
+  (void)gc;
+  // bottom
+  {
+    const int64_t n = (int64_t)B * net.ch[3] * ws.vox(3);
+    hipLaunchKernelGGL(k_relu_mask, grid1(n), dim3(256), 0, s, g, ws.t(3, 2), n);
+    if ((e = conv_bwd_weight(net, 7, ws.t(3, 1), g, B, N[3], s)) != hipSuccess) return e;
+    float* g2 = ws.t(3, 8);
+    if ((e = conv_bwd_data(net, 7, g, g2, B, N[3], s)) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_relu_mask, grid1(n), dim3(256), 0, s, g2, ws.t(3, 1), n);
+    if ((e = conv_bwd_weight(net, 6, ws.t(3, 0), g2, B, N[3], s)) != hipSuccess) return e;
+    g = ws.t(3, 7);
+    if ((e = conv_bwd_data(net, 6, g2, g, B, N[3], s)) != hipSuccess) return e;
+  }
+  for (int l = 2; l >= 0; --l) {
+    const int64_t bc = (int64_t)B * net.ch[l];
+    const int64_t n = bc * ws.vox(l);
+    float* gb = ws.t(l, 7);
+    // gradient of pool input, plus the skip's gradient
+    hipLaunchKernelGGL(k_pool_bwd, grid1(n), dim3(256), 0, s, g, gb, (int)bc, N[l], N[l], N[l]);
+    hipLaunchKernelGGL(k_add, grid1(n), dim3(256), 0, s, gb, gskip[l], n);
+    hipLaunchKernelGGL(k_relu_mask, grid1(n), dim3(256), 0, s, gb, ws.t(l, 2), n);
+    if ((e = conv_bwd_weight(net, 2 * l + 1, ws.t(l, 1), gb, B, N[l], s)) != hipSuccess) return e;
+    float* g2 = ws.t(l, 8);
+    if ((e = conv_bwd_data(net, 2 * l + 1, gb, g2, B, N[l], s)) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_relu_mask, grid1(n), dim3(256), 0, s, g2, ws.t(l, 1), n);
+    const float* xin = l == 0 ? x : ws.t(l, 0);
+    if ((e = conv_bwd_weight(net, 2 * l, xin, g2, B, N[l], s)) != hipSuccess) return e;
+    if (l > 0) {
+      g = ws.t(l, 7);   // reuse: data gradient into the pooled input of level l
+      if ((e = conv_bwd_data(net, 2 * l, g2, g, B, N[l], s)) != hipSuccess) return e;
+    }
+  }
+  return hipGetLastError();
+}
+
+hipError_t net_mse(NetWs& ws, const float* target, float* gy, int64_t n, hipStream_t s) {
+  hipLaunchKernelGGL(k_mse, dim3(1024), dim3(256), 0, s, ws.y(), target, gy, n, ws.partial);
+  return hipGetLastError();
+}
+
+hipError_t net_adam(Net& net, float lr, int64_t step, hipStream_t s) {
+  const float b1 = 0.9f, b2 = 0.999f;
+  const float c1 = 1.f - powf(b1, (float)step), c2 = 1.f - powf(b2, (float)step);
+  hipLaunchKernelGGL(k_adam, grid1(net.nparam), dim3(256), 0, s, net.p, net.g, net.m, net.v,
+                     net.wbf, net.nparam, lr, b1, b2, 1e-8f, c1, c2);
+  return hipGetLastError();
+}
+
+hipError_t net_sync_bf16(Net& net, hipStream_t s) {
+  hipLaunchKernelGGL(k_to_bf16, grid1(net.nparam), dim3(256), 0, s, net.p, net.wbf, net.nparam);
+  return hipGetLastError();
+}
+
+}  // namespace fc
