@@ -121,6 +121,79 @@ def forms(fc, pb, b, tol, t_f64, it_f64):
     return res
 
 
+def learned_bench(fc, args):
+    """Learned coarse correction: a U-Net trained on solver-generated pairs
+    from 48^3-cell, p=2 porous Poisson cubes, evaluated inside flexible CG
+    on a 64^3-cell, p=2 cube (2.1M unknowns), against plain FP64 PCG, both
+    to ||r||/||b|| <= 1e-8; then plain PCG judges whether the network is kept."""
+    import torch
+    import fcgen
+    from paper_1809_00828_amd import learned as LR
+    ch = (8, 16, 32, 32)
+    t0 = time.perf_counter()
+    descs = [fcgen.porous_poisson_3d(1000 + i, n=48, p=2) for i in range(args.learned_train)]
+    xin, t, G = LR.training_set(descs, args.learned_pairs // args.learned_train,
+                                kind=args.learned_target, log=log)
+    t_data = time.perf_counter() - t0
+    model = fc.Model(fcgen.unet_init(ch, 2, seed=0), ch)
+    t0 = time.perf_counter()
+    hist = LR.train(model, xin, t, G, epochs=args.learned_epochs, batch=8, lr=3e-4)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    log(f"learned: {xin.shape[0]} pairs in {t_data:.0f} s, {args.learned_epochs} epochs in "
+        f"{t_train:.0f} s, loss {hist[0]:.3f} -> {hist[-1]:.3f}")
+    del xin, t
+    desc = fcgen.porous_poisson_3d(100, n=64, p=2)
+    hs = fc.HostSystem(desc)
+    pb = hs.upload()
+    del hs
+    pc = fc.Precond(pb)
+    b = torch.empty(pb.n, dtype=torch.float64, device="cuda")
+    pb.rhs(b)
+    x = torch.zeros_like(b)
+    runs = {}
+    for name, mode in (("plain", "f64"), ("learned", "learned")):
+        if mode == "learned":
+            pc.attach(model)
+        fc.pcg_solve(pb, pc, b, x, tol=args.tol, stop="residual", mode=mode)  # warm
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        info = fc.pcg_solve(pb, pc, b, x, tol=args.tol, stop="residual", mode=mode)
+        torch.cuda.synchronize()
+        wall = (time.perf_counter() - t0) * 1e3
+        runs[name] = {"iters": info["iters"], "time_to_tol_ms": wall,
+                      "ms_per_iter": wall / max(1, info["iters"]), "status": info["status"],
+                      "rel_res_true": info["rel_res_true"]}
+        log(f"learned: {name} {info['iters']} iterations, {wall:.0f} ms")
+    st = pc.learned_stats()
+    use, ip, il = pc.validate(b, tol=args.tol)
+    x.zero_()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    info = fc.pcg_solve(pb, pc, b, x, tol=args.tol, stop="residual", mode="learned")
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) * 1e3
+    log(f"learned: validated solve ({'network kept' if use else 'plain fallback'}) "
+        f"{info['iters']} iterations, {wall:.0f} ms")
+    return {
+        "workload": "3D finite cell Poisson, 64^3 cells, p=2, 64 spherical voids, alpha=1e-10 "
+                    "(2.1M unknowns); network trained on 48^3-cell cubes",
+        "n_dofs": pb.n, "coarse_grid": pc.coarse_grid(), "train_coarse_grid": G,
+        "params": model.n_params,
+        "train": {"problems": len(descs), "pairs": int(args.learned_pairs // args.learned_train)
+                  * len(descs), "target": args.learned_target, "epochs": args.learned_epochs,
+                  "loss_first": float(hist[0]), "loss_last": float(hist[-1]),
+                  "data_s": t_data, "train_s": t_train},
+        "plain": runs["plain"], "learned": runs["learned"],
+        "corrections": st,
+        "speedup_vs_plain": runs["plain"]["time_to_tol_ms"] / runs["learned"]["time_to_tol_ms"],
+        "iteration_ratio": runs["learned"]["iters"] / max(1, runs["plain"]["iters"]),
+        "validated": {"network_kept": use, "iters": info["iters"], "time_to_tol_ms": wall,
+                      "fallbacks": info["fallbacks"],
+                      "speedup_vs_plain": runs["plain"]["time_to_tol_ms"] / wall},
+    }
+
+
 def batch_bench(fc, args):
     """Uneven batch of 2-D/3-D Poisson problems (grids 8^2..128^2 and
     8^3..24^3, p = 1..4, elliptical inclusions or voids, alpha = 1e-10,
@@ -189,6 +262,12 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-forms", action="store_true",
                     help="skip the mixed-precision forms comparison")
+    ap.add_argument("--no-learned", action="store_true",
+                    help="skip the learned coarse-correction comparison")
+    ap.add_argument("--learned-train", type=int, default=8, help="training problems (48^3)")
+    ap.add_argument("--learned-pairs", type=int, default=2000, help="training pairs in total")
+    ap.add_argument("--learned-epochs", type=int, default=15)
+    ap.add_argument("--learned-target", default="e-Sr", choices=["e-Sr", "e"])
     ap.add_argument("--batch", type=int, default=0,
                     help="instead: solve this many problems of the uneven batch "
                          "generator together (512 = the full batch)")
@@ -285,6 +364,8 @@ def main():
     }
     if not args.no_forms:
         out["forms"] = forms(fc, pb, b, args.tol, out["time_to_tol_ms"][-1], iters[-1])
+    if not args.no_learned and not args.small:
+        out["learned"] = learned_bench(fc, args)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out), flush=True)

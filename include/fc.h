@@ -359,6 +359,16 @@ fc_status fc_coarse_prolong(fc_precond pc, const float* y_dev, double gamma, dou
  * fc_coarse_restrict (0 when not positive finite).  Synchronises. */
 fc_status fc_coarse_apply(fc_precond pc, const float* y_dev, double* v_dev, double* gamma,
                           void* stream);
+/* Plain Schwarz-PCG judges the network: solve A x = b to tol (relative
+ * residual) once with FC_MODE_F64 and once with FC_MODE_LEARNED, keep the
+ * network for later FC_MODE_LEARNED solves of this preconditioner only if
+ * the learned run converges in less device time, else those solves run
+ * plain PCG (fc_solve_info.fallbacks = 1).  *use_network receives the
+ * decision; plain / learned (may be NULL) the two runs' infos.
+ * fc_learned_attach resets the decision to "use". */
+fc_status fc_learned_validate(fc_precond pc, const double* b_dev, double tol,
+                              int32_t* use_network, fc_solve_info* plain,
+                              fc_solve_info* learned, void* stream);
 /* Corrections applied and dropped since fc_learned_attach. */
 fc_status fc_learned_stats(fc_precond pc, int64_t* n_apply, int64_t* n_drop);
 /* Training pairs from a running FP64 Schwarz-PCG solve of A x = b from

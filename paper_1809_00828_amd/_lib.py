@@ -37,6 +37,7 @@ EXPORTS = [
     "fc_model_forward", "fc_model_loss_grad", "fc_model_train", "fc_model_destroy",
     "fc_learned_attach", "fc_coarse_grid", "fc_coarse_channels", "fc_coarse_restrict",
     "fc_coarse_prolong", "fc_coarse_apply", "fc_learned_stats", "fc_learned_snapshots",
+    "fc_learned_validate",
 ]
 
 
@@ -128,6 +129,7 @@ def load():
         "fc_coarse_apply": [vp, dp, dp, P(C.c_double), vp],
         "fc_learned_stats": [vp, P(i64), P(i64)],
         "fc_learned_snapshots": [vp, dp, dp, i32, vp, i32, C.c_double, dp, dp, P(i32), vp],
+        "fc_learned_validate": [vp, dp, C.c_double, P(i32), P(SolveInfo), P(SolveInfo), vp],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -378,6 +380,15 @@ class Precond:
                                        C.byref(g), C.c_void_p(_stream(stream))))
         return g.value
 
+    def validate(self, b, tol=1e-8, stream=None):
+        """fc_learned_validate: returns (use_network, plain info, learned info)."""
+        use = C.c_int32()
+        ip, il = SolveInfo(), SolveInfo()
+        _check(load().fc_learned_validate(self._h, C.c_void_p(_dptr(b)), float(tol),
+                                          C.byref(use), C.byref(ip), C.byref(il),
+                                          C.c_void_p(_stream(stream))))
+        return bool(use.value), _info_dict(ip), _info_dict(il)
+
     def learned_stats(self):
         a, d = C.c_int64(), C.c_int64()
         _check(load().fc_learned_stats(self._h, C.byref(a), C.byref(d)))
@@ -412,6 +423,10 @@ def pcg_solve(problem: Problem, precond: Precond, b, x, tol=1e-10, maxit=300000,
                              C.byref(o), C.byref(info), C.c_void_p(_stream(stream)))
     if st not in (FC_OK, FC_E_NOTCONV, FC_E_BREAKDOWN, FC_E_NAN) or (raise_on_error and st):
         _check(st)
+    return _info_dict(info, st)
+
+
+def _info_dict(info, st=FC_OK):
     return {"iters": info.iters, "outer_iters": info.outer_iters,
             "rel_res_true": info.rel_res_true, "rel_res_prec": info.rel_res_prec,
             "status": STATUS_NAMES.get(info.status if st == FC_OK else st, st),

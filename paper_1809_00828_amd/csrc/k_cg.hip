@@ -418,6 +418,36 @@ struct CoreResult {
   int64_t n_timed = 0;
 };
 
+// (Re)capture the chunk of steps into a graph when the buffers, precisions
+// or length change.  Capturing is host work: callers that time the solve
+// on the device call this before their first event so the timed region
+// does not include it.
+static fc_status ensure_graph(fc_precond_s& pc, SolverWs& w, const CoreArgs& a, hipStream_t s) {
+  const int chunk = a.chunk > 0 ? a.chunk : 16;
+  const int prec = a.precA * 4 + a.precS + (a.learn ? 16 : 0);
+  if (w.exec && w.key[0] == a.x && w.key_chunk == chunk && w.key_prec == prec) return FC_OK;
+  if (w.exec) {
+    FC_HIP(hipGraphExecDestroy(w.exec));
+    w.exec = nullptr;
+  }
+  if (w.graph) {
+    FC_HIP(hipGraphDestroy(w.graph));
+    w.graph = nullptr;
+  }
+  FC_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+  hipError_t e = enqueue_steps(pc, w, a.x, chunk, a.precA, a.precS, s, nullptr, a.learn);
+  hipGraph_t g = nullptr;
+  hipError_t e2 = hipStreamEndCapture(s, &g);
+  if (e != hipSuccess) FC_HIP(e);
+  FC_HIP(e2);
+  w.graph = g;
+  FC_HIP(hipGraphInstantiate(&w.exec, g, nullptr, nullptr, 0));
+  w.key[0] = a.x;
+  w.key_chunk = chunk;
+  w.key_prec = prec;
+  return FC_OK;
+}
+
 // One PCG run from x = 0 on the solver stream s.
 static fc_status pcg_core(fc_precond_s& pc, SolverWs& w, const CoreArgs& a, CoreResult* res,
                           hipStream_t s) {
@@ -441,7 +471,6 @@ static fc_status pcg_core(fc_precond_s& pc, SolverWs& w, const CoreArgs& a, Core
                      w.sc);
   FC_HIP(hipGetLastError());
   const int chunk = a.chunk > 0 ? a.chunk : 16;
-  const int prec = a.precA * 4 + a.precS + (a.learn ? 16 : 0);
   const int64_t max_chunks = (a.maxit + chunk - 1) / chunk + 1;
   int64_t launched = 0;
   if (a.timing) {
@@ -469,28 +498,7 @@ static fc_status pcg_core(fc_precond_s& pc, SolverWs& w, const CoreArgs& a, Core
       if (w.host->done != 0 || launched > max_chunks) break;
     }
   } else {
-    // (re)capture the chunk when the buffers, precisions or length change
-    if (!w.exec || w.key[0] != a.x || w.key_chunk != chunk || w.key_prec != prec) {
-      if (w.exec) {
-        FC_HIP(hipGraphExecDestroy(w.exec));
-        w.exec = nullptr;
-      }
-      if (w.graph) {
-        FC_HIP(hipGraphDestroy(w.graph));
-        w.graph = nullptr;
-      }
-      FC_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-      hipError_t e = enqueue_steps(pc, w, a.x, chunk, a.precA, a.precS, s, nullptr, a.learn);
-      hipGraph_t g = nullptr;
-      hipError_t e2 = hipStreamEndCapture(s, &g);
-      if (e != hipSuccess) FC_HIP(e);
-      FC_HIP(e2);
-      w.graph = g;
-      FC_HIP(hipGraphInstantiate(&w.exec, g, nullptr, nullptr, 0));
-      w.key[0] = a.x;
-      w.key_chunk = chunk;
-      w.key_prec = prec;
-    }
+    FC_TRY_ST(ensure_graph(pc, w, a, s));
     for (;;) {
       FC_HIP(hipGraphLaunch(w.exec, s));
       ++launched;
@@ -546,7 +554,6 @@ fc_status pcg_solve(fc_precond_s& pc, const double* b, double* x, const fc_solve
   hipStream_t s = w.stream;
   FC_HIP(hipEventRecord(w.ev[0], user));
   FC_HIP(hipStreamWaitEvent(s, w.ev[0], 0));
-  FC_HIP(hipEventRecord(w.ev[1], s));
 
   fc_status result = FC_OK;
   int64_t iters = 0, outer = 1;
@@ -567,13 +574,18 @@ fc_status pcg_solve(fc_precond_s& pc, const double* b, double* x, const fc_solve
       set_error("fc_pcg_solve: FC_MODE_LEARNED needs a network attached with fc_learned_attach");
       return FC_E_ARG;
     }
-    learn = pc.coarse;
+    // a network that validation found not to pay falls back to plain PCG
+    if (pc.coarse->enabled) learn = pc.coarse;
+    else fallbacks = 1;
   }
-  if (o.mode == FC_MODE_F64 || o.mode == FC_MODE_S_F32 || o.mode == FC_MODE_S_BF16 || learn) {
+  if (o.mode == FC_MODE_F64 || o.mode == FC_MODE_S_F32 || o.mode == FC_MODE_S_BF16 ||
+      o.mode == FC_MODE_LEARNED) {
     // one PCG run with the FP64 matrix (and a low-precision S if asked, or
     // flexible CG with the learned correction)
-    CoreArgs a{b, x, o.tol, o.maxit, learn ? (int)FC_STOP_RESIDUAL : o.stop, 0, precS, o.timing,
-               o.check_every, o.history_dev, learn};
+    const int stop = o.mode == FC_MODE_LEARNED ? (int)FC_STOP_RESIDUAL : o.stop;
+    CoreArgs a{b, x, o.tol, o.maxit, stop, 0, precS, o.timing, o.check_every, o.history_dev, learn};
+    if (!o.timing) FC_TRY_ST(ensure_graph(pc, w, a, s));
+    FC_HIP(hipEventRecord(w.ev[1], s));
     FC_TRY_ST(pcg_core(pc, w, a, &acc, s));
     iters = acc.iters;
     rel_prec = acc.zn0 > 0 ? std::sqrt(acc.zz) / acc.zn0 : 0.0;
@@ -592,6 +604,7 @@ fc_status pcg_solve(fc_precond_s& pc, const double* b, double* x, const fc_solve
     }
     if (!w.d) FC_HIP(hipMalloc(&w.d, n * sizeof(double)));
     if (!w.ro) FC_HIP(hipMalloc(&w.ro, n * sizeof(double)));
+    FC_HIP(hipEventRecord(w.ev[1], s));
     hipLaunchKernelGGL(k_fill, dim3(1024), dim3(256), 0, s, x, 0.0, n);
     hipLaunchKernelGGL(k_copy, dim3(1024), dim3(256), 0, s, b, w.ro, n);
     FC_HIP(hipGetLastError());
@@ -732,3 +745,34 @@ extern "C" fc_status fc_learned_snapshots(fc_precond pc, const double* b, const 
   if (n_taken) *n_taken = j;
   return FC_OK;
 }
+
+extern "C" fc_status fc_learned_validate(fc_precond pc, const double* b, double tol,
+                                         int32_t* use_network, fc_solve_info* plain,
+                                         fc_solve_info* learned, void* stream) {
+  if (!pc || !b || !pc->coarse || !pc->coarse->model || !(tol > 0.0)) {
+    set_error("fc_learned_validate: needs a preconditioner with an attached network, b, tol > 0");
+    return FC_E_ARG;
+  }
+  hipStream_t user = (hipStream_t)stream;
+  const int64_t n = pc->pb->n_dofs;
+  double* x = nullptr;
+  FC_HIP(hipMalloc(&x, n * sizeof(double)));
+  fc_solve_opts o{tol, 300000, FC_STOP_RESIDUAL, FC_MODE_F64, 16, 1e-4, nullptr, 0};
+  fc_solve_info ip{}, il{};
+  pc->coarse->enabled = 1;
+  const fc_status s1 = pcg_solve(*pc, b, x, o, &ip, user);
+  o.mode = FC_MODE_LEARNED;
+  const fc_status s2 = pcg_solve(*pc, b, x, o, &il, user);
+  (void)hipStreamSynchronize(user);
+  (void)hipFree(x);
+  if (s1 != FC_OK && s1 != FC_E_NOTCONV && s1 != FC_E_BREAKDOWN && s1 != FC_E_NAN) return s1;
+  if (s2 != FC_OK && s2 != FC_E_NOTCONV && s2 != FC_E_BREAKDOWN && s2 != FC_E_NAN) return s2;
+  // keep the network only where it reaches tol and beats plain PCG in time
+  const bool keep = s2 == FC_OK && (s1 != FC_OK || il.ms_solve < ip.ms_solve);
+  pc->coarse->enabled = keep ? 1 : 0;
+  if (use_network) *use_network = keep ? 1 : 0;
+  if (plain) *plain = ip;
+  if (learned) *learned = il;
+  return FC_OK;
+}
+

@@ -443,6 +443,7 @@ fc_status fc_learned_attach(fc_precond pc, fc_model m) {
   CoarseCtx& c = *pc->coarse;
   c.ws.release();
   c.model = m;
+  c.enabled = 1;
   if (m) {
     st = c.ws.ensure(m->net, 1, c.G);
     if (st != FC_OK) return st;

@@ -13,8 +13,8 @@
 // then b[co]; tap = dz*9 + dy*3 + dx), a BF16 copy used by every
 // convolution, FP32 activations and FP32 accumulation.
 //
-// Convolution kernels: every thread owns one output voxel and 16 output
-// channels; the 16 x Ci x 27 BF16 weights of the chunk are staged in LDS.
+// Convolution kernels: every lane owns one output voxel and 8 output
+// channels, with the BF16 weights arriving through wave-uniform loads.
 // The data gradient is the same kernel with the weights transposed and the
 // taps mirrored; the weight gradient is one workgroup per (co, ci) pair
 // reducing over voxels (fixed order, no atomics).
@@ -31,7 +31,8 @@
 
 namespace fc {
 
-constexpr int kCoChunk = 16;
+constexpr int kCoT = 8;      // output channels per lane
+constexpr int kConvT = 64;   // lanes per workgroup (one wave)
 
 __device__ __forceinline__ uint16_t f2bf(float f) {
   uint32_t u = __float_as_uint(f);
@@ -40,55 +41,71 @@ __device__ __forceinline__ uint16_t f2bf(float f) {
 }
 
 // y[b][o][v] = act(bias[o] + sum_{i,t} w(o,i,t) x[b][i][v + off_t])
-// kTrans: w(o,i,t) = W[i][o][26-t] (data gradient of a convolution with
-// Ci = Cout of the layer), no bias, no activation.
+// One wave per workgroup, one voxel and kCoT output channels per lane.  The
+// weights are read at wave-uniform addresses from rows of 14 dwords (27
+// BF16 taps and one pad per (co, ci) pair), so they arrive through scalar
+// loads and feed the FMAs as scalar operands; the 27 neighbour values of
+// an input channel are loaded once and reused for all kCoT outputs.
+// kTrans: w(o,i,t) = W[i][o][26-t] (data gradient of a convolution whose
+// input width is this kernel's Co), no bias, no activation.
 template <bool kTrans>
-__global__ __launch_bounds__(256) void k_conv3d(const float* __restrict__ x, int Ci,
-                                                const uint16_t* __restrict__ W,
-                                                const float* __restrict__ bias,
-                                                float* __restrict__ y, int Co, int D, int H,
-                                                int Wd, int relu) {
-  extern __shared__ uint16_t wsh[];   // [kCoChunk][Ci][27]
-  const int V = D * H * Wd;
+__global__ __launch_bounds__(kConvT) void k_conv3d(const float* __restrict__ x, int Ci,
+                                                   const uint32_t* __restrict__ W,
+                                                   const float* __restrict__ bias,
+                                                   float* __restrict__ y, int Co, int N,
+                                                   int relu) {
+  const int V = N * N * N;
   const int b = blockIdx.z;
-  const int o0 = blockIdx.y * kCoChunk;
-  const int nco = min(kCoChunk, Co - o0);
-  // stage weights of this output chunk
-  for (int t = threadIdx.x; t < nco * Ci * 27; t += blockDim.x) {
-    const int o = t / (Ci * 27), rem = t % (Ci * 27), i = rem / 27, k = rem % 27;
-    uint16_t v;
-    if (kTrans)
-      v = W[((int64_t)i * Co + (o0 + o)) * 27 + (26 - k)];   // layer W[co=i][ci=o0+o]
-    else
-      v = W[((int64_t)(o0 + o) * Ci + i) * 27 + k];
-    wsh[(o * Ci + i) * 27 + k] = v;
-  }
-  __syncthreads();
-  const int v = blockIdx.x * blockDim.x + threadIdx.x;
-  if (v >= V) return;
-  const int xx = v % Wd, yy = (v / Wd) % H, zz = v / (Wd * H);
-  float acc[kCoChunk];
+  const int o0 = blockIdx.y * kCoT;
+  const int v = blockIdx.x * kConvT + threadIdx.x;
+  const bool active = v < V;
+  const int vv = active ? v : 0;
+  const int xx = vv % N, yy = (vv / N) % N, zz = vv / (N * N);
+  float acc[kCoT];
 #pragma unroll
-  for (int o = 0; o < kCoChunk; ++o) acc[o] = (!kTrans && bias && o < nco) ? bias[o0 + o] : 0.f;
+  for (int o = 0; o < kCoT; ++o) acc[o] = (!kTrans && bias && o0 + o < Co) ? bias[o0 + o] : 0.f;
   const float* xb = x + (int64_t)b * Ci * V;
   for (int i = 0; i < Ci; ++i) {
     const float* xi = xb + (int64_t)i * V;
-    const uint16_t* wi = wsh + i * 27;
+    float xv[27];
 #pragma unroll
     for (int k = 0; k < 27; ++k) {
-      const int dz = k / 9 - 1, dy = (k / 3) % 3 - 1, dx = k % 3 - 1;
-      const int z2 = zz + dz, y2 = yy + dy, x2 = xx + dx;
-      const bool in = z2 >= 0 && z2 < D && y2 >= 0 && y2 < H && x2 >= 0 && x2 < Wd;
-      const float xv = in ? xi[(z2 * H + y2) * Wd + x2] : 0.f;
+      const int z2 = zz + k / 9 - 1, y2 = yy + (k / 3) % 3 - 1, x2 = xx + k % 3 - 1;
+      const bool in = z2 >= 0 && z2 < N && y2 >= 0 && y2 < N && x2 >= 0 && x2 < N;
+      xv[k] = in ? xi[(z2 * N + y2) * N + x2] : 0.f;
+    }
 #pragma unroll
-      for (int o = 0; o < kCoChunk; ++o)
-        acc[o] = fmaf(bf16_to_f32(wi[o * Ci * 27 + k]), xv, acc[o]);
+    for (int o = 0; o < kCoT; ++o) {
+      if (o0 + o >= Co) break;
+      const int64_t row = kTrans ? ((int64_t)i * Co + (o0 + o)) : ((int64_t)(o0 + o) * Ci + i);
+      const uint32_t* wr = W + row * kRowDw;
+#pragma unroll
+      for (int j = 0; j < kRowDw; ++j) {
+        const uint32_t pr = wr[j];
+        const float wlo = __uint_as_float(pr << 16), whi = __uint_as_float(pr & 0xffff0000u);
+        const int k0 = 2 * j, k1 = 2 * j + 1;
+        acc[o] = fmaf(wlo, xv[kTrans ? 26 - k0 : k0], acc[o]);
+        if (k1 < 27) acc[o] = fmaf(whi, xv[kTrans ? 26 - k1 : k1], acc[o]);
+      }
     }
   }
+  if (!active) return;
   float* yb = y + (int64_t)b * Co * V;
 #pragma unroll
-  for (int o = 0; o < kCoChunk; ++o)
-    if (o < nco) yb[(int64_t)(o0 + o) * V + v] = relu ? fmaxf(acc[o], 0.f) : acc[o];
+  for (int o = 0; o < kCoT; ++o)
+    if (o0 + o < Co) yb[(int64_t)(o0 + o) * V + v] = relu ? fmaxf(acc[o], 0.f) : acc[o];
+}
+
+// BF16 rows of 14 dwords from the FP32 weights W[rows][27]
+__global__ void k_pack_w(const float* __restrict__ w, uint32_t* __restrict__ out, int64_t rows) {
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < rows * kRowDw;
+       t += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t row = t / kRowDw;
+    const int j = (int)(t % kRowDw);
+    const uint32_t lo = f2bf(w[row * 27 + 2 * j]);
+    const uint32_t hi = 2 * j + 1 < 27 ? f2bf(w[row * 27 + 2 * j + 1]) : 0u;
+    out[t] = lo | (hi << 16);
+  }
 }
 
 // gw[co][ci][t] = sum_{b,v} g[b][co][v] x[b][ci][v + off_t];  gb[co] = sum g
@@ -243,8 +260,8 @@ __global__ __launch_bounds__(256) void k_mse(const float* __restrict__ y,
 }
 
 __global__ void k_adam(float* __restrict__ p, const float* __restrict__ g, float* __restrict__ m,
-                       float* __restrict__ v, uint16_t* __restrict__ pb, int64_t n, float lr,
-                       float b1, float b2, float eps, float c1, float c2) {
+                       float* __restrict__ v, int64_t n, float lr, float b1, float b2, float eps,
+                       float c1, float c2) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x) {
     const float gi = g[i];
@@ -252,16 +269,8 @@ __global__ void k_adam(float* __restrict__ p, const float* __restrict__ g, float
     const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
     m[i] = mi;
     v[i] = vi;
-    const float pi = p[i] - lr * (mi / c1) / (sqrtf(vi / c2) + eps);
-    p[i] = pi;
-    pb[i] = f2bf(pi);
+    p[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
   }
-}
-
-__global__ void k_to_bf16(const float* __restrict__ p, uint16_t* __restrict__ pb, int64_t n) {
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-       i += (int64_t)gridDim.x * blockDim.x)
-    pb[i] = f2bf(p[i]);
 }
 
 static inline dim3 grid1(int64_t n) {
@@ -286,6 +295,12 @@ void Net::init(const int32_t* c, int32_t in_channels) {
     off += co[l];
   }
   nparam = off;
+  int64_t dw = 0;
+  for (int l = 0; l < 15; ++l) {
+    wpoff[l] = dw;
+    dw += (int64_t)ci[l] * co[l] * kRowDw;
+  }
+  nwpk = dw;
 }
 
 int64_t net_param_count(const int32_t* c, int32_t in_channels) {
@@ -298,10 +313,9 @@ static hipError_t conv_fwd(const Net& net, int l, const float* x, float* y, int 
                            hipStream_t s) {
   const int Ci = net.ci[l], Co = net.co[l];
   const int V = N * N * N;
-  dim3 g((V + 255) / 256, (Co + kCoChunk - 1) / kCoChunk, B);
-  const size_t lds = (size_t)kCoChunk * Ci * 27 * sizeof(uint16_t);
-  hipLaunchKernelGGL(k_conv3d<false>, g, dim3(256), lds, s, x, Ci, net.wbf + net.woff[l],
-                     net.p + net.boff[l], y, Co, N, N, N, relu ? 1 : 0);
+  dim3 g((V + kConvT - 1) / kConvT, (Co + kCoT - 1) / kCoT, B);
+  hipLaunchKernelGGL(k_conv3d<false>, g, dim3(kConvT), 0, s, x, Ci, net.wpk + net.wpoff[l],
+                     net.p + net.boff[l], y, Co, N, relu ? 1 : 0);
   return hipGetLastError();
 }
 
@@ -310,10 +324,9 @@ static hipError_t conv_bwd_data(const Net& net, int l, const float* gy, float* g
                                 hipStream_t s) {
   const int Ci = net.ci[l], Co = net.co[l];
   const int V = N * N * N;
-  dim3 g((V + 255) / 256, (Ci + kCoChunk - 1) / kCoChunk, B);
-  const size_t lds = (size_t)kCoChunk * Co * 27 * sizeof(uint16_t);
-  hipLaunchKernelGGL(k_conv3d<true>, g, dim3(256), lds, s, gy, Co, net.wbf + net.woff[l], nullptr,
-                     gx, Ci, N, N, N, 0);
+  dim3 g((V + kConvT - 1) / kConvT, (Ci + kCoT - 1) / kCoT, B);
+  hipLaunchKernelGGL(k_conv3d<true>, g, dim3(kConvT), 0, s, gy, Co, net.wpk + net.wpoff[l],
+                     nullptr, gx, Ci, N, 0);
   return hipGetLastError();
 }
 
@@ -485,12 +498,18 @@ hipError_t net_adam(Net& net, float lr, int64_t step, hipStream_t s) {
   const float b1 = 0.9f, b2 = 0.999f;
   const float c1 = 1.f - powf(b1, (float)step), c2 = 1.f - powf(b2, (float)step);
   hipLaunchKernelGGL(k_adam, grid1(net.nparam), dim3(256), 0, s, net.p, net.g, net.m, net.v,
-                     net.wbf, net.nparam, lr, b1, b2, 1e-8f, c1, c2);
-  return hipGetLastError();
+                     net.nparam, lr, b1, b2, 1e-8f, c1, c2);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  return net_sync_bf16(net, s);
 }
 
 hipError_t net_sync_bf16(Net& net, hipStream_t s) {
-  hipLaunchKernelGGL(k_to_bf16, grid1(net.nparam), dim3(256), 0, s, net.p, net.wbf, net.nparam);
+  for (int l = 0; l < 15; ++l) {
+    const int64_t rows = (int64_t)net.ci[l] * net.co[l];
+    hipLaunchKernelGGL(k_pack_w, grid1(rows * kRowDw), dim3(256), 0, s, net.p + net.woff[l],
+                       net.wpk + net.wpoff[l], rows);
+  }
   return hipGetLastError();
 }
 

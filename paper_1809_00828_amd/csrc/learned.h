@@ -9,15 +9,19 @@
 
 namespace fc {
 
+constexpr int kRowDw = 14;   // dwords per packed BF16 weight row (27 taps + pad)
+
 // Parameters and optimiser state of the 4-level U-Net (device memory).
 struct Net {
   int ch[4] = {0, 0, 0, 0};
   int in_ch = 2;
   int ci[15], co[15];
   int64_t woff[15], boff[15];
-  int64_t nparam = 0;
+  int64_t wpoff[15];       // dword offset of each layer's packed BF16 rows
+  int64_t nparam = 0, nwpk = 0;
   float* p = nullptr;      // FP32 master parameters
-  uint16_t* wbf = nullptr; // BF16 copy used by the convolutions
+  uint32_t* wpk = nullptr; // BF16 weights used by the convolutions: per
+                           // (co, ci) a row of 14 dwords, 27 taps + pad
   float* g = nullptr;      // gradient
   float* m = nullptr;      // Adam first moment
   float* v = nullptr;      // Adam second moment
@@ -80,6 +84,7 @@ struct CoarseCtx {
   double* partial = nullptr; // [2 * kCoarsePartials]
   LearnScalars* ls = nullptr;
   fc_model_s* model = nullptr;
+  int enabled = 1;           // 0: validation found the network does not pay
   NetWs ws;                  // inference activations (batch 1)
 };
 constexpr int kCoarsePartials = 2048;

@@ -262,3 +262,41 @@ def test_learned_fcg_matches_oracle_fcg(torch, name):
     st = pc.learned_stats()
     assert st["applied"] == il["iters"] + 1
     assert st["dropped"] == 0
+
+
+def test_trained_network_gain_and_fallback(torch):
+    """Train on pairs from three 16^3 problems, then let plain Schwarz-PCG
+    judge the network on a fourth: the learned solve is kept only where it
+    is faster, and otherwise FC_MODE_LEARNED runs exactly the plain solve.
+    Prints what the trained network gains (or loses) in iterations and time."""
+    from paper_1809_00828_amd import learned as LR
+    print("[learned] gain test: data", flush=True)
+    descs = [fcgen.porous_poisson_3d(500 + i, n=16, p=2, n_voids=24, rmin=0.04, rmax=0.1)
+             for i in range(3)]
+    xin, t, G = LR.training_set(descs, 80, kind="e")
+    assert xin.shape == (240, 2, G ** 3) and G == 9
+    m = fc.Model(fcgen.unet_init(CH, 2, seed=1), CH)
+    hist = LR.train(m, xin, t, G, epochs=30, batch=8, lr=3e-4)
+    print("[learned] loss", hist[0], "->", hist[-1], flush=True)
+    assert hist[-1] < hist[0]
+    desc = fcgen.porous_poisson_3d(599, n=16, p=2, n_voids=24, rmin=0.04, rmax=0.1)
+    pb = fc.Problem.setup(desc)
+    pc = fc.Precond(pb)
+    pc.attach(m)
+    b = torch.empty(pb.n, dtype=torch.float64, device="cuda")
+    pb.rhs(b)
+    use, ip, il = pc.validate(b, tol=1e-8)
+    print(f"[learned] plain {ip['iters']} it {ip['ms_solve']:.2f} ms, learned {il['iters']} it "
+          f"{il['ms_solve']:.2f} ms, network kept: {use}", flush=True)
+    assert ip["status"] == "OK" and il["status"] == "OK"
+    assert use == (il["ms_solve"] < ip["ms_solve"])
+    x = torch.zeros_like(b)
+    info = fc.pcg_solve(pb, pc, b, x, tol=1e-8, stop="residual", mode="learned")
+    xp = torch.zeros_like(b)
+    infp = fc.pcg_solve(pb, pc, b, xp, tol=1e-8, stop="residual", mode="f64")
+    assert info["status"] == "OK"
+    if use:
+        assert info["fallbacks"] == 0 and info["iters"] == il["iters"]
+    else:
+        assert info["fallbacks"] == 1 and info["iters"] == infp["iters"]
+        assert torch.equal(x, xp)
