@@ -27,6 +27,11 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# HBM bytes per launch on the 32^3 elasticity workload from two rocprofv3
+# counter passes (FETCH_SIZE, WRITE_SIZE), scaled by what the same counters
+# read for a plain 4 GiB copy (profiles/pcg_fp64_elastic32_p3_hbm_counters.md);
+# to be re-measured whenever one of these kernels changes.
+TRAFFIC = {"spmv": 8.5544e9, "schwarz": 4.6883e9}
 METRIC = "DOF·iter/s and time-to-1e-8 residual: mixed/learned vs plain FP64 PCG"
 
 
@@ -119,6 +124,22 @@ def forms(fc, pb, b, tol, t_f64, it_f64):
         log(f"form {mode}: {r['iters']} iterations, {r['ms_solve']:.0f} ms, {r['status']}")
     del pc
     return res
+
+
+COPY_BYTES = 4 << 30
+
+
+def copy_calibration(torch):
+    """Three device-to-device copies of COPY_BYTES by torch's elementwise copy
+    kernel: it reads and writes exactly COPY_BYTES, so a byte counter's
+    reading for it gives the factor from counter units to HBM bytes."""
+    a = torch.ones(COPY_BYTES // 8, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    log(f"copy calibration: 3 copies of {COPY_BYTES} bytes")
+    del a, b
 
 
 def learned_bench(fc, args):
@@ -268,6 +289,9 @@ def main():
     ap.add_argument("--learned-pairs", type=int, default=2000, help="training pairs in total")
     ap.add_argument("--learned-epochs", type=int, default=15)
     ap.add_argument("--learned-target", default="e-Sr", choices=["e-Sr", "e"])
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="first copy 4 GiB three times with a plain copy kernel, the reference "
+                         "for scaling hardware byte counters")
     ap.add_argument("--batch", type=int, default=0,
                     help="instead: solve this many problems of the uneven batch "
                          "generator together (512 = the full batch)")
@@ -281,6 +305,8 @@ def main():
     import paper_1809_00828_amd as fc
 
     torch.cuda.set_device(0)
+    if args.copy_calibration:
+        copy_calibration(torch)
     if args.batch:
         print(json.dumps(batch_bench(fc, args)), flush=True)
         return
@@ -332,13 +358,16 @@ def main():
     gbs_schw = schw_b / (ms_schw * 1e-3) / 1e9
     gbs_spmv = spmv_b / (ms_spmv * 1e-3) / 1e9
     total_dof_iters = n * sum(iters)
+    on_bench_workload = not args.small
     k_spmv = {"bound": "hbm", "kernel": "k_spmv_bsr<3,64,double> (SpMV q = A p)",
               "achieved": gbs_spmv, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-              "frac": gbs_spmv / HBM_PEAK_GBS, "traffic": None,
+              "frac": gbs_spmv / HBM_PEAK_GBS,
+              "traffic": TRAFFIC["spmv"] if on_bench_workload else None,
               "bytes_per_launch": spmv_b, "avg_ms": ms_spmv}
     k_schw = {"bound": "hbm", "kernel": "k_schwarz_sym_staged<double> (block products)",
               "achieved": gbs_schw, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-              "frac": gbs_schw / HBM_PEAK_GBS, "traffic": None,
+              "frac": gbs_schw / HBM_PEAK_GBS,
+              "traffic": TRAFFIC["schwarz"] if on_bench_workload else None,
               "bytes_per_launch": schw_b, "avg_ms": ms_schw}
     dominant, other = (k_spmv, k_schw) if ms_spmv >= ms_schw else (k_schw, k_spmv)
     out = {
