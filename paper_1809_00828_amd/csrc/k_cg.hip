@@ -5,8 +5,11 @@
 //   q = A p;  alpha = (r,z)/(p,q);  x += alpha p;  r -= alpha q;
 //   z = S r;  beta = (r,z)_new/(r,z);  p = z + beta p.
 // One step is six kernels, all reading their scalars from device memory:
-//   1. SpMV q = A p with per-workgroup (p,q) partials (k_spmv.hip)
-//   2. one workgroup sums them in a fixed order: alpha, step count
+//   1. SpMV q = A p (k_spmv.hip)
+//   2. (p, q) by workgroup partials, summed in a fixed order by the last
+//      workgroup: alpha, step count.  Fusing the dot into the SpMV costs
+//      more than this extra pass over p and q: the SpMV's end-of-workgroup
+//      reduction holds its four waves until the slowest one finishes.
 //   3. Schwarz phase 1 on the gathered r - alpha q (k_schwarz.hip)
 //   4. pull z = sum_B R_B^T y_B + fallback, fused with the x and r updates
 //      and per-workgroup (r,z), (z,z), (r,r) partials
@@ -20,6 +23,7 @@
 #include <hip/hip_runtime.h>
 
 #include <chrono>
+#include <cstdlib>
 #include <cmath>
 #include <vector>
 
@@ -130,6 +134,36 @@ __global__ __launch_bounds__(1024) void k_cg_alpha(const double* __restrict__ pa
   }
   for (; i < np; i += blockDim.x) t0 += partial[i];
   const double pq = block_sum((t0 + t1) + (t2 + t3), lds);
+  if (threadIdx.x == 0) {
+    sc->pq = pq;
+    sc->iter += 1;
+    const double rz = sc->rz;
+    if (!(pq > 0.0) || !(rz > 0.0)) {
+      sc->done = (pq != pq || rz != rz) ? 4 : 3;
+    } else {
+      sc->alpha = rz / pq;
+    }
+  }
+}
+
+// Step length from a separate (p, q) reduction: per-workgroup partials,
+// the last workgroup sums them in a fixed order and sets alpha (used when
+// the SpMV runs without its fused dot).
+__global__ __launch_bounds__(256) void k_cg_pq_alpha(const double* __restrict__ p,
+                                                     const double* __restrict__ q, int64_t n,
+                                                     double* __restrict__ partial,
+                                                     CgScalars* sc) {
+  __shared__ double lds[16];
+  __shared__ int flag;
+  if (sc->done) return;
+  double a = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    a = fma(p[i], q[i], a);
+  a = block_sum(a, lds);
+  if (threadIdx.x == 0) partial[blockIdx.x] = a;
+  if (!last_block(&sc->ticket, gridDim.x, &flag)) return;
+  const double pq = sum_partials(partial, gridDim.x, lds);
   if (threadIdx.x == 0) {
     sc->pq = pq;
     sc->iter += 1;
@@ -359,6 +393,16 @@ static fc_status ensure_ws(fc_precond_s& pc, SolverWs** out) {
   return FC_OK;
 }
 
+// FC_CG_SPLIT_DOT=0 fuses (p, A p) into the SpMV (one partial per SpMV
+// workgroup); the default computes it in a separate pass over p and q.
+static bool split_dot() {
+  static const bool v = [] {
+    const char* e = std::getenv("FC_CG_SPLIT_DOT");
+    return !(e && e[0] == '0');
+  }();
+  return v;
+}
+
 // Enqueue `chunk` PCG steps on stream s (with timing events when tev).
 // precA: 0 = FP64 matrix, 1 = FP32 copy; precS: 0/1/2 = FP64/FP32/BF16
 // local inverses.
@@ -370,11 +414,20 @@ static hipError_t enqueue_steps(fc_precond_s& pc, SolverWs& w, double* x, int ch
   for (int it = 0; it < chunk; ++it) {
     hipError_t e;
     if (tev && (e = hipEventRecord(tev[4 * it + 0], s)) != hipSuccess) return e;
-    e = launch_spmv_pq(pb.A, precA == 1, w.p, w.q, w.sc, w.partial, s);
-    if (e != hipSuccess) return e;
-    if (tev && (e = hipEventRecord(tev[4 * it + 1], s)) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_cg_alpha, dim3(1), dim3(1024), 0, s, w.partial, spmv_num_blocks(pb.A),
-                       w.sc);
+    if (split_dot()) {
+      // SpMV without its fused dot, then (p, q) and alpha in one reduction
+      e = launch_spmv_pq(pb.A, precA == 1, w.p, w.q, w.sc, nullptr, s);
+      if (e != hipSuccess) return e;
+      if (tev && (e = hipEventRecord(tev[4 * it + 1], s)) != hipSuccess) return e;
+      hipLaunchKernelGGL(k_cg_pq_alpha, dim3(kRedBlocks), dim3(256), 0, s, w.p, w.q, n,
+                         w.partial, w.sc);
+    } else {
+      e = launch_spmv_pq(pb.A, precA == 1, w.p, w.q, w.sc, w.partial, s);
+      if (e != hipSuccess) return e;
+      if (tev && (e = hipEventRecord(tev[4 * it + 1], s)) != hipSuccess) return e;
+      hipLaunchKernelGGL(k_cg_alpha, dim3(1), dim3(1024), 0, s, w.partial,
+                         spmv_num_blocks(pb.A), w.sc);
+    }
     if (tev && (e = hipEventRecord(tev[4 * it + 2], s)) != hipSuccess) return e;
     e = launch_schwarz_phase1(pc, precS, w.r, w.q, w.sc, s);
     if (e != hipSuccess) return e;
