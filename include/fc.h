@@ -335,8 +335,8 @@ void fc_model_destroy(fc_model m);
  *       coarse vertex = mean over the touching coarse cells of their fine
  *       cells' eta_T),
  *   gamma = (y . P_c^T r) / (y . A_c y), z += gamma P_c y,
- * with gamma = 0 (network term dropped) when the quotient is not a
- * positive finite number, so (z, r) > 0 whenever (S r, r) > 0.
+ * with gamma = 0 (network term dropped) unless y . A_c y > 0 and the
+ * quotient is finite, so (z, r) > 0 whenever (S r, r) > 0.
  * The coarse context lives with the preconditioner and is built on first
  * use by any of these calls. */
 
@@ -356,7 +356,7 @@ fc_status fc_coarse_restrict(fc_precond pc, const double* r_dev, double* rc_dev,
 fc_status fc_coarse_prolong(fc_precond pc, const float* y_dev, double gamma, double* z_dev,
                             void* stream);
 /* v = A_c y; *gamma receives (y . rc) / (y . A_c y) for the rc of the last
- * fc_coarse_restrict (0 when not positive finite).  Synchronises. */
+ * fc_coarse_restrict (0 unless y . A_c y > 0 and finite).  Synchronises. */
 fc_status fc_coarse_apply(fc_precond pc, const float* y_dev, double* v_dev, double* gamma,
                           void* stream);
 /* Plain Schwarz-PCG judges the network: solve A x = b to tol (relative

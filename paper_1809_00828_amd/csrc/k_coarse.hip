@@ -13,8 +13,8 @@
 //
 // Correction inside flexible CG, after z = S r:
 //   rc = P_c^T r; y = N(rc / rms(rc), eta_c); gamma = (y.rc)/(y.A_c y);
-//   z += gamma P_c y  (gamma = 0, the network term dropped, when the
-//   quotient is not a positive finite number).
+//   z += gamma P_c y  (gamma = 0, the network term dropped, unless
+//   y.A_c y > 0 and the quotient is finite).
 // The kernels gate on the solver's stop flag so captured chunks can run on
 // after convergence without changing the iterate.
 #include <hip/hip_runtime.h>
