@@ -52,14 +52,17 @@ struct BProb {
   int32_t spmv_item0, spmv_items, pull_item0, pull_items;
 };
 
+// One tile of one problem.  slot is the item's fixed position in the
+// partial-sum array, so a compacted list of the still-running problems'
+// items writes where the per-problem reductions read.
 struct WorkItem {
-  int32_t prob, tile;
+  int32_t prob, tile, slot;
 };
 
 // ------------------------------------------------------------ kernels
 template <int B, int G>
 __global__ __launch_bounds__(256) void kb_spmv(const BProb* __restrict__ probs,
-                                               const WorkItem* __restrict__ items, int item_base,
+                                               const WorkItem* __restrict__ items,
                                                const CgScalars* __restrict__ sc,
                                                const double* __restrict__ pvec,
                                                double* __restrict__ qvec,
@@ -102,14 +105,15 @@ __global__ __launch_bounds__(256) void kb_spmv(const BProb* __restrict__ probs,
     }
   }
   dot = block_sum(dot, lds);
-  if (threadIdx.x == 0) partial[item_base + blockIdx.x] = dot;
+  if (threadIdx.x == 0) partial[it.slot] = dot;
 }
 
 // alpha per problem from its SpMV partials (one workgroup per problem).
 __global__ __launch_bounds__(256) void kb_alpha(const BProb* __restrict__ probs, CgScalars* sc,
-                                                const double* __restrict__ partial) {
+                                                const double* __restrict__ partial,
+                                                const int32_t* __restrict__ active) {
   __shared__ double lds[16];
-  const int k = blockIdx.x;
+  const int k = active ? active[blockIdx.x] : (int)blockIdx.x;
   CgScalars& S = sc[k];
   if (S.done) return;
   const BProb& P = probs[k];
@@ -258,18 +262,19 @@ __global__ __launch_bounds__(256) void kb_pull(const BProb* __restrict__ probs,
   b = block_sum(b, lds);
   c = block_sum(c, lds);
   if (threadIdx.x == 0) {
-    partial[blockIdx.x] = a;
-    partial[n_items + blockIdx.x] = b;
-    partial[2 * n_items + blockIdx.x] = c;
+    partial[it.slot] = a;
+    partial[n_items + it.slot] = b;
+    partial[2 * n_items + it.slot] = c;
   }
 }
 
 // Per-problem stop test and beta (mode 1) or start (mode 0).
 template <int kMode>
 __global__ __launch_bounds__(256) void kb_beta(const BProb* __restrict__ probs, CgScalars* sc,
-                                               const double* __restrict__ partial, int n_items) {
+                                               const double* __restrict__ partial, int n_items,
+                                               const int32_t* __restrict__ active) {
   __shared__ double lds[16];
-  const int k = blockIdx.x;
+  const int k = active ? active[blockIdx.x] : (int)blockIdx.x;
   CgScalars& S = sc[k];
   if (kMode == 1 && S.done) return;
   const BProb& P = probs[k];
@@ -334,11 +339,15 @@ __global__ __launch_bounds__(256) void kb_vec(const BProb* __restrict__ probs,
 }
 
 // ---------------------------------------------------------- host side
+// items: every tile of every problem of the class; act / d_act: the tiles
+// of the problems still running, which the captured iteration launches.
 struct SpmvClass {
   int B, G;
   std::vector<WorkItem> items;
   WorkItem* d_items = nullptr;
   int item_base = 0;
+  int n_act = 0;
+  WorkItem* d_act = nullptr;
 };
 
 struct SchwarzClass {
@@ -346,6 +355,8 @@ struct SchwarzClass {
   bool small;
   std::vector<WorkItem> items;
   WorkItem* d_items = nullptr;
+  int n_act = 0;
+  WorkItem* d_act = nullptr;
 };
 
 }  // namespace fc
@@ -360,6 +371,11 @@ struct fc_batch_s {
   std::vector<fc::SchwarzClass> schw;
   std::vector<fc::WorkItem> pull_items;
   fc::WorkItem* d_pull = nullptr;
+  int n_act_pull = 0;                 // compacted pull items (see SpmvClass)
+  fc::WorkItem* d_act_pull = nullptr;
+  int n_act_probs = 0;                // problems still running
+  int32_t* d_act_probs = nullptr;
+  int64_t act_dofs = 0;               // unknowns of the problems in the lists
   int spmv_total = 0;
   double *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr, *partial = nullptr;
   fc::CgScalars* sc = nullptr;
@@ -380,10 +396,13 @@ static void destroy_batch(fc_batch_s* b) {
   if (!b) return;
   if (b->exec) (void)hipGraphExecDestroy(b->exec);
   if (b->graph) (void)hipGraphDestroy(b->graph);
-  for (auto& c : b->spmv) if (c.d_items) (void)hipFree(c.d_items);
-  for (auto& c : b->schw) if (c.d_items) (void)hipFree(c.d_items);
-  for (void* p : {(void*)b->d_probs, (void*)b->d_pull, (void*)b->r, (void*)b->z, (void*)b->p,
-                  (void*)b->q, (void*)b->partial, (void*)b->sc})
+  for (auto& c : b->spmv)
+    for (void* p : {(void*)c.d_items, (void*)c.d_act}) if (p) (void)hipFree(p);
+  for (auto& c : b->schw)
+    for (void* p : {(void*)c.d_items, (void*)c.d_act}) if (p) (void)hipFree(p);
+  for (void* p : {(void*)b->d_probs, (void*)b->d_pull, (void*)b->d_act_pull,
+                  (void*)b->d_act_probs, (void*)b->r, (void*)b->z, (void*)b->p, (void*)b->q,
+                  (void*)b->partial, (void*)b->sc})
     if (p) (void)hipFree(p);
   if (b->host_sc) (void)hipHostFree(b->host_sc);
   for (auto& e : b->ev) if (e) (void)hipEventDestroy(e);
@@ -393,13 +412,12 @@ static void destroy_batch(fc_batch_s* b) {
 
 template <int B>
 static void launch_bspmv_G(int G, dim3 g, hipStream_t s, const BProb* probs, const WorkItem* it,
-                           int base, const CgScalars* sc, const double* p, double* q,
-                           double* part) {
+                           const CgScalars* sc, const double* p, double* q, double* part) {
   switch (G) {
-    case 8: hipLaunchKernelGGL((kb_spmv<B, 8>), g, dim3(256), 0, s, probs, it, base, sc, p, q, part); break;
-    case 16: hipLaunchKernelGGL((kb_spmv<B, 16>), g, dim3(256), 0, s, probs, it, base, sc, p, q, part); break;
-    case 32: hipLaunchKernelGGL((kb_spmv<B, 32>), g, dim3(256), 0, s, probs, it, base, sc, p, q, part); break;
-    default: hipLaunchKernelGGL((kb_spmv<B, 64>), g, dim3(256), 0, s, probs, it, base, sc, p, q, part); break;
+    case 8: hipLaunchKernelGGL((kb_spmv<B, 8>), g, dim3(256), 0, s, probs, it, sc, p, q, part); break;
+    case 16: hipLaunchKernelGGL((kb_spmv<B, 16>), g, dim3(256), 0, s, probs, it, sc, p, q, part); break;
+    case 32: hipLaunchKernelGGL((kb_spmv<B, 32>), g, dim3(256), 0, s, probs, it, sc, p, q, part); break;
+    default: hipLaunchKernelGGL((kb_spmv<B, 64>), g, dim3(256), 0, s, probs, it, sc, p, q, part); break;
   }
 }
 
@@ -408,52 +426,59 @@ static hipError_t launch_spmv_class(fc_batch_s& bt, const SpmvClass& c, const Wo
   if (n == 0) return hipSuccess;
   dim3 g((unsigned)n);
   switch (c.B) {
-    case 1: launch_bspmv_G<1>(c.G, g, s, bt.d_probs, items, c.item_base, bt.sc, bt.p, bt.q, bt.partial); break;
-    case 2: launch_bspmv_G<2>(c.G, g, s, bt.d_probs, items, c.item_base, bt.sc, bt.p, bt.q, bt.partial); break;
-    case 3: launch_bspmv_G<3>(c.G, g, s, bt.d_probs, items, c.item_base, bt.sc, bt.p, bt.q, bt.partial); break;
+    case 1: launch_bspmv_G<1>(c.G, g, s, bt.d_probs, items, bt.sc, bt.p, bt.q, bt.partial); break;
+    case 2: launch_bspmv_G<2>(c.G, g, s, bt.d_probs, items, bt.sc, bt.p, bt.q, bt.partial); break;
+    case 3: launch_bspmv_G<3>(c.G, g, s, bt.d_probs, items, bt.sc, bt.p, bt.q, bt.partial); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }
 
-static hipError_t launch_schwarz_class(fc_batch_s& bt, const SchwarzClass& c, const double* q,
-                                       hipStream_t s) {
-  const int n = (int)c.items.size();
+static hipError_t launch_schwarz_class(fc_batch_s& bt, const SchwarzClass& c, const WorkItem* items,
+                                       int n, const double* q, hipStream_t s) {
   if (n == 0) return hipSuccess;
   const int threads = c.small ? 256 : 64 * ((c.m + 63) / 64);
   dim3 g((unsigned)n), b((unsigned)threads);
   if (c.variant == 0) {
     if (c.small)
-      hipLaunchKernelGGL(kb_schwarz<true>, g, b, 0, s, bt.d_probs, c.d_items, bt.sc, bt.r, q, c.m, c.bpw);
+      hipLaunchKernelGGL(kb_schwarz<true>, g, b, 0, s, bt.d_probs, items, bt.sc, bt.r, q, c.m, c.bpw);
     else
-      hipLaunchKernelGGL(kb_schwarz<false>, g, b, 0, s, bt.d_probs, c.d_items, bt.sc, bt.r, q, c.m, c.bpw);
+      hipLaunchKernelGGL(kb_schwarz<false>, g, b, 0, s, bt.d_probs, items, bt.sc, bt.r, q, c.m, c.bpw);
   } else {
     if (c.small)
-      hipLaunchKernelGGL(kb_schwarz_dense<true>, g, b, 0, s, bt.d_probs, c.d_items, bt.sc, bt.r, q, c.m, c.bpw);
+      hipLaunchKernelGGL(kb_schwarz_dense<true>, g, b, 0, s, bt.d_probs, items, bt.sc, bt.r, q, c.m, c.bpw);
     else
-      hipLaunchKernelGGL(kb_schwarz_dense<false>, g, b, 0, s, bt.d_probs, c.d_items, bt.sc, bt.r, q, c.m, c.bpw);
+      hipLaunchKernelGGL(kb_schwarz_dense<false>, g, b, 0, s, bt.d_probs, items, bt.sc, bt.r, q, c.m, c.bpw);
   }
   return hipGetLastError();
 }
 
+// The steps launch the compacted lists: tiles and problems still running.
 static hipError_t enqueue_batch_steps(fc_batch_s& bt, int chunk, hipStream_t s) {
   const int np = (int)bt.pull_items.size();
+  const int na = bt.n_act_pull;
+  if (bt.n_act_probs == 0) return hipSuccess;
   for (int it = 0; it < chunk; ++it) {
     for (auto& c : bt.spmv) {
-      hipError_t e = launch_spmv_class(bt, c, c.d_items, (int)c.items.size(), s);
+      hipError_t e = launch_spmv_class(bt, c, c.d_act, c.n_act, s);
       if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL(kb_alpha, dim3(bt.nprob), dim3(256), 0, s, bt.d_probs, bt.sc, bt.partial);
+    hipLaunchKernelGGL(kb_alpha, dim3(bt.n_act_probs), dim3(256), 0, s, bt.d_probs, bt.sc,
+                       bt.partial, bt.d_act_probs);
     for (auto& c : bt.schw) {
-      hipError_t e = launch_schwarz_class(bt, c, bt.q, s);
+      hipError_t e = launch_schwarz_class(bt, c, c.d_act, c.n_act, bt.q, s);
       if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL(kb_pull<1>, dim3(np), dim3(256), 0, s, bt.d_probs, bt.d_pull, np, bt.sc,
-                       bt.r, bt.p, bt.q, bt.z, bt.partial);
-    hipLaunchKernelGGL(kb_beta<1>, dim3(bt.nprob), dim3(256), 0, s, bt.d_probs, bt.sc, bt.partial,
-                       np);
-    hipLaunchKernelGGL(kb_vec<1>, dim3(np), dim3(256), 0, s, bt.d_probs, bt.d_pull, bt.sc, bt.r,
-                       bt.p, bt.z);
+    if (na > 0) {
+      hipLaunchKernelGGL(kb_pull<1>, dim3(na), dim3(256), 0, s, bt.d_probs, bt.d_act_pull, np,
+                         bt.sc, bt.r, bt.p, bt.q, bt.z, bt.partial);
+    }
+    hipLaunchKernelGGL(kb_beta<1>, dim3(bt.n_act_probs), dim3(256), 0, s, bt.d_probs, bt.sc,
+                       bt.partial, np, bt.d_act_probs);
+    if (na > 0) {
+      hipLaunchKernelGGL(kb_vec<1>, dim3(na), dim3(256), 0, s, bt.d_probs, bt.d_act_pull, bt.sc,
+                         bt.r, bt.p, bt.z);
+    }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
@@ -567,7 +592,8 @@ extern "C" fc_status fc_batch_create(int32_t nprob, const fc_problem* problems,
       if (spmv_key[std::make_pair(pb->bdim, bucket)] != cls) continue;
       const int rpw = 256 / c.G;
       const int64_t nt = (pb->A.n_rows + rpw - 1) / rpw;
-      for (int64_t t = 0; t < nt; ++t) c.items.push_back({k, (int32_t)t});
+      for (int64_t t = 0; t < nt; ++t)
+        c.items.push_back({k, (int32_t)t, (int32_t)c.items.size()});
     }
   };
   for (size_t c = 0; c < B.spmv.size(); ++c) build_spmv_items(B.spmv[c], (int)c);
@@ -576,14 +602,16 @@ extern "C" fc_status fc_batch_create(int32_t nprob, const fc_problem* problems,
       if (B.host[k].m != c.m) continue;
       const int64_t per = c.small ? 4 * (int64_t)c.bpw : 1;
       const int64_t nt = (B.host[k].n_blocks + per - 1) / per;
-      for (int64_t t = 0; t < nt; ++t) c.items.push_back({k, (int32_t)t});
+      for (int64_t t = 0; t < nt; ++t)
+        c.items.push_back({k, (int32_t)t, (int32_t)c.items.size()});
     }
   }
   for (int k = 0; k < nprob; ++k) {
     const int64_t nt = (B.host[k].n_dofs + 255) / 256;
     B.host[k].pull_item0 = (int32_t)B.pull_items.size();
     B.host[k].pull_items = (int32_t)nt;
-    for (int64_t t = 0; t < nt; ++t) B.pull_items.push_back({k, (int32_t)t});
+    for (int64_t t = 0; t < nt; ++t)
+      B.pull_items.push_back({k, (int32_t)t, (int32_t)B.pull_items.size()});
   }
   auto upload_items = [&](std::vector<WorkItem>& v, WorkItem** d) -> fc_status {
     if (*d) {
@@ -600,6 +628,7 @@ extern "C" fc_status fc_batch_create(int32_t nprob, const fc_problem* problems,
     for (auto& c : B.spmv) {
       c.item_base = base;
       for (size_t i = 0; i < c.items.size(); ++i) {
+        c.items[i].slot = base + (int32_t)i;
         BProb& P = B.host[c.items[i].prob];
         if (i == 0 || c.items[i - 1].prob != c.items[i].prob) {
           P.spmv_item0 = base + (int)i;
@@ -669,8 +698,9 @@ extern "C" fc_status fc_batch_create(int32_t nprob, const fc_problem* problems,
       int bestv = 0;
       for (int v : {0, 1}) {
         c.variant = v;
-        float ms = time_launches(s, B.ev[1], B.ev[2], 3,
-                                 [&]() { (void)launch_schwarz_class(B, c, nullptr, s); });
+        float ms = time_launches(s, B.ev[1], B.ev[2], 3, [&]() {
+          (void)launch_schwarz_class(B, c, c.d_items, (int)c.items.size(), nullptr, s);
+        });
         rep << "schwarz m=" << c.m << " " << (v ? "dense" : "symmetric") << ": " << ms << " ms\n";
         if (ms < best) {
           best = ms;
@@ -690,6 +720,13 @@ extern "C" fc_status fc_batch_create(int32_t nprob, const fc_problem* problems,
     rep << "chosen schwarz m=" << c.m << " " << (c.variant ? "dense" : "symmetric")
         << " items=" << c.items.size() << "\n";
   B.report = rep.str();
+  for (auto& c : B.spmv)
+    if (!c.items.empty()) FC_HIP(hipMalloc(&c.d_act, c.items.size() * sizeof(WorkItem)));
+  for (auto& c : B.schw)
+    if (!c.items.empty()) FC_HIP(hipMalloc(&c.d_act, c.items.size() * sizeof(WorkItem)));
+  FC_HIP(hipMalloc(&B.d_act_pull, B.pull_items.size() * sizeof(WorkItem)));
+  FC_HIP(hipMalloc(&B.d_act_probs, nprob * sizeof(int32_t)));
+  B.act_dofs = -1;   // lists not built yet
   FC_HIP(hipStreamSynchronize(s));
   *out = bt.release();
   return FC_OK;
@@ -706,6 +743,57 @@ extern "C" fc_status fc_batch_info(fc_batch bt, int64_t* total_dofs, int32_t* n_
     std::memcpy(report, bt->report.data(), k);
     report[k] = '\0';
   }
+  return FC_OK;
+}
+
+// Launched lists = the tiles of the problems marked running (synchronous
+// upload into the full-size arrays allocated at creation).
+static fc_status compact_lists(fc_batch_s& B, const std::vector<char>& running) {
+  auto filter = [&](const std::vector<WorkItem>& all, WorkItem* d, int* n) -> fc_status {
+    std::vector<WorkItem> v;
+    v.reserve(all.size());
+    for (const WorkItem& w : all)
+      if (running[w.prob]) v.push_back(w);
+    *n = (int)v.size();
+    if (!v.empty()) FC_HIP(hipMemcpy(d, v.data(), v.size() * sizeof(WorkItem), hipMemcpyHostToDevice));
+    return FC_OK;
+  };
+  for (auto& c : B.spmv) FC_TRY_B(filter(c.items, c.d_act, &c.n_act));
+  for (auto& c : B.schw) FC_TRY_B(filter(c.items, c.d_act, &c.n_act));
+  FC_TRY_B(filter(B.pull_items, B.d_act_pull, &B.n_act_pull));
+  std::vector<int32_t> ap;
+  int64_t dofs = 0;
+  for (int k = 0; k < B.nprob; ++k)
+    if (running[k]) {
+      ap.push_back(k);
+      dofs += B.host[k].n_dofs;
+    }
+  B.n_act_probs = (int)ap.size();
+  B.act_dofs = dofs;
+  if (!ap.empty())
+    FC_HIP(hipMemcpy(B.d_act_probs, ap.data(), ap.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+  return FC_OK;
+}
+
+// Capture `chunk` steps over the current lists into the batch's graph.
+static fc_status capture_steps(fc_batch_s& B, int chunk, hipStream_t s) {
+  if (B.exec) {
+    FC_HIP(hipGraphExecDestroy(B.exec));
+    B.exec = nullptr;
+  }
+  if (B.graph) {
+    FC_HIP(hipGraphDestroy(B.graph));
+    B.graph = nullptr;
+  }
+  FC_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+  hipError_t e = enqueue_batch_steps(B, chunk, s);
+  hipGraph_t g = nullptr;
+  hipError_t e2 = hipStreamEndCapture(s, &g);
+  if (e != hipSuccess) FC_HIP(e);
+  FC_HIP(e2);
+  B.graph = g;
+  FC_HIP(hipGraphInstantiate(&B.exec, g, nullptr, nullptr, 0));
+  B.key_chunk = chunk;
   return FC_OK;
 }
 
@@ -756,31 +844,20 @@ extern "C" fc_status fc_pcg_solve_batch(fc_batch bt, const double* const* b_dev,
   const int np = (int)B.pull_items.size();
   // start: r = b, x = 0, z = S r, p = z, scalars
   hipLaunchKernelGGL(kb_vec<0>, dim3(np), dim3(256), 0, s, B.d_probs, B.d_pull, B.sc, B.r, B.p, B.z);
-  for (auto& c : B.schw) FC_HIP(launch_schwarz_class(B, c, nullptr, s));
+  for (auto& c : B.schw)
+    FC_HIP(launch_schwarz_class(B, c, c.d_items, (int)c.items.size(), nullptr, s));
   hipLaunchKernelGGL(kb_pull<0>, dim3(np), dim3(256), 0, s, B.d_probs, B.d_pull, np, B.sc, B.r,
                      B.p, B.q, B.z, B.partial);
-  hipLaunchKernelGGL(kb_beta<0>, dim3(B.nprob), dim3(256), 0, s, B.d_probs, B.sc, B.partial, np);
+  hipLaunchKernelGGL(kb_beta<0>, dim3(B.nprob), dim3(256), 0, s, B.d_probs, B.sc, B.partial, np,
+                     nullptr);
   hipLaunchKernelGGL(kb_vec<2>, dim3(np), dim3(256), 0, s, B.d_probs, B.d_pull, B.sc, B.r, B.p, B.z);
   FC_HIP(hipGetLastError());
   const int chunk = o.check_every > 0 ? o.check_every : 16;
-  if (!B.exec || B.key_chunk != chunk) {
-    if (B.exec) {
-      FC_HIP(hipGraphExecDestroy(B.exec));
-      B.exec = nullptr;
-    }
-    if (B.graph) {
-      FC_HIP(hipGraphDestroy(B.graph));
-      B.graph = nullptr;
-    }
-    FC_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-    hipError_t e = enqueue_batch_steps(B, chunk, s);
-    hipGraph_t g = nullptr;
-    hipError_t e2 = hipStreamEndCapture(s, &g);
-    if (e != hipSuccess) FC_HIP(e);
-    FC_HIP(e2);
-    B.graph = g;
-    FC_HIP(hipGraphInstantiate(&B.exec, g, nullptr, nullptr, 0));
-    B.key_chunk = chunk;
+  // every problem runs at the start; the lists shrink as problems stop
+  std::vector<char> running(B.nprob, 1);
+  if (B.act_dofs != B.total_dofs || !B.exec || B.key_chunk != chunk) {
+    FC_TRY_B(compact_lists(B, running));
+    FC_TRY_B(capture_steps(B, chunk, s));
   }
   const int64_t max_chunks = (o.maxit + chunk - 1) / chunk + 1;
   // FC_BATCH_PROGRESS=k: report the number of converged members on stderr
@@ -794,13 +871,25 @@ extern "C" fc_status fc_pcg_solve_batch(fc_batch bt, const double* const* b_dev,
     FC_HIP(hipMemcpyAsync(B.host_sc, B.sc, B.nprob * sizeof(CgScalars), hipMemcpyDeviceToHost, s));
     FC_HIP(hipStreamSynchronize(s));
     int ndone = 0;
-    for (int k = 0; k < B.nprob; ++k) ndone += B.host_sc[k].done != 0;
+    int64_t run_dofs = 0;
+    for (int k = 0; k < B.nprob; ++k) {
+      running[k] = B.host_sc[k].done == 0;
+      ndone += !running[k];
+      if (running[k]) run_dofs += B.host[k].n_dofs;
+    }
     if (prog && launched % prog == 0) {
       std::fprintf(stderr, "[batch] %lld iterations: %d of %d members stopped\n",
                    (long long)(launched * chunk), ndone, B.nprob);
       std::fflush(stderr);
     }
     if (ndone == B.nprob || launched > max_chunks) break;
+    // drop stopped problems from the launched lists once they hold 30 % of
+    // the unknowns (their tiles would only return at once, but each still
+    // costs a workgroup dispatch)
+    if (run_dofs < 0.7 * (double)B.act_dofs) {
+      FC_TRY_B(compact_lists(B, running));
+      FC_TRY_B(capture_steps(B, chunk, s));
+    }
   }
   FC_HIP(hipEventRecord(B.ev[2], s));
   FC_HIP(hipStreamSynchronize(s));
