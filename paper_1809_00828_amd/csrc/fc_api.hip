@@ -102,6 +102,7 @@ static fc_status upload_system(const HostSystem& S, hipStream_t stream, fc_probl
   pb->eta = S.eta;
   pb->elem_nodes_host = S.elem_nodes;
   FC_HIP(launch_diag(*pb, stream));
+  FC_HIP(spmv_autotune(pb->A, stream));
   FC_HIP(hipStreamSynchronize(stream));
   *out = pb.release();
   return FC_OK;

@@ -49,6 +49,7 @@ struct DeviceBsr {
   int64_t n_rows = 0;      // block rows
   int64_t nnzb = 0;
   int32_t max_row = 0;     // longest block row
+  int32_t group = 0;       // SpMV lanes per block row chosen at set-up (0: heuristic)
   int32_t* rowptr = nullptr;
   int32_t* col = nullptr;
   double* val = nullptr;   // row-SoA layout
@@ -104,6 +105,8 @@ hipError_t launch_spmv(const DeviceBsr& A, const double* x, double* y,
                        hipStream_t s);
 hipError_t launch_spmv_f32(const DeviceBsr& A, const double* x, double* y,
                            hipStream_t s);
+// time the SpMV group widths on A and keep the fastest in A.group
+hipError_t spmv_autotune(DeviceBsr& A, hipStream_t s);
 
 hipError_t launch_block_extract(const fc_problem_s& pb, const fc_precond_s& pc,
                                 hipStream_t s);

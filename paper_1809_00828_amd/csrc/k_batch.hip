@@ -65,60 +65,83 @@ __global__ __launch_bounds__(256) void kb_spmv(const BProb* __restrict__ probs,
                                                const WorkItem* __restrict__ items,
                                                const CgScalars* __restrict__ sc,
                                                const double* __restrict__ pvec,
-                                               double* __restrict__ qvec,
-                                               double* __restrict__ partial) {
+                                               double* __restrict__ qvec) {
   constexpr int BB = B * B;
   constexpr int RPW = 256 / G;
+  constexpr int U = B == 1 ? 4 : 2;   // blocks per lane per pass
+  const WorkItem it = items[blockIdx.x];
+  const BProb& P = probs[it.prob];
+  if (sc[it.prob].done) return;
+  const int64_t row = (int64_t)it.tile * RPW + threadIdx.x / G;
+  const int lane = threadIdx.x % G;
+  const double* x = pvec + P.voff;
+  if (row >= P.n_rows) return;
+  const int64_t base = P.rowptr[row];
+  const int L = P.rowptr[row + 1] - (int32_t)base;
+  const double* v = P.val + base * BB;
+  double acc[B];
+#pragma unroll
+  for (int i = 0; i < B; ++i) acc[i] = 0.0;
+  for (int k = lane; k < L; k += U * G) {
+    int c[U];
+    double a[U][BB];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int ku = k + u * G;
+      const bool on = ku < L;
+      c[u] = on ? __builtin_nontemporal_load(P.col + base + ku) : -1;
+#pragma unroll
+      for (int e = 0; e < BB; ++e)
+        a[u][e] = on ? __builtin_nontemporal_load(v + (int64_t)e * L + ku) : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+      for (int i = 0; i < B; ++i)
+#pragma unroll
+        for (int j = 0; j < B; ++j)
+          acc[i] = fma(a[u][i * B + j], c[u] >= 0 ? x[(int64_t)c[u] * B + j] : 0.0, acc[i]);
+  }
+#pragma unroll
+  for (int i = 0; i < B; ++i) acc[i] = group_sum<G>(acc[i]);
+  if (lane == 0) {
+#pragma unroll
+    for (int i = 0; i < B; ++i) qvec[P.voff + row * B + i] = acc[i];
+  }
+}
+
+// (p, q) per pull tile into partial[3 n_items + slot]: the step length's
+// dot runs as its own pass rather than at the end of every SpMV workgroup
+// (which would hold a workgroup's waves until the slowest row finishes).
+__global__ __launch_bounds__(256) void kb_pq(const BProb* __restrict__ probs,
+                                             const WorkItem* __restrict__ items, int n_items,
+                                             const CgScalars* __restrict__ sc,
+                                             const double* __restrict__ pvec,
+                                             const double* __restrict__ qvec,
+                                             double* __restrict__ partial) {
   __shared__ double lds[16];
   const WorkItem it = items[blockIdx.x];
   const BProb& P = probs[it.prob];
-  double dot = 0.0;
-  if (!sc[it.prob].done) {
-    const int64_t row = (int64_t)it.tile * RPW + threadIdx.x / G;
-    const int lane = threadIdx.x % G;
-    const double* x = pvec + P.voff;
-    if (row < P.n_rows) {
-      const int64_t base = P.rowptr[row];
-      const int L = P.rowptr[row + 1] - (int32_t)base;
-      const double* v = P.val + base * BB;
-      double acc[B];
-#pragma unroll
-      for (int i = 0; i < B; ++i) acc[i] = 0.0;
-      for (int k = lane; k < L; k += G) {
-        const int c = __builtin_nontemporal_load(P.col + base + k);
-#pragma unroll
-        for (int i = 0; i < B; ++i)
-#pragma unroll
-          for (int j = 0; j < B; ++j)
-            acc[i] = fma(__builtin_nontemporal_load(v + (int64_t)(i * B + j) * L + k),
-                         x[(int64_t)c * B + j], acc[i]);
-      }
-#pragma unroll
-      for (int i = 0; i < B; ++i) acc[i] = group_sum<G>(acc[i]);
-      if (lane == 0) {
-#pragma unroll
-        for (int i = 0; i < B; ++i) {
-          qvec[P.voff + row * B + i] = acc[i];
-          dot = fma(x[row * B + i], acc[i], dot);
-        }
-      }
-    }
-  }
-  dot = block_sum(dot, lds);
-  if (threadIdx.x == 0) partial[it.slot] = dot;
+  if (sc[it.prob].done) return;
+  const int64_t i = (int64_t)it.tile * 256 + threadIdx.x;
+  double a = 0.0;
+  if (i < P.n_dofs) a = pvec[P.voff + i] * qvec[P.voff + i];
+  a = block_sum(a, lds);
+  if (threadIdx.x == 0) partial[3 * (int64_t)n_items + it.slot] = a;
 }
 
-// alpha per problem from its SpMV partials (one workgroup per problem).
+// alpha per problem from its (p, q) partials (one workgroup per problem).
 __global__ __launch_bounds__(256) void kb_alpha(const BProb* __restrict__ probs, CgScalars* sc,
-                                                const double* __restrict__ partial,
+                                                const double* __restrict__ partial, int n_items,
                                                 const int32_t* __restrict__ active) {
   __shared__ double lds[16];
   const int k = active ? active[blockIdx.x] : (int)blockIdx.x;
   CgScalars& S = sc[k];
   if (S.done) return;
   const BProb& P = probs[k];
+  const double* pp = partial + 3 * (int64_t)n_items + P.pull_item0;
   double t = 0.0;
-  for (int i = threadIdx.x; i < P.spmv_items; i += blockDim.x) t += partial[P.spmv_item0 + i];
+  for (int i = threadIdx.x; i < P.pull_items; i += blockDim.x) t += pp[i];
   const double pq = block_sum(t, lds);
   if (threadIdx.x == 0) {
     S.pq = pq;
@@ -412,12 +435,12 @@ static void destroy_batch(fc_batch_s* b) {
 
 template <int B>
 static void launch_bspmv_G(int G, dim3 g, hipStream_t s, const BProb* probs, const WorkItem* it,
-                           const CgScalars* sc, const double* p, double* q, double* part) {
+                           const CgScalars* sc, const double* p, double* q) {
   switch (G) {
-    case 8: hipLaunchKernelGGL((kb_spmv<B, 8>), g, dim3(256), 0, s, probs, it, sc, p, q, part); break;
-    case 16: hipLaunchKernelGGL((kb_spmv<B, 16>), g, dim3(256), 0, s, probs, it, sc, p, q, part); break;
-    case 32: hipLaunchKernelGGL((kb_spmv<B, 32>), g, dim3(256), 0, s, probs, it, sc, p, q, part); break;
-    default: hipLaunchKernelGGL((kb_spmv<B, 64>), g, dim3(256), 0, s, probs, it, sc, p, q, part); break;
+    case 8: hipLaunchKernelGGL((kb_spmv<B, 8>), g, dim3(256), 0, s, probs, it, sc, p, q); break;
+    case 16: hipLaunchKernelGGL((kb_spmv<B, 16>), g, dim3(256), 0, s, probs, it, sc, p, q); break;
+    case 32: hipLaunchKernelGGL((kb_spmv<B, 32>), g, dim3(256), 0, s, probs, it, sc, p, q); break;
+    default: hipLaunchKernelGGL((kb_spmv<B, 64>), g, dim3(256), 0, s, probs, it, sc, p, q); break;
   }
 }
 
@@ -426,9 +449,9 @@ static hipError_t launch_spmv_class(fc_batch_s& bt, const SpmvClass& c, const Wo
   if (n == 0) return hipSuccess;
   dim3 g((unsigned)n);
   switch (c.B) {
-    case 1: launch_bspmv_G<1>(c.G, g, s, bt.d_probs, items, bt.sc, bt.p, bt.q, bt.partial); break;
-    case 2: launch_bspmv_G<2>(c.G, g, s, bt.d_probs, items, bt.sc, bt.p, bt.q, bt.partial); break;
-    case 3: launch_bspmv_G<3>(c.G, g, s, bt.d_probs, items, bt.sc, bt.p, bt.q, bt.partial); break;
+    case 1: launch_bspmv_G<1>(c.G, g, s, bt.d_probs, items, bt.sc, bt.p, bt.q); break;
+    case 2: launch_bspmv_G<2>(c.G, g, s, bt.d_probs, items, bt.sc, bt.p, bt.q); break;
+    case 3: launch_bspmv_G<3>(c.G, g, s, bt.d_probs, items, bt.sc, bt.p, bt.q); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -463,8 +486,12 @@ static hipError_t enqueue_batch_steps(fc_batch_s& bt, int chunk, hipStream_t s) 
       hipError_t e = launch_spmv_class(bt, c, c.d_act, c.n_act, s);
       if (e != hipSuccess) return e;
     }
+    if (na > 0) {
+      hipLaunchKernelGGL(kb_pq, dim3(na), dim3(256), 0, s, bt.d_probs, bt.d_act_pull, np, bt.sc,
+                         bt.p, bt.q, bt.partial);
+    }
     hipLaunchKernelGGL(kb_alpha, dim3(bt.n_act_probs), dim3(256), 0, s, bt.d_probs, bt.sc,
-                       bt.partial, bt.d_act_probs);
+                       bt.partial, np, bt.d_act_probs);
     for (auto& c : bt.schw) {
       hipError_t e = launch_schwarz_class(bt, c, c.d_act, c.n_act, bt.q, s);
       if (e != hipSuccess) return e;
@@ -653,7 +680,7 @@ extern "C" fc_status fc_batch_create(int32_t nprob, const fc_problem* problems,
   // minimum) and 3 per pull item
   int64_t max_spmv = 0;
   for (int k = 0; k < nprob; ++k) max_spmv += (B.host[k].n_rows + 3) / 4 + 1;
-  const int64_t plen = std::max<int64_t>(max_spmv, 3 * (int64_t)B.pull_items.size()) + 8;
+  const int64_t plen = std::max<int64_t>(max_spmv, 4 * (int64_t)B.pull_items.size()) + 8;
   FC_HIP(hipMalloc(&B.partial, plen * sizeof(double)));
   FC_HIP(hipMalloc(&B.sc, nprob * sizeof(CgScalars)));
   FC_HIP(hipMemset(B.sc, 0, nprob * sizeof(CgScalars)));

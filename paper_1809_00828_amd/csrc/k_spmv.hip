@@ -54,36 +54,38 @@ __global__ __launch_bounds__(256) void k_spmv_bsr(
       acc[i] = 0.0;
       accf[i] = 0.0f;
     }
-    // two blocks per lane per pass: twice the loads in flight
-    for (int k = lane; k < L; k += 2 * G) {
-      const int k2 = k + G;
-      const bool two = k2 < L;
-      const int c = __builtin_nontemporal_load(col + base + k);
-      const int c2 = two ? __builtin_nontemporal_load(col + base + k2) : c;
-      T a1[BB], a2[BB];
+    // U blocks per lane per pass: all loads of a pass are in flight
+    // together (scalar rows are short, so four; 3x3 blocks carry nine
+    // values each, so two)
+    constexpr int U = B == 1 ? 4 : 2;
+    for (int k = lane; k < L; k += U * G) {
+      int c[U];
+      T a[U][BB];
 #pragma unroll
-      for (int e = 0; e < BB; ++e) {
-        a1[e] = __builtin_nontemporal_load(v + (int64_t)e * L + k);
-        a2[e] = two ? __builtin_nontemporal_load(v + (int64_t)e * L + k2) : T(0);
+      for (int u = 0; u < U; ++u) {
+        const int ku = k + u * G;
+        const bool on = ku < L;
+        c[u] = on ? __builtin_nontemporal_load(col + base + ku) : -1;
+#pragma unroll
+        for (int e = 0; e < BB; ++e)
+          a[u][e] = on ? __builtin_nontemporal_load(v + (int64_t)e * L + ku) : T(0);
       }
-      double xv[B], xv2[B];
+      double xv[U][B];
 #pragma unroll
-      for (int jj = 0; jj < B; ++jj) {
-        xv[jj] = x[(int64_t)c * B + jj];
-        xv2[jj] = x[(int64_t)c2 * B + jj];
-      }
+      for (int u = 0; u < U; ++u)
 #pragma unroll
-      for (int i = 0; i < B; ++i)
+        for (int jj = 0; jj < B; ++jj) xv[u][jj] = c[u] >= 0 ? x[(int64_t)c[u] * B + jj] : 0.0;
 #pragma unroll
-        for (int jj = 0; jj < B; ++jj) {
-          if constexpr (sizeof(T) == 8) {
-            acc[i] = fma((double)a1[i * B + jj], xv[jj], acc[i]);
-            acc[i] = fma((double)a2[i * B + jj], xv2[jj], acc[i]);
-          } else {
-            accf[i] = fmaf((float)a1[i * B + jj], (float)xv[jj], accf[i]);
-            accf[i] = fmaf((float)a2[i * B + jj], (float)xv2[jj], accf[i]);
+      for (int u = 0; u < U; ++u)
+#pragma unroll
+        for (int i = 0; i < B; ++i)
+#pragma unroll
+          for (int jj = 0; jj < B; ++jj) {
+            if constexpr (sizeof(T) == 8)
+              acc[i] = fma((double)a[u][i * B + jj], xv[u][jj], acc[i]);
+            else
+              accf[i] = fmaf((float)a[u][i * B + jj], (float)xv[u][jj], accf[i]);
           }
-        }
     }
 #pragma unroll
     for (int i = 0; i < B; ++i) {
@@ -105,8 +107,9 @@ __global__ __launch_bounds__(256) void k_spmv_bsr(
   if (threadIdx.x == 0) partial[blockIdx.x] = dot;
 }
 
-// Launch shape.  Group width from the mean row length (FC_SPMV_GROUP
-// overrides it); the PCG variant uses one tile per workgroup unless
+// Launch shape.  Group width chosen per matrix by spmv_autotune at set-up,
+// else from the mean row length (FC_SPMV_GROUP overrides both); the PCG
+// variant uses one tile per workgroup unless
 // FC_SPMV_FUSED_GRID caps the grid (then workgroups loop over tiles).
 static int env_int(const char* name, int dflt) {
   const char* e = std::getenv(name);
@@ -116,6 +119,7 @@ static int env_int(const char* name, int dflt) {
 static int group_width(const DeviceBsr& A) {
   static const int forced = env_int("FC_SPMV_GROUP", 0);
   if (forced == 8 || forced == 16 || forced == 32 || forced == 64) return forced;
+  if (A.group) return A.group;
   const double mean = A.n_rows ? double(A.nnzb) / double(A.n_rows) : 1.0;
   if (mean < 12) return 8;
   if (mean < 24) return 16;
@@ -178,6 +182,44 @@ hipError_t launch_spmv_f32(const DeviceBsr& A, const double* x, double* y, hipSt
 }
 
 int spmv_num_blocks(const DeviceBsr& A) { return (int)fused_grid(A); }
+
+// Group width of this matrix: time every width on the matrix itself
+// (x = 0, so only the memory traffic counts) and keep the fastest.
+hipError_t spmv_autotune(DeviceBsr& A, hipStream_t s) {
+  A.group = 0;
+  const int64_t n = A.n_rows * A.bdim;
+  if (n == 0) return hipSuccess;
+  double *x = nullptr, *y = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  hipError_t err = hipMalloc(&x, n * sizeof(double));
+  if (err == hipSuccess) err = hipMalloc(&y, n * sizeof(double));
+  if (err == hipSuccess) err = hipMemsetAsync(x, 0, n * sizeof(double), s);
+  if (err == hipSuccess) err = hipEventCreate(&e0);
+  if (err == hipSuccess) err = hipEventCreate(&e1);
+  float best = 1e30f;
+  int best_g = 0;
+  for (int G : {8, 16, 32, 64}) {
+    if (err != hipSuccess) break;
+    A.group = G;
+    err = launch_spmv(A, x, y, s);
+    if (err == hipSuccess) err = hipEventRecord(e0, s);
+    for (int r = 0; r < 3 && err == hipSuccess; ++r) err = launch_spmv(A, x, y, s);
+    if (err == hipSuccess) err = hipEventRecord(e1, s);
+    if (err == hipSuccess) err = hipEventSynchronize(e1);
+    float ms = 0.f;
+    if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
+    if (err == hipSuccess && ms < best) {
+      best = ms;
+      best_g = G;
+    }
+  }
+  A.group = err == hipSuccess ? best_g : 0;
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  if (x) (void)hipFree(x);
+  if (y) (void)hipFree(y);
+  return err;
+}
 
 hipError_t launch_spmv_pq(const DeviceBsr& A, bool f32, const double* p, double* q,
                           CgScalars* sc, double* partial, hipStream_t s) {
