@@ -216,10 +216,11 @@ fc_status fc_apply_M(fc_precond pc, const double* r_dev, double* z_dev,
  *   check_every  iterations between host checks of the device stop flag
  *   history_dev  optional device buffer of maxit+1 doubles receiving the
  *                relative stop criterion of every iteration, or NULL
- *   timing       nonzero: launch the iteration without a captured graph and
- *                bracket every SpMV and Schwarz block-product kernel with
- *                events on the solver stream (fc_solve_info.ms_spmv,
- *                ms_schwarz); costs a few microseconds per iteration */
+ *   timing       k > 0: launch the steps directly (no captured graph) and
+ *                bracket the SpMV and Schwarz block-product kernels of every
+ *                k-th step with events on the solver stream;
+ *                fc_solve_info.ms_spmv / ms_schwarz receive their summed
+ *                times over the n_timed bracketed steps */
 enum { FC_STOP_PRECOND = 0, FC_STOP_RESIDUAL = 1 };
 enum { FC_MODE_F64 = 0, FC_MODE_IR_F32 = 1, FC_MODE_IR_BF16 = 2, FC_MODE_S_F32 = 3,
        FC_MODE_S_BF16 = 4, FC_MODE_LEARNED = 5 };

@@ -417,7 +417,7 @@ def pcg_solve(problem: Problem, precond: Precond, b, x, tol=1e-10, maxit=300000,
     """Run fc_pcg_solve; returns the info dict (status included)."""
     o = SolveOpts(float(tol), int(maxit), STOP[stop], MODE[mode], int(check_every),
                   float(inner_tol), C.c_void_p(_dptr(history)) if history is not None else None,
-                  1 if timing else 0)
+                  int(timing))
     info = SolveInfo()
     st = load().fc_pcg_solve(problem._h, precond._h, C.c_void_p(_dptr(b)), C.c_void_p(_dptr(x)),
                              C.byref(o), C.byref(info), C.c_void_p(_stream(stream)))

@@ -4,12 +4,13 @@
 // Recurrences (x_0 = 0):  r_0 = b, z_0 = S r_0, p_0 = z_0, then per step
 //   q = A p;  alpha = (r,z)/(p,q);  x += alpha p;  r -= alpha q;
 //   z = S r;  beta = (r,z)_new/(r,z);  p = z + beta p.
-// One step is six kernels, all reading their scalars from device memory:
+// One step is seven kernels, all reading their scalars from device memory:
 //   1. SpMV q = A p (k_spmv.hip)
-//   2. (p, q) by workgroup partials, summed in a fixed order by the last
-//      workgroup: alpha, step count.  Fusing the dot into the SpMV costs
-//      more than this extra pass over p and q: the SpMV's end-of-workgroup
-//      reduction holds its four waves until the slowest one finishes.
+//   2. (p, q) by workgroup partials in a separate pass over p and q, then
+//      one workgroup sums them in a fixed order: alpha, step count.
+//      Fusing the dot into the SpMV costs more than this extra pass: the
+//      SpMV's end-of-workgroup reduction holds its four waves until the
+//      slowest one finishes.
 //   3. Schwarz phase 1 on the gathered r - alpha q (k_schwarz.hip)
 //   4. pull z = sum_B R_B^T y_B + fallback, fused with the x and r updates
 //      and per-workgroup (r,z), (z,z), (r,r) partials
@@ -146,15 +147,14 @@ __global__ __launch_bounds__(1024) void k_cg_alpha(const double* __restrict__ pa
   }
 }
 
-// Step length from a separate (p, q) reduction: per-workgroup partials,
-// the last workgroup sums them in a fixed order and sets alpha (used when
-// the SpMV runs without its fused dot).
-__global__ __launch_bounds__(256) void k_cg_pq_alpha(const double* __restrict__ p,
-                                                     const double* __restrict__ q, int64_t n,
-                                                     double* __restrict__ partial,
-                                                     CgScalars* sc) {
+// (p, q) partials of a separate pass over p and q, one per workgroup; the
+// one-workgroup k_cg_alpha sums them in a fixed order.  (A last-workgroup
+// ticket here would serialise thousands of same-address atomics in L2.)
+__global__ __launch_bounds__(256) void k_cg_pq(const double* __restrict__ p,
+                                               const double* __restrict__ q, int64_t n,
+                                               double* __restrict__ partial,
+                                               const CgScalars* __restrict__ sc) {
   __shared__ double lds[16];
-  __shared__ int flag;
   if (sc->done) return;
   double a = 0.0;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
@@ -162,18 +162,6 @@ __global__ __launch_bounds__(256) void k_cg_pq_alpha(const double* __restrict__ 
     a = fma(p[i], q[i], a);
   a = block_sum(a, lds);
   if (threadIdx.x == 0) partial[blockIdx.x] = a;
-  if (!last_block(&sc->ticket, gridDim.x, &flag)) return;
-  const double pq = sum_partials(partial, gridDim.x, lds);
-  if (threadIdx.x == 0) {
-    sc->pq = pq;
-    sc->iter += 1;
-    const double rz = sc->rz;
-    if (!(pq > 0.0) || !(rz > 0.0)) {
-      sc->done = (pq != pq || rz != rz) ? 4 : 3;
-    } else {
-      sc->alpha = rz / pq;
-    }
-  }
 }
 
 // Pull of the Schwarz apply fused with x += alpha p, r -= alpha q and the
@@ -364,6 +352,9 @@ static inline unsigned nblk(int64_t n) { return (unsigned)((n + kVecThreads - 1)
 static constexpr unsigned kRedBlocks = 1024;
 // grid of the fused pull: enough workgroups to fill the chip, few partials
 static inline unsigned pull_grid(int64_t n) { return std::min<unsigned>(nblk(n), 2048u); }
+// grid of a two-vector dot: a few elements per lane keep enough loads in
+// flight (1024 workgroups left ten dependent iterations per lane at 2.7M)
+static inline unsigned dot_grid(int64_t n) { return std::min<unsigned>(nblk(n), 4096u); }
 
 // ----------------------------------------------------------- host side
 static fc_status ensure_ws(fc_precond_s& pc, SolverWs** out) {
@@ -408,30 +399,33 @@ static bool split_dot() {
 // local inverses.
 static hipError_t enqueue_steps(fc_precond_s& pc, SolverWs& w, double* x, int chunk, int precA,
                                 int precS, hipStream_t s, hipEvent_t* tev = nullptr,
-                                CoarseCtx* learn = nullptr) {
+                                CoarseCtx* learn = nullptr, int every = 1) {
   fc_problem_s& pb = *pc.pb;
   const int64_t n = pb.n_dofs;
   for (int it = 0; it < chunk; ++it) {
     hipError_t e;
-    if (tev && (e = hipEventRecord(tev[4 * it + 0], s)) != hipSuccess) return e;
+    hipEvent_t* tev_it = (tev && it % every == 0) ? tev : nullptr;
+    if (tev_it && (e = hipEventRecord(tev[4 * it + 0], s)) != hipSuccess) return e;
     if (split_dot()) {
       // SpMV without its fused dot, then (p, q) and alpha in one reduction
       e = launch_spmv_pq(pb.A, precA == 1, w.p, w.q, w.sc, nullptr, s);
       if (e != hipSuccess) return e;
-      if (tev && (e = hipEventRecord(tev[4 * it + 1], s)) != hipSuccess) return e;
-      hipLaunchKernelGGL(k_cg_pq_alpha, dim3(kRedBlocks), dim3(256), 0, s, w.p, w.q, n,
-                         w.partial, w.sc);
+      if (tev_it && (e = hipEventRecord(tev[4 * it + 1], s)) != hipSuccess) return e;
+      hipLaunchKernelGGL(k_cg_pq, dim3(dot_grid(n)), dim3(256), 0, s, w.p, w.q, n, w.partial,
+                         w.sc);
+      hipLaunchKernelGGL(k_cg_alpha, dim3(1), dim3(1024), 0, s, w.partial, (int)dot_grid(n),
+                         w.sc);
     } else {
       e = launch_spmv_pq(pb.A, precA == 1, w.p, w.q, w.sc, w.partial, s);
       if (e != hipSuccess) return e;
-      if (tev && (e = hipEventRecord(tev[4 * it + 1], s)) != hipSuccess) return e;
+      if (tev_it && (e = hipEventRecord(tev[4 * it + 1], s)) != hipSuccess) return e;
       hipLaunchKernelGGL(k_cg_alpha, dim3(1), dim3(1024), 0, s, w.partial,
                          spmv_num_blocks(pb.A), w.sc);
     }
-    if (tev && (e = hipEventRecord(tev[4 * it + 2], s)) != hipSuccess) return e;
+    if (tev_it && (e = hipEventRecord(tev[4 * it + 2], s)) != hipSuccess) return e;
     e = launch_schwarz_phase1(pc, precS, w.r, w.q, w.sc, s);
     if (e != hipSuccess) return e;
-    if (tev && (e = hipEventRecord(tev[4 * it + 3], s)) != hipSuccess) return e;
+    if (tev_it && (e = hipEventRecord(tev[4 * it + 3], s)) != hipSuccess) return e;
     const unsigned pg = pull_grid(n);
     if (learn) {
       hipLaunchKernelGGL(k_cg_pull<true>, dim3(pg), dim3(kVecThreads), 0, s, pc.y, pc.inv_ptr,
@@ -471,10 +465,20 @@ struct CoreResult {
   int64_t n_timed = 0;
 };
 
+// Events bracketing the SpMV and the block products of the steps of a
+// chunk (timing mode).
+static fc_status ensure_events(SolverWs& w, int chunk) {
+  if ((int)w.tev.size() >= 4 * chunk) return FC_OK;
+  const size_t old = w.tev.size();
+  w.tev.resize(4 * chunk, nullptr);
+  for (size_t i = old; i < w.tev.size(); ++i) FC_HIP(hipEventCreate(&w.tev[i]));
+  return FC_OK;
+}
+
 // (Re)capture the chunk of steps into a graph when the buffers, precisions
-// or length change.  Capturing is host work: callers that time the solve
-// on the device call this before their first event so the timed region
-// does not include it.
+// or length change.
+// Capturing is host work: callers that time the solve on the device call
+// this before their first event so the timed region does not include it.
 static fc_status ensure_graph(fc_precond_s& pc, SolverWs& w, const CoreArgs& a, hipStream_t s) {
   const int chunk = a.chunk > 0 ? a.chunk : 16;
   const int prec = a.precA * 4 + a.precS + (a.learn ? 16 : 0);
@@ -487,12 +491,16 @@ static fc_status ensure_graph(fc_precond_s& pc, SolverWs& w, const CoreArgs& a, 
     FC_HIP(hipGraphDestroy(w.graph));
     w.graph = nullptr;
   }
+  w.key_prec = -1;
   FC_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
   hipError_t e = enqueue_steps(pc, w, a.x, chunk, a.precA, a.precS, s, nullptr, a.learn);
   hipGraph_t g = nullptr;
   hipError_t e2 = hipStreamEndCapture(s, &g);
-  if (e != hipSuccess) FC_HIP(e);
-  FC_HIP(e2);
+  if (e != hipSuccess || e2 != hipSuccess) {
+    if (g) (void)hipGraphDestroy(g);
+    (void)hipGetLastError();
+    FC_HIP(e != hipSuccess ? e : e2);
+  }
   w.graph = g;
   FC_HIP(hipGraphInstantiate(&w.exec, g, nullptr, nullptr, 0));
   w.key[0] = a.x;
@@ -527,27 +535,27 @@ static fc_status pcg_core(fc_precond_s& pc, SolverWs& w, const CoreArgs& a, Core
   const int64_t max_chunks = (a.maxit + chunk - 1) / chunk + 1;
   int64_t launched = 0;
   if (a.timing) {
-    if ((int)w.tev.size() < 4 * chunk) {
-      size_t old = w.tev.size();
-      w.tev.resize(4 * chunk, nullptr);
-      for (size_t i = old; i < w.tev.size(); ++i) FC_HIP(hipEventCreate(&w.tev[i]));
-    }
+    // direct launches (events recorded by a captured graph carry no
+    // timestamps here); every a.timing-th step is bracketed by events
+    FC_TRY_ST(ensure_events(w, chunk));
+    const int every = std::max(1, a.timing);
     int64_t iter_before = 0;
     for (;;) {
-      FC_HIP(enqueue_steps(pc, w, a.x, chunk, a.precA, a.precS, s, w.tev.data(), a.learn));
+      FC_HIP(enqueue_steps(pc, w, a.x, chunk, a.precA, a.precS, s, w.tev.data(), a.learn, every));
       ++launched;
       FC_HIP(hipMemcpyAsync(w.host, w.sc, sizeof(CgScalars), hipMemcpyDeviceToHost, s));
       FC_HIP(hipStreamSynchronize(s));
       const int64_t ran = std::min<int64_t>(chunk, w.host->iter - iter_before);
       iter_before = w.host->iter;
       for (int64_t it = 0; it < ran; ++it) {
+        if (it % every) continue;
         float t0 = 0.f, t1 = 0.f;
         FC_HIP(hipEventElapsedTime(&t0, w.tev[4 * it + 0], w.tev[4 * it + 1]));
         FC_HIP(hipEventElapsedTime(&t1, w.tev[4 * it + 2], w.tev[4 * it + 3]));
         res->t_spmv += t0;
         res->t_schw += t1;
+        res->n_timed += 1;
       }
-      res->n_timed += ran;
       if (w.host->done != 0 || launched > max_chunks) break;
     }
   } else {
