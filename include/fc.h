@@ -156,7 +156,11 @@ fc_status fc_apply_A(fc_problem pb, const double* x_dev, double* y_dev,
  *   eps        pseudo-inverse threshold: eigenvalues <= eps*max are dropped
  *   stabilize  1 = pseudo-inverse of Eqs. 10-11, 0 = plain inverse (S*)
  *   store_mask FC_STORE_* bits: extra low-precision copies of the block
- *              inverses (FP64 is always kept) */
+ *              inverses (FP64 is always kept): FC_STORE_F32 the rounded
+ *              scaled inverse with an FP64 list for blocks it would leave
+ *              indefinite (fc_precond_lowprec_info), FC_STORE_BF16 the
+ *              scaled Cholesky factor (positive semi-definite however
+ *              rounded) */
 enum { FC_STORE_F64 = 1, FC_STORE_F32 = 2, FC_STORE_BF16 = 4 };
 typedef struct {
   double eta_bar;
@@ -180,6 +184,13 @@ fc_status fc_precond_build(fc_problem pb, const fc_precond_opts* opts,
 fc_status fc_precond_info(fc_precond pc, int64_t* n_blocks,
                           int64_t* n_fallback, int64_t* n_eig_blocks,
                           int64_t* n_dropped);
+/* FP32 copy (FC_STORE_F32): the diagonally scaled inverse D^1/2 P_B D^1/2
+ * (D = diag(A) on the block) rounded to FP32, kept for the blocks where a
+ * Cholesky factorisation of the rounded matrix shows it positive definite
+ * (no pivot below 1e-10 of the largest diagonal entry); the other blocks
+ * are applied from the FP64 copy.  Counts of both kinds. */
+fc_status fc_precond_lowprec_info(fc_precond pc, int64_t* n_f32_blocks,
+                                  int64_t* n_f32_from_f64);
 
 /* Copy the FP64 local inverse of block k (m*m values, row-major) to host. */
 fc_status fc_get_block_inverse(fc_precond pc, int64_t k, double* out_host);
@@ -197,9 +208,11 @@ fc_status fc_apply_M(fc_precond pc, const double* r_dev, double* z_dev,
  *   mode         FC_MODE_F64 plain FP64 PCG;
  *                FC_MODE_IR_F32 / FC_MODE_IR_BF16: iterative refinement --
  *                the FP64 residual b - A x is recomputed outside, and each
- *                correction comes from a PCG run with the FP32 copy of A and
- *                the FP32 / BF16 factored copy of the local inverses (built
- *                with FC_STORE_F32 / FC_STORE_BF16), FP32 accumulation, FP64
+ *                correction comes from a PCG run with an FP32 copy of A
+ *                (the diagonally scaled D^{-1/2} A D^{-1/2} rounded to FP32,
+ *                applied as D^{1/2} (.) D^{1/2}) and the FP32 / BF16 copy
+ *                of the local inverses (built with FC_STORE_F32 /
+ *                FC_STORE_BF16), FP32 accumulation, FP64
  *                vectors and scalars, stopped at inner_tol (relative to
  *                its right-hand side) or at breakdown.  A correction that
  *                does not reduce the FP64 residual by 10 % is undone and the
@@ -207,7 +220,7 @@ fc_status fc_apply_M(fc_precond pc, const double* r_dev, double* z_dev,
  *                fc_solve_info.fallbacks).  tol then applies to
  *                ||b - A x|| / ||b|| whatever `stop` says;
  *                FC_MODE_S_F32 / FC_MODE_S_BF16: one PCG run with the FP64
- *                matrix and the FP32 / BF16 factored local inverses as the
+ *                matrix and the FP32 / BF16 copy of the local inverses as the
  *                preconditioner (positive semi-definite however rounded);
  *                FC_MODE_LEARNED: flexible CG (beta = -(z_new, A p)/(p, A p))
  *                with z = S r + gamma P_c y, y the network attached with

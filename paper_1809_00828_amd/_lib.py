@@ -37,7 +37,7 @@ EXPORTS = [
     "fc_model_forward", "fc_model_loss_grad", "fc_model_train", "fc_model_destroy",
     "fc_learned_attach", "fc_coarse_grid", "fc_coarse_channels", "fc_coarse_restrict",
     "fc_coarse_prolong", "fc_coarse_apply", "fc_learned_stats", "fc_learned_snapshots",
-    "fc_learned_validate",
+    "fc_learned_validate", "fc_precond_lowprec_info",
 ]
 
 
@@ -108,6 +108,7 @@ def load():
         "fc_apply_A": [vp, dp, dp, vp],
         "fc_precond_build": [vp, P(PrecondOpts), vp, P(vp)],
         "fc_precond_info": [vp, P(i64), P(i64), P(i64), P(i64)],
+        "fc_precond_lowprec_info": [vp, P(i64), P(i64)],
         "fc_get_block_inverse": [vp, i64, vp],
         "fc_apply_M": [vp, dp, dp, vp],
         "fc_pcg_solve": [vp, vp, dp, dp, P(SolveOpts), P(SolveInfo), vp],
@@ -336,8 +337,10 @@ class Precond:
     def info(self):
         a, b, c, d = C.c_int64(), C.c_int64(), C.c_int64(), C.c_int64()
         _check(load().fc_precond_info(self._h, C.byref(a), C.byref(b), C.byref(c), C.byref(d)))
+        e, f = C.c_int64(), C.c_int64()
+        _check(load().fc_precond_lowprec_info(self._h, C.byref(e), C.byref(f)))
         return {"n_blocks": a.value, "n_fallback": b.value, "n_eig_blocks": c.value,
-                "n_dropped": d.value}
+                "n_dropped": d.value, "n_f32_blocks": e.value, "n_f32_from_f64": f.value}
 
     def block_inverse(self, k):
         out = np.zeros((self.m, self.m), np.float64)

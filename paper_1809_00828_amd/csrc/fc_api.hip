@@ -58,7 +58,7 @@ static fc_status upload(T** p, const T* src, size_t count) {
 static void free_problem(fc_problem_s* pb) {
   if (!pb) return;
   for (void* p : {(void*)pb->A.rowptr, (void*)pb->A.col, (void*)pb->A.val, (void*)pb->A.val32,
-                  (void*)pb->rhs, (void*)pb->elem_nodes, (void*)pb->diag})
+                  (void*)pb->rhs, (void*)pb->elem_nodes, (void*)pb->diag, (void*)pb->sqd})
     if (p) (void)hipFree(p);
   delete pb;
 }
@@ -67,7 +67,8 @@ static void free_precond(fc_precond_s* pc) {
   if (!pc) return;
   solver_ws_destroy(pc->ws);
   coarse_destroy(pc->coarse);
-  for (void* p : {(void*)pc->block_elem, (void*)pc->P, (void*)pc->Q, (void*)pc->L32, (void*)pc->Lbf, (void*)pc->isd,
+  for (void* p : {(void*)pc->block_elem, (void*)pc->P, (void*)pc->Q, (void*)pc->Q32,
+                  (void*)pc->unsafe32, (void*)pc->unsafe_flag32, (void*)pc->L32, (void*)pc->Lbf, (void*)pc->isd,
                   (void*)pc->inv_ptr, (void*)pc->inv_idx, (void*)pc->fallback, (void*)pc->y})
     if (p) (void)hipFree(p);
   delete pc;
@@ -460,11 +461,30 @@ fc_status fc_precond_build(fc_problem pb, const fc_precond_opts* opts, void* str
     FC_TRY(dev_alloc(&pc->isd, (size_t)pb->n_dofs));
     FC_HIP(launch_inv_sqrt_diag(*pb, pc->isd, s));
   }
-  // positive semi-definite low-precision copies: scaled Cholesky factors
+  // FP32: the rounded, diagonally scaled inverse D^1/2 P_B D^1/2 in
+  // wrapped-diagonal storage; scaling removes most of a cut block's ill
+  // conditioning, so the rounding keeps it positive definite.  Blocks where
+  // a Cholesky factorisation of the rounded matrix shows otherwise are
+  // listed and applied from the FP64 copy.
+  if (o.store_mask & FC_STORE_F32) {
+    FC_TRY(dev_alloc(&pc->Q32, qn));
+    FC_HIP(launch_pack_sym(*pc, pc->Q32, 1, s));
+    FC_TRY(dev_alloc(&pc->unsafe_flag32, (size_t)std::max<int64_t>(nb, 1)));
+    FC_HIP(launch_chol_pack(*pc, s, pc->unsafe_flag32));
+    std::vector<int32_t> hf(std::max<int64_t>(nb, 1), 0);
+    FC_HIP(hipMemcpyAsync(hf.data(), pc->unsafe_flag32, nb * sizeof(int32_t),
+                          hipMemcpyDeviceToHost, s));
+    FC_HIP(hipStreamSynchronize(s));
+    std::vector<int32_t> list;
+    for (int64_t k = 0; k < nb; ++k)
+      if (hf[k]) list.push_back((int32_t)k);
+    pc->n_unsafe32 = (int64_t)list.size();
+    if (!list.empty()) FC_TRY(upload(&pc->unsafe32, list.data(), list.size()));
+  }
+  // BF16: scaled Cholesky factors (positive semi-definite however rounded)
   const size_t ln = (size_t)nb * ((size_t)m * (m + 1) / 2);
-  if (o.store_mask & FC_STORE_F32) FC_TRY(dev_alloc(&pc->L32, ln));
   if (o.store_mask & FC_STORE_BF16) FC_TRY(dev_alloc(&pc->Lbf, ln));
-  if (pc->L32 || pc->Lbf) FC_HIP(launch_chol_pack(*pc, s));
+  if (pc->Lbf) FC_HIP(launch_chol_pack(*pc, s));
   unsigned long long cnt = 0;
   std::vector<int32_t> drop(std::max<int64_t>(nb, 1));
   FC_HIP(hipMemcpyAsync(&cnt, d_count, sizeof(cnt), hipMemcpyDeviceToHost, s));
@@ -475,6 +495,14 @@ fc_status fc_precond_build(fc_problem pb, const fc_precond_opts* opts, void* str
   for (int64_t k = 0; k < nb; ++k) nd += drop[k];
   pc->n_dropped = nd;
   *out = pc.release();
+  return FC_OK;
+}
+
+fc_status fc_precond_lowprec_info(fc_precond pc, int64_t* n_f32_blocks,
+                                  int64_t* n_f32_from_f64) {
+  if (!pc) return FC_E_ARG;
+  if (n_f32_blocks) *n_f32_blocks = pc->Q32 ? pc->n_blocks - pc->n_unsafe32 : 0;
+  if (n_f32_from_f64) *n_f32_from_f64 = pc->Q32 ? pc->n_unsafe32 : 0;
   return FC_OK;
 }
 

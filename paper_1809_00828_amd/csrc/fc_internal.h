@@ -74,6 +74,7 @@ struct fc_problem_s {
   std::vector<double> eta;         // host copy [n_el]
   std::vector<int32_t> elem_nodes_host;
   double* diag = nullptr;          // A_ll [n_dofs]
+  double* sqd = nullptr;           // sqrt(A_ll), with the scaled FP32 matrix
 };
 
 struct fc_precond_s {
@@ -83,6 +84,10 @@ struct fc_precond_s {
   int32_t* block_elem = nullptr;   // [n_blocks] element of each block
   double* P = nullptr;             // [n_blocks*m*m] FP64 local inverses (dense)
   double* Q = nullptr;             // wrapped-diagonal symmetric copy, FP64
+  float* Q32 = nullptr;            // optional FP32 wrapped-diagonal copy of D^1/2 P D^1/2
+  int32_t* unsafe32 = nullptr;     // blocks whose FP32 copy is not safely positive
+  int32_t* unsafe_flag32 = nullptr; // the same as one flag per block
+  int64_t n_unsafe32 = 0;          //   (applied from the FP64 copy instead)
   float* L32 = nullptr;            // optional FP32 scaled Cholesky factors
   uint16_t* Lbf = nullptr;         // optional BF16 scaled Cholesky factors
   double* isd = nullptr;           // [n_dofs] 1/sqrt(A_ll), scaling of L32/Lbf
@@ -104,7 +109,7 @@ namespace fc {
 hipError_t launch_spmv(const DeviceBsr& A, const double* x, double* y,
                        hipStream_t s);
 hipError_t launch_spmv_f32(const DeviceBsr& A, const double* x, double* y,
-                           hipStream_t s);
+                           hipStream_t s, const double* rs);
 // time the SpMV group widths on A and keep the fastest in A.group
 hipError_t spmv_autotune(DeviceBsr& A, hipStream_t s);
 

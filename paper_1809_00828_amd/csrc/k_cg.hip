@@ -292,6 +292,15 @@ __global__ __launch_bounds__(256) void k_cg_p(const double* __restrict__ z, doub
   if (i < n) p[i] = fma(beta, p[i], z[i]);
 }
 
+// c = a * b elementwise (skipped once the stop flag is set)
+__global__ void k_mul(const double* __restrict__ a, const double* __restrict__ b,
+                      double* __restrict__ c, int64_t n, const CgScalars* __restrict__ sc) {
+  if (sc && sc->done) return;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    c[i] = a[i] * b[i];
+}
+
 __global__ void k_copy(const double* __restrict__ a, double* __restrict__ b, int64_t n) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x)
@@ -406,9 +415,20 @@ static hipError_t enqueue_steps(fc_precond_s& pc, SolverWs& w, double* x, int ch
     hipError_t e;
     hipEvent_t* tev_it = (tev && it % every == 0) ? tev : nullptr;
     if (tev_it && (e = hipEventRecord(tev[4 * it + 0], s)) != hipSuccess) return e;
-    if (split_dot()) {
+    if (precA == 1) {
+      // scaled FP32 matrix: q = D^{1/2} (fl32(D^{-1/2} A D^{-1/2}) (D^{1/2} p))
+      hipLaunchKernelGGL(k_mul, dim3(pull_grid(n)), dim3(kVecThreads), 0, s, w.p, pb.sqd, w.t,
+                         n, w.sc);
+      e = launch_spmv_pq(pb.A, true, w.t, w.q, w.sc, nullptr, s, pb.sqd);
+      if (e != hipSuccess) return e;
+      if (tev_it && (e = hipEventRecord(tev[4 * it + 1], s)) != hipSuccess) return e;
+      hipLaunchKernelGGL(k_cg_pq, dim3(dot_grid(n)), dim3(256), 0, s, w.p, w.q, n, w.partial,
+                         w.sc);
+      hipLaunchKernelGGL(k_cg_alpha, dim3(1), dim3(1024), 0, s, w.partial, (int)dot_grid(n),
+                         w.sc);
+    } else if (split_dot()) {
       // SpMV without its fused dot, then (p, q) and alpha in one reduction
-      e = launch_spmv_pq(pb.A, precA == 1, w.p, w.q, w.sc, nullptr, s);
+      e = launch_spmv_pq(pb.A, false, w.p, w.q, w.sc, nullptr, s);
       if (e != hipSuccess) return e;
       if (tev_it && (e = hipEventRecord(tev[4 * it + 1], s)) != hipSuccess) return e;
       hipLaunchKernelGGL(k_cg_pq, dim3(dot_grid(n)), dim3(256), 0, s, w.p, w.q, n, w.partial,
@@ -416,7 +436,7 @@ static hipError_t enqueue_steps(fc_precond_s& pc, SolverWs& w, double* x, int ch
       hipLaunchKernelGGL(k_cg_alpha, dim3(1), dim3(1024), 0, s, w.partial, (int)dot_grid(n),
                          w.sc);
     } else {
-      e = launch_spmv_pq(pb.A, precA == 1, w.p, w.q, w.sc, w.partial, s);
+      e = launch_spmv_pq(pb.A, false, w.p, w.q, w.sc, w.partial, s);
       if (e != hipSuccess) return e;
       if (tev_it && (e = hipEventRecord(tev[4 * it + 1], s)) != hipSuccess) return e;
       hipLaunchKernelGGL(k_cg_alpha, dim3(1), dim3(1024), 0, s, w.partial,
@@ -625,7 +645,7 @@ fc_status pcg_solve(fc_precond_s& pc, const double* b, double* x, const fc_solve
                      o.mode == FC_MODE_IR_F32 || o.mode == FC_MODE_IR_BF16;
   const int precS = !low_s ? 0
                     : (o.mode == FC_MODE_S_F32 || o.mode == FC_MODE_IR_F32) ? 1 : 2;
-  if ((precS == 1 && !pc.L32) || (precS == 2 && !pc.Lbf)) {
+  if ((precS == 1 && !pc.Q32) || (precS == 2 && !pc.Lbf)) {
     set_error("fc_pcg_solve: the preconditioner holds no copy in the requested precision");
     return FC_E_ARG;
   }
@@ -661,7 +681,8 @@ fc_status pcg_solve(fc_precond_s& pc, const double* b, double* x, const fc_solve
     int precA = 1;
     if (!pb.A.val32) {
       FC_HIP(hipMalloc(&pb.A.val32, pb.A.nnzb * pb.bdim * pb.bdim * sizeof(float)));
-      FC_HIP(launch_cast_matrix(pb.A, s));
+      if (!pb.sqd) FC_HIP(hipMalloc(&pb.sqd, n * sizeof(double)));
+      FC_HIP(launch_cast_matrix(pb.A, pb.diag, pb.sqd, s));
     }
     if (!w.d) FC_HIP(hipMalloc(&w.d, n * sizeof(double)));
     if (!w.ro) FC_HIP(hipMalloc(&w.ro, n * sizeof(double)));

@@ -10,9 +10,13 @@ bool jacobi_needs_work(int m);
 hipError_t launch_sweep(fc_precond_s& pc, int32_t* need_eig, hipStream_t s);
 // Scaled Cholesky factors of the local inverses in FP32 / BF16 (pc.L32,
 // pc.Lbf, whichever is allocated; needs pc.isd).
-hipError_t launch_chol_pack(fc_precond_s& pc, hipStream_t s);
+// scaled Cholesky factors into pc.L32 / pc.Lbf; with `unsafe` instead only
+// flag the blocks whose FP32-rounded scaled inverse is not safely positive
+hipError_t launch_chol_pack(fc_precond_s& pc, hipStream_t s, int32_t* unsafe = nullptr);
 hipError_t launch_diag(const fc_problem_s& pb, hipStream_t s);
 hipError_t launch_fallback(const fc_problem_s& pb, fc_precond_s& pc,
                            unsigned long long* d_count, hipStream_t s);
-hipError_t launch_cast_matrix(const DeviceBsr& A, hipStream_t s);
+// A.val32 = FP32 of D^{-1/2} A D^{-1/2}; sqd receives sqrt(diag)
+hipError_t launch_cast_matrix(const DeviceBsr& A, const double* diag, double* sqd,
+                              hipStream_t s);
 }  // namespace fc

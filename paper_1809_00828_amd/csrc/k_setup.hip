@@ -308,11 +308,15 @@ __device__ __forceinline__ uint16_t f32_to_bf16(float f) {
   return (uint16_t)(u >> 16);
 }
 
-template <int GRID, int T>
+// kCheck: factor fl32(D^{1/2} P_B D^{1/2}) instead (the FP32 rounding of
+// the diagonally scaled inverse) and only report, in unsafe[blk], whether a
+// pivot fell to 1e-10 of the largest diagonal entry: where it does not, the
+// rounded matrix is positive definite with margin and may stand in for P_B.
+template <int GRID, int T, bool kCheck>
 __global__ __launch_bounds__(GRID * GRID) void k_chol_pack(
     const double* __restrict__ P, int m, const double* __restrict__ isd,
     const int32_t* __restrict__ elem_nodes, const int32_t* __restrict__ block_elem, int nn,
-    int bd, float* __restrict__ L32, uint16_t* __restrict__ Lbf) {
+    int bd, float* __restrict__ L32, uint16_t* __restrict__ Lbf, int32_t* __restrict__ unsafe) {
   __shared__ double rowbuf[2][GRID * T];
   __shared__ double red[16];
   __shared__ double sc[GRID * T];
@@ -332,6 +336,7 @@ __global__ __launch_bounds__(GRID * GRID) void k_chol_pack(
     for (int c = 0; c < T; ++c) {
       const int i = ti * T + r, j = tj * T + c;
       a[r][c] = (i < m && j < m) ? Pb[(int64_t)i * m + j] : 0.0;
+      if (kCheck && i < m && j < m) a[r][c] = (double)(float)(a[r][c] * sc[i] * sc[j]);
       if (i == j && i < m) dmax = fmax(dmax, a[r][c]);
     }
   {
@@ -344,7 +349,8 @@ __global__ __launch_bounds__(GRID * GRID) void k_chol_pack(
     for (int w = 0; w < (GRID * GRID + 63) / 64; ++w) v = fmax(v, red[w]);
     dmax = v;
   }
-  const double tiny = 1e-14 * dmax;
+  const double tiny = (kCheck ? 1e-10 : 1e-14) * dmax;
+  bool bad = false;
   for (int k = 0; k < m; ++k) {
     double* buf = rowbuf[k & 1];
     if (ti == k / T) {
@@ -359,6 +365,7 @@ __global__ __launch_bounds__(GRID * GRID) void k_chol_pack(
     __syncthreads();
     const double d = buf[k];
     const bool live = d > tiny;
+    bad = bad || !live;
     const double lkk = live ? sqrt(d) : 0.0;
     const double rl = live ? 1.0 / lkk : 0.0;
 #pragma unroll
@@ -379,6 +386,10 @@ __global__ __launch_bounds__(GRID * GRID) void k_chol_pack(
     }
   }
   __syncthreads();
+  if constexpr (kCheck) {
+    if (tid == 0) unsafe[blk] = bad ? 1 : 0;
+    return;
+  }
   // write the scaled lower triangle by subdiagonals
   const int64_t per = (int64_t)m * (m + 1) / 2;
 #pragma unroll
@@ -395,15 +406,20 @@ __global__ __launch_bounds__(GRID * GRID) void k_chol_pack(
     }
 }
 
-hipError_t launch_chol_pack(fc_precond_s& pc, hipStream_t s) {
+hipError_t launch_chol_pack(fc_precond_s& pc, hipStream_t s, int32_t* unsafe) {
   const int m = pc.m;
   const int64_t nb = pc.n_blocks;
   if (nb == 0) return hipSuccess;
   dim3 g((unsigned)nb);
   const fc_problem_s& pb = *pc.pb;
 #define FC_CHOL(GR, TT)                                                                     \
-  hipLaunchKernelGGL((k_chol_pack<GR, TT>), g, dim3(GR * GR), 0, s, pc.P, m, pc.isd,       \
-                     pb.elem_nodes, pc.block_elem, pc.nn, pc.bdim, pc.L32, pc.Lbf)
+  if (unsafe)                                                                               \
+    hipLaunchKernelGGL((k_chol_pack<GR, TT, true>), g, dim3(GR * GR), 0, s, pc.P, m, pc.isd, \
+                       pb.elem_nodes, pc.block_elem, pc.nn, pc.bdim, nullptr, nullptr, unsafe); \
+  else                                                                                      \
+    hipLaunchKernelGGL((k_chol_pack<GR, TT, false>), g, dim3(GR * GR), 0, s, pc.P, m,        \
+                       pc.isd, pb.elem_nodes, pc.block_elem, pc.nn, pc.bdim, pc.L32, pc.Lbf,    \
+                       nullptr)
   if (m <= 8) FC_CHOL(8, 1);
   else if (m <= 16) FC_CHOL(8, 2);
   else if (m <= 32) FC_CHOL(8, 4);
@@ -543,10 +559,42 @@ hipError_t launch_fallback(const fc_problem_s& pb, fc_precond_s& pc,
   return hipGetLastError();
 }
 
-hipError_t launch_cast_matrix(const DeviceBsr& A, hipStream_t s) {
+// sqd_i = sqrt(A_ii) (1 where A_ii <= 0)
+__global__ void k_sqrt_diag(const double* __restrict__ diag, double* __restrict__ sqd, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    sqd[i] = diag[i] > 0.0 ? sqrt(diag[i]) : 1.0;
+}
+
+// FP32 copy of the diagonally scaled matrix D^{-1/2} A D^{-1/2} (D = diag A),
+// same row-SoA layout; one thread per block row.
+__global__ void k_cast_scaled_f32(const int32_t* __restrict__ rowptr,
+                                  const int32_t* __restrict__ col, const double* __restrict__ val,
+                                  const double* __restrict__ sqd, int bd, int64_t n_rows,
+                                  float* __restrict__ out) {
+  const int bb = bd * bd;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_rows;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t base = rowptr[i];
+    const int L = rowptr[i + 1] - (int32_t)base;
+    for (int k = 0; k < L; ++k) {
+      const int64_t c = col[base + k];
+      for (int e = 0; e < bb; ++e) {
+        const int a = e / bd, b = e % bd;
+        const int64_t pos = base * bb + (int64_t)e * L + k;
+        out[pos] = (float)(val[pos] / (sqd[i * bd + a] * sqd[c * bd + b]));
+      }
+    }
+  }
+}
+
+hipError_t launch_cast_matrix(const DeviceBsr& A, const double* diag, double* sqd,
+                              hipStream_t s) {
   const int64_t n = A.nnzb * A.bdim * A.bdim;
   if (!A.val32 || n == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_cast_f32, dim3(4096), dim3(256), 0, s, A.val, A.val32, n);
+  hipLaunchKernelGGL(k_sqrt_diag, dim3(1024), dim3(256), 0, s, diag, sqd, A.n_rows * A.bdim);
+  hipLaunchKernelGGL(k_cast_scaled_f32, dim3((unsigned)((A.n_rows + 255) / 256)), dim3(256), 0, s,
+                     A.rowptr, A.col, A.val, sqd, A.bdim, A.n_rows, A.val32);
   return hipGetLastError();
 }
 

@@ -7,6 +7,8 @@ namespace fc {
 int spmv_num_blocks(const DeviceBsr& A);
 // q = A p leaving one partial (p, q) per workgroup in partial[0..nb)
 // (skipped when sc->done is set).
+// f32: the scaled FP32 copy, p already multiplied by rs = sqrt(diag A)
 hipError_t launch_spmv_pq(const DeviceBsr& A, bool f32, const double* p, double* q,
-                          CgScalars* sc, double* partial, hipStream_t s);
+                          CgScalars* sc, double* partial, hipStream_t s,
+                          const double* rs = nullptr);
 }  // namespace fc

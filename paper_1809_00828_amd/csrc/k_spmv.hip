@@ -24,12 +24,14 @@
 
 namespace fc {
 
+// rs (may be null): y_i *= rs_i, for the scaled FP32 copy D^{-1/2} A D^{-1/2}
+// applied to x already multiplied by D^{1/2}.
 template <int B, int G, typename T>
 __global__ __launch_bounds__(256) void k_spmv_bsr(
     const int32_t* __restrict__ rowptr, const int32_t* __restrict__ col,
     const T* __restrict__ val, const double* __restrict__ x,
     double* __restrict__ y, int64_t n_rows, const CgScalars* __restrict__ sc,
-    double* __restrict__ partial) {
+    double* __restrict__ partial, const double* __restrict__ rs) {
   constexpr int BB = B * B;
   constexpr int RPW = 256 / G;   // rows per tile
   __shared__ double lds[16];
@@ -97,6 +99,7 @@ __global__ __launch_bounds__(256) void k_spmv_bsr(
     if (lane == 0) {
 #pragma unroll
       for (int i = 0; i < B; ++i) {
+        if (rs) acc[i] *= rs[row * B + i];
         y[row * B + i] = acc[i];
         if (partial) dot = fma(x[row * B + i], acc[i], dot);
       }
@@ -141,7 +144,7 @@ static int64_t fused_grid(const DeviceBsr& A) {
 template <int B, typename T>
 static hipError_t spmv_dispatch(const DeviceBsr& A, const T* val, const double* x,
                                 double* y, hipStream_t s, const CgScalars* sc,
-                                double* partial) {
+                                double* partial, const double* rs) {
   const int G = group_width(A);
   const int64_t nt = num_tiles(A);
   if (nt == 0) return hipSuccess;
@@ -150,7 +153,7 @@ static hipError_t spmv_dispatch(const DeviceBsr& A, const T* val, const double* 
 #define FC_SPMV_CASE(GG)                                                           \
   case GG:                                                                         \
     hipLaunchKernelGGL((k_spmv_bsr<B, GG, T>), grid, block, 0, s, A.rowptr, A.col, \
-                       val, x, y, A.n_rows, sc, partial);                         \
+                       val, x, y, A.n_rows, sc, partial, rs);                     \
     break;
   switch (G) {
     FC_SPMV_CASE(8)
@@ -164,11 +167,12 @@ static hipError_t spmv_dispatch(const DeviceBsr& A, const T* val, const double* 
 
 template <typename T>
 static hipError_t spmv_any(const DeviceBsr& A, const T* val, const double* x, double* y,
-                           hipStream_t s, const CgScalars* sc, double* partial) {
+                           hipStream_t s, const CgScalars* sc, double* partial,
+                           const double* rs = nullptr) {
   switch (A.bdim) {
-    case 1: return spmv_dispatch<1, T>(A, val, x, y, s, sc, partial);
-    case 2: return spmv_dispatch<2, T>(A, val, x, y, s, sc, partial);
-    case 3: return spmv_dispatch<3, T>(A, val, x, y, s, sc, partial);
+    case 1: return spmv_dispatch<1, T>(A, val, x, y, s, sc, partial, rs);
+    case 2: return spmv_dispatch<2, T>(A, val, x, y, s, sc, partial, rs);
+    case 3: return spmv_dispatch<3, T>(A, val, x, y, s, sc, partial, rs);
   }
   return hipErrorInvalidValue;
 }
@@ -177,8 +181,9 @@ hipError_t launch_spmv(const DeviceBsr& A, const double* x, double* y, hipStream
   return spmv_any<double>(A, A.val, x, y, s, nullptr, nullptr);
 }
 
-hipError_t launch_spmv_f32(const DeviceBsr& A, const double* x, double* y, hipStream_t s) {
-  return spmv_any<float>(A, A.val32, x, y, s, nullptr, nullptr);
+hipError_t launch_spmv_f32(const DeviceBsr& A, const double* x, double* y, hipStream_t s,
+                           const double* rs) {
+  return spmv_any<float>(A, A.val32, x, y, s, nullptr, nullptr, rs);
 }
 
 int spmv_num_blocks(const DeviceBsr& A) { return (int)fused_grid(A); }
@@ -222,8 +227,8 @@ hipError_t spmv_autotune(DeviceBsr& A, hipStream_t s) {
 }
 
 hipError_t launch_spmv_pq(const DeviceBsr& A, bool f32, const double* p, double* q,
-                          CgScalars* sc, double* partial, hipStream_t s) {
-  if (f32) return spmv_any<float>(A, A.val32, p, q, s, sc, partial);
+                          CgScalars* sc, double* partial, hipStream_t s, const double* rs) {
+  if (f32) return spmv_any<float>(A, A.val32, p, q, s, sc, partial, rs);
   return spmv_any<double>(A, A.val, p, q, s, sc, partial);
 }
 
