@@ -328,6 +328,7 @@ __global__ __launch_bounds__(GRID * GRID) void k_chol_pack(
     const int64_t dof = (int64_t)elem_nodes[e * nn + i / bd] * bd + (i % bd);
     sc[i] = 1.0 / isd[dof];   // sqrt(A_ii)
   }
+  __syncthreads();   // the check scales every tile entry by sc[i] sc[j]
   double a[T][T];
   double dmax = 0.0;
 #pragma unroll

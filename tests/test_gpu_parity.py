@@ -318,3 +318,53 @@ def test_low_precision_copies_required(torch):
     x = torch.zeros_like(b)
     with pytest.raises(fc.FcError):
         fc.pcg_solve(pb, pc, b, x, mode="s_bf16", raise_on_error=True)
+
+
+def _min_rel_pivot(M):
+    """Smallest Cholesky pivot of M relative to its largest diagonal entry
+    (negative where the factorisation breaks down)."""
+    M = M.copy()
+    n = M.shape[0]
+    dmax = max(float(np.max(np.diag(M))), 1e-300)
+    worst = np.inf
+    for k in range(n):
+        d = M[k, k]
+        worst = min(worst, d / dmax)
+        if d <= 0:
+            return worst
+        l = M[k + 1:, k] / np.sqrt(d)
+        M[k + 1:, k + 1:] -= np.outer(l, l)
+        M[k + 1:, k] = l
+    return worst
+
+
+@pytest.mark.parametrize("name", ["elast3d_p2", "pois3d_p3", "disk7_p4"])
+def test_f32_copy_certificate_counts(torch, name):
+    """The FP32 copy keeps exactly the blocks whose rounded, diagonally
+    scaled inverse factors with every pivot above 1e-10 of the largest
+    diagonal entry.  Recomputed here from each block's FP64 inverse (the
+    library's own: on ill-determined blocks the oracle's differs by
+    eps * kappa, enough to move a pivot across the threshold) and the
+    oracle's matrix diagonal: blocks far from the threshold on either side
+    must be classified the same way."""
+    print(f"[f32 certificate] {name}", flush=True)
+    _, s = oracle_system(name)
+    A = s["A"]
+    S, _, blocks = oracle_precond(name)
+    pc = fc.Precond(lib_problem(name), store=fc.STORE_F64 | fc.STORE_F32)
+    clearly_bad = maybe = 0
+    for k, B in enumerate(blocks):
+        AB = schwarz.extract_submatrix(A, B)
+        P = pc.block_inverse(k)
+        dg = np.sqrt(np.maximum(np.diag(AB), 0.0))
+        dg[dg == 0] = 1.0
+        Ph = (P * dg[:, None] * dg[None, :]).astype(np.float32).astype(np.float64)
+        piv = _min_rel_pivot(Ph)
+        if piv < 1e-12:
+            clearly_bad += 1
+        elif piv < 1e-8:
+            maybe += 1
+    info = pc.info()
+    assert info["n_f32_blocks"] + info["n_f32_from_f64"] == info["n_blocks"]
+    assert clearly_bad <= info["n_f32_from_f64"] <= clearly_bad + maybe, \
+        (info, clearly_bad, maybe)
