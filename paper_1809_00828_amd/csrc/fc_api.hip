@@ -68,7 +68,7 @@ static void free_precond(fc_precond_s* pc) {
   solver_ws_destroy(pc->ws);
   coarse_destroy(pc->coarse);
   for (void* p : {(void*)pc->block_elem, (void*)pc->P, (void*)pc->Q, (void*)pc->Q32,
-                  (void*)pc->unsafe32, (void*)pc->unsafe_flag32, (void*)pc->L32, (void*)pc->Lbf, (void*)pc->isd,
+                  (void*)pc->unsafe32, (void*)pc->unsafe_flag32, (void*)pc->Lbf, (void*)pc->isd,
                   (void*)pc->inv_ptr, (void*)pc->inv_idx, (void*)pc->fallback, (void*)pc->y})
     if (p) (void)hipFree(p);
   delete pc;

@@ -88,9 +88,8 @@ struct fc_precond_s {
   int32_t* unsafe32 = nullptr;     // blocks whose FP32 copy is not safely positive
   int32_t* unsafe_flag32 = nullptr; // the same as one flag per block
   int64_t n_unsafe32 = 0;          //   (applied from the FP64 copy instead)
-  float* L32 = nullptr;            // optional FP32 scaled Cholesky factors
   uint16_t* Lbf = nullptr;         // optional BF16 scaled Cholesky factors
-  double* isd = nullptr;           // [n_dofs] 1/sqrt(A_ll), scaling of L32/Lbf
+  double* isd = nullptr;           // [n_dofs] 1/sqrt(A_ll), scaling of Q32/Lbf
   int32_t* inv_ptr = nullptr;      // [n_nodes+1] node -> (block, local node)
   int32_t* inv_idx = nullptr;      // entries: block*m + local_node*bdim
   double* fallback = nullptr;      // [n_dofs] 1/A_ll where S_ll = 0, else 0

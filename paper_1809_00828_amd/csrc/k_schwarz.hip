@@ -19,12 +19,17 @@
 //     even the row k = m/2 holds every pair twice and is used once.
 //   * Dense layout: lane i accumulates sum_j P_B[j][i] r_B[j] (row j of a
 //     symmetric matrix is its column j) reading P_B row by row.
+//   * FP32: the same wrapped diagonals of the diagonally scaled inverse
+//     D^{1/2} P_B D^{1/2} rounded to FP32 (FP32 accumulation), applied as
+//     D^{-1/2} (.) D^{-1/2}; blocks whose rounded copy is not certified
+//     positive definite are skipped there and done from the FP64 copy.
+//   * BF16: the scaled Cholesky factor of the same matrix, two triangular
+//     passes through LDS (positive semi-definite however rounded).
 // Phase 2 (pull): every unknown sums the y_B entries of the blocks that
 // contain it, in a fixed order (no atomics, bitwise reproducible), and adds
 // its diagonal-scaling term.
 #include <algorithm>
 #include <cstdlib>
-#include <string>
 
 #include "dev_common.h"
 #include "k_schwarz.h"
@@ -290,160 +295,6 @@ __global__ __launch_bounds__(256) void k_schwarz_chol_small(
   if (active) y[blk * m + i] = (double)chol_pass2<T>(Lb, &tb[w][lb * m], m, i) * s;
 }
 
-// Offset of diagonal d of a packed-by-subdiagonals lower triangle.
-__device__ __forceinline__ int64_t diag_off(int d, int m) {
-  return (int64_t)d * m - (int64_t)d * (d - 1) / 2;
-}
-
-// t_j = sum_{d=0}^{m-1-j} L[j+d][j] rb[j+d] with the factor read straight
-// from global memory, U independent loads per lane in flight.
-template <typename T, int U>
-__device__ __forceinline__ float col_dot_g(const T* __restrict__ Lb, const float* rb, int m,
-                                           int j) {
-  const int n = m - j;
-  float acc[U];
-#pragma unroll
-  for (int u = 0; u < U; ++u) acc[u] = 0.f;
-  int d = 0;
-  for (; d + U <= n; d += U) {
-    float v[U];
-#pragma unroll
-    for (int u = 0; u < U; ++u) v[u] = ld_f32(Lb + diag_off(d + u, m) + j);
-#pragma unroll
-    for (int u = 0; u < U; ++u) acc[u] = fmaf(v[u], rb[j + d + u], acc[u]);
-  }
-  for (; d < n; ++d) acc[0] = fmaf(ld_f32(Lb + diag_off(d, m) + j), rb[j + d], acc[0]);
-  float t = 0.f;
-#pragma unroll
-  for (int u = 0; u < U; ++u) t += acc[u];
-  return t;
-}
-
-// y_i = sum_{d=0}^{i} L[i][i-d] tb[i-d], factor from global memory (the
-// second read of the block's factor, served by the caches).
-template <typename T, int U>
-__device__ __forceinline__ float row_dot_g(const T* __restrict__ Lb, const float* tb, int m,
-                                           int i) {
-  const int n = i + 1;
-  float acc[U];
-#pragma unroll
-  for (int u = 0; u < U; ++u) acc[u] = 0.f;
-  int d = 0;
-  for (; d + U <= n; d += U) {
-    float v[U];
-#pragma unroll
-    for (int u = 0; u < U; ++u) v[u] = ld_f32(Lb + diag_off(d + u, m) + i - d - u);
-#pragma unroll
-    for (int u = 0; u < U; ++u) acc[u] = fmaf(v[u], tb[i - d - u], acc[u]);
-  }
-  for (; d < n; ++d) acc[0] = fmaf(ld_f32(Lb + diag_off(d, m) + i - d), tb[i - d], acc[0]);
-  float t = 0.f;
-#pragma unroll
-  for (int u = 0; u < U; ++u) t += acc[u];
-  return t;
-}
-
-// Factored apply for m > 64 without staging the factor in LDS: both
-// triangular passes read it from global memory, the second from the
-// caches.  Small LDS use keeps many blocks resident per CU, so the
-// factor's loads of many blocks are in flight together.
-template <typename T>
-__global__ __launch_bounds__(256) void k_schwarz_chol_stream(
-    const T* __restrict__ L, const int32_t* __restrict__ elem_nodes,
-    const int32_t* __restrict__ block_elem, int nn, int bd, int m,
-    const double* __restrict__ r, const double* __restrict__ q, const double* __restrict__ isd,
-    const CgScalars* __restrict__ sc, double* __restrict__ y, int64_t n_blocks) {
-  __shared__ float rb[256], tb[256];
-  if (sc && sc->done) return;
-  const int64_t blk = xcd_remap(blockIdx.x, gridDim.x);
-  if (blk >= n_blocks) return;
-  const double alpha = (sc && q) ? sc->alpha : 0.0;
-  const int i = threadIdx.x;
-  const int64_t per = (int64_t)m * (m + 1) / 2;
-  const T* Lb = L + blk * per;
-  const int64_t e = block_elem[blk];
-  int64_t dof = 0;
-  double sdof = 1.0;
-  if (i < m) {
-    dof = (int64_t)elem_nodes[e * nn + i / bd] * bd + (i % bd);
-    sdof = isd[dof];
-    rb[i] = (float)(gather_r(r, q, alpha, dof) * sdof);
-  }
-  __syncthreads();
-  if (i < m) tb[i] = col_dot_g<T, 8>(Lb, rb, m, i);
-  __syncthreads();
-  if (i < m) y[blk * m + i] = (double)row_dot_g<T, 8>(Lb, tb, m, i) * sdof;
-}
-
-// Factored apply for m > 64 with the factor staged in LDS and the next
-// block's factor prefetched into registers while the current block's two
-// triangular passes run: persistent workgroups, one block at a time.
-// Requires every block's packed factor to start 16-byte aligned.
-constexpr int kPipePre = 20;   // 16-byte chunks per lane: factors <= 81,920 B
-
-template <typename T>
-__global__ __launch_bounds__(256) void k_schwarz_chol_pipe(
-    const T* __restrict__ L, const int32_t* __restrict__ elem_nodes,
-    const int32_t* __restrict__ block_elem, int nn, int bd, int m,
-    const double* __restrict__ r, const double* __restrict__ q, const double* __restrict__ isd,
-    const CgScalars* __restrict__ sc, double* __restrict__ y, int64_t n_blocks) {
-  typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
-  extern __shared__ __align__(16) unsigned char dyn_lds[];
-  __shared__ float rb[256], tb[256];
-  if (sc && sc->done) return;
-  const double alpha = (sc && q) ? sc->alpha : 0.0;
-  const int tid = threadIdx.x;
-  const int64_t per = (int64_t)m * (m + 1) / 2;
-  const int nv = (int)(per * (int64_t)sizeof(T) / 16);
-  u32x4* Ls4 = reinterpret_cast<u32x4*>(dyn_lds);
-  const T* Ls = reinterpret_cast<const T*>(dyn_lds);
-  u32x4 pre[kPipePre];
-  auto fetch = [&](int64_t blk) {
-    const u32x4* src = reinterpret_cast<const u32x4*>(L + blk * per);
-#pragma unroll
-    for (int c = 0; c < kPipePre; ++c) {
-      const int idx = tid + c * 256;
-      if (idx < nv) pre[c] = __builtin_nontemporal_load(src + idx);
-    }
-  };
-  int64_t blk = blockIdx.x;
-  if (blk >= n_blocks) return;
-  fetch(blk);
-  for (; blk < n_blocks; blk += gridDim.x) {
-#pragma unroll
-    for (int c = 0; c < kPipePre; ++c) {
-      const int idx = tid + c * 256;
-      if (idx < nv) Ls4[idx] = pre[c];
-    }
-    const int64_t e = block_elem[blk];
-    int64_t dof = 0;
-    double sdof = 1.0;
-    if (tid < m) {
-      dof = (int64_t)elem_nodes[e * nn + tid / bd] * bd + (tid % bd);
-      sdof = isd[dof];
-      rb[tid] = (float)(gather_r(r, q, alpha, dof) * sdof);
-    }
-    __syncthreads();
-    if (blk + gridDim.x < n_blocks) fetch(blk + gridDim.x);
-    if (tid < m) tb[tid] = chol_pass1<T>(Ls, rb, m, tid);
-    __syncthreads();
-    if (tid < m) y[blk * m + tid] = (double)chol_pass2<T>(Ls, tb, m, tid) * sdof;
-    __syncthreads();
-  }
-}
-
-// FC_CHOL_KERNEL = lds | stream | pipe selects the factored apply for
-// m > 64 (default pipe).
-static int chol_kernel() {
-  static const int v = [] {
-    const char* e = std::getenv("FC_CHOL_KERNEL");
-    if (e && std::string(e) == "lds") return 0;
-    if (e && std::string(e) == "stream") return 1;
-    return 2;
-  }();
-  return v;
-}
-
 template <typename T>
 static hipError_t phase1_chol(const fc_precond_s& pc, const T* L, const double* r,
                               const double* q, const CgScalars* sc, hipStream_t s) {
@@ -451,27 +302,7 @@ static hipError_t phase1_chol(const fc_precond_s& pc, const T* L, const double* 
   if (pc.n_blocks == 0) return hipSuccess;
   const int m = pc.m;
   const int64_t per = (int64_t)m * (m + 1) / 2;
-  const bool aligned16 = (per * (int64_t)sizeof(T)) % 16 == 0 &&
-                         (reinterpret_cast<uintptr_t>(L) % 16) == 0;
-  if (m > 64 && chol_kernel() == 2 && aligned16 &&
-      per * (int64_t)sizeof(T) <= (int64_t)kPipePre * 256 * 16) {
-    const size_t lds = (size_t)per * sizeof(T);
-    (void)hipFuncSetAttribute((const void*)k_schwarz_chol_pipe<T>,
-                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    int dev = 0, ncu = 256;
-    (void)hipGetDevice(&dev);
-    (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
-    const int64_t per_cu = std::max<int64_t>(1, (160 * 1024) / (int64_t)(lds + 2048));
-    const int64_t nwg = std::min<int64_t>(pc.n_blocks, (int64_t)ncu * per_cu);
-    hipLaunchKernelGGL(k_schwarz_chol_pipe<T>, dim3((unsigned)nwg), dim3(256), lds, s, L,
-                       pb.elem_nodes, pc.block_elem, pc.nn, pc.bdim, m, r, q, pc.isd, sc, pc.y,
-                       pc.n_blocks);
-  } else if (m > 64 && chol_kernel() == 1) {
-    const int threads = 64 * ((m + 63) / 64);
-    hipLaunchKernelGGL(k_schwarz_chol_stream<T>, dim3((unsigned)pc.n_blocks), dim3(threads), 0,
-                       s, L, pb.elem_nodes, pc.block_elem, pc.nn, pc.bdim, m, r, q, pc.isd, sc,
-                       pc.y, pc.n_blocks);
-  } else if (m > 64) {
+  if (m > 64) {
     const int threads = 64 * ((m + 63) / 64);
     const size_t lds = (size_t)per * sizeof(T);
     (void)hipFuncSetAttribute((const void*)k_schwarz_chol_large<T>,

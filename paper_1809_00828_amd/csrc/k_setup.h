@@ -8,10 +8,9 @@ hipError_t launch_jacobi(fc_precond_s& pc, const int32_t* sel, int64_t count,
 // true when the Jacobi eigen path keeps its blocks in global memory
 bool jacobi_needs_work(int m);
 hipError_t launch_sweep(fc_precond_s& pc, int32_t* need_eig, hipStream_t s);
-// Scaled Cholesky factors of the local inverses in FP32 / BF16 (pc.L32,
-// pc.Lbf, whichever is allocated; needs pc.isd).
-// scaled Cholesky factors into pc.L32 / pc.Lbf; with `unsafe` instead only
-// flag the blocks whose FP32-rounded scaled inverse is not safely positive
+// Scaled Cholesky factors of the local inverses in BF16 into pc.Lbf (needs
+// pc.isd); with `unsafe` instead only flag the blocks whose FP32-rounded
+// scaled inverse is not safely positive definite
 hipError_t launch_chol_pack(fc_precond_s& pc, hipStream_t s, int32_t* unsafe = nullptr);
 hipError_t launch_diag(const fc_problem_s& pb, hipStream_t s);
 hipError_t launch_fallback(const fc_problem_s& pb, fc_precond_s& pc,

@@ -316,7 +316,7 @@ template <int GRID, int T, bool kCheck>
 __global__ __launch_bounds__(GRID * GRID) void k_chol_pack(
     const double* __restrict__ P, int m, const double* __restrict__ isd,
     const int32_t* __restrict__ elem_nodes, const int32_t* __restrict__ block_elem, int nn,
-    int bd, float* __restrict__ L32, uint16_t* __restrict__ Lbf, int32_t* __restrict__ unsafe) {
+    int bd, uint16_t* __restrict__ Lbf, int32_t* __restrict__ unsafe) {
   __shared__ double rowbuf[2][GRID * T];
   __shared__ double red[16];
   __shared__ double sc[GRID * T];
@@ -402,8 +402,7 @@ __global__ __launch_bounds__(GRID * GRID) void k_chol_pack(
       const int dg = i - j;
       const int64_t pos = blk * per + (int64_t)dg * m - (int64_t)dg * (dg - 1) / 2 + j;
       const double v = a[r][c] * sc[i];
-      if (L32) L32[pos] = (float)v;
-      if (Lbf) Lbf[pos] = f32_to_bf16((float)v);
+      Lbf[pos] = f32_to_bf16((float)v);
     }
 }
 
@@ -416,11 +415,10 @@ hipError_t launch_chol_pack(fc_precond_s& pc, hipStream_t s, int32_t* unsafe) {
 #define FC_CHOL(GR, TT)                                                                     \
   if (unsafe)                                                                               \
     hipLaunchKernelGGL((k_chol_pack<GR, TT, true>), g, dim3(GR * GR), 0, s, pc.P, m, pc.isd, \
-                       pb.elem_nodes, pc.block_elem, pc.nn, pc.bdim, nullptr, nullptr, unsafe); \
+                       pb.elem_nodes, pc.block_elem, pc.nn, pc.bdim, nullptr, unsafe);          \
   else                                                                                      \
     hipLaunchKernelGGL((k_chol_pack<GR, TT, false>), g, dim3(GR * GR), 0, s, pc.P, m,        \
-                       pc.isd, pb.elem_nodes, pc.block_elem, pc.nn, pc.bdim, pc.L32, pc.Lbf,    \
-                       nullptr)
+                       pc.isd, pb.elem_nodes, pc.block_elem, pc.nn, pc.bdim, pc.Lbf, nullptr)
   if (m <= 8) FC_CHOL(8, 1);
   else if (m <= 16) FC_CHOL(8, 2);
   else if (m <= 32) FC_CHOL(8, 4);
