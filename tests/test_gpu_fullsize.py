@@ -1,13 +1,16 @@
-"""Full-size checks on the benchmark workload: 3-D elasticity on 32^3 cells,
-p = 3, 64 voids, 2,738,019 unknowns.  They run in the launch configuration
-that bench.py times, on outputs the oracle can compute one by one.
-- Sampled rows of y = A x against rows assembled from the oracle's element
-  systems of the cells that touch each sampled node.
-- Sampled local inverses P_B against the oracle's pseudo-inverse of A_B,
-  assembled from the 27 cells around the block.
+"""Full-size checks on the benchmark workloads, in the launch configuration
+that bench.py times, on outputs the oracle can compute one by one:
+- 3-D elasticity on 32^3 cells, p = 3, 64 voids (2,738,019 unknowns);
+- 3-D Poisson on 64^3 cells, p = 2, 64 voids (2,146,689 unknowns), the
+  learned form's evaluation problem.
+Checked are:
+- sampled rows of y = A x against rows assembled from the oracle's element
+  systems of the cells that touch each sampled node;
+- sampled local inverses P_B against the oracle's pseudo-inverse of A_B,
+  assembled from the 27 cells around the block;
 - z = S r at the block's interior unknowns, which belong to that block
-  alone.
-- The benchmark solve: true residual at or below the tolerance, and bitwise
+  alone;
+- the plain solve: true residual at or below the tolerance, and bitwise
   reproducible."""
 import itertools
 
@@ -22,9 +25,63 @@ from tests.gpu_common import require_gpu
 
 pytestmark = pytest.mark.gpu
 
-DESC = fcgen.porous_elasticity_3d(seed=0)
-N, P = DESC["n"], DESC["p"]
-N1 = P * N + 1
+WORKLOADS = {
+    "elastic32_p3": lambda: fcgen.porous_elasticity_3d(seed=0),
+    "poisson64_p2": lambda: fcgen.porous_poisson_3d(100, n=64, p=2),
+}
+
+
+class Workload:
+    def __init__(self, name):
+        self.name = name
+        self.desc = WORKLOADS[name]()
+        self.n, self.p = self.desc["n"], self.desc["p"]
+        self.n1 = self.p * self.n + 1
+        self.bd = 3 if self.desc["pde"] == "elasticity" else 1
+        self.cache = {}
+        self.clamped = set(ASM.clamped_dofs(self.desc).tolist())
+
+    def element(self, cell):
+        if cell not in self.cache:
+            Ke, _, _ = ASM.element_system(self.desc, cell)
+            self.cache[cell] = (Ke, ASM.element_dofs(self.desc, cell))
+        return self.cache[cell]
+
+    def local_rows(self, dofs, cells):
+        """Rows of the assembled, clamped A for `dofs`, from the element
+        systems of `cells` (which must hold every cell touching them)."""
+        rows = {int(d): {} for d in dofs}
+        for c in cells:
+            Ke, ed = self.element(c)
+            for a, da in enumerate(ed):
+                da = int(da)
+                if da not in rows:
+                    continue
+                r = rows[da]
+                for b, db in enumerate(ed):
+                    r[int(db)] = r.get(int(db), 0.0) + Ke[a, b]
+        for d, r in rows.items():
+            if d in self.clamped:
+                rows[d] = {d: r[d]}
+            else:
+                for c in list(r):
+                    if c in self.clamped:
+                        del r[c]
+        return rows
+
+    def cells_of_node(self, g):
+        """Cells whose closure contains lattice point g = (gx, gy, gz)."""
+        ranges = []
+        for gk in g:
+            e = gk // self.p
+            cand = {e, e - 1} if gk % self.p == 0 else {e}
+            ranges.append(sorted(c for c in cand if 0 <= c < self.n))
+        return list(itertools.product(*ranges))
+
+    def neighbourhood(self, cell):
+        return [tuple(c + o for c, o in zip(cell, off))
+                for off in itertools.product((-1, 0, 1), repeat=3)
+                if all(0 <= c + o < self.n for c, o in zip(cell, off))]
 
 
 @pytest.fixture(scope="module")
@@ -32,83 +89,33 @@ def torch():
     return require_gpu()
 
 
-@pytest.fixture(scope="module")
-def lib(torch):
-    print("[fullsize] host assembly + upload", flush=True)
-    pb = fc.HostSystem(DESC).upload()
+@pytest.fixture(scope="module", params=list(WORKLOADS))
+def lib(request, torch):
+    wl = Workload(request.param)
+    print(f"[fullsize] {wl.name}: host assembly + upload", flush=True)
+    pb = fc.HostSystem(wl.desc).upload()
     pc = fc.Precond(pb)
-    eta = pb.eta()
-    return pb, pc, eta
-
-
-_cache = {}
-
-
-def element(cell):
-    if cell not in _cache:
-        Ke, _, _ = ASM.element_system(DESC, cell)
-        _cache[cell] = (Ke, ASM.element_dofs(DESC, cell))
-    return _cache[cell]
-
-
-def local_rows(dofs, cells):
-    """Rows of the assembled, clamped A for `dofs`, from the element
-    systems of `cells` (which must hold every cell touching them)."""
-    clamped = set(ASM.clamped_dofs(DESC).tolist())
-    rows = {int(d): {} for d in dofs}
-    for c in cells:
-        Ke, ed = element(c)
-        for a, da in enumerate(ed):
-            da = int(da)
-            if da not in rows:
-                continue
-            r = rows[da]
-            for b, db in enumerate(ed):
-                r[int(db)] = r.get(int(db), 0.0) + Ke[a, b]
-    for d, r in rows.items():
-        if d in clamped:
-            rows[d] = {d: r[d]}
-        else:
-            for c in list(r):
-                if c in clamped:
-                    del r[c]
-    return rows
-
-
-def cells_of_node(g):
-    """Cells whose closure contains lattice point g = (gx, gy, gz)."""
-    ranges = []
-    for gk in g:
-        e = gk // P
-        cand = {e, e - 1} if gk % P == 0 else {e}
-        ranges.append(sorted(c for c in cand if 0 <= c < N))
-    return list(itertools.product(*ranges))
+    return wl, pb, pc, pb.eta()
 
 
 def test_spmv_sampled_rows(torch, lib):
-    pb, _, _ = lib
+    wl, pb, _, _ = lib
     rng = np.random.default_rng(31)
     x = rng.standard_normal(pb.n)
     y = torch.empty(pb.n, dtype=torch.float64, device="cuda")
     pb.apply_A(torch.as_tensor(x, device="cuda"), y)
     y = y.cpu().numpy()
+    N1 = wl.n1
     nodes = [tuple(int(v) for v in rng.integers(0, N1, size=3)) for _ in range(12)]
     nodes += [(0, 0, 0), (N1 - 1, N1 - 1, N1 - 1), (N1 // 2, N1 // 2, 0), (5, 7, N1 - 1)]
     for g in nodes:
         node = g[0] + N1 * (g[1] + N1 * g[2])
-        dofs = [3 * node + c for c in range(3)]
-        cells = [(cx, cy, cz) for (cx, cy, cz) in cells_of_node(g)]
-        rows = local_rows(dofs, cells)
+        dofs = [wl.bd * node + c for c in range(wl.bd)]
+        rows = wl.local_rows(dofs, wl.cells_of_node(g))
         for d in dofs:
             ref = sum(v * x[c] for c, v in rows[d].items())
             scale = sum(abs(v * x[c]) for c, v in rows[d].items())
-            assert abs(y[d] - ref) <= 1e-13 * scale + 1e-300, (g, d, y[d], ref)
-
-
-def _neighbourhood(cell):
-    return [tuple(c + o for c, o in zip(cell, off))
-            for off in itertools.product((-1, 0, 1), repeat=3)
-            if all(0 <= c + o < N for c, o in zip(cell, off))]
+            assert abs(y[d] - ref) <= 1e-13 * scale + 1e-300, (wl.name, g, d, y[d], ref)
 
 
 def _pick_blocks(eta):
@@ -123,17 +130,18 @@ def _pick_blocks(eta):
 
 
 def test_local_inverse_and_apply_sampled_blocks(torch, lib):
-    pb, pc, eta = lib
+    wl, pb, pc, eta = lib
     rng = np.random.default_rng(33)
     r = rng.standard_normal(pb.n)
     z = torch.empty(pb.n, dtype=torch.float64, device="cuda")
     pc.apply_M(torch.as_tensor(r, device="cuda"), z)
     z = z.cpu().numpy()
+    N, N1, P = wl.n, wl.n1, wl.p
     for k in _pick_blocks(eta):
         cell = (k % N, (k // N) % N, k // (N * N))
-        print(f"[fullsize] block {k} cell {cell} eta {eta[k]:.3f}", flush=True)
-        _, ed = element(cell)
-        rows = local_rows(ed, _neighbourhood(cell))
+        print(f"[fullsize] {wl.name} block {k} cell {cell} eta {eta[k]:.3f}", flush=True)
+        _, ed = wl.element(cell)
+        rows = wl.local_rows(ed, wl.neighbourhood(cell))
         AB = np.array([[rows[int(a)].get(int(b), 0.0) for b in ed] for a in ed])
         ref = SCH.pseudo_inverse(AB)
         got = pc.block_inverse(k)
@@ -142,28 +150,28 @@ def test_local_inverse_and_apply_sampled_blocks(torch, lib):
         kappa = kept.max() / kept.min()
         tol = 1e-15 * AB.shape[0] * kappa + 1e-13
         err = np.linalg.norm(got - ref) / np.linalg.norm(ref)
-        assert err <= tol, (k, err, kappa)
+        assert err <= tol, (wl.name, k, err, kappa)
         # unknowns interior to the cell belong to this block only
         zr = ref @ r[ed]
         for a, d in enumerate(ed):
-            node = int(d) // 3
+            node = int(d) // wl.bd
             g = (node % N1, (node // N1) % N1, node // (N1 * N1))
             if all(gk % P != 0 for gk in g):
                 bound = tol * np.linalg.norm(ref) * np.linalg.norm(r[ed]) + 1e-14 * abs(zr[a])
-                assert abs(z[int(d)] - zr[a]) <= bound, (k, int(d), z[int(d)], zr[a])
+                assert abs(z[int(d)] - zr[a]) <= bound, (wl.name, k, int(d), z[int(d)], zr[a])
 
 
 def test_benchmark_solve_properties(torch, lib):
     """The solve bench.py times: residual stop at 1e-8 with timing events."""
-    pb, pc, _ = lib
+    wl, pb, pc, _ = lib
     b = torch.empty(pb.n, dtype=torch.float64, device="cuda")
     pb.rhs(b)
     xs = []
     for _ in range(2):
         x = torch.zeros_like(b)
         info = fc.pcg_solve(pb, pc, b, x, tol=1e-8, stop="residual", timing=True)
-        print(f"[fullsize] solve {info['iters']} iterations, rel res {info['rel_res_true']:.3e}",
-              flush=True)
+        print(f"[fullsize] {wl.name} solve {info['iters']} iterations, rel res "
+              f"{info['rel_res_true']:.3e}", flush=True)
         assert info["status"] == "OK"
         assert info["rel_res_true"] <= 1e-8
         xs.append(x)
