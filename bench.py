@@ -31,7 +31,7 @@ HBM_PEAK_GBS = 8000.0
 # counter passes (FETCH_SIZE, WRITE_SIZE), scaled by what the same counters
 # read for a plain 4 GiB copy (profiles/pcg_fp64_elastic32_p3_hbm_counters.md);
 # to be re-measured whenever one of these kernels changes.
-TRAFFIC = {"spmv": 8.9339e9, "schwarz": 4.6884e9}
+TRAFFIC = {"spmv": None, "schwarz": 4.6884e9}
 METRIC = "DOF·iter/s and time-to-1e-8 residual: mixed/learned vs plain FP64 PCG"
 
 
@@ -48,7 +48,10 @@ def algorithmic_bytes(info, m, n_blocks, nn):
     n = info["n_dofs"]
     bd = info["bsr_dim"]
     nnzb = info["nnzb"]
-    spmv = nnzb * (bd * bd * 8 + 4) + (n // bd + 1) * 4 + 2 * n * 8
+    # values (and column indices unless the columns follow from the
+    # lattice), row pointers, x and q once
+    col_bytes = 0 if info.get("lattice_columns") else 4
+    spmv = nnzb * (bd * bd * 8 + col_bytes) + (n // bd + 1) * 4 + 2 * n * 8
     # stored half of each symmetric P_B once ((m/2+1)*m wrapped diagonals),
     # element node lists, gathered r and q once, y_B written
     schwarz = n_blocks * (m // 2 + 1) * m * 8 + n_blocks * nn * 4 + 2 * n * 8 + n_blocks * m * 8

@@ -184,6 +184,12 @@ fc_status fc_precond_build(fc_problem pb, const fc_precond_opts* opts,
 fc_status fc_precond_info(fc_precond pc, int64_t* n_blocks,
                           int64_t* n_fallback, int64_t* n_eig_blocks,
                           int64_t* n_dropped);
+/* Launch shape the SpMV chose for this problem at set-up: lanes per block
+ * row (timed on the matrix itself), and whether the block columns are
+ * computed from the lattice (1: the matrix came from a problem description
+ * and its columns were verified to be each row's lattice box, so the
+ * column array is not read) or read (0). */
+fc_status fc_spmv_info(fc_problem pb, int32_t* group, int32_t* lattice);
 /* FP32 copy (FC_STORE_F32): the diagonally scaled inverse D^1/2 P_B D^1/2
  * (D = diag(A) on the block) rounded to FP32, kept for the blocks where a
  * Cholesky factorisation of the rounded matrix shows it positive definite

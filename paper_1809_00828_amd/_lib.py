@@ -37,7 +37,7 @@ EXPORTS = [
     "fc_model_forward", "fc_model_loss_grad", "fc_model_train", "fc_model_destroy",
     "fc_learned_attach", "fc_coarse_grid", "fc_coarse_channels", "fc_coarse_restrict",
     "fc_coarse_prolong", "fc_coarse_apply", "fc_learned_stats", "fc_learned_snapshots",
-    "fc_learned_validate", "fc_precond_lowprec_info",
+    "fc_learned_validate", "fc_precond_lowprec_info", "fc_spmv_info",
 ]
 
 
@@ -109,6 +109,7 @@ def load():
         "fc_precond_build": [vp, P(PrecondOpts), vp, P(vp)],
         "fc_precond_info": [vp, P(i64), P(i64), P(i64), P(i64)],
         "fc_precond_lowprec_info": [vp, P(i64), P(i64)],
+        "fc_spmv_info": [vp, P(i32), P(i32)],
         "fc_get_block_inverse": [vp, i64, vp],
         "fc_apply_M": [vp, dp, dp, vp],
         "fc_pcg_solve": [vp, vp, dp, dp, P(SolveOpts), P(SolveInfo), vp],
@@ -284,8 +285,11 @@ class Problem:
             m, bd = C.c_int32(), C.c_int32()
             _check(load().fc_problem_info(self._h, C.byref(n), C.byref(nnzb), C.byref(nel),
                                           C.byref(m), C.byref(bd)))
+            g, lat = C.c_int32(), C.c_int32()
+            _check(load().fc_spmv_info(self._h, C.byref(g), C.byref(lat)))
             self._info = {"n_dofs": n.value, "nnzb": nnzb.value, "n_el": nel.value,
-                          "m": m.value, "bsr_dim": bd.value}
+                          "m": m.value, "bsr_dim": bd.value, "spmv_group": g.value,
+                          "lattice_columns": bool(lat.value)}
         return self._info
 
     @property

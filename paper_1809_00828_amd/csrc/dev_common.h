@@ -77,6 +77,43 @@ __device__ __forceinline__ double sum_partials(const double* part, int n,
   return block_sum(t, lds);
 }
 
+// Lattice box of row node `row`: for every direction the range of lattice
+// indices of the functions whose support meets the row's support (a vertex
+// index reaches one cell to each side, an interior index only its cell).
+struct RowBox {
+  int lo[3], len[3];
+};
+
+__device__ __forceinline__ RowBox row_box(int64_t row, const LatticeInfo lat) {
+  RowBox b;
+  int64_t r = row;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    b.lo[k] = 0;
+    b.len[k] = 1;
+    if (k < lat.dim) {
+      const int g = (int)(r % lat.n1);
+      r /= lat.n1;
+      if (g % lat.p == 0) {
+        const int lo = max(0, g - lat.p), hi = min(lat.n1 - 1, g + lat.p);
+        b.lo[k] = lo;
+        b.len[k] = hi - lo + 1;
+      } else {
+        b.lo[k] = (g / lat.p) * lat.p;
+        b.len[k] = lat.p + 1;
+      }
+    }
+  }
+  return b;
+}
+
+// column of the k-th block of the row (first direction fastest)
+__device__ __forceinline__ int lattice_col(const RowBox& b, int k, int n1) {
+  const int kx = k % b.len[0], r = k / b.len[0];
+  const int ky = r % b.len[1], kz = r / b.len[1];
+  return (b.lo[0] + kx) + n1 * ((b.lo[1] + ky) + n1 * (b.lo[2] + kz));
+}
+
 __device__ __forceinline__ float bf16_to_f32(uint16_t v) {
   return __uint_as_float(((uint32_t)v) << 16);
 }

@@ -103,6 +103,7 @@ static fc_status upload_system(const HostSystem& S, hipStream_t stream, fc_probl
   pb->eta = S.eta;
   pb->elem_nodes_host = S.elem_nodes;
   FC_HIP(launch_diag(*pb, stream));
+  if (S.dim > 0) FC_HIP(spmv_enable_lattice(pb->A, S.dim, S.p * S.n + 1, S.p, stream));
   FC_HIP(spmv_autotune(pb->A, stream));
   FC_HIP(hipStreamSynchronize(stream));
   *out = pb.release();
@@ -495,6 +496,13 @@ fc_status fc_precond_build(fc_problem pb, const fc_precond_opts* opts, void* str
   for (int64_t k = 0; k < nb; ++k) nd += drop[k];
   pc->n_dropped = nd;
   *out = pc.release();
+  return FC_OK;
+}
+
+fc_status fc_spmv_info(fc_problem pb, int32_t* group, int32_t* lattice) {
+  if (!pb) return FC_E_ARG;
+  if (group) *group = pb->A.group;
+  if (lattice) *lattice = pb->A.lat.dim > 0 ? 1 : 0;
   return FC_OK;
 }
 

@@ -44,12 +44,21 @@ struct CgScalars {
   double* history;  // optional per-iteration criterion
 };
 
+// Tensor-product lattice behind a matrix assembled from a problem
+// description (dim = 0 otherwise): the block columns of every row are the
+// lattice box spanned by the supports through the row's node, so they can
+// be computed instead of read.
+struct LatticeInfo {
+  int32_t dim = 0, n1 = 0, p = 0;
+};
+
 struct DeviceBsr {
   int32_t bdim = 1;
   int64_t n_rows = 0;      // block rows
   int64_t nnzb = 0;
   int32_t max_row = 0;     // longest block row
   int32_t group = 0;       // SpMV lanes per block row chosen at set-up (0: heuristic)
+  LatticeInfo lat;         // set when the columns were verified to be the lattice box
   int32_t* rowptr = nullptr;
   int32_t* col = nullptr;
   double* val = nullptr;   // row-SoA layout
@@ -111,6 +120,10 @@ hipError_t launch_spmv_f32(const DeviceBsr& A, const double* x, double* y,
                            hipStream_t s, const double* rs);
 // time the SpMV group widths on A and keep the fastest in A.group
 hipError_t spmv_autotune(DeviceBsr& A, hipStream_t s);
+// verify on the device that A's columns are the lattice boxes of (dim, n1,
+// p); if so record it in A.lat, so the SpMV computes columns instead of
+// reading them
+hipError_t spmv_enable_lattice(DeviceBsr& A, int dim, int n1, int p, hipStream_t s);
 
 hipError_t launch_block_extract(const fc_problem_s& pb, const fc_precond_s& pc,
                                 hipStream_t s);

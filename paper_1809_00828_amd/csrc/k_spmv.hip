@@ -26,12 +26,13 @@ namespace fc {
 
 // rs (may be null): y_i *= rs_i, for the scaled FP32 copy D^{-1/2} A D^{-1/2}
 // applied to x already multiplied by D^{1/2}.
-template <int B, int G, typename T>
+// kLat: columns computed from the lattice box (col is not read).
+template <int B, int G, typename T, bool kLat>
 __global__ __launch_bounds__(256) void k_spmv_bsr(
     const int32_t* __restrict__ rowptr, const int32_t* __restrict__ col,
     const T* __restrict__ val, const double* __restrict__ x,
     double* __restrict__ y, int64_t n_rows, const CgScalars* __restrict__ sc,
-    double* __restrict__ partial, const double* __restrict__ rs) {
+    double* __restrict__ partial, const double* __restrict__ rs, const LatticeInfo lat) {
   constexpr int BB = B * B;
   constexpr int RPW = 256 / G;   // rows per tile
   __shared__ double lds[16];
@@ -49,6 +50,8 @@ __global__ __launch_bounds__(256) void k_spmv_bsr(
     const int64_t base = rowptr[row];
     const int L = rowptr[row + 1] - (int32_t)base;
     const T* v = val + base * BB;
+    RowBox box;
+    if constexpr (kLat) box = row_box(row, lat);
     double acc[B];
     float accf[B];
 #pragma unroll
@@ -67,7 +70,10 @@ __global__ __launch_bounds__(256) void k_spmv_bsr(
       for (int u = 0; u < U; ++u) {
         const int ku = k + u * G;
         const bool on = ku < L;
-        c[u] = on ? __builtin_nontemporal_load(col + base + ku) : -1;
+        if constexpr (kLat)
+          c[u] = on ? lattice_col(box, ku, lat.n1) : -1;
+        else
+          c[u] = on ? __builtin_nontemporal_load(col + base + ku) : -1;
 #pragma unroll
         for (int e = 0; e < BB; ++e)
           a[u][e] = on ? __builtin_nontemporal_load(v + (int64_t)e * L + ku) : T(0);
@@ -149,11 +155,17 @@ static hipError_t spmv_dispatch(const DeviceBsr& A, const T* val, const double* 
   const int64_t nt = num_tiles(A);
   if (nt == 0) return hipSuccess;
   const int64_t nb = partial ? fused_grid(A) : nt;
+  static const bool lat_allowed = env_int("FC_SPMV_LATTICE", 1) != 0;
+  const bool lat = lat_allowed && A.lat.dim > 0;
   dim3 grid((unsigned)nb), block(256);
-#define FC_SPMV_CASE(GG)                                                           \
-  case GG:                                                                         \
-    hipLaunchKernelGGL((k_spmv_bsr<B, GG, T>), grid, block, 0, s, A.rowptr, A.col, \
-                       val, x, y, A.n_rows, sc, partial, rs);                     \
+#define FC_SPMV_CASE(GG)                                                                  \
+  case GG:                                                                                \
+    if (lat)                                                                              \
+      hipLaunchKernelGGL((k_spmv_bsr<B, GG, T, true>), grid, block, 0, s, A.rowptr, A.col, \
+                         val, x, y, A.n_rows, sc, partial, rs, A.lat);                    \
+    else                                                                                  \
+      hipLaunchKernelGGL((k_spmv_bsr<B, GG, T, false>), grid, block, 0, s, A.rowptr,       \
+                         A.col, val, x, y, A.n_rows, sc, partial, rs, A.lat);             \
     break;
   switch (G) {
     FC_SPMV_CASE(8)
@@ -187,6 +199,46 @@ hipError_t launch_spmv_f32(const DeviceBsr& A, const double* x, double* y, hipSt
 }
 
 int spmv_num_blocks(const DeviceBsr& A) { return (int)fused_grid(A); }
+
+// mismatches between stored columns and lattice boxes (counted with an
+// atomic only where one occurs)
+__global__ void k_check_lattice(const int32_t* __restrict__ rowptr, const int32_t* __restrict__ col,
+                                int64_t n_rows, const LatticeInfo lat,
+                                unsigned long long* __restrict__ bad) {
+  for (int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; row < n_rows;
+       row += (int64_t)gridDim.x * blockDim.x) {
+    const RowBox b = row_box(row, lat);
+    const int64_t base = rowptr[row];
+    const int L = rowptr[row + 1] - (int32_t)base;
+    int miss = L != b.len[0] * b.len[1] * b.len[2];
+    for (int k = 0; k < L && !miss; ++k) miss = col[base + k] != lattice_col(b, k, lat.n1);
+    if (miss) atomicAdd(bad, 1ull);
+  }
+}
+
+hipError_t spmv_enable_lattice(DeviceBsr& A, int dim, int n1, int p, hipStream_t s) {
+  A.lat = LatticeInfo{};
+  if (dim < 1 || dim > 3 || p < 1 || A.n_rows == 0) return hipSuccess;
+  int64_t nodes = 1;
+  for (int k = 0; k < dim; ++k) nodes *= n1;
+  if (nodes != A.n_rows) return hipSuccess;
+  unsigned long long* bad = nullptr;
+  hipError_t e = hipMalloc(&bad, sizeof(*bad));
+  if (e != hipSuccess) return e;
+  unsigned long long hbad = 1;
+  const LatticeInfo lat{dim, n1, p};
+  e = hipMemsetAsync(bad, 0, sizeof(*bad), s);
+  if (e == hipSuccess) {
+    hipLaunchKernelGGL(k_check_lattice, dim3(2048), dim3(256), 0, s, A.rowptr, A.col, A.n_rows,
+                       lat, bad);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) e = hipMemcpyAsync(&hbad, bad, sizeof(hbad), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  (void)hipFree(bad);
+  if (e == hipSuccess && hbad == 0) A.lat = lat;
+  return e;
+}
 
 // Group width of this matrix: time every width on the matrix itself
 // (x = 0, so only the memory traffic counts) and keep the fastest.
