@@ -31,7 +31,7 @@ HBM_PEAK_GBS = 8000.0
 # counter passes (FETCH_SIZE, WRITE_SIZE), scaled by what the same counters
 # read for a plain 4 GiB copy (profiles/pcg_fp64_elastic32_p3_hbm_counters.md);
 # to be re-measured whenever one of these kernels changes.
-TRAFFIC = {"spmv": None, "schwarz": 4.6884e9}
+TRAFFIC = {"spmv": 8.3620e9, "schwarz": 4.6881e9}
 METRIC = "DOF·iter/s and time-to-1e-8 residual: mixed/learned vs plain FP64 PCG"
 
 
@@ -375,7 +375,7 @@ def main():
     gbs_spmv = spmv_b / (ms_spmv * 1e-3) / 1e9
     total_dof_iters = n * sum(iters)
     on_bench_workload = not args.small
-    k_spmv = {"bound": "hbm", "kernel": "k_spmv_bsr<3,64,double> (SpMV q = A p)",
+    k_spmv = {"bound": "hbm", "kernel": "k_spmv_bsr<3,64,double,lattice> (SpMV q = A p)",
               "achieved": gbs_spmv, "peak": HBM_PEAK_GBS, "unit": "GB/s",
               "frac": gbs_spmv / HBM_PEAK_GBS,
               "traffic": TRAFFIC["spmv"] if on_bench_workload else None,
