@@ -66,8 +66,12 @@ __global__ __launch_bounds__(256) void k_schwarz_large(
 // m > 64, symmetric layout staged through LDS: chunks of kRows stored rows
 // are loaded with coalesced non-temporal loads (every thread its own entry),
 // written to LDS, and the rotated entries are read back from LDS, so HBM
-// and L2 see each stored entry exactly once.
-constexpr int kStageRows = 8;
+// and L2 see each stored entry exactly once.  A chunk is 16 KB of LDS:
+// 8 rows of FP64 or 16 of FP32 (twice the loads in flight per barrier).
+template <typename T>
+struct StageRows {
+  static constexpr int value = sizeof(T) == 8 ? 8 : 16;
+};
 
 template <typename T>
 __global__ __launch_bounds__(256) void k_schwarz_sym_staged(
@@ -77,6 +81,7 @@ __global__ __launch_bounds__(256) void k_schwarz_sym_staged(
     const CgScalars* __restrict__ sc, double* __restrict__ y, int64_t n_blocks,
     const int32_t* __restrict__ list, const int32_t* __restrict__ skip) {
   using A = typename Acc<T>::type;
+  constexpr int kStageRows = StageRows<T>::value;
   __shared__ double rB[256];
   __shared__ T tile[kStageRows][256];
   if (sc && sc->done) return;
