@@ -28,11 +28,20 @@ the definition the GPU solver follows):
   * correction: z = S r + gamma P_c y with y the network output and
     gamma = (y . P_c^T r) / (y . A_c y), A_c = P_c^T A P_c the Galerkin
     coarse operator, gamma = 0 when the quotient is not positive finite;
-  * flexible CG: beta = -(z_new . A p) / (p . A p), so p stays A-orthogonal
-    to the previous direction when the preconditioner changes per step;
-  * training targets: the error e = x* - x_k minus the Schwarz apply
-    z_k = S r_k, sampled at the coarse vertices, zero where the vertex
-    function touches no physical material, scaled to unit RMS.
+  * flexible CG, truncated to m directions: the new direction is z_new
+    made A-orthogonal to the last m directions,
+    p = z_new - sum_j (z_new . A p_j) / (p_j . A p_j) p_j, since a
+    preconditioner that changes from step to step (a network is nonlinear
+    in r) breaks the short recurrence of CG; m = 1 is the Polak-Ribiere
+    form beta = -(z_new . A p) / (p . A p);
+  * training targets, at the coarse vertices, zero where the vertex
+    function touches no physical material, scaled to unit RMS: the error
+    e = x* - x_k minus the Schwarz apply z_k = S r_k, sampled (kind
+    "e-Sr"); the error itself (kind "e"); or the coarse Galerkin
+    projection of the error (kind "coarse"): the y minimising
+    ||e - P_c y||_A over the material vertices, the solution of
+    A_c y = P_c^T r there (r = A e), a plain function of the network's
+    residual input.
 Parameters are one flat vector: per convolution W[co][ci][27] then b[co],
 in the order enc0a enc0b enc1a enc1b enc2a enc2b bota botb up2a up2b up1a
 up1b up0a up0b head; the tap index is dz*9 + dy*3 + dx (offsets -1..1).
@@ -380,12 +389,32 @@ def snapshot_target(desc, e, z, eta, kind="e-Sr"):
     return unit_rms(sample(desc, v) * vertex_mask(desc, eta))
 
 
-def fcg(A, b, S, P, Ac, correction, tol=1e-8, maxit=300000):
-    """Flexible CG (one A-orthogonalisation, the Polak-Ribiere form) with
-    the preconditioner z = S r + gamma P y, y = correction(r) on the coarse
-    vertices and gamma = (y . P^T r) / (y . A_c y) the energy-optimal step
-    along P y (zero when that is not a positive finite number).  Residual
-    stop ||r|| / ||b|| <= tol; x_0 = 0."""
+def coarse_projection(desc, A, r, eta):
+    """Coarse Galerkin projection of the error behind the residual r: on the
+    material vertices (vertex_mask) y solves A_c y = P_c^T r, elsewhere
+    y = 0.  P_c y is then the A-orthogonal projection of e = A^{-1} r onto
+    the span of the material coarse vertex functions."""
+    m = vertex_mask(desc, eta).ravel() > 0
+    Ac = coarse_operator(desc, A)
+    rc = restrict(desc, r).ravel()
+    y = np.zeros(rc.size)
+    y[m] = np.linalg.solve(Ac[np.ix_(m, m)], rc[m])
+    return y.reshape(vertex_mask(desc, eta).shape)
+
+
+def coarse_projection_target(desc, A, r, eta):
+    """Training target of kind "coarse": coarse_projection scaled to unit
+    RMS."""
+    return unit_rms(coarse_projection(desc, A, r, eta))
+
+
+def fcg(A, b, S, P, Ac, correction, tol=1e-8, maxit=300000, m=1):
+    """Flexible CG with the preconditioner z = S r + gamma P y,
+    y = correction(r) on the coarse vertices and
+    gamma = (y . P^T r) / (y . A_c y) the energy-optimal step along P y
+    (zero when that is not a positive finite number).  Each new direction is
+    made A-orthogonal to the last m directions (m = 1: the Polak-Ribiere
+    form).  Residual stop ||r|| / ||b|| <= tol; x_0 = 0."""
     n = b.size
     x = np.zeros(n)
     r = b.copy()
@@ -409,6 +438,7 @@ def fcg(A, b, S, P, Ac, correction, tol=1e-8, maxit=300000):
     status = NOTCONV
     if b0 == 0.0:
         return x, {"iters": 0, "status": OK, "res": res, "gamma": gammas}
+    kept = []          # (p_j, A p_j, p_j . A p_j) of the last m directions
     while it < maxit:
         q = A @ p
         pq = float(p @ q)
@@ -423,9 +453,12 @@ def fcg(A, b, S, P, Ac, correction, tol=1e-8, maxit=300000):
         if res[-1] <= tol:
             status = OK
             break
+        kept.append((p, q, pq))
+        if len(kept) > m:
+            kept.pop(0)
         z = precond(r)
-        beta = -float(z @ q) / pq
         rz = float(r @ z)
-        p = z + beta * p
+        p = z.copy()
+        for pj, qj, pqj in kept:
+            p -= (float(z @ qj) / pqj) * pj
     return x, {"iters": it, "status": status, "res": res, "gamma": gammas}
-

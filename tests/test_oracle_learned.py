@@ -283,3 +283,80 @@ def test_fcg_with_exact_coarse_solve():
     assert i2["iters"] < i0["iters"], (i2["iters"], i0["iters"])
     xs = PCG.direct_solve(A, b)
     assert PCG.energy_error(A, xs, x2) <= 1e-6 * np.sqrt(xs @ (A @ xs))
+
+
+def test_fcg_truncated_with_fixed_preconditioner_is_pcg():
+    """With a fixed SPD preconditioner the older directions are already
+    A-orthogonal to the new one, so keeping m > 1 of them changes nothing:
+    FCG(m) reproduces PCG."""
+    desc, sysm, S = _small_system()
+    A, b = sysm["A"], sysm["b"]
+    P = L.prolong_matrix(desc)
+    Ac = L.coarse_operator(desc, A)
+    G = desc["n"] // 2 + 1
+    x0, i0 = PCG.pcg(A, b, S, tol=1e-8, stop="residual")
+    for m in (2, 8):
+        x1, i1 = L.fcg(A, b, S, P, Ac, lambda r: np.zeros(G ** 3), tol=1e-8, m=m)
+        assert i1["status"] == PCG.OK and abs(i1["iters"] - i0["iters"]) <= 1, (m, i1["iters"])
+        assert PCG.energy_error(A, x0, x1) <= 1e-8
+
+
+def _nonlinear_problem(n=14, k=4, seed=5):
+    rng = np.random.default_rng(seed)
+    Q = rng.standard_normal((n, n))
+    A = Q @ Q.T + 0.05 * np.eye(n)
+    S = np.diag(1.0 / np.diag(A))
+    P = rng.standard_normal((n, k))
+    Ac = P.T @ A @ P
+    b = rng.standard_normal(n)
+
+    def corr(r):
+        v = P.T @ r
+        return np.tanh(3.0 * v / np.linalg.norm(v)) + 0.3 * np.sign(v) * v ** 2
+    return A, b, S, P, Ac, corr
+
+
+def test_fcg_full_orthogonalisation_terminates_with_nonlinear_preconditioner():
+    """Keeping every direction makes them all A-orthogonal whatever the
+    preconditioner does, so x_k minimises the energy error over their span
+    and the solve ends within n steps on an n-unknown system; the
+    Polak-Ribiere form FCG(1) does not, with this nonlinear correction."""
+    A, b, S, P, Ac, corr = _nonlinear_problem()
+    n = b.size
+    x, info = L.fcg(A, b, S, P, Ac, corr, tol=1e-10, maxit=n, m=n)
+    assert info["status"] == PCG.OK, info["res"][-3:]
+    xs = np.linalg.solve(A, b)
+    assert np.linalg.norm(x - xs) <= 1e-7 * np.linalg.norm(xs)
+    _, info1 = L.fcg(A, b, S, P, Ac, corr, tol=1e-10, maxit=n, m=1)
+    assert info1["status"] != PCG.OK
+
+
+def test_coarse_projection_is_the_energy_projection_of_the_error():
+    """P_c y of the "coarse" target is the A-orthogonal projection of e onto
+    the material coarse vertex functions: the remaining error is
+    A-orthogonal to each of them (checked with the fine A and P_c, not
+    A_c), and any other coarse correction leaves more energy, by exactly
+    the energy of the difference (Pythagoras)."""
+    desc = fcgen.porous_poisson_3d(3, n=4, p=2, n_voids=3, rmin=0.1, rmax=0.18)
+    sysm = ASM.assemble(desc)
+    A, eta = sysm["A"], sysm["eta"]
+    rng = np.random.default_rng(21)
+    e = rng.standard_normal(A.shape[0])
+    r = A @ e
+    y = L.coarse_projection(desc, A, r, eta).ravel()
+    m = (L.vertex_mask(desc, eta) > 0).ravel()
+    assert 0 < m.sum() < m.size or m.all()
+    assert np.all(y[~m] == 0.0)
+    Pm = L.prolong_matrix(desc)[:, m]
+    w = L.prolong_matrix(desc) @ y
+    resid = Pm.T @ (A @ (e - w))
+    assert np.linalg.norm(resid) <= 1e-9 * np.linalg.norm(Pm.T @ (A @ e))
+    energy = lambda v: float(v @ (A @ v))
+    d = np.zeros_like(y)
+    d[m] = rng.standard_normal(m.sum())
+    wd = L.prolong_matrix(desc) @ d
+    lhs = energy(e - w - wd)
+    assert np.isclose(lhs, energy(e - w) + energy(wd), rtol=1e-9)
+    t = L.coarse_projection_target(desc, A, r, eta).ravel()
+    assert np.isclose(np.sqrt(np.mean(t ** 2)), 1.0)
+    assert np.allclose(t * np.sqrt(np.mean(y ** 2)), y)
