@@ -167,6 +167,7 @@ def learned_bench(fc, args):
     import fcgen
     from paper_1809_00828_amd import learned as LR
     ch = (8, 16, 32, 32)
+    m = args.learned_fcg_m
     t0 = time.perf_counter()
     descs = [fcgen.porous_poisson_3d(1000 + i, n=48, p=2) for i in range(args.learned_train)]
     xin, t, G = LR.training_set(descs, args.learned_pairs // args.learned_train,
@@ -174,7 +175,7 @@ def learned_bench(fc, args):
     t_data = time.perf_counter() - t0
     model = fc.Model(fcgen.unet_init(ch, 2, seed=0), ch)
     t0 = time.perf_counter()
-    hist = LR.train(model, xin, t, G, epochs=args.learned_epochs, batch=8, lr=3e-4)
+    hist = LR.train(model, xin, t, G, epochs=args.learned_epochs, batch=8, lr=args.learned_lr)
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t0
     log(f"learned: {xin.shape[0]} pairs in {t_data:.0f} s, {args.learned_epochs} epochs in "
@@ -192,10 +193,10 @@ def learned_bench(fc, args):
     for name, mode in (("plain", "f64"), ("learned", "learned")):
         if mode == "learned":
             pc.attach(model)
-        fc.pcg_solve(pb, pc, b, x, tol=args.tol, stop="residual", mode=mode)  # warm
+        fc.pcg_solve(pb, pc, b, x, tol=args.tol, stop="residual", mode=mode, fcg_m=m)  # warm
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        info = fc.pcg_solve(pb, pc, b, x, tol=args.tol, stop="residual", mode=mode)
+        info = fc.pcg_solve(pb, pc, b, x, tol=args.tol, stop="residual", mode=mode, fcg_m=m)
         torch.cuda.synchronize()
         wall = (time.perf_counter() - t0) * 1e3
         runs[name] = {"iters": info["iters"], "time_to_tol_ms": wall,
@@ -203,11 +204,11 @@ def learned_bench(fc, args):
                       "rel_res_true": info["rel_res_true"]}
         log(f"learned: {name} {info['iters']} iterations, {wall:.0f} ms")
     st = pc.learned_stats()
-    use, ip, il = pc.validate(b, tol=args.tol)
+    use, ip, il = pc.validate(b, tol=args.tol, fcg_m=m)
     x.zero_()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    info = fc.pcg_solve(pb, pc, b, x, tol=args.tol, stop="residual", mode="learned")
+    info = fc.pcg_solve(pb, pc, b, x, tol=args.tol, stop="residual", mode="learned", fcg_m=m)
     torch.cuda.synchronize()
     wall = (time.perf_counter() - t0) * 1e3
     log(f"learned: validated solve ({'network kept' if use else 'plain fallback'}) "
@@ -216,9 +217,11 @@ def learned_bench(fc, args):
         "workload": "3D finite cell Poisson, 64^3 cells, p=2, 64 spherical voids, alpha=1e-10 "
                     "(2.1M unknowns); network trained on 48^3-cell cubes",
         "n_dofs": pb.n, "coarse_grid": pc.coarse_grid(), "train_coarse_grid": G,
+        "fcg_directions": m,
         "params": model.n_params,
         "train": {"problems": len(descs), "pairs": int(args.learned_pairs // args.learned_train)
                   * len(descs), "target": args.learned_target, "epochs": args.learned_epochs,
+                  "lr": args.learned_lr,
                   "loss_first": float(hist[0]), "loss_last": float(hist[-1]),
                   "data_s": t_data, "train_s": t_train},
         "plain": runs["plain"], "learned": runs["learned"],
@@ -303,8 +306,13 @@ def main():
                     help="skip the learned coarse-correction comparison")
     ap.add_argument("--learned-train", type=int, default=8, help="training problems (48^3)")
     ap.add_argument("--learned-pairs", type=int, default=2000, help="training pairs in total")
-    ap.add_argument("--learned-epochs", type=int, default=15)
-    ap.add_argument("--learned-target", default="e-Sr", choices=["e-Sr", "e"])
+    ap.add_argument("--learned-epochs", type=int, default=20)
+    ap.add_argument("--learned-lr", type=float, default=1e-3)
+    ap.add_argument("--learned-target", default="coarse", choices=["coarse", "e-Sr", "e"],
+                    help="training target: the coarse Galerkin projection of the error, the "
+                         "error left by the Schwarz apply, or the error")
+    ap.add_argument("--learned-fcg-m", type=int, default=64,
+                    help="directions kept by the learned flexible CG")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first copy 4 GiB three times with a plain copy kernel, the reference "
                          "for scaling hardware byte counters")

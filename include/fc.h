@@ -228,9 +228,11 @@ fc_status fc_apply_M(fc_precond pc, const double* r_dev, double* z_dev,
  *                FC_MODE_S_F32 / FC_MODE_S_BF16: one PCG run with the FP64
  *                matrix and the FP32 / BF16 copy of the local inverses as the
  *                preconditioner (positive semi-definite however rounded);
- *                FC_MODE_LEARNED: flexible CG (beta = -(z_new, A p)/(p, A p))
- *                with z = S r + gamma P_c y, y the network attached with
- *                fc_learned_attach (see there); always the residual stop
+ *                FC_MODE_LEARNED: flexible CG with z = S r + gamma P_c y,
+ *                y the network attached with fc_learned_attach (see
+ *                there); each new direction is z made A-orthogonal to the
+ *                last fcg_m directions (fcg_m <= 1: the Polak-Ribiere form
+ *                beta = -(z_new, A p)/(p, A p)); always the residual stop
  *                ||r_i|| / ||b||
  *   check_every  iterations between host checks of the device stop flag
  *   history_dev  optional device buffer of maxit+1 doubles receiving the
@@ -239,7 +241,13 @@ fc_status fc_apply_M(fc_precond pc, const double* r_dev, double* z_dev,
  *                bracket the SpMV and Schwarz block-product kernels of every
  *                k-th step with events on the solver stream;
  *                fc_solve_info.ms_spmv / ms_schwarz receive their summed
- *                times over the n_timed bracketed steps */
+ *                times over the n_timed bracketed steps
+ *   fcg_m        FC_MODE_LEARNED: directions kept by the flexible CG, 0 or
+ *                1 (one) to 64; the solver holds 2 fcg_m vectors of n_dofs
+ *                doubles for them.  A network is nonlinear in r, so the
+ *                preconditioner changes from step to step, and one
+ *                A-orthogonalisation no longer keeps the directions
+ *                conjugate (FC_E_ARG above 64) */
 enum { FC_STOP_PRECOND = 0, FC_STOP_RESIDUAL = 1 };
 enum { FC_MODE_F64 = 0, FC_MODE_IR_F32 = 1, FC_MODE_IR_BF16 = 2, FC_MODE_S_F32 = 3,
        FC_MODE_S_BF16 = 4, FC_MODE_LEARNED = 5 };
@@ -252,6 +260,7 @@ typedef struct {
   double inner_tol;
   double* history_dev;
   int32_t timing;
+  int32_t fcg_m;
 } fc_solve_opts;
 
 typedef struct {
@@ -380,14 +389,15 @@ fc_status fc_coarse_prolong(fc_precond pc, const float* y_dev, double gamma, dou
 fc_status fc_coarse_apply(fc_precond pc, const float* y_dev, double* v_dev, double* gamma,
                           void* stream);
 /* Plain Schwarz-PCG judges the network: solve A x = b to tol (relative
- * residual) once with FC_MODE_F64 and once with FC_MODE_LEARNED, keep the
+ * residual) once with FC_MODE_F64 and once with FC_MODE_LEARNED (fcg_m
+ * kept directions, as in fc_solve_opts), keep the
  * network for later FC_MODE_LEARNED solves of this preconditioner only if
  * the learned run converges in less device time, else those solves run
  * plain PCG (fc_solve_info.fallbacks = 1).  *use_network receives the
  * decision; plain / learned (may be NULL) the two runs' infos.
  * fc_learned_attach resets the decision to "use". */
 fc_status fc_learned_validate(fc_precond pc, const double* b_dev, double tol,
-                              int32_t* use_network, fc_solve_info* plain,
+                              int32_t fcg_m, int32_t* use_network, fc_solve_info* plain,
                               fc_solve_info* learned, void* stream);
 /* Corrections applied and dropped since fc_learned_attach. */
 fc_status fc_learned_stats(fc_precond pc, int64_t* n_apply, int64_t* n_drop);
@@ -397,6 +407,12 @@ fc_status fc_learned_stats(fc_precond pc, int64_t* n_apply, int64_t* n_drop);
  * target to t_dev + i*G^3:
  *   kind 0: mask * (x_star - x_k - S r_k) at the coarse vertices,
  *   kind 1: mask * (x_star - x_k),
+ *   kind 2: the coarse Galerkin projection of the error: y with
+ *           A_c y = P_c^T r_k on the material vertices (mask 1), 0
+ *           elsewhere, so that P_c y is the A-orthogonal projection of
+ *           x_star - x_k onto those coarse vertex functions (solved by
+ *           Jacobi-preconditioned CG on A_c to 1e-8; FC_E_NOTCONV or
+ *           FC_E_BREAKDOWN if that fails; x_star is not read),
  * scaled to unit RMS (x_star: the converged solution, device).  Stops
  * early at convergence to tol (relative residual); *n_taken receives the
  * number of pairs written. */

@@ -65,7 +65,7 @@ class PrecondOpts(C.Structure):
 class SolveOpts(C.Structure):
     _fields_ = [("tol", C.c_double), ("maxit", C.c_int64), ("stop", C.c_int32),
                 ("mode", C.c_int32), ("check_every", C.c_int32), ("inner_tol", C.c_double),
-                ("history_dev", C.c_void_p), ("timing", C.c_int32)]
+                ("history_dev", C.c_void_p), ("timing", C.c_int32), ("fcg_m", C.c_int32)]
 
 
 class TrainOpts(C.Structure):
@@ -131,7 +131,7 @@ def load():
         "fc_coarse_apply": [vp, dp, dp, P(C.c_double), vp],
         "fc_learned_stats": [vp, P(i64), P(i64)],
         "fc_learned_snapshots": [vp, dp, dp, i32, vp, i32, C.c_double, dp, dp, P(i32), vp],
-        "fc_learned_validate": [vp, dp, C.c_double, P(i32), P(SolveInfo), P(SolveInfo), vp],
+        "fc_learned_validate": [vp, dp, C.c_double, i32, P(i32), P(SolveInfo), P(SolveInfo), vp],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -387,12 +387,12 @@ class Precond:
                                        C.byref(g), C.c_void_p(_stream(stream))))
         return g.value
 
-    def validate(self, b, tol=1e-8, stream=None):
+    def validate(self, b, tol=1e-8, fcg_m=1, stream=None):
         """fc_learned_validate: returns (use_network, plain info, learned info)."""
         use = C.c_int32()
         ip, il = SolveInfo(), SolveInfo()
         _check(load().fc_learned_validate(self._h, C.c_void_p(_dptr(b)), float(tol),
-                                          C.byref(use), C.byref(ip), C.byref(il),
+                                          int(fcg_m), C.byref(use), C.byref(ip), C.byref(il),
                                           C.c_void_p(_stream(stream))))
         return bool(use.value), _info_dict(ip), _info_dict(il)
 
@@ -408,7 +408,7 @@ class Precond:
         k = C.c_int32()
         _check(load().fc_learned_snapshots(
             self._h, C.c_void_p(_dptr(b)), C.c_void_p(_dptr(x_star)), int(it.size), _np_ptr(it),
-            {"e-Sr": 0, "e": 1}[kind], float(tol), C.c_void_p(_fptr(xin)), C.c_void_p(_fptr(t)),
+            {"e-Sr": 0, "e": 1, "coarse": 2}[kind], float(tol), C.c_void_p(_fptr(xin)), C.c_void_p(_fptr(t)),
             C.byref(k), C.c_void_p(_stream(stream))))
         return k.value
 
@@ -420,11 +420,11 @@ class Precond:
 
 def pcg_solve(problem: Problem, precond: Precond, b, x, tol=1e-10, maxit=300000,
               stop="precond", mode="f64", check_every=16, inner_tol=1e-4, history=None,
-              timing=False, stream=None, raise_on_error=False):
+              timing=False, stream=None, raise_on_error=False, fcg_m=1):
     """Run fc_pcg_solve; returns the info dict (status included)."""
     o = SolveOpts(float(tol), int(maxit), STOP[stop], MODE[mode], int(check_every),
                   float(inner_tol), C.c_void_p(_dptr(history)) if history is not None else None,
-                  int(timing))
+                  int(timing), int(fcg_m))
     info = SolveInfo()
     st = load().fc_pcg_solve(problem._h, precond._h, C.c_void_p(_dptr(b)), C.c_void_p(_dptr(x)),
                              C.byref(o), C.byref(info), C.c_void_p(_stream(stream)))

@@ -58,13 +58,20 @@ struct SolverWs {
   int key_chunk = 0, key_prec = -1;
   const void* key_b = nullptr;
   std::vector<hipEvent_t> tev;  // timing mode: 4 events per step of a chunk
+  // learned mode with m > 1 kept directions (flexible CG, FCG(m))
+  double* ring = nullptr;         // [2][ring_cap][n]: p_j, then A p_j
+  double* ring_part = nullptr;    // [ring_cap][ring_blocks] dot partials
+  struct FcgRing* fr = nullptr;
+  int ring_cap = 0;
 };
 
 void solver_ws_destroy(SolverWs* w) {
   if (!w) return;
   if (w->exec) (void)hipGraphExecDestroy(w->exec);
   if (w->graph) (void)hipGraphDestroy(w->graph);
-  for (auto* p : {w->r, w->z, w->p, w->q, w->t, w->d, w->ro, w->partial}) if (p) (void)hipFree(p);
+  for (auto* p : {w->r, w->z, w->p, w->q, w->t, w->d, w->ro, w->partial, w->ring, w->ring_part})
+    if (p) (void)hipFree(p);
+  if (w->fr) (void)hipFree(w->fr);
   if (w->sc) (void)hipFree(w->sc);
   if (w->host) (void)hipHostFree(w->host);
   for (auto& e : w->ev) if (e) (void)hipEventDestroy(e);
@@ -292,6 +299,136 @@ __global__ __launch_bounds__(256) void k_cg_p(const double* __restrict__ z, doub
   if (i < n) p[i] = fma(beta, p[i], z[i]);
 }
 
+// ---- flexible CG keeping m > 1 directions (learned mode)
+// The direction of every step (p, A p, (p, A p)) goes to slot count mod m
+// of a ring; the next direction is z made A-orthogonal to every kept one,
+// p = z - sum_j (z, A p_j) / (p_j, A p_j) p_j (slots in index order).
+constexpr int kMaxFcg = 64;
+constexpr int kRingElems = 8;   // unknowns per thread of the dot pass
+struct FcgRing {
+  int64_t count;                // directions taken so far
+  double pq[kMaxFcg];           // (p_j, A p_j) per slot
+  double beta[kMaxFcg];         // -(z, A p_j) / (p_j, A p_j) per slot
+};
+
+inline unsigned ring_blocks(int64_t n) {
+  return (unsigned)((n + 256 * kRingElems - 1) / (256 * kRingElems));
+}
+
+__global__ void k_fcg_reset(FcgRing* fr) { fr->count = 0; }
+
+// Store the step's p and q = A p in slot count mod m and form, per
+// workgroup (one contiguous chunk of unknowns), the partial (z, A p_j) of
+// every kept slot j.
+__global__ __launch_bounds__(256) void k_fcg_keep_dots(
+    const double* __restrict__ p, const double* __restrict__ q, const double* __restrict__ z,
+    int64_t n, int m, double* __restrict__ ring, double* __restrict__ part, FcgRing* fr,
+    const CgScalars* __restrict__ sc) {
+  __shared__ double lds[16];
+  if (sc->done) return;
+  const int64_t cnt0 = fr->count;
+  const int slot = (int)(cnt0 % m);
+  const int cnt = (int)(cnt0 + 1 < m ? cnt0 + 1 : m);
+  double* P = ring + (int64_t)slot * n;
+  const double* Q = ring + (int64_t)m * n;
+  double* Qs = ring + ((int64_t)m + slot) * n;
+  const int64_t base = (int64_t)blockIdx.x * (256 * kRingElems) + threadIdx.x;
+  double zv[kRingElems], qv[kRingElems];
+#pragma unroll
+  for (int e = 0; e < kRingElems; ++e) {
+    const int64_t i = base + (int64_t)e * 256;
+    zv[e] = 0.0;
+    qv[e] = 0.0;
+    if (i < n) {
+      zv[e] = z[i];
+      qv[e] = q[i];
+      P[i] = p[i];
+      Qs[i] = qv[e];
+    }
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) fr->pq[slot] = sc->pq;
+  for (int j = 0; j < cnt; ++j) {
+    const double* Qj = Q + (int64_t)j * n;
+    double d = 0.0;
+#pragma unroll
+    for (int e = 0; e < kRingElems; ++e) {
+      const int64_t i = base + (int64_t)e * 256;
+      if (i < n) d = fma(zv[e], j == slot ? qv[e] : Qj[i], d);
+    }
+    d = block_sum(d, lds);
+    if (threadIdx.x == 0) part[(int64_t)j * gridDim.x + blockIdx.x] = d;
+  }
+}
+
+// Stop test as in k_cg_beta_flex (residual stop; (r, z) gains the
+// correction's gamma (y . P_c^T r)), then beta_j for every kept slot.
+__global__ __launch_bounds__(1024) void k_fcg_beta(const double* __restrict__ partial, int np,
+                                                   const double* __restrict__ part, int nb,
+                                                   int m, FcgRing* fr, CgScalars* sc,
+                                                   const LearnScalars* __restrict__ ls) {
+  __shared__ double lds[16];
+  if (sc->done) return;
+  double ta = 0.0, tb = 0.0, tc = 0.0;
+  for (int i = threadIdx.x; i < np; i += blockDim.x) {
+    ta += partial[i];
+    tb += partial[np + i];
+    tc += partial[2 * np + i];
+  }
+  double rz = block_sum(ta, lds);
+  const double zz = block_sum(tb, lds);
+  const double rr = block_sum(tc, lds);
+  const int64_t cnt0 = fr->count;
+  const int cnt = (int)(cnt0 + 1 < m ? cnt0 + 1 : m);
+  bool bad = false;
+  for (int j = 0; j < cnt; ++j) {
+    double t = 0.0;
+    for (int i = threadIdx.x; i < nb; i += blockDim.x) t += part[(int64_t)j * nb + i];
+    const double d = block_sum(t, lds);
+    if (threadIdx.x == 0) {
+      const double b = -d / fr->pq[j];
+      fr->beta[j] = b;
+      bad = bad || !(b == b) || isinf(b);
+    }
+  }
+  if (threadIdx.x == 0) {
+    fr->count = cnt0 + 1;
+    const double g = ls->gamma;
+    if (g != 0.0) rz += g * ls->yrc;
+    const double crit = sqrt(rr) / sc->crit0;
+    sc->zz = zz;
+    sc->rr = rr;
+    sc->crit = crit;
+    if (sc->history) sc->history[sc->iter] = crit;
+    if (!(crit == crit) || !(rz == rz) || isinf(rz) || bad) {
+      sc->done = 4;
+    } else if (crit <= sc->tol) {
+      sc->done = 1;
+    } else if (sc->iter >= sc->maxit) {
+      sc->done = 2;
+    }
+    sc->rz = rz;
+  }
+}
+
+// p = z + sum_j beta_j p_j over the kept slots
+__global__ __launch_bounds__(256) void k_fcg_dir(const double* __restrict__ z,
+                                                 double* __restrict__ p,
+                                                 const double* __restrict__ ring, int64_t n,
+                                                 int m, const FcgRing* __restrict__ fr,
+                                                 const CgScalars* __restrict__ sc) {
+  __shared__ double beta[kMaxFcg];
+  if (sc->done) return;
+  const int cnt = (int)(fr->count < m ? fr->count : m);
+  for (int j = threadIdx.x; j < cnt; j += blockDim.x) beta[j] = fr->beta[j];
+  __syncthreads();
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    double v = z[i];
+    for (int j = 0; j < cnt; ++j) v = fma(beta[j], ring[(int64_t)j * n + i], v);
+    p[i] = v;
+  }
+}
+
 // c = a * b elementwise (skipped once the stop flag is set)
 __global__ void k_mul(const double* __restrict__ a, const double* __restrict__ b,
                       double* __restrict__ c, int64_t n, const CgScalars* __restrict__ sc) {
@@ -393,6 +530,31 @@ static fc_status ensure_ws(fc_precond_s& pc, SolverWs** out) {
   return FC_OK;
 }
 
+// Ring of m kept directions for the learned mode's FCG(m); a larger ring
+// replaces the old one and drops the captured chunk that used it.
+static fc_status ensure_ring(SolverWs& w, int m) {
+  if (m <= 1 || w.ring_cap >= m) return FC_OK;
+  if (w.exec) {
+    FC_HIP(hipGraphExecDestroy(w.exec));
+    w.exec = nullptr;
+  }
+  if (w.graph) {
+    FC_HIP(hipGraphDestroy(w.graph));
+    w.graph = nullptr;
+  }
+  w.key_prec = -1;
+  if (w.ring) FC_HIP(hipFree(w.ring));
+  if (w.ring_part) FC_HIP(hipFree(w.ring_part));
+  w.ring = nullptr;
+  w.ring_part = nullptr;
+  w.ring_cap = 0;
+  FC_HIP(hipMalloc(&w.ring, (size_t)2 * m * w.n * sizeof(double)));
+  FC_HIP(hipMalloc(&w.ring_part, (size_t)m * ring_blocks(w.n) * sizeof(double)));
+  if (!w.fr) FC_HIP(hipMalloc(&w.fr, sizeof(FcgRing)));
+  w.ring_cap = m;
+  return FC_OK;
+}
+
 // FC_CG_SPLIT_DOT=0 fuses (p, A p) into the SpMV (one partial per SpMV
 // workgroup); the default computes it in a separate pass over p and q.
 static bool split_dot() {
@@ -408,7 +570,7 @@ static bool split_dot() {
 // local inverses.
 static hipError_t enqueue_steps(fc_precond_s& pc, SolverWs& w, double* x, int chunk, int precA,
                                 int precS, hipStream_t s, hipEvent_t* tev = nullptr,
-                                CoarseCtx* learn = nullptr, int every = 1) {
+                                CoarseCtx* learn = nullptr, int every = 1, int fcg_m = 1) {
   fc_problem_s& pb = *pc.pb;
   const int64_t n = pb.n_dofs;
   for (int it = 0; it < chunk; ++it) {
@@ -447,7 +609,22 @@ static hipError_t enqueue_steps(fc_precond_s& pc, SolverWs& w, double* x, int ch
     if (e != hipSuccess) return e;
     if (tev_it && (e = hipEventRecord(tev[4 * it + 3], s)) != hipSuccess) return e;
     const unsigned pg = pull_grid(n);
-    if (learn) {
+    const bool ring = learn && fcg_m > 1;
+    if (ring) {
+      // FCG(m): Schwarz pull, correction, then the new direction made
+      // A-orthogonal to the m kept ones
+      hipLaunchKernelGGL(k_cg_pull<false>, dim3(pg), dim3(kVecThreads), 0, s, pc.y, pc.inv_ptr,
+                         pc.inv_idx, pc.fallback, pc.bdim, n, x, w.r, w.p, w.q, w.z, w.partial,
+                         w.sc);
+      if ((e = coarse_correct(*learn, w.r, w.z, nullptr, w.sc, s)) != hipSuccess) return e;
+      const unsigned rb = ring_blocks(n);
+      hipLaunchKernelGGL(k_fcg_keep_dots, dim3(rb), dim3(256), 0, s, w.p, w.q, w.z, n, fcg_m,
+                         w.ring, w.ring_part, w.fr, w.sc);
+      hipLaunchKernelGGL(k_fcg_beta, dim3(1), dim3(1024), 0, s, w.partial, (int)pg, w.ring_part,
+                         (int)rb, fcg_m, w.fr, w.sc, learn->ls);
+      hipLaunchKernelGGL(k_fcg_dir, dim3(pg), dim3(kVecThreads), 0, s, w.z, w.p, w.ring, n, fcg_m,
+                         w.fr, w.sc);
+    } else if (learn) {
       hipLaunchKernelGGL(k_cg_pull<true>, dim3(pg), dim3(kVecThreads), 0, s, pc.y, pc.inv_ptr,
                          pc.inv_idx, pc.fallback, pc.bdim, n, x, w.r, w.p, w.q, w.z, w.partial,
                          w.sc);
@@ -460,7 +637,8 @@ static hipError_t enqueue_steps(fc_precond_s& pc, SolverWs& w, double* x, int ch
                          w.sc);
       hipLaunchKernelGGL(k_cg_beta, dim3(1), dim3(1024), 0, s, w.partial, (int)pg, w.sc);
     }
-    hipLaunchKernelGGL(k_cg_p, dim3(nblk(n)), dim3(kVecThreads), 0, s, w.z, w.p, n, w.sc);
+    if (!ring)
+      hipLaunchKernelGGL(k_cg_p, dim3(nblk(n)), dim3(kVecThreads), 0, s, w.z, w.p, n, w.sc);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
@@ -475,6 +653,7 @@ struct CoreArgs {
   int stop, precA, precS, timing, chunk;
   double* history;
   CoarseCtx* learn = nullptr;   // learned correction (flexible CG) when set
+  int fcg_m = 1;                // directions kept by the flexible CG
 };
 
 struct CoreResult {
@@ -501,7 +680,7 @@ static fc_status ensure_events(SolverWs& w, int chunk) {
 // this before their first event so the timed region does not include it.
 static fc_status ensure_graph(fc_precond_s& pc, SolverWs& w, const CoreArgs& a, hipStream_t s) {
   const int chunk = a.chunk > 0 ? a.chunk : 16;
-  const int prec = a.precA * 4 + a.precS + (a.learn ? 16 : 0);
+  const int prec = a.precA * 4 + a.precS + (a.learn ? 16 + 32 * a.fcg_m : 0);
   if (w.exec && w.key[0] == a.x && w.key_chunk == chunk && w.key_prec == prec) return FC_OK;
   if (w.exec) {
     FC_HIP(hipGraphExecDestroy(w.exec));
@@ -513,7 +692,8 @@ static fc_status ensure_graph(fc_precond_s& pc, SolverWs& w, const CoreArgs& a, 
   }
   w.key_prec = -1;
   FC_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-  hipError_t e = enqueue_steps(pc, w, a.x, chunk, a.precA, a.precS, s, nullptr, a.learn);
+  hipError_t e = enqueue_steps(pc, w, a.x, chunk, a.precA, a.precS, s, nullptr, a.learn, 1,
+                               a.fcg_m);
   hipGraph_t g = nullptr;
   hipError_t e2 = hipStreamEndCapture(s, &g);
   if (e != hipSuccess || e2 != hipSuccess) {
@@ -547,6 +727,7 @@ static fc_status pcg_core(fc_precond_s& pc, SolverWs& w, const CoreArgs& a, Core
   FC_HIP(launch_schwarz_phase1(pc, a.precS, w.r, nullptr, nullptr, s));
   FC_HIP(launch_schwarz_pull(pc, w.r, w.z, s));
   if (a.learn) FC_HIP(coarse_correct(*a.learn, w.r, w.z, nullptr, w.sc, s));
+  if (a.learn && a.fcg_m > 1) hipLaunchKernelGGL(k_fcg_reset, dim3(1), dim3(1), 0, s, w.fr);
   hipLaunchKernelGGL(k_copy, dim3(1024), dim3(256), 0, s, w.z, w.p, n);
   hipLaunchKernelGGL(k_cg_start, dim3(kRedBlocks), dim3(256), 0, s, w.r, w.z, n, w.partial,
                      w.sc);
@@ -561,7 +742,8 @@ static fc_status pcg_core(fc_precond_s& pc, SolverWs& w, const CoreArgs& a, Core
     const int every = std::max(1, a.timing);
     int64_t iter_before = 0;
     for (;;) {
-      FC_HIP(enqueue_steps(pc, w, a.x, chunk, a.precA, a.precS, s, w.tev.data(), a.learn, every));
+      FC_HIP(enqueue_steps(pc, w, a.x, chunk, a.precA, a.precS, s, w.tev.data(), a.learn, every,
+                           a.fcg_m));
       ++launched;
       FC_HIP(hipMemcpyAsync(w.host, w.sc, sizeof(CgScalars), hipMemcpyDeviceToHost, s));
       FC_HIP(hipStreamSynchronize(s));
@@ -659,12 +841,19 @@ fc_status pcg_solve(fc_precond_s& pc, const double* b, double* x, const fc_solve
     if (pc.coarse->enabled) learn = pc.coarse;
     else fallbacks = 1;
   }
+  const int fcg_m = o.fcg_m > 1 ? o.fcg_m : 1;
+  if (fcg_m > kMaxFcg) {
+    set_error("fc_pcg_solve: fcg_m above 64");
+    return FC_E_ARG;
+  }
+  if (learn) FC_TRY_ST(ensure_ring(w, fcg_m));
   if (o.mode == FC_MODE_F64 || o.mode == FC_MODE_S_F32 || o.mode == FC_MODE_S_BF16 ||
       o.mode == FC_MODE_LEARNED) {
     // one PCG run with the FP64 matrix (and a low-precision S if asked, or
     // flexible CG with the learned correction)
     const int stop = o.mode == FC_MODE_LEARNED ? (int)FC_STOP_RESIDUAL : o.stop;
-    CoreArgs a{b, x, o.tol, o.maxit, stop, 0, precS, o.timing, o.check_every, o.history_dev, learn};
+    CoreArgs a{b, x, o.tol, o.maxit, stop, 0, precS, o.timing, o.check_every, o.history_dev, learn,
+               fcg_m};
     if (!o.timing) FC_TRY_ST(ensure_graph(pc, w, a, s));
     FC_HIP(hipEventRecord(w.ev[1], s));
     FC_TRY_ST(pcg_core(pc, w, a, &acc, s));
@@ -765,7 +954,7 @@ extern "C" fc_status fc_learned_snapshots(fc_precond pc, const double* b, const 
                                           int32_t n_snap, const int32_t* iters, int32_t kind,
                                           double tol, float* xin, float* t, int32_t* n_taken,
                                           void* stream) {
-  if (!pc || !b || !xs || n_snap < 1 || !iters || !xin || !t || (kind != 0 && kind != 1)) {
+  if (!pc || !b || !xs || n_snap < 1 || !iters || !xin || !t || kind < 0 || kind > 2) {
     set_error("fc_learned_snapshots: invalid arguments");
     return FC_E_ARG;
   }
@@ -805,20 +994,22 @@ extern "C" fc_status fc_learned_snapshots(fc_precond pc, const double* b, const 
   const int64_t nv = c.nvox;
   int j = 0;
   int64_t it = 0;
-  auto take = [&]() -> hipError_t {
-    hipError_t e = coarse_snapshot(c, w.r, xs, x, kind == 0 ? w.z : nullptr,
-                                   xin + (int64_t)j * 2 * nv, t + (int64_t)j * nv, s);
+  auto take = [&]() -> fc_status {
+    float* xo = xin + (int64_t)j * 2 * nv;
+    float* to = t + (int64_t)j * nv;
     ++j;
-    return e;
+    if (kind == 2) return coarse_snapshot_projection(c, w.r, xo, to, 1e-8, 20000, s);
+    FC_HIP(coarse_snapshot(c, w.r, xs, x, kind == 0 ? w.z : nullptr, xo, to, s));
+    return FC_OK;
   };
-  if (iters[0] == 0) FC_HIP(take());
+  if (iters[0] == 0) FC_TRY_ST(take());
   while (j < n_snap) {
     FC_HIP(enqueue_steps(*pc, w, x, 1, 0, 0, s));
     ++it;
     FC_HIP(hipMemcpyAsync(w.host, w.sc, sizeof(CgScalars), hipMemcpyDeviceToHost, s));
     FC_HIP(hipStreamSynchronize(s));
     if (w.host->iter != it) break;   // stopped before this step (flag set earlier)
-    if (iters[j] == it) FC_HIP(take());
+    if (iters[j] == it) FC_TRY_ST(take());
     if (w.host->done != 0) break;
   }
   FC_HIP(hipEventRecord(w.ev[3], s));
@@ -829,8 +1020,9 @@ extern "C" fc_status fc_learned_snapshots(fc_precond pc, const double* b, const 
 }
 
 extern "C" fc_status fc_learned_validate(fc_precond pc, const double* b, double tol,
-                                         int32_t* use_network, fc_solve_info* plain,
-                                         fc_solve_info* learned, void* stream) {
+                                         int32_t fcg_m, int32_t* use_network,
+                                         fc_solve_info* plain, fc_solve_info* learned,
+                                         void* stream) {
   if (!pc || !b || !pc->coarse || !pc->coarse->model || !(tol > 0.0)) {
     set_error("fc_learned_validate: needs a preconditioner with an attached network, b, tol > 0");
     return FC_E_ARG;
@@ -844,6 +1036,7 @@ extern "C" fc_status fc_learned_validate(fc_precond pc, const double* b, double 
   pc->coarse->enabled = 1;
   const fc_status s1 = pcg_solve(*pc, b, x, o, &ip, user);
   o.mode = FC_MODE_LEARNED;
+  o.fcg_m = fcg_m;
   const fc_status s2 = pcg_solve(*pc, b, x, o, &il, user);
   (void)hipStreamSynchronize(user);
   (void)hipFree(x);

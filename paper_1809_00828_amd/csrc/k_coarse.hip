@@ -243,6 +243,171 @@ __global__ __launch_bounds__(kT) void k_target(const double* __restrict__ xs,
   for (int64_t i = threadIdx.x; i < nvox; i += blockDim.x) t[i] = (float)(raw[i] * scale);
 }
 
+// ---- Jacobi-preconditioned CG on A_c restricted to the material vertices
+// (y = 0 on the others), for the projection targets.  Vectors x, r, z, p, v
+// of G^3 values each; the diagonal is the centre tap of the stencil.
+__device__ __forceinline__ double stencil_apply(const double* __restrict__ Ac,
+                                                const double* __restrict__ v, int G,
+                                                int64_t nvox, int64_t a) {
+  const int ax = (int)(a % G), ay = (int)((a / G) % G), az = (int)(a / ((int64_t)G * G));
+  double s = 0.0;
+  for (int o = 0; o < 27; ++o) {
+    const int bx = ax + o % 3 - 1, by = ay + (o / 3) % 3 - 1, bz = az + o / 9 - 1;
+    if (bx < 0 || bx >= G || by < 0 || by >= G || bz < 0 || bz >= G) continue;
+    s = fma(Ac[(int64_t)o * nvox + a], v[bx + (int64_t)G * (by + (int64_t)G * bz)], s);
+  }
+  return s;
+}
+
+__device__ __forceinline__ double jacobi_of(const double* __restrict__ Ac,
+                                            const float* __restrict__ mask, int64_t nvox,
+                                            int64_t a, double ra) {
+  const double d = Ac[13 * nvox + a];
+  return (mask[a] > 0.f && d > 0.0) ? ra / d : 0.0;
+}
+
+__global__ __launch_bounds__(kT) void k_ccg_init(const double* __restrict__ Ac,
+                                                 const float* __restrict__ mask,
+                                                 const double* __restrict__ rhs, int64_t nvox,
+                                                 double* __restrict__ v5,
+                                                 double* __restrict__ partial, CoarseCg* cs) {
+  __shared__ double lds[16];
+  __shared__ int flag;
+  double* x = v5;
+  double* r = v5 + nvox;
+  double* z = v5 + 2 * nvox;
+  double* p = v5 + 3 * nvox;
+  double s1 = 0.0, s2 = 0.0;
+  for (int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; a < nvox;
+       a += (int64_t)gridDim.x * blockDim.x) {
+    const double ra = mask[a] > 0.f ? rhs[a] : 0.0;
+    const double za = jacobi_of(Ac, mask, nvox, a, ra);
+    x[a] = 0.0;
+    r[a] = ra;
+    z[a] = za;
+    p[a] = za;
+    s1 = fma(ra, za, s1);
+    s2 = fma(ra, ra, s2);
+  }
+  s1 = block_sum(s1, lds);
+  s2 = block_sum(s2, lds);
+  if (threadIdx.x == 0) {
+    partial[blockIdx.x] = s1;
+    partial[gridDim.x + blockIdx.x] = s2;
+  }
+  if (!last_block(&cs->ticket[0], gridDim.x, &flag)) return;
+  const double rz = sum_partials(partial, gridDim.x, lds);
+  const double rr = sum_partials(partial + gridDim.x, gridDim.x, lds);
+  if (threadIdx.x == 0) {
+    cs->rz = rz;
+    cs->rr0 = rr;
+    cs->rr = rr;
+    cs->iters = 0;
+    cs->done = rr > 0.0 ? 0 : 1;
+  }
+}
+
+// v = A_c p on the material vertices and (p, v); the last workgroup sets
+// alpha (breakdown unless (p, v) > 0)
+__global__ __launch_bounds__(kT) void k_ccg_apply(const double* __restrict__ Ac,
+                                                  const float* __restrict__ mask, int G,
+                                                  int64_t nvox, double* __restrict__ v5,
+                                                  double* __restrict__ partial, CoarseCg* cs) {
+  __shared__ double lds[16];
+  __shared__ int flag;
+  if (cs->done) return;
+  const double* p = v5 + 3 * nvox;
+  double* v = v5 + 4 * nvox;
+  double s = 0.0;
+  for (int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; a < nvox;
+       a += (int64_t)gridDim.x * blockDim.x) {
+    const double va = mask[a] > 0.f ? stencil_apply(Ac, p, G, nvox, a) : 0.0;
+    v[a] = va;
+    s = fma(p[a], va, s);
+  }
+  s = block_sum(s, lds);
+  if (threadIdx.x == 0) partial[blockIdx.x] = s;
+  if (!last_block(&cs->ticket[1], gridDim.x, &flag)) return;
+  const double pq = sum_partials(partial, gridDim.x, lds);
+  if (threadIdx.x == 0) {
+    cs->iters += 1;
+    if (!(pq > 0.0) || !(cs->rz > 0.0)) cs->done = 3;
+    else cs->alpha = cs->rz / pq;
+  }
+}
+
+// x += alpha p, r -= alpha v, z = r / diag; the last workgroup sets beta
+// and tests ||r|| / ||r_0|| <= tol
+__global__ __launch_bounds__(kT) void k_ccg_update(const double* __restrict__ Ac,
+                                                   const float* __restrict__ mask, int64_t nvox,
+                                                   double* __restrict__ v5, double tol,
+                                                   double* __restrict__ partial, CoarseCg* cs) {
+  __shared__ double lds[16];
+  __shared__ int flag;
+  if (cs->done) return;
+  const double alpha = cs->alpha;
+  double* x = v5;
+  double* r = v5 + nvox;
+  double* z = v5 + 2 * nvox;
+  const double* p = v5 + 3 * nvox;
+  const double* v = v5 + 4 * nvox;
+  double s1 = 0.0, s2 = 0.0;
+  for (int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; a < nvox;
+       a += (int64_t)gridDim.x * blockDim.x) {
+    x[a] = fma(alpha, p[a], x[a]);
+    const double ra = fma(-alpha, v[a], r[a]);
+    const double za = jacobi_of(Ac, mask, nvox, a, ra);
+    r[a] = ra;
+    z[a] = za;
+    s1 = fma(ra, za, s1);
+    s2 = fma(ra, ra, s2);
+  }
+  s1 = block_sum(s1, lds);
+  s2 = block_sum(s2, lds);
+  if (threadIdx.x == 0) {
+    partial[blockIdx.x] = s1;
+    partial[gridDim.x + blockIdx.x] = s2;
+  }
+  if (!last_block(&cs->ticket[2], gridDim.x, &flag)) return;
+  const double rz = sum_partials(partial, gridDim.x, lds);
+  const double rr = sum_partials(partial + gridDim.x, gridDim.x, lds);
+  if (threadIdx.x == 0) {
+    cs->beta = rz / cs->rz;
+    cs->rz = rz;
+    cs->rr = rr;
+    if (!(rr == rr)) cs->done = 3;
+    else if (sqrt(rr) <= tol * sqrt(cs->rr0)) cs->done = 1;
+  }
+}
+
+__global__ void k_ccg_dir(int64_t nvox, double* __restrict__ v5, const CoarseCg* cs) {
+  if (cs->done) return;
+  const double beta = cs->beta;
+  const double* z = v5 + 2 * nvox;
+  double* p = v5 + 3 * nvox;
+  for (int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; a < nvox;
+       a += (int64_t)gridDim.x * blockDim.x)
+    p[a] = fma(beta, p[a], z[a]);
+}
+
+// t = x at unit RMS
+__global__ __launch_bounds__(kT) void k_unit_rms(const double* __restrict__ x, int64_t nvox,
+                                                 float* __restrict__ t,
+                                                 double* __restrict__ partial, LearnScalars* ls) {
+  __shared__ double lds[16];
+  __shared__ int flag;
+  double ss = 0.0;
+  for (int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; a < nvox;
+       a += (int64_t)gridDim.x * blockDim.x)
+    ss = fma(x[a], x[a], ss);
+  ss = block_sum(ss, lds);
+  if (threadIdx.x == 0) partial[blockIdx.x] = ss;
+  if (!last_block(&ls->ticket[3], gridDim.x, &flag)) return;
+  const double nrm2 = sum_partials(partial, gridDim.x, lds);
+  const double scale = nrm2 > 0.0 ? sqrt((double)nvox / nrm2) : 0.0;
+  for (int64_t i = threadIdx.x; i < nvox; i += blockDim.x) t[i] = (float)(x[i] * scale);
+}
+
 inline unsigned blocks_for(int64_t n) { return (unsigned)((n + kT - 1) / kT); }
 // grid of the reducing kernels: at most kCoarsePartials workgroups
 inline unsigned red_blocks(int64_t n) {
@@ -297,11 +462,51 @@ hipError_t coarse_snapshot(CoarseCtx& c, const double* r, const double* xs, cons
   return hipGetLastError();
 }
 
+fc_status coarse_snapshot_projection(CoarseCtx& c, const double* r, float* xin_out,
+                                     float* t_out, double tol, int64_t maxit, hipStream_t s) {
+  const int64_t nv = c.nvox;
+  if (!c.cg) FC_HIP(hipMalloc(&c.cg, 5 * nv * sizeof(double)));
+  if (!c.cs) {
+    FC_HIP(hipMalloc(&c.cs, sizeof(CoarseCg)));
+    FC_HIP(hipMemsetAsync(c.cs, 0, sizeof(CoarseCg), s));
+  }
+  FC_HIP(coarse_restrict(c, r, xin_out, nullptr, s));
+  FC_HIP(hipMemcpyAsync(xin_out + nv, c.xin + nv, nv * sizeof(float), hipMemcpyDeviceToDevice,
+                        s));
+  const unsigned nb = red_blocks(nv);
+  hipLaunchKernelGGL(k_ccg_init, dim3(nb), dim3(kT), 0, s, c.Ac, c.mask, c.rc, nv, c.cg,
+                     c.partial, c.cs);
+  FC_HIP(hipGetLastError());
+  constexpr int kChunk = 32;
+  CoarseCg h{};
+  for (int64_t it = 0;; it += kChunk) {
+    for (int k = 0; k < kChunk; ++k) {
+      hipLaunchKernelGGL(k_ccg_apply, dim3(nb), dim3(kT), 0, s, c.Ac, c.mask, c.G, nv, c.cg,
+                         c.partial, c.cs);
+      hipLaunchKernelGGL(k_ccg_update, dim3(nb), dim3(kT), 0, s, c.Ac, c.mask, nv, c.cg, tol,
+                         c.partial, c.cs);
+      hipLaunchKernelGGL(k_ccg_dir, dim3(nb), dim3(kT), 0, s, nv, c.cg, c.cs);
+    }
+    FC_HIP(hipGetLastError());
+    FC_HIP(hipMemcpyAsync(&h, c.cs, sizeof(h), hipMemcpyDeviceToHost, s));
+    FC_HIP(hipStreamSynchronize(s));
+    if (h.done != 0 || h.iters >= maxit) break;
+  }
+  if (h.done != 1) {
+    set_error(h.done == 3 ? "coarse projection target: CG breakdown on A_c"
+                          : "coarse projection target: CG on A_c did not converge");
+    return h.done == 3 ? FC_E_BREAKDOWN : FC_E_NOTCONV;
+  }
+  hipLaunchKernelGGL(k_unit_rms, dim3(nb), dim3(kT), 0, s, c.cg, nv, t_out, c.partial, c.ls);
+  FC_HIP(hipGetLastError());
+  return FC_OK;
+}
+
 void coarse_destroy(CoarseCtx* c) {
   if (!c) return;
   c->ws.release();
   for (void* p : {(void*)c->Ac, (void*)c->xin, (void*)c->mask, (void*)c->rc, (void*)c->partial,
-                  (void*)c->ls})
+                  (void*)c->ls, (void*)c->cg, (void*)c->cs})
     if (p) (void)hipFree(p);
   delete c;
 }

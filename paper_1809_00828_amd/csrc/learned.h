@@ -86,8 +86,18 @@ struct CoarseCtx {
   fc_model_s* model = nullptr;
   int enabled = 1;           // 0: validation found the network does not pay
   NetWs ws;                  // inference activations (batch 1)
+  double* cg = nullptr;      // [5][nvox] coarse CG vectors x, r, z, p, A_c p
+  struct CoarseCg* cs = nullptr;
 };
 constexpr int kCoarsePartials = 2048;
+
+// Scalars of the Jacobi-preconditioned CG on A_c (training targets).
+struct CoarseCg {
+  double rz, rr0, rr, alpha, beta;
+  int64_t iters;
+  int32_t done;              // 0 running, 1 converged, 3 breakdown
+  uint32_t ticket[3];
+};
 
 // Build the coarse context of a preconditioner's problem (transfers,
 // Galerkin operator by probing with 27 coloured prolongations, eta and
@@ -114,6 +124,12 @@ hipError_t coarse_correct(CoarseCtx& c, const double* r, double* z, const double
 // t = mask * sample(xs - x - [z]) at unit RMS
 hipError_t coarse_snapshot(CoarseCtx& c, const double* r, const double* xs, const double* x,
                            const double* z, float* xin_out, float* t_out, hipStream_t s);
+// training pair with the coarse Galerkin projection of the error as the
+// target: xin from r, t = y at unit RMS, A_c y = P_c^T r on the material
+// vertices (y = 0 elsewhere), solved by Jacobi-preconditioned CG to a
+// relative residual of tol (synchronises; FC_E_NOTCONV past maxit)
+fc_status coarse_snapshot_projection(CoarseCtx& c, const double* r, float* xin_out,
+                                     float* t_out, double tol, int64_t maxit, hipStream_t s);
 
 }  // namespace fc
 

@@ -203,13 +203,33 @@ def test_snapshots_match_oracle(torch, name):
             got_in = xin[j].cpu().numpy()
             assert np.abs(got_in - ref_in).max() <= 1e-5 * max(1.0, np.abs(ref_in).max()), (kind, it)
             assert np.abs(t[j].cpu().numpy() - ref_t).max() <= 1e-5 * np.abs(ref_t).max(), (kind, it)
+    # the coarse Galerkin projection of the error, solved on the device by
+    # CG on A_c to a relative residual of 1e-8: error at most kappa * 1e-8
+    msk = L.vertex_mask(desc, s["eta"]).ravel() > 0
+    Acm = Ac[np.ix_(msk, msk)]
+    dm = np.sqrt(np.diag(Acm))
+    lam = np.linalg.eigvalsh(Acm / dm[:, None] / dm[None, :])
+    tol_c = max(1e-5, 10.0 * (lam[-1] / lam[0]) * 1e-8)
+    k = pc.snapshots(bd, torch.as_tensor(xs, device="cuda"), iters, xin, t, kind="coarse",
+                     tol=1e-12)
+    assert k == len(iters)
+    for j, it in enumerate(iters):
+        xk, _ = PCG.pcg(A, b, S, tol=0.0, maxit=it, stop="residual")
+        rk = b - A @ xk
+        ref_in = L.network_input(desc, rk, s["eta"]).reshape(2, -1)
+        ref_t = L.coarse_projection_target(desc, A, rk, s["eta"]).ravel()
+        got_in = xin[j].cpu().numpy()
+        assert np.abs(got_in - ref_in).max() <= 1e-5 * max(1.0, np.abs(ref_in).max()), ("coarse", it)
+        err = np.abs(t[j].cpu().numpy() - ref_t).max() / np.abs(ref_t).max()
+        assert err <= tol_c, ("coarse", it, err, tol_c)
 
 
-def _learned_solve(torch, pb, pc, tol=1e-8, mode="learned"):
+def _learned_solve(torch, pb, pc, tol=1e-8, mode="learned", fcg_m=1):
     b = torch.empty(pb.n, dtype=torch.float64, device="cuda")
     pb.rhs(b)
     x = torch.zeros_like(b)
-    info = fc.pcg_solve(pb, pc, b, x, tol=tol, stop="residual", mode=mode, check_every=8)
+    info = fc.pcg_solve(pb, pc, b, x, tol=tol, stop="residual", mode=mode, check_every=8,
+                        fcg_m=fcg_m)
     torch.cuda.synchronize()
     return x.cpu().numpy(), info
 
@@ -231,6 +251,48 @@ def test_learned_fcg_with_zero_network_reproduces_pcg(torch):
     A = s["A"]
     en = np.sqrt(xo @ (A @ xo))
     assert np.sqrt((xl - xp) @ (A @ (xl - xp))) <= 1e-7 * en
+
+
+def test_learned_fcg_m_with_zero_network_reproduces_pcg(torch):
+    """Keeping 8 directions changes nothing for a fixed preconditioner."""
+    print("[learned] zero network, fcg_m 8", flush=True)
+    desc, s, S, P, Ac = coarse_case("pois8_p2")
+    _, pb, pc = _lib_case("pois8_p2")
+    m = fc.Model(np.zeros(L.n_params(CH), np.float32), CH)
+    pc.attach(m)
+    xl, il = _learned_solve(torch, pb, pc, fcg_m=8)
+    xp, ip = _learned_solve(torch, pb, pc, mode="f64")
+    assert il["status"] == "OK" and abs(il["iters"] - ip["iters"]) <= 1
+    A = s["A"]
+    en = np.sqrt(xp @ (A @ xp))
+    assert np.sqrt((xl - xp) @ (A @ (xl - xp))) <= 1e-7 * en
+
+
+@pytest.mark.parametrize("name,fcg_m", [("pois8_p2", 4), ("pois8_p2", 64), ("pois6_p3", 16)])
+def test_learned_fcg_m_matches_oracle(torch, name, fcg_m):
+    """A seeded network inside flexible CG keeping fcg_m directions: GPU
+    against the oracle's FCG(m) with the same network."""
+    print(f"[learned] oracle fcg({fcg_m}) {name}", flush=True)
+    desc, s, S, P, Ac = coarse_case(name)
+    _, pb, pc = _lib_case(name)
+    theta = fcgen.unet_init(CH, 2, seed=7)
+    m = fc.Model(theta, CH)
+    pc.attach(m)
+    xl, il = _learned_solve(torch, pb, pc, fcg_m=fcg_m)
+    th = _oracle_theta(theta)
+
+    def corr(r):
+        xin = L.network_input(desc, r, s["eta"])[None]
+        return L.forward(th, xin, CH).ravel()
+
+    xo, io = L.fcg(s["A"], s["b"], S, P, Ac, corr, tol=1e-8, m=fcg_m)
+    assert il["status"] == "OK" and io["status"] == PCG.OK
+    assert abs(il["iters"] - io["iters"]) <= max(2, 0.1 * io["iters"]), (il["iters"], io["iters"])
+    assert il["rel_res_true"] <= 1.5e-8
+    A = s["A"]
+    xs = PCG.direct_solve(A, s["b"])
+    en = np.sqrt(xs @ (A @ xs))
+    assert np.sqrt((xl - xs) @ (A @ (xl - xs))) <= 1e-5 * en
 
 
 @pytest.mark.parametrize("name", list(COARSE_PROBLEMS))
@@ -265,15 +327,16 @@ def test_learned_fcg_matches_oracle_fcg(torch, name):
 
 
 def test_trained_network_gain_and_fallback(torch):
-    """Train on pairs from three 16^3 problems, then let plain Schwarz-PCG
-    judge the network on a fourth: the learned solve is kept only where it
+    """Train on pairs (coarse Galerkin projections of the error) from three
+    16^3 problems, then let plain Schwarz-PCG judge the network, inside
+    flexible CG keeping 16 directions, on a fourth: the learned solve is kept only where it
     is faster, and otherwise FC_MODE_LEARNED runs exactly the plain solve.
     Prints what the trained network gains (or loses) in iterations and time."""
     from paper_1809_00828_amd import learned as LR
     print("[learned] gain test: data", flush=True)
     descs = [fcgen.porous_poisson_3d(500 + i, n=16, p=2, n_voids=24, rmin=0.04, rmax=0.1)
              for i in range(3)]
-    xin, t, G = LR.training_set(descs, 80, kind="e")
+    xin, t, G = LR.training_set(descs, 80, kind="coarse")
     assert xin.shape == (240, 2, G ** 3) and G == 9
     m = fc.Model(fcgen.unet_init(CH, 2, seed=1), CH)
     hist = LR.train(m, xin, t, G, epochs=30, batch=8, lr=3e-4)
@@ -285,13 +348,13 @@ def test_trained_network_gain_and_fallback(torch):
     pc.attach(m)
     b = torch.empty(pb.n, dtype=torch.float64, device="cuda")
     pb.rhs(b)
-    use, ip, il = pc.validate(b, tol=1e-8)
+    use, ip, il = pc.validate(b, tol=1e-8, fcg_m=16)
     print(f"[learned] plain {ip['iters']} it {ip['ms_solve']:.2f} ms, learned {il['iters']} it "
           f"{il['ms_solve']:.2f} ms, network kept: {use}", flush=True)
     assert ip["status"] == "OK" and il["status"] == "OK"
     assert use == (il["ms_solve"] < ip["ms_solve"])
     x = torch.zeros_like(b)
-    info = fc.pcg_solve(pb, pc, b, x, tol=1e-8, stop="residual", mode="learned")
+    info = fc.pcg_solve(pb, pc, b, x, tol=1e-8, stop="residual", mode="learned", fcg_m=16)
     xp = torch.zeros_like(b)
     infp = fc.pcg_solve(pb, pc, b, xp, tol=1e-8, stop="residual", mode="f64")
     assert info["status"] == "OK"
