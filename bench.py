@@ -234,6 +234,90 @@ def learned_bench(fc, args):
     }
 
 
+def _solve_record(fc, pb, pc, b, x, **kw):
+    import torch
+    x.zero_()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    info = fc.pcg_solve(pb, pc, b, x, **kw)
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) * 1e3
+    return {"iters": info["iters"], "status": info["status"], "solve_ms": wall,
+            "ms_per_iter": wall / max(1, info["iters"]),
+            "rel_res_true": info["rel_res_true"], "rel_res_prec": info["rel_res_prec"]}
+
+
+def eta_sweep_bench(fc, args):
+    """Blocks only for elements with eta_T <= eta_bar, diagonal scaling for
+    the unknowns no block covers (the paper's study of the threshold):
+    iterations, time and preconditioner size on the 32^3-cell, p = 3
+    elasticity workload; eta_bar < 0 leaves only the diagonal scaling."""
+    import torch
+    import fcgen
+    desc = fcgen.porous_elasticity_3d(seed=0)
+    pb = fc.HostSystem(desc).upload()
+    info = pb.info()
+    m = info["m"]
+    b = torch.empty(pb.n, dtype=torch.float64, device="cuda")
+    pb.rhs(b)
+    x = torch.zeros_like(b)
+    rows = []
+    for eb in args.eta_values:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        pc = fc.Precond(pb, eta_bar=eb)
+        torch.cuda.synchronize()
+        build = (time.perf_counter() - t0) * 1e3
+        pi = pc.info()
+        rec = _solve_record(fc, pb, pc, b, x, tol=args.tol, maxit=args.maxit, stop="residual")
+        rec.update({"eta_bar": eb, "blocks": pi["n_blocks"], "diag_unknowns": pi["n_fallback"],
+                    "inverse_bytes": pi["n_blocks"] * (m // 2 + 1) * m * 8, "build_ms": build,
+                    "time_to_tol_ms": build + rec["solve_ms"]})
+        log(f"eta sweep: eta_bar {eb}: {pi['n_blocks']} blocks, {rec['iters']} iterations "
+            f"{rec['status']}, {rec['solve_ms']:.0f} ms ({rec['ms_per_iter']:.3f} ms/iter)")
+        rows.append(rec)
+        del pc
+    return {"metric": "time-to-1e-8 residual vs the block threshold eta_bar",
+            "workload": "3D finite cell elasticity, 32^3 cells, p=3, 64 spherical voids, "
+                        "alpha=1e-8 (2,738,019 unknowns)",
+            "n_dofs": pb.n, "maxit": args.maxit, "sweep": rows}
+
+
+def compare_bench(fc, args):
+    """Preconditioners compared on the elasticity geometry at fictitious
+    stiffnesses down to zero (the paper's CT examples use about 1e-12):
+    diagonal scaling (DA), Schwarz with plain local inverses (S*) and with
+    the stabilised pseudo-inverses (S), stopped by the relative
+    preconditioned residual ||z|| / ||z_0|| <= 1e-10 (Eq. 12) or at maxit."""
+    import torch
+    import fcgen
+    rows = []
+    n = 0
+    for alpha in args.compare_alpha:
+        desc = fcgen.porous_elasticity_3d(seed=0, alpha=alpha)
+        pb = fc.HostSystem(desc).upload()
+        n = pb.n
+        b = torch.empty(pb.n, dtype=torch.float64, device="cuda")
+        pb.rhs(b)
+        x = torch.zeros_like(b)
+        for name, kw in (("DA", {"eta_bar": -1.0}), ("S*", {"stabilize": False}), ("S", {})):
+            pc = fc.Precond(pb, **kw)
+            pi = pc.info()
+            rec = _solve_record(fc, pb, pc, b, x, tol=1e-10, maxit=args.maxit, stop="precond")
+            rec.update({"alpha": alpha, "preconditioner": name,
+                        "dropped_eigenvalues": pi["n_dropped"]})
+            log(f"compare: alpha {alpha:g} {name}: {rec['iters']} iterations {rec['status']}, "
+                f"||z||/||z0|| {rec['rel_res_prec']:.2e}, ||r||/||b|| {rec['rel_res_true']:.2e}, "
+                f"{pi['n_dropped']} eigenvalues dropped")
+            rows.append(rec)
+            del pc
+        del pb
+    return {"metric": "PCG with DA, S* and S to ||z||/||z_0|| <= 1e-10",
+            "workload": "3D finite cell elasticity, 32^3 cells, p=3, 64 spherical voids "
+                        "(2,738,019 unknowns), fictitious stiffness alpha as listed",
+            "n_dofs": n, "maxit": args.maxit, "runs": rows}
+
+
 def batch_bench(fc, args):
     """Uneven batch of 2-D/3-D Poisson problems (grids 8^2..128^2 and
     8^3..24^3, p = 1..4, elliptical inclusions or voids, alpha = 1e-10,
@@ -319,6 +403,15 @@ def main():
     ap.add_argument("--batch", type=int, default=0,
                     help="instead: solve this many problems of the uneven batch "
                          "generator together (512 = the full batch)")
+    ap.add_argument("--eta-sweep", action="store_true",
+                    help="instead: sweep the block threshold eta_bar on the elasticity workload")
+    ap.add_argument("--eta-values", type=float, nargs="+",
+                    default=[1.0, 0.9, 0.8, 0.7, 0.6, 0.4, 0.2, 0.0, -1.0])
+    ap.add_argument("--compare", action="store_true",
+                    help="instead: DA, S* and S on the elasticity geometry at small alpha")
+    ap.add_argument("--compare-alpha", type=float, nargs="+", default=[1e-12, 1e-16, 0.0])
+    ap.add_argument("--maxit", type=int, default=20000,
+                    help="iteration cap of the sweep and comparison runs")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
@@ -333,6 +426,12 @@ def main():
         copy_calibration(torch)
     if args.batch:
         print(json.dumps(batch_bench(fc, args)), flush=True)
+        return
+    if args.eta_sweep:
+        print(json.dumps(eta_sweep_bench(fc, args)), flush=True)
+        return
+    if args.compare:
+        print(json.dumps(compare_bench(fc, args)), flush=True)
         return
     desc, wl = workload(args.small)
     t0 = time.perf_counter()
