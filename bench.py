@@ -407,6 +407,8 @@ def main():
                     help="instead: sweep the block threshold eta_bar on the elasticity workload")
     ap.add_argument("--eta-values", type=float, nargs="+",
                     default=[1.0, 0.9, 0.8, 0.7, 0.6, 0.4, 0.2, 0.0, -1.0])
+    ap.add_argument("--learned-only", action="store_true",
+                    help="instead: only the learned coarse-correction comparison")
     ap.add_argument("--compare", action="store_true",
                     help="instead: DA, S* and S on the elasticity geometry at small alpha")
     ap.add_argument("--compare-alpha", type=float, nargs="+", default=[1e-12, 1e-16, 0.0])
@@ -426,6 +428,9 @@ def main():
         copy_calibration(torch)
     if args.batch:
         print(json.dumps(batch_bench(fc, args)), flush=True)
+        return
+    if args.learned_only:
+        print(json.dumps(learned_bench(fc, args)), flush=True)
         return
     if args.eta_sweep:
         print(json.dumps(eta_sweep_bench(fc, args)), flush=True)

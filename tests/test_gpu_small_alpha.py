@@ -1,0 +1,74 @@
+"""Stabilised pseudo-inverses (S, Sec. 3.2 Eqs. 9-11) and plain inverses
+(S*) at tiny fictitious stiffness, on a 6^3-cell, p = 3 elasticity cube
+whose large void holds eight cells entirely, against the oracle's runs in
+tests/golden/small_alpha_cube.json (written by make_small_alpha_cube.py,
+which calls only the oracle).  Stop: ||z|| / ||z_0|| <= 1e-10 (Eq. 12).
+
+The oracle shows both sides of the stabilisation here: at alpha = 1e-16
+the pseudo-inverse solve converges while the eigen-decomposition inverse
+breaks down, and at alpha = 1e-12, where the threshold of Eq. 11 falls
+among the fictitious modes' eigenvalues, the pseudo-inverse solve stalls
+while the plain inverse converges."""
+import json
+import os
+
+import pytest
+
+import fcgen
+import paper_1809_00828_amd as fc
+from tests.gpu_common import require_gpu
+
+pytestmark = pytest.mark.gpu
+
+with open(os.path.join(os.path.dirname(__file__), "golden", "small_alpha_cube.json")) as _f:
+    GOLD = json.load(_f)
+
+
+@pytest.fixture(scope="module")
+def torch():
+    return require_gpu()
+
+
+def _ref(alpha, stab):
+    return next(r for r in GOLD["runs"] if r["alpha"] == alpha and r["stabilize"] == stab)
+
+
+def _run(torch, alpha, stab):
+    d = fcgen.custom(3, GOLD["n"], GOLD["p"], pde="elasticity", alpha=alpha,
+                     shapes=GOLD["shapes"], clamp_zmin=True)
+    pb = fc.Problem.setup(d)
+    pc = fc.Precond(pb, stabilize=stab)
+    b = torch.empty(pb.n, dtype=torch.float64, device="cuda")
+    pb.rhs(b)
+    x = torch.zeros_like(b)
+    info = fc.pcg_solve(pb, pc, b, x, tol=GOLD["tol"], maxit=GOLD["maxit"], stop="precond")
+    print(f"[small alpha] alpha {alpha:g} stabilize {stab}: {info['iters']} iterations "
+          f"{info['status']}, ||z||/||z0|| {info['rel_res_prec']:.2e}, dropped "
+          f"{pc.info()['n_dropped']}", flush=True)
+    return info, pc.info()
+
+
+@pytest.mark.parametrize("alpha", [1e-16, 1e-12])
+def test_stabilised_schwarz_at_small_alpha_matches_oracle(torch, alpha):
+    ref = _ref(alpha, True)
+    info, pi = _run(torch, alpha, True)
+    # which eigenvalues fall below eps * lambda_max is fixed by FP64 data only
+    # up to eps * kappa(A_B): a few decisions may differ on the threshold
+    assert abs(pi["n_dropped"] - ref["dropped"]) <= max(2, 0.02 * ref["dropped"])
+    assert info["status"] == ref["status"]
+    if ref["status"] == "OK":
+        assert abs(info["iters"] - ref["iters"]) <= 0.05 * ref["iters"], (info["iters"], ref)
+        assert info["rel_res_true"] <= 10.0 * ref["rel_res_true"] + 1e-12
+    else:
+        # both stall far above the tolerance
+        assert info["rel_res_prec"] > 100.0 * GOLD["tol"]
+        assert ref["rel_res_prec"] > 100.0 * GOLD["tol"]
+
+
+def test_plain_inverse_at_alpha_1e12_matches_oracle(torch):
+    """Blocks with kappa * eps well below one: the plain inverse is well
+    defined and both sides converge alike."""
+    ref = _ref(1e-12, False)
+    info, _ = _run(torch, 1e-12, False)
+    assert ref["status"] == "OK" and info["status"] == "OK"
+    assert abs(info["iters"] - ref["iters"]) <= 0.05 * ref["iters"], (info["iters"], ref)
