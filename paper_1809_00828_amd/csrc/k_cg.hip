@@ -319,12 +319,12 @@ __global__ void k_fcg_reset(FcgRing* fr) { fr->count = 0; }
 
 // Store the step's p and q = A p in slot count mod m and form, per
 // workgroup (one contiguous chunk of unknowns), the partial (z, A p_j) of
-// every kept slot j.
+// every kept slot j: wave sums by shuffles, one barrier for all slots.
 __global__ __launch_bounds__(256) void k_fcg_keep_dots(
     const double* __restrict__ p, const double* __restrict__ q, const double* __restrict__ z,
     int64_t n, int m, double* __restrict__ ring, double* __restrict__ part, FcgRing* fr,
     const CgScalars* __restrict__ sc) {
-  __shared__ double lds[16];
+  __shared__ double red[kMaxFcg][4];
   if (sc->done) return;
   const int64_t cnt0 = fr->count;
   const int slot = (int)(cnt0 % m);
@@ -333,6 +333,7 @@ __global__ __launch_bounds__(256) void k_fcg_keep_dots(
   const double* Q = ring + (int64_t)m * n;
   double* Qs = ring + ((int64_t)m + slot) * n;
   const int64_t base = (int64_t)blockIdx.x * (256 * kRingElems) + threadIdx.x;
+  const int w = threadIdx.x / kWave, l = threadIdx.x % kWave;
   double zv[kRingElems], qv[kRingElems];
 #pragma unroll
   for (int e = 0; e < kRingElems; ++e) {
@@ -355,19 +356,26 @@ __global__ __launch_bounds__(256) void k_fcg_keep_dots(
       const int64_t i = base + (int64_t)e * 256;
       if (i < n) d = fma(zv[e], j == slot ? qv[e] : Qj[i], d);
     }
-    d = block_sum(d, lds);
-    if (threadIdx.x == 0) part[(int64_t)j * gridDim.x + blockIdx.x] = d;
+    d = group_sum<kWave>(d);
+    if (l == 0) red[j][w] = d;
   }
+  __syncthreads();
+  for (int j = threadIdx.x; j < cnt; j += blockDim.x)
+    part[(int64_t)j * gridDim.x + blockIdx.x] = (red[j][0] + red[j][1]) + (red[j][2] + red[j][3]);
 }
 
 // Stop test as in k_cg_beta_flex (residual stop; (r, z) gains the
-// correction's gamma (y . P_c^T r)), then beta_j for every kept slot.
+// correction's gamma (y . P_c^T r)), then beta_j for every kept slot: one
+// wave per slot (16 waves take the slots in turn), each summing that
+// slot's partials in a fixed order.
 __global__ __launch_bounds__(1024) void k_fcg_beta(const double* __restrict__ partial, int np,
                                                    const double* __restrict__ part, int nb,
                                                    int m, FcgRing* fr, CgScalars* sc,
                                                    const LearnScalars* __restrict__ ls) {
   __shared__ double lds[16];
+  __shared__ int bad;
   if (sc->done) return;
+  if (threadIdx.x == 0) bad = 0;
   double ta = 0.0, tb = 0.0, tc = 0.0;
   for (int i = threadIdx.x; i < np; i += blockDim.x) {
     ta += partial[i];
@@ -379,17 +387,25 @@ __global__ __launch_bounds__(1024) void k_fcg_beta(const double* __restrict__ pa
   const double rr = block_sum(tc, lds);
   const int64_t cnt0 = fr->count;
   const int cnt = (int)(cnt0 + 1 < m ? cnt0 + 1 : m);
-  bool bad = false;
-  for (int j = 0; j < cnt; ++j) {
-    double t = 0.0;
-    for (int i = threadIdx.x; i < nb; i += blockDim.x) t += part[(int64_t)j * nb + i];
-    const double d = block_sum(t, lds);
-    if (threadIdx.x == 0) {
+  const int w = threadIdx.x / kWave, l = threadIdx.x % kWave;
+  const int nw = blockDim.x / kWave;
+  for (int j = w; j < cnt; j += nw) {
+    const double* pj = part + (int64_t)j * nb;
+    double t0 = 0.0, t1 = 0.0;
+    int i = l;
+    for (; i + kWave < nb; i += 2 * kWave) {
+      t0 += pj[i];
+      t1 += pj[i + kWave];
+    }
+    if (i < nb) t0 += pj[i];
+    const double d = group_sum<kWave>(t0 + t1);
+    if (l == 0) {
       const double b = -d / fr->pq[j];
       fr->beta[j] = b;
-      bad = bad || !(b == b) || isinf(b);
+      if (!(b == b) || isinf(b)) bad = 1;
     }
   }
+  __syncthreads();
   if (threadIdx.x == 0) {
     fr->count = cnt0 + 1;
     const double g = ls->gamma;
