@@ -31,8 +31,8 @@
 
 namespace fc {
 
-constexpr int kCoT = 8;      // output channels per lane
 constexpr int kConvT = 64;   // lanes per workgroup (one wave)
+constexpr int kWgradSlots = 4096;   // (co, ci, chunk) partials of the weight gradient
 
 __device__ __forceinline__ uint16_t f2bf(float f) {
   uint32_t u = __float_as_uint(f);
@@ -41,14 +41,15 @@ __device__ __forceinline__ uint16_t f2bf(float f) {
 }
 
 // y[b][o][v] = act(bias[o] + sum_{i,t} w(o,i,t) x[b][i][v + off_t])
-// One wave per workgroup, one voxel and kCoT output channels per lane.  The
+// One wave per workgroup, one voxel and CoT output channels per lane (CoT
+// shrinks on the coarse levels so that the launch still spans the chip).  The
 // weights are read at wave-uniform addresses from rows of 14 dwords (27
 // BF16 taps and one pad per (co, ci) pair), so they arrive through scalar
 // loads and feed the FMAs as scalar operands; the 27 neighbour values of
-// an input channel are loaded once and reused for all kCoT outputs.
+// an input channel are loaded once and reused for all CoT outputs.
 // kTrans: w(o,i,t) = W[i][o][26-t] (data gradient of a convolution whose
 // input width is this kernel's Co), no bias, no activation.
-template <bool kTrans>
+template <bool kTrans, int kCoT>
 __global__ __launch_bounds__(kConvT) void k_conv3d(const float* __restrict__ x, int Ci,
                                                    const uint32_t* __restrict__ W,
                                                    const float* __restrict__ bias,
@@ -108,20 +109,25 @@ __global__ void k_pack_w(const float* __restrict__ w, uint32_t* __restrict__ out
   }
 }
 
-// gw[co][ci][t] = sum_{b,v} g[b][co][v] x[b][ci][v + off_t];  gb[co] = sum g
+// Weight gradient, gw[co][ci][t] = sum_{b,v} g[b][co][v] x[b][ci][v + off_t]
+// and gb[co] = sum g, in two deterministic passes: workgroup (ci, co, c)
+// sums chunk c of the (b, v) range into 28 partials, then one thread per
+// (co, ci, t) adds the chunks in order.
 __global__ __launch_bounds__(256) void k_conv3d_wgrad(const float* __restrict__ x, int Ci,
                                                       const float* __restrict__ g, int Co, int B,
-                                                      int D, int H, int Wd,
-                                                      float* __restrict__ gw,
-                                                      float* __restrict__ gb) {
+                                                      int D, int H, int Wd, int nchunk,
+                                                      float* __restrict__ part) {
   __shared__ float red[16];
-  const int ci = blockIdx.x, co = blockIdx.y;
+  const int ci = blockIdx.x, co = blockIdx.y, c = blockIdx.z;
   const int V = D * H * Wd;
+  const int64_t total = (int64_t)B * V;
+  const int64_t len = (total + nchunk - 1) / nchunk;
+  const int64_t lo = (int64_t)c * len, hi = lo + len < total ? lo + len : total;
   float acc[27];
 #pragma unroll
   for (int k = 0; k < 27; ++k) acc[k] = 0.f;
   float accb = 0.f;
-  for (int64_t idx = threadIdx.x; idx < (int64_t)B * V; idx += blockDim.x) {
+  for (int64_t idx = lo + threadIdx.x; idx < hi; idx += blockDim.x) {
     const int b = (int)(idx / V), v = (int)(idx % V);
     const float gv = g[((int64_t)b * Co + co) * V + v];
     accb += gv;
@@ -136,13 +142,30 @@ __global__ __launch_bounds__(256) void k_conv3d_wgrad(const float* __restrict__ 
         acc[k] = fmaf(gv, xi[(z2 * H + y2) * Wd + x2], acc[k]);
     }
   }
+  float* out = part + (((int64_t)co * Ci + ci) * nchunk + c) * 28;
   for (int k = 0; k < 27; ++k) {
     const float s = block_sum(acc[k], red);
-    if (threadIdx.x == 0) gw[((int64_t)co * Ci + ci) * 27 + k] = s;
+    if (threadIdx.x == 0) out[k] = s;
   }
-  if (ci == 0) {
-    const float s = block_sum(accb, red);
-    if (threadIdx.x == 0) gb[co] = s;
+  const float sb = block_sum(accb, red);
+  if (threadIdx.x == 0) out[27] = sb;
+}
+
+__global__ void k_wgrad_reduce(const float* __restrict__ part, int Ci, int Co, int nchunk,
+                               float* __restrict__ gw, float* __restrict__ gb) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t rows = (int64_t)Co * Ci;
+  if (t >= rows * 28) return;
+  const int64_t row = t / 28;
+  const int k = (int)(t % 28);
+  const float* p = part + row * nchunk * 28 + k;
+  float s = 0.f;
+  for (int c = 0; c < nchunk; ++c) s += p[(int64_t)c * 28];
+  const int co = (int)(row / Ci), ci = (int)(row % Ci);
+  if (k < 27) gw[row * 27 + k] = s;
+  else if (ci == 0) {
+    // the bias gradient is the same sum for every ci; keep ci = 0's
+    gb[co] = s;
   }
 }
 
@@ -309,32 +332,61 @@ int64_t net_param_count(const int32_t* c, int32_t in_channels) {
   return n.nparam;
 }
 
+// Output channels per lane: the largest of 8, 4, 2, 1 that still gives at
+// least 1024 workgroups (the coarse levels hold few voxels).
+template <bool kTrans>
+static hipError_t launch_conv(const float* x, int cin, const uint32_t* W, const float* bias,
+                              float* y, int cout, int N, int B, int relu, hipStream_t s) {
+  const int V = N * N * N;
+  const int64_t vb = (V + kConvT - 1) / kConvT;
+  int cot = 8;
+  while (cot > 1 && vb * ((cout + cot - 1) / cot) * B < 1024) cot /= 2;
+  dim3 g((unsigned)vb, (unsigned)((cout + cot - 1) / cot), (unsigned)B);
+  switch (cot) {
+    case 8:
+      hipLaunchKernelGGL((k_conv3d<kTrans, 8>), g, dim3(kConvT), 0, s, x, cin, W, bias, y, cout,
+                         N, relu);
+      break;
+    case 4:
+      hipLaunchKernelGGL((k_conv3d<kTrans, 4>), g, dim3(kConvT), 0, s, x, cin, W, bias, y, cout,
+                         N, relu);
+      break;
+    case 2:
+      hipLaunchKernelGGL((k_conv3d<kTrans, 2>), g, dim3(kConvT), 0, s, x, cin, W, bias, y, cout,
+                         N, relu);
+      break;
+    default:
+      hipLaunchKernelGGL((k_conv3d<kTrans, 1>), g, dim3(kConvT), 0, s, x, cin, W, bias, y, cout,
+                         N, relu);
+  }
+  return hipGetLastError();
+}
+
 static hipError_t conv_fwd(const Net& net, int l, const float* x, float* y, int B, int N, bool relu,
                            hipStream_t s) {
-  const int Ci = net.ci[l], Co = net.co[l];
-  const int V = N * N * N;
-  dim3 g((V + kConvT - 1) / kConvT, (Co + kCoT - 1) / kCoT, B);
-  hipLaunchKernelGGL(k_conv3d<false>, g, dim3(kConvT), 0, s, x, Ci, net.wpk + net.wpoff[l],
-                     net.p + net.boff[l], y, Co, N, relu ? 1 : 0);
-  return hipGetLastError();
+  return launch_conv<false>(x, net.ci[l], net.wpk + net.wpoff[l], net.p + net.boff[l], y,
+                            net.co[l], N, B, relu ? 1 : 0, s);
 }
 
 // data gradient of layer l: gx (Ci channels) from gy (Co channels)
 static hipError_t conv_bwd_data(const Net& net, int l, const float* gy, float* gx, int B, int N,
                                 hipStream_t s) {
-  const int Ci = net.ci[l], Co = net.co[l];
-  const int V = N * N * N;
-  dim3 g((V + kConvT - 1) / kConvT, (Ci + kCoT - 1) / kCoT, B);
-  hipLaunchKernelGGL(k_conv3d<true>, g, dim3(kConvT), 0, s, gy, Co, net.wpk + net.wpoff[l],
-                     nullptr, gx, Ci, N, 0);
-  return hipGetLastError();
+  return launch_conv<true>(gy, net.co[l], net.wpk + net.wpoff[l], nullptr, gx, net.ci[l], N, B,
+                           0, s);
 }
 
-static hipError_t conv_bwd_weight(Net& net, int l, const float* x, const float* gy, int B, int N,
-                                  hipStream_t s) {
+static hipError_t conv_bwd_weight(Net& net, NetWs& ws, int l, const float* x, const float* gy,
+                                  int B, int N, hipStream_t s) {
   const int Ci = net.ci[l], Co = net.co[l];
-  hipLaunchKernelGGL(k_conv3d_wgrad, dim3(Ci, Co), dim3(256), 0, s, x, Ci, gy, Co, B, N, N, N,
-                     net.g + net.woff[l], net.g + net.boff[l]);
+  const int64_t total = (int64_t)B * N * N * N;
+  const int64_t pairs = (int64_t)Ci * Co;
+  // chunks of at least 1024 (b, v) points, at most ws.wslots partial rows
+  int64_t nchunk = std::max<int64_t>(1, std::min<int64_t>(ws.wslots / pairs, total / 1024));
+  hipLaunchKernelGGL(k_conv3d_wgrad, dim3(Ci, Co, (unsigned)nchunk), dim3(256), 0, s, x, Ci, gy,
+                     Co, B, N, N, N, (int)nchunk, ws.wpart);
+  const int64_t nt = pairs * 28;
+  hipLaunchKernelGGL(k_wgrad_reduce, dim3((unsigned)((nt + 255) / 256)), dim3(256), 0, s, ws.wpart,
+                     Ci, Co, (int)nchunk, net.g + net.woff[l], net.g + net.boff[l]);
   return hipGetLastError();
 }
 
@@ -369,14 +421,20 @@ fc_status NetWs::ensure(const Net& net, int B_, int N0) {
     return FC_E_NOMEM;
   }
   if (hipMalloc(&partial, 1024 * sizeof(double)) != hipSuccess) return FC_E_NOMEM;
+  // partial rows of the weight gradient: at least one per (co, ci) pair
+  wslots = kWgradSlots;
+  for (int l = 0; l < 15; ++l) wslots = std::max<int64_t>(wslots, (int64_t)net.ci[l] * net.co[l]);
+  if (hipMalloc(&wpart, (size_t)wslots * 28 * sizeof(float)) != hipSuccess) return FC_E_NOMEM;
   return FC_OK;
 }
 
 void NetWs::release() {
   if (buf) (void)hipFree(buf);
   if (partial) (void)hipFree(partial);
+  if (wpart) (void)hipFree(wpart);
   buf = nullptr;
   partial = nullptr;
+  wpart = nullptr;
   capB = 0;
 }
 
@@ -426,7 +484,7 @@ hipError_t net_backward(Net& net, NetWs& ws, const float* x, float* gy, int B, h
   hipError_t e;
   // head
   float* g = ws.t(0, 7);
-  if ((e = conv_bwd_weight(net, 14, ws.t(0, 6), gy, B, N[0], s)) != hipSuccess) return e;
+  if ((e = conv_bwd_weight(net, ws, 14, ws.t(0, 6), gy, B, N[0], s)) != hipSuccess) return e;
   if ((e = conv_bwd_data(net, 14, gy, g, B, N[0], s)) != hipSuccess) return e;
   std::vector<float*> gskip(3, nullptr);
   int gc = net.ch[0];
@@ -434,7 +492,7 @@ hipError_t net_backward(Net& net, NetWs& ws, const float* x, float* gy, int B, h
     const int la = 8 + 2 * (2 - l), lb = la + 1;
     const int64_t n = (int64_t)B * net.ch[l] * ws.vox(l);
     hipLaunchKernelGGL(k_relu_mask, grid1(n), dim3(256), 0, s, g, ws.t(l, 6), n);
-    if ((e = conv_bwd_weight(net, lb, ws.t(l, 5), g, B, N[l], s)) != hipSuccess) return e;
+    if ((e = conv_bwd_weight(net, ws, lb, ws.t(l, 5), g, B, N[l], s)) != hipSuccess) return e;
     float* gm = ws.t(l, 8);
     if ((e = conv_bwd_data(net, lb, g, gm, B, N[l], s)) != hipSuccess) return e;
     // gm flows to the skip (kept in slot 8) and to da
@@ -442,7 +500,7 @@ hipError_t net_backward(Net& net, NetWs& ws, const float* x, float* gy, int B, h
     (void)hipMemcpyAsync(gda, gm, n * sizeof(float), hipMemcpyDeviceToDevice, s);
     gskip[l] = gm;
     hipLaunchKernelGGL(k_relu_mask, grid1(n), dim3(256), 0, s, gda, ws.t(l, 4), n);
-    if ((e = conv_bwd_weight(net, la, ws.t(l, 3), gda, B, N[l], s)) != hipSuccess) return e;
+    if ((e = conv_bwd_weight(net, ws, la, ws.t(l, 3), gda, B, N[l], s)) != hipSuccess) return e;
     // data gradient of up_a lands on the upsampled tensor (Ci = width below)
     float* gu = ws.t(l, 3);   // the upsampled input is no longer needed
     if ((e = conv_bwd_data(net, la, gda, gu, B, N[l], s)) != hipSuccess) return e;
@@ -459,11 +517,11 @@ hipError_t net_backward(Net& net, NetWs& ws, const float* x, float* gy, int B, h
   {
     const int64_t n = (int64_t)B * net.ch[3] * ws.vox(3);
     hipLaunchKernelGGL(k_relu_mask, grid1(n), dim3(256), 0, s, g, ws.t(3, 2), n);
-    if ((e = conv_bwd_weight(net, 7, ws.t(3, 1), g, B, N[3], s)) != hipSuccess) return e;
+    if ((e = conv_bwd_weight(net, ws, 7, ws.t(3, 1), g, B, N[3], s)) != hipSuccess) return e;
     float* g2 = ws.t(3, 8);
     if ((e = conv_bwd_data(net, 7, g, g2, B, N[3], s)) != hipSuccess) return e;
     hipLaunchKernelGGL(k_relu_mask, grid1(n), dim3(256), 0, s, g2, ws.t(3, 1), n);
-    if ((e = conv_bwd_weight(net, 6, ws.t(3, 0), g2, B, N[3], s)) != hipSuccess) return e;
+    if ((e = conv_bwd_weight(net, ws, 6, ws.t(3, 0), g2, B, N[3], s)) != hipSuccess) return e;
     g = ws.t(3, 7);
     if ((e = conv_bwd_data(net, 6, g2, g, B, N[3], s)) != hipSuccess) return e;
   }
@@ -475,12 +533,12 @@ hipError_t net_backward(Net& net, NetWs& ws, const float* x, float* gy, int B, h
     hipLaunchKernelGGL(k_pool_bwd, grid1(n), dim3(256), 0, s, g, gb, (int)bc, N[l], N[l], N[l]);
     hipLaunchKernelGGL(k_add, grid1(n), dim3(256), 0, s, gb, gskip[l], n);
     hipLaunchKernelGGL(k_relu_mask, grid1(n), dim3(256), 0, s, gb, ws.t(l, 2), n);
-    if ((e = conv_bwd_weight(net, 2 * l + 1, ws.t(l, 1), gb, B, N[l], s)) != hipSuccess) return e;
+    if ((e = conv_bwd_weight(net, ws, 2 * l + 1, ws.t(l, 1), gb, B, N[l], s)) != hipSuccess) return e;
     float* g2 = ws.t(l, 8);
     if ((e = conv_bwd_data(net, 2 * l + 1, gb, g2, B, N[l], s)) != hipSuccess) return e;
     hipLaunchKernelGGL(k_relu_mask, grid1(n), dim3(256), 0, s, g2, ws.t(l, 1), n);
     const float* xin = l == 0 ? x : ws.t(l, 0);
-    if ((e = conv_bwd_weight(net, 2 * l, xin, g2, B, N[l], s)) != hipSuccess) return e;
+    if ((e = conv_bwd_weight(net, ws, 2 * l, xin, g2, B, N[l], s)) != hipSuccess) return e;
     if (l > 0) {
       g = ws.t(l, 7);   // reuse: data gradient into the pooled input of level l
       if ((e = conv_bwd_data(net, 2 * l, g2, g, B, N[l], s)) != hipSuccess) return e;

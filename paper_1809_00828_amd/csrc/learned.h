@@ -39,6 +39,8 @@ struct NetWs {
   int64_t off_y = 0;
   float* buf = nullptr;
   double* partial = nullptr;
+  float* wpart = nullptr;   // weight-gradient partials, wslots rows of 28
+  int64_t wslots = 0;
   float* t(int l, int k) const { return buf + off[l][k]; }
   int64_t vox(int l) const { return (int64_t)N[l] * N[l] * N[l]; }
   float* y() const { return buf + off_y; }
