@@ -285,7 +285,8 @@ def eta_sweep_bench(fc, args):
 
 def compare_bench(fc, args):
     """Preconditioners compared on the elasticity geometry at fictitious
-    stiffnesses down to zero (the paper's CT examples use about 1e-12):
+    stiffnesses down to zero (the paper's CT examples use about 1e-12),
+    optionally after removing the functions of cells without material:
     diagonal scaling (DA), Schwarz with plain local inverses (S*) and with
     the stabilised pseudo-inverses (S), stopped by the relative
     preconditioned residual ||z|| / ||z_0|| <= 1e-10 (Eq. 12) or at maxit."""
@@ -294,7 +295,8 @@ def compare_bench(fc, args):
     rows = []
     n = 0
     for alpha in args.compare_alpha:
-        desc = fcgen.porous_elasticity_3d(seed=0, alpha=alpha)
+        desc = fcgen.porous_elasticity_3d(seed=0, alpha=alpha,
+                                          discard_fictitious=args.discard_fictitious)
         pb = fc.HostSystem(desc).upload()
         n = pb.n
         b = torch.empty(pb.n, dtype=torch.float64, device="cuda")
@@ -305,6 +307,7 @@ def compare_bench(fc, args):
             pi = pc.info()
             rec = _solve_record(fc, pb, pc, b, x, tol=1e-10, maxit=args.maxit, stop="precond")
             rec.update({"alpha": alpha, "preconditioner": name,
+                        "discard_fictitious": bool(args.discard_fictitious),
                         "dropped_eigenvalues": pi["n_dropped"]})
             log(f"compare: alpha {alpha:g} {name}: {rec['iters']} iterations {rec['status']}, "
                 f"||z||/||z0|| {rec['rel_res_prec']:.2e}, ||r||/||b|| {rec['rel_res_true']:.2e}, "
@@ -412,6 +415,8 @@ def main():
     ap.add_argument("--compare", action="store_true",
                     help="instead: DA, S* and S on the elasticity geometry at small alpha")
     ap.add_argument("--compare-alpha", type=float, nargs="+", default=[1e-12, 1e-16, 0.0])
+    ap.add_argument("--discard-fictitious", action="store_true",
+                    help="compare: first remove the functions of cells without material")
     ap.add_argument("--maxit", type=int, default=20000,
                     help="iteration cap of the sweep and comparison runs")
     args = ap.parse_args()

@@ -23,6 +23,9 @@ modes        scalar load f(x) = sum_k amp_k cos(2 pi k.x + phase_k)
 E, nu        elasticity constants
 traction     traction vector applied on the face z = 1 (3-D elasticity)
 clamp_zmin   clamp every function that is nonzero on z = 0
+discard_fictitious
+             (optional, default False) remove every function whose support
+             lies only in cells without physical material
 """
 from __future__ import annotations
 
@@ -53,7 +56,7 @@ def _fourier_modes(rng: np.random.Generator, dim: int, count: int = 8):
 
 def custom(dim, n, p, pde="poisson", alpha=1e-10, shapes=(), domain="voids",
            modes=None, quad_depth=3, E=1.0, nu=0.3, traction=None,
-           clamp_zmin=False, seed=0) -> dict:
+           clamp_zmin=False, seed=0, discard_fictitious=False) -> dict:
     """A description with explicitly given geometry (used by tests)."""
     if modes is None:
         modes = _fourier_modes(np.random.default_rng(seed), dim)
@@ -70,6 +73,7 @@ def custom(dim, n, p, pde="poisson", alpha=1e-10, shapes=(), domain="voids",
         "modes": modes, "E": float(E), "nu": float(nu),
         "traction": [float(t) for t in traction],
         "clamp_zmin": bool(clamp_zmin), "seed": int(seed),
+        "discard_fictitious": bool(discard_fictitious),
     }
 
 
@@ -108,7 +112,8 @@ def _spherical_voids(rng, count, rmin, rmax):
 
 def porous_elasticity_3d(seed: int = 0, n: int = 32, p: int = 3,
                          n_voids: int = 64, rmin: float = 0.02,
-                         rmax: float = 0.06, alpha: float = 1e-8) -> dict:
+                         rmax: float = 0.06, alpha: float = 1e-8,
+                         discard_fictitious: bool = False) -> dict:
     """3-D linear elasticity on the unit cube minus seeded spherical voids.
 
     Radii are uniform in [rmin, rmax]; centres are uniform in [r, 1-r]^3 so
@@ -119,7 +124,7 @@ def porous_elasticity_3d(seed: int = 0, n: int = 32, p: int = 3,
     voids = _spherical_voids(rng, n_voids, rmin, rmax)
     return custom(3, n, p, "elasticity", alpha, shapes=voids, domain="voids",
                   modes=[], E=1.0, nu=0.3, traction=[0.0, 0.0, -1.0],
-                  clamp_zmin=True, seed=seed)
+                  clamp_zmin=True, seed=seed, discard_fictitious=discard_fictitious)
 
 
 def porous_poisson_3d(seed: int = 0, n: int = 64, p: int = 2,

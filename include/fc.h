@@ -73,6 +73,10 @@ enum { FC_DOMAIN_VOIDS = 0, FC_DOMAIN_INCLUSIONS = 1 };
  *               face x_{dim-1} = 1; clamp_zmin clamps (strongly: rows and
  *               columns zeroed, diagonal kept, load zeroed) every function
  *               that is nonzero on x_{dim-1} = 0.
+ * discard_fictitious removes, in the same way, every function whose support
+ * lies only in cells with eta_T = 0 (the paper's preprocessing of elements
+ * completely outside the physical domain, Sec. 5.2; the unknowns keep their
+ * lattice numbering).
  * All pointers are host pointers read during fc_setup only.
  */
 typedef struct {
@@ -89,6 +93,7 @@ typedef struct {
   double E, nu;
   double traction[3];
   int32_t clamp_zmin;
+  int32_t discard_fictitious;
 } fc_problem_desc;
 
 /* Assemble A (BSR, block = ncomp x ncomp), b, the per-cell volume fraction

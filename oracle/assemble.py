@@ -10,7 +10,11 @@ the element stiffness is the textbook sum over quadrature points of
 B^T D B.  The face x_{d-1} = 1 carries the traction; when the description
 asks for it, every function that is nonzero on x_{d-1} = 0 is clamped
 strongly: its rows and columns are zeroed, the diagonal entry is kept and
-its load entry is set to zero.
+its load entry is set to zero.  With discard_fictitious, every function
+whose support lies only in cells without physical material (eta_T = 0) is
+removed the same way: the preprocessing the paper applies to elements
+completely outside the physical domain (Sec. 5.2), done in place so that
+the numbering stays the lattice's.
 
 Numbering.  Per direction the global 1-D index of local function a on cell
 e is g = p*e + L(a) with L(0) = 0, L(1) = p, L(j) = j - 1; the node id is
@@ -275,12 +279,27 @@ def assemble(desc, keep_cells=None):
                       shape=(ndof, ndof)).tocsr()
     A.sum_duplicates()
     A, b = apply_clamp(desc, A, b)
+    if desc.get("discard_fictitious"):
+        A, b = remove_dofs(A, b, fictitious_dofs(np.array(edofs), eta, ndof))
     return {"A": A, "b": b, "eta": eta, "elem_dofs": np.array(edofs),
             "cells": cl}
 
 
+def fictitious_dofs(elem_dofs, eta, ndof):
+    """Unknowns of the functions that touch no cell with eta_T > 0."""
+    touch = np.zeros(ndof, dtype=bool)
+    for c in np.flatnonzero(eta > 0.0):
+        touch[elem_dofs[c]] = True
+    return np.flatnonzero(~touch)
+
+
 def apply_clamp(desc, A, b):
-    cd = clamped_dofs(desc)
+    return remove_dofs(A, b, clamped_dofs(desc))
+
+
+def remove_dofs(A, b, cd):
+    """Zero the rows and columns of the unknowns cd, keep their diagonal
+    entries and set their load entries to zero."""
     if cd.size == 0:
         return A, b
     diag = A.diagonal()[cd].copy()

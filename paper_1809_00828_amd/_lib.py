@@ -54,7 +54,8 @@ class ProblemDesc(C.Structure):
                 ("shape_semi", C.POINTER(C.c_double)), ("n_modes", C.c_int32),
                 ("mode_k", C.POINTER(C.c_double)), ("mode_amp", C.POINTER(C.c_double)),
                 ("mode_phase", C.POINTER(C.c_double)), ("E", C.c_double), ("nu", C.c_double),
-                ("traction", C.c_double * 3), ("clamp_zmin", C.c_int32)]
+                ("traction", C.c_double * 3), ("clamp_zmin", C.c_int32),
+                ("discard_fictitious", C.c_int32)]
 
 
 class PrecondOpts(C.Structure):
@@ -205,6 +206,7 @@ def make_desc(d: dict):
     t = list(d["traction"]) + [0.0] * (3 - len(d["traction"]))
     desc.traction = (C.c_double * 3)(*t[:3])
     desc.clamp_zmin = 1 if d.get("clamp_zmin") else 0
+    desc.discard_fictitious = 1 if d.get("discard_fictitious") else 0
     return desc, keep
 
 

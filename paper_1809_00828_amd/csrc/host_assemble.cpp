@@ -624,6 +624,16 @@ fc_status assemble_host(const fc_problem_desc& d, HostSystem* out, std::string* 
   S.val.assign((size_t)nnzb * bb, 0.0);
 
   const bool clamp = d.clamp_zmin != 0;
+  // functions that touch no cell with physical material: removed in place
+  // (rows and columns zeroed, diagonal kept) when the description asks
+  const bool discard = d.discard_fictitious != 0;
+  std::vector<uint8_t> gone;
+  if (discard) {
+    gone.assign(n_nodes, 1);
+    for (int64_t e = 0; e < n_el; ++e)
+      if (res[e].eta > 0.0)
+        for (int a = 0; a < nn; ++a) gone[S.elem_nodes[(size_t)e * nn + a]] = 0;
+  }
   parallel_for(n_nodes, [&](int64_t nd) {
     int64_t g[kMaxDim], lo[kMaxDim], hi[kMaxDim], len[kMaxDim];
     int64_t r = nd;
@@ -692,13 +702,13 @@ fc_status assemble_host(const fc_problem_desc& d, HostSystem* out, std::string* 
             V[(size_t)(i * bd + j) * L + pos] += scale * K[(size_t)(a * bd + i) * m + (b * bd + j)];
       }
     }
-    if (clamp) {
-      const bool row_cl = g[dim - 1] == 0;
+    if (clamp || discard) {
+      const bool row_cl = (clamp && g[dim - 1] == 0) || (discard && gone[nd]);
       for (int64_t t = 0; t < L; ++t) {
         int64_t cnode = S.col[base + t];
         int64_t gz = cnode;
         for (int k = 0; k < dim - 1; ++k) gz /= n1;
-        const bool col_cl = gz == 0;
+        const bool col_cl = (clamp && gz == 0) || (discard && gone[cnode]);
         if (!row_cl && !col_cl) continue;
         for (int i = 0; i < bd; ++i)
           for (int j = 0; j < bd; ++j)
@@ -720,6 +730,10 @@ fc_status assemble_host(const fc_problem_desc& d, HostSystem* out, std::string* 
     for (int64_t nd = 0; nd < plane; ++nd)
       for (int c = 0; c < bd; ++c) S.rhs[nd * bd + c] = 0.0;
   }
+  if (discard)
+    for (int64_t nd = 0; nd < n_nodes; ++nd)
+      if (gone[nd])
+        for (int c = 0; c < bd; ++c) S.rhs[nd * bd + c] = 0.0;
   return FC_OK;
 }
 

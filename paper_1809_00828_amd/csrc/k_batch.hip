@@ -68,7 +68,7 @@ __global__ __launch_bounds__(256) void kb_spmv(const BProb* __restrict__ probs,
                                                double* __restrict__ qvec) {
   constexpr int BB = B * B;
   constexpr int RPW = 256 / G;
-  constexpr int U = B == 1 ? 4 : 2;   // blocks per lane per pass
+  constexpr int U = B == 1 ? 8 : 2;   // blocks per lane per pass
   const WorkItem it = items[blockIdx.x];
   const BProb& P = probs[it.prob];
   if (sc[it.prob].done) return;

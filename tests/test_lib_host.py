@@ -40,6 +40,8 @@ def bsr_to_csr(e):
     return sp.csr_matrix((val.ravel(), (R.ravel(), Cc.ravel())), shape=(nbr * bd, nbr * bd))
 
 
+BIG_VOID = [{"centre": [0.5, 0.52, 0.48], "semi": [0.33, 0.33, 0.33]}]
+
 CASES = {
     "disk2d_p2": lambda: fcgen.disk_poisson_2d(0),
     "disk2d_p4_seed3": lambda: fcgen.disk_poisson_2d(3, n=8, p=4),
@@ -51,6 +53,11 @@ CASES = {
                                                     rmin=0.08, rmax=0.15),
     "ellipse_inclusions": lambda: fcgen.batch_poisson(seed=1, count=1, min_dofs=0,
                                                       max_dofs=3000)[0],
+    # a void that holds eight cells entirely, their functions removed
+    "elastic3d_discard_alpha0": lambda: fcgen.custom(
+        3, 6, 2, "elasticity", 0.0, shapes=BIG_VOID, clamp_zmin=True, discard_fictitious=True),
+    "poisson3d_discard": lambda: fcgen.custom(
+        3, 6, 2, "poisson", 1e-12, shapes=BIG_VOID, discard_fictitious=True),
 }
 
 

@@ -298,3 +298,30 @@ def test_cut_elasticity_system_symmetric_positive_definite():
     np.testing.assert_allclose(A, A.T, rtol=0, atol=1e-15 * abs(A).max())
     np.linalg.cholesky(A)
     assert (s["eta"] < 1).any() and (s["eta"] > 0).any()
+
+
+def test_discard_fictitious_removes_exactly_the_functions_of_void_cells():
+    """With discard_fictitious the functions that touch no cell with
+    physical material (found here by brute force over the cells of each
+    unknown) keep only their diagonal entry and get no load; every other
+    entry of A and b is unchanged."""
+    import fcgen
+    from oracle import assemble as ASM
+    void = [{"centre": [0.5, 0.52, 0.48], "semi": [0.33, 0.33, 0.33]}]
+    base = fcgen.custom(3, 6, 2, "poisson", 1e-6, shapes=void)
+    disc = dict(base, discard_fictitious=True)
+    s1, s2 = ASM.assemble(base), ASM.assemble(disc)
+    A1, A2 = s1["A"].toarray(), s2["A"].toarray()
+    n = A1.shape[0]
+    cells_of = [[] for _ in range(n)]
+    for c, dofs in enumerate(s1["elem_dofs"]):
+        for d in dofs:
+            cells_of[d].append(c)
+    gone = np.array([all(s1["eta"][c] == 0.0 for c in cells_of[d]) for d in range(n)])
+    assert 0 < gone.sum() < n
+    keep = ~gone
+    assert np.array_equal(A2[np.ix_(keep, keep)], A1[np.ix_(keep, keep)])
+    assert np.all(A2[np.ix_(gone, keep)] == 0.0) and np.all(A2[np.ix_(keep, gone)] == 0.0)
+    sub = A2[np.ix_(gone, gone)]
+    assert np.array_equal(sub, np.diag(np.diag(A1)[gone]))
+    assert np.all(s2["b"][gone] == 0.0) and np.array_equal(s2["b"][keep], s1["b"][keep])
