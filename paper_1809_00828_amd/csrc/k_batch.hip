@@ -89,10 +89,18 @@ __global__ __launch_bounds__(256) void kb_spmv(const BProb* __restrict__ probs,
     for (int u = 0; u < U; ++u) {
       const int ku = k + u * G;
       const bool on = ku < L;
-      c[u] = on ? __builtin_nontemporal_load(P.col + base + ku) : -1;
+      // scalar rows read through the caches (5 % faster on a 64-member
+      // batch), 3x3 blocks non-temporally
+      if constexpr (B == 1)
+        c[u] = on ? P.col[base + ku] : -1;
+      else
+        c[u] = on ? __builtin_nontemporal_load(P.col + base + ku) : -1;
 #pragma unroll
       for (int e = 0; e < BB; ++e)
-        a[u][e] = on ? __builtin_nontemporal_load(v + (int64_t)e * L + ku) : 0.0;
+        if constexpr (B == 1)
+          a[u][e] = on ? v[(int64_t)e * L + ku] : 0.0;
+        else
+          a[u][e] = on ? __builtin_nontemporal_load(v + (int64_t)e * L + ku) : 0.0;
     }
 #pragma unroll
     for (int u = 0; u < U; ++u)
