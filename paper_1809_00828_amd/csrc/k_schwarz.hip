@@ -82,7 +82,10 @@ __global__ __launch_bounds__(256) void k_schwarz_sym_staged(
     const int32_t* __restrict__ list, const int32_t* __restrict__ skip) {
   using A = typename Acc<T>::type;
   constexpr int kStageRows = StageRows<T>::value;
-  __shared__ double rB[256];
+  // the gathered residual is kept in the accumulation type: an FP32 copy
+  // rounds it to FP32 at every use anyway, and half-width entries halve the
+  // LDS traffic of the rotated reads
+  __shared__ A rB[256];
   __shared__ T tile[kStageRows][256];
   if (sc && sc->done) return;
   // list: the workgroups handle only the listed blocks; skip: blocks
@@ -97,7 +100,7 @@ __global__ __launch_bounds__(256) void k_schwarz_sym_staged(
   int64_t dof = 0;
   if (act) {
     dof = (int64_t)elem_nodes[e * nn + i / bd] * bd + (i % bd);
-    rB[i] = gather_r(r, q, alpha, dof) * (isd ? isd[dof] : 1.0);
+    rB[i] = (A)(gather_r(r, q, alpha, dof) * (isd ? isd[dof] : 1.0));
   }
   const T* Qb = P + blk * block_stride;
   const int h = m / 2;
