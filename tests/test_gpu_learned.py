@@ -363,3 +363,17 @@ def test_trained_network_gain_and_fallback(torch):
     else:
         assert info["fallbacks"] == 1 and info["iters"] == infp["iters"]
         assert torch.equal(x, xp)
+
+
+def test_fcg_m_above_limit_is_rejected(torch):
+    _, pb, pc = _lib_case("pois8_p2")
+    m = fc.Model(fcgen.unet_init(CH, 2, seed=7), CH)
+    pc.attach(m)
+    b = torch.empty(pb.n, dtype=torch.float64, device="cuda")
+    pb.rhs(b)
+    x = torch.zeros_like(b)
+    with pytest.raises(fc.FcError) as ei:
+        fc.pcg_solve(pb, pc, b, x, tol=1e-8, stop="residual", mode="learned", fcg_m=65)
+    assert ei.value.status == 1   # FC_E_ARG
+    info = fc.pcg_solve(pb, pc, b, x, tol=1e-8, stop="residual", mode="learned", fcg_m=64)
+    assert info["status"] == "OK"
