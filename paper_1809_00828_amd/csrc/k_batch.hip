@@ -193,6 +193,8 @@ __global__ __launch_bounds__(256) void kb_schwarz(const BProb* __restrict__ prob
     if (!active) return;
     P.y[blk * m + i] = sym_row<double>(P.Q + blk * stride, &rB[w * 64 + lb * m], m, i);
   } else {
+    // one block per workgroup, its stored rows staged through LDS
+    __shared__ double tile[StageRows<double>::value][256];
     const int64_t blk = it.tile;
     const int i = threadIdx.x;
     if (i < m) {
@@ -200,9 +202,8 @@ __global__ __launch_bounds__(256) void kb_schwarz(const BProb* __restrict__ prob
       const int64_t dof = (int64_t)P.elem_nodes[e * P.nn + i / P.bdim] * P.bdim + (i % P.bdim);
       rB[i] = gather_r(r, q, alpha, dof);
     }
-    __syncthreads();
-    if (i >= m) return;
-    P.y[blk * m + i] = sym_row<double>(P.Q + blk * stride, rB, m, i);
+    const double v = sym_block_staged<double>(P.Q + blk * stride, rB, m, i, tile);
+    if (i < m) P.y[blk * m + i] = v;
   }
 }
 

@@ -63,16 +63,7 @@ __global__ __launch_bounds__(256) void k_schwarz_large(
   y[blk * m + i] = isd ? v * isd[dof] : v;
 }
 
-// m > 64, symmetric layout staged through LDS: chunks of kRows stored rows
-// are loaded with coalesced non-temporal loads (every thread its own entry),
-// written to LDS, and the rotated entries are read back from LDS, so HBM
-// and L2 see each stored entry exactly once.  A chunk is 16 KB of LDS:
-// 8 rows of FP64 or 16 of FP32 (twice the loads in flight per barrier).
-template <typename T>
-struct StageRows {
-  static constexpr int value = sizeof(T) == 8 ? 8 : 16;
-};
-
+// m > 64, symmetric layout staged through LDS (sym_block_staged).
 template <typename T>
 __global__ __launch_bounds__(256) void k_schwarz_sym_staged(
     const T* __restrict__ P, int64_t block_stride, const int32_t* __restrict__ elem_nodes,
@@ -103,41 +94,8 @@ __global__ __launch_bounds__(256) void k_schwarz_sym_staged(
     rB[i] = (A)(gather_r(r, q, alpha, dof) * (isd ? isd[dof] : 1.0));
   }
   const T* Qb = P + blk * block_stride;
-  const int h = m / 2;
-  const bool even = (m & 1) == 0;
-  A acc0 = 0, acc1 = 0;
-  int ip = i, im = i;
-  for (int k0 = 0; k0 <= h; k0 += kStageRows) {
-    T v[kStageRows];
-#pragma unroll
-    for (int kk = 0; kk < kStageRows; ++kk) {
-      const int k = k0 + kk;
-      v[kk] = (act && k <= h) ? __builtin_nontemporal_load(Qb + (int64_t)k * m + i) : T(0);
-    }
-    __syncthreads();   // previous chunk's rotated reads are done
-#pragma unroll
-    for (int kk = 0; kk < kStageRows; ++kk) tile[kk][i] = v[kk];
-    __syncthreads();
-    if (act) {
-#pragma unroll
-      for (int kk = 0; kk < kStageRows; ++kk) {
-        const int k = k0 + kk;
-        if (k > h) break;
-        if (k == 0) {
-          acc0 = madd<A>(v[kk], rB[i], acc0);
-          continue;
-        }
-        ip = (ip + 1 == m) ? 0 : ip + 1;
-        im = (im == 0) ? m - 1 : im - 1;
-        acc0 = madd<A>(v[kk], rB[ip], acc0);
-        if (!(even && k == h)) acc1 = madd<A>(tile[kk][im], rB[im], acc1);
-      }
-    }
-  }
-  if (act) {
-    const double v = (double)acc0 + (double)acc1;
-    y[blk * m + i] = isd ? v * isd[dof] : v;
-  }
+  const double v = sym_block_staged<T>(Qb, rB, m, i, tile);
+  if (act) y[blk * m + i] = isd ? v * isd[dof] : v;
 }
 
 // m <= 64: each wave handles floor(64/m) blocks, one lane per output row.

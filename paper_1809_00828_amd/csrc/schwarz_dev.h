@@ -53,6 +53,60 @@ __device__ __forceinline__ double gather_r(const double* r, const double* q, dou
   return v;
 }
 
+// Rows of the wrapped-diagonal layout staged through LDS per chunk: 16 KB
+// of LDS, 8 rows of FP64 or 16 of FP32.
+template <typename T>
+struct StageRows {
+  static constexpr int value = sizeof(T) == 8 ? 8 : 16;
+};
+
+// Symmetric product of one block (m > 64) by a whole workgroup, one output
+// row i per thread (threads with i >= m take part in the barriers only):
+// chunks of stored rows are loaded with coalesced non-temporal loads, every
+// thread its own entry, written to LDS, and the rotated entries are read
+// back from LDS, so HBM and L2 see each stored entry exactly once.  rB holds
+// the block's gathered right-hand side (m entries, in LDS).
+template <typename T, typename RB>
+__device__ __forceinline__ double sym_block_staged(const T* __restrict__ Qb, const RB* rB,
+                                                   int m, int i,
+                                                   T (*tile)[256]) {
+  using A = typename Acc<T>::type;
+  constexpr int kStageRows = StageRows<T>::value;
+  const bool act = i < m;
+  const int h = m / 2;
+  const bool even = (m & 1) == 0;
+  A acc0 = 0, acc1 = 0;
+  int ip = i, im = i;
+  for (int k0 = 0; k0 <= h; k0 += kStageRows) {
+    T v[kStageRows];
+#pragma unroll
+    for (int kk = 0; kk < kStageRows; ++kk) {
+      const int k = k0 + kk;
+      v[kk] = (act && k <= h) ? __builtin_nontemporal_load(Qb + (int64_t)k * m + i) : T(0);
+    }
+    __syncthreads();   // previous chunk's rotated reads are done
+#pragma unroll
+    for (int kk = 0; kk < kStageRows; ++kk) tile[kk][i] = v[kk];
+    __syncthreads();
+    if (act) {
+#pragma unroll
+      for (int kk = 0; kk < kStageRows; ++kk) {
+        const int k = k0 + kk;
+        if (k > h) break;
+        if (k == 0) {
+          acc0 = madd<A>(v[kk], rB[i], acc0);
+          continue;
+        }
+        ip = (ip + 1 == m) ? 0 : ip + 1;
+        im = (im == 0) ? m - 1 : im - 1;
+        acc0 = madd<A>(v[kk], rB[ip], acc0);
+        if (!(even && k == h)) acc1 = madd<A>(tile[kk][im], rB[im], acc1);
+      }
+    }
+  }
+  return (double)acc0 + (double)acc1;
+}
+
 // Wrapped-diagonal symmetric product for one block row i (0 <= i < m).
 template <typename T>
 __device__ __forceinline__ double sym_row(const T* __restrict__ Qb, const double* rb, int m,
