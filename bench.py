@@ -421,8 +421,8 @@ def main():
                     help="iteration cap of the sweep and comparison runs")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
-              "(the solver holds no multi-GPU path)", file=sys.stderr)
+        print("bench.py runs on exactly one GPU: the solver has no multi-GPU path",
+              file=sys.stderr)
         sys.exit(2)
 
     import torch
