@@ -51,7 +51,7 @@ typedef enum {
   FC_E_NOTCONV = 4,      /* PCG reached maxit; x holds the last iterate   */
   FC_E_BREAKDOWN = 5,    /* (p,Ap) <= 0 or (r,z) <= 0 during PCG          */
   FC_E_NAN = 6,          /* a non-finite value appeared                    */
-  FC_E_UNSUPPORTED = 7   /* a size or option this build does not support */
+  FC_E_UNSUPPORTED = 7   /* a size or option the library does not support */
 } fc_status;
 
 enum { FC_PDE_POISSON = 0, FC_PDE_ELASTICITY = 1 };
