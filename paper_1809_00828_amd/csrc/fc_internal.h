@@ -63,6 +63,11 @@ struct DeviceBsr {
   int32_t* col = nullptr;
   double* val = nullptr;   // row-SoA layout
   float* val32 = nullptr;  // optional FP32 copy, same layout
+  // mixed-precision products: block rows read in FP64 (rows_hi) and from
+  // the FP32 copy (rows_lo), ascending
+  int32_t* rows_hi = nullptr;
+  int32_t* rows_lo = nullptr;
+  int64_t n_hi = 0, n_lo = 0;
 };
 
 struct SolverWs;
@@ -83,7 +88,6 @@ struct fc_problem_s {
   std::vector<double> eta;         // host copy [n_el]
   std::vector<int32_t> elem_nodes_host;
   double* diag = nullptr;          // A_ll [n_dofs]
-  double* sqd = nullptr;           // sqrt(A_ll), with the scaled FP32 matrix
 };
 
 struct fc_precond_s {
@@ -116,8 +120,6 @@ namespace fc {
 // y = A x  (and optionally partial dots (x, y) per workgroup)
 hipError_t launch_spmv(const DeviceBsr& A, const double* x, double* y,
                        hipStream_t s);
-hipError_t launch_spmv_f32(const DeviceBsr& A, const double* x, double* y,
-                           hipStream_t s, const double* rs);
 // time the SpMV group widths on A and keep the fastest in A.group
 hipError_t spmv_autotune(DeviceBsr& A, hipStream_t s);
 // verify on the device that A's columns are the lattice boxes of (dim, n1,

@@ -445,15 +445,6 @@ __global__ __launch_bounds__(256) void k_fcg_dir(const double* __restrict__ z,
   }
 }
 
-// c = a * b elementwise (skipped once the stop flag is set)
-__global__ void k_mul(const double* __restrict__ a, const double* __restrict__ b,
-                      double* __restrict__ c, int64_t n, const CgScalars* __restrict__ sc) {
-  if (sc && sc->done) return;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-       i += (int64_t)gridDim.x * blockDim.x)
-    c[i] = a[i] * b[i];
-}
-
 __global__ void k_copy(const double* __restrict__ a, double* __restrict__ b, int64_t n) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x)
@@ -594,10 +585,9 @@ static hipError_t enqueue_steps(fc_precond_s& pc, SolverWs& w, double* x, int ch
     hipEvent_t* tev_it = (tev && it % every == 0) ? tev : nullptr;
     if (tev_it && (e = hipEventRecord(tev[4 * it + 0], s)) != hipSuccess) return e;
     if (precA == 1) {
-      // scaled FP32 matrix: q = D^{1/2} (fl32(D^{-1/2} A D^{-1/2}) (D^{1/2} p))
-      hipLaunchKernelGGL(k_mul, dim3(pull_grid(n)), dim3(kVecThreads), 0, s, w.p, pb.sqd, w.t,
-                         n, w.sc);
-      e = launch_spmv_pq(pb.A, true, w.t, w.q, w.sc, nullptr, s, pb.sqd);
+      // row-mixed matrix: rows touching cut or fictitious cells in FP64,
+      // the others from the FP32 copy
+      e = launch_spmv_mixed(pb.A, w.p, w.q, w.sc, s);
       if (e != hipSuccess) return e;
       if (tev_it && (e = hipEventRecord(tev[4 * it + 1], s)) != hipSuccess) return e;
       hipLaunchKernelGGL(k_cg_pq, dim3(dot_grid(n)), dim3(256), 0, s, w.p, w.q, n, w.partial,
@@ -822,6 +812,39 @@ static fc_status status_of(int done) {
   return FC_E_NOTCONV;
 }
 
+// The refinement's inner matrix: an FP32 copy of A, read only for the block
+// rows whose functions touch no cell with eta_T < 1; the rows of functions
+// on cut or fictitious cells keep FP64, so the low-energy modes of the cut
+// cells (energies down to alpha, below the FP32 unit roundoff) keep their
+// exact entries.  Problems without cell data read every row from FP32.
+static fc_status ensure_mixed_matrix(fc_problem_s& pb, hipStream_t s) {
+  DeviceBsr& A = pb.A;
+  if (A.val32) return FC_OK;
+  const int64_t nr = A.n_rows;
+  std::vector<uint8_t> hi((size_t)nr, 0);
+  const int64_t nn = pb.nn;
+  if (!pb.eta.empty() && (int64_t)pb.elem_nodes_host.size() == pb.n_el * nn)
+    for (int64_t e = 0; e < pb.n_el; ++e)
+      if (pb.eta[e] < 1.0)
+        for (int64_t a = 0; a < nn; ++a) hi[pb.elem_nodes_host[e * nn + a]] = 1;
+  std::vector<int32_t> rh, rl;
+  for (int64_t r = 0; r < nr; ++r) (hi[r] ? rh : rl).push_back((int32_t)r);
+  auto up = [&](const std::vector<int32_t>& v, int32_t** d) -> fc_status {
+    if (v.empty()) return FC_OK;
+    FC_HIP(hipMalloc(d, v.size() * sizeof(int32_t)));
+    FC_HIP(hipMemcpyAsync(*d, v.data(), v.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    return FC_OK;
+  };
+  FC_TRY_ST(up(rh, &A.rows_hi));
+  FC_TRY_ST(up(rl, &A.rows_lo));
+  A.n_hi = (int64_t)rh.size();
+  A.n_lo = (int64_t)rl.size();
+  FC_HIP(hipMalloc(&A.val32, A.nnzb * A.bdim * A.bdim * sizeof(float)));
+  FC_HIP(launch_cast_matrix(A, s));
+  FC_HIP(hipStreamSynchronize(s));   // the host lists must outlive the copies
+  return FC_OK;
+}
+
 fc_status pcg_solve(fc_precond_s& pc, const double* b, double* x, const fc_solve_opts& o,
                     fc_solve_info* info, hipStream_t user) {
   fc_problem_s& pb = *pc.pb;
@@ -884,11 +907,7 @@ fc_status pcg_solve(fc_precond_s& pc, const double* b, double* x, const fc_solve
     // inner solves continue with the FP64 matrix (FP32 rounding can make
     // the stored matrix indefinite on the low-energy fictitious modes).
     int precA = 1;
-    if (!pb.A.val32) {
-      FC_HIP(hipMalloc(&pb.A.val32, pb.A.nnzb * pb.bdim * pb.bdim * sizeof(float)));
-      if (!pb.sqd) FC_HIP(hipMalloc(&pb.sqd, n * sizeof(double)));
-      FC_HIP(launch_cast_matrix(pb.A, pb.diag, pb.sqd, s));
-    }
+    FC_TRY_ST(ensure_mixed_matrix(pb, s));
     if (!w.d) FC_HIP(hipMalloc(&w.d, n * sizeof(double)));
     if (!w.ro) FC_HIP(hipMalloc(&w.ro, n * sizeof(double)));
     FC_HIP(hipEventRecord(w.ev[1], s));

@@ -15,7 +15,6 @@ hipError_t launch_chol_pack(fc_precond_s& pc, hipStream_t s, int32_t* unsafe = n
 hipError_t launch_diag(const fc_problem_s& pb, hipStream_t s);
 hipError_t launch_fallback(const fc_problem_s& pb, fc_precond_s& pc,
                            unsigned long long* d_count, hipStream_t s);
-// A.val32 = FP32 of D^{-1/2} A D^{-1/2}; sqd receives sqrt(diag)
-hipError_t launch_cast_matrix(const DeviceBsr& A, const double* diag, double* sqd,
-                              hipStream_t s);
+// A.val32 = FP32 copy of A.val (same layout)
+hipError_t launch_cast_matrix(const DeviceBsr& A, hipStream_t s);
 }  // namespace fc

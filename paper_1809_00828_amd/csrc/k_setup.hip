@@ -558,42 +558,11 @@ hipError_t launch_fallback(const fc_problem_s& pb, fc_precond_s& pc,
   return hipGetLastError();
 }
 
-// sqd_i = sqrt(A_ii) (1 where A_ii <= 0)
-__global__ void k_sqrt_diag(const double* __restrict__ diag, double* __restrict__ sqd, int64_t n) {
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-       i += (int64_t)gridDim.x * blockDim.x)
-    sqd[i] = diag[i] > 0.0 ? sqrt(diag[i]) : 1.0;
-}
-
-// FP32 copy of the diagonally scaled matrix D^{-1/2} A D^{-1/2} (D = diag A),
-// same row-SoA layout; one thread per block row.
-__global__ void k_cast_scaled_f32(const int32_t* __restrict__ rowptr,
-                                  const int32_t* __restrict__ col, const double* __restrict__ val,
-                                  const double* __restrict__ sqd, int bd, int64_t n_rows,
-                                  float* __restrict__ out) {
-  const int bb = bd * bd;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_rows;
-       i += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t base = rowptr[i];
-    const int L = rowptr[i + 1] - (int32_t)base;
-    for (int k = 0; k < L; ++k) {
-      const int64_t c = col[base + k];
-      for (int e = 0; e < bb; ++e) {
-        const int a = e / bd, b = e % bd;
-        const int64_t pos = base * bb + (int64_t)e * L + k;
-        out[pos] = (float)(val[pos] / (sqd[i * bd + a] * sqd[c * bd + b]));
-      }
-    }
-  }
-}
-
-hipError_t launch_cast_matrix(const DeviceBsr& A, const double* diag, double* sqd,
-                              hipStream_t s) {
+// FP32 copy of the matrix values, same layout (k_cast_f32 above)
+hipError_t launch_cast_matrix(const DeviceBsr& A, hipStream_t s) {
   const int64_t n = A.nnzb * A.bdim * A.bdim;
   if (!A.val32 || n == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_sqrt_diag, dim3(1024), dim3(256), 0, s, diag, sqd, A.n_rows * A.bdim);
-  hipLaunchKernelGGL(k_cast_scaled_f32, dim3((unsigned)((A.n_rows + 255) / 256)), dim3(256), 0, s,
-                     A.rowptr, A.col, A.val, sqd, A.bdim, A.n_rows, A.val32);
+  hipLaunchKernelGGL(k_cast_f32, dim3(4096), dim3(256), 0, s, A.val, A.val32, n);
   return hipGetLastError();
 }
 

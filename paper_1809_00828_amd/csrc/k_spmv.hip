@@ -33,15 +33,15 @@ __device__ __forceinline__ T stream_load(const T* p) {
   else return *p;
 }
 
-// rs (may be null): y_i *= rs_i, for the scaled FP32 copy D^{-1/2} A D^{-1/2}
-// applied to x already multiplied by D^{1/2}.
+// rows (may be null): the launch covers only these n_rows block rows
+// (ascending), the others of y are left alone.
 // kLat: columns computed from the lattice box (col is not read).
 template <int B, int G, typename T, bool kLat>
 __global__ __launch_bounds__(256) void k_spmv_bsr(
     const int32_t* __restrict__ rowptr, const int32_t* __restrict__ col,
     const T* __restrict__ val, const double* __restrict__ x,
     double* __restrict__ y, int64_t n_rows, const CgScalars* __restrict__ sc,
-    double* __restrict__ partial, const double* __restrict__ rs, const LatticeInfo lat) {
+    double* __restrict__ partial, const int32_t* __restrict__ rows, const LatticeInfo lat) {
   constexpr int BB = B * B;
   constexpr int RPW = 256 / G;   // rows per tile
   __shared__ double lds[16];
@@ -54,8 +54,9 @@ __global__ __launch_bounds__(256) void k_spmv_bsr(
   const int lane = threadIdx.x % G;
   double dot = 0.0;
   for (int64_t tile = t0 + j; tile < t1; tile += per) {
-    const int64_t row = tile * RPW + threadIdx.x / G;
-    if (row >= n_rows) continue;
+    const int64_t idx = tile * RPW + threadIdx.x / G;
+    if (idx >= n_rows) continue;
+    const int64_t row = rows ? (int64_t)rows[idx] : idx;
     const int64_t base = rowptr[row];
     const int L = rowptr[row + 1] - (int32_t)base;
     const T* v = val + base * BB;
@@ -114,7 +115,6 @@ __global__ __launch_bounds__(256) void k_spmv_bsr(
     if (lane == 0) {
 #pragma unroll
       for (int i = 0; i < B; ++i) {
-        if (rs) acc[i] *= rs[row * B + i];
         y[row * B + i] = acc[i];
         if (partial) dot = fma(x[row * B + i], acc[i], dot);
       }
@@ -159,11 +159,12 @@ static int64_t fused_grid(const DeviceBsr& A) {
 template <int B, typename T>
 static hipError_t spmv_dispatch(const DeviceBsr& A, const T* val, const double* x,
                                 double* y, hipStream_t s, const CgScalars* sc,
-                                double* partial, const double* rs) {
+                                double* partial, const int32_t* rows, int64_t n_list) {
   const int G = group_width(A);
-  const int64_t nt = num_tiles(A);
+  const int64_t n_rows = rows ? n_list : A.n_rows;
+  const int64_t nt = (n_rows + 256 / G - 1) / (256 / G);
   if (nt == 0) return hipSuccess;
-  const int64_t nb = partial ? fused_grid(A) : nt;
+  const int64_t nb = (partial && !rows) ? fused_grid(A) : nt;
   static const bool lat_allowed = env_int("FC_SPMV_LATTICE", 1) != 0;
   const bool lat = lat_allowed && A.lat.dim > 0;
   dim3 grid((unsigned)nb), block(256);
@@ -171,10 +172,10 @@ static hipError_t spmv_dispatch(const DeviceBsr& A, const T* val, const double* 
   case GG:                                                                                \
     if (lat)                                                                              \
       hipLaunchKernelGGL((k_spmv_bsr<B, GG, T, true>), grid, block, 0, s, A.rowptr, A.col, \
-                         val, x, y, A.n_rows, sc, partial, rs, A.lat);                    \
+                         val, x, y, n_rows, sc, partial, rows, A.lat);                    \
     else                                                                                  \
       hipLaunchKernelGGL((k_spmv_bsr<B, GG, T, false>), grid, block, 0, s, A.rowptr,       \
-                         A.col, val, x, y, A.n_rows, sc, partial, rs, A.lat);             \
+                         A.col, val, x, y, n_rows, sc, partial, rows, A.lat);             \
     break;
   switch (G) {
     FC_SPMV_CASE(8)
@@ -189,22 +190,17 @@ static hipError_t spmv_dispatch(const DeviceBsr& A, const T* val, const double* 
 template <typename T>
 static hipError_t spmv_any(const DeviceBsr& A, const T* val, const double* x, double* y,
                            hipStream_t s, const CgScalars* sc, double* partial,
-                           const double* rs = nullptr) {
+                           const int32_t* rows = nullptr, int64_t n_list = 0) {
   switch (A.bdim) {
-    case 1: return spmv_dispatch<1, T>(A, val, x, y, s, sc, partial, rs);
-    case 2: return spmv_dispatch<2, T>(A, val, x, y, s, sc, partial, rs);
-    case 3: return spmv_dispatch<3, T>(A, val, x, y, s, sc, partial, rs);
+    case 1: return spmv_dispatch<1, T>(A, val, x, y, s, sc, partial, rows, n_list);
+    case 2: return spmv_dispatch<2, T>(A, val, x, y, s, sc, partial, rows, n_list);
+    case 3: return spmv_dispatch<3, T>(A, val, x, y, s, sc, partial, rows, n_list);
   }
   return hipErrorInvalidValue;
 }
 
 hipError_t launch_spmv(const DeviceBsr& A, const double* x, double* y, hipStream_t s) {
   return spmv_any<double>(A, A.val, x, y, s, nullptr, nullptr);
-}
-
-hipError_t launch_spmv_f32(const DeviceBsr& A, const double* x, double* y, hipStream_t s,
-                           const double* rs) {
-  return spmv_any<float>(A, A.val32, x, y, s, nullptr, nullptr, rs);
 }
 
 int spmv_num_blocks(const DeviceBsr& A) { return (int)fused_grid(A); }
@@ -288,9 +284,19 @@ hipError_t spmv_autotune(DeviceBsr& A, hipStream_t s) {
 }
 
 hipError_t launch_spmv_pq(const DeviceBsr& A, bool f32, const double* p, double* q,
-                          CgScalars* sc, double* partial, hipStream_t s, const double* rs) {
-  if (f32) return spmv_any<float>(A, A.val32, p, q, s, sc, partial, rs);
+                          CgScalars* sc, double* partial, hipStream_t s) {
+  if (f32) return spmv_any<float>(A, A.val32, p, q, s, sc, partial);
   return spmv_any<double>(A, A.val, p, q, s, sc, partial);
+}
+
+hipError_t launch_spmv_mixed(const DeviceBsr& A, const double* p, double* q,
+                             const CgScalars* sc, hipStream_t s) {
+  hipError_t e = hipSuccess;
+  if (A.n_hi > 0 &&
+      (e = spmv_any<double>(A, A.val, p, q, s, sc, nullptr, A.rows_hi, A.n_hi)) != hipSuccess)
+    return e;
+  if (A.n_lo > 0) e = spmv_any<float>(A, A.val32, p, q, s, sc, nullptr, A.rows_lo, A.n_lo);
+  return e;
 }
 
 }  // namespace fc
