@@ -24,9 +24,11 @@
 
 namespace fc {
 
-// Matrix data is read once per product.  3x3 blocks read it non-temporally;
-// scalar rows read it through the caches, which at 64^3 p = 2 is 13 % faster
-// (measured; the non-temporal stream there costs more than it saves).
+// Matrix data is read once per product.  FP64 3x3 blocks read it
+// non-temporally; scalar rows and the FP32 copy read it through the caches,
+// which is 13 % faster at 64^3 p = 2 and 3.5 % for the FP32 rows of the
+// mixed product (measured; there the non-temporal stream costs more than
+// it saves).
 template <bool kNT, typename T>
 __device__ __forceinline__ T stream_load(const T* p) {
   if constexpr (kNT) return __builtin_nontemporal_load(p);
@@ -83,10 +85,10 @@ __global__ __launch_bounds__(256) void k_spmv_bsr(
         if constexpr (kLat)
           c[u] = on ? lattice_col(box, ku, lat.n1) : -1;
         else
-          c[u] = on ? stream_load<B != 1>(col + base + ku) : -1;
+          c[u] = on ? stream_load<B != 1 && sizeof(T) == 8>(col + base + ku) : -1;
 #pragma unroll
         for (int e = 0; e < BB; ++e)
-          a[u][e] = on ? stream_load<B != 1>(v + (int64_t)e * L + ku) : T(0);
+          a[u][e] = on ? stream_load<B != 1 && sizeof(T) == 8>(v + (int64_t)e * L + ku) : T(0);
       }
       double xv[U][B];
 #pragma unroll
