@@ -219,13 +219,15 @@ fc_status fc_apply_M(fc_precond pc, const double* r_dev, double* z_dev,
  *   mode         FC_MODE_F64 plain FP64 PCG;
  *                FC_MODE_IR_F32 / FC_MODE_IR_BF16: iterative refinement --
  *                the FP64 residual b - A x is recomputed outside, and each
- *                correction comes from a PCG run with an FP32 copy of A
- *                (the diagonally scaled D^{-1/2} A D^{-1/2} rounded to FP32,
- *                applied as D^{1/2} (.) D^{1/2}) and the FP32 / BF16 copy
- *                of the local inverses (built with FC_STORE_F32 /
- *                FC_STORE_BF16), FP32 accumulation, FP64
- *                vectors and scalars, stopped at inner_tol (relative to
- *                its right-hand side) or at breakdown.  A correction that
+ *                correction comes from a PCG run with a row-mixed copy of A
+ *                (the block rows of functions that touch a cell with
+ *                eta_T < 1 in FP64, all other rows rounded to FP32; every
+ *                row in FP32 for a problem set up from a bare matrix) and
+ *                the FP32 / BF16 copy of the local inverses (built with
+ *                FC_STORE_F32 / FC_STORE_BF16), FP32 accumulation in the
+ *                FP32 rows and the block products, FP64 vectors and
+ *                scalars, stopped at inner_tol (relative to its right-hand
+ *                side) or at breakdown.  A correction that
  *                does not reduce the FP64 residual by 10 % is undone and the
  *                remaining inner runs use the FP64 matrix (counted in
  *                fc_solve_info.fallbacks).  tol then applies to
