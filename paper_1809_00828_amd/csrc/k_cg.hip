@@ -46,6 +46,7 @@ struct SolverWs {
   int64_t n = 0;
   double *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr, *t = nullptr;
   double *d = nullptr, *ro = nullptr;   // refinement correction and outer residual
+  float* p32 = nullptr;                  // fl32(p) for the mixed product
   double* partial = nullptr;
   int64_t partial_len = 0;
   CgScalars* sc = nullptr;
@@ -71,6 +72,7 @@ void solver_ws_destroy(SolverWs* w) {
   if (w->graph) (void)hipGraphDestroy(w->graph);
   for (auto* p : {w->r, w->z, w->p, w->q, w->t, w->d, w->ro, w->partial, w->ring, w->ring_part})
     if (p) (void)hipFree(p);
+  if (w->p32) (void)hipFree(w->p32);
   if (w->fr) (void)hipFree(w->fr);
   if (w->sc) (void)hipFree(w->sc);
   if (w->host) (void)hipHostFree(w->host);
@@ -445,6 +447,15 @@ __global__ __launch_bounds__(256) void k_fcg_dir(const double* __restrict__ z,
   }
 }
 
+// b = fl32(a) (skipped once the stop flag is set)
+__global__ void k_round_f32(const double* __restrict__ a, float* __restrict__ b, int64_t n,
+                            const CgScalars* __restrict__ sc) {
+  if (sc && sc->done) return;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    b[i] = (float)a[i];
+}
+
 __global__ void k_copy(const double* __restrict__ a, double* __restrict__ b, int64_t n) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x)
@@ -586,8 +597,11 @@ static hipError_t enqueue_steps(fc_precond_s& pc, SolverWs& w, double* x, int ch
     if (tev_it && (e = hipEventRecord(tev[4 * it + 0], s)) != hipSuccess) return e;
     if (precA == 1) {
       // row-mixed matrix: rows touching cut or fictitious cells in FP64,
-      // the others from the FP32 copy
-      e = launch_spmv_mixed(pb.A, w.p, w.q, w.sc, s);
+      // the others from the FP32 copy, which gather p rounded to FP32 (half
+      // the gathered bytes; those products round p to FP32 anyway)
+      hipLaunchKernelGGL(k_round_f32, dim3(pull_grid(n)), dim3(kVecThreads), 0, s, w.p, w.p32,
+                         n, w.sc);
+      e = launch_spmv_mixed(pb.A, w.p, w.p32, w.q, w.sc, s);
       if (e != hipSuccess) return e;
       if (tev_it && (e = hipEventRecord(tev[4 * it + 1], s)) != hipSuccess) return e;
       hipLaunchKernelGGL(k_cg_pq, dim3(dot_grid(n)), dim3(256), 0, s, w.p, w.q, n, w.partial,
@@ -596,7 +610,7 @@ static hipError_t enqueue_steps(fc_precond_s& pc, SolverWs& w, double* x, int ch
                          w.sc);
     } else if (split_dot()) {
       // SpMV without its fused dot, then (p, q) and alpha in one reduction
-      e = launch_spmv_pq(pb.A, false, w.p, w.q, w.sc, nullptr, s);
+      e = launch_spmv_pq(pb.A, w.p, w.q, w.sc, nullptr, s);
       if (e != hipSuccess) return e;
       if (tev_it && (e = hipEventRecord(tev[4 * it + 1], s)) != hipSuccess) return e;
       hipLaunchKernelGGL(k_cg_pq, dim3(dot_grid(n)), dim3(256), 0, s, w.p, w.q, n, w.partial,
@@ -604,7 +618,7 @@ static hipError_t enqueue_steps(fc_precond_s& pc, SolverWs& w, double* x, int ch
       hipLaunchKernelGGL(k_cg_alpha, dim3(1), dim3(1024), 0, s, w.partial, (int)dot_grid(n),
                          w.sc);
     } else {
-      e = launch_spmv_pq(pb.A, false, w.p, w.q, w.sc, w.partial, s);
+      e = launch_spmv_pq(pb.A, w.p, w.q, w.sc, w.partial, s);
       if (e != hipSuccess) return e;
       if (tev_it && (e = hipEventRecord(tev[4 * it + 1], s)) != hipSuccess) return e;
       hipLaunchKernelGGL(k_cg_alpha, dim3(1), dim3(1024), 0, s, w.partial,
@@ -908,6 +922,7 @@ fc_status pcg_solve(fc_precond_s& pc, const double* b, double* x, const fc_solve
     // the stored matrix indefinite on the low-energy fictitious modes).
     int precA = 1;
     FC_TRY_ST(ensure_mixed_matrix(pb, s));
+    if (!w.p32) FC_HIP(hipMalloc(&w.p32, n * sizeof(float)));
     if (!w.d) FC_HIP(hipMalloc(&w.d, n * sizeof(double)));
     if (!w.ro) FC_HIP(hipMalloc(&w.ro, n * sizeof(double)));
     FC_HIP(hipEventRecord(w.ev[1], s));

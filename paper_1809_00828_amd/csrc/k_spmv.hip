@@ -38,10 +38,12 @@ __device__ __forceinline__ T stream_load(const T* p) {
 // rows (may be null): the launch covers only these n_rows block rows
 // (ascending), the others of y are left alone.
 // kLat: columns computed from the lattice box (col is not read).
-template <int B, int G, typename T, bool kLat>
+// XT: type of x (FP32 for the FP32 rows of the mixed product, which round
+// x to FP32 before every product anyway).
+template <int B, int G, typename T, bool kLat, typename XT>
 __global__ __launch_bounds__(256) void k_spmv_bsr(
     const int32_t* __restrict__ rowptr, const int32_t* __restrict__ col,
-    const T* __restrict__ val, const double* __restrict__ x,
+    const T* __restrict__ val, const XT* __restrict__ x,
     double* __restrict__ y, int64_t n_rows, const CgScalars* __restrict__ sc,
     double* __restrict__ partial, const int32_t* __restrict__ rows, const LatticeInfo lat) {
   constexpr int BB = B * B;
@@ -90,11 +92,11 @@ __global__ __launch_bounds__(256) void k_spmv_bsr(
         for (int e = 0; e < BB; ++e)
           a[u][e] = on ? stream_load<B != 1 && sizeof(T) == 8>(v + (int64_t)e * L + ku) : T(0);
       }
-      double xv[U][B];
+      XT xv[U][B];
 #pragma unroll
       for (int u = 0; u < U; ++u)
 #pragma unroll
-        for (int jj = 0; jj < B; ++jj) xv[u][jj] = c[u] >= 0 ? x[(int64_t)c[u] * B + jj] : 0.0;
+        for (int jj = 0; jj < B; ++jj) xv[u][jj] = c[u] >= 0 ? x[(int64_t)c[u] * B + jj] : XT(0);
 #pragma unroll
       for (int u = 0; u < U; ++u)
 #pragma unroll
@@ -102,7 +104,7 @@ __global__ __launch_bounds__(256) void k_spmv_bsr(
 #pragma unroll
           for (int jj = 0; jj < B; ++jj) {
             if constexpr (sizeof(T) == 8)
-              acc[i] = fma((double)a[u][i * B + jj], xv[u][jj], acc[i]);
+              acc[i] = fma((double)a[u][i * B + jj], (double)xv[u][jj], acc[i]);
             else
               accf[i] = fmaf((float)a[u][i * B + jj], (float)xv[u][jj], accf[i]);
           }
@@ -118,7 +120,7 @@ __global__ __launch_bounds__(256) void k_spmv_bsr(
 #pragma unroll
       for (int i = 0; i < B; ++i) {
         y[row * B + i] = acc[i];
-        if (partial) dot = fma(x[row * B + i], acc[i], dot);
+        if (partial) dot = fma((double)x[row * B + i], acc[i], dot);
       }
     }
   }
@@ -158,8 +160,8 @@ static int64_t fused_grid(const DeviceBsr& A) {
   return cap > 0 ? std::min<int64_t>(nt, cap) : nt;
 }
 
-template <int B, typename T>
-static hipError_t spmv_dispatch(const DeviceBsr& A, const T* val, const double* x,
+template <int B, typename T, typename XT>
+static hipError_t spmv_dispatch(const DeviceBsr& A, const T* val, const XT* x,
                                 double* y, hipStream_t s, const CgScalars* sc,
                                 double* partial, const int32_t* rows, int64_t n_list) {
   const int G = group_width(A);
@@ -173,10 +175,10 @@ static hipError_t spmv_dispatch(const DeviceBsr& A, const T* val, const double* 
 #define FC_SPMV_CASE(GG)                                                                  \
   case GG:                                                                                \
     if (lat)                                                                              \
-      hipLaunchKernelGGL((k_spmv_bsr<B, GG, T, true>), grid, block, 0, s, A.rowptr, A.col, \
+      hipLaunchKernelGGL((k_spmv_bsr<B, GG, T, true, XT>), grid, block, 0, s, A.rowptr, A.col, \
                          val, x, y, n_rows, sc, partial, rows, A.lat);                    \
     else                                                                                  \
-      hipLaunchKernelGGL((k_spmv_bsr<B, GG, T, false>), grid, block, 0, s, A.rowptr,       \
+      hipLaunchKernelGGL((k_spmv_bsr<B, GG, T, false, XT>), grid, block, 0, s, A.rowptr,   \
                          A.col, val, x, y, n_rows, sc, partial, rows, A.lat);             \
     break;
   switch (G) {
@@ -189,14 +191,14 @@ static hipError_t spmv_dispatch(const DeviceBsr& A, const T* val, const double* 
   return hipGetLastError();
 }
 
-template <typename T>
-static hipError_t spmv_any(const DeviceBsr& A, const T* val, const double* x, double* y,
+template <typename T, typename XT = double>
+static hipError_t spmv_any(const DeviceBsr& A, const T* val, const XT* x, double* y,
                            hipStream_t s, const CgScalars* sc, double* partial,
                            const int32_t* rows = nullptr, int64_t n_list = 0) {
   switch (A.bdim) {
-    case 1: return spmv_dispatch<1, T>(A, val, x, y, s, sc, partial, rows, n_list);
-    case 2: return spmv_dispatch<2, T>(A, val, x, y, s, sc, partial, rows, n_list);
-    case 3: return spmv_dispatch<3, T>(A, val, x, y, s, sc, partial, rows, n_list);
+    case 1: return spmv_dispatch<1, T, XT>(A, val, x, y, s, sc, partial, rows, n_list);
+    case 2: return spmv_dispatch<2, T, XT>(A, val, x, y, s, sc, partial, rows, n_list);
+    case 3: return spmv_dispatch<3, T, XT>(A, val, x, y, s, sc, partial, rows, n_list);
   }
   return hipErrorInvalidValue;
 }
@@ -285,19 +287,19 @@ hipError_t spmv_autotune(DeviceBsr& A, hipStream_t s) {
   return err;
 }
 
-hipError_t launch_spmv_pq(const DeviceBsr& A, bool f32, const double* p, double* q,
-                          CgScalars* sc, double* partial, hipStream_t s) {
-  if (f32) return spmv_any<float>(A, A.val32, p, q, s, sc, partial);
+hipError_t launch_spmv_pq(const DeviceBsr& A, const double* p, double* q, CgScalars* sc,
+                          double* partial, hipStream_t s) {
   return spmv_any<double>(A, A.val, p, q, s, sc, partial);
 }
 
-hipError_t launch_spmv_mixed(const DeviceBsr& A, const double* p, double* q,
+hipError_t launch_spmv_mixed(const DeviceBsr& A, const double* p, const float* p32, double* q,
                              const CgScalars* sc, hipStream_t s) {
   hipError_t e = hipSuccess;
   if (A.n_hi > 0 &&
       (e = spmv_any<double>(A, A.val, p, q, s, sc, nullptr, A.rows_hi, A.n_hi)) != hipSuccess)
     return e;
-  if (A.n_lo > 0) e = spmv_any<float>(A, A.val32, p, q, s, sc, nullptr, A.rows_lo, A.n_lo);
+  if (A.n_lo > 0)
+    e = spmv_any<float, float>(A, A.val32, p32, q, s, sc, nullptr, A.rows_lo, A.n_lo);
   return e;
 }
 
