@@ -585,8 +585,7 @@ static bool split_dot() {
 
 // Enqueue `chunk` PCG steps on stream s (with timing events when tev).
 // precA: 0 = FP64 matrix, 1 = row-mixed FP64/FP32 matrix; precS: 0/1/2 =
-// FP64/FP32/BF16
-// local inverses.
+// FP64/FP32/BF16 local inverses.
 static hipError_t enqueue_steps(fc_precond_s& pc, SolverWs& w, double* x, int chunk, int precA,
                                 int precS, hipStream_t s, hipEvent_t* tev = nullptr,
                                 CoarseCtx* learn = nullptr, int every = 1, int fcg_m = 1) {
