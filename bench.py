@@ -31,7 +31,7 @@ HBM_PEAK_GBS = 8000.0
 # counter passes (FETCH_SIZE, WRITE_SIZE), scaled by what the same counters
 # read for a plain 4 GiB copy (profiles/pcg_fp64_elastic32_p3_hbm_counters.md);
 # to be re-measured whenever one of these kernels changes.
-TRAFFIC = {"spmv": 8.3640e9, "schwarz": 4.6881e9}
+TRAFFIC = {"spmv": 8.3640e9, "spmv_shared": None, "schwarz": 4.6881e9}
 METRIC = "DOF·iter/s and time-to-1e-8 residual: mixed/learned vs plain FP64 PCG"
 
 
@@ -54,7 +54,13 @@ def algorithmic_bytes(info, m, n_blocks, nn):
     # values (and column indices unless the columns follow from the
     # lattice), row pointers, x and q once
     col_bytes = 0 if info.get("lattice_columns") else 4
-    spmv = nnzb * (bd * bd * 8 + col_bytes) + (n // bd + 1) * 4 + 2 * n * 8
+    if info.get("shared_values"):
+        # bitwise-equal rows stored once: the kept values once, one 8-byte
+        # value offset per block row
+        spmv = (info["shared_values"] * 8 + nnzb * col_bytes + (n // bd) * 8
+                + (n // bd + 1) * 4 + 2 * n * 8)
+    else:
+        spmv = nnzb * (bd * bd * 8 + col_bytes) + (n // bd + 1) * 4 + 2 * n * 8
     # stored half of each symmetric P_B once ((m/2+1)*m wrapped diagonals),
     # element node lists, gathered r and q once, y_B written
     schwarz = n_blocks * (m // 2 + 1) * m * 8 + n_blocks * nn * 4 + 2 * n * 8 + n_blocks * m * 8
@@ -504,12 +510,15 @@ def main():
     total_dof_iters = n * sum(iters)
     # the counter traffic was taken on the elasticity workload
     on_bench_workload = not args.small and args.workload == "elastic32"
+    shared = bool(info.get("shared_values"))
     spmv_name = (f"k_spmv_bsr<{info['bsr_dim']},{info['spmv_group']},double,"
-                 f"{'lattice' if info.get('lattice_columns') else 'columns'}> (SpMV q = A p)")
+                 f"{'lattice' if info.get('lattice_columns') else 'columns'}"
+                 f"{',shared' if shared else ''}> (SpMV q = A p)")
     k_spmv = {"bound": "hbm", "kernel": spmv_name,
               "achieved": gbs_spmv, "peak": HBM_PEAK_GBS, "unit": "GB/s",
               "frac": gbs_spmv / HBM_PEAK_GBS,
-              "traffic": TRAFFIC["spmv"] if on_bench_workload else None,
+              "traffic": (TRAFFIC["spmv_shared" if shared else "spmv"]
+                          if on_bench_workload else None),
               "bytes_per_launch": spmv_b, "avg_ms": ms_spmv}
     schw_name = ("k_schwarz_sym_staged<double>" if m > 64 else "k_schwarz_small<double,sym>")
     k_schw = {"bound": "hbm", "kernel": schw_name + " (block products)",
@@ -528,7 +537,9 @@ def main():
         "dtype": "f64", "data": "synthetic",
         "config": {"workload": wl, "n_dofs": n, "nnz_blocks": info["nnzb"],
                    "blocks": pinfo["n_blocks"], "block_size": m, "tol": args.tol,
-                   "stop": "relative residual ||b-Ax||/||b||", "form": "fp64"},
+                   "stop": "relative residual ||b-Ax||/||b||", "form": "fp64",
+                   "shared_rows": info.get("shared_rows", 0),
+                   "shared_values": info.get("shared_values", 0)},
         "roofline": dominant,
         "roofline_other": other,
         "iters": iters, "status": status,

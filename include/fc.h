@@ -119,6 +119,19 @@ fc_status fc_host_system_export(fc_host_system hs, int32_t* rowptr, int32_t* col
                                 double* eta);
 fc_status fc_setup_from_host(fc_host_system hs, void* stream, fc_problem* out);
 void fc_host_system_destroy(fc_host_system hs);
+/* Shared rows of the assembled matrix (Sec. 3.1, Eq. 2: on the Cartesian
+ * cell grid every block row whose supporting cells are uncut repeats one of
+ * a few stencils).  Block rows whose stored values are bitwise equal (same
+ * length, same values in the same order) keep one copy.  *distinct_rows and
+ * *n_values receive the number of kept rows and of their values; when ofs
+ * and vals are not NULL, ofs[n/bsr_dim] receives each block row's offset
+ * into vals and vals[*n_values] the kept rows, each row entry-major
+ * (value e of the row's k-th block at ofs[row] + e*L + k, L the row's block
+ * count).  The first row seen with given values is the one kept.  Host
+ * only; the caller sizes ofs and vals from a first call with both NULL.
+ * Errors: FC_E_ARG (NULL hs, distinct_rows or n_values), FC_E_NOMEM. */
+fc_status fc_host_system_share(fc_host_system hs, int64_t* distinct_rows, int64_t* n_values,
+                               int64_t* ofs, double* vals);
 
 /* Wrap an assembled system given by the caller (host arrays, copied).
  * BSR with bsr_dim x bsr_dim blocks stored row-major per block:
@@ -195,6 +208,14 @@ fc_status fc_precond_info(fc_precond pc, int64_t* n_blocks,
  * and its columns were verified to be each row's lattice box, so the
  * column array is not read) or read (0). */
 fc_status fc_spmv_info(fc_problem pb, int32_t* group, int32_t* lattice);
+/* Shared rows used by this problem's FP64 products (the layout of
+ * fc_host_system_share, uploaded at set-up): kept rows and their values,
+ * both 0 when the products read the full matrix.  The environment variable
+ * FC_SPMV_SHARE, read at every set-up, selects 0: never share, 1: share
+ * whenever a row repeats, unset or other: share when the kept rows hold at
+ * most three quarters of the values.  Products are bitwise the same either
+ * way; sharing lets repeated rows be read from the caches instead of HBM. */
+fc_status fc_spmv_share_info(fc_problem pb, int64_t* distinct_rows, int64_t* distinct_values);
 /* FP32 copy (FC_STORE_F32): the diagonally scaled inverse D^1/2 P_B D^1/2
  * (D = diag(A) on the block) rounded to FP32, kept for the blocks where a
  * Cholesky factorisation of the rounded matrix shows it positive definite

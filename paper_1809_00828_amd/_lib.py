@@ -38,6 +38,7 @@ EXPORTS = [
     "fc_learned_attach", "fc_coarse_grid", "fc_coarse_channels", "fc_coarse_restrict",
     "fc_coarse_prolong", "fc_coarse_apply", "fc_learned_stats", "fc_learned_snapshots",
     "fc_learned_validate", "fc_precond_lowprec_info", "fc_spmv_info",
+    "fc_host_system_share", "fc_spmv_share_info",
 ]
 
 
@@ -111,6 +112,8 @@ def load():
         "fc_precond_info": [vp, P(i64), P(i64), P(i64), P(i64)],
         "fc_precond_lowprec_info": [vp, P(i64), P(i64)],
         "fc_spmv_info": [vp, P(i32), P(i32)],
+        "fc_spmv_share_info": [vp, P(i64), P(i64)],
+        "fc_host_system_share": [vp, P(i64), P(i64), vp, vp],
         "fc_get_block_inverse": [vp, i64, vp],
         "fc_apply_M": [vp, dp, dp, vp],
         "fc_pcg_solve": [vp, vp, dp, dp, P(SolveOpts), P(SolveInfo), vp],
@@ -243,6 +246,19 @@ class HostSystem:
         return {"rowptr": rp, "col": col, "val": val.reshape(-1, bd, bd), "rhs": rhs,
                 "elem_dofs": ed.reshape(inf["n_el"], inf["m"]), "eta": eta, **inf}
 
+    def share(self):
+        """Bitwise-equal block rows kept once (fc_host_system_share): the
+        per-row offsets and the kept rows, entry-major per row."""
+        lib = load()
+        nr, nv = C.c_int64(), C.c_int64()
+        _check(lib.fc_host_system_share(self._h, C.byref(nr), C.byref(nv), None, None))
+        bd = self.info()["bsr_dim"]
+        ofs = np.zeros(self.info()["n_dofs"] // bd, np.int64)
+        vals = np.zeros(nv.value, np.float64)
+        _check(lib.fc_host_system_share(self._h, C.byref(nr), C.byref(nv), _np_ptr(ofs),
+                                        _np_ptr(vals)))
+        return {"distinct_rows": nr.value, "ofs": ofs, "vals": vals}
+
     def upload(self, stream=None):
         h = C.c_void_p()
         _check(load().fc_setup_from_host(self._h, C.c_void_p(_stream(stream)), C.byref(h)))
@@ -289,9 +305,12 @@ class Problem:
                                           C.byref(m), C.byref(bd)))
             g, lat = C.c_int32(), C.c_int32()
             _check(load().fc_spmv_info(self._h, C.byref(g), C.byref(lat)))
+            sr, sv = C.c_int64(), C.c_int64()
+            _check(load().fc_spmv_share_info(self._h, C.byref(sr), C.byref(sv)))
             self._info = {"n_dofs": n.value, "nnzb": nnzb.value, "n_el": nel.value,
                           "m": m.value, "bsr_dim": bd.value, "spmv_group": g.value,
-                          "lattice_columns": bool(lat.value)}
+                          "lattice_columns": bool(lat.value), "shared_rows": sr.value,
+                          "shared_values": sv.value}
         return self._info
 
     @property

@@ -4,6 +4,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <memory>
 #include <new>
@@ -58,7 +59,8 @@ static fc_status upload(T** p, const T* src, size_t count) {
 static void free_problem(fc_problem_s* pb) {
   if (!pb) return;
   for (void* p : {(void*)pb->A.rowptr, (void*)pb->A.col, (void*)pb->A.val, (void*)pb->A.val32,
-                  (void*)pb->A.rows_hi, (void*)pb->A.rows_lo, (void*)pb->rhs,
+                  (void*)pb->A.rows_hi, (void*)pb->A.rows_lo, (void*)pb->A.vsh,
+                  (void*)pb->A.vofs, (void*)pb->rhs,
                   (void*)pb->elem_nodes, (void*)pb->diag})
     if (p) (void)hipFree(p);
   delete pb;
@@ -104,6 +106,25 @@ static fc_status upload_system(const HostSystem& S, hipStream_t stream, fc_probl
   pb->eta = S.eta;
   pb->elem_nodes_host = S.elem_nodes;
   FC_HIP(launch_diag(*pb, stream));
+  // bitwise-equal block rows share one copy for the FP64 products.
+  // FC_SPMV_SHARE: 0 never, 1 whenever a row repeats, otherwise when the
+  // distinct rows hold at most three quarters of the values.
+  {
+    const char* env = std::getenv("FC_SPMV_SHARE");
+    const int mode = env ? std::atoi(env) : -1;
+    if (mode != 0 && pb->A.n_rows > 0) {
+      SharedRows sh;
+      share_rows(S, &sh);
+      const bool use = sh.distinct_rows < pb->A.n_rows &&
+                       (mode == 1 || 4 * (int64_t)sh.vals.size() <= 3 * (int64_t)S.val.size());
+      if (use) {
+        FC_TRY(upload(&pb->A.vsh, sh.vals.data(), sh.vals.size()));
+        FC_TRY(upload(&pb->A.vofs, sh.ofs.data(), sh.ofs.size()));
+        pb->A.sh_rows = sh.distinct_rows;
+        pb->A.sh_vals = (int64_t)sh.vals.size();
+      }
+    }
+  }
   if (S.dim > 0) FC_HIP(spmv_enable_lattice(pb->A, S.dim, S.p * S.n + 1, S.p, stream));
   FC_HIP(spmv_autotune(pb->A, stream));
   FC_HIP(hipStreamSynchronize(stream));
@@ -154,6 +175,27 @@ fc_status fc_host_system_info(fc_host_system hs, int64_t* n_dofs, int64_t* nnzb,
   if (n_el) *n_el = S.n_el;
   if (m) *m = S.m;
   if (bsr_dim) *bsr_dim = S.bdim;
+  return FC_OK;
+}
+
+fc_status fc_host_system_share(fc_host_system hs, int64_t* distinct_rows, int64_t* n_values,
+                               int64_t* ofs, double* vals) {
+  if (!hs || !distinct_rows || !n_values) {
+    set_error("fc_host_system_share: NULL argument");
+    return FC_E_ARG;
+  }
+  SharedRows sh;
+  try {
+    share_rows(hs->sys, &sh);
+  } catch (const std::bad_alloc&) {
+    set_error("fc_host_system_share: out of host memory");
+    return FC_E_NOMEM;
+  }
+  *distinct_rows = sh.distinct_rows;
+  *n_values = (int64_t)sh.vals.size();
+  if (ofs && !sh.ofs.empty()) std::memcpy(ofs, sh.ofs.data(), sh.ofs.size() * sizeof(int64_t));
+  if (vals && !sh.vals.empty())
+    std::memcpy(vals, sh.vals.data(), sh.vals.size() * sizeof(double));
   return FC_OK;
 }
 
@@ -504,6 +546,13 @@ fc_status fc_spmv_info(fc_problem pb, int32_t* group, int32_t* lattice) {
   if (!pb) return FC_E_ARG;
   if (group) *group = pb->A.group;
   if (lattice) *lattice = pb->A.lat.dim > 0 ? 1 : 0;
+  return FC_OK;
+}
+
+fc_status fc_spmv_share_info(fc_problem pb, int64_t* distinct_rows, int64_t* distinct_values) {
+  if (!pb) return FC_E_ARG;
+  if (distinct_rows) *distinct_rows = pb->A.sh_rows;
+  if (distinct_values) *distinct_values = pb->A.sh_vals;
   return FC_OK;
 }
 

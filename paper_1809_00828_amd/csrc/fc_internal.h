@@ -68,6 +68,11 @@ struct DeviceBsr {
   int32_t* rows_hi = nullptr;
   int32_t* rows_lo = nullptr;
   int64_t n_hi = 0, n_lo = 0;
+  // FP64 products read the rows through vsh when set: bitwise-equal block
+  // rows keep one copy there and vofs[row] is the offset of a row's values
+  double* vsh = nullptr;
+  int64_t* vofs = nullptr;
+  int64_t sh_rows = 0, sh_vals = 0;   // distinct rows and their values
 };
 
 struct SolverWs;

@@ -10,7 +10,10 @@
 // combined with a butterfly reduction.  Values and column indices are read
 // once per product and streamed with non-temporal loads, which leaves the
 // cache to the gathered x entries (neighbouring rows of the lattice share
-// most of their columns).
+// most of their columns).  When block rows repeat (every row whose cells are
+// uncut repeats one of a few stencils of the cell grid), the FP64 products
+// read one stored copy per distinct row through a per-row offset and the
+// caches serve the repeats.
 //
 // Tiles of 256/G rows are dealt out so that the workgroups resident on one
 // XCD (hardware ids congruent mod 8) walk one contiguous range of rows and
@@ -40,12 +43,17 @@ __device__ __forceinline__ T stream_load(const T* p) {
 // kLat: columns computed from the lattice box (col is not read).
 // XT: type of x (FP32 for the FP32 rows of the mixed product, which round
 // x to FP32 before every product anyway).
-template <int B, int G, typename T, bool kLat, typename XT>
+// kShared: a row's values start at val + vofs[row] (bitwise-equal rows share
+// one copy) instead of val + rowptr[row]*B*B; shared values are read
+// through the caches, where the rows that repeat stay resident.
+template <int B, int G, typename T, bool kLat, typename XT, bool kShared>
 __global__ __launch_bounds__(256) void k_spmv_bsr(
     const int32_t* __restrict__ rowptr, const int32_t* __restrict__ col,
     const T* __restrict__ val, const XT* __restrict__ x,
     double* __restrict__ y, int64_t n_rows, const CgScalars* __restrict__ sc,
-    double* __restrict__ partial, const int32_t* __restrict__ rows, const LatticeInfo lat) {
+    double* __restrict__ partial, const int32_t* __restrict__ rows, const LatticeInfo lat,
+    const int64_t* __restrict__ vofs) {
+  constexpr bool kNT = B != 1 && sizeof(T) == 8 && !kShared;
   constexpr int BB = B * B;
   constexpr int RPW = 256 / G;   // rows per tile
   __shared__ double lds[16];
@@ -63,7 +71,7 @@ __global__ __launch_bounds__(256) void k_spmv_bsr(
     const int64_t row = rows ? (int64_t)rows[idx] : idx;
     const int64_t base = rowptr[row];
     const int L = rowptr[row + 1] - (int32_t)base;
-    const T* v = val + base * BB;
+    const T* v = val + (kShared ? vofs[row] : base * BB);
     RowBox box;
     if constexpr (kLat) box = row_box(row, lat);
     double acc[B];
@@ -87,10 +95,10 @@ __global__ __launch_bounds__(256) void k_spmv_bsr(
         if constexpr (kLat)
           c[u] = on ? lattice_col(box, ku, lat.n1) : -1;
         else
-          c[u] = on ? stream_load<B != 1 && sizeof(T) == 8>(col + base + ku) : -1;
+          c[u] = on ? stream_load<kNT>(col + base + ku) : -1;
 #pragma unroll
         for (int e = 0; e < BB; ++e)
-          a[u][e] = on ? stream_load<B != 1 && sizeof(T) == 8>(v + (int64_t)e * L + ku) : T(0);
+          a[u][e] = on ? stream_load<kNT>(v + (int64_t)e * L + ku) : T(0);
       }
       XT xv[U][B];
 #pragma unroll
@@ -163,7 +171,8 @@ static int64_t fused_grid(const DeviceBsr& A) {
 template <int B, typename T, typename XT>
 static hipError_t spmv_dispatch(const DeviceBsr& A, const T* val, const XT* x,
                                 double* y, hipStream_t s, const CgScalars* sc,
-                                double* partial, const int32_t* rows, int64_t n_list) {
+                                double* partial, const int32_t* rows, int64_t n_list,
+                                const int64_t* vofs) {
   const int G = group_width(A);
   const int64_t n_rows = rows ? n_list : A.n_rows;
   const int64_t nt = (n_rows + 256 / G - 1) / (256 / G);
@@ -172,14 +181,23 @@ static hipError_t spmv_dispatch(const DeviceBsr& A, const T* val, const XT* x,
   static const bool lat_allowed = env_int("FC_SPMV_LATTICE", 1) != 0;
   const bool lat = lat_allowed && A.lat.dim > 0;
   dim3 grid((unsigned)nb), block(256);
-#define FC_SPMV_CASE(GG)                                                                  \
-  case GG:                                                                                \
-    if (lat)                                                                              \
-      hipLaunchKernelGGL((k_spmv_bsr<B, GG, T, true, XT>), grid, block, 0, s, A.rowptr, A.col, \
-                         val, x, y, n_rows, sc, partial, rows, A.lat);                    \
-    else                                                                                  \
-      hipLaunchKernelGGL((k_spmv_bsr<B, GG, T, false, XT>), grid, block, 0, s, A.rowptr,   \
-                         A.col, val, x, y, n_rows, sc, partial, rows, A.lat);             \
+#define FC_SPMV_LAUNCH(GG, SH)                                                             \
+  if (lat)                                                                                 \
+    hipLaunchKernelGGL((k_spmv_bsr<B, GG, T, true, XT, SH>), grid, block, 0, s, A.rowptr,   \
+                       A.col, val, x, y, n_rows, sc, partial, rows, A.lat, vofs);          \
+  else                                                                                     \
+    hipLaunchKernelGGL((k_spmv_bsr<B, GG, T, false, XT, SH>), grid, block, 0, s, A.rowptr,  \
+                       A.col, val, x, y, n_rows, sc, partial, rows, A.lat, vofs);
+  // only FP64 values are ever shared
+#define FC_SPMV_CASE(GG)                                                                   \
+  case GG:                                                                                 \
+    if constexpr (sizeof(T) == 8) {                                                        \
+      if (vofs) {                                                                          \
+        FC_SPMV_LAUNCH(GG, true)                                                           \
+        break;                                                                             \
+      }                                                                                    \
+    }                                                                                      \
+    FC_SPMV_LAUNCH(GG, false)                                                              \
     break;
   switch (G) {
     FC_SPMV_CASE(8)
@@ -188,23 +206,28 @@ static hipError_t spmv_dispatch(const DeviceBsr& A, const T* val, const XT* x,
     FC_SPMV_CASE(64)
   }
 #undef FC_SPMV_CASE
+#undef FC_SPMV_LAUNCH
   return hipGetLastError();
 }
 
 template <typename T, typename XT = double>
 static hipError_t spmv_any(const DeviceBsr& A, const T* val, const XT* x, double* y,
                            hipStream_t s, const CgScalars* sc, double* partial,
-                           const int32_t* rows = nullptr, int64_t n_list = 0) {
+                           const int32_t* rows = nullptr, int64_t n_list = 0,
+                           const int64_t* vofs = nullptr) {
   switch (A.bdim) {
-    case 1: return spmv_dispatch<1, T, XT>(A, val, x, y, s, sc, partial, rows, n_list);
-    case 2: return spmv_dispatch<2, T, XT>(A, val, x, y, s, sc, partial, rows, n_list);
-    case 3: return spmv_dispatch<3, T, XT>(A, val, x, y, s, sc, partial, rows, n_list);
+    case 1: return spmv_dispatch<1, T, XT>(A, val, x, y, s, sc, partial, rows, n_list, vofs);
+    case 2: return spmv_dispatch<2, T, XT>(A, val, x, y, s, sc, partial, rows, n_list, vofs);
+    case 3: return spmv_dispatch<3, T, XT>(A, val, x, y, s, sc, partial, rows, n_list, vofs);
   }
   return hipErrorInvalidValue;
 }
 
+// FP64 values: the shared rows when set-up kept them, else the full matrix
+static const double* f64_values(const DeviceBsr& A) { return A.vofs ? A.vsh : A.val; }
+
 hipError_t launch_spmv(const DeviceBsr& A, const double* x, double* y, hipStream_t s) {
-  return spmv_any<double>(A, A.val, x, y, s, nullptr, nullptr);
+  return spmv_any<double>(A, f64_values(A), x, y, s, nullptr, nullptr, nullptr, 0, A.vofs);
 }
 
 int spmv_num_blocks(const DeviceBsr& A) { return (int)fused_grid(A); }
@@ -289,14 +312,15 @@ hipError_t spmv_autotune(DeviceBsr& A, hipStream_t s) {
 
 hipError_t launch_spmv_pq(const DeviceBsr& A, const double* p, double* q, CgScalars* sc,
                           double* partial, hipStream_t s) {
-  return spmv_any<double>(A, A.val, p, q, s, sc, partial);
+  return spmv_any<double>(A, f64_values(A), p, q, s, sc, partial, nullptr, 0, A.vofs);
 }
 
 hipError_t launch_spmv_mixed(const DeviceBsr& A, const double* p, const float* p32, double* q,
                              const CgScalars* sc, hipStream_t s) {
   hipError_t e = hipSuccess;
   if (A.n_hi > 0 &&
-      (e = spmv_any<double>(A, A.val, p, q, s, sc, nullptr, A.rows_hi, A.n_hi)) != hipSuccess)
+      (e = spmv_any<double>(A, f64_values(A), p, q, s, sc, nullptr, A.rows_hi, A.n_hi,
+                            A.vofs)) != hipSuccess)
     return e;
   if (A.n_lo > 0)
     e = spmv_any<float, float>(A, A.val32, p32, q, s, sc, nullptr, A.rows_lo, A.n_lo);

@@ -99,3 +99,49 @@ def test_refinement_on_uncut_cube(torch):
     e64 = energy(A, x64.cpu().numpy() - xr) / energy(A, xr)
     e = energy(A, x.cpu().numpy() - xr) / energy(A, xr)
     assert e <= 10 * e64 + 1e-12
+
+
+def test_shared_rows_give_the_same_products(torch, monkeypatch):
+    """The same problem set up with the full matrix (FC_SPMV_SHARE=0) and
+    with bitwise-equal rows kept once (FC_SPMV_SHARE=1): products and PCG
+    solves agree bit for bit when both chose the same lanes per row (the
+    set-up times the group width on each matrix), else to rounding."""
+    d, s = oracle_system("elast3d_p2")
+    monkeypatch.setenv("FC_SPMV_SHARE", "0")
+    plain = fc.Problem.setup(d)
+    monkeypatch.setenv("FC_SPMV_SHARE", "1")
+    shared = fc.Problem.setup(d)
+    ip, ish = plain.info(), shared.info()
+    print(f"[share] rows {ish['shared_rows']} of {ish['n_dofs'] // 3}, values "
+          f"{ish['shared_values']} of {ish['nnzb'] * 9}; groups {ip['spmv_group']} "
+          f"{ish['spmv_group']}", flush=True)
+    assert ip["shared_rows"] == 0 and ip["shared_values"] == 0
+    assert 0 < ish["shared_rows"] < ish["n_dofs"] // 3
+    same_group = ip["spmv_group"] == ish["spmv_group"]
+    x = _dev(torch, np.random.default_rng(5).standard_normal(plain.n))
+    y0 = torch.empty_like(x)
+    y1 = torch.empty_like(x)
+    plain.apply_A(x, y0)
+    shared.apply_A(x, y1)
+    torch.cuda.synchronize()
+    a, b = y0.cpu().numpy(), y1.cpu().numpy()
+    if same_group:
+        assert a.tobytes() == b.tobytes()
+    else:
+        assert np.abs(a - b).max() <= 1e-14 * np.abs(a).max()
+    ref = s["A"] @ x.cpu().numpy()
+    assert np.abs(b - ref).max() <= 1e-13 * np.abs(ref).max()
+    res = []
+    for pb in (plain, shared):
+        pc = fc.Precond(pb)
+        rhs = torch.empty(pb.n, dtype=torch.float64, device="cuda")
+        pb.rhs(rhs)
+        xs = torch.zeros_like(rhs)
+        info = fc.pcg_solve(pb, pc, rhs, xs, tol=1e-10)
+        torch.cuda.synchronize()
+        res.append((info["iters"], xs.cpu().numpy()))
+    assert res[0][0] == res[1][0] or not same_group
+    if same_group:
+        assert res[0][1].tobytes() == res[1][1].tobytes()
+    else:
+        assert abs(res[0][0] - res[1][0]) <= 2

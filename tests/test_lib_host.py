@@ -82,3 +82,29 @@ def test_host_assembly_rejects_bad_description():
     with pytest.raises(fc.FcError) as ei:
         fc.HostSystem(d)
     assert ei.value.status == 1
+
+
+@pytest.mark.parametrize("desc", [
+    lambda: fcgen.disk_poisson_2d(0),
+    lambda: fcgen.porous_elasticity_3d(seed=3, n=4, p=2, n_voids=3, rmin=0.06, rmax=0.12),
+    lambda: fcgen.custom(3, 4, 2, "elasticity", 1e-8, shapes=[], clamp_zmin=True),
+])
+def test_shared_rows_reproduce_every_row(desc):
+    """Rows kept once by the library: every block row read through its
+    offset gives back its own values bit for bit, and the number of kept
+    rows equals the number of distinct value sequences (grouped here by
+    their bytes, independently of the library's hashing)."""
+    h = fc.HostSystem(desc())
+    e = h.export()
+    sh = h.share()
+    rp, bd = e["rowptr"], e["bsr_dim"]
+    val = e["val"].reshape(-1, bd * bd)
+    distinct = set()
+    for r in range(rp.size - 1):
+        L = rp[r + 1] - rp[r]
+        mine = val[rp[r]:rp[r + 1]]                           # [L, bd*bd], block-major
+        got = sh["vals"][sh["ofs"][r]: sh["ofs"][r] + L * bd * bd].reshape(bd * bd, L).T
+        assert got.tobytes() == mine.tobytes(), r
+        distinct.add(mine.T.tobytes())
+    assert sh["distinct_rows"] == len(distinct)
+    assert sh["vals"].size == sum(len(b) // 8 for b in distinct)
