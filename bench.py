@@ -31,7 +31,7 @@ HBM_PEAK_GBS = 8000.0
 # counter passes (FETCH_SIZE, WRITE_SIZE), scaled by what the same counters
 # read for a plain 4 GiB copy (profiles/pcg_fp64_elastic32_p3_hbm_counters.md);
 # to be re-measured whenever one of these kernels changes.
-TRAFFIC = {"spmv": 8.3640e9, "spmv_shared": None, "schwarz": 4.6881e9}
+TRAFFIC = {"spmv": 8.3640e9, "spmv_shared": None, "schwarz": 4.6881e9, "schwarz_shared": None}
 METRIC = "DOF·iter/s and time-to-1e-8 residual: mixed/learned vs plain FP64 PCG"
 
 
@@ -46,8 +46,9 @@ def workload(small: bool, name: str = "elastic32"):
             "3D finite cell linear elasticity, 32^3 cells, p=3, 64 spherical voids, alpha=1e-8")
 
 
-def algorithmic_bytes(info, m, n_blocks, nn):
-    """Bytes each streaming kernel must move per launch (FP64 layout)."""
+def algorithmic_bytes(info, m, n_blocks, nn, distinct_blocks=0):
+    """Bytes each streaming kernel must move per launch (FP64 layout).
+    Shared rows and shared local inverses count once per distinct copy."""
     n = info["n_dofs"]
     bd = info["bsr_dim"]
     nnzb = info["nnzb"]
@@ -63,7 +64,10 @@ def algorithmic_bytes(info, m, n_blocks, nn):
         spmv = nnzb * (bd * bd * 8 + col_bytes) + (n // bd + 1) * 4 + 2 * n * 8
     # stored half of each symmetric P_B once ((m/2+1)*m wrapped diagonals),
     # element node lists, gathered r and q once, y_B written
-    schwarz = n_blocks * (m // 2 + 1) * m * 8 + n_blocks * nn * 4 + 2 * n * 8 + n_blocks * m * 8
+    stored = distinct_blocks if distinct_blocks else n_blocks
+    schwarz = stored * (m // 2 + 1) * m * 8 + n_blocks * nn * 4 + 2 * n * 8 + n_blocks * m * 8
+    if distinct_blocks:
+        schwarz += n_blocks * 8     # one 8-byte offset per block
     return spmv, schwarz
 
 
@@ -502,7 +506,8 @@ def main():
     pinfo = res[-1][2]
     m = info["m"]
     nn = m // info["bsr_dim"]
-    spmv_b, schw_b = algorithmic_bytes(info, m, pinfo["n_blocks"], nn)
+    dblk = pinfo.get("shared_distinct_blocks", 0)
+    spmv_b, schw_b = algorithmic_bytes(info, m, pinfo["n_blocks"], nn, dblk)
     ms_spmv = sum(r[1]["ms_spmv"] for r in res) / max(1, sum(r[1]["n_timed"] for r in res))
     ms_schw = sum(r[1]["ms_schwarz"] for r in res) / max(1, sum(r[1]["n_timed"] for r in res))
     gbs_schw = schw_b / (ms_schw * 1e-3) / 1e9
@@ -519,13 +524,20 @@ def main():
               "frac": gbs_spmv / HBM_PEAK_GBS,
               "traffic": (TRAFFIC["spmv_shared" if shared else "spmv"]
                           if on_bench_workload else None),
-              "bytes_per_launch": spmv_b, "avg_ms": ms_spmv}
-    schw_name = ("k_schwarz_sym_staged<double>" if m > 64 else "k_schwarz_small<double,sym>")
+              "bytes_per_launch": spmv_b, "avg_ms": ms_spmv,
+              # values the lanes load per launch when every row is counted
+              # (repeats of shared rows come from the caches)
+              "loaded_bytes_per_launch": algorithmic_bytes(
+                  {**info, "shared_values": 0}, m, pinfo["n_blocks"], nn)[0]}
+    schw_name = ((f"k_schwarz_sym_staged<double{',shared' if dblk else ''}>") if m > 64
+                 else "k_schwarz_small<double,sym>")
     k_schw = {"bound": "hbm", "kernel": schw_name + " (block products)",
               "achieved": gbs_schw, "peak": HBM_PEAK_GBS, "unit": "GB/s",
               "frac": gbs_schw / HBM_PEAK_GBS,
-              "traffic": TRAFFIC["schwarz"] if on_bench_workload else None,
-              "bytes_per_launch": schw_b, "avg_ms": ms_schw}
+              "traffic": (TRAFFIC["schwarz_shared" if dblk else "schwarz"]
+                          if on_bench_workload else None),
+              "bytes_per_launch": schw_b, "avg_ms": ms_schw,
+              "loaded_bytes_per_launch": algorithmic_bytes(info, m, pinfo["n_blocks"], nn)[1]}
     dominant, other = (k_spmv, k_schw) if ms_spmv >= ms_schw else (k_schw, k_spmv)
     out = {
         "metric": METRIC,
@@ -539,7 +551,8 @@ def main():
                    "blocks": pinfo["n_blocks"], "block_size": m, "tol": args.tol,
                    "stop": "relative residual ||b-Ax||/||b||", "form": "fp64",
                    "shared_rows": info.get("shared_rows", 0),
-                   "shared_values": info.get("shared_values", 0)},
+                   "shared_values": info.get("shared_values", 0),
+                   "shared_distinct_blocks": dblk},
         "roofline": dominant,
         "roofline_other": other,
         "iters": iters, "status": status,

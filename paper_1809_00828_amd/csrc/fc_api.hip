@@ -72,7 +72,8 @@ static void free_precond(fc_precond_s* pc) {
   coarse_destroy(pc->coarse);
   for (void* p : {(void*)pc->block_elem, (void*)pc->P, (void*)pc->Q, (void*)pc->Q32,
                   (void*)pc->unsafe32, (void*)pc->unsafe_flag32, (void*)pc->Lbf, (void*)pc->isd,
-                  (void*)pc->inv_ptr, (void*)pc->inv_idx, (void*)pc->fallback, (void*)pc->y})
+                  (void*)pc->inv_ptr, (void*)pc->inv_idx, (void*)pc->fallback, (void*)pc->y,
+                  (void*)pc->qofs})
     if (p) (void)hipFree(p);
   delete pc;
 }
@@ -501,6 +502,7 @@ fc_status fc_precond_build(fc_problem pb, const fc_precond_opts* opts, void* str
   const size_t qn = (size_t)nb * sym_block_stride(m);
   FC_TRY(dev_alloc(&pc->Q, qn));
   FC_HIP(launch_pack_sym(*pc, pc->Q, 0, s));
+  FC_HIP(launch_share_blocks(*pc, s));
   if (o.store_mask & (FC_STORE_F32 | FC_STORE_BF16)) {
     FC_TRY(dev_alloc(&pc->isd, (size_t)pb->n_dofs));
     FC_HIP(launch_inv_sqrt_diag(*pb, pc->isd, s));
@@ -546,6 +548,12 @@ fc_status fc_spmv_info(fc_problem pb, int32_t* group, int32_t* lattice) {
   if (!pb) return FC_E_ARG;
   if (group) *group = pb->A.group;
   if (lattice) *lattice = pb->A.lat.dim > 0 ? 1 : 0;
+  return FC_OK;
+}
+
+fc_status fc_precond_share_info(fc_precond pc, int64_t* distinct_blocks) {
+  if (!pc) return FC_E_ARG;
+  if (distinct_blocks) *distinct_blocks = pc->qofs ? pc->q_distinct : 0;
   return FC_OK;
 }
 

@@ -102,6 +102,10 @@ struct fc_precond_s {
   int32_t* block_elem = nullptr;   // [n_blocks] element of each block
   double* P = nullptr;             // [n_blocks*m*m] FP64 local inverses (dense)
   double* Q = nullptr;             // wrapped-diagonal symmetric copy, FP64
+  // FP64 block products read block k's copy at Q + qofs[k] when set: blocks
+  // whose stored copies are bitwise equal read one of them
+  int64_t* qofs = nullptr;
+  int64_t q_distinct = 0;          // blocks read through qofs that are their own source
   float* Q32 = nullptr;            // optional FP32 wrapped-diagonal copy of D^1/2 P D^1/2
   int32_t* unsafe32 = nullptr;     // blocks whose FP32 copy is not safely positive
   int32_t* unsafe_flag32 = nullptr; // the same as one flag per block

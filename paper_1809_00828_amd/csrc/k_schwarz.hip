@@ -30,6 +30,8 @@
 // its diagonal-scaling term.
 #include <algorithm>
 #include <cstdlib>
+#include <unordered_map>
+#include <vector>
 
 #include "dev_common.h"
 #include "k_schwarz.h"
@@ -64,13 +66,15 @@ __global__ __launch_bounds__(256) void k_schwarz_large(
 }
 
 // m > 64, symmetric layout staged through LDS (sym_block_staged).
-template <typename T>
+// kShared: block blk reads the copy at P + qofs[blk] through the caches.
+template <typename T, bool kShared = false>
 __global__ __launch_bounds__(256) void k_schwarz_sym_staged(
     const T* __restrict__ P, int64_t block_stride, const int32_t* __restrict__ elem_nodes,
     const int32_t* __restrict__ block_elem, int nn, int bd, int m,
     const double* __restrict__ r, const double* __restrict__ q, const double* __restrict__ isd,
     const CgScalars* __restrict__ sc, double* __restrict__ y, int64_t n_blocks,
-    const int32_t* __restrict__ list, const int32_t* __restrict__ skip) {
+    const int32_t* __restrict__ list, const int32_t* __restrict__ skip,
+    const int64_t* __restrict__ qofs) {
   using A = typename Acc<T>::type;
   constexpr int kStageRows = StageRows<T>::value;
   // the gathered residual is kept in the accumulation type: an FP32 copy
@@ -93,8 +97,8 @@ __global__ __launch_bounds__(256) void k_schwarz_sym_staged(
     dof = (int64_t)elem_nodes[e * nn + i / bd] * bd + (i % bd);
     rB[i] = (A)(gather_r(r, q, alpha, dof) * (isd ? isd[dof] : 1.0));
   }
-  const T* Qb = P + blk * block_stride;
-  const double v = sym_block_staged<T>(Qb, rB, m, i, tile);
+  const T* Qb = P + (kShared ? qofs[blk] : blk * block_stride);
+  const double v = sym_block_staged<T, A, !kShared>(Qb, rB, m, i, tile);
   if (act) y[blk * m + i] = isd ? v * isd[dof] : v;
 }
 
@@ -346,6 +350,135 @@ __global__ void k_pack_sym(const double* __restrict__ P, T* __restrict__ Q, int 
 
 int64_t sym_block_stride(int m) { return (int64_t)(m / 2 + 1) * m; }
 
+// ------------------------------------------------------------ shared copies
+// On a Cartesian cell grid the element blocks of uncut cells with the same
+// kind of neighbourhood are the same matrix, so their stored inverses can be
+// the same bits.  A content hash groups candidates; a bitwise comparison
+// decides.
+
+// Hash of one block's copy: the wrapping sum over its words of a mix of
+// (word, index), so it does not depend on the order lanes visit the words.
+__global__ __launch_bounds__(256) void k_block_hash(const double* __restrict__ Q, int64_t stride,
+                                                    int64_t nb, uint64_t* __restrict__ h) {
+  __shared__ uint64_t part[256];
+  const int64_t blk = blockIdx.x;
+  const uint64_t* w = reinterpret_cast<const uint64_t*>(Q + blk * stride);
+  uint64_t acc = 0;
+  for (int64_t k = threadIdx.x; k < stride; k += 256) {
+    uint64_t z = w[k] ^ ((uint64_t)k * 0x9E3779B97F4A7C15ull);
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    acc += z ^ (z >> 31);
+  }
+  part[threadIdx.x] = acc;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if (threadIdx.x < off) part[threadIdx.x] += part[threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0 && blk < nb) h[blk] = part[0];
+}
+
+// differ[blk] = 1 when block blk's copy is not bitwise equal to that of
+// block rep[blk] (0 for blocks that are their own representative).
+__global__ __launch_bounds__(256) void k_block_differs(const double* __restrict__ Q,
+                                                       int64_t stride,
+                                                       const int32_t* __restrict__ rep,
+                                                       int32_t* __restrict__ differ) {
+  __shared__ int32_t any[256];
+  const int64_t blk = blockIdx.x;
+  const int64_t q = rep[blk];
+  int32_t d = 0;
+  if (q != blk) {
+    const uint64_t* a = reinterpret_cast<const uint64_t*>(Q + blk * stride);
+    const uint64_t* b = reinterpret_cast<const uint64_t*>(Q + q * stride);
+    for (int64_t k = threadIdx.x; k < stride; k += 256) d |= a[k] != b[k] ? 1 : 0;
+  }
+  any[threadIdx.x] = d;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if (threadIdx.x < off) any[threadIdx.x] |= any[threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) differ[blk] = any[0];
+}
+
+hipError_t launch_share_blocks(fc_precond_s& pc, hipStream_t s) {
+  const int64_t nb = pc.n_blocks;
+  if (pc.qofs) {
+    (void)hipFree(pc.qofs);
+    pc.qofs = nullptr;
+  }
+  pc.q_distinct = 0;
+  const char* env = std::getenv("FC_SCHWARZ_SHARE");
+  const int mode = env ? std::atoi(env) : -1;
+  if (mode == 0 || pc.m <= 64 || nb < 2 || !pc.Q) return hipSuccess;
+  const int64_t stride = sym_block_stride(pc.m);
+  uint64_t* dh = nullptr;
+  int32_t* drep = nullptr;
+  int32_t* ddiff = nullptr;
+  struct Free {
+    void* p[3];
+    ~Free() {
+      for (void* q : p)
+        if (q) (void)hipFree(q);
+    }
+  } tmp{{nullptr, nullptr, nullptr}};
+  hipError_t e = hipMalloc(&dh, nb * sizeof(uint64_t));
+  tmp.p[0] = dh;
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_block_hash, dim3((unsigned)nb), dim3(256), 0, s, pc.Q, stride, nb, dh);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  std::vector<uint64_t> h((size_t)nb);
+  if ((e = hipMemcpyAsync(h.data(), dh, nb * sizeof(uint64_t), hipMemcpyDeviceToHost, s)) !=
+          hipSuccess ||
+      (e = hipStreamSynchronize(s)) != hipSuccess)
+    return e;
+  // the first block with each hash is the candidate source
+  std::unordered_map<uint64_t, int32_t> first;
+  first.reserve((size_t)nb);
+  std::vector<int32_t> rep((size_t)nb);
+  int64_t repeats = 0;
+  for (int64_t k = 0; k < nb; ++k) {
+    rep[k] = first.emplace(h[k], (int32_t)k).first->second;
+    repeats += rep[k] != k;
+  }
+  if (repeats == 0 || (mode != 1 && 4 * repeats < nb)) return hipSuccess;
+  if ((e = hipMalloc(&drep, nb * sizeof(int32_t))) != hipSuccess) return e;
+  tmp.p[1] = drep;
+  if ((e = hipMalloc(&ddiff, nb * sizeof(int32_t))) != hipSuccess) return e;
+  tmp.p[2] = ddiff;
+  if ((e = hipMemcpyAsync(drep, rep.data(), nb * sizeof(int32_t), hipMemcpyHostToDevice, s)) !=
+      hipSuccess)
+    return e;
+  hipLaunchKernelGGL(k_block_differs, dim3((unsigned)nb), dim3(256), 0, s, pc.Q, stride, drep,
+                     ddiff);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  std::vector<int32_t> diff((size_t)nb);
+  if ((e = hipMemcpyAsync(diff.data(), ddiff, nb * sizeof(int32_t), hipMemcpyDeviceToHost, s)) !=
+          hipSuccess ||
+      (e = hipStreamSynchronize(s)) != hipSuccess)
+    return e;
+  // a hash collision leaves the block with its own copy
+  std::vector<int64_t> ofs((size_t)nb);
+  int64_t distinct = 0;
+  for (int64_t k = 0; k < nb; ++k) {
+    const int64_t src = diff[k] ? k : rep[k];
+    ofs[k] = src * stride;
+    distinct += src == k;
+  }
+  if ((e = hipMalloc(&pc.qofs, nb * sizeof(int64_t))) != hipSuccess) {
+    pc.qofs = nullptr;
+    return e;
+  }
+  if ((e = hipMemcpyAsync(pc.qofs, ofs.data(), nb * sizeof(int64_t), hipMemcpyHostToDevice, s)) !=
+          hipSuccess ||
+      (e = hipStreamSynchronize(s)) != hipSuccess)
+    return e;
+  pc.q_distinct = distinct;
+  return hipSuccess;
+}
+
 hipError_t launch_pack_sym(const fc_precond_s& pc, void* Q, int precision, hipStream_t s) {
   const int64_t nb = pc.n_blocks;
   const int m = pc.m;
@@ -394,11 +527,16 @@ static hipError_t phase1(const fc_precond_s& pc, const T* P, const double* r, co
   }();
   if (pc.m > 64) {
     const int threads = 64 * ((pc.m + 63) / 64);
-    if (kSym && variant)
+    if (kSym && variant && sizeof(T) == 8 && pc.qofs && (const void*)P == (const void*)pc.Q)
+      hipLaunchKernelGGL((k_schwarz_sym_staged<T, true>), dim3((unsigned)pc.n_blocks),
+                         dim3(threads), 0, s, P, stride, pb.elem_nodes, pc.block_elem, pc.nn,
+                         pc.bdim, pc.m, r, q, isd, sc, pc.y, pc.n_blocks, nullptr, nullptr,
+                         pc.qofs);
+    else if (kSym && variant)
       hipLaunchKernelGGL((k_schwarz_sym_staged<T>), dim3((unsigned)pc.n_blocks), dim3(threads),
                          0, s, P, stride, pb.elem_nodes, pc.block_elem, pc.nn, pc.bdim, pc.m, r,
                          q, isd, sc, pc.y, pc.n_blocks, nullptr,
-                         sizeof(T) == 4 ? pc.unsafe_flag32 : nullptr);
+                         sizeof(T) == 4 ? pc.unsafe_flag32 : nullptr, nullptr);
     else
       hipLaunchKernelGGL((k_schwarz_large<T, kSym>), dim3((unsigned)pc.n_blocks), dim3(threads),
                          0, s, P, stride, pb.elem_nodes, pc.block_elem, pc.nn, pc.bdim, pc.m, r,
@@ -450,7 +588,7 @@ hipError_t launch_schwarz_phase1(const fc_precond_s& pc, int precision, const do
         hipLaunchKernelGGL((k_schwarz_sym_staged<double>), dim3((unsigned)pc.n_unsafe32),
                            dim3(64 * ((pc.m + 63) / 64)), 0, s, pc.Q, sym_block_stride(pc.m),
                            pb.elem_nodes, pc.block_elem, pc.nn, pc.bdim, pc.m, r, q, nullptr, sc,
-                           pc.y, pc.n_blocks, pc.unsafe32, nullptr);
+                           pc.y, pc.n_blocks, pc.unsafe32, nullptr, nullptr);
       else
         hipLaunchKernelGGL(k_schwarz_sym_list, dim3((unsigned)pc.n_unsafe32),
                            dim3(64 * ((pc.m + 63) / 64)), 0, s, pc.Q, sym_block_stride(pc.m),

@@ -66,7 +66,9 @@ struct StageRows {
 // thread its own entry, written to LDS, and the rotated entries are read
 // back from LDS, so HBM and L2 see each stored entry exactly once.  rB holds
 // the block's gathered right-hand side (m entries, in LDS).
-template <typename T, typename RB>
+// kNT: stream the stored entries non-temporally (each is read once per
+// product); shared copies are read through the caches instead.
+template <typename T, typename RB, bool kNT = true>
 __device__ __forceinline__ double sym_block_staged(const T* __restrict__ Qb, const RB* rB,
                                                    int m, int i,
                                                    T (*tile)[256]) {
@@ -82,7 +84,8 @@ __device__ __forceinline__ double sym_block_staged(const T* __restrict__ Qb, con
 #pragma unroll
     for (int kk = 0; kk < kStageRows; ++kk) {
       const int k = k0 + kk;
-      v[kk] = (act && k <= h) ? __builtin_nontemporal_load(Qb + (int64_t)k * m + i) : T(0);
+      const T* src = Qb + (int64_t)k * m + i;
+      v[kk] = (act && k <= h) ? (kNT ? __builtin_nontemporal_load(src) : *src) : T(0);
     }
     __syncthreads();   // previous chunk's rotated reads are done
 #pragma unroll
