@@ -29,9 +29,11 @@ if ROOT not in sys.path:
 HBM_PEAK_GBS = 8000.0
 # HBM bytes per launch on the 32^3 elasticity workload from two rocprofv3
 # counter passes (FETCH_SIZE, WRITE_SIZE), scaled by what the same counters
-# read for a plain 4 GiB copy (profiles/pcg_fp64_elastic32_p3_hbm_counters.md);
+# read for a plain 4 GiB copy (profiles/pcg_fp64_elastic32_p3_hbm_counters.md, full
+# copies; profiles/pcg_fp64_elastic32_p3_shared_hbm_counters.md, shared copies);
 # to be re-measured whenever one of these kernels changes.
-TRAFFIC = {"spmv": 8.3640e9, "spmv_shared": None, "schwarz": 4.6881e9, "schwarz_shared": None}
+TRAFFIC = {"spmv": 8.3640e9, "spmv_shared": 9.2376e8, "schwarz": 4.6881e9,
+           "schwarz_shared": 1.3893e9}
 METRIC = "DOF·iter/s and time-to-1e-8 residual: mixed/learned vs plain FP64 PCG"
 
 

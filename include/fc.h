@@ -227,13 +227,16 @@ fc_status fc_precond_lowprec_info(fc_precond pc, int64_t* n_f32_blocks,
  * its own P_B, but on the Cartesian cell grid the blocks of uncut cells
  * with the same kind of neighbourhood are equal matrices and give equal
  * inverses).  Blocks whose stored FP64 inverses are bitwise equal are read
- * from one copy by the FP64 block products when m > 64; every block keeps
- * its own copy for all other uses.  *distinct_blocks receives the number
- * of copies read (0 when no block is shared).  The environment variable
+ * from one copy by the block products when m > 64; every block keeps
+ * its own copy for all other uses; the FP32 copy (FC_STORE_F32) is shared
+ * the same way.  *distinct_blocks and *distinct_blocks32 (either may be
+ * NULL) receive the number of FP64 and FP32 copies read (0 when no block is
+ * shared).  The environment variable
  * FC_SCHWARZ_SHARE, read at every build, selects 0: never share, 1: share
  * whenever a block repeats, unset or other: share when at least a quarter
  * of the blocks repeat.  Products are bitwise the same either way. */
-fc_status fc_precond_share_info(fc_precond pc, int64_t* distinct_blocks);
+fc_status fc_precond_share_info(fc_precond pc, int64_t* distinct_blocks,
+                                int64_t* distinct_blocks32);
 
 /* Copy the FP64 local inverse of block k (m*m values, row-major) to host. */
 fc_status fc_get_block_inverse(fc_precond pc, int64_t k, double* out_host);

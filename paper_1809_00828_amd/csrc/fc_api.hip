@@ -60,6 +60,7 @@ static void free_problem(fc_problem_s* pb) {
   if (!pb) return;
   for (void* p : {(void*)pb->A.rowptr, (void*)pb->A.col, (void*)pb->A.val, (void*)pb->A.val32,
                   (void*)pb->A.rows_hi, (void*)pb->A.rows_lo, (void*)pb->A.vsh,
+                  (void*)pb->A.vsh32,
                   (void*)pb->A.vofs, (void*)pb->rhs,
                   (void*)pb->elem_nodes, (void*)pb->diag})
     if (p) (void)hipFree(p);
@@ -73,7 +74,7 @@ static void free_precond(fc_precond_s* pc) {
   for (void* p : {(void*)pc->block_elem, (void*)pc->P, (void*)pc->Q, (void*)pc->Q32,
                   (void*)pc->unsafe32, (void*)pc->unsafe_flag32, (void*)pc->Lbf, (void*)pc->isd,
                   (void*)pc->inv_ptr, (void*)pc->inv_idx, (void*)pc->fallback, (void*)pc->y,
-                  (void*)pc->qofs})
+                  (void*)pc->qofs, (void*)pc->qofs32})
     if (p) (void)hipFree(p);
   delete pc;
 }
@@ -526,6 +527,7 @@ fc_status fc_precond_build(fc_problem pb, const fc_precond_opts* opts, void* str
       if (hf[k]) list.push_back((int32_t)k);
     pc->n_unsafe32 = (int64_t)list.size();
     if (!list.empty()) FC_TRY(upload(&pc->unsafe32, list.data(), list.size()));
+    FC_HIP(launch_share_blocks(*pc, s));
   }
   // BF16: scaled Cholesky factors (positive semi-definite however rounded)
   const size_t ln = (size_t)nb * ((size_t)m * (m + 1) / 2);
@@ -551,9 +553,11 @@ fc_status fc_spmv_info(fc_problem pb, int32_t* group, int32_t* lattice) {
   return FC_OK;
 }
 
-fc_status fc_precond_share_info(fc_precond pc, int64_t* distinct_blocks) {
+fc_status fc_precond_share_info(fc_precond pc, int64_t* distinct_blocks,
+                                int64_t* distinct_blocks32) {
   if (!pc) return FC_E_ARG;
   if (distinct_blocks) *distinct_blocks = pc->qofs ? pc->q_distinct : 0;
+  if (distinct_blocks32) *distinct_blocks32 = pc->qofs32 ? pc->q32_distinct : 0;
   return FC_OK;
 }
 

@@ -68,9 +68,11 @@ struct DeviceBsr {
   int32_t* rows_hi = nullptr;
   int32_t* rows_lo = nullptr;
   int64_t n_hi = 0, n_lo = 0;
-  // FP64 products read the rows through vsh when set: bitwise-equal block
-  // rows keep one copy there and vofs[row] is the offset of a row's values
+  // products read the rows through vsh (FP64) and vsh32 (the FP32 rows of
+  // the mixed product) when set: bitwise-equal block rows keep one copy
+  // there and vofs[row] is the offset of a row's values
   double* vsh = nullptr;
+  float* vsh32 = nullptr;   // FP32 copy of vsh (mixed products), same offsets
   int64_t* vofs = nullptr;
   int64_t sh_rows = 0, sh_vals = 0;   // distinct rows and their values
 };
@@ -106,6 +108,8 @@ struct fc_precond_s {
   // whose stored copies are bitwise equal read one of them
   int64_t* qofs = nullptr;
   int64_t q_distinct = 0;          // blocks read through qofs that are their own source
+  int64_t* qofs32 = nullptr;       // the same for the FP32 copy Q32
+  int64_t q32_distinct = 0;
   float* Q32 = nullptr;            // optional FP32 wrapped-diagonal copy of D^1/2 P D^1/2
   int32_t* unsafe32 = nullptr;     // blocks whose FP32 copy is not safely positive
   int32_t* unsafe_flag32 = nullptr; // the same as one flag per block

@@ -854,6 +854,7 @@ static fc_status ensure_mixed_matrix(fc_problem_s& pb, hipStream_t s) {
   A.n_hi = (int64_t)rh.size();
   A.n_lo = (int64_t)rl.size();
   FC_HIP(hipMalloc(&A.val32, A.nnzb * A.bdim * A.bdim * sizeof(float)));
+  if (A.vofs && A.sh_vals > 0) FC_HIP(hipMalloc(&A.vsh32, A.sh_vals * sizeof(float)));
   FC_HIP(launch_cast_matrix(A, s));
   FC_HIP(hipStreamSynchronize(s));   // the host lists must outlive the copies
   return FC_OK;

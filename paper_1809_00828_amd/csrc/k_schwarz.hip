@@ -356,16 +356,17 @@ int64_t sym_block_stride(int m) { return (int64_t)(m / 2 + 1) * m; }
 // the same bits.  A content hash groups candidates; a bitwise comparison
 // decides.
 
-// Hash of one block's copy: the wrapping sum over its words of a mix of
-// (word, index), so it does not depend on the order lanes visit the words.
-__global__ __launch_bounds__(256) void k_block_hash(const double* __restrict__ Q, int64_t stride,
-                                                    int64_t nb, uint64_t* __restrict__ h) {
+// Hash of one block's copy (nw 32-bit words): the wrapping sum over its
+// words of a mix of (word, index), so it does not depend on the order lanes
+// visit the words.
+__global__ __launch_bounds__(256) void k_block_hash(const uint32_t* __restrict__ Q, int64_t nw,
+                                                    uint64_t* __restrict__ h) {
   __shared__ uint64_t part[256];
   const int64_t blk = blockIdx.x;
-  const uint64_t* w = reinterpret_cast<const uint64_t*>(Q + blk * stride);
+  const uint32_t* w = Q + blk * nw;
   uint64_t acc = 0;
-  for (int64_t k = threadIdx.x; k < stride; k += 256) {
-    uint64_t z = w[k] ^ ((uint64_t)k * 0x9E3779B97F4A7C15ull);
+  for (int64_t k = threadIdx.x; k < nw; k += 256) {
+    uint64_t z = (uint64_t)w[k] ^ ((uint64_t)k * 0x9E3779B97F4A7C15ull);
     z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
     z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
     acc += z ^ (z >> 31);
@@ -376,13 +377,12 @@ __global__ __launch_bounds__(256) void k_block_hash(const double* __restrict__ Q
     if (threadIdx.x < off) part[threadIdx.x] += part[threadIdx.x + off];
     __syncthreads();
   }
-  if (threadIdx.x == 0 && blk < nb) h[blk] = part[0];
+  if (threadIdx.x == 0) h[blk] = part[0];
 }
 
 // differ[blk] = 1 when block blk's copy is not bitwise equal to that of
 // block rep[blk] (0 for blocks that are their own representative).
-__global__ __launch_bounds__(256) void k_block_differs(const double* __restrict__ Q,
-                                                       int64_t stride,
+__global__ __launch_bounds__(256) void k_block_differs(const uint32_t* __restrict__ Q, int64_t nw,
                                                        const int32_t* __restrict__ rep,
                                                        int32_t* __restrict__ differ) {
   __shared__ int32_t any[256];
@@ -390,9 +390,9 @@ __global__ __launch_bounds__(256) void k_block_differs(const double* __restrict_
   const int64_t q = rep[blk];
   int32_t d = 0;
   if (q != blk) {
-    const uint64_t* a = reinterpret_cast<const uint64_t*>(Q + blk * stride);
-    const uint64_t* b = reinterpret_cast<const uint64_t*>(Q + q * stride);
-    for (int64_t k = threadIdx.x; k < stride; k += 256) d |= a[k] != b[k] ? 1 : 0;
+    const uint32_t* a = Q + blk * nw;
+    const uint32_t* b = Q + q * nw;
+    for (int64_t k = threadIdx.x; k < nw; k += 256) d |= a[k] != b[k] ? 1 : 0;
   }
   any[threadIdx.x] = d;
   __syncthreads();
@@ -403,17 +403,16 @@ __global__ __launch_bounds__(256) void k_block_differs(const double* __restrict_
   if (threadIdx.x == 0) differ[blk] = any[0];
 }
 
-hipError_t launch_share_blocks(fc_precond_s& pc, hipStream_t s) {
-  const int64_t nb = pc.n_blocks;
-  if (pc.qofs) {
-    (void)hipFree(pc.qofs);
-    pc.qofs = nullptr;
-  }
-  pc.q_distinct = 0;
-  const char* env = std::getenv("FC_SCHWARZ_SHARE");
-  const int mode = env ? std::atoi(env) : -1;
-  if (mode == 0 || pc.m <= 64 || nb < 2 || !pc.Q) return hipSuccess;
-  const int64_t stride = sym_block_stride(pc.m);
+// Offsets (in elements of `stride` per block) of the copy each of the nb
+// blocks reads; *ofs stays null when no block is shared.
+static hipError_t share_copies(const void* Q, int64_t stride, int elem_bytes, int64_t nb,
+                               int mode, int64_t** ofs_out, int64_t* distinct_out,
+                               hipStream_t s) {
+  *ofs_out = nullptr;
+  *distinct_out = 0;
+  if ((stride * elem_bytes) % 4 != 0) return hipSuccess;
+  const int64_t nw = stride * elem_bytes / 4;
+  const uint32_t* W = static_cast<const uint32_t*>(Q);
   uint64_t* dh = nullptr;
   int32_t* drep = nullptr;
   int32_t* ddiff = nullptr;
@@ -427,7 +426,7 @@ hipError_t launch_share_blocks(fc_precond_s& pc, hipStream_t s) {
   hipError_t e = hipMalloc(&dh, nb * sizeof(uint64_t));
   tmp.p[0] = dh;
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_block_hash, dim3((unsigned)nb), dim3(256), 0, s, pc.Q, stride, nb, dh);
+  hipLaunchKernelGGL(k_block_hash, dim3((unsigned)nb), dim3(256), 0, s, W, nw, dh);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   std::vector<uint64_t> h((size_t)nb);
   if ((e = hipMemcpyAsync(h.data(), dh, nb * sizeof(uint64_t), hipMemcpyDeviceToHost, s)) !=
@@ -451,8 +450,7 @@ hipError_t launch_share_blocks(fc_precond_s& pc, hipStream_t s) {
   if ((e = hipMemcpyAsync(drep, rep.data(), nb * sizeof(int32_t), hipMemcpyHostToDevice, s)) !=
       hipSuccess)
     return e;
-  hipLaunchKernelGGL(k_block_differs, dim3((unsigned)nb), dim3(256), 0, s, pc.Q, stride, drep,
-                     ddiff);
+  hipLaunchKernelGGL(k_block_differs, dim3((unsigned)nb), dim3(256), 0, s, W, nw, drep, ddiff);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   std::vector<int32_t> diff((size_t)nb);
   if ((e = hipMemcpyAsync(diff.data(), ddiff, nb * sizeof(int32_t), hipMemcpyDeviceToHost, s)) !=
@@ -467,16 +465,31 @@ hipError_t launch_share_blocks(fc_precond_s& pc, hipStream_t s) {
     ofs[k] = src * stride;
     distinct += src == k;
   }
-  if ((e = hipMalloc(&pc.qofs, nb * sizeof(int64_t))) != hipSuccess) {
-    pc.qofs = nullptr;
+  int64_t* d = nullptr;
+  if ((e = hipMalloc(&d, nb * sizeof(int64_t))) != hipSuccess) return e;
+  if ((e = hipMemcpyAsync(d, ofs.data(), nb * sizeof(int64_t), hipMemcpyHostToDevice, s)) !=
+          hipSuccess ||
+      (e = hipStreamSynchronize(s)) != hipSuccess) {
+    (void)hipFree(d);
     return e;
   }
-  if ((e = hipMemcpyAsync(pc.qofs, ofs.data(), nb * sizeof(int64_t), hipMemcpyHostToDevice, s)) !=
-          hipSuccess ||
-      (e = hipStreamSynchronize(s)) != hipSuccess)
-    return e;
-  pc.q_distinct = distinct;
+  *ofs_out = d;
+  *distinct_out = distinct;
   return hipSuccess;
+}
+
+hipError_t launch_share_blocks(fc_precond_s& pc, hipStream_t s) {
+  const int64_t nb = pc.n_blocks;
+  const char* env = std::getenv("FC_SCHWARZ_SHARE");
+  const int mode = env ? std::atoi(env) : -1;
+  if (mode == 0 || pc.m <= 64 || nb < 2) return hipSuccess;
+  const int64_t stride = sym_block_stride(pc.m);
+  hipError_t e = hipSuccess;
+  if (pc.Q && !pc.qofs)
+    e = share_copies(pc.Q, stride, 8, nb, mode, &pc.qofs, &pc.q_distinct, s);
+  if (e == hipSuccess && pc.Q32 && !pc.qofs32)
+    e = share_copies(pc.Q32, stride, 4, nb, mode, &pc.qofs32, &pc.q32_distinct, s);
+  return e;
 }
 
 hipError_t launch_pack_sym(const fc_precond_s& pc, void* Q, int precision, hipStream_t s) {
@@ -527,11 +540,14 @@ static hipError_t phase1(const fc_precond_s& pc, const T* P, const double* r, co
   }();
   if (pc.m > 64) {
     const int threads = 64 * ((pc.m + 63) / 64);
-    if (kSym && variant && sizeof(T) == 8 && pc.qofs && (const void*)P == (const void*)pc.Q)
+    const int64_t* qo = (const void*)P == (const void*)pc.Q     ? pc.qofs
+                        : (const void*)P == (const void*)pc.Q32 ? pc.qofs32
+                                                                : nullptr;
+    if (kSym && variant && qo)
       hipLaunchKernelGGL((k_schwarz_sym_staged<T, true>), dim3((unsigned)pc.n_blocks),
                          dim3(threads), 0, s, P, stride, pb.elem_nodes, pc.block_elem, pc.nn,
-                         pc.bdim, pc.m, r, q, isd, sc, pc.y, pc.n_blocks, nullptr, nullptr,
-                         pc.qofs);
+                         pc.bdim, pc.m, r, q, isd, sc, pc.y, pc.n_blocks, nullptr,
+                         sizeof(T) == 4 ? pc.unsafe_flag32 : nullptr, qo);
     else if (kSym && variant)
       hipLaunchKernelGGL((k_schwarz_sym_staged<T>), dim3((unsigned)pc.n_blocks), dim3(threads),
                          0, s, P, stride, pb.elem_nodes, pc.block_elem, pc.nn, pc.bdim, pc.m, r,

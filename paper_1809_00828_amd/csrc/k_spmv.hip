@@ -188,16 +188,13 @@ static hipError_t spmv_dispatch(const DeviceBsr& A, const T* val, const XT* x,
   else                                                                                     \
     hipLaunchKernelGGL((k_spmv_bsr<B, GG, T, false, XT, SH>), grid, block, 0, s, A.rowptr,  \
                        A.col, val, x, y, n_rows, sc, partial, rows, A.lat, vofs);
-  // only FP64 values are ever shared
 #define FC_SPMV_CASE(GG)                                                                   \
   case GG:                                                                                 \
-    if constexpr (sizeof(T) == 8) {                                                        \
-      if (vofs) {                                                                          \
-        FC_SPMV_LAUNCH(GG, true)                                                           \
-        break;                                                                             \
-      }                                                                                    \
+    if (vofs) {                                                                            \
+      FC_SPMV_LAUNCH(GG, true)                                                             \
+    } else {                                                                               \
+      FC_SPMV_LAUNCH(GG, false)                                                            \
     }                                                                                      \
-    FC_SPMV_LAUNCH(GG, false)                                                              \
     break;
   switch (G) {
     FC_SPMV_CASE(8)
@@ -323,7 +320,8 @@ hipError_t launch_spmv_mixed(const DeviceBsr& A, const double* p, const float* p
                             A.vofs)) != hipSuccess)
     return e;
   if (A.n_lo > 0)
-    e = spmv_any<float, float>(A, A.val32, p32, q, s, sc, nullptr, A.rows_lo, A.n_lo);
+    e = spmv_any<float, float>(A, A.vsh32 ? A.vsh32 : A.val32, p32, q, s, sc, nullptr, A.rows_lo,
+                               A.n_lo, A.vsh32 ? A.vofs : nullptr);
   return e;
 }
 

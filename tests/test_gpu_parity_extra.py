@@ -140,11 +140,24 @@ def test_shared_rows_give_the_same_products(torch, monkeypatch):
         info = fc.pcg_solve(pb, pc, rhs, xs, tol=1e-10)
         torch.cuda.synchronize()
         res.append((info["iters"], xs.cpu().numpy()))
-    assert res[0][0] == res[1][0] or not same_group
-    if same_group:
-        assert res[0][1].tobytes() == res[1][1].tobytes()
-    else:
-        assert abs(res[0][0] - res[1][0]) <= 2
+    # refinement on the row-mixed matrix: its FP32 rows read the FP32 copy
+    # of the shared rows through the same offsets
+    for pb in (plain, shared):
+        pc = fc.Precond(pb, store=fc.STORE_F64 | fc.STORE_F32)
+        rhs = torch.empty(pb.n, dtype=torch.float64, device="cuda")
+        pb.rhs(rhs)
+        xs = torch.zeros_like(rhs)
+        info = fc.pcg_solve(pb, pc, rhs, xs, tol=1e-8, stop="residual", mode="ir_f32",
+                            inner_tol=1e-4, maxit=200000)
+        torch.cuda.synchronize()
+        assert info["status"] == "OK" and info["fallbacks"] == 0, info
+        res.append((info["iters"], xs.cpu().numpy()))
+    for a, b in ((0, 1), (2, 3)):
+        if same_group:
+            assert res[a][0] == res[b][0]
+            assert res[a][1].tobytes() == res[b][1].tobytes()
+        else:
+            assert abs(res[a][0] - res[b][0]) <= 2
 
 
 def test_shared_block_inverses_give_the_same_products(torch, monkeypatch):
@@ -156,15 +169,17 @@ def test_shared_block_inverses_give_the_same_products(torch, monkeypatch):
     d = fcgen.custom(3, 4, 3, "elasticity", 1e-8, shapes=[], clamp_zmin=True)
     s = assemble.assemble(d)
     pb = fc.Problem.setup(d)
+    store = fc.STORE_F64 | fc.STORE_F32
     monkeypatch.setenv("FC_SCHWARZ_SHARE", "0")
-    own = fc.Precond(pb)
+    own = fc.Precond(pb, store=store)
     monkeypatch.setenv("FC_SCHWARZ_SHARE", "1")
-    shared = fc.Precond(pb)
+    shared = fc.Precond(pb, store=store)
     io, ish = own.info(), shared.info()
-    print(f"[share blocks] distinct {ish['shared_distinct_blocks']} of {ish['n_blocks']}",
-          flush=True)
-    assert io["shared_distinct_blocks"] == 0
+    print(f"[share blocks] distinct {ish['shared_distinct_blocks']} (FP64), "
+          f"{ish['shared_distinct_blocks32']} (FP32) of {ish['n_blocks']}", flush=True)
+    assert io["shared_distinct_blocks"] == 0 and io["shared_distinct_blocks32"] == 0
     assert 0 < ish["shared_distinct_blocks"] < ish["n_blocks"]
+    assert 0 < ish["shared_distinct_blocks32"] < ish["n_blocks"]
     r = _dev(torch, np.random.default_rng(8).standard_normal(pb.n))
     z0 = torch.empty_like(r)
     z1 = torch.empty_like(r)
@@ -176,13 +191,15 @@ def test_shared_block_inverses_give_the_same_products(torch, monkeypatch):
         s["elem_dofs"], s["eta"], 1.0))
     ref = S @ r.cpu().numpy()
     assert np.linalg.norm(z1.cpu().numpy() - ref) <= 1e-8 * np.linalg.norm(ref)
-    out = []
-    for pc in (own, shared):
-        b = torch.empty(pb.n, dtype=torch.float64, device="cuda")
-        pb.rhs(b)
-        x = torch.zeros_like(b)
-        info = fc.pcg_solve(pb, pc, b, x, tol=1e-10)
-        torch.cuda.synchronize()
-        assert info["status"] == "OK", info
-        out.append((info["iters"], x.cpu().numpy().tobytes()))
-    assert out[0] == out[1]
+    # FP64 PCG and PCG with the FP32 copy of the inverses
+    for kw in ({}, {"mode": "s_f32", "stop": "residual", "tol": 1e-8}):
+        out = []
+        for pc in (own, shared):
+            b = torch.empty(pb.n, dtype=torch.float64, device="cuda")
+            pb.rhs(b)
+            x = torch.zeros_like(b)
+            info = fc.pcg_solve(pb, pc, b, x, **{"tol": 1e-10, **kw})
+            torch.cuda.synchronize()
+            assert info["status"] == "OK", info
+            out.append((info["iters"], x.cpu().numpy().tobytes()))
+        assert out[0] == out[1], kw
