@@ -32,7 +32,8 @@ HBM_PEAK_GBS = 8000.0
 # read for a plain 4 GiB copy (profiles/pcg_fp64_elastic32_p3_hbm_counters.md, full
 # copies; profiles/pcg_fp64_elastic32_p3_shared_hbm_counters.md, shared copies);
 # to be re-measured whenever one of these kernels changes.
-TRAFFIC = {"spmv": 8.3640e9, "spmv_shared": 9.2376e8, "schwarz": 4.6881e9,
+TRAFFIC = {"spmv": 8.3640e9, "spmv_shared": 9.2376e8, "spmv_grouped": None,
+           "schwarz": 4.6881e9,
            "schwarz_shared": 1.3893e9}
 METRIC = "DOF·iter/s and time-to-1e-8 residual: mixed/learned vs plain FP64 PCG"
 
@@ -518,13 +519,15 @@ def main():
     # the counter traffic was taken on the elasticity workload
     on_bench_workload = not args.small and args.workload == "elastic32"
     shared = bool(info.get("shared_values"))
-    spmv_name = (f"k_spmv_bsr<{info['bsr_dim']},{info['spmv_group']},double,"
+    grouped = bool(info.get("row_groups"))
+    spmv_name = (f"k_spmv_bsr{'_grp' if grouped else ''}<{info['bsr_dim']},{info['spmv_group']},double,"
                  f"{'lattice' if info.get('lattice_columns') else 'columns'}"
                  f"{',shared' if shared else ''}> (SpMV q = A p)")
     k_spmv = {"bound": "hbm", "kernel": spmv_name,
               "achieved": gbs_spmv, "peak": HBM_PEAK_GBS, "unit": "GB/s",
               "frac": gbs_spmv / HBM_PEAK_GBS,
-              "traffic": (TRAFFIC["spmv_shared" if shared else "spmv"]
+              "traffic": (TRAFFIC["spmv_grouped" if grouped else
+                                  "spmv_shared" if shared else "spmv"]
                           if on_bench_workload else None),
               "bytes_per_launch": spmv_b, "avg_ms": ms_spmv,
               # values the lanes load per launch when every row is counted
@@ -554,6 +557,7 @@ def main():
                    "stop": "relative residual ||b-Ax||/||b||", "form": "fp64",
                    "shared_rows": info.get("shared_rows", 0),
                    "shared_values": info.get("shared_values", 0),
+                   "row_groups": info.get("row_groups", 0),
                    "shared_distinct_blocks": dblk},
         "roofline": dominant,
         "roofline_other": other,

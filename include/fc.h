@@ -214,8 +214,13 @@ fc_status fc_spmv_info(fc_problem pb, int32_t* group, int32_t* lattice);
  * FC_SPMV_SHARE, read at every set-up, selects 0: never share, 1: share
  * whenever a row repeats, unset or other: share when the kept rows hold at
  * most three quarters of the values.  Products are bitwise the same either
- * way; sharing lets repeated rows be read from the caches instead of HBM. */
-fc_status fc_spmv_share_info(fc_problem pb, int64_t* distinct_rows, int64_t* distinct_values);
+ * way; sharing lets repeated rows be read from the caches instead of HBM.
+ * *row_groups (may be NULL) receives the number of groups of up to four
+ * rows with one shared copy (and one lattice box shape) that the full FP64
+ * products process together, loading each value once per group (0: rows
+ * one at a time; FC_SPMV_GROUPED=0 at set-up switches grouping off). */
+fc_status fc_spmv_share_info(fc_problem pb, int64_t* distinct_rows, int64_t* distinct_values,
+                             int64_t* row_groups);
 /* FP32 copy (FC_STORE_F32): the diagonally scaled inverse D^1/2 P_B D^1/2
  * (D = diag(A) on the block) rounded to FP32, kept for the blocks where a
  * Cholesky factorisation of the rounded matrix shows it positive definite

@@ -112,7 +112,7 @@ def load():
         "fc_precond_info": [vp, P(i64), P(i64), P(i64), P(i64)],
         "fc_precond_lowprec_info": [vp, P(i64), P(i64)],
         "fc_spmv_info": [vp, P(i32), P(i32)],
-        "fc_spmv_share_info": [vp, P(i64), P(i64)],
+        "fc_spmv_share_info": [vp, P(i64), P(i64), P(i64)],
         "fc_precond_share_info": [vp, P(i64), P(i64)],
         "fc_host_system_share": [vp, P(i64), P(i64), vp, vp],
         "fc_get_block_inverse": [vp, i64, vp],
@@ -306,12 +306,12 @@ class Problem:
                                           C.byref(m), C.byref(bd)))
             g, lat = C.c_int32(), C.c_int32()
             _check(load().fc_spmv_info(self._h, C.byref(g), C.byref(lat)))
-            sr, sv = C.c_int64(), C.c_int64()
-            _check(load().fc_spmv_share_info(self._h, C.byref(sr), C.byref(sv)))
+            sr, sv, sg = C.c_int64(), C.c_int64(), C.c_int64()
+            _check(load().fc_spmv_share_info(self._h, C.byref(sr), C.byref(sv), C.byref(sg)))
             self._info = {"n_dofs": n.value, "nnzb": nnzb.value, "n_el": nel.value,
                           "m": m.value, "bsr_dim": bd.value, "spmv_group": g.value,
                           "lattice_columns": bool(lat.value), "shared_rows": sr.value,
-                          "shared_values": sv.value}
+                          "shared_values": sv.value, "row_groups": sg.value}
         return self._info
 
     @property

@@ -9,6 +9,7 @@
 #include <memory>
 #include <new>
 #include <string>
+#include <unordered_map>
 #include <vector>
 
 #include "fc_internal.h"
@@ -60,7 +61,7 @@ static void free_problem(fc_problem_s* pb) {
   if (!pb) return;
   for (void* p : {(void*)pb->A.rowptr, (void*)pb->A.col, (void*)pb->A.val, (void*)pb->A.val32,
                   (void*)pb->A.rows_hi, (void*)pb->A.rows_lo, (void*)pb->A.vsh,
-                  (void*)pb->A.vsh32,
+                  (void*)pb->A.vsh32, (void*)pb->A.grp,
                   (void*)pb->A.vofs, (void*)pb->rhs,
                   (void*)pb->elem_nodes, (void*)pb->diag})
     if (p) (void)hipFree(p);
@@ -77,6 +78,70 @@ static void free_precond(fc_precond_s* pc) {
                   (void*)pc->qofs, (void*)pc->qofs32})
     if (p) (void)hipFree(p);
   delete pc;
+}
+
+// Lattice box shape of a row node (the extent of its columns in each
+// direction; the device decodes columns from it).
+static void box_len(int64_t row, const LatticeInfo& lat, int len[3]) {
+  int64_t r = row;
+  for (int k = 0; k < 3; ++k) {
+    len[k] = 1;
+    if (k < lat.dim) {
+      const int g = (int)(r % lat.n1);
+      r /= lat.n1;
+      if (g % lat.p == 0)
+        len[k] = std::min(lat.n1 - 1, g + lat.p) - std::max(0, g - lat.p) + 1;
+      else
+        len[k] = lat.p + 1;
+    }
+  }
+}
+
+// Groups of kShareGroup rows with the same value offset (and, with lattice
+// columns, the same box shape), filled in row order; a group is emitted when
+// full, the rest at the end padded with -1.  Empty when no group would hold
+// more than one row.
+static std::vector<int32_t> group_shared_rows(const std::vector<int64_t>& ofs,
+                                              const LatticeInfo& lat) {
+  const int64_t nr = (int64_t)ofs.size();
+  struct Key {
+    int64_t o;
+    int len[3];
+    bool operator==(const Key& k) const {
+      return o == k.o && len[0] == k.len[0] && len[1] == k.len[1] && len[2] == k.len[2];
+    }
+  };
+  struct Hash {
+    size_t operator()(const Key& k) const {
+      uint64_t h = (uint64_t)k.o * 0x9E3779B97F4A7C15ull;
+      h ^= (uint64_t)(k.len[0] + 16 * k.len[1] + 256 * k.len[2]) * 0xBF58476D1CE4E5B9ull;
+      return (size_t)(h ^ (h >> 29));
+    }
+  };
+  std::unordered_map<Key, std::vector<int32_t>, Hash> open;
+  std::vector<int32_t> out;
+  out.reserve((size_t)nr + kShareGroup);
+  bool multi = false;
+  for (int64_t r = 0; r < nr; ++r) {
+    Key k{ofs[r], {1, 1, 1}};
+    if (lat.dim > 0) box_len(r, lat, k.len);
+    std::vector<int32_t>& g = open[k];
+    g.push_back((int32_t)r);
+    if ((int)g.size() == kShareGroup) {
+      out.insert(out.end(), g.begin(), g.end());
+      g.clear();
+      multi = true;
+    }
+  }
+  for (auto& kv : open) {
+    std::vector<int32_t>& g = kv.second;
+    if (g.empty()) continue;
+    if (g.size() > 1) multi = true;
+    out.insert(out.end(), g.begin(), g.end());
+    out.insert(out.end(), kShareGroup - g.size(), -1);
+  }
+  if (!multi) out.clear();
+  return out;
 }
 
 static fc_status upload_system(const HostSystem& S, hipStream_t stream, fc_problem* out) {
@@ -111,11 +176,11 @@ static fc_status upload_system(const HostSystem& S, hipStream_t stream, fc_probl
   // bitwise-equal block rows share one copy for the FP64 products.
   // FC_SPMV_SHARE: 0 never, 1 whenever a row repeats, otherwise when the
   // distinct rows hold at most three quarters of the values.
+  SharedRows sh;
   {
     const char* env = std::getenv("FC_SPMV_SHARE");
     const int mode = env ? std::atoi(env) : -1;
     if (mode != 0 && pb->A.n_rows > 0) {
-      SharedRows sh;
       share_rows(S, &sh);
       const bool use = sh.distinct_rows < pb->A.n_rows &&
                        (mode == 1 || 4 * (int64_t)sh.vals.size() <= 3 * (int64_t)S.val.size());
@@ -128,6 +193,16 @@ static fc_status upload_system(const HostSystem& S, hipStream_t stream, fc_probl
     }
   }
   if (S.dim > 0) FC_HIP(spmv_enable_lattice(pb->A, S.dim, S.p * S.n + 1, S.p, stream));
+  if (pb->A.vofs) {
+    const char* env = std::getenv("FC_SPMV_GROUPED");
+    if (!env || std::atoi(env) != 0) {
+      std::vector<int32_t> g = group_shared_rows(sh.ofs, pb->A.lat);
+      if (!g.empty()) {
+        FC_TRY(upload(&pb->A.grp, g.data(), g.size()));
+        pb->A.n_grp = (int64_t)g.size() / kShareGroup;
+      }
+    }
+  }
   FC_HIP(spmv_autotune(pb->A, stream));
   FC_HIP(hipStreamSynchronize(stream));
   *out = pb.release();
@@ -561,10 +636,12 @@ fc_status fc_precond_share_info(fc_precond pc, int64_t* distinct_blocks,
   return FC_OK;
 }
 
-fc_status fc_spmv_share_info(fc_problem pb, int64_t* distinct_rows, int64_t* distinct_values) {
+fc_status fc_spmv_share_info(fc_problem pb, int64_t* distinct_rows, int64_t* distinct_values,
+                             int64_t* row_groups) {
   if (!pb) return FC_E_ARG;
   if (distinct_rows) *distinct_rows = pb->A.sh_rows;
   if (distinct_values) *distinct_values = pb->A.sh_vals;
+  if (row_groups) *row_groups = pb->A.grp ? pb->A.n_grp : 0;
   return FC_OK;
 }
 

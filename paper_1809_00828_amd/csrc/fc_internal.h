@@ -75,7 +75,14 @@ struct DeviceBsr {
   float* vsh32 = nullptr;   // FP32 copy of vsh (mixed products), same offsets
   int64_t* vofs = nullptr;
   int64_t sh_rows = 0, sh_vals = 0;   // distinct rows and their values
+  // rows reading one shared copy (and, with lattice columns, of one box
+  // shape), kShareGroup per group in row order, -1 padding: full FP64
+  // products load each shared value once per group
+  int32_t* grp = nullptr;
+  int64_t n_grp = 0;
 };
+
+constexpr int kShareGroup = 4;
 
 struct SolverWs;
 void solver_ws_destroy(SolverWs* ws);

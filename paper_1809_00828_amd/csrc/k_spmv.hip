@@ -21,6 +21,7 @@
 // per workgroup; a one-workgroup kernel of the solver sums them in a fixed
 // order (no atomics).
 #include <cstdlib>
+#include <type_traits>
 
 #include "dev_common.h"
 #include "k_spmv.h"
@@ -137,6 +138,103 @@ __global__ __launch_bounds__(256) void k_spmv_bsr(
   if (threadIdx.x == 0) partial[blockIdx.x] = dot;
 }
 
+// Rows that read one shared copy, R at a time (grp: R row indices per
+// group, -1 padding; with lattice columns the rows of a group have one box
+// shape, so a column is the first row's plus a fixed shift).  Each value is
+// loaded once for the R rows; every row keeps the lane order, the order of
+// its fused multiply-adds and the reduction of k_spmv_bsr, so its result is
+// bitwise that kernel's at the same G.
+template <int B, int G, bool kLat, int R>
+__global__ __launch_bounds__(256) void k_spmv_bsr_grp(
+    const int32_t* __restrict__ rowptr, const int32_t* __restrict__ col,
+    const double* __restrict__ val, const int64_t* __restrict__ vofs,
+    const int32_t* __restrict__ grp, int64_t n_grp, const double* __restrict__ x,
+    double* __restrict__ y, const CgScalars* __restrict__ sc, const LatticeInfo lat) {
+  constexpr int BB = B * B;
+  constexpr int RPW = 256 / G;
+  if (sc && sc->done) return;
+  const int64_t ntiles = (n_grp + RPW - 1) / RPW;
+  const uint32_t nwg = gridDim.x, xcd = blockIdx.x % kNumXcd, j = blockIdx.x / kNumXcd;
+  const uint32_t per = nwg / kNumXcd + (xcd < nwg % kNumXcd ? 1u : 0u);
+  const int64_t t0 = ntiles * xcd / kNumXcd, t1 = ntiles * (xcd + 1) / kNumXcd;
+  const int lane = threadIdx.x % G;
+  for (int64_t tile = t0 + j; tile < t1; tile += per) {
+    const int64_t gi = tile * RPW + threadIdx.x / G;
+    if (gi >= n_grp) continue;
+    int64_t row[R];
+#pragma unroll
+    for (int q = 0; q < R; ++q) row[q] = grp[gi * R + q];
+    const int64_t r0 = row[0];
+    const int L = rowptr[r0 + 1] - rowptr[r0];
+    const double* v = val + vofs[r0];
+    // kLat: shift of each row's columns against row 0's; else the start of
+    // each row's column list
+    int64_t cb[R];
+    RowBox box;
+    if constexpr (kLat) {
+      box = row_box(r0, lat);
+      const int64_t b0 = box.lo[0] + (int64_t)lat.n1 * (box.lo[1] + (int64_t)lat.n1 * box.lo[2]);
+#pragma unroll
+      for (int q = 0; q < R; ++q) {
+        cb[q] = 0;
+        if (row[q] >= 0) {
+          const RowBox bq = row_box(row[q], lat);
+          cb[q] = bq.lo[0] + (int64_t)lat.n1 * (bq.lo[1] + (int64_t)lat.n1 * bq.lo[2]) - b0;
+        }
+      }
+    } else {
+#pragma unroll
+      for (int q = 0; q < R; ++q) cb[q] = row[q] >= 0 ? (int64_t)rowptr[row[q]] : 0;
+    }
+    double acc[R][B];
+#pragma unroll
+    for (int q = 0; q < R; ++q)
+#pragma unroll
+      for (int i = 0; i < B; ++i) acc[q][i] = 0.0;
+    constexpr int U = B == 1 ? 8 : 2;
+    for (int k = lane; k < L; k += U * G) {
+      double a[U][BB];
+      int c0[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int ku = k + u * G;
+        const bool on = ku < L;
+        if constexpr (kLat) c0[u] = on ? lattice_col(box, ku, lat.n1) : -1;
+        else c0[u] = on ? ku : -1;
+#pragma unroll
+        for (int e = 0; e < BB; ++e) a[u][e] = on ? v[(int64_t)e * L + ku] : 0.0;
+      }
+#pragma unroll
+      for (int q = 0; q < R; ++q) {
+        if (row[q] < 0) continue;
+        double xv[U][B];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          int64_t c = -1;
+          if (c0[u] >= 0) c = kLat ? c0[u] + cb[q] : (int64_t)col[cb[q] + c0[u]];
+#pragma unroll
+          for (int jj = 0; jj < B; ++jj) xv[u][jj] = c >= 0 ? x[c * B + jj] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+          for (int i = 0; i < B; ++i)
+#pragma unroll
+            for (int jj = 0; jj < B; ++jj) acc[q][i] = fma(a[u][i * B + jj], xv[u][jj], acc[q][i]);
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+      if (row[q] < 0) continue;
+#pragma unroll
+      for (int i = 0; i < B; ++i) {
+        const double s = group_sum<G>(acc[q][i]);
+        if (lane == 0) y[row[q] * B + i] = s;
+      }
+    }
+  }
+}
+
 // Launch shape.  Group width chosen per matrix by spmv_autotune at set-up,
 // else from the mean row length (FC_SPMV_GROUP overrides both); the PCG
 // variant uses one tile per workgroup unless
@@ -180,6 +278,31 @@ static hipError_t spmv_dispatch(const DeviceBsr& A, const T* val, const XT* x,
   const int64_t nb = (partial && !rows) ? fused_grid(A) : nt;
   static const bool lat_allowed = env_int("FC_SPMV_LATTICE", 1) != 0;
   const bool lat = lat_allowed && A.lat.dim > 0;
+  // full FP64 products over shared rows: grouped rows (the groups were
+  // formed for lattice columns only when the lattice is in use)
+  if constexpr (std::is_same<T, double>::value && std::is_same<XT, double>::value) {
+    if (vofs && val == A.vsh && A.grp && !rows && !partial && lat == (A.lat.dim > 0)) {
+      const int64_t ng = (A.n_grp + 256 / G - 1) / (256 / G);
+      dim3 gg((unsigned)ng), bb(256);
+#define FC_SPMV_GRP(GG)                                                                    \
+  case GG:                                                                                 \
+    if (lat)                                                                               \
+      hipLaunchKernelGGL((k_spmv_bsr_grp<B, GG, true, kShareGroup>), gg, bb, 0, s,          \
+                         A.rowptr, A.col, val, vofs, A.grp, A.n_grp, x, y, sc, A.lat);      \
+    else                                                                                   \
+      hipLaunchKernelGGL((k_spmv_bsr_grp<B, GG, false, kShareGroup>), gg, bb, 0, s,         \
+                         A.rowptr, A.col, val, vofs, A.grp, A.n_grp, x, y, sc, A.lat);      \
+    break;
+      switch (G) {
+        FC_SPMV_GRP(8)
+        FC_SPMV_GRP(16)
+        FC_SPMV_GRP(32)
+        FC_SPMV_GRP(64)
+      }
+#undef FC_SPMV_GRP
+      return hipGetLastError();
+    }
+  }
   dim3 grid((unsigned)nb), block(256);
 #define FC_SPMV_LAUNCH(GG, SH)                                                             \
   if (lat)                                                                                 \

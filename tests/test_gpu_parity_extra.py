@@ -113,8 +113,9 @@ def test_shared_rows_give_the_same_products(torch, monkeypatch):
     shared = fc.Problem.setup(d)
     ip, ish = plain.info(), shared.info()
     print(f"[share] rows {ish['shared_rows']} of {ish['n_dofs'] // 3}, values "
-          f"{ish['shared_values']} of {ish['nnzb'] * 9}; groups {ip['spmv_group']} "
-          f"{ish['spmv_group']}", flush=True)
+          f"{ish['shared_values']} of {ish['nnzb'] * 9}, row groups {ish['row_groups']}; "
+          f"lanes {ip['spmv_group']} {ish['spmv_group']}", flush=True)
+    assert 0 < ish["row_groups"] < ish["n_dofs"] // 3
     assert ip["shared_rows"] == 0 and ip["shared_values"] == 0
     assert 0 < ish["shared_rows"] < ish["n_dofs"] // 3
     same_group = ip["spmv_group"] == ish["spmv_group"]
