@@ -34,7 +34,7 @@ HBM_PEAK_GBS = 8000.0
 # to be re-measured whenever one of these kernels changes.
 TRAFFIC = {"spmv": 8.3640e9, "spmv_shared": 9.2376e8, "spmv_grouped": None,
            "schwarz": 4.6881e9,
-           "schwarz_shared": 1.3893e9}
+           "schwarz_shared": 1.3893e9, "schwarz_grouped": None}
 METRIC = "DOF·iter/s and time-to-1e-8 residual: mixed/learned vs plain FP64 PCG"
 
 
@@ -534,12 +534,15 @@ def main():
               # (repeats of shared rows come from the caches)
               "loaded_bytes_per_launch": algorithmic_bytes(
                   {**info, "shared_values": 0}, m, pinfo["n_blocks"], nn)[0]}
-    schw_name = ((f"k_schwarz_sym_staged<double{',shared' if dblk else ''}>") if m > 64
+    bgrp = bool(pinfo.get("block_groups"))
+    schw_name = (("k_schwarz_sym_grp<4>" if bgrp else
+                  f"k_schwarz_sym_staged<double{',shared' if dblk else ''}>") if m > 64
                  else "k_schwarz_small<double,sym>")
     k_schw = {"bound": "hbm", "kernel": schw_name + " (block products)",
               "achieved": gbs_schw, "peak": HBM_PEAK_GBS, "unit": "GB/s",
               "frac": gbs_schw / HBM_PEAK_GBS,
-              "traffic": (TRAFFIC["schwarz_shared" if dblk else "schwarz"]
+              "traffic": (TRAFFIC["schwarz_grouped" if bgrp else
+                                  "schwarz_shared" if dblk else "schwarz"]
                           if on_bench_workload else None),
               "bytes_per_launch": schw_b, "avg_ms": ms_schw,
               "loaded_bytes_per_launch": algorithmic_bytes(info, m, pinfo["n_blocks"], nn)[1]}
@@ -558,7 +561,8 @@ def main():
                    "shared_rows": info.get("shared_rows", 0),
                    "shared_values": info.get("shared_values", 0),
                    "row_groups": info.get("row_groups", 0),
-                   "shared_distinct_blocks": dblk},
+                   "shared_distinct_blocks": dblk,
+                   "block_groups": pinfo.get("block_groups", 0)},
         "roofline": dominant,
         "roofline_other": other,
         "iters": iters, "status": status,

@@ -236,12 +236,16 @@ fc_status fc_precond_lowprec_info(fc_precond pc, int64_t* n_f32_blocks,
  * its own copy for all other uses; the FP32 copy (FC_STORE_F32) is shared
  * the same way.  *distinct_blocks and *distinct_blocks32 (either may be
  * NULL) receive the number of FP64 and FP32 copies read (0 when no block is
- * shared).  The environment variable
+ * shared).  *block_groups (may be NULL) receives the number of groups of
+ * up to four blocks with one FP64 copy that the FP64 block products process
+ * together, loading each staged chunk once per group (0: blocks one at a
+ * time; FC_SCHWARZ_GROUPED=0 at the build switches grouping off).  The
+ * environment variable
  * FC_SCHWARZ_SHARE, read at every build, selects 0: never share, 1: share
  * whenever a block repeats, unset or other: share when at least a quarter
  * of the blocks repeat.  Products are bitwise the same either way. */
 fc_status fc_precond_share_info(fc_precond pc, int64_t* distinct_blocks,
-                                int64_t* distinct_blocks32);
+                                int64_t* distinct_blocks32, int64_t* block_groups);
 
 /* Copy the FP64 local inverse of block k (m*m values, row-major) to host. */
 fc_status fc_get_block_inverse(fc_precond pc, int64_t k, double* out_host);

@@ -113,7 +113,7 @@ def load():
         "fc_precond_lowprec_info": [vp, P(i64), P(i64)],
         "fc_spmv_info": [vp, P(i32), P(i32)],
         "fc_spmv_share_info": [vp, P(i64), P(i64), P(i64)],
-        "fc_precond_share_info": [vp, P(i64), P(i64)],
+        "fc_precond_share_info": [vp, P(i64), P(i64), P(i64)],
         "fc_host_system_share": [vp, P(i64), P(i64), vp, vp],
         "fc_get_block_inverse": [vp, i64, vp],
         "fc_apply_M": [vp, dp, dp, vp],
@@ -365,11 +365,12 @@ class Precond:
         _check(load().fc_precond_info(self._h, C.byref(a), C.byref(b), C.byref(c), C.byref(d)))
         e, f = C.c_int64(), C.c_int64()
         _check(load().fc_precond_lowprec_info(self._h, C.byref(e), C.byref(f)))
-        g, g32 = C.c_int64(), C.c_int64()
-        _check(load().fc_precond_share_info(self._h, C.byref(g), C.byref(g32)))
+        g, g32, gg = C.c_int64(), C.c_int64(), C.c_int64()
+        _check(load().fc_precond_share_info(self._h, C.byref(g), C.byref(g32), C.byref(gg)))
         return {"n_blocks": a.value, "n_fallback": b.value, "n_eig_blocks": c.value,
                 "n_dropped": d.value, "n_f32_blocks": e.value, "n_f32_from_f64": f.value,
-                "shared_distinct_blocks": g.value, "shared_distinct_blocks32": g32.value}
+                "shared_distinct_blocks": g.value, "shared_distinct_blocks32": g32.value,
+                "block_groups": gg.value}
 
     def block_inverse(self, k):
         out = np.zeros((self.m, self.m), np.float64)

@@ -75,7 +75,7 @@ static void free_precond(fc_precond_s* pc) {
   for (void* p : {(void*)pc->block_elem, (void*)pc->P, (void*)pc->Q, (void*)pc->Q32,
                   (void*)pc->unsafe32, (void*)pc->unsafe_flag32, (void*)pc->Lbf, (void*)pc->isd,
                   (void*)pc->inv_ptr, (void*)pc->inv_idx, (void*)pc->fallback, (void*)pc->y,
-                  (void*)pc->qofs, (void*)pc->qofs32})
+                  (void*)pc->qofs, (void*)pc->qofs32, (void*)pc->qgrp})
     if (p) (void)hipFree(p);
   delete pc;
 }
@@ -629,8 +629,9 @@ fc_status fc_spmv_info(fc_problem pb, int32_t* group, int32_t* lattice) {
 }
 
 fc_status fc_precond_share_info(fc_precond pc, int64_t* distinct_blocks,
-                                int64_t* distinct_blocks32) {
+                                int64_t* distinct_blocks32, int64_t* block_groups) {
   if (!pc) return FC_E_ARG;
+  if (block_groups) *block_groups = pc->qgrp ? pc->n_qgrp : 0;
   if (distinct_blocks) *distinct_blocks = pc->qofs ? pc->q_distinct : 0;
   if (distinct_blocks32) *distinct_blocks32 = pc->qofs32 ? pc->q32_distinct : 0;
   return FC_OK;

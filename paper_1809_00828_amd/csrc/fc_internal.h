@@ -117,6 +117,10 @@ struct fc_precond_s {
   int64_t q_distinct = 0;          // blocks read through qofs that are their own source
   int64_t* qofs32 = nullptr;       // the same for the FP32 copy Q32
   int64_t q32_distinct = 0;
+  // blocks reading one FP64 copy, kShareGroup per group in block order, -1
+  // padding: the FP64 block products load each staged chunk once per group
+  int32_t* qgrp = nullptr;
+  int64_t n_qgrp = 0;
   float* Q32 = nullptr;            // optional FP32 wrapped-diagonal copy of D^1/2 P D^1/2
   int32_t* unsafe32 = nullptr;     // blocks whose FP32 copy is not safely positive
   int32_t* unsafe_flag32 = nullptr; // the same as one flag per block

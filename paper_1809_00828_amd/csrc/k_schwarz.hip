@@ -102,6 +102,46 @@ __global__ __launch_bounds__(256) void k_schwarz_sym_staged(
   if (act) y[blk * m + i] = isd ? v * isd[dof] : v;
 }
 
+// FP64, m > 64: groups of R blocks that read one stored copy (grp: R block
+// indices per group, -1 padding), one workgroup per group.  Each staged
+// chunk of the copy is loaded once for the R blocks; every block's result is
+// bitwise that of k_schwarz_sym_staged.
+template <int R>
+__global__ __launch_bounds__(256) void k_schwarz_sym_grp(
+    const double* __restrict__ P, const int64_t* __restrict__ qofs,
+    const int32_t* __restrict__ grp, int64_t n_grp, const int32_t* __restrict__ elem_nodes,
+    const int32_t* __restrict__ block_elem, int nn, int bd, int m,
+    const double* __restrict__ r, const double* __restrict__ q,
+    const CgScalars* __restrict__ sc, double* __restrict__ y) {
+  __shared__ double rB[R][256];
+  __shared__ double tile[StageRows<double>::value][256];
+  if (sc && sc->done) return;
+  const int64_t g = xcd_remap(blockIdx.x, gridDim.x);
+  if (g >= n_grp) return;
+  const double alpha = (sc && q) ? sc->alpha : 0.0;
+  const int i = threadIdx.x;
+  const bool act = i < m;
+  int64_t blk[R];
+  bool use[R];
+#pragma unroll
+  for (int k = 0; k < R; ++k) {
+    blk[k] = grp[g * R + k];
+    use[k] = blk[k] >= 0;
+    if (act && use[k]) {
+      const int64_t e = block_elem[blk[k]];
+      const int64_t dof = (int64_t)elem_nodes[e * nn + i / bd] * bd + (i % bd);
+      rB[k][i] = gather_r(r, q, alpha, dof);
+    }
+  }
+  double v[R];
+  sym_block_staged_multi<double, double, R>(P + qofs[blk[0]], rB, use, m, i, tile, v);
+  if (act) {
+#pragma unroll
+    for (int k = 0; k < R; ++k)
+      if (use[k]) y[blk[k] * m + i] = v[k];
+  }
+}
+
 // m <= 64: each wave handles floor(64/m) blocks, one lane per output row.
 template <typename T, bool kSym>
 __global__ __launch_bounds__(256) void k_schwarz_small(
@@ -407,9 +447,13 @@ __global__ __launch_bounds__(256) void k_block_differs(const uint32_t* __restric
 // blocks reads; *ofs stays null when no block is shared.
 static hipError_t share_copies(const void* Q, int64_t stride, int elem_bytes, int64_t nb,
                                int mode, int64_t** ofs_out, int64_t* distinct_out,
-                               hipStream_t s) {
+                               int32_t** grp_out, int64_t* n_grp_out, hipStream_t s) {
   *ofs_out = nullptr;
   *distinct_out = 0;
+  if (grp_out) {
+    *grp_out = nullptr;
+    *n_grp_out = 0;
+  }
   if ((stride * elem_bytes) % 4 != 0) return hipSuccess;
   const int64_t nw = stride * elem_bytes / 4;
   const uint32_t* W = static_cast<const uint32_t*>(Q);
@@ -475,6 +519,34 @@ static hipError_t share_copies(const void* Q, int64_t stride, int elem_bytes, in
   }
   *ofs_out = d;
   *distinct_out = distinct;
+  if (!grp_out) return hipSuccess;
+  // groups of kShareGroup blocks with one source, filled in block order
+  std::unordered_map<int64_t, std::vector<int32_t>> open;
+  std::vector<int32_t> gl;
+  gl.reserve((size_t)nb + kShareGroup);
+  for (int64_t k = 0; k < nb; ++k) {
+    std::vector<int32_t>& g = open[ofs[k]];
+    g.push_back((int32_t)k);
+    if ((int)g.size() == kShareGroup) {
+      gl.insert(gl.end(), g.begin(), g.end());
+      g.clear();
+    }
+  }
+  for (auto& kv : open) {
+    if (kv.second.empty()) continue;
+    gl.insert(gl.end(), kv.second.begin(), kv.second.end());
+    gl.insert(gl.end(), kShareGroup - kv.second.size(), -1);
+  }
+  int32_t* dg = nullptr;
+  if ((e = hipMalloc(&dg, gl.size() * sizeof(int32_t))) != hipSuccess) return e;
+  if ((e = hipMemcpyAsync(dg, gl.data(), gl.size() * sizeof(int32_t), hipMemcpyHostToDevice,
+                          s)) != hipSuccess ||
+      (e = hipStreamSynchronize(s)) != hipSuccess) {
+    (void)hipFree(dg);
+    return e;
+  }
+  *grp_out = dg;
+  *n_grp_out = (int64_t)gl.size() / kShareGroup;
   return hipSuccess;
 }
 
@@ -485,10 +557,14 @@ hipError_t launch_share_blocks(fc_precond_s& pc, hipStream_t s) {
   if (mode == 0 || pc.m <= 64 || nb < 2) return hipSuccess;
   const int64_t stride = sym_block_stride(pc.m);
   hipError_t e = hipSuccess;
+  const char* genv = std::getenv("FC_SCHWARZ_GROUPED");
+  const bool grouped = !genv || std::atoi(genv) != 0;
   if (pc.Q && !pc.qofs)
-    e = share_copies(pc.Q, stride, 8, nb, mode, &pc.qofs, &pc.q_distinct, s);
+    e = share_copies(pc.Q, stride, 8, nb, mode, &pc.qofs, &pc.q_distinct,
+                     grouped ? &pc.qgrp : nullptr, &pc.n_qgrp, s);
   if (e == hipSuccess && pc.Q32 && !pc.qofs32)
-    e = share_copies(pc.Q32, stride, 4, nb, mode, &pc.qofs32, &pc.q32_distinct, s);
+    e = share_copies(pc.Q32, stride, 4, nb, mode, &pc.qofs32, &pc.q32_distinct, nullptr,
+                     nullptr, s);
   return e;
 }
 
@@ -543,7 +619,11 @@ static hipError_t phase1(const fc_precond_s& pc, const T* P, const double* r, co
     const int64_t* qo = (const void*)P == (const void*)pc.Q     ? pc.qofs
                         : (const void*)P == (const void*)pc.Q32 ? pc.qofs32
                                                                 : nullptr;
-    if (kSym && variant && qo)
+    if (kSym && variant && sizeof(T) == 8 && qo && qo == pc.qofs && pc.qgrp)
+      hipLaunchKernelGGL((k_schwarz_sym_grp<kShareGroup>), dim3((unsigned)pc.n_qgrp),
+                         dim3(threads), 0, s, pc.Q, pc.qofs, pc.qgrp, pc.n_qgrp, pb.elem_nodes,
+                         pc.block_elem, pc.nn, pc.bdim, pc.m, r, q, sc, pc.y);
+    else if (kSym && variant && qo)
       hipLaunchKernelGGL((k_schwarz_sym_staged<T, true>), dim3((unsigned)pc.n_blocks),
                          dim3(threads), 0, s, P, stride, pb.elem_nodes, pc.block_elem, pc.nn,
                          pc.bdim, pc.m, r, q, isd, sc, pc.y, pc.n_blocks, nullptr,

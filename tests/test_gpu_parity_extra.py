@@ -181,6 +181,8 @@ def test_shared_block_inverses_give_the_same_products(torch, monkeypatch):
     assert io["shared_distinct_blocks"] == 0 and io["shared_distinct_blocks32"] == 0
     assert 0 < ish["shared_distinct_blocks"] < ish["n_blocks"]
     assert 0 < ish["shared_distinct_blocks32"] < ish["n_blocks"]
+    # the FP64 products take the blocks with one copy four at a time
+    assert ish["shared_distinct_blocks"] <= ish["block_groups"] < ish["n_blocks"]
     r = _dev(torch, np.random.default_rng(8).standard_normal(pb.n))
     z0 = torch.empty_like(r)
     z1 = torch.empty_like(r)
