@@ -30,11 +30,12 @@ HBM_PEAK_GBS = 8000.0
 # HBM bytes per launch on the 32^3 elasticity workload from two rocprofv3
 # counter passes (FETCH_SIZE, WRITE_SIZE), scaled by what the same counters
 # read for a plain 4 GiB copy (profiles/pcg_fp64_elastic32_p3_hbm_counters.md, full
-# copies; profiles/pcg_fp64_elastic32_p3_shared_hbm_counters.md, shared copies);
+# copies; profiles/pcg_fp64_elastic32_p3_shared_hbm_counters.md, shared copies one
+# at a time; profiles/pcg_fp64_elastic32_p3_grouped_hbm_counters.md, grouped);
 # to be re-measured whenever one of these kernels changes.
-TRAFFIC = {"spmv": 8.3640e9, "spmv_shared": 9.2376e8, "spmv_grouped": None,
+TRAFFIC = {"spmv": 8.3640e9, "spmv_shared": 9.2376e8, "spmv_grouped": 1.1796e9,
            "schwarz": 4.6881e9,
-           "schwarz_shared": 1.3893e9, "schwarz_grouped": None}
+           "schwarz_shared": 1.3893e9, "schwarz_grouped": 1.3659e9}
 METRIC = "DOF·iter/s and time-to-1e-8 residual: mixed/learned vs plain FP64 PCG"
 
 
