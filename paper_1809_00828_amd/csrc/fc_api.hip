@@ -61,7 +61,7 @@ static void free_problem(fc_problem_s* pb) {
   if (!pb) return;
   for (void* p : {(void*)pb->A.rowptr, (void*)pb->A.col, (void*)pb->A.val, (void*)pb->A.val32,
                   (void*)pb->A.rows_hi, (void*)pb->A.rows_lo, (void*)pb->A.vsh,
-                  (void*)pb->A.vsh32, (void*)pb->A.grp,
+                  (void*)pb->A.vsh32, (void*)pb->A.grp, (void*)pb->A.grp_lo,
                   (void*)pb->A.vofs, (void*)pb->rhs,
                   (void*)pb->elem_nodes, (void*)pb->diag})
     if (p) (void)hipFree(p);
@@ -75,7 +75,7 @@ static void free_precond(fc_precond_s* pc) {
   for (void* p : {(void*)pc->block_elem, (void*)pc->P, (void*)pc->Q, (void*)pc->Q32,
                   (void*)pc->unsafe32, (void*)pc->unsafe_flag32, (void*)pc->Lbf, (void*)pc->isd,
                   (void*)pc->inv_ptr, (void*)pc->inv_idx, (void*)pc->fallback, (void*)pc->y,
-                  (void*)pc->qofs, (void*)pc->qofs32, (void*)pc->qgrp})
+                  (void*)pc->qofs, (void*)pc->qofs32, (void*)pc->qgrp, (void*)pc->qgrp32})
     if (p) (void)hipFree(p);
   delete pc;
 }
@@ -97,13 +97,10 @@ static void box_len(int64_t row, const LatticeInfo& lat, int len[3]) {
   }
 }
 
-// Groups of kShareGroup rows with the same value offset (and, with lattice
-// columns, the same box shape), filled in row order; a group is emitted when
-// full, the rest at the end padded with -1.  Empty when no group would hold
-// more than one row.
-static std::vector<int32_t> group_shared_rows(const std::vector<int64_t>& ofs,
-                                              const LatticeInfo& lat) {
-  const int64_t nr = (int64_t)ofs.size();
+// A group is emitted when full, the rest at the end padded with -1.
+std::vector<int32_t> group_rows_by_copy(const std::vector<int64_t>& ofs, const LatticeInfo& lat,
+                                        const std::vector<int32_t>* subset) {
+  const int64_t nr = subset ? (int64_t)subset->size() : (int64_t)ofs.size();
   struct Key {
     int64_t o;
     int len[3];
@@ -122,7 +119,8 @@ static std::vector<int32_t> group_shared_rows(const std::vector<int64_t>& ofs,
   std::vector<int32_t> out;
   out.reserve((size_t)nr + kShareGroup);
   bool multi = false;
-  for (int64_t r = 0; r < nr; ++r) {
+  for (int64_t t = 0; t < nr; ++t) {
+    const int64_t r = subset ? (int64_t)(*subset)[t] : t;
     Key k{ofs[r], {1, 1, 1}};
     if (lat.dim > 0) box_len(r, lat, k.len);
     std::vector<int32_t>& g = open[k];
@@ -189,6 +187,7 @@ static fc_status upload_system(const HostSystem& S, hipStream_t stream, fc_probl
         FC_TRY(upload(&pb->A.vofs, sh.ofs.data(), sh.ofs.size()));
         pb->A.sh_rows = sh.distinct_rows;
         pb->A.sh_vals = (int64_t)sh.vals.size();
+        pb->vofs_host = sh.ofs;
       }
     }
   }
@@ -196,7 +195,7 @@ static fc_status upload_system(const HostSystem& S, hipStream_t stream, fc_probl
   if (pb->A.vofs) {
     const char* env = std::getenv("FC_SPMV_GROUPED");
     if (!env || std::atoi(env) != 0) {
-      std::vector<int32_t> g = group_shared_rows(sh.ofs, pb->A.lat);
+      std::vector<int32_t> g = group_rows_by_copy(sh.ofs, pb->A.lat, nullptr);
       if (!g.empty()) {
         FC_TRY(upload(&pb->A.grp, g.data(), g.size()));
         pb->A.n_grp = (int64_t)g.size() / kShareGroup;

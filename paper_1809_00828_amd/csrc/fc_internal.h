@@ -80,9 +80,18 @@ struct DeviceBsr {
   // products load each shared value once per group
   int32_t* grp = nullptr;
   int64_t n_grp = 0;
+  // the same over the FP32 rows (rows_lo) of the mixed product
+  int32_t* grp_lo = nullptr;
+  int64_t n_grp_lo = 0;
 };
 
 constexpr int kShareGroup = 4;
+
+// Groups of kShareGroup rows with the same value offset (and, with lattice
+// columns, the same box shape) among `subset` (all rows when null), filled
+// in row order, -1 padding; empty when no group would hold two rows.
+std::vector<int32_t> group_rows_by_copy(const std::vector<int64_t>& ofs, const LatticeInfo& lat,
+                                        const std::vector<int32_t>* subset);
 
 struct SolverWs;
 void solver_ws_destroy(SolverWs* ws);
@@ -101,6 +110,7 @@ struct fc_problem_s {
   int32_t* elem_nodes = nullptr;   // [n_el*nn]
   std::vector<double> eta;         // host copy [n_el]
   std::vector<int32_t> elem_nodes_host;
+  std::vector<int64_t> vofs_host;  // host copy of A.vofs (empty when rows are not shared)
   double* diag = nullptr;          // A_ll [n_dofs]
 };
 
@@ -121,6 +131,8 @@ struct fc_precond_s {
   // padding: the FP64 block products load each staged chunk once per group
   int32_t* qgrp = nullptr;
   int64_t n_qgrp = 0;
+  int32_t* qgrp32 = nullptr;       // the same for the FP32 copy
+  int64_t n_qgrp32 = 0;
   float* Q32 = nullptr;            // optional FP32 wrapped-diagonal copy of D^1/2 P D^1/2
   int32_t* unsafe32 = nullptr;     // blocks whose FP32 copy is not safely positive
   int32_t* unsafe_flag32 = nullptr; // the same as one flag per block

@@ -102,43 +102,46 @@ __global__ __launch_bounds__(256) void k_schwarz_sym_staged(
   if (act) y[blk * m + i] = isd ? v * isd[dof] : v;
 }
 
-// FP64, m > 64: groups of R blocks that read one stored copy (grp: R block
+// m > 64: groups of R blocks that read one stored copy (grp: R block
 // indices per group, -1 padding), one workgroup per group.  Each staged
 // chunk of the copy is loaded once for the R blocks; every block's result is
-// bitwise that of k_schwarz_sym_staged.
-template <int R>
+// bitwise that of k_schwarz_sym_staged (FP32 copies: scaled by isd, blocks
+// flagged in skip left to the FP64 launch, as there).
+template <typename T, int R>
 __global__ __launch_bounds__(256) void k_schwarz_sym_grp(
-    const double* __restrict__ P, const int64_t* __restrict__ qofs,
+    const T* __restrict__ P, const int64_t* __restrict__ qofs,
     const int32_t* __restrict__ grp, int64_t n_grp, const int32_t* __restrict__ elem_nodes,
     const int32_t* __restrict__ block_elem, int nn, int bd, int m,
-    const double* __restrict__ r, const double* __restrict__ q,
-    const CgScalars* __restrict__ sc, double* __restrict__ y) {
-  __shared__ double rB[R][256];
-  __shared__ double tile[StageRows<double>::value][256];
+    const double* __restrict__ r, const double* __restrict__ q, const double* __restrict__ isd,
+    const CgScalars* __restrict__ sc, double* __restrict__ y, const int32_t* __restrict__ skip) {
+  using A = typename Acc<T>::type;
+  __shared__ A rB[R][256];
+  __shared__ T tile[StageRows<T>::value][256];
   if (sc && sc->done) return;
   const int64_t g = xcd_remap(blockIdx.x, gridDim.x);
   if (g >= n_grp) return;
   const double alpha = (sc && q) ? sc->alpha : 0.0;
   const int i = threadIdx.x;
   const bool act = i < m;
-  int64_t blk[R];
+  int64_t blk[R], dof[R];
   bool use[R];
 #pragma unroll
   for (int k = 0; k < R; ++k) {
     blk[k] = grp[g * R + k];
-    use[k] = blk[k] >= 0;
+    use[k] = blk[k] >= 0 && !(skip && skip[blk[k]]);
+    dof[k] = 0;
     if (act && use[k]) {
       const int64_t e = block_elem[blk[k]];
-      const int64_t dof = (int64_t)elem_nodes[e * nn + i / bd] * bd + (i % bd);
-      rB[k][i] = gather_r(r, q, alpha, dof);
+      dof[k] = (int64_t)elem_nodes[e * nn + i / bd] * bd + (i % bd);
+      rB[k][i] = (A)(gather_r(r, q, alpha, dof[k]) * (isd ? isd[dof[k]] : 1.0));
     }
   }
   double v[R];
-  sym_block_staged_multi<double, double, R>(P + qofs[blk[0]], rB, use, m, i, tile, v);
+  sym_block_staged_multi<T, A, R>(P + qofs[blk[0]], rB, use, m, i, tile, v);
   if (act) {
 #pragma unroll
     for (int k = 0; k < R; ++k)
-      if (use[k]) y[blk[k] * m + i] = v[k];
+      if (use[k]) y[blk[k] * m + i] = isd ? v[k] * isd[dof[k]] : v[k];
   }
 }
 
@@ -563,8 +566,8 @@ hipError_t launch_share_blocks(fc_precond_s& pc, hipStream_t s) {
     e = share_copies(pc.Q, stride, 8, nb, mode, &pc.qofs, &pc.q_distinct,
                      grouped ? &pc.qgrp : nullptr, &pc.n_qgrp, s);
   if (e == hipSuccess && pc.Q32 && !pc.qofs32)
-    e = share_copies(pc.Q32, stride, 4, nb, mode, &pc.qofs32, &pc.q32_distinct, nullptr,
-                     nullptr, s);
+    e = share_copies(pc.Q32, stride, 4, nb, mode, &pc.qofs32, &pc.q32_distinct,
+                     grouped ? &pc.qgrp32 : nullptr, &pc.n_qgrp32, s);
   return e;
 }
 
@@ -619,10 +622,13 @@ static hipError_t phase1(const fc_precond_s& pc, const T* P, const double* r, co
     const int64_t* qo = (const void*)P == (const void*)pc.Q     ? pc.qofs
                         : (const void*)P == (const void*)pc.Q32 ? pc.qofs32
                                                                 : nullptr;
-    if (kSym && variant && sizeof(T) == 8 && qo && qo == pc.qofs && pc.qgrp)
-      hipLaunchKernelGGL((k_schwarz_sym_grp<kShareGroup>), dim3((unsigned)pc.n_qgrp),
-                         dim3(threads), 0, s, pc.Q, pc.qofs, pc.qgrp, pc.n_qgrp, pb.elem_nodes,
-                         pc.block_elem, pc.nn, pc.bdim, pc.m, r, q, sc, pc.y);
+    const int32_t* qg = qo == nullptr ? nullptr : qo == pc.qofs ? pc.qgrp : pc.qgrp32;
+    const int64_t nqg = qo == pc.qofs ? pc.n_qgrp : pc.n_qgrp32;
+    if (kSym && variant && qo && qg)
+      hipLaunchKernelGGL((k_schwarz_sym_grp<T, kShareGroup>), dim3((unsigned)nqg),
+                         dim3(threads), 0, s, P, qo, qg, nqg, pb.elem_nodes, pc.block_elem,
+                         pc.nn, pc.bdim, pc.m, r, q, isd, sc, pc.y,
+                         sizeof(T) == 4 ? pc.unsafe_flag32 : nullptr);
     else if (kSym && variant && qo)
       hipLaunchKernelGGL((k_schwarz_sym_staged<T, true>), dim3((unsigned)pc.n_blocks),
                          dim3(threads), 0, s, P, stride, pb.elem_nodes, pc.block_elem, pc.nn,

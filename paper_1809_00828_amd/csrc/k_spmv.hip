@@ -144,12 +144,14 @@ __global__ __launch_bounds__(256) void k_spmv_bsr(
 // loaded once for the R rows; every row keeps the lane order, the order of
 // its fused multiply-adds and the reduction of k_spmv_bsr, so its result is
 // bitwise that kernel's at the same G.
-template <int B, int G, bool kLat, int R>
+template <int B, int G, bool kLat, int R, typename T = double, typename XT = double>
 __global__ __launch_bounds__(256) void k_spmv_bsr_grp(
     const int32_t* __restrict__ rowptr, const int32_t* __restrict__ col,
-    const double* __restrict__ val, const int64_t* __restrict__ vofs,
-    const int32_t* __restrict__ grp, int64_t n_grp, const double* __restrict__ x,
+    const T* __restrict__ val, const int64_t* __restrict__ vofs,
+    const int32_t* __restrict__ grp, int64_t n_grp, const XT* __restrict__ x,
     double* __restrict__ y, const CgScalars* __restrict__ sc, const LatticeInfo lat) {
+  // FP32 values accumulate in FP32, as in k_spmv_bsr
+  using AC = typename std::conditional<sizeof(T) == 8, double, float>::type;
   constexpr int BB = B * B;
   constexpr int RPW = 256 / G;
   if (sc && sc->done) return;
@@ -166,7 +168,7 @@ __global__ __launch_bounds__(256) void k_spmv_bsr_grp(
     for (int q = 0; q < R; ++q) row[q] = grp[gi * R + q];
     const int64_t r0 = row[0];
     const int L = rowptr[r0 + 1] - rowptr[r0];
-    const double* v = val + vofs[r0];
+    const T* v = val + vofs[r0];
     // kLat: shift of each row's columns against row 0's; else the start of
     // each row's column list
     int64_t cb[R];
@@ -186,14 +188,14 @@ __global__ __launch_bounds__(256) void k_spmv_bsr_grp(
 #pragma unroll
       for (int q = 0; q < R; ++q) cb[q] = row[q] >= 0 ? (int64_t)rowptr[row[q]] : 0;
     }
-    double acc[R][B];
+    AC acc[R][B];
 #pragma unroll
     for (int q = 0; q < R; ++q)
 #pragma unroll
-      for (int i = 0; i < B; ++i) acc[q][i] = 0.0;
+      for (int i = 0; i < B; ++i) acc[q][i] = AC(0);
     constexpr int U = B == 1 ? 8 : 2;
     for (int k = lane; k < L; k += U * G) {
-      double a[U][BB];
+      T a[U][BB];
       int c0[U];
 #pragma unroll
       for (int u = 0; u < U; ++u) {
@@ -202,25 +204,30 @@ __global__ __launch_bounds__(256) void k_spmv_bsr_grp(
         if constexpr (kLat) c0[u] = on ? lattice_col(box, ku, lat.n1) : -1;
         else c0[u] = on ? ku : -1;
 #pragma unroll
-        for (int e = 0; e < BB; ++e) a[u][e] = on ? v[(int64_t)e * L + ku] : 0.0;
+        for (int e = 0; e < BB; ++e) a[u][e] = on ? v[(int64_t)e * L + ku] : T(0);
       }
 #pragma unroll
       for (int q = 0; q < R; ++q) {
         if (row[q] < 0) continue;
-        double xv[U][B];
+        XT xv[U][B];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
           int64_t c = -1;
           if (c0[u] >= 0) c = kLat ? c0[u] + cb[q] : (int64_t)col[cb[q] + c0[u]];
 #pragma unroll
-          for (int jj = 0; jj < B; ++jj) xv[u][jj] = c >= 0 ? x[c * B + jj] : 0.0;
+          for (int jj = 0; jj < B; ++jj) xv[u][jj] = c >= 0 ? x[c * B + jj] : XT(0);
         }
 #pragma unroll
         for (int u = 0; u < U; ++u)
 #pragma unroll
           for (int i = 0; i < B; ++i)
 #pragma unroll
-            for (int jj = 0; jj < B; ++jj) acc[q][i] = fma(a[u][i * B + jj], xv[u][jj], acc[q][i]);
+            for (int jj = 0; jj < B; ++jj) {
+              if constexpr (sizeof(T) == 8)
+                acc[q][i] = fma((double)a[u][i * B + jj], (double)xv[u][jj], acc[q][i]);
+              else
+                acc[q][i] = fmaf((float)a[u][i * B + jj], (float)xv[u][jj], acc[q][i]);
+            }
       }
     }
 #pragma unroll
@@ -228,7 +235,7 @@ __global__ __launch_bounds__(256) void k_spmv_bsr_grp(
       if (row[q] < 0) continue;
 #pragma unroll
       for (int i = 0; i < B; ++i) {
-        const double s = group_sum<G>(acc[q][i]);
+        const double s = (double)group_sum<G>(acc[q][i]);
         if (lane == 0) y[row[q] * B + i] = s;
       }
     }
@@ -280,18 +287,33 @@ static hipError_t spmv_dispatch(const DeviceBsr& A, const T* val, const XT* x,
   const bool lat = lat_allowed && A.lat.dim > 0;
   // full FP64 products over shared rows: grouped rows (the groups were
   // formed for lattice columns only when the lattice is in use)
+  // (full FP64 products over all rows; FP32 products over the FP32 rows of
+  // the mixed product, grouped among those rows)
+  const int32_t* gl = nullptr;
+  int64_t gn = 0;
   if constexpr (std::is_same<T, double>::value && std::is_same<XT, double>::value) {
-    if (vofs && val == A.vsh && A.grp && !rows && !partial && lat == (A.lat.dim > 0)) {
-      const int64_t ng = (A.n_grp + 256 / G - 1) / (256 / G);
+    if (vofs && val == A.vsh && !rows) {
+      gl = A.grp;
+      gn = A.n_grp;
+    }
+  } else if constexpr (std::is_same<T, float>::value && std::is_same<XT, float>::value) {
+    if (vofs && val == A.vsh32 && rows == A.rows_lo) {
+      gl = A.grp_lo;
+      gn = A.n_grp_lo;
+    }
+  }
+  {
+    if (gl && gn > 0 && !partial && lat == (A.lat.dim > 0)) {
+      const int64_t ng = (gn + 256 / G - 1) / (256 / G);
       dim3 gg((unsigned)ng), bb(256);
 #define FC_SPMV_GRP(GG)                                                                    \
   case GG:                                                                                 \
     if (lat)                                                                               \
-      hipLaunchKernelGGL((k_spmv_bsr_grp<B, GG, true, kShareGroup>), gg, bb, 0, s,          \
-                         A.rowptr, A.col, val, vofs, A.grp, A.n_grp, x, y, sc, A.lat);      \
+      hipLaunchKernelGGL((k_spmv_bsr_grp<B, GG, true, kShareGroup, T, XT>), gg, bb, 0, s,   \
+                         A.rowptr, A.col, val, vofs, gl, gn, x, y, sc, A.lat);              \
     else                                                                                   \
-      hipLaunchKernelGGL((k_spmv_bsr_grp<B, GG, false, kShareGroup>), gg, bb, 0, s,         \
-                         A.rowptr, A.col, val, vofs, A.grp, A.n_grp, x, y, sc, A.lat);      \
+      hipLaunchKernelGGL((k_spmv_bsr_grp<B, GG, false, kShareGroup, T, XT>), gg, bb, 0, s,  \
+                         A.rowptr, A.col, val, vofs, gl, gn, x, y, sc, A.lat);              \
     break;
       switch (G) {
         FC_SPMV_GRP(8)
