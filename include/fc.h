@@ -330,7 +330,9 @@ typedef struct {
 /* Preconditioned CG (Sec. 5, with S of Eq. 6) from x = 0: b_dev and x_dev
  * are device buffers of n_dofs FP64 values (x_dev receives the solution).
  * Returns FC_OK, FC_E_NOTCONV (x = last iterate), FC_E_BREAKDOWN or
- * FC_E_NAN, and fills *info (may be NULL).  Synchronises the stream. */
+ * FC_E_NAN, and fills *info (may be NULL); FC_E_ARG or FC_E_UNSUPPORTED for
+ * invalid arguments or options, FC_E_NOMEM or FC_E_DEVICE when a device or
+ * host allocation or a launch fails.  Synchronises the stream. */
 fc_status fc_pcg_solve(fc_problem pb, fc_precond pc, const double* b_dev,
                        double* x_dev, const fc_solve_opts* opts,
                        fc_solve_info* info, void* stream);

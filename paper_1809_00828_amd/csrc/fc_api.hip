@@ -142,7 +142,7 @@ std::vector<int32_t> group_rows_by_copy(const std::vector<int64_t>& ofs, const L
   return out;
 }
 
-static fc_status upload_system(const HostSystem& S, hipStream_t stream, fc_problem* out) {
+static fc_status upload_system_body(const HostSystem& S, hipStream_t stream, fc_problem* out) {
   std::unique_ptr<fc_problem_s, void (*)(fc_problem_s*)> pb(new (std::nothrow) fc_problem_s(),
                                                            free_problem);
   if (!pb) return FC_E_NOMEM;
@@ -206,6 +206,18 @@ static fc_status upload_system(const HostSystem& S, hipStream_t stream, fc_probl
   FC_HIP(hipStreamSynchronize(stream));
   *out = pb.release();
   return FC_OK;
+}
+
+// Host containers of the set-up can run out of memory (the kept copies of
+// shared rows hold up to three quarters of the values): report it instead of
+// letting the exception cross the C boundary.
+static fc_status upload_system(const HostSystem& S, hipStream_t stream, fc_problem* out) {
+  try {
+    return upload_system_body(S, stream, out);
+  } catch (const std::bad_alloc&) {
+    set_error("set-up: out of host memory");
+    return FC_E_NOMEM;
+  }
 }
 
 static void to_desc_check() {}
@@ -440,8 +452,8 @@ fc_status fc_apply_A(fc_problem pb, const double* x_dev, double* y_dev, void* st
   return FC_OK;
 }
 
-fc_status fc_precond_build(fc_problem pb, const fc_precond_opts* opts, void* stream,
-                           fc_precond* out) {
+static fc_status precond_build_body(fc_problem pb, const fc_precond_opts* opts, void* stream,
+                                    fc_precond* out) {
   if (!pb || !out) {
     set_error("fc_precond_build: NULL argument");
     return FC_E_ARG;
@@ -682,8 +694,18 @@ fc_status fc_apply_M(fc_precond pc, const double* r_dev, double* z_dev, void* st
   return FC_OK;
 }
 
-fc_status fc_pcg_solve(fc_problem pb, fc_precond pc, const double* b_dev, double* x_dev,
-                       const fc_solve_opts* opts, fc_solve_info* info, void* stream) {
+fc_status fc_precond_build(fc_problem pb, const fc_precond_opts* opts, void* stream,
+                           fc_precond* out) {
+  try {
+    return precond_build_body(pb, opts, stream, out);
+  } catch (const std::bad_alloc&) {
+    set_error("fc_precond_build: out of host memory");
+    return FC_E_NOMEM;
+  }
+}
+
+static fc_status pcg_solve_body(fc_problem pb, fc_precond pc, const double* b_dev, double* x_dev,
+                                const fc_solve_opts* opts, fc_solve_info* info, void* stream) {
   if (!pb || !pc || pc->pb != pb || !b_dev || !x_dev || b_dev == x_dev) {
     set_error("fc_pcg_solve: invalid arguments");
     return FC_E_ARG;
@@ -699,6 +721,16 @@ fc_status fc_pcg_solve(fc_problem pb, fc_precond pc, const double* b_dev, double
     return FC_E_UNSUPPORTED;
   }
   return pcg_solve(*pc, b_dev, x_dev, o, info, (hipStream_t)stream);
+}
+
+fc_status fc_pcg_solve(fc_problem pb, fc_precond pc, const double* b_dev, double* x_dev,
+                       const fc_solve_opts* opts, fc_solve_info* info, void* stream) {
+  try {
+    return pcg_solve_body(pb, pc, b_dev, x_dev, opts, info, stream);
+  } catch (const std::bad_alloc&) {
+    set_error("fc_pcg_solve: out of host memory");
+    return FC_E_NOMEM;
+  }
 }
 
 void fc_problem_destroy(fc_problem pb) { free_problem(pb); }
