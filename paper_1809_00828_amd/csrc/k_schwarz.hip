@@ -25,6 +25,13 @@
 //     positive definite are skipped there and done from the FP64 copy.
 //   * BF16: the scaled Cholesky factor of the same matrix, two triangular
 //     passes through LDS (positive semi-definite however rounded).
+//   * Shared copies: on a Cartesian cell grid the blocks of uncut cells with
+//     the same kind of neighbourhood are equal matrices, and their stored
+//     inverses (FP64 and FP32 copies) come out bit for bit equal.  Set-up
+//     finds them (content hash, then a bitwise comparison) and gives every
+//     block the offset of the copy it reads; blocks reading one copy are
+//     taken four to a workgroup, each staged chunk loaded once for the four.
+//     Results are bitwise those of the per-block kernel.
 // Phase 2 (pull): every unknown sums the y_B entries of the blocks that
 // contain it, in a fixed order (no atomics, bitwise reproducible), and adds
 // its diagonal-scaling term.

@@ -11,9 +11,10 @@
 // once per product and streamed with non-temporal loads, which leaves the
 // cache to the gathered x entries (neighbouring rows of the lattice share
 // most of their columns).  When block rows repeat (every row whose cells are
-// uncut repeats one of a few stencils of the cell grid), the FP64 products
-// read one stored copy per distinct row through a per-row offset and the
-// caches serve the repeats.
+// uncut repeats one of a few stencils of the cell grid), the products read
+// one stored copy per distinct row through a per-row offset; rows with one
+// copy and one lattice box shape are taken four at a time, each value loaded
+// once for the four (k_spmv_bsr_grp), and the caches serve the repeats.
 //
 // Tiles of 256/G rows are dealt out so that the workgroups resident on one
 // XCD (hardware ids congruent mod 8) walk one contiguous range of rows and
