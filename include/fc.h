@@ -132,6 +132,15 @@ void fc_host_system_destroy(fc_host_system hs);
  * Errors: FC_E_ARG (NULL hs, distinct_rows or n_values), FC_E_NOMEM. */
 fc_status fc_host_system_share(fc_host_system hs, int64_t* distinct_rows, int64_t* n_values,
                                int64_t* ofs, double* vals);
+/* The groups of block rows that set-up hands to the grouped FP64 products
+ * when the columns follow the lattice (a problem from a description): up to
+ * four rows with bitwise-equal values and the same lattice box shape per
+ * group, groups[4*g + k] the k-th row of group g or -1 (padding), filled in
+ * row order.  *n_groups receives the number of groups (0 when no group
+ * would hold two rows); groups (may be NULL) receives 4 * *n_groups
+ * entries.  Host only.  Errors: FC_E_ARG (NULL hs or n_groups),
+ * FC_E_NOMEM. */
+fc_status fc_host_system_row_groups(fc_host_system hs, int64_t* n_groups, int32_t* groups);
 
 /* Wrap an assembled system given by the caller (host arrays, copied).
  * BSR with bsr_dim x bsr_dim blocks stored row-major per block:

@@ -39,6 +39,7 @@ EXPORTS = [
     "fc_coarse_prolong", "fc_coarse_apply", "fc_learned_stats", "fc_learned_snapshots",
     "fc_learned_validate", "fc_precond_lowprec_info", "fc_spmv_info",
     "fc_host_system_share", "fc_spmv_share_info", "fc_precond_share_info",
+    "fc_host_system_row_groups",
 ]
 
 
@@ -115,6 +116,7 @@ def load():
         "fc_spmv_share_info": [vp, P(i64), P(i64), P(i64)],
         "fc_precond_share_info": [vp, P(i64), P(i64), P(i64)],
         "fc_host_system_share": [vp, P(i64), P(i64), vp, vp],
+        "fc_host_system_row_groups": [vp, P(i64), vp],
         "fc_get_block_inverse": [vp, i64, vp],
         "fc_apply_M": [vp, dp, dp, vp],
         "fc_pcg_solve": [vp, vp, dp, dp, P(SolveOpts), P(SolveInfo), vp],
@@ -259,6 +261,18 @@ class HostSystem:
         _check(lib.fc_host_system_share(self._h, C.byref(nr), C.byref(nv), _np_ptr(ofs),
                                         _np_ptr(vals)))
         return {"distinct_rows": nr.value, "ofs": ofs, "vals": vals}
+
+    def row_groups(self):
+        """Groups of up to four rows that the grouped products take
+        together (fc_host_system_row_groups), shape (n_groups, 4), -1
+        padding."""
+        lib = load()
+        ng = C.c_int64()
+        _check(lib.fc_host_system_row_groups(self._h, C.byref(ng), None))
+        g = np.zeros(4 * ng.value, np.int32)
+        if ng.value:
+            _check(lib.fc_host_system_row_groups(self._h, C.byref(ng), _np_ptr(g)))
+        return g.reshape(-1, 4)
 
     def upload(self, stream=None):
         h = C.c_void_p()

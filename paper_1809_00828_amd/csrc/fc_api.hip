@@ -287,6 +287,27 @@ fc_status fc_host_system_share(fc_host_system hs, int64_t* distinct_rows, int64_
   return FC_OK;
 }
 
+fc_status fc_host_system_row_groups(fc_host_system hs, int64_t* n_groups, int32_t* groups) {
+  if (!hs || !n_groups) {
+    set_error("fc_host_system_row_groups: NULL argument");
+    return FC_E_ARG;
+  }
+  const HostSystem& S = hs->sys;
+  try {
+    SharedRows sh;
+    share_rows(S, &sh);
+    LatticeInfo lat{};
+    if (S.dim > 0) lat = LatticeInfo{S.dim, S.p * S.n + 1, S.p};
+    const std::vector<int32_t> g = group_rows_by_copy(sh.ofs, lat, nullptr);
+    *n_groups = (int64_t)g.size() / kShareGroup;
+    if (groups && !g.empty()) std::memcpy(groups, g.data(), g.size() * sizeof(int32_t));
+  } catch (const std::bad_alloc&) {
+    set_error("fc_host_system_row_groups: out of host memory");
+    return FC_E_NOMEM;
+  }
+  return FC_OK;
+}
+
 static void soa_to_rowmajor(const std::vector<int32_t>& rp, const double* soa, int bd,
                             int64_t n_rows, double* out) {
   const int bb = bd * bd;
