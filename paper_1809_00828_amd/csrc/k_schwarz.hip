@@ -547,6 +547,22 @@ static hipError_t share_copies(const void* Q, int64_t stride, int elem_bytes, in
     gl.insert(gl.end(), kv.second.begin(), kv.second.end());
     gl.insert(gl.end(), kShareGroup - kv.second.size(), -1);
   }
+  // groups in the order of their first blocks (the partial groups, among
+  // them every block with a copy of its own, would otherwise come in hash
+  // order and scatter the residual gathers)
+  {
+    const int64_t ng = (int64_t)gl.size() / kShareGroup;
+    std::vector<int64_t> order((size_t)ng);
+    for (int64_t k = 0; k < ng; ++k) order[k] = k;
+    std::sort(order.begin(), order.end(), [&](int64_t a, int64_t b) {
+      return gl[a * kShareGroup] < gl[b * kShareGroup];
+    });
+    std::vector<int32_t> sorted(gl.size());
+    for (int64_t k = 0; k < ng; ++k)
+      std::copy(gl.begin() + order[k] * kShareGroup, gl.begin() + (order[k] + 1) * kShareGroup,
+                sorted.begin() + k * kShareGroup);
+    gl.swap(sorted);
+  }
   int32_t* dg = nullptr;
   if ((e = hipMalloc(&dg, gl.size() * sizeof(int32_t))) != hipSuccess) return e;
   if ((e = hipMemcpyAsync(dg, gl.data(), gl.size() * sizeof(int32_t), hipMemcpyHostToDevice,
