@@ -1,5 +1,6 @@
-"""GPU parity for two degenerate settings of the preconditioner and of the
-mixed-precision solver.
+"""GPU parity for degenerate settings of the preconditioner and of the
+mixed-precision solver, and for the shared copies of repeated rows and
+local inverses.
 
   * eta_bar < 0 keeps no element block (every eta_T >= 0), so Algorithm 1
     reduces to diagonal scaling: z = r / diag(A) on every unknown with a
@@ -12,6 +13,10 @@ mixed-precision solver.
     row-mixed matrix holds no FP64 row at all.  The refinement must still
     reach the FP64 residual with no fallback to the FP64 matrix, and the
     solution must agree with the oracle's direct solve in the energy norm.
+  * Shared copies: the same problem and preconditioner with every row and
+    block read from its own copy and with bitwise-equal ones read from one
+    copy, four at a time, give the same products and solves (bit for bit
+    where the launch shapes agree) and match the oracle.
 """
 import numpy as np
 import pytest
