@@ -34,3 +34,20 @@ def test_poisson_workload_bytes():
     assert spmv == 513 ** 3 * 8 + (n + 1) * 4 + 2 * n * 8
     assert spmv == pytest.approx(1.123e9, rel=1e-3)
     assert schwarz == 64 ** 3 * 14 * 27 * 8 + 64 ** 3 * 27 * 4 + 2 * n * 8 + 64 ** 3 * 27 * 8
+
+
+def test_shared_copies_bytes():
+    # the same elasticity workload with the kept copies it has at set-up:
+    # 103,041,504 kept row values (one 8-byte offset per block row) and
+    # 8,817 kept inverses (one 8-byte offset per block)
+    n_nodes = 97 ** 3
+    info = {"n_dofs": 3 * n_nodes, "bsr_dim": 3, "nnzb": 111_284_641, "lattice_columns": True,
+            "shared_values": 103_041_504}
+    spmv, schwarz = bench.algorithmic_bytes(info, m=192, n_blocks=32_768, nn=64,
+                                            distinct_blocks=8_817)
+    assert spmv == (103_041_504 * 8 + n_nodes * 8 + (n_nodes + 1) * 4
+                    + 2 * 3 * n_nodes * 8)
+    assert spmv == pytest.approx(0.879e9, rel=1e-3)
+    assert schwarz == (8_817 * 97 * 192 * 8 + 32_768 * (64 * 4 + 8) + 2 * 3 * n_nodes * 8
+                       + 32_768 * 192 * 8)
+    assert schwarz == pytest.approx(1.416e9, rel=1e-3)
