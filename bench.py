@@ -7,11 +7,14 @@ One step = one pass of the whole hot path: build the preconditioner
 (extract the 32,768 element blocks, their FP64 local inverses, the
 diagonal fallback) and run PCG to ||b - A x|| / ||b|| <= 1e-8.  The
 problem (assembled matrix and load) is resident in HBM before the timed
-region starts.
+region starts.  Every block row and every local inverse is read from its
+own stored copy.  The timed steps run the production launch mode (each
+chunk of PCG steps replayed from a captured hipGraph).
 
-Prints one JSON line.  The kernel-level roofline is measured live: the
-solver brackets every SpMV and Schwarz block-product launch with HIP events
-on its own stream during the timed steps.
+Prints one JSON line.  The kernel-level roofline comes from one more solve
+after the timed steps, in the library's timing mode: the same kernels with
+the same launch shapes, launched directly with HIP events around every SpMV
+and every Schwarz block-product launch on the solver's own stream.
 """
 from __future__ import annotations
 
@@ -29,13 +32,9 @@ if ROOT not in sys.path:
 HBM_PEAK_GBS = 8000.0
 # HBM bytes per launch on the 32^3 elasticity workload from two rocprofv3
 # counter passes (FETCH_SIZE, WRITE_SIZE), scaled by what the same counters
-# read for a plain 4 GiB copy (profiles/pcg_fp64_elastic32_p3_hbm_counters.md, full
-# copies; profiles/pcg_fp64_elastic32_p3_shared_hbm_counters.md, shared copies one
-# at a time; profiles/pcg_fp64_elastic32_p3_grouped_hbm_counters.md, grouped);
+# read for a plain 4 GiB copy (profiles/pcg_fp64_elastic32_p3_hbm_counters.md);
 # to be re-measured whenever one of these kernels changes.
-TRAFFIC = {"spmv": 8.3640e9, "spmv_shared": 9.2376e8, "spmv_grouped": 1.1796e9,
-           "schwarz": 4.6881e9,
-           "schwarz_shared": 1.3893e9, "schwarz_grouped": 1.3664e9}
+TRAFFIC = {"spmv": 8.3640e9, "schwarz": 4.6881e9}
 METRIC = "DOF·iter/s and time-to-1e-8 residual: mixed/learned vs plain FP64 PCG"
 
 
@@ -50,85 +49,153 @@ def workload(small: bool, name: str = "elastic32"):
             "3D finite cell linear elasticity, 32^3 cells, p=3, 64 spherical voids, alpha=1e-8")
 
 
-def algorithmic_bytes(info, m, n_blocks, nn, distinct_blocks=0):
-    """Bytes each streaming kernel must move per launch (FP64 layout).
-    Shared rows and shared local inverses count once per distinct copy."""
+def algorithmic_bytes(info, m, n_blocks, nn):
+    """Bytes each streaming kernel must move per launch in the implemented
+    FP64 layout: the matrix once (values, plus 4-byte block columns unless
+    the columns follow from the lattice), row pointers, x and y once; the
+    stored half of every symmetric local inverse once ((m/2+1)*m wrapped
+    diagonals), the element node lists, the gathered r and q once and the
+    block outputs y_B written."""
     n = info["n_dofs"]
     bd = info["bsr_dim"]
     nnzb = info["nnzb"]
-    # values (and column indices unless the columns follow from the
-    # lattice), row pointers, x and q once
     col_bytes = 0 if info.get("lattice_columns") else 4
-    if info.get("shared_values"):
-        # bitwise-equal rows stored once: the kept values once, one 8-byte
-        # value offset per block row
-        spmv = (info["shared_values"] * 8 + nnzb * col_bytes + (n // bd) * 8
-                + (n // bd + 1) * 4 + 2 * n * 8)
-    else:
-        spmv = nnzb * (bd * bd * 8 + col_bytes) + (n // bd + 1) * 4 + 2 * n * 8
-    # stored half of each symmetric P_B once ((m/2+1)*m wrapped diagonals),
-    # element node lists, gathered r and q once, y_B written
-    stored = distinct_blocks if distinct_blocks else n_blocks
-    schwarz = stored * (m // 2 + 1) * m * 8 + n_blocks * nn * 4 + 2 * n * 8 + n_blocks * m * 8
-    if distinct_blocks:
-        schwarz += n_blocks * 8     # one 8-byte offset per block
+    spmv = nnzb * (bd * bd * 8 + col_bytes) + (n // bd + 1) * 4 + 2 * n * 8
+    schwarz = n_blocks * (m // 2 + 1) * m * 8 + n_blocks * nn * 4 + 2 * n * 8 + n_blocks * m * 8
     return spmv, schwarz
+
+
+def iteration_bytes(info, m, n_blocks, nn):
+    """Bytes of one whole PCG iteration: both streaming kernels, plus the
+    vector passes of the CG updates (p and q read for (p, A p); the pull
+    reads y_B, the inverse map, x, r, p, q and writes x, r, z; p = z + beta p
+    reads z, p and writes p)."""
+    spmv, schwarz = algorithmic_bytes(info, m, n_blocks, nn)
+    n = info["n_dofs"]
+    n_entries = n_blocks * nn
+    pull = n_blocks * m * 8 + n_entries * 4 + (n // info["bsr_dim"] + 1) * 4 + 7 * n * 8
+    return spmv + schwarz + 2 * n * 8 + pull + 3 * n * 8
 
 
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def cpu_baseline(seconds=10.0):
-    """The FP64 oracle's PCG on a bounded sample of the same workload family
-    (4^3 cells of the same generator, seed 0), timed on the host."""
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or platform.machine()
+
+
+def cpu_baseline(gpu_iters=None, full_nnz=None, full_n=None):
+    """The FP64 oracle (assembly, Algorithm 1, PCG) timed on the host on a
+    bounded sample of the benchmark's generator: the 4^3-cell instance of
+    the same porous elasticity family (p = 3, seed 0).  Assembly runs once;
+    the preconditioner build (LAPACK eigen-decompositions, threaded by the
+    BLAS) and the PCG solve (scipy's CSR products, single-threaded) run with
+    every BLAS thread and again with one.  The 32^3-cell time per iteration
+    is extrapolated from the sample's time per stored entry of A and S
+    (the sample is cache-resident, so this is a lower bound on the oracle's
+    time at full size)."""
     import numpy as np
     import fcgen
     from oracle import assemble, pcg, schwarz
+    try:
+        from threadpoolctl import threadpool_info, threadpool_limits
+    except Exception:  # noqa: BLE001
+        threadpool_info = threadpool_limits = None
+    blas = (max([p.get("num_threads", 1) for p in threadpool_info()] or [1])
+            if threadpool_info else None)
     d = fcgen.porous_elasticity_3d(seed=0, n=4)
     log("cpu baseline: oracle assembly of the 4^3-cell sample")
-    s = assemble.assemble(d)
-    blocks = schwarz.select_blocks(s["elem_dofs"], s["eta"], 1.0)
-    S, _ = schwarz.compute_preconditioner(s["A"], blocks)
-    n = s["A"].shape[0]
     t0 = time.perf_counter()
-    total = 0
-    runs = 0
-    while True:
-        _, info = pcg.pcg(s["A"], s["b"], S, tol=1e-8, stop="residual")
-        total += info["iters"]
-        runs += 1
-        log(f"cpu baseline: oracle solve {runs} done ({info['iters']} iterations)")
-        if time.perf_counter() - t0 >= seconds:
-            break
-    dt = time.perf_counter() - t0
-    try:
-        from threadpoolctl import threadpool_info
-        blas = max([p.get("num_threads", 1) for p in threadpool_info()] or [1])
-    except Exception:  # noqa: BLE001
-        blas = None
-    return {
-        "value": n * total / dt, "unit": "DOF·iter/s", "cores": 1, "kind": "oracle",
-        "sample": (f"oracle PCG (scipy CSR products with A and with the assembled S) to "
-                   f"1e-8 residual on the 4^3-cell instance of the same generator "
-                   f"({n} DOFs, {info['iters']} iterations), {runs} solves in {dt:.1f} s; "
-                   f"single-threaded sparse products (BLAS threads available: {blas}); "
-                   f"the small instance is cache-resident, so this overstates the "
-                   f"oracle's rate at full size"),
-        "host_cpus": os.cpu_count(), "cpu_model": platform.processor() or platform.machine(),
+    s = assemble.assemble(d)
+    t_asm = time.perf_counter() - t0
+    A, b = s["A"], s["b"]
+    n = A.shape[0]
+    runs = {}
+    for label, limit in (("all_threads", None), ("one_thread", 1)):
+        ctx = threadpool_limits(limits=limit) if (threadpool_limits and limit) else None
+        if ctx is not None:
+            ctx.__enter__()
+        try:
+            t0 = time.perf_counter()
+            blocks = schwarz.select_blocks(s["elem_dofs"], s["eta"], 1.0)
+            S, _ = schwarz.compute_preconditioner(A, blocks)
+            t_pre = time.perf_counter() - t0
+            t0 = time.perf_counter()
+            _, info = pcg.pcg(A, b, S, tol=1e-8, stop="residual")
+            t_sol = time.perf_counter() - t0
+        finally:
+            if ctx is not None:
+                ctx.__exit__(None, None, None)
+        runs[label] = {"blas_threads": limit or blas, "precond_s": t_pre, "solve_s": t_sol,
+                       "iters": info["iters"], "ms_per_iter": t_sol / max(1, info["iters"]) * 1e3,
+                       "dof_iter_per_s": n * info["iters"] / t_sol}
+        log(f"cpu baseline ({label}): precond {t_pre:.2f} s, solve {t_sol:.2f} s, "
+            f"{info['iters']} iterations")
+    entries = A.nnz + S.nnz
+    out = {
+        "value": runs["all_threads"]["dof_iter_per_s"], "unit": "DOF·iter/s",
+        "cores": blas or 1, "kind": "oracle",
+        "sample": (f"oracle (python/scipy, FP64) on the 4^3-cell, p=3 instance of the "
+                   f"benchmark's generator ({n} DOFs): assembly once, then Algorithm 1 and "
+                   f"PCG to ||r||/||b|| <= 1e-8 with every BLAS thread and with one; the CSR "
+                   f"products of the solve are single-threaded in scipy, the eigen-"
+                   f"decompositions of the build use the BLAS threads"),
+        "cpu_model": _cpu_model(), "host_cpus": os.cpu_count(), "blas_threads": blas,
+        "assembly_s": t_asm, "runs": runs,
+        "sample_entries_A_plus_S": int(entries),
     }
+    if gpu_iters and full_nnz and full_n:
+        per_entry = runs["all_threads"]["ms_per_iter"] * 1e-3 / entries
+        per_iter = per_entry * 2 * full_nnz
+        out["extrapolated_full"] = {
+            "label": "extrapolated",
+            "ms_per_iter": per_iter * 1e3,
+            "time_to_tol_s": per_iter * gpu_iters,
+            "dof_iter_per_s": full_n / per_iter,
+            "how": (f"sample time per stored entry of A and S ({per_entry * 1e9:.2f} ns) x "
+                    f"2 x {full_nnz} entries (S has the pattern of A for element blocks) x "
+                    f"{gpu_iters} iterations (the GPU's count at full size)"),
+        }
+    return out
+
+
+def _energy(fc, pb, v, work):
+    """sqrt(v . A v) with the library's FP64 product."""
+    pb.apply_A(v, work)
+    return float(max((v * work).sum().item(), 0.0)) ** 0.5
 
 
 def forms(fc, pb, b, tol, t_f64, it_f64):
     """Time-to-tolerance of the mixed-precision forms against plain FP64 on
     the same problem: build (FP64 inverses plus the low-precision copy the
-    form uses) + solve to ||b - A x|| / ||b|| <= tol."""
+    form uses) + solve to ||b - A x|| / ||b|| <= tol.  Each result's error
+    is stated in the energy norm (Eq. 13) against an FP64 reference solved
+    to ||b - A x|| / ||b|| <= 1e-12 (at this size the oracle's own solve
+    would take hours; its parity with the oracle is checked at smaller
+    sizes), for the plain FP64 result too."""
     import torch
     x64 = torch.zeros_like(b)
-    res = {"fp64": {"time_to_tol_ms": t_f64, "iters": it_f64}}
+    xref = torch.zeros_like(b)
+    work = torch.empty_like(b)
     pc = fc.Precond(pb)
     fc.pcg_solve(pb, pc, b, x64, tol=tol, stop="residual")
+    ref = fc.pcg_solve(pb, pc, b, xref, tol=1e-12, stop="residual")
     del pc
+    eref = _energy(fc, pb, xref, work)
+    e64 = _energy(fc, pb, x64 - xref, work) / eref
+    res = {"fp64": {"time_to_tol_ms": t_f64, "iters": it_f64, "energy_error_vs_ref": e64},
+           "reference": {"tol": 1e-12, "iters": ref["iters"], "status": ref["status"],
+                         "rel_res_true": ref["rel_res_true"]}}
+    log(f"forms: FP64 reference to 1e-12 in {ref['iters']} iterations; FP64 energy error "
+        f"{e64:.2e}")
     for store, modes in ((fc.STORE_F64 | fc.STORE_F32, ("s_f32", "ir_f32")),
                          (fc.STORE_F64 | fc.STORE_BF16, ("s_bf16", "ir_bf16"))):
         for mode in modes:
@@ -139,26 +206,29 @@ def forms(fc, pb, b, tol, t_f64, it_f64):
             build = (time.perf_counter() - tb) * 1e3
             x = torch.zeros_like(b)
             # inner tolerance of the refinement: 1e-4 with the FP32 inverses
-            # (two outer steps to 1e-8; 1e-2 takes four and 6 % more inner
-            # iterations), 1e-2 with the weaker BF16 ones
+            # (two outer steps to 1e-8), 1e-2 with the weaker BF16 ones
             inner = 1e-4 if mode == "ir_f32" else 1e-2
             r = fc.pcg_solve(pb, pc, b, x, tol=tol, stop="residual", mode=mode, inner_tol=inner,
                              maxit=60000)
             diff = float((x - x64).norm() / x64.norm())
+            err = _energy(fc, pb, x - xref, work) / eref
             res[mode] = {"time_to_tol_ms": build + r["ms_solve"], "solve_ms": r["ms_solve"],
                          "build_ms": build, "iters": r["iters"], "outer": r["outer_iters"],
                          "inner_tol": inner if mode.startswith("ir") else None,
                          "fallbacks": r["fallbacks"], "status": r["status"],
                          "rel_res_true": r["rel_res_true"], "rel_diff_vs_fp64": diff,
+                         "energy_error_vs_ref": err,
+                         "iteration_overhead": r["iters"] / max(1, it_f64),
                          "speedup_vs_fp64": t_f64 / (build + r["ms_solve"])}
             if mode.endswith("f32"):
                 info = pc.info()
                 res[mode]["f32_blocks"] = info["n_f32_blocks"]
                 res[mode]["f32_blocks_from_f64"] = info["n_f32_from_f64"]
             log(f"form {mode}: build {build:.0f} ms, {r['iters']} iterations, "
-                f"{r['ms_solve']:.0f} ms, {r['status']}")
+                f"{r['ms_solve']:.0f} ms, {r['status']}, energy error {err:.2e}")
             del pc
-    best = max((k for k in res if k != "fp64"), key=lambda k: res[k]["speedup_vs_fp64"])
+    best = max((k for k in res if k not in ("fp64", "reference")),
+               key=lambda k: res[k]["speedup_vs_fp64"])
     res["best"] = {"form": best, "speedup_vs_fp64": res[best]["speedup_vs_fp64"],
                    "time_to_tol_ms": res[best]["time_to_tol_ms"]}
     return res
@@ -305,7 +375,35 @@ def eta_sweep_bench(fc, args):
             "n_dofs": pb.n, "maxit": args.maxit, "sweep": rows}
 
 
-def compare_bench(fc, args):
+def eta_pair(fc, pb, b, args, t_f64, it_f64):
+    """The paper's study of preconditioning only cut cells, at one point:
+    blocks only for elements with eta_T <= 0.8 and diagonal scaling for
+    every unknown they leave uncovered, against blocks for every element
+    (the timed steps), both to ||b - A x|| / ||b|| <= tol; the time counts
+    the preconditioner build."""
+    import torch
+    x = torch.zeros_like(b)
+    rec = {}
+    for eb in (0.8,):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        pc = fc.Precond(pb, eta_bar=eb)
+        torch.cuda.synchronize()
+        build = (time.perf_counter() - t0) * 1e3
+        pi = pc.info()
+        r = _solve_record(fc, pb, pc, b, x, tol=args.tol, maxit=args.maxit, stop="residual")
+        rec = {"eta_bar": eb, "blocks": pi["n_blocks"], "diag_unknowns": pi["n_fallback"],
+               "iters": r["iters"], "status": r["status"], "build_ms": build,
+               "solve_ms": r["solve_ms"], "time_to_tol_ms": build + r["solve_ms"],
+               "ms_per_iter": r["ms_per_iter"]}
+        del pc
+        log(f"eta_bar {eb}: {pi['n_blocks']} blocks, {r['iters']} iterations, "
+            f"{build + r['solve_ms']:.0f} ms to tol")
+    return {"all_blocks": {"eta_bar": 1.0, "iters": it_f64, "time_to_tol_ms": t_f64},
+            "threshold": rec, "speedup": t_f64 / rec["time_to_tol_ms"]}
+
+
+def compare_bench(fc, args, alphas=None, maxit=None):
     """Preconditioners compared on the elasticity geometry at fictitious
     stiffnesses down to zero (the paper's CT examples use about 1e-12),
     optionally after removing the functions of cells without material:
@@ -316,7 +414,8 @@ def compare_bench(fc, args):
     import fcgen
     rows = []
     n = 0
-    for alpha in args.compare_alpha:
+    maxit = maxit or args.maxit
+    for alpha in (alphas if alphas is not None else args.compare_alpha):
         desc = fcgen.porous_elasticity_3d(seed=0, alpha=alpha,
                                           discard_fictitious=args.discard_fictitious)
         pb = fc.HostSystem(desc).upload()
@@ -327,7 +426,7 @@ def compare_bench(fc, args):
         for name, kw in (("DA", {"eta_bar": -1.0}), ("S*", {"stabilize": False}), ("S", {})):
             pc = fc.Precond(pb, **kw)
             pi = pc.info()
-            rec = _solve_record(fc, pb, pc, b, x, tol=1e-10, maxit=args.maxit, stop="precond")
+            rec = _solve_record(fc, pb, pc, b, x, tol=1e-10, maxit=maxit, stop="precond")
             rec.update({"alpha": alpha, "preconditioner": name,
                         "discard_fictitious": bool(args.discard_fictitious),
                         "dropped_eigenvalues": pi["n_dropped"]})
@@ -340,16 +439,17 @@ def compare_bench(fc, args):
     return {"metric": "PCG with DA, S* and S to ||z||/||z_0|| <= 1e-10",
             "workload": "3D finite cell elasticity, 32^3 cells, p=3, 64 spherical voids "
                         "(2,738,019 unknowns), fictitious stiffness alpha as listed",
-            "n_dofs": n, "maxit": args.maxit, "runs": rows}
+            "n_dofs": n, "maxit": maxit, "runs": rows}
 
 
-def batch_bench(fc, args):
+def batch_bench(fc, args, count=None, line=True):
     """Uneven batch of 2-D/3-D Poisson problems (grids 8^2..128^2 and
     8^3..24^3, p = 1..4, elliptical inclusions or voids, alpha = 1e-10,
     50k-200k DOFs each) solved together to ||r||/||b|| <= 1e-8."""
     import torch
     import fcgen
-    descs = fcgen.batch_poisson(seed=0, count=args.batch)
+    count = count or args.batch
+    descs = fcgen.batch_poisson(seed=0, count=count)
     pbs, pcs = [], []
     t0 = time.perf_counter()
     for k, d in enumerate(descs):
@@ -375,20 +475,21 @@ def batch_bench(fc, args):
         xs.append(torch.zeros_like(b))
     # the library reports converged members every 64 chunks of 32 steps
     os.environ.setdefault("FC_BATCH_PROGRESS", "64")
-    for _ in range(args.warmup):
+    steps, warmup = (args.steps, args.warmup) if line else (1, 1)
+    for _ in range(warmup):
         batch.solve(bs, xs, tol=args.tol, stop="residual", check_every=32)
         log("batch: warmup solve done")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for k in range(args.steps):
+    for k in range(steps):
         res = batch.solve(bs, xs, tol=args.tol, stop="residual", check_every=32)
-        log(f"batch: timed solve {k + 1}/{args.steps} done")
+        log(f"batch: timed solve {k + 1}/{steps} done")
     torch.cuda.synchronize()
-    wall = (time.perf_counter() - t0) / args.steps
+    wall = (time.perf_counter() - t0) / steps
     dof_iters = sum(p.n * r["iters"] for p, r in zip(pbs, res))
     return {
         "metric": METRIC + " (batched form)", "value": dof_iters / wall, "unit": "DOF·iter/s",
-        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": wall * 1e3,
+        "n_gpus": 1, "steps": steps, "warmup": warmup, "ms_per_step": wall * 1e3,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": f"{len(descs)} uneven 2D/3D finite cell Poisson problems, "
@@ -416,6 +517,8 @@ def main():
                     help="skip the mixed-precision forms comparison")
     ap.add_argument("--no-learned", action="store_true",
                     help="skip the learned coarse-correction comparison")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the block-threshold, DA/S*/S and 32-member batch extras")
     ap.add_argument("--learned-train", type=int, default=8, help="training problems (48^3)")
     ap.add_argument("--learned-pairs", type=int, default=2000, help="training pairs in total")
     ap.add_argument("--learned-epochs", type=int, default=20)
@@ -482,17 +585,17 @@ def main():
     x = torch.zeros_like(b)
     torch.cuda.synchronize()
 
-    def step():
+    def step(timing=0):
         tb = time.perf_counter()
         pc = fc.Precond(pb)
         torch.cuda.synchronize()
         build = time.perf_counter() - tb
         r = fc.pcg_solve(pb, pc, b, x, tol=args.tol, stop="residual", check_every=16,
-                         timing=True)
+                         timing=timing)
         pinfo = pc.info()
         del pc
-        log(f"step: build {build * 1e3:.1f} ms, solve {r['ms_solve']:.1f} ms, "
-            f"{r['iters']} iterations, {r['status']}")
+        log(f"step{' (kernel timing)' if timing else ''}: build {build * 1e3:.1f} ms, "
+            f"solve {r['ms_solve']:.1f} ms, {r['iters']} iterations, {r['status']}")
         return build, r, pinfo
 
     for _ in range(args.warmup):
@@ -502,6 +605,9 @@ def main():
     res = [step() for _ in range(args.steps)]
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    # per-kernel durations: one more solve with events around every SpMV
+    # and block-product launch (direct launches, same kernels and shapes)
+    kt = step(timing=1)[1]
 
     iters = [r[1]["iters"] for r in res]
     status = [r[1]["status"] for r in res]
@@ -510,44 +616,33 @@ def main():
     pinfo = res[-1][2]
     m = info["m"]
     nn = m // info["bsr_dim"]
-    dblk = pinfo.get("shared_distinct_blocks", 0)
-    spmv_b, schw_b = algorithmic_bytes(info, m, pinfo["n_blocks"], nn, dblk)
-    ms_spmv = sum(r[1]["ms_spmv"] for r in res) / max(1, sum(r[1]["n_timed"] for r in res))
-    ms_schw = sum(r[1]["ms_schwarz"] for r in res) / max(1, sum(r[1]["n_timed"] for r in res))
+    spmv_b, schw_b = algorithmic_bytes(info, m, pinfo["n_blocks"], nn)
+    it_b = iteration_bytes(info, m, pinfo["n_blocks"], nn)
+    ms_spmv = kt["ms_spmv"] / max(1, kt["n_timed"])
+    ms_schw = kt["ms_schwarz"] / max(1, kt["n_timed"])
     gbs_schw = schw_b / (ms_schw * 1e-3) / 1e9
     gbs_spmv = spmv_b / (ms_spmv * 1e-3) / 1e9
     total_dof_iters = n * sum(iters)
     # the counter traffic was taken on the elasticity workload
     on_bench_workload = not args.small and args.workload == "elastic32"
-    shared = bool(info.get("shared_values"))
-    grouped = bool(info.get("row_groups"))
-    spmv_name = (f"k_spmv_bsr{'_grp' if grouped else ''}<{info['bsr_dim']},{info['spmv_group']},double,"
-                 f"{'lattice' if info.get('lattice_columns') else 'columns'}"
-                 f"{',shared' if shared else ''}> (SpMV q = A p)")
+    spmv_name = (f"k_spmv_bsr<{info['bsr_dim']},{info['spmv_group']},double,"
+                 f"{'lattice' if info.get('lattice_columns') else 'columns'}> (SpMV q = A p)")
     k_spmv = {"bound": "hbm", "kernel": spmv_name,
               "achieved": gbs_spmv, "peak": HBM_PEAK_GBS, "unit": "GB/s",
               "frac": gbs_spmv / HBM_PEAK_GBS,
-              "traffic": (TRAFFIC["spmv_grouped" if grouped else
-                                  "spmv_shared" if shared else "spmv"]
-                          if on_bench_workload else None),
-              "bytes_per_launch": spmv_b, "avg_ms": ms_spmv,
-              # values the lanes load per launch when every row is counted
-              # (repeats of shared rows come from the caches)
-              "loaded_bytes_per_launch": algorithmic_bytes(
-                  {**info, "shared_values": 0}, m, pinfo["n_blocks"], nn)[0]}
-    bgrp = bool(pinfo.get("block_groups"))
-    schw_name = (("k_schwarz_sym_grp<double,4>" if bgrp else
-                  f"k_schwarz_sym_staged<double{',shared' if dblk else ''}>") if m > 64
-                 else "k_schwarz_small<double,sym>")
+              "traffic": TRAFFIC["spmv"] if on_bench_workload else None,
+              "bytes_per_launch": spmv_b, "avg_ms": ms_spmv, "launches_timed": kt["n_timed"]}
+    if info.get("lattice_columns"):
+        # the same product with the 4-byte block columns read from memory
+        k_spmv["bytes_per_launch_with_columns"] = spmv_b + info["nnzb"] * 4
+    schw_name = "k_schwarz_sym_staged<double>" if m > 64 else "k_schwarz_small<double,sym>"
     k_schw = {"bound": "hbm", "kernel": schw_name + " (block products)",
               "achieved": gbs_schw, "peak": HBM_PEAK_GBS, "unit": "GB/s",
               "frac": gbs_schw / HBM_PEAK_GBS,
-              "traffic": (TRAFFIC["schwarz_grouped" if bgrp else
-                                  "schwarz_shared" if dblk else "schwarz"]
-                          if on_bench_workload else None),
-              "bytes_per_launch": schw_b, "avg_ms": ms_schw,
-              "loaded_bytes_per_launch": algorithmic_bytes(info, m, pinfo["n_blocks"], nn)[1]}
+              "traffic": TRAFFIC["schwarz"] if on_bench_workload else None,
+              "bytes_per_launch": schw_b, "avg_ms": ms_schw, "launches_timed": kt["n_timed"]}
     dominant, other = (k_spmv, k_schw) if ms_spmv >= ms_schw else (k_schw, k_spmv)
+    ms_iter = sum(solves) / max(1, sum(iters))
     out = {
         "metric": METRIC,
         "value": total_dof_iters / wall,
@@ -559,27 +654,36 @@ def main():
         "config": {"workload": wl, "n_dofs": n, "nnz_blocks": info["nnzb"],
                    "blocks": pinfo["n_blocks"], "block_size": m, "tol": args.tol,
                    "stop": "relative residual ||b-Ax||/||b||", "form": "fp64",
-                   "shared_rows": info.get("shared_rows", 0),
-                   "shared_values": info.get("shared_values", 0),
-                   "row_groups": info.get("row_groups", 0),
-                   "shared_distinct_blocks": dblk,
-                   "block_groups": pinfo.get("block_groups", 0)},
+                   "launch": "hipGraph-captured chunks of 16 PCG steps",
+                   "spmv_lanes_per_row": info["spmv_group"]},
         "roofline": dominant,
         "roofline_other": other,
+        "iteration_roofline": {
+            "bytes_per_iter": it_b, "ms_per_iter": ms_iter,
+            "achieved": it_b / (ms_iter * 1e-3) / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": it_b / (ms_iter * 1e-3) / 1e9 / HBM_PEAK_GBS},
         "iters": iters, "status": status,
         "time_to_tol_ms": [bd + sv for bd, sv in zip(builds, solves)],
         "build_ms": builds, "solve_ms": solves,
-        "solve_dof_iter_per_s": n * iters[-1] / (solves[-1] * 1e-3),
-        "ms_per_iter": solves[-1] / max(1, iters[-1]),
+        "solve_dof_iter_per_s": n * sum(iters) / (sum(solves) * 1e-3),
+        "ms_per_iter": ms_iter,
+        "kernel_timing_solve": {"iters": kt["iters"], "ms_solve": kt["ms_solve"],
+                                "ms_per_iter": kt["ms_solve"] / max(1, kt["iters"])},
         "rel_res_true": res[-1][1]["rel_res_true"],
         "precond": pinfo, "host_assembly_s": t_asm,
     }
+    on_full = not args.small and args.workload == "elastic32"
     if not args.no_forms:
         out["forms"] = forms(fc, pb, b, args.tol, out["time_to_tol_ms"][-1], iters[-1])
+    if not args.no_extras and on_full:
+        out["eta_bar"] = eta_pair(fc, pb, b, args, out["time_to_tol_ms"][-1], iters[-1])
+        del pb
+        out["compare"] = compare_bench(fc, args, alphas=[0.0], maxit=1500)
+        out["batch"] = batch_bench(fc, args, count=32, line=False)
     if not args.no_learned and not args.small:
         out["learned"] = learned_bench(fc, args)
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline()
+        out["cpu_baseline"] = cpu_baseline(iters[-1], info["nnzb"] * info["bsr_dim"] ** 2, n)
     print(json.dumps(out), flush=True)
 
 

@@ -119,29 +119,6 @@ fc_status fc_host_system_export(fc_host_system hs, int32_t* rowptr, int32_t* col
                                 double* eta);
 fc_status fc_setup_from_host(fc_host_system hs, void* stream, fc_problem* out);
 void fc_host_system_destroy(fc_host_system hs);
-/* Shared rows of the assembled matrix (Sec. 3.1, Eq. 2: on the Cartesian
- * cell grid every block row whose supporting cells are uncut repeats one of
- * a few stencils).  Block rows whose stored values are bitwise equal (same
- * length, same values in the same order) keep one copy.  *distinct_rows and
- * *n_values receive the number of kept rows and of their values; when ofs
- * and vals are not NULL, ofs[n/bsr_dim] receives each block row's offset
- * into vals and vals[*n_values] the kept rows, each row entry-major
- * (value e of the row's k-th block at ofs[row] + e*L + k, L the row's block
- * count).  The first row seen with given values is the one kept.  Host
- * only; the caller sizes ofs and vals from a first call with both NULL.
- * Errors: FC_E_ARG (NULL hs, distinct_rows or n_values), FC_E_NOMEM. */
-fc_status fc_host_system_share(fc_host_system hs, int64_t* distinct_rows, int64_t* n_values,
-                               int64_t* ofs, double* vals);
-/* The groups of block rows that set-up hands to the grouped FP64 products
- * when the columns follow the lattice (a problem from a description): up to
- * four rows with bitwise-equal values and the same lattice box shape per
- * group, groups[4*g + k] the k-th row of group g or -1 (padding), filled in
- * row order.  *n_groups receives the number of groups (0 when no group
- * would hold two rows); groups (may be NULL) receives 4 * *n_groups
- * entries.  Host only.  Errors: FC_E_ARG (NULL hs or n_groups),
- * FC_E_NOMEM. */
-fc_status fc_host_system_row_groups(fc_host_system hs, int64_t* n_groups, int32_t* groups);
-
 /* Wrap an assembled system given by the caller (host arrays, copied).
  * BSR with bsr_dim x bsr_dim blocks stored row-major per block:
  * rowptr[n/bsr_dim+1], col[nnzb] (sorted within each block row),
@@ -212,24 +189,13 @@ fc_status fc_precond_info(fc_precond pc, int64_t* n_blocks,
                           int64_t* n_fallback, int64_t* n_eig_blocks,
                           int64_t* n_dropped);
 /* Launch shape the SpMV chose for this problem at set-up: lanes per block
- * row (timed on the matrix itself), and whether the block columns are
- * computed from the lattice (1: the matrix came from a problem description
- * and its columns were verified to be each row's lattice box, so the
- * column array is not read) or read (0). */
+ * row (fixed from the mean row length: the fewest of 8, 16, 32, 64 lanes
+ * whose first pass covers the mean row, so the result of every product is
+ * the same in every process), and whether the block columns are computed
+ * from the lattice (1: the matrix came from a problem description and its
+ * columns were verified to be each row's lattice box, so the column array
+ * is not read) or read (0). */
 fc_status fc_spmv_info(fc_problem pb, int32_t* group, int32_t* lattice);
-/* Shared rows used by this problem's FP64 products (the layout of
- * fc_host_system_share, uploaded at set-up): kept rows and their values,
- * both 0 when the products read the full matrix.  The environment variable
- * FC_SPMV_SHARE, read at every set-up, selects 0: never share, 1: share
- * whenever a row repeats, unset or other: share when the kept rows hold at
- * most three quarters of the values.  Products are bitwise the same either
- * way; sharing lets repeated rows be read from the caches instead of HBM.
- * *row_groups (may be NULL) receives the number of groups of up to four
- * rows with one shared copy (and one lattice box shape) that the full FP64
- * products process together, loading each value once per group (0: rows
- * one at a time; FC_SPMV_GROUPED=0 at set-up switches grouping off). */
-fc_status fc_spmv_share_info(fc_problem pb, int64_t* distinct_rows, int64_t* distinct_values,
-                             int64_t* row_groups);
 /* FP32 copy (FC_STORE_F32): the diagonally scaled inverse D^1/2 P_B D^1/2
  * (D = diag(A) on the block) rounded to FP32, kept for the blocks where a
  * Cholesky factorisation of the rounded matrix shows it positive definite
@@ -237,25 +203,6 @@ fc_status fc_spmv_share_info(fc_problem pb, int64_t* distinct_rows, int64_t* dis
  * are applied from the FP64 copy.  Counts of both kinds. */
 fc_status fc_precond_lowprec_info(fc_precond pc, int64_t* n_f32_blocks,
                                   int64_t* n_f32_from_f64);
-/* Shared local inverses (Sec. 3.2, Algorithm 1: every element block gets
- * its own P_B, but on the Cartesian cell grid the blocks of uncut cells
- * with the same kind of neighbourhood are equal matrices and give equal
- * inverses).  Blocks whose stored FP64 inverses are bitwise equal are read
- * from one copy by the block products when m > 64; every block keeps
- * its own copy for all other uses; the FP32 copy (FC_STORE_F32) is shared
- * the same way.  *distinct_blocks and *distinct_blocks32 (either may be
- * NULL) receive the number of FP64 and FP32 copies read (0 when no block is
- * shared).  *block_groups (may be NULL) receives the number of groups of
- * up to four blocks with one FP64 copy that the FP64 block products process
- * together, loading each staged chunk once per group (0: blocks one at a
- * time; FC_SCHWARZ_GROUPED=0 at the build switches grouping off).  The
- * environment variable
- * FC_SCHWARZ_SHARE, read at every build, selects 0: never share, 1: share
- * whenever a block repeats, unset or other: share when at least a quarter
- * of the blocks repeat.  Products are bitwise the same either way. */
-fc_status fc_precond_share_info(fc_precond pc, int64_t* distinct_blocks,
-                                int64_t* distinct_blocks32, int64_t* block_groups);
-
 /* Copy the FP64 local inverse of block k (m*m values, row-major) to host. */
 fc_status fc_get_block_inverse(fc_precond pc, int64_t k, double* out_host);
 

@@ -38,8 +38,6 @@ EXPORTS = [
     "fc_learned_attach", "fc_coarse_grid", "fc_coarse_channels", "fc_coarse_restrict",
     "fc_coarse_prolong", "fc_coarse_apply", "fc_learned_stats", "fc_learned_snapshots",
     "fc_learned_validate", "fc_precond_lowprec_info", "fc_spmv_info",
-    "fc_host_system_share", "fc_spmv_share_info", "fc_precond_share_info",
-    "fc_host_system_row_groups",
 ]
 
 
@@ -113,10 +111,6 @@ def load():
         "fc_precond_info": [vp, P(i64), P(i64), P(i64), P(i64)],
         "fc_precond_lowprec_info": [vp, P(i64), P(i64)],
         "fc_spmv_info": [vp, P(i32), P(i32)],
-        "fc_spmv_share_info": [vp, P(i64), P(i64), P(i64)],
-        "fc_precond_share_info": [vp, P(i64), P(i64), P(i64)],
-        "fc_host_system_share": [vp, P(i64), P(i64), vp, vp],
-        "fc_host_system_row_groups": [vp, P(i64), vp],
         "fc_get_block_inverse": [vp, i64, vp],
         "fc_apply_M": [vp, dp, dp, vp],
         "fc_pcg_solve": [vp, vp, dp, dp, P(SolveOpts), P(SolveInfo), vp],
@@ -249,31 +243,6 @@ class HostSystem:
         return {"rowptr": rp, "col": col, "val": val.reshape(-1, bd, bd), "rhs": rhs,
                 "elem_dofs": ed.reshape(inf["n_el"], inf["m"]), "eta": eta, **inf}
 
-    def share(self):
-        """Bitwise-equal block rows kept once (fc_host_system_share): the
-        per-row offsets and the kept rows, entry-major per row."""
-        lib = load()
-        nr, nv = C.c_int64(), C.c_int64()
-        _check(lib.fc_host_system_share(self._h, C.byref(nr), C.byref(nv), None, None))
-        bd = self.info()["bsr_dim"]
-        ofs = np.zeros(self.info()["n_dofs"] // bd, np.int64)
-        vals = np.zeros(nv.value, np.float64)
-        _check(lib.fc_host_system_share(self._h, C.byref(nr), C.byref(nv), _np_ptr(ofs),
-                                        _np_ptr(vals)))
-        return {"distinct_rows": nr.value, "ofs": ofs, "vals": vals}
-
-    def row_groups(self):
-        """Groups of up to four rows that the grouped products take
-        together (fc_host_system_row_groups), shape (n_groups, 4), -1
-        padding."""
-        lib = load()
-        ng = C.c_int64()
-        _check(lib.fc_host_system_row_groups(self._h, C.byref(ng), None))
-        g = np.zeros(4 * ng.value, np.int32)
-        if ng.value:
-            _check(lib.fc_host_system_row_groups(self._h, C.byref(ng), _np_ptr(g)))
-        return g.reshape(-1, 4)
-
     def upload(self, stream=None):
         h = C.c_void_p()
         _check(load().fc_setup_from_host(self._h, C.c_void_p(_stream(stream)), C.byref(h)))
@@ -320,12 +289,9 @@ class Problem:
                                           C.byref(m), C.byref(bd)))
             g, lat = C.c_int32(), C.c_int32()
             _check(load().fc_spmv_info(self._h, C.byref(g), C.byref(lat)))
-            sr, sv, sg = C.c_int64(), C.c_int64(), C.c_int64()
-            _check(load().fc_spmv_share_info(self._h, C.byref(sr), C.byref(sv), C.byref(sg)))
             self._info = {"n_dofs": n.value, "nnzb": nnzb.value, "n_el": nel.value,
                           "m": m.value, "bsr_dim": bd.value, "spmv_group": g.value,
-                          "lattice_columns": bool(lat.value), "shared_rows": sr.value,
-                          "shared_values": sv.value, "row_groups": sg.value}
+                          "lattice_columns": bool(lat.value)}
         return self._info
 
     @property
@@ -379,12 +345,8 @@ class Precond:
         _check(load().fc_precond_info(self._h, C.byref(a), C.byref(b), C.byref(c), C.byref(d)))
         e, f = C.c_int64(), C.c_int64()
         _check(load().fc_precond_lowprec_info(self._h, C.byref(e), C.byref(f)))
-        g, g32, gg = C.c_int64(), C.c_int64(), C.c_int64()
-        _check(load().fc_precond_share_info(self._h, C.byref(g), C.byref(g32), C.byref(gg)))
         return {"n_blocks": a.value, "n_fallback": b.value, "n_eig_blocks": c.value,
-                "n_dropped": d.value, "n_f32_blocks": e.value, "n_f32_from_f64": f.value,
-                "shared_distinct_blocks": g.value, "shared_distinct_blocks32": g32.value,
-                "block_groups": gg.value}
+                "n_dropped": d.value, "n_f32_blocks": e.value, "n_f32_from_f64": f.value}
 
     def block_inverse(self, k):
         out = np.zeros((self.m, self.m), np.float64)

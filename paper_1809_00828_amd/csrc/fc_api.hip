@@ -9,7 +9,6 @@
 #include <memory>
 #include <new>
 #include <string>
-#include <unordered_map>
 #include <vector>
 
 #include "fc_internal.h"
@@ -60,9 +59,7 @@ static fc_status upload(T** p, const T* src, size_t count) {
 static void free_problem(fc_problem_s* pb) {
   if (!pb) return;
   for (void* p : {(void*)pb->A.rowptr, (void*)pb->A.col, (void*)pb->A.val, (void*)pb->A.val32,
-                  (void*)pb->A.rows_hi, (void*)pb->A.rows_lo, (void*)pb->A.vsh,
-                  (void*)pb->A.vsh32, (void*)pb->A.grp, (void*)pb->A.grp_lo,
-                  (void*)pb->A.vofs, (void*)pb->rhs,
+                  (void*)pb->A.rows_hi, (void*)pb->A.rows_lo, (void*)pb->rhs,
                   (void*)pb->elem_nodes, (void*)pb->diag})
     if (p) (void)hipFree(p);
   delete pb;
@@ -74,72 +71,9 @@ static void free_precond(fc_precond_s* pc) {
   coarse_destroy(pc->coarse);
   for (void* p : {(void*)pc->block_elem, (void*)pc->P, (void*)pc->Q, (void*)pc->Q32,
                   (void*)pc->unsafe32, (void*)pc->unsafe_flag32, (void*)pc->Lbf, (void*)pc->isd,
-                  (void*)pc->inv_ptr, (void*)pc->inv_idx, (void*)pc->fallback, (void*)pc->y,
-                  (void*)pc->qofs, (void*)pc->qofs32, (void*)pc->qgrp, (void*)pc->qgrp32})
+                  (void*)pc->inv_ptr, (void*)pc->inv_idx, (void*)pc->fallback, (void*)pc->y})
     if (p) (void)hipFree(p);
   delete pc;
-}
-
-// Lattice box shape of a row node (the extent of its columns in each
-// direction; the device decodes columns from it).
-static void box_len(int64_t row, const LatticeInfo& lat, int len[3]) {
-  int64_t r = row;
-  for (int k = 0; k < 3; ++k) {
-    len[k] = 1;
-    if (k < lat.dim) {
-      const int g = (int)(r % lat.n1);
-      r /= lat.n1;
-      if (g % lat.p == 0)
-        len[k] = std::min(lat.n1 - 1, g + lat.p) - std::max(0, g - lat.p) + 1;
-      else
-        len[k] = lat.p + 1;
-    }
-  }
-}
-
-// A group is emitted when full, the rest at the end padded with -1.
-std::vector<int32_t> group_rows_by_copy(const std::vector<int64_t>& ofs, const LatticeInfo& lat,
-                                        const std::vector<int32_t>* subset) {
-  const int64_t nr = subset ? (int64_t)subset->size() : (int64_t)ofs.size();
-  struct Key {
-    int64_t o;
-    int len[3];
-    bool operator==(const Key& k) const {
-      return o == k.o && len[0] == k.len[0] && len[1] == k.len[1] && len[2] == k.len[2];
-    }
-  };
-  struct Hash {
-    size_t operator()(const Key& k) const {
-      uint64_t h = (uint64_t)k.o * 0x9E3779B97F4A7C15ull;
-      h ^= (uint64_t)(k.len[0] + 16 * k.len[1] + 256 * k.len[2]) * 0xBF58476D1CE4E5B9ull;
-      return (size_t)(h ^ (h >> 29));
-    }
-  };
-  std::unordered_map<Key, std::vector<int32_t>, Hash> open;
-  std::vector<int32_t> out;
-  out.reserve((size_t)nr + kShareGroup);
-  bool multi = false;
-  for (int64_t t = 0; t < nr; ++t) {
-    const int64_t r = subset ? (int64_t)(*subset)[t] : t;
-    Key k{ofs[r], {1, 1, 1}};
-    if (lat.dim > 0) box_len(r, lat, k.len);
-    std::vector<int32_t>& g = open[k];
-    g.push_back((int32_t)r);
-    if ((int)g.size() == kShareGroup) {
-      out.insert(out.end(), g.begin(), g.end());
-      g.clear();
-      multi = true;
-    }
-  }
-  for (auto& kv : open) {
-    std::vector<int32_t>& g = kv.second;
-    if (g.empty()) continue;
-    if (g.size() > 1) multi = true;
-    out.insert(out.end(), g.begin(), g.end());
-    out.insert(out.end(), kShareGroup - g.size(), -1);
-  }
-  if (!multi) out.clear();
-  return out;
 }
 
 static fc_status upload_system_body(const HostSystem& S, hipStream_t stream, fc_problem* out) {
@@ -171,46 +105,15 @@ static fc_status upload_system_body(const HostSystem& S, hipStream_t stream, fc_
   pb->eta = S.eta;
   pb->elem_nodes_host = S.elem_nodes;
   FC_HIP(launch_diag(*pb, stream));
-  // bitwise-equal block rows share one copy for the FP64 products.
-  // FC_SPMV_SHARE: 0 never, 1 whenever a row repeats, otherwise when the
-  // distinct rows hold at most three quarters of the values.
-  SharedRows sh;
-  {
-    const char* env = std::getenv("FC_SPMV_SHARE");
-    const int mode = env ? std::atoi(env) : -1;
-    if (mode != 0 && pb->A.n_rows > 0) {
-      share_rows(S, &sh);
-      const bool use = sh.distinct_rows < pb->A.n_rows &&
-                       (mode == 1 || 4 * (int64_t)sh.vals.size() <= 3 * (int64_t)S.val.size());
-      if (use) {
-        FC_TRY(upload(&pb->A.vsh, sh.vals.data(), sh.vals.size()));
-        FC_TRY(upload(&pb->A.vofs, sh.ofs.data(), sh.ofs.size()));
-        pb->A.sh_rows = sh.distinct_rows;
-        pb->A.sh_vals = (int64_t)sh.vals.size();
-        pb->vofs_host = sh.ofs;
-      }
-    }
-  }
   if (S.dim > 0) FC_HIP(spmv_enable_lattice(pb->A, S.dim, S.p * S.n + 1, S.p, stream));
-  if (pb->A.vofs) {
-    const char* env = std::getenv("FC_SPMV_GROUPED");
-    if (!env || std::atoi(env) != 0) {
-      std::vector<int32_t> g = group_rows_by_copy(sh.ofs, pb->A.lat, nullptr);
-      if (!g.empty()) {
-        FC_TRY(upload(&pb->A.grp, g.data(), g.size()));
-        pb->A.n_grp = (int64_t)g.size() / kShareGroup;
-      }
-    }
-  }
-  FC_HIP(spmv_autotune(pb->A, stream));
+  pb->A.group = spmv_group_for(pb->A);
   FC_HIP(hipStreamSynchronize(stream));
   *out = pb.release();
   return FC_OK;
 }
 
-// Host containers of the set-up can run out of memory (the kept copies of
-// shared rows hold up to three quarters of the values): report it instead of
-// letting the exception cross the C boundary.
+// Host containers of the set-up can run out of memory: report it instead
+// of letting the exception cross the C boundary.
 static fc_status upload_system(const HostSystem& S, hipStream_t stream, fc_problem* out) {
   try {
     return upload_system_body(S, stream, out);
@@ -219,8 +122,6 @@ static fc_status upload_system(const HostSystem& S, hipStream_t stream, fc_probl
     return FC_E_NOMEM;
   }
 }
-
-static void to_desc_check() {}
 
 }  // namespace fc
 
@@ -263,48 +164,6 @@ fc_status fc_host_system_info(fc_host_system hs, int64_t* n_dofs, int64_t* nnzb,
   if (n_el) *n_el = S.n_el;
   if (m) *m = S.m;
   if (bsr_dim) *bsr_dim = S.bdim;
-  return FC_OK;
-}
-
-fc_status fc_host_system_share(fc_host_system hs, int64_t* distinct_rows, int64_t* n_values,
-                               int64_t* ofs, double* vals) {
-  if (!hs || !distinct_rows || !n_values) {
-    set_error("fc_host_system_share: NULL argument");
-    return FC_E_ARG;
-  }
-  SharedRows sh;
-  try {
-    share_rows(hs->sys, &sh);
-  } catch (const std::bad_alloc&) {
-    set_error("fc_host_system_share: out of host memory");
-    return FC_E_NOMEM;
-  }
-  *distinct_rows = sh.distinct_rows;
-  *n_values = (int64_t)sh.vals.size();
-  if (ofs && !sh.ofs.empty()) std::memcpy(ofs, sh.ofs.data(), sh.ofs.size() * sizeof(int64_t));
-  if (vals && !sh.vals.empty())
-    std::memcpy(vals, sh.vals.data(), sh.vals.size() * sizeof(double));
-  return FC_OK;
-}
-
-fc_status fc_host_system_row_groups(fc_host_system hs, int64_t* n_groups, int32_t* groups) {
-  if (!hs || !n_groups) {
-    set_error("fc_host_system_row_groups: NULL argument");
-    return FC_E_ARG;
-  }
-  const HostSystem& S = hs->sys;
-  try {
-    SharedRows sh;
-    share_rows(S, &sh);
-    LatticeInfo lat{};
-    if (S.dim > 0) lat = LatticeInfo{S.dim, S.p * S.n + 1, S.p};
-    const std::vector<int32_t> g = group_rows_by_copy(sh.ofs, lat, nullptr);
-    *n_groups = (int64_t)g.size() / kShareGroup;
-    if (groups && !g.empty()) std::memcpy(groups, g.data(), g.size() * sizeof(int32_t));
-  } catch (const std::bad_alloc&) {
-    set_error("fc_host_system_row_groups: out of host memory");
-    return FC_E_NOMEM;
-  }
   return FC_OK;
 }
 
@@ -610,7 +469,6 @@ static fc_status precond_build_body(fc_problem pb, const fc_precond_opts* opts, 
   const size_t qn = (size_t)nb * sym_block_stride(m);
   FC_TRY(dev_alloc(&pc->Q, qn));
   FC_HIP(launch_pack_sym(*pc, pc->Q, 0, s));
-  FC_HIP(launch_share_blocks(*pc, s));
   if (o.store_mask & (FC_STORE_F32 | FC_STORE_BF16)) {
     FC_TRY(dev_alloc(&pc->isd, (size_t)pb->n_dofs));
     FC_HIP(launch_inv_sqrt_diag(*pb, pc->isd, s));
@@ -634,7 +492,6 @@ static fc_status precond_build_body(fc_problem pb, const fc_precond_opts* opts, 
       if (hf[k]) list.push_back((int32_t)k);
     pc->n_unsafe32 = (int64_t)list.size();
     if (!list.empty()) FC_TRY(upload(&pc->unsafe32, list.data(), list.size()));
-    FC_HIP(launch_share_blocks(*pc, s));
   }
   // BF16: scaled Cholesky factors (positive semi-definite however rounded)
   const size_t ln = (size_t)nb * ((size_t)m * (m + 1) / 2);
@@ -657,24 +514,6 @@ fc_status fc_spmv_info(fc_problem pb, int32_t* group, int32_t* lattice) {
   if (!pb) return FC_E_ARG;
   if (group) *group = pb->A.group;
   if (lattice) *lattice = pb->A.lat.dim > 0 ? 1 : 0;
-  return FC_OK;
-}
-
-fc_status fc_precond_share_info(fc_precond pc, int64_t* distinct_blocks,
-                                int64_t* distinct_blocks32, int64_t* block_groups) {
-  if (!pc) return FC_E_ARG;
-  if (block_groups) *block_groups = pc->qgrp ? pc->n_qgrp : 0;
-  if (distinct_blocks) *distinct_blocks = pc->qofs ? pc->q_distinct : 0;
-  if (distinct_blocks32) *distinct_blocks32 = pc->qofs32 ? pc->q32_distinct : 0;
-  return FC_OK;
-}
-
-fc_status fc_spmv_share_info(fc_problem pb, int64_t* distinct_rows, int64_t* distinct_values,
-                             int64_t* row_groups) {
-  if (!pb) return FC_E_ARG;
-  if (distinct_rows) *distinct_rows = pb->A.sh_rows;
-  if (distinct_values) *distinct_values = pb->A.sh_vals;
-  if (row_groups) *row_groups = pb->A.grp ? pb->A.n_grp : 0;
   return FC_OK;
 }
 

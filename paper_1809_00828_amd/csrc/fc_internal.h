@@ -57,7 +57,7 @@ struct DeviceBsr {
   int64_t n_rows = 0;      // block rows
   int64_t nnzb = 0;
   int32_t max_row = 0;     // longest block row
-  int32_t group = 0;       // SpMV lanes per block row chosen at set-up (0: heuristic)
+  int32_t group = 0;       // SpMV lanes per block row, fixed at set-up from the row lengths
   LatticeInfo lat;         // set when the columns were verified to be the lattice box
   int32_t* rowptr = nullptr;
   int32_t* col = nullptr;
@@ -68,30 +68,7 @@ struct DeviceBsr {
   int32_t* rows_hi = nullptr;
   int32_t* rows_lo = nullptr;
   int64_t n_hi = 0, n_lo = 0;
-  // products read the rows through vsh (FP64) and vsh32 (the FP32 rows of
-  // the mixed product) when set: bitwise-equal block rows keep one copy
-  // there and vofs[row] is the offset of a row's values
-  double* vsh = nullptr;
-  float* vsh32 = nullptr;   // FP32 copy of vsh (mixed products), same offsets
-  int64_t* vofs = nullptr;
-  int64_t sh_rows = 0, sh_vals = 0;   // distinct rows and their values
-  // rows reading one shared copy (and, with lattice columns, of one box
-  // shape), kShareGroup per group in row order, -1 padding: full FP64
-  // products load each shared value once per group
-  int32_t* grp = nullptr;
-  int64_t n_grp = 0;
-  // the same over the FP32 rows (rows_lo) of the mixed product
-  int32_t* grp_lo = nullptr;
-  int64_t n_grp_lo = 0;
 };
-
-constexpr int kShareGroup = 4;
-
-// Groups of kShareGroup rows with the same value offset (and, with lattice
-// columns, the same box shape) among `subset` (all rows when null), filled
-// in row order, -1 padding; empty when no group would hold two rows.
-std::vector<int32_t> group_rows_by_copy(const std::vector<int64_t>& ofs, const LatticeInfo& lat,
-                                        const std::vector<int32_t>* subset);
 
 struct SolverWs;
 void solver_ws_destroy(SolverWs* ws);
@@ -110,7 +87,6 @@ struct fc_problem_s {
   int32_t* elem_nodes = nullptr;   // [n_el*nn]
   std::vector<double> eta;         // host copy [n_el]
   std::vector<int32_t> elem_nodes_host;
-  std::vector<int64_t> vofs_host;  // host copy of A.vofs (empty when rows are not shared)
   double* diag = nullptr;          // A_ll [n_dofs]
 };
 
@@ -121,18 +97,6 @@ struct fc_precond_s {
   int32_t* block_elem = nullptr;   // [n_blocks] element of each block
   double* P = nullptr;             // [n_blocks*m*m] FP64 local inverses (dense)
   double* Q = nullptr;             // wrapped-diagonal symmetric copy, FP64
-  // FP64 block products read block k's copy at Q + qofs[k] when set: blocks
-  // whose stored copies are bitwise equal read one of them
-  int64_t* qofs = nullptr;
-  int64_t q_distinct = 0;          // blocks read through qofs that are their own source
-  int64_t* qofs32 = nullptr;       // the same for the FP32 copy Q32
-  int64_t q32_distinct = 0;
-  // blocks reading one FP64 copy, kShareGroup per group in block order, -1
-  // padding: the FP64 block products load each staged chunk once per group
-  int32_t* qgrp = nullptr;
-  int64_t n_qgrp = 0;
-  int32_t* qgrp32 = nullptr;       // the same for the FP32 copy
-  int64_t n_qgrp32 = 0;
   float* Q32 = nullptr;            // optional FP32 wrapped-diagonal copy of D^1/2 P D^1/2
   int32_t* unsafe32 = nullptr;     // blocks whose FP32 copy is not safely positive
   int32_t* unsafe_flag32 = nullptr; // the same as one flag per block
@@ -156,8 +120,8 @@ namespace fc {
 // y = A x  (and optionally partial dots (x, y) per workgroup)
 hipError_t launch_spmv(const DeviceBsr& A, const double* x, double* y,
                        hipStream_t s);
-// time the SpMV group widths on A and keep the fastest in A.group
-hipError_t spmv_autotune(DeviceBsr& A, hipStream_t s);
+// lanes per block row of A's products, from its mean row length
+int spmv_group_for(const DeviceBsr& A);
 // verify on the device that A's columns are the lattice boxes of (dim, n1,
 // p); if so record it in A.lat, so the SpMV computes columns instead of
 // reading them

@@ -19,7 +19,6 @@
 #include <cstring>
 #include <memory>
 #include <thread>
-#include <unordered_map>
 
 namespace fc {
 
@@ -736,56 +735,6 @@ fc_status assemble_host(const fc_problem_desc& d, HostSystem* out, std::string* 
       if (gone[nd])
         for (int c = 0; c < bd; ++c) S.rhs[nd * bd + c] = 0.0;
   return FC_OK;
-}
-
-void share_rows(const HostSystem& S, SharedRows* out) {
-  const int64_t nr = (int64_t)S.rowptr.size() - 1;
-  const int64_t bb = (int64_t)S.bdim * S.bdim;
-  auto row_ptr = [&](int64_t r) { return S.val.data() + (int64_t)S.rowptr[r] * bb; };
-  auto row_len = [&](int64_t r) { return (int64_t)(S.rowptr[r + 1] - S.rowptr[r]) * bb; };
-  // 1. a hash of every row's bits
-  std::vector<uint64_t> h((size_t)std::max<int64_t>(nr, 0));
-  parallel_for(nr, [&](int64_t r) {
-    const int64_t n = row_len(r);
-    uint64_t x = 0x9E3779B97F4A7C15ull ^ (uint64_t)n;
-    const double* v = row_ptr(r);
-    for (int64_t k = 0; k < n; ++k) {
-      uint64_t w;
-      std::memcpy(&w, v + k, sizeof(w));
-      x = (x ^ w) * 0xFF51AFD7ED558CCDull;
-      x ^= x >> 32;
-    }
-    h[r] = x;
-  });
-  // 2. the first row seen with each hash is that hash's representative
-  std::unordered_map<uint64_t, int64_t> first;
-  first.reserve((size_t)nr);
-  std::vector<int64_t> rep((size_t)std::max<int64_t>(nr, 0));
-  for (int64_t r = 0; r < nr; ++r) rep[r] = first.emplace(h[r], r).first->second;
-  // 3. a row shares only when its bits equal the representative's (a hash
-  // collision leaves the row with a copy of its own)
-  parallel_for(nr, [&](int64_t r) {
-    const int64_t q = rep[r];
-    if (q != r && (row_len(q) != row_len(r) ||
-                   std::memcmp(row_ptr(q), row_ptr(r), row_len(r) * sizeof(double)) != 0))
-      rep[r] = r;
-  });
-  // 4. offsets of the kept rows, then every row's offset
-  out->ofs.assign((size_t)std::max<int64_t>(nr, 0), 0);
-  int64_t total = 0, kept = 0;
-  for (int64_t r = 0; r < nr; ++r)
-    if (rep[r] == r) {
-      out->ofs[r] = total;
-      total += row_len(r);
-      ++kept;
-    }
-  for (int64_t r = 0; r < nr; ++r) out->ofs[r] = out->ofs[rep[r]];
-  out->vals.assign((size_t)total, 0.0);
-  parallel_for(nr, [&](int64_t r) {
-    if (rep[r] == r)
-      std::memcpy(out->vals.data() + out->ofs[r], row_ptr(r), row_len(r) * sizeof(double));
-  });
-  out->distinct_rows = kept;
 }
 
 }  // namespace fc

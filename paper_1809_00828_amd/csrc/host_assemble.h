@@ -43,18 +43,6 @@ inline int64_t soa_index(const std::vector<int32_t>& rp, int64_t row, int bb,
 // Number of worker threads for host loops.
 int host_threads();
 
-// Block rows whose stored values are bitwise equal (same length, same values
-// in the same order) keep one copy: on a Cartesian cell grid every row whose
-// supporting cells are all uncut and of the same interior/boundary kind
-// repeats one of a few stencils.  A row's product still multiplies its own
-// columns, so sharing the values changes no product.
-struct SharedRows {
-  std::vector<int64_t> ofs;    // [n_rows] offset of the row's values in vals
-  std::vector<double> vals;    // distinct rows, row-SoA layout, first-seen order
-  int64_t distinct_rows = 0;
-};
-void share_rows(const HostSystem& S, SharedRows* out);
-
 template <class F>
 void parallel_for(int64_t n, F&& f);
 

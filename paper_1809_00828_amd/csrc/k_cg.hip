@@ -854,18 +854,6 @@ static fc_status ensure_mixed_matrix(fc_problem_s& pb, hipStream_t s) {
   A.n_hi = (int64_t)rh.size();
   A.n_lo = (int64_t)rl.size();
   FC_HIP(hipMalloc(&A.val32, A.nnzb * A.bdim * A.bdim * sizeof(float)));
-  if (A.vofs && A.sh_vals > 0) FC_HIP(hipMalloc(&A.vsh32, A.sh_vals * sizeof(float)));
-  // the FP32 rows that read one shared copy go four at a time, like the
-  // full FP64 products
-  std::vector<int32_t> gl;
-  if (A.vsh32 && A.grp && !rl.empty() && (int64_t)pb.vofs_host.size() == nr)
-    gl = group_rows_by_copy(pb.vofs_host, A.lat, &rl);
-  if (!gl.empty()) {
-    FC_HIP(hipMalloc(&A.grp_lo, gl.size() * sizeof(int32_t)));
-    FC_HIP(hipMemcpyAsync(A.grp_lo, gl.data(), gl.size() * sizeof(int32_t),
-                          hipMemcpyHostToDevice, s));
-    A.n_grp_lo = (int64_t)gl.size() / kShareGroup;
-  }
   FC_HIP(launch_cast_matrix(A, s));
   FC_HIP(hipStreamSynchronize(s));   // the host lists must outlive the copies
   return FC_OK;

@@ -16,13 +16,6 @@ int64_t sym_block_stride(int m);
 // Q = wrapped-diagonal copy of the dense FP64 local inverses pc.P in FP64
 // (0), or diagonally scaled in FP32 (1) or BF16 (2) (needs pc.isd).
 hipError_t launch_pack_sym(const fc_precond_s& pc, void* Q, int precision, hipStream_t s);
-// Blocks whose wrapped-diagonal copies are bitwise equal: every block gets
-// the offset of the first such copy, pc.qofs for the FP64 copy pc.Q and
-// pc.qofs32 for the FP32 copy pc.Q32 (each done once, when the copy exists),
-// read by the staged block products (m > 64).  FC_SCHWARZ_SHARE: 0 never,
-// 1 whenever a block repeats, otherwise when at least a quarter of the
-// blocks repeat.
-hipError_t launch_share_blocks(fc_precond_s& pc, hipStream_t s);
 // isd = 1/sqrt(diag(A)) (1 where the diagonal is not positive).
 hipError_t launch_inv_sqrt_diag(const fc_problem_s& pb, double* isd, hipStream_t s);
 }  // namespace fc

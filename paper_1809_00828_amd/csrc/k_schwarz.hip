@@ -25,19 +25,12 @@
 //     positive definite are skipped there and done from the FP64 copy.
 //   * BF16: the scaled Cholesky factor of the same matrix, two triangular
 //     passes through LDS (positive semi-definite however rounded).
-//   * Shared copies: on a Cartesian cell grid the blocks of uncut cells with
-//     the same kind of neighbourhood are equal matrices, and their stored
-//     inverses (FP64 and FP32 copies) come out bit for bit equal.  Set-up
-//     finds them (content hash, then a bitwise comparison) and gives every
-//     block the offset of the copy it reads; blocks reading one copy are
-//     taken four to a workgroup, each staged chunk loaded once for the four.
-//     Results are bitwise those of the per-block kernel.
+//   Every block reads its own stored inverse once per apply.
 // Phase 2 (pull): every unknown sums the y_B entries of the blocks that
 // contain it, in a fixed order (no atomics, bitwise reproducible), and adds
 // its diagonal-scaling term.
 #include <algorithm>
 #include <cstdlib>
-#include <unordered_map>
 #include <vector>
 
 #include "dev_common.h"
@@ -73,15 +66,13 @@ __global__ __launch_bounds__(256) void k_schwarz_large(
 }
 
 // m > 64, symmetric layout staged through LDS (sym_block_staged).
-// kShared: block blk reads the copy at P + qofs[blk] through the caches.
-template <typename T, bool kShared = false>
+template <typename T>
 __global__ __launch_bounds__(256) void k_schwarz_sym_staged(
     const T* __restrict__ P, int64_t block_stride, const int32_t* __restrict__ elem_nodes,
     const int32_t* __restrict__ block_elem, int nn, int bd, int m,
     const double* __restrict__ r, const double* __restrict__ q, const double* __restrict__ isd,
     const CgScalars* __restrict__ sc, double* __restrict__ y, int64_t n_blocks,
-    const int32_t* __restrict__ list, const int32_t* __restrict__ skip,
-    const int64_t* __restrict__ qofs) {
+    const int32_t* __restrict__ list, const int32_t* __restrict__ skip) {
   using A = typename Acc<T>::type;
   constexpr int kStageRows = StageRows<T>::value;
   // the gathered residual is kept in the accumulation type: an FP32 copy
@@ -104,52 +95,9 @@ __global__ __launch_bounds__(256) void k_schwarz_sym_staged(
     dof = (int64_t)elem_nodes[e * nn + i / bd] * bd + (i % bd);
     rB[i] = (A)(gather_r(r, q, alpha, dof) * (isd ? isd[dof] : 1.0));
   }
-  const T* Qb = P + (kShared ? qofs[blk] : blk * block_stride);
-  const double v = sym_block_staged<T, A, !kShared>(Qb, rB, m, i, tile);
+  const T* Qb = P + blk * block_stride;
+  const double v = sym_block_staged<T, A>(Qb, rB, m, i, tile);
   if (act) y[blk * m + i] = isd ? v * isd[dof] : v;
-}
-
-// m > 64: groups of R blocks that read one stored copy (grp: R block
-// indices per group, -1 padding), one workgroup per group.  Each staged
-// chunk of the copy is loaded once for the R blocks; every block's result is
-// bitwise that of k_schwarz_sym_staged (FP32 copies: scaled by isd, blocks
-// flagged in skip left to the FP64 launch, as there).
-template <typename T, int R>
-__global__ __launch_bounds__(256) void k_schwarz_sym_grp(
-    const T* __restrict__ P, const int64_t* __restrict__ qofs,
-    const int32_t* __restrict__ grp, int64_t n_grp, const int32_t* __restrict__ elem_nodes,
-    const int32_t* __restrict__ block_elem, int nn, int bd, int m,
-    const double* __restrict__ r, const double* __restrict__ q, const double* __restrict__ isd,
-    const CgScalars* __restrict__ sc, double* __restrict__ y, const int32_t* __restrict__ skip) {
-  using A = typename Acc<T>::type;
-  __shared__ A rB[R][256];
-  __shared__ T tile[StageRows<T>::value][256];
-  if (sc && sc->done) return;
-  const int64_t g = xcd_remap(blockIdx.x, gridDim.x);
-  if (g >= n_grp) return;
-  const double alpha = (sc && q) ? sc->alpha : 0.0;
-  const int i = threadIdx.x;
-  const bool act = i < m;
-  int64_t blk[R], dof[R];
-  bool use[R];
-#pragma unroll
-  for (int k = 0; k < R; ++k) {
-    blk[k] = grp[g * R + k];
-    use[k] = blk[k] >= 0 && !(skip && skip[blk[k]]);
-    dof[k] = 0;
-    if (act && use[k]) {
-      const int64_t e = block_elem[blk[k]];
-      dof[k] = (int64_t)elem_nodes[e * nn + i / bd] * bd + (i % bd);
-      rB[k][i] = (A)(gather_r(r, q, alpha, dof[k]) * (isd ? isd[dof[k]] : 1.0));
-    }
-  }
-  double v[R];
-  sym_block_staged_multi<T, A, R>(P + qofs[blk[0]], rB, use, m, i, tile, v);
-  if (act) {
-#pragma unroll
-    for (int k = 0; k < R; ++k)
-      if (use[k]) y[blk[k] * m + i] = isd ? v[k] * isd[dof[k]] : v[k];
-  }
 }
 
 // m <= 64: each wave handles floor(64/m) blocks, one lane per output row.
@@ -400,200 +348,6 @@ __global__ void k_pack_sym(const double* __restrict__ P, T* __restrict__ Q, int 
 
 int64_t sym_block_stride(int m) { return (int64_t)(m / 2 + 1) * m; }
 
-// ------------------------------------------------------------ shared copies
-// On a Cartesian cell grid the element blocks of uncut cells with the same
-// kind of neighbourhood are the same matrix, so their stored inverses can be
-// the same bits.  A content hash groups candidates; a bitwise comparison
-// decides.
-
-// Hash of one block's copy (nw 32-bit words): the wrapping sum over its
-// words of a mix of (word, index), so it does not depend on the order lanes
-// visit the words.
-__global__ __launch_bounds__(256) void k_block_hash(const uint32_t* __restrict__ Q, int64_t nw,
-                                                    uint64_t* __restrict__ h) {
-  __shared__ uint64_t part[256];
-  const int64_t blk = blockIdx.x;
-  const uint32_t* w = Q + blk * nw;
-  uint64_t acc = 0;
-  for (int64_t k = threadIdx.x; k < nw; k += 256) {
-    uint64_t z = (uint64_t)w[k] ^ ((uint64_t)k * 0x9E3779B97F4A7C15ull);
-    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
-    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
-    acc += z ^ (z >> 31);
-  }
-  part[threadIdx.x] = acc;
-  __syncthreads();
-  for (int off = 128; off > 0; off >>= 1) {
-    if (threadIdx.x < off) part[threadIdx.x] += part[threadIdx.x + off];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) h[blk] = part[0];
-}
-
-// differ[blk] = 1 when block blk's copy is not bitwise equal to that of
-// block rep[blk] (0 for blocks that are their own representative).
-__global__ __launch_bounds__(256) void k_block_differs(const uint32_t* __restrict__ Q, int64_t nw,
-                                                       const int32_t* __restrict__ rep,
-                                                       int32_t* __restrict__ differ) {
-  __shared__ int32_t any[256];
-  const int64_t blk = blockIdx.x;
-  const int64_t q = rep[blk];
-  int32_t d = 0;
-  if (q != blk) {
-    const uint32_t* a = Q + blk * nw;
-    const uint32_t* b = Q + q * nw;
-    for (int64_t k = threadIdx.x; k < nw; k += 256) d |= a[k] != b[k] ? 1 : 0;
-  }
-  any[threadIdx.x] = d;
-  __syncthreads();
-  for (int off = 128; off > 0; off >>= 1) {
-    if (threadIdx.x < off) any[threadIdx.x] |= any[threadIdx.x + off];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) differ[blk] = any[0];
-}
-
-// Offsets (in elements of `stride` per block) of the copy each of the nb
-// blocks reads; *ofs stays null when no block is shared.
-static hipError_t share_copies(const void* Q, int64_t stride, int elem_bytes, int64_t nb,
-                               int mode, int64_t** ofs_out, int64_t* distinct_out,
-                               int32_t** grp_out, int64_t* n_grp_out, hipStream_t s) {
-  *ofs_out = nullptr;
-  *distinct_out = 0;
-  if (grp_out) {
-    *grp_out = nullptr;
-    *n_grp_out = 0;
-  }
-  if ((stride * elem_bytes) % 4 != 0) return hipSuccess;
-  const int64_t nw = stride * elem_bytes / 4;
-  const uint32_t* W = static_cast<const uint32_t*>(Q);
-  uint64_t* dh = nullptr;
-  int32_t* drep = nullptr;
-  int32_t* ddiff = nullptr;
-  struct Free {
-    void* p[3];
-    ~Free() {
-      for (void* q : p)
-        if (q) (void)hipFree(q);
-    }
-  } tmp{{nullptr, nullptr, nullptr}};
-  hipError_t e = hipMalloc(&dh, nb * sizeof(uint64_t));
-  tmp.p[0] = dh;
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_block_hash, dim3((unsigned)nb), dim3(256), 0, s, W, nw, dh);
-  if ((e = hipGetLastError()) != hipSuccess) return e;
-  std::vector<uint64_t> h((size_t)nb);
-  if ((e = hipMemcpyAsync(h.data(), dh, nb * sizeof(uint64_t), hipMemcpyDeviceToHost, s)) !=
-          hipSuccess ||
-      (e = hipStreamSynchronize(s)) != hipSuccess)
-    return e;
-  // the first block with each hash is the candidate source
-  std::unordered_map<uint64_t, int32_t> first;
-  first.reserve((size_t)nb);
-  std::vector<int32_t> rep((size_t)nb);
-  int64_t repeats = 0;
-  for (int64_t k = 0; k < nb; ++k) {
-    rep[k] = first.emplace(h[k], (int32_t)k).first->second;
-    repeats += rep[k] != k;
-  }
-  if (repeats == 0 || (mode != 1 && 4 * repeats < nb)) return hipSuccess;
-  if ((e = hipMalloc(&drep, nb * sizeof(int32_t))) != hipSuccess) return e;
-  tmp.p[1] = drep;
-  if ((e = hipMalloc(&ddiff, nb * sizeof(int32_t))) != hipSuccess) return e;
-  tmp.p[2] = ddiff;
-  if ((e = hipMemcpyAsync(drep, rep.data(), nb * sizeof(int32_t), hipMemcpyHostToDevice, s)) !=
-      hipSuccess)
-    return e;
-  hipLaunchKernelGGL(k_block_differs, dim3((unsigned)nb), dim3(256), 0, s, W, nw, drep, ddiff);
-  if ((e = hipGetLastError()) != hipSuccess) return e;
-  std::vector<int32_t> diff((size_t)nb);
-  if ((e = hipMemcpyAsync(diff.data(), ddiff, nb * sizeof(int32_t), hipMemcpyDeviceToHost, s)) !=
-          hipSuccess ||
-      (e = hipStreamSynchronize(s)) != hipSuccess)
-    return e;
-  // a hash collision leaves the block with its own copy
-  std::vector<int64_t> ofs((size_t)nb);
-  int64_t distinct = 0;
-  for (int64_t k = 0; k < nb; ++k) {
-    const int64_t src = diff[k] ? k : rep[k];
-    ofs[k] = src * stride;
-    distinct += src == k;
-  }
-  int64_t* d = nullptr;
-  if ((e = hipMalloc(&d, nb * sizeof(int64_t))) != hipSuccess) return e;
-  if ((e = hipMemcpyAsync(d, ofs.data(), nb * sizeof(int64_t), hipMemcpyHostToDevice, s)) !=
-          hipSuccess ||
-      (e = hipStreamSynchronize(s)) != hipSuccess) {
-    (void)hipFree(d);
-    return e;
-  }
-  *ofs_out = d;
-  *distinct_out = distinct;
-  if (!grp_out) return hipSuccess;
-  // groups of kShareGroup blocks with one source, filled in block order
-  std::unordered_map<int64_t, std::vector<int32_t>> open;
-  std::vector<int32_t> gl;
-  gl.reserve((size_t)nb + kShareGroup);
-  for (int64_t k = 0; k < nb; ++k) {
-    std::vector<int32_t>& g = open[ofs[k]];
-    g.push_back((int32_t)k);
-    if ((int)g.size() == kShareGroup) {
-      gl.insert(gl.end(), g.begin(), g.end());
-      g.clear();
-    }
-  }
-  for (auto& kv : open) {
-    if (kv.second.empty()) continue;
-    gl.insert(gl.end(), kv.second.begin(), kv.second.end());
-    gl.insert(gl.end(), kShareGroup - kv.second.size(), -1);
-  }
-  // groups in the order of their first blocks (the partial groups, among
-  // them every block with a copy of its own, would otherwise come in hash
-  // order and scatter the residual gathers)
-  {
-    const int64_t ng = (int64_t)gl.size() / kShareGroup;
-    std::vector<int64_t> order((size_t)ng);
-    for (int64_t k = 0; k < ng; ++k) order[k] = k;
-    std::sort(order.begin(), order.end(), [&](int64_t a, int64_t b) {
-      return gl[a * kShareGroup] < gl[b * kShareGroup];
-    });
-    std::vector<int32_t> sorted(gl.size());
-    for (int64_t k = 0; k < ng; ++k)
-      std::copy(gl.begin() + order[k] * kShareGroup, gl.begin() + (order[k] + 1) * kShareGroup,
-                sorted.begin() + k * kShareGroup);
-    gl.swap(sorted);
-  }
-  int32_t* dg = nullptr;
-  if ((e = hipMalloc(&dg, gl.size() * sizeof(int32_t))) != hipSuccess) return e;
-  if ((e = hipMemcpyAsync(dg, gl.data(), gl.size() * sizeof(int32_t), hipMemcpyHostToDevice,
-                          s)) != hipSuccess ||
-      (e = hipStreamSynchronize(s)) != hipSuccess) {
-    (void)hipFree(dg);
-    return e;
-  }
-  *grp_out = dg;
-  *n_grp_out = (int64_t)gl.size() / kShareGroup;
-  return hipSuccess;
-}
-
-hipError_t launch_share_blocks(fc_precond_s& pc, hipStream_t s) {
-  const int64_t nb = pc.n_blocks;
-  const char* env = std::getenv("FC_SCHWARZ_SHARE");
-  const int mode = env ? std::atoi(env) : -1;
-  if (mode == 0 || pc.m <= 64 || nb < 2) return hipSuccess;
-  const int64_t stride = sym_block_stride(pc.m);
-  hipError_t e = hipSuccess;
-  const char* genv = std::getenv("FC_SCHWARZ_GROUPED");
-  const bool grouped = !genv || std::atoi(genv) != 0;
-  if (pc.Q && !pc.qofs)
-    e = share_copies(pc.Q, stride, 8, nb, mode, &pc.qofs, &pc.q_distinct,
-                     grouped ? &pc.qgrp : nullptr, &pc.n_qgrp, s);
-  if (e == hipSuccess && pc.Q32 && !pc.qofs32)
-    e = share_copies(pc.Q32, stride, 4, nb, mode, &pc.qofs32, &pc.q32_distinct,
-                     grouped ? &pc.qgrp32 : nullptr, &pc.n_qgrp32, s);
-  return e;
-}
-
 hipError_t launch_pack_sym(const fc_precond_s& pc, void* Q, int precision, hipStream_t s) {
   const int64_t nb = pc.n_blocks;
   const int m = pc.m;
@@ -642,26 +396,11 @@ static hipError_t phase1(const fc_precond_s& pc, const T* P, const double* r, co
   }();
   if (pc.m > 64) {
     const int threads = 64 * ((pc.m + 63) / 64);
-    const int64_t* qo = (const void*)P == (const void*)pc.Q     ? pc.qofs
-                        : (const void*)P == (const void*)pc.Q32 ? pc.qofs32
-                                                                : nullptr;
-    const int32_t* qg = qo == nullptr ? nullptr : qo == pc.qofs ? pc.qgrp : pc.qgrp32;
-    const int64_t nqg = qo == pc.qofs ? pc.n_qgrp : pc.n_qgrp32;
-    if (kSym && variant && qo && qg)
-      hipLaunchKernelGGL((k_schwarz_sym_grp<T, kShareGroup>), dim3((unsigned)nqg),
-                         dim3(threads), 0, s, P, qo, qg, nqg, pb.elem_nodes, pc.block_elem,
-                         pc.nn, pc.bdim, pc.m, r, q, isd, sc, pc.y,
-                         sizeof(T) == 4 ? pc.unsafe_flag32 : nullptr);
-    else if (kSym && variant && qo)
-      hipLaunchKernelGGL((k_schwarz_sym_staged<T, true>), dim3((unsigned)pc.n_blocks),
-                         dim3(threads), 0, s, P, stride, pb.elem_nodes, pc.block_elem, pc.nn,
-                         pc.bdim, pc.m, r, q, isd, sc, pc.y, pc.n_blocks, nullptr,
-                         sizeof(T) == 4 ? pc.unsafe_flag32 : nullptr, qo);
-    else if (kSym && variant)
+    if (kSym && variant)
       hipLaunchKernelGGL((k_schwarz_sym_staged<T>), dim3((unsigned)pc.n_blocks), dim3(threads),
                          0, s, P, stride, pb.elem_nodes, pc.block_elem, pc.nn, pc.bdim, pc.m, r,
                          q, isd, sc, pc.y, pc.n_blocks, nullptr,
-                         sizeof(T) == 4 ? pc.unsafe_flag32 : nullptr, nullptr);
+                         sizeof(T) == 4 ? pc.unsafe_flag32 : nullptr);
     else
       hipLaunchKernelGGL((k_schwarz_large<T, kSym>), dim3((unsigned)pc.n_blocks), dim3(threads),
                          0, s, P, stride, pb.elem_nodes, pc.block_elem, pc.nn, pc.bdim, pc.m, r,
@@ -713,7 +452,7 @@ hipError_t launch_schwarz_phase1(const fc_precond_s& pc, int precision, const do
         hipLaunchKernelGGL((k_schwarz_sym_staged<double>), dim3((unsigned)pc.n_unsafe32),
                            dim3(64 * ((pc.m + 63) / 64)), 0, s, pc.Q, sym_block_stride(pc.m),
                            pb.elem_nodes, pc.block_elem, pc.nn, pc.bdim, pc.m, r, q, nullptr, sc,
-                           pc.y, pc.n_blocks, pc.unsafe32, nullptr, nullptr);
+                           pc.y, pc.n_blocks, pc.unsafe32, nullptr);
       else
         hipLaunchKernelGGL(k_schwarz_sym_list, dim3((unsigned)pc.n_unsafe32),
                            dim3(64 * ((pc.m + 63) / 64)), 0, s, pc.Q, sym_block_stride(pc.m),

@@ -16,7 +16,5 @@ hipError_t launch_diag(const fc_problem_s& pb, hipStream_t s);
 hipError_t launch_fallback(const fc_problem_s& pb, fc_precond_s& pc,
                            unsigned long long* d_count, hipStream_t s);
 // A.val32 = FP32 copy of A.val (same layout)
-// FP32 copies of the matrix values (val32, and vsh32 of the shared rows when
-// both are allocated).
 hipError_t launch_cast_matrix(const DeviceBsr& A, hipStream_t s);
 }  // namespace fc

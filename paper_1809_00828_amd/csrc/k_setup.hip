@@ -563,8 +563,6 @@ hipError_t launch_cast_matrix(const DeviceBsr& A, hipStream_t s) {
   const int64_t n = A.nnzb * A.bdim * A.bdim;
   if (!A.val32 || n == 0) return hipSuccess;
   hipLaunchKernelGGL(k_cast_f32, dim3(4096), dim3(256), 0, s, A.val, A.val32, n);
-  if (A.vsh32 && A.sh_vals > 0)
-    hipLaunchKernelGGL(k_cast_f32, dim3(4096), dim3(256), 0, s, A.vsh, A.vsh32, A.sh_vals);
   return hipGetLastError();
 }
 

@@ -7,14 +7,13 @@
 // val[rowptr[i]*B*B + e*L + k] for entry e of the k-th block of the row,
 // so G lanes sweeping the blocks of one row read G consecutive values per
 // entry.  A group of G lanes owns one block row; its partial sums are
-// combined with a butterfly reduction.  Values and column indices are read
-// once per product and streamed with non-temporal loads, which leaves the
-// cache to the gathered x entries (neighbouring rows of the lattice share
-// most of their columns).  When block rows repeat (every row whose cells are
-// uncut repeats one of a few stencils of the cell grid), the products read
-// one stored copy per distinct row through a per-row offset; rows with one
-// copy and one lattice box shape are taken four at a time, each value loaded
-// once for the four (k_spmv_bsr_grp), and the caches serve the repeats.
+// combined with a butterfly reduction.  Every block row reads its own
+// stored values once per product; FP64 3x3 values and column indices are
+// streamed with non-temporal loads, which leaves the cache to the gathered x
+// entries (neighbouring rows of the lattice share most of their columns).
+// The group width G is fixed at set-up from the mean row length, so the
+// summation order of a row, and with it every result, is the same in every
+// process.
 //
 // Tiles of 256/G rows are dealt out so that the workgroups resident on one
 // XCD (hardware ids congruent mod 8) walk one contiguous range of rows and
@@ -22,7 +21,6 @@
 // per workgroup; a one-workgroup kernel of the solver sums them in a fixed
 // order (no atomics).
 #include <cstdlib>
-#include <type_traits>
 
 #include "dev_common.h"
 #include "k_spmv.h"
@@ -45,17 +43,13 @@ __device__ __forceinline__ T stream_load(const T* p) {
 // kLat: columns computed from the lattice box (col is not read).
 // XT: type of x (FP32 for the FP32 rows of the mixed product, which round
 // x to FP32 before every product anyway).
-// kShared: a row's values start at val + vofs[row] (bitwise-equal rows share
-// one copy) instead of val + rowptr[row]*B*B; shared values are read
-// through the caches, where the rows that repeat stay resident.
-template <int B, int G, typename T, bool kLat, typename XT, bool kShared>
+template <int B, int G, typename T, bool kLat, typename XT>
 __global__ __launch_bounds__(256) void k_spmv_bsr(
     const int32_t* __restrict__ rowptr, const int32_t* __restrict__ col,
     const T* __restrict__ val, const XT* __restrict__ x,
     double* __restrict__ y, int64_t n_rows, const CgScalars* __restrict__ sc,
-    double* __restrict__ partial, const int32_t* __restrict__ rows, const LatticeInfo lat,
-    const int64_t* __restrict__ vofs) {
-  constexpr bool kNT = B != 1 && sizeof(T) == 8 && !kShared;
+    double* __restrict__ partial, const int32_t* __restrict__ rows, const LatticeInfo lat) {
+  constexpr bool kNT = B != 1 && sizeof(T) == 8;
   constexpr int BB = B * B;
   constexpr int RPW = 256 / G;   // rows per tile
   __shared__ double lds[16];
@@ -73,7 +67,7 @@ __global__ __launch_bounds__(256) void k_spmv_bsr(
     const int64_t row = rows ? (int64_t)rows[idx] : idx;
     const int64_t base = rowptr[row];
     const int L = rowptr[row + 1] - (int32_t)base;
-    const T* v = val + (kShared ? vofs[row] : base * BB);
+    const T* v = val + base * BB;
     RowBox box;
     if constexpr (kLat) box = row_box(row, lat);
     double acc[B];
@@ -139,128 +133,33 @@ __global__ __launch_bounds__(256) void k_spmv_bsr(
   if (threadIdx.x == 0) partial[blockIdx.x] = dot;
 }
 
-// Rows that read one shared copy, R at a time (grp: R row indices per
-// group, -1 padding; with lattice columns the rows of a group have one box
-// shape, so a column is the first row's plus a fixed shift).  Each value is
-// loaded once for the R rows; every row keeps the lane order, the order of
-// its fused multiply-adds and the reduction of k_spmv_bsr, so its result is
-// bitwise that kernel's at the same G.
-template <int B, int G, bool kLat, int R, typename T = double, typename XT = double>
-__global__ __launch_bounds__(256) void k_spmv_bsr_grp(
-    const int32_t* __restrict__ rowptr, const int32_t* __restrict__ col,
-    const T* __restrict__ val, const int64_t* __restrict__ vofs,
-    const int32_t* __restrict__ grp, int64_t n_grp, const XT* __restrict__ x,
-    double* __restrict__ y, const CgScalars* __restrict__ sc, const LatticeInfo lat) {
-  // FP32 values accumulate in FP32, as in k_spmv_bsr
-  using AC = typename std::conditional<sizeof(T) == 8, double, float>::type;
-  constexpr int BB = B * B;
-  constexpr int RPW = 256 / G;
-  if (sc && sc->done) return;
-  const int64_t ntiles = (n_grp + RPW - 1) / RPW;
-  const uint32_t nwg = gridDim.x, xcd = blockIdx.x % kNumXcd, j = blockIdx.x / kNumXcd;
-  const uint32_t per = nwg / kNumXcd + (xcd < nwg % kNumXcd ? 1u : 0u);
-  const int64_t t0 = ntiles * xcd / kNumXcd, t1 = ntiles * (xcd + 1) / kNumXcd;
-  const int lane = threadIdx.x % G;
-  for (int64_t tile = t0 + j; tile < t1; tile += per) {
-    const int64_t gi = tile * RPW + threadIdx.x / G;
-    if (gi >= n_grp) continue;
-    int64_t row[R];
-#pragma unroll
-    for (int q = 0; q < R; ++q) row[q] = grp[gi * R + q];
-    const int64_t r0 = row[0];
-    const int L = rowptr[r0 + 1] - rowptr[r0];
-    const T* v = val + vofs[r0];
-    // kLat: shift of each row's columns against row 0's; else the start of
-    // each row's column list
-    int64_t cb[R];
-    RowBox box;
-    if constexpr (kLat) {
-      box = row_box(r0, lat);
-      const int64_t b0 = box.lo[0] + (int64_t)lat.n1 * (box.lo[1] + (int64_t)lat.n1 * box.lo[2]);
-#pragma unroll
-      for (int q = 0; q < R; ++q) {
-        cb[q] = 0;
-        if (row[q] >= 0) {
-          const RowBox bq = row_box(row[q], lat);
-          cb[q] = bq.lo[0] + (int64_t)lat.n1 * (bq.lo[1] + (int64_t)lat.n1 * bq.lo[2]) - b0;
-        }
-      }
-    } else {
-#pragma unroll
-      for (int q = 0; q < R; ++q) cb[q] = row[q] >= 0 ? (int64_t)rowptr[row[q]] : 0;
-    }
-    AC acc[R][B];
-#pragma unroll
-    for (int q = 0; q < R; ++q)
-#pragma unroll
-      for (int i = 0; i < B; ++i) acc[q][i] = AC(0);
-    constexpr int U = B == 1 ? 8 : 2;
-    for (int k = lane; k < L; k += U * G) {
-      T a[U][BB];
-      int c0[U];
-#pragma unroll
-      for (int u = 0; u < U; ++u) {
-        const int ku = k + u * G;
-        const bool on = ku < L;
-        if constexpr (kLat) c0[u] = on ? lattice_col(box, ku, lat.n1) : -1;
-        else c0[u] = on ? ku : -1;
-#pragma unroll
-        for (int e = 0; e < BB; ++e) a[u][e] = on ? v[(int64_t)e * L + ku] : T(0);
-      }
-#pragma unroll
-      for (int q = 0; q < R; ++q) {
-        if (row[q] < 0) continue;
-        XT xv[U][B];
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-          int64_t c = -1;
-          if (c0[u] >= 0) c = kLat ? c0[u] + cb[q] : (int64_t)col[cb[q] + c0[u]];
-#pragma unroll
-          for (int jj = 0; jj < B; ++jj) xv[u][jj] = c >= 0 ? x[c * B + jj] : XT(0);
-        }
-#pragma unroll
-        for (int u = 0; u < U; ++u)
-#pragma unroll
-          for (int i = 0; i < B; ++i)
-#pragma unroll
-            for (int jj = 0; jj < B; ++jj) {
-              if constexpr (sizeof(T) == 8)
-                acc[q][i] = fma((double)a[u][i * B + jj], (double)xv[u][jj], acc[q][i]);
-              else
-                acc[q][i] = fmaf((float)a[u][i * B + jj], (float)xv[u][jj], acc[q][i]);
-            }
-      }
-    }
-#pragma unroll
-    for (int q = 0; q < R; ++q) {
-      if (row[q] < 0) continue;
-#pragma unroll
-      for (int i = 0; i < B; ++i) {
-        const double s = (double)group_sum<G>(acc[q][i]);
-        if (lane == 0) y[row[q] * B + i] = s;
-      }
-    }
-  }
-}
-
-// Launch shape.  Group width chosen per matrix by spmv_autotune at set-up,
-// else from the mean row length (FC_SPMV_GROUP overrides both); the PCG
-// variant uses one tile per workgroup unless
-// FC_SPMV_FUSED_GRID caps the grid (then workgroups loop over tiles).
+// Launch shape.  G lanes per block row: enough lanes that one pass of U
+// blocks per lane (eight scalar blocks, two 3x3 blocks) covers the mean row,
+// rounded up to 8, 16, 32 or 64 (FC_SPMV_GROUP overrides it).  Measured on
+// MI355X this picks the fastest width for both FP64 workloads: 64 for the
+// 3x3 rows of 32^3-cell p = 3 elasticity (about 122 blocks), 8 for the
+// scalar rows of 64^3-cell p = 2 Poisson (about 63).  The PCG variant uses
+// one tile per workgroup unless FC_SPMV_FUSED_GRID caps the grid (then
+// workgroups loop over tiles).
 static int env_int(const char* name, int dflt) {
   const char* e = std::getenv(name);
   return e ? std::atoi(e) : dflt;
 }
 
+int spmv_group_for(const DeviceBsr& A) {
+  const double mean = A.n_rows ? double(A.nnzb) / double(A.n_rows) : 1.0;
+  const int U = A.bdim == 1 ? 8 : 2;
+  const double lanes = mean / U;
+  if (lanes <= 8) return 8;
+  if (lanes <= 16) return 16;
+  if (lanes <= 32) return 32;
+  return 64;
+}
+
 static int group_width(const DeviceBsr& A) {
   static const int forced = env_int("FC_SPMV_GROUP", 0);
   if (forced == 8 || forced == 16 || forced == 32 || forced == 64) return forced;
-  if (A.group) return A.group;
-  const double mean = A.n_rows ? double(A.nnzb) / double(A.n_rows) : 1.0;
-  if (mean < 12) return 8;
-  if (mean < 24) return 16;
-  if (mean < 48) return 32;
-  return 64;
+  return A.group ? A.group : spmv_group_for(A);
 }
 
 static int64_t num_tiles(const DeviceBsr& A) {
@@ -277,8 +176,7 @@ static int64_t fused_grid(const DeviceBsr& A) {
 template <int B, typename T, typename XT>
 static hipError_t spmv_dispatch(const DeviceBsr& A, const T* val, const XT* x,
                                 double* y, hipStream_t s, const CgScalars* sc,
-                                double* partial, const int32_t* rows, int64_t n_list,
-                                const int64_t* vofs) {
+                                double* partial, const int32_t* rows, int64_t n_list) {
   const int G = group_width(A);
   const int64_t n_rows = rows ? n_list : A.n_rows;
   const int64_t nt = (n_rows + 256 / G - 1) / (256 / G);
@@ -286,61 +184,15 @@ static hipError_t spmv_dispatch(const DeviceBsr& A, const T* val, const XT* x,
   const int64_t nb = (partial && !rows) ? fused_grid(A) : nt;
   static const bool lat_allowed = env_int("FC_SPMV_LATTICE", 1) != 0;
   const bool lat = lat_allowed && A.lat.dim > 0;
-  // full FP64 products over shared rows: grouped rows (the groups were
-  // formed for lattice columns only when the lattice is in use)
-  // (full FP64 products over all rows; FP32 products over the FP32 rows of
-  // the mixed product, grouped among those rows)
-  const int32_t* gl = nullptr;
-  int64_t gn = 0;
-  if constexpr (std::is_same<T, double>::value && std::is_same<XT, double>::value) {
-    if (vofs && val == A.vsh && !rows) {
-      gl = A.grp;
-      gn = A.n_grp;
-    }
-  } else if constexpr (std::is_same<T, float>::value && std::is_same<XT, float>::value) {
-    if (vofs && val == A.vsh32 && rows == A.rows_lo) {
-      gl = A.grp_lo;
-      gn = A.n_grp_lo;
-    }
-  }
-  {
-    if (gl && gn > 0 && !partial && lat == (A.lat.dim > 0)) {
-      const int64_t ng = (gn + 256 / G - 1) / (256 / G);
-      dim3 gg((unsigned)ng), bb(256);
-#define FC_SPMV_GRP(GG)                                                                    \
-  case GG:                                                                                 \
-    if (lat)                                                                               \
-      hipLaunchKernelGGL((k_spmv_bsr_grp<B, GG, true, kShareGroup, T, XT>), gg, bb, 0, s,   \
-                         A.rowptr, A.col, val, vofs, gl, gn, x, y, sc, A.lat);              \
-    else                                                                                   \
-      hipLaunchKernelGGL((k_spmv_bsr_grp<B, GG, false, kShareGroup, T, XT>), gg, bb, 0, s,  \
-                         A.rowptr, A.col, val, vofs, gl, gn, x, y, sc, A.lat);              \
-    break;
-      switch (G) {
-        FC_SPMV_GRP(8)
-        FC_SPMV_GRP(16)
-        FC_SPMV_GRP(32)
-        FC_SPMV_GRP(64)
-      }
-#undef FC_SPMV_GRP
-      return hipGetLastError();
-    }
-  }
   dim3 grid((unsigned)nb), block(256);
-#define FC_SPMV_LAUNCH(GG, SH)                                                             \
-  if (lat)                                                                                 \
-    hipLaunchKernelGGL((k_spmv_bsr<B, GG, T, true, XT, SH>), grid, block, 0, s, A.rowptr,   \
-                       A.col, val, x, y, n_rows, sc, partial, rows, A.lat, vofs);          \
-  else                                                                                     \
-    hipLaunchKernelGGL((k_spmv_bsr<B, GG, T, false, XT, SH>), grid, block, 0, s, A.rowptr,  \
-                       A.col, val, x, y, n_rows, sc, partial, rows, A.lat, vofs);
 #define FC_SPMV_CASE(GG)                                                                   \
   case GG:                                                                                 \
-    if (vofs) {                                                                            \
-      FC_SPMV_LAUNCH(GG, true)                                                             \
-    } else {                                                                               \
-      FC_SPMV_LAUNCH(GG, false)                                                            \
-    }                                                                                      \
+    if (lat)                                                                               \
+      hipLaunchKernelGGL((k_spmv_bsr<B, GG, T, true, XT>), grid, block, 0, s, A.rowptr,     \
+                         A.col, val, x, y, n_rows, sc, partial, rows, A.lat);              \
+    else                                                                                   \
+      hipLaunchKernelGGL((k_spmv_bsr<B, GG, T, false, XT>), grid, block, 0, s, A.rowptr,    \
+                         A.col, val, x, y, n_rows, sc, partial, rows, A.lat);              \
     break;
   switch (G) {
     FC_SPMV_CASE(8)
@@ -349,28 +201,23 @@ static hipError_t spmv_dispatch(const DeviceBsr& A, const T* val, const XT* x,
     FC_SPMV_CASE(64)
   }
 #undef FC_SPMV_CASE
-#undef FC_SPMV_LAUNCH
   return hipGetLastError();
 }
 
 template <typename T, typename XT = double>
 static hipError_t spmv_any(const DeviceBsr& A, const T* val, const XT* x, double* y,
                            hipStream_t s, const CgScalars* sc, double* partial,
-                           const int32_t* rows = nullptr, int64_t n_list = 0,
-                           const int64_t* vofs = nullptr) {
+                           const int32_t* rows = nullptr, int64_t n_list = 0) {
   switch (A.bdim) {
-    case 1: return spmv_dispatch<1, T, XT>(A, val, x, y, s, sc, partial, rows, n_list, vofs);
-    case 2: return spmv_dispatch<2, T, XT>(A, val, x, y, s, sc, partial, rows, n_list, vofs);
-    case 3: return spmv_dispatch<3, T, XT>(A, val, x, y, s, sc, partial, rows, n_list, vofs);
+    case 1: return spmv_dispatch<1, T, XT>(A, val, x, y, s, sc, partial, rows, n_list);
+    case 2: return spmv_dispatch<2, T, XT>(A, val, x, y, s, sc, partial, rows, n_list);
+    case 3: return spmv_dispatch<3, T, XT>(A, val, x, y, s, sc, partial, rows, n_list);
   }
   return hipErrorInvalidValue;
 }
 
-// FP64 values: the shared rows when set-up kept them, else the full matrix
-static const double* f64_values(const DeviceBsr& A) { return A.vofs ? A.vsh : A.val; }
-
 hipError_t launch_spmv(const DeviceBsr& A, const double* x, double* y, hipStream_t s) {
-  return spmv_any<double>(A, f64_values(A), x, y, s, nullptr, nullptr, nullptr, 0, A.vofs);
+  return spmv_any<double>(A, A.val, x, y, s, nullptr, nullptr);
 }
 
 int spmv_num_blocks(const DeviceBsr& A) { return (int)fused_grid(A); }
@@ -415,59 +262,19 @@ hipError_t spmv_enable_lattice(DeviceBsr& A, int dim, int n1, int p, hipStream_t
   return e;
 }
 
-// Group width of this matrix: time every width on the matrix itself
-// (x = 0, so only the memory traffic counts) and keep the fastest.
-hipError_t spmv_autotune(DeviceBsr& A, hipStream_t s) {
-  A.group = 0;
-  const int64_t n = A.n_rows * A.bdim;
-  if (n == 0) return hipSuccess;
-  double *x = nullptr, *y = nullptr;
-  hipEvent_t e0 = nullptr, e1 = nullptr;
-  hipError_t err = hipMalloc(&x, n * sizeof(double));
-  if (err == hipSuccess) err = hipMalloc(&y, n * sizeof(double));
-  if (err == hipSuccess) err = hipMemsetAsync(x, 0, n * sizeof(double), s);
-  if (err == hipSuccess) err = hipEventCreate(&e0);
-  if (err == hipSuccess) err = hipEventCreate(&e1);
-  float best = 1e30f;
-  int best_g = 0;
-  for (int G : {8, 16, 32, 64}) {
-    if (err != hipSuccess) break;
-    A.group = G;
-    err = launch_spmv(A, x, y, s);
-    if (err == hipSuccess) err = hipEventRecord(e0, s);
-    for (int r = 0; r < 3 && err == hipSuccess; ++r) err = launch_spmv(A, x, y, s);
-    if (err == hipSuccess) err = hipEventRecord(e1, s);
-    if (err == hipSuccess) err = hipEventSynchronize(e1);
-    float ms = 0.f;
-    if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
-    if (err == hipSuccess && ms < best) {
-      best = ms;
-      best_g = G;
-    }
-  }
-  A.group = err == hipSuccess ? best_g : 0;
-  if (e0) (void)hipEventDestroy(e0);
-  if (e1) (void)hipEventDestroy(e1);
-  if (x) (void)hipFree(x);
-  if (y) (void)hipFree(y);
-  return err;
-}
-
 hipError_t launch_spmv_pq(const DeviceBsr& A, const double* p, double* q, CgScalars* sc,
                           double* partial, hipStream_t s) {
-  return spmv_any<double>(A, f64_values(A), p, q, s, sc, partial, nullptr, 0, A.vofs);
+  return spmv_any<double>(A, A.val, p, q, s, sc, partial);
 }
 
 hipError_t launch_spmv_mixed(const DeviceBsr& A, const double* p, const float* p32, double* q,
                              const CgScalars* sc, hipStream_t s) {
   hipError_t e = hipSuccess;
   if (A.n_hi > 0 &&
-      (e = spmv_any<double>(A, f64_values(A), p, q, s, sc, nullptr, A.rows_hi, A.n_hi,
-                            A.vofs)) != hipSuccess)
+      (e = spmv_any<double>(A, A.val, p, q, s, sc, nullptr, A.rows_hi, A.n_hi)) != hipSuccess)
     return e;
   if (A.n_lo > 0)
-    e = spmv_any<float, float>(A, A.vsh32 ? A.vsh32 : A.val32, p32, q, s, sc, nullptr, A.rows_lo,
-                               A.n_lo, A.vsh32 ? A.vofs : nullptr);
+    e = spmv_any<float, float>(A, A.val32, p32, q, s, sc, nullptr, A.rows_lo, A.n_lo);
   return e;
 }
 

@@ -65,10 +65,9 @@ struct StageRows {
 // chunks of stored rows are loaded with coalesced non-temporal loads, every
 // thread its own entry, written to LDS, and the rotated entries are read
 // back from LDS, so HBM and L2 see each stored entry exactly once.  rB holds
-// the block's gathered right-hand side (m entries, in LDS).
-// kNT: stream the stored entries non-temporally (each is read once per
-// product); shared copies are read through the caches instead.
-template <typename T, typename RB, bool kNT = true>
+// the block's gathered right-hand side (m entries, in LDS).  The stored
+// entries are streamed non-temporally (each is read once per product).
+template <typename T, typename RB>
 __device__ __forceinline__ double sym_block_staged(const T* __restrict__ Qb, const RB* rB,
                                                    int m, int i,
                                                    T (*tile)[256]) {
@@ -85,7 +84,7 @@ __device__ __forceinline__ double sym_block_staged(const T* __restrict__ Qb, con
     for (int kk = 0; kk < kStageRows; ++kk) {
       const int k = k0 + kk;
       const T* src = Qb + (int64_t)k * m + i;
-      v[kk] = (act && k <= h) ? (kNT ? __builtin_nontemporal_load(src) : *src) : T(0);
+      v[kk] = (act && k <= h) ? __builtin_nontemporal_load(src) : T(0);
     }
     __syncthreads();   // previous chunk's rotated reads are done
 #pragma unroll
@@ -108,63 +107,6 @@ __device__ __forceinline__ double sym_block_staged(const T* __restrict__ Qb, con
     }
   }
   return (double)acc0 + (double)acc1;
-}
-
-// The same product for R right-hand sides that share one block (R blocks
-// reading one stored copy): every chunk of stored rows is loaded once and
-// applied to all R; each right-hand side keeps the accumulation order of
-// sym_block_staged, so out[q] is bitwise that routine's result.  Right-hand
-// sides with use[q] false are skipped.
-template <typename T, typename RB, int R>
-__device__ __forceinline__ void sym_block_staged_multi(const T* __restrict__ Qb,
-                                                       const RB (*rB)[256], const bool* use,
-                                                       int m, int i, T (*tile)[256],
-                                                       double* out) {
-  using A = typename Acc<T>::type;
-  constexpr int kStageRows = StageRows<T>::value;
-  const bool act = i < m;
-  const int h = m / 2;
-  const bool even = (m & 1) == 0;
-  A acc0[R], acc1[R];
-#pragma unroll
-  for (int q = 0; q < R; ++q) acc0[q] = acc1[q] = 0;
-  int ip = i, im = i;
-  for (int k0 = 0; k0 <= h; k0 += kStageRows) {
-    T v[kStageRows];
-#pragma unroll
-    for (int kk = 0; kk < kStageRows; ++kk) {
-      const int k = k0 + kk;
-      v[kk] = (act && k <= h) ? Qb[(int64_t)k * m + i] : T(0);
-    }
-    __syncthreads();   // previous chunk's rotated reads are done
-#pragma unroll
-    for (int kk = 0; kk < kStageRows; ++kk) tile[kk][i] = v[kk];
-    __syncthreads();
-    if (act) {
-#pragma unroll
-      for (int kk = 0; kk < kStageRows; ++kk) {
-        const int k = k0 + kk;
-        if (k > h) break;
-        if (k == 0) {
-#pragma unroll
-          for (int q = 0; q < R; ++q)
-            if (use[q]) acc0[q] = madd<A>(v[kk], rB[q][i], acc0[q]);
-          continue;
-        }
-        ip = (ip + 1 == m) ? 0 : ip + 1;
-        im = (im == 0) ? m - 1 : im - 1;
-        const T w = tile[kk][im];
-#pragma unroll
-        for (int q = 0; q < R; ++q) {
-          if (!use[q]) continue;
-          acc0[q] = madd<A>(v[kk], rB[q][ip], acc0[q]);
-          if (!(even && k == h)) acc1[q] = madd<A>(w, rB[q][im], acc1[q]);
-        }
-      }
-    }
-  }
-#pragma unroll
-  for (int q = 0; q < R; ++q) out[q] = (double)acc0[q] + (double)acc1[q];
 }
 
 // Wrapped-diagonal symmetric product for one block row i (0 <= i < m).

@@ -82,75 +82,3 @@ def test_host_assembly_rejects_bad_description():
     with pytest.raises(fc.FcError) as ei:
         fc.HostSystem(d)
     assert ei.value.status == 1
-
-
-@pytest.mark.parametrize("desc", [
-    lambda: fcgen.disk_poisson_2d(0),
-    lambda: fcgen.porous_elasticity_3d(seed=3, n=4, p=2, n_voids=3, rmin=0.06, rmax=0.12),
-    lambda: fcgen.custom(3, 4, 2, "elasticity", 1e-8, shapes=[], clamp_zmin=True),
-])
-def test_shared_rows_reproduce_every_row(desc):
-    """Rows kept once by the library: every block row read through its
-    offset gives back its own values bit for bit, and the number of kept
-    rows equals the number of distinct value sequences (grouped here by
-    their bytes, independently of the library's hashing)."""
-    h = fc.HostSystem(desc())
-    e = h.export()
-    sh = h.share()
-    rp, bd = e["rowptr"], e["bsr_dim"]
-    val = e["val"].reshape(-1, bd * bd)
-    distinct = set()
-    for r in range(rp.size - 1):
-        L = rp[r + 1] - rp[r]
-        mine = val[rp[r]:rp[r + 1]]                           # [L, bd*bd], block-major
-        got = sh["vals"][sh["ofs"][r]: sh["ofs"][r] + L * bd * bd].reshape(bd * bd, L).T
-        assert got.tobytes() == mine.tobytes(), r
-        distinct.add(mine.T.tobytes())
-    assert sh["distinct_rows"] == len(distinct)
-    assert sh["vals"].size == sum(len(b) // 8 for b in distinct)
-
-
-def _box_shape(row, dim, n1, p):
-    """Extent of a row node's columns per direction: a vertex function
-    (index a multiple of p) meets the cells on both sides of its vertex, an
-    interior function only its own cell."""
-    shape = []
-    for _ in range(dim):
-        g = row % n1
-        row //= n1
-        shape.append(min(n1 - 1, g + p) - max(0, g - p) + 1 if g % p == 0 else p + 1)
-    return tuple(shape)
-
-
-@pytest.mark.parametrize("desc", [
-    lambda: fcgen.disk_poisson_2d(0),
-    lambda: fcgen.porous_elasticity_3d(seed=3, n=4, p=2, n_voids=3, rmin=0.06, rmax=0.12),
-    lambda: fcgen.custom(3, 4, 3, "elasticity", 1e-8, shapes=[], clamp_zmin=True),
-])
-def test_row_groups_cover_every_row_once(desc):
-    """The grouped products write exactly the rows their groups name: every
-    block row must appear in exactly one group, and the rows of a group must
-    have bitwise-equal values and one lattice box shape."""
-    d = desc()
-    h = fc.HostSystem(d)
-    e = h.export()
-    groups = h.row_groups()
-    rp, bd = e["rowptr"], e["bsr_dim"]
-    nr = rp.size - 1
-    assert groups.shape[0] > 0 and groups.shape[1] == 4
-    rows = groups[groups >= 0]
-    np.testing.assert_array_equal(np.sort(rows), np.arange(nr))
-    # -1 only pads the tail of a group
-    for g in groups:
-        k = int(np.sum(g >= 0))
-        assert k >= 1 and np.all(g[:k] >= 0) and np.all(g[k:] == -1)
-    assert np.any(np.sum(groups >= 0, axis=1) > 1)
-    val = e["val"].reshape(-1, bd * bd)
-    n1 = d["p"] * d["n"] + 1
-    for g in groups:
-        g = g[g >= 0]
-        ref = val[rp[g[0]]:rp[g[0] + 1]].tobytes()
-        shape = _box_shape(int(g[0]), d["dim"], n1, d["p"])
-        for r in g[1:]:
-            assert val[rp[r]:rp[r + 1]].tobytes() == ref
-            assert _box_shape(int(r), d["dim"], n1, d["p"]) == shape
