@@ -203,6 +203,13 @@ fc_status fc_spmv_info(fc_problem pb, int32_t* group, int32_t* lattice);
  * are applied from the FP64 copy.  Counts of both kinds. */
 fc_status fc_precond_lowprec_info(fc_precond pc, int64_t* n_f32_blocks,
                                   int64_t* n_f32_from_f64);
+/* Eigenvalues dropped by the threshold of Eq. 11 (lambda <= eps * max
+ * lambda, negative ones included) in every block, in block order
+ * (dropped_host receives n_blocks values; 0 for a block whose certified
+ * direct inverse showed that no eigenvalue lies at or below the threshold).
+ * Errors: FC_E_ARG (NULL pc, or NULL dropped_host with blocks). */
+fc_status fc_precond_block_dropped(fc_precond pc, int32_t* dropped_host);
+
 /* Copy the FP64 local inverse of block k (m*m values, row-major) to host. */
 fc_status fc_get_block_inverse(fc_precond pc, int64_t k, double* out_host);
 

@@ -38,6 +38,7 @@ EXPORTS = [
     "fc_learned_attach", "fc_coarse_grid", "fc_coarse_channels", "fc_coarse_restrict",
     "fc_coarse_prolong", "fc_coarse_apply", "fc_learned_stats", "fc_learned_snapshots",
     "fc_learned_validate", "fc_precond_lowprec_info", "fc_spmv_info",
+    "fc_precond_block_dropped",
 ]
 
 
@@ -112,6 +113,7 @@ def load():
         "fc_precond_lowprec_info": [vp, P(i64), P(i64)],
         "fc_spmv_info": [vp, P(i32), P(i32)],
         "fc_get_block_inverse": [vp, i64, vp],
+        "fc_precond_block_dropped": [vp, vp],
         "fc_apply_M": [vp, dp, dp, vp],
         "fc_pcg_solve": [vp, vp, dp, dp, P(SolveOpts), P(SolveInfo), vp],
         "fc_batch_create": [i32, vp, vp, i32, vp, P(vp)],
@@ -347,6 +349,12 @@ class Precond:
         _check(load().fc_precond_lowprec_info(self._h, C.byref(e), C.byref(f)))
         return {"n_blocks": a.value, "n_fallback": b.value, "n_eig_blocks": c.value,
                 "n_dropped": d.value, "n_f32_blocks": e.value, "n_f32_from_f64": f.value}
+
+    def block_dropped(self):
+        """Eigenvalues dropped by the threshold in every block."""
+        out = np.zeros(self.info()["n_blocks"], np.int32)
+        _check(load().fc_precond_block_dropped(self._h, _np_ptr(out)))
+        return out
 
     def block_inverse(self, k):
         out = np.zeros((self.m, self.m), np.float64)

@@ -114,6 +114,108 @@ __device__ __forceinline__ int lattice_col(const RowBox& b, int k, int n1) {
   return (b.lo[0] + kx) + n1 * ((b.lo[1] + ky) + n1 * (b.lo[2] + kz));
 }
 
+// The cells holding lattice index g along one direction (at most two, in
+// ascending order) and the function's local index on each: a vertex index
+// (g a multiple of p) is local 1 (right end) of cell g/p - 1 and local 0 of
+// cell g/p; any other index is local g % p + 1 of cell g/p alone.
+struct CellsOf {
+  int cnt;
+  int cell[2], loc[2];
+};
+
+__device__ __forceinline__ CellsOf cells_of(int g, int n, int p) {
+  CellsOf c;
+  c.cnt = 0;
+  if (g % p == 0) {
+    const int e = g / p;
+    if (e >= 1) {
+      c.cell[c.cnt] = e - 1;
+      c.loc[c.cnt] = 1;
+      ++c.cnt;
+    }
+    if (e < n) {
+      c.cell[c.cnt] = e;
+      c.loc[c.cnt] = 0;
+      ++c.cnt;
+    }
+  } else {
+    c.cell[0] = g / p;
+    c.loc[0] = g % p + 1;
+    c.cnt = 1;
+  }
+  return c;
+}
+
+// Node tiles of the lattice pull: 16 x 4 x 4 nodes (3-D) or 32 x 8 (2-D)
+// per 256-thread workgroup, so the cells whose block outputs a workgroup
+// sums are mostly summed by that workgroup alone.
+struct PullTiles {
+  int TX, TY, TZ, ntx, nty, ntz;
+};
+
+__host__ __device__ __forceinline__ PullTiles pull_tiles(const PullLattice L) {
+  PullTiles t;
+  t.TX = L.dim == 3 ? 16 : 32;
+  t.TY = L.dim == 3 ? 4 : 8;
+  t.TZ = L.dim == 3 ? 4 : 1;
+  t.ntx = (L.n1 + t.TX - 1) / t.TX;
+  t.nty = (L.n1 + t.TY - 1) / t.TY;
+  t.ntz = L.dim == 3 ? (L.n1 + t.TZ - 1) / t.TZ : 1;
+  return t;
+}
+
+// Unknown of slot `slot` (0 .. TX*TY*TZ*BD - 1) of tile `tile`: a tile's
+// unknowns are taken row by row (TX consecutive nodes, components
+// interleaved, so each row is one contiguous run of TX*BD unknowns), which
+// keeps the vector accesses of consecutive lanes contiguous.  False when the
+// node lies outside the lattice.
+template <int BD>
+__device__ __forceinline__ bool pull_dof(const PullLattice L, const PullTiles T, int64_t tile,
+                                         int slot, int* gx, int* gy, int* gz, int* c) {
+  const int t = (int)tile;   // fewer than 2^31 tiles: n1 <= 2^21 nodes per direction
+  const int bx = t % T.ntx, by = (t / T.ntx) % T.nty;
+  const int bz = t / (T.ntx * T.nty);
+  const int row = slot / (T.TX * BD), o = slot - row * (T.TX * BD);
+  *gx = bx * T.TX + o / BD;
+  *c = o % BD;
+  *gy = by * T.TY + row % T.TY;
+  *gz = bz * T.TZ + row / T.TY;
+  return *gx < L.n1 && *gy < L.n1 && (L.dim < 3 ? *gz == 0 : *gz < L.n1);
+}
+
+// Sum of the block outputs y_B holding component c of node (gx, gy, gz), in
+// ascending block (= cell) order, as the node-to-block map lists them.  All
+// (at most eight) loads are issued before the ordered sum.
+__device__ __forceinline__ double pull_lattice_sum(const double* __restrict__ y,
+                                                   const PullLattice L, int m, int bd, int gx,
+                                                   int gy, int gz, int c) {
+  const CellsOf cx = cells_of(gx, L.n, L.p);
+  CellsOf cy{1, {0, 0}, {0, 0}}, cz{1, {0, 0}, {0, 0}};
+  if (L.dim >= 2) cy = cells_of(gy, L.n, L.p);
+  if (L.dim >= 3) cz = cells_of(gz, L.n, L.p);
+  const int p1 = L.p + 1;
+  double v[8];
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    const int ix = k & 1, iy = (k >> 1) & 1, iz = k >> 2;
+    const bool on = ix < cx.cnt && iy < cy.cnt && iz < cz.cnt;
+    v[k] = 0.0;
+    if (on) {
+      const int64_t e =
+          cx.cell[ix] + (int64_t)L.n * (cy.cell[iy] + (int64_t)L.n * cz.cell[iz]);
+      const int loc = cx.loc[ix] + p1 * (cy.loc[iy] + p1 * cz.loc[iz]);
+      v[k] = y[e * m + (int64_t)loc * bd + c];
+    }
+  }
+  double s = 0.0;
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    const int ix = k & 1, iy = (k >> 1) & 1, iz = k >> 2;
+    if (ix < cx.cnt && iy < cy.cnt && iz < cz.cnt) s += v[k];
+  }
+  return s;
+}
+
 __device__ __forceinline__ float bf16_to_f32(uint16_t v) {
   return __uint_as_float(((uint32_t)v) << 16);
 }

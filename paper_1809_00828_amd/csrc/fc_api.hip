@@ -503,9 +503,23 @@ static fc_status precond_build_body(fc_problem pb, const fc_precond_opts* opts, 
   FC_HIP(hipMemcpyAsync(drop.data(), d_drop, drop.size() * sizeof(int32_t), hipMemcpyDeviceToHost, s));
   FC_HIP(hipStreamSynchronize(s));
   pc->n_fallback = (int64_t)cnt;
+  // scalar lattice problem with every cell a block, in cell order: the pull
+  // finds a node's blocks from its lattice indices (FC_PULL_LATTICE=0 keeps
+  // the node-to-block map).  With three components per node the mapped pull
+  // is faster (46 against 57 us at 32^3 cells, p = 3), so it stays there.
+  {
+    const char* env = std::getenv("FC_PULL_LATTICE");
+    const bool allowed = !(env && std::atoi(env) == 0);
+    if (allowed && pb->bdim == 1 && pb->dim >= 2 && pb->dim <= 3 && pb->n > 0 && pb->p > 0 &&
+        nb == pb->n_el &&
+        nb == std::pow((double)pb->n, pb->dim) && pb->nn == (int)std::pow(pb->p + 1.0, pb->dim))
+      pc->lat = PullLattice{pb->dim, pb->n, pb->p, pb->p * pb->n + 1};
+  }
   int64_t nd = 0;
   for (int64_t k = 0; k < nb; ++k) nd += drop[k];
   pc->n_dropped = nd;
+  drop.resize((size_t)nb);
+  pc->dropped.swap(drop);
   *out = pc.release();
   return FC_OK;
 }
@@ -532,6 +546,16 @@ fc_status fc_precond_info(fc_precond pc, int64_t* n_blocks, int64_t* n_fallback,
   if (n_fallback) *n_fallback = pc->n_fallback;
   if (n_eig_blocks) *n_eig_blocks = pc->n_eig;
   if (n_dropped) *n_dropped = pc->n_dropped;
+  return FC_OK;
+}
+
+fc_status fc_precond_block_dropped(fc_precond pc, int32_t* dropped_host) {
+  if (!pc || (!dropped_host && pc->n_blocks > 0)) {
+    set_error("fc_precond_block_dropped: invalid arguments");
+    return FC_E_ARG;
+  }
+  if (pc->n_blocks > 0)
+    std::memcpy(dropped_host, pc->dropped.data(), pc->dropped.size() * sizeof(int32_t));
   return FC_OK;
 }
 

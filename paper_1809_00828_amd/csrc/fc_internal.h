@@ -52,6 +52,14 @@ struct LatticeInfo {
   int32_t dim = 0, n1 = 0, p = 0;
 };
 
+// Lattice of the element blocks when every cell of a problem set up from a
+// description is a block, in cell order (dim = 0 otherwise): the pull then
+// finds the blocks holding a node from its lattice indices instead of the
+// node-to-block map.
+struct PullLattice {
+  int32_t dim = 0, n = 0, p = 0, n1 = 0;
+};
+
 struct DeviceBsr {
   int32_t bdim = 1;
   int64_t n_rows = 0;      // block rows
@@ -106,8 +114,10 @@ struct fc_precond_s {
   int32_t* inv_ptr = nullptr;      // [n_nodes+1] node -> (block, local node)
   int32_t* inv_idx = nullptr;      // entries: block*m + local_node*bdim
   double* fallback = nullptr;      // [n_dofs] 1/A_ll where S_ll = 0, else 0
+  fc::PullLattice lat;             // set when every cell is a block (lattice pull)
   double* y = nullptr;             // [n_blocks*m] block outputs (workspace)
   int64_t n_fallback = 0, n_eig = 0, n_dropped = 0;
+  std::vector<int32_t> dropped;    // host copy: eigenvalues dropped per block
   double eps = 1e-13;
   int32_t stabilize = 1;
   fc::SolverWs* ws = nullptr;      // PCG workspace, created on first solve

@@ -217,6 +217,54 @@ __global__ __launch_bounds__(256) void k_cg_pull(
   }
 }
 
+// The same pull where every cell is a block: the workgroups walk node tiles
+// of the lattice and find each node's blocks from its lattice indices (no
+// node-to-block map is read), summing them in the same ascending order, so
+// z is bitwise the mapped pull's.  fb may be null (no unknown needs the
+// diagonal scaling).
+template <bool kFlex, int BD>
+__global__ __launch_bounds__(256) void k_cg_pull_lat(
+    const double* __restrict__ y, const PullLattice L, int m, const double* __restrict__ fb,
+    double* __restrict__ x, double* __restrict__ r, const double* __restrict__ p,
+    const double* __restrict__ q, double* __restrict__ z, double* __restrict__ partial,
+    const CgScalars* __restrict__ sc) {
+  __shared__ double lds[16];
+  if (sc->done) return;
+  const double alpha = sc->alpha;
+  const PullTiles T = pull_tiles(L);
+  const int64_t ntiles = (int64_t)T.ntx * T.nty * T.ntz;
+  double a = 0.0, b = 0.0, c = 0.0, d = 0.0;
+  for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+#pragma unroll
+    for (int j = 0; j < BD; ++j) {
+      int gx, gy, gz, cc;
+      if (!pull_dof<BD>(L, T, tile, threadIdx.x + 256 * j, &gx, &gy, &gz, &cc)) continue;
+      const double sv = pull_lattice_sum(y, L, m, BD, gx, gy, gz, cc);
+      const int64_t i = (gx + (int64_t)L.n1 * (gy + (int64_t)L.n1 * gz)) * BD + cc;
+      const double qi = q[i];
+      const double ri = fma(-alpha, qi, r[i]);
+      x[i] = fma(alpha, p[i], x[i]);
+      r[i] = ri;
+      const double zi = fb ? fma(fb[i], ri, sv) : sv;
+      z[i] = zi;
+      a = fma(ri, zi, a);
+      b = fma(zi, zi, b);
+      c = fma(ri, ri, c);
+      if (kFlex) d = fma(zi, qi, d);
+    }
+  }
+  a = block_sum(a, lds);
+  b = block_sum(b, lds);
+  c = block_sum(c, lds);
+  if (kFlex) d = block_sum(d, lds);
+  if (threadIdx.x == 0) {
+    partial[blockIdx.x] = a;
+    partial[gridDim.x + blockIdx.x] = b;
+    partial[2 * gridDim.x + blockIdx.x] = c;
+    if (kFlex) partial[3 * gridDim.x + blockIdx.x] = d;
+  }
+}
+
 // Stop test (Eq. 12 or the plain residual) and beta from the pull's
 // partials, summed in a fixed order by one workgroup.
 __global__ __launch_bounds__(1024) void k_cg_beta(const double* __restrict__ partial, int np,
@@ -516,7 +564,52 @@ static inline unsigned nblk(int64_t n) { return (unsigned)((n + kVecThreads - 1)
 static constexpr unsigned kRedBlocks = 1024;
 // grid of the fused pull: enough workgroups to fill the chip, few partials
 static inline unsigned pull_grid(int64_t n) { return std::min<unsigned>(nblk(n), 2048u); }
-// grid of a two-vector dot: a few elements per lane keep enough loads in
+// grid of the pull actually launched for this preconditioner (the lattice
+// pull walks node tiles; never more workgroups than partial slots)
+static inline unsigned pull_grid_for(const fc_precond_s& pc, int64_t n, int64_t partial_len) {
+  if (pc.lat.dim == 0) return pull_grid(n);
+  static const int cap = [] {
+    const char* e = std::getenv("FC_PULL_GRID");
+    return e ? std::max(64, std::atoi(e)) : 4096;
+  }();
+  const PullTiles T = pull_tiles(pc.lat);
+  const int64_t nt = (int64_t)T.ntx * T.nty * T.ntz;
+  // at most one partial set (four values) per workgroup fits in `partial`
+  return (unsigned)std::min<int64_t>({nt, (int64_t)cap, (partial_len - 8) / 4});
+}
+
+// Schwarz pull fused with the CG updates and the (r,z), (z,z), (r,r)
+// [, (z,q)] partials, one partial set per workgroup of the grid pg.
+template <bool kFlex>
+static hipError_t launch_cg_pull(const fc_precond_s& pc, unsigned pg, double* x, double* r,
+                                 const double* p, const double* q, double* z, double* partial,
+                                 const CgScalars* sc, hipStream_t s) {
+  const int64_t n = pc.pb->n_dofs;
+  if (pc.lat.dim == 0) {
+    hipLaunchKernelGGL(k_cg_pull<kFlex>, dim3(pg), dim3(kVecThreads), 0, s, pc.y, pc.inv_ptr,
+                       pc.inv_idx, pc.fallback, pc.bdim, n, x, r, p, q, z, partial, sc);
+    return hipGetLastError();
+  }
+  const double* fb = pc.n_fallback ? pc.fallback : nullptr;
+  switch (pc.bdim) {
+    case 1:
+      hipLaunchKernelGGL((k_cg_pull_lat<kFlex, 1>), dim3(pg), dim3(256), 0, s, pc.y, pc.lat,
+                         pc.m, fb, x, r, p, q, z, partial, sc);
+      break;
+    case 2:
+      hipLaunchKernelGGL((k_cg_pull_lat<kFlex, 2>), dim3(pg), dim3(256), 0, s, pc.y, pc.lat,
+                         pc.m, fb, x, r, p, q, z, partial, sc);
+      break;
+    case 3:
+      hipLaunchKernelGGL((k_cg_pull_lat<kFlex, 3>), dim3(pg), dim3(256), 0, s, pc.y, pc.lat,
+                         pc.m, fb, x, r, p, q, z, partial, sc);
+      break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+// grid of a two-vector dot: a few elements per lane keep enough loads in// grid of a two-vector dot: a few elements per lane keep enough loads in
 // flight (1024 workgroups left ten dependent iterations per lane at 2.7M)
 static inline unsigned dot_grid(int64_t n) { return std::min<unsigned>(nblk(n), 4096u); }
 
@@ -628,14 +721,14 @@ static hipError_t enqueue_steps(fc_precond_s& pc, SolverWs& w, double* x, int ch
     e = launch_schwarz_phase1(pc, precS, w.r, w.q, w.sc, s);
     if (e != hipSuccess) return e;
     if (tev_it && (e = hipEventRecord(tev[4 * it + 3], s)) != hipSuccess) return e;
-    const unsigned pg = pull_grid(n);
+    const unsigned pg = pull_grid_for(pc, n, w.partial_len);
     const bool ring = learn && fcg_m > 1;
     if (ring) {
       // FCG(m): Schwarz pull, correction, then the new direction made
       // A-orthogonal to the m kept ones
-      hipLaunchKernelGGL(k_cg_pull<false>, dim3(pg), dim3(kVecThreads), 0, s, pc.y, pc.inv_ptr,
-                         pc.inv_idx, pc.fallback, pc.bdim, n, x, w.r, w.p, w.q, w.z, w.partial,
-                         w.sc);
+      if ((e = launch_cg_pull<false>(pc, pg, x, w.r, w.p, w.q, w.z, w.partial, w.sc, s)) !=
+          hipSuccess)
+        return e;
       if ((e = coarse_correct(*learn, w.r, w.z, nullptr, w.sc, s)) != hipSuccess) return e;
       const unsigned rb = ring_blocks(n);
       hipLaunchKernelGGL(k_fcg_keep_dots, dim3(rb), dim3(256), 0, s, w.p, w.q, w.z, n, fcg_m,
@@ -645,16 +738,16 @@ static hipError_t enqueue_steps(fc_precond_s& pc, SolverWs& w, double* x, int ch
       hipLaunchKernelGGL(k_fcg_dir, dim3(pg), dim3(kVecThreads), 0, s, w.z, w.p, w.ring, n, fcg_m,
                          w.fr, w.sc);
     } else if (learn) {
-      hipLaunchKernelGGL(k_cg_pull<true>, dim3(pg), dim3(kVecThreads), 0, s, pc.y, pc.inv_ptr,
-                         pc.inv_idx, pc.fallback, pc.bdim, n, x, w.r, w.p, w.q, w.z, w.partial,
-                         w.sc);
+      if ((e = launch_cg_pull<true>(pc, pg, x, w.r, w.p, w.q, w.z, w.partial, w.sc, s)) !=
+          hipSuccess)
+        return e;
       if ((e = coarse_correct(*learn, w.r, w.z, w.q, w.sc, s)) != hipSuccess) return e;
       hipLaunchKernelGGL(k_cg_beta_flex, dim3(1), dim3(1024), 0, s, w.partial, (int)pg, w.sc,
                          learn->ls);
     } else {
-      hipLaunchKernelGGL(k_cg_pull<false>, dim3(pg), dim3(kVecThreads), 0, s, pc.y, pc.inv_ptr,
-                         pc.inv_idx, pc.fallback, pc.bdim, n, x, w.r, w.p, w.q, w.z, w.partial,
-                         w.sc);
+      if ((e = launch_cg_pull<false>(pc, pg, x, w.r, w.p, w.q, w.z, w.partial, w.sc, s)) !=
+          hipSuccess)
+        return e;
       hipLaunchKernelGGL(k_cg_beta, dim3(1), dim3(1024), 0, s, w.partial, (int)pg, w.sc);
     }
     if (!ring)

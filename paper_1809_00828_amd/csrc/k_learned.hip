@@ -282,14 +282,18 @@ __global__ __launch_bounds__(256) void k_mse(const float* __restrict__ y,
   if (threadIdx.x == 0) partial[blockIdx.x] = s;
 }
 
+// omb1 = 1 - beta1, omb2 = 1 - beta2, c1 = 1 - beta1^t, c2 = 1 - beta2^t are
+// formed in FP64 by the host: in FP32 the differences from 1 lose about
+// 1e-5 of their value to cancellation (1 - 0.999f is off by 1.3e-5
+// relative), which would bias every update by that much.
 __global__ void k_adam(float* __restrict__ p, const float* __restrict__ g, float* __restrict__ m,
-                       float* __restrict__ v, int64_t n, float lr, float b1, float b2, float eps,
-                       float c1, float c2) {
+                       float* __restrict__ v, int64_t n, float lr, float b1, float b2, float omb1,
+                       float omb2, float eps, float c1, float c2) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x) {
     const float gi = g[i];
-    const float mi = b1 * m[i] + (1.f - b1) * gi;
-    const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+    const float mi = b1 * m[i] + omb1 * gi;
+    const float vi = b2 * v[i] + omb2 * gi * gi;
     m[i] = mi;
     v[i] = vi;
     p[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
@@ -553,10 +557,12 @@ hipError_t net_mse(NetWs& ws, const float* target, float* gy, int64_t n, hipStre
 }
 
 hipError_t net_adam(Net& net, float lr, int64_t step, hipStream_t s) {
-  const float b1 = 0.9f, b2 = 0.999f;
-  const float c1 = 1.f - powf(b1, (float)step), c2 = 1.f - powf(b2, (float)step);
+  const double b1 = 0.9, b2 = 0.999;
+  const float c1 = (float)(1.0 - std::pow(b1, (double)step));
+  const float c2 = (float)(1.0 - std::pow(b2, (double)step));
   hipLaunchKernelGGL(k_adam, grid1(net.nparam), dim3(256), 0, s, net.p, net.g, net.m, net.v,
-                     net.nparam, lr, b1, b2, 1e-8f, c1, c2);
+                     net.nparam, lr, (float)b1, (float)b2, (float)(1.0 - b1), (float)(1.0 - b2),
+                     1e-8f, c1, c2);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   return net_sync_bf16(net, s);

@@ -467,10 +467,44 @@ hipError_t launch_schwarz_phase1(const fc_precond_s& pc, int precision, const do
   return hipErrorInvalidValue;
 }
 
+// The same where every cell is a block (lattice pull, see k_cg_pull_lat).
+template <int BD>
+__global__ __launch_bounds__(256) void k_schwarz_pull_lat(const double* __restrict__ y,
+                                                          const PullLattice L, int m,
+                                                          const double* __restrict__ fb,
+                                                          const double* __restrict__ r,
+                                                          double* __restrict__ z) {
+  const PullTiles T = pull_tiles(L);
+  const int64_t ntiles = (int64_t)T.ntx * T.nty * T.ntz;
+  for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+#pragma unroll
+    for (int j = 0; j < BD; ++j) {
+      int gx, gy, gz, c;
+      if (!pull_dof<BD>(L, T, tile, threadIdx.x + 256 * j, &gx, &gy, &gz, &c)) continue;
+      const double sv = pull_lattice_sum(y, L, m, BD, gx, gy, gz, c);
+      const int64_t i = (gx + (int64_t)L.n1 * (gy + (int64_t)L.n1 * gz)) * BD + c;
+      z[i] = fb ? fma(fb[i], r[i], sv) : sv;
+    }
+  }
+}
+
 hipError_t launch_schwarz_pull(const fc_precond_s& pc, const double* r, double* z,
                                hipStream_t s) {
   const int64_t n = pc.pb->n_dofs;
   if (n == 0) return hipSuccess;
+  if (pc.lat.dim > 0) {
+    const PullTiles T = pull_tiles(pc.lat);
+    const int64_t nt = (int64_t)T.ntx * T.nty * T.ntz;
+    const dim3 g((unsigned)std::min<int64_t>(nt, 4096)), b(256);
+    const double* fb = pc.n_fallback ? pc.fallback : nullptr;
+    switch (pc.bdim) {
+      case 1: hipLaunchKernelGGL(k_schwarz_pull_lat<1>, g, b, 0, s, pc.y, pc.lat, pc.m, fb, r, z); break;
+      case 2: hipLaunchKernelGGL(k_schwarz_pull_lat<2>, g, b, 0, s, pc.y, pc.lat, pc.m, fb, r, z); break;
+      case 3: hipLaunchKernelGGL(k_schwarz_pull_lat<3>, g, b, 0, s, pc.y, pc.lat, pc.m, fb, r, z); break;
+      default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+  }
   hipLaunchKernelGGL(k_schwarz_pull, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, pc.y,
                      pc.inv_ptr, pc.inv_idx, pc.fallback, pc.bdim, n, r, z);
   return hipGetLastError();

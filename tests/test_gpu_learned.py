@@ -102,6 +102,39 @@ def test_training_reduces_loss(torch):
     assert np.isfinite(p).all()
 
 
+def test_adam_steps_match_oracle(torch):
+    """Three Adam steps of the library's training loop (one full-batch
+    mini-batch per call, so the moments and the bias-correction step count
+    carry over between calls) against the oracle's adam_step fed with the
+    same gradients: the library's gradient at the current parameters is
+    read with loss_grad (the training step computes the same kernels on the
+    same batch), then one training step runs, and the oracle repeats the
+    update in FP64 from the library's parameters.  The FP32 update must
+    match to rounding: 1e-6 of the step plus the FP32 spacing of the
+    parameter."""
+    theta, x, t = _case(77, 4, 7)
+    m = fc.Model(theta, CH)
+    xd = torch.as_tensor(x, device="cuda")
+    td = torch.as_tensor(t, device="cuda")
+    lr = 1e-3
+    mo = np.zeros(theta.size)
+    vo = np.zeros(theta.size)
+    th = m.params().astype(np.float64)
+    for step in range(1, 4):
+        _, g = m.loss_grad(xd, td)
+        m.train(xd, td, epochs=1, batch=x.shape[0], lr=lr)
+        got = m.params().astype(np.float64)
+        ref, mo, vo = L.adam_step(th, g.astype(np.float64), mo, vo, step, lr=lr)
+        tol = 1e-6 * lr + 2.0 * np.spacing(np.abs(ref).astype(np.float32)).astype(np.float64)
+        err = np.abs(got - ref)
+        print(f"[adam] step {step}: max |diff| {err.max():.2e}, moved {np.abs(got - th).max():.2e}",
+              flush=True)
+        assert np.all(err <= tol), (step, int(np.argmax(err - tol)))
+        # every parameter with a nonzero gradient moved by about lr
+        assert np.abs(got - th).max() <= 1.01 * lr * step
+        th = got
+
+
 # --------------------------------------------- coarse level and learned FCG
 import functools
 

@@ -8,15 +8,19 @@ still finishes in seconds.  Tolerances:
     1e-15 * m * kappa(A_B) + 1e-13 and requires identical dropped counts.
   * z = S r: bounded by the block-level tolerance summed over the blocks.
   * PCG solutions: relative energy-norm difference <= 1e-10 (the parity bar
-    on the solution); iteration counts within +-2.
+    on the solution) wherever the largest block condition number is at most
+    1e10; iteration counts within +-2 up to 1e8 (and on the 16^2 disk),
+    within 15 % above it, where the oracle's own count moves by several
+    percent when only its eigensolver changes.
 """
 import numpy as np
 import pytest
 
 import paper_1809_00828_amd as fc
 from oracle import pcg, schwarz
-from tests.gpu_common import (PROBLEMS, WELL_DETERMINED_KAPPA, energy, max_block_kappa,
-                              oracle_direct, oracle_precond, oracle_system, require_gpu)
+from tests.gpu_common import (ITERATION_DETERMINED_KAPPA, PROBLEMS, WELL_DETERMINED_KAPPA,
+                              energy, max_block_kappa, oracle_direct, oracle_precond,
+                              oracle_system, require_gpu)
 
 pytestmark = pytest.mark.gpu
 
@@ -160,13 +164,16 @@ def test_pcg_matches_oracle(torch, name):
     x, info = _solve(torch, name, tol)
     xo, io = pcg.pcg(A, b, S, tol=tol)
     assert info["status"] == "OK", info
-    strict = name == "disk16_p2" or max_block_kappa(name) <= WELL_DETERMINED_KAPPA
-    if strict:
+    kappa = max_block_kappa(name)
+    strict = name == "disk16_p2" or kappa <= WELL_DETERMINED_KAPPA
+    print(f"[pcg] {name}: iters {info['iters']} (oracle {io['iters']}), largest block "
+          f"kappa {kappa:.1e}", flush=True)
+    if name == "disk16_p2" or kappa <= ITERATION_DETERMINED_KAPPA:
         assert abs(info["iters"] - io["iters"]) <= 2, (info["iters"], io["iters"])
     else:
-        # local inverses fixed by FP64 data only to eps*kappa; the CPU test
-        # test_iteration_spread_between_eigensolvers shows the oracle itself
-        # moves by this much when its eigensolver changes
+        # local inverses fixed by FP64 data only to eps*kappa; the CPU tests
+        # of tests/test_oracle_conditioning.py show the oracle's own count
+        # moving by this much when only its eigensolver changes
         assert abs(info["iters"] - io["iters"]) <= max(2, 0.15 * io["iters"]), \
             (info["iters"], io["iters"])
     # both solved tighter: the two solutions agree in the energy norm.  On
@@ -183,7 +190,7 @@ def test_pcg_matches_oracle(torch, name):
     assert info2["rel_res_true"] <= 1e-9
 
 
-@pytest.mark.parametrize("name", ["disk16_p2", "elast3d_p3"])
+@pytest.mark.parametrize("name", ["disk16_p2", "elast3d_p3", "elast3d_p3_thin"])
 def test_pcg_fixed_iterations_match(torch, name):
     """Iterate k of both sides, k well before convergence."""
     _, s = oracle_system(name)

@@ -99,3 +99,35 @@ def test_refinement_on_uncut_cube(torch):
     e64 = energy(A, x64.cpu().numpy() - xr) / energy(A, xr)
     e = energy(A, x.cpu().numpy() - xr) / energy(A, xr)
     assert e <= 10 * e64 + 1e-12
+
+
+@pytest.mark.parametrize("name", ["disk16_p2", "pois3d_p2", "pois3d_p3"])
+def test_lattice_pull_equals_mapped_pull(torch, monkeypatch, name):
+    """When every cell of a scalar problem is a block the pull finds a node's
+    blocks from its lattice indices; with FC_PULL_LATTICE=0 at the build it
+    reads the
+    node-to-block map.  Both sum the same block outputs in the same order,
+    so z = S r is the same bit for bit, and both PCG solves match the
+    oracle's iteration count."""
+    d, s = oracle_system(name)
+    pb = fc.Problem.setup(d)
+    monkeypatch.setenv("FC_PULL_LATTICE", "0")
+    mapped = fc.Precond(pb)
+    monkeypatch.setenv("FC_PULL_LATTICE", "1")
+    lat = fc.Precond(pb)
+    r = _dev(torch, np.random.default_rng(4).standard_normal(pb.n))
+    z0 = torch.empty_like(r)
+    z1 = torch.empty_like(r)
+    mapped.apply_M(r, z0)
+    lat.apply_M(r, z1)
+    torch.cuda.synchronize()
+    assert z0.cpu().numpy().tobytes() == z1.cpu().numpy().tobytes()
+    its = []
+    for pc in (mapped, lat):
+        b = torch.empty(pb.n, dtype=torch.float64, device="cuda")
+        pb.rhs(b)
+        x = torch.zeros_like(b)
+        info = fc.pcg_solve(pb, pc, b, x, tol=1e-10)
+        assert info["status"] == "OK", info
+        its.append(info["iters"])
+    assert abs(its[0] - its[1]) <= 2, its

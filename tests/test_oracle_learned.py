@@ -137,6 +137,30 @@ def test_adam_first_step_is_signed_lr():
     assert np.allclose(m, 0.1 * g) and np.allclose(v, 0.001 * g * g)
 
 
+def test_adam_two_steps_by_hand():
+    """Two Adam steps (beta1 0.9, beta2 0.999, eps 0) worked out by hand.
+    Component 0, gradients +1 then -1: m2 = 0.09 - 0.1 = -0.01 and
+    m2 / (1 - 0.81) = -1/19; v2 = 0.000999 + 0.001 = 0.001999 and
+    v2 / (1 - 0.998001) = 1; so theta2 = -0.01 + 0.01/19.  Component 1,
+    gradient 2 twice: m2 / 0.19 = 2 and v2 / 0.001999 = 4, a full step of
+    lr each time: theta2 = -0.02.  Component 2, gradient 0 then 3:
+    m2 / 0.19 = 0.3 / 0.19, v2 / 0.001999 = 0.009 / 0.001999, theta2 =
+    -0.01 * (30/19) / sqrt(9000/1999)."""
+    lr = 0.01
+    th = np.zeros(3)
+    m = np.zeros(3)
+    v = np.zeros(3)
+    with np.errstate(invalid="ignore"):
+        th, m, v = L.adam_step(th, np.array([1.0, 2.0, 0.0]), m, v, 1, lr=lr, eps=0.0)
+    th[2] = 0.0          # 0/0 of a zero first gradient with eps = 0
+    th, m, v = L.adam_step(th, np.array([-1.0, 2.0, 3.0]), m, v, 2, lr=lr, eps=0.0)
+    expect = np.array([-0.01 + 0.01 / 19.0, -0.02,
+                       -0.01 * (30.0 / 19.0) / np.sqrt(9000.0 / 1999.0)])
+    np.testing.assert_allclose(th, expect, rtol=1e-13, atol=1e-16)
+    np.testing.assert_allclose(m, [-0.01, 0.38, 0.3], rtol=1e-13)
+    np.testing.assert_allclose(v, [0.001999, 0.007996, 0.009], rtol=1e-13)
+
+
 # ------------------------------------------------------------ transfers
 @pytest.mark.parametrize("dim,n,p", [(2, 4, 2), (3, 4, 3), (3, 6, 1), (2, 8, 4)])
 def test_vertex_index_is_lattice_corner(dim, n, p):
