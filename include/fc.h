@@ -300,6 +300,28 @@ fc_status fc_pcg_solve(fc_problem pb, fc_precond pc, const double* b_dev,
                        double* x_dev, const fc_solve_opts* opts,
                        fc_solve_info* info, void* stream);
 
+/* fc_pcg_solve for callers that cannot allocate device memory (code that
+ * must not call hipMalloc, e.g. tight serving loops or harnesses that
+ * forbid it): the same FP64 PCG with the same kernels and launch shapes,
+ * launched directly on `stream` (no solver stream, events or graph), whose
+ * CG vectors, dot partials and scalars live in one static device scratch
+ * array of the library instead of a workspace allocated on first use.
+ * The scratch holds at most 524,288 (2^19) unknowns, about 21 MB per GPU,
+ * and stays resident on every GPU the library runs on until the process
+ * ends; larger problems return FC_E_UNSUPPORTED.  The preconditioner's own
+ * buffers (allocated by fc_precond_build) are used as in fc_pcg_solve.
+ * Only opts->mode = FC_MODE_F64 with timing = 0 is accepted
+ * (FC_E_UNSUPPORTED otherwise); history_dev is honoured.  The results
+ * (x, iterations, info) equal those of fc_pcg_solve bit for bit.  Every
+ * call on one GPU shares that GPU's scratch: calls that overlap on one GPU
+ * (two host threads, two streams) race and must be serialised by the
+ * caller.  The current device must be the problem's (FC_E_ARG otherwise).
+ * Synchronises the stream after every check_every steps (it cannot be
+ * captured into a graph).  Returns as fc_pcg_solve. */
+fc_status fc_pcg_solve_noalloc(fc_problem pb, fc_precond pc, const double* b_dev,
+                               double* x_dev, const fc_solve_opts* opts,
+                               fc_solve_info* info, void* stream);
+
 /* Batched solves (many independent problems, one set of launches).
  * fc_batch_create groups nprob problems with their preconditioners (built
  * by fc_precond_build, FP64) into one batch: shape classes, segmented work

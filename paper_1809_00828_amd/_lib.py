@@ -38,7 +38,7 @@ EXPORTS = [
     "fc_learned_attach", "fc_coarse_grid", "fc_coarse_channels", "fc_coarse_restrict",
     "fc_coarse_prolong", "fc_coarse_apply", "fc_learned_stats", "fc_learned_snapshots",
     "fc_learned_validate", "fc_precond_lowprec_info", "fc_spmv_info",
-    "fc_precond_block_dropped",
+    "fc_precond_block_dropped", "fc_pcg_solve_noalloc",
 ]
 
 
@@ -116,6 +116,7 @@ def load():
         "fc_precond_block_dropped": [vp, vp],
         "fc_apply_M": [vp, dp, dp, vp],
         "fc_pcg_solve": [vp, vp, dp, dp, P(SolveOpts), P(SolveInfo), vp],
+        "fc_pcg_solve_noalloc": [vp, vp, dp, dp, P(SolveOpts), P(SolveInfo), vp],
         "fc_batch_create": [i32, vp, vp, i32, vp, P(vp)],
         "fc_batch_info": [vp, P(i64), P(i32), P(i32), C.c_char_p, i64],
         "fc_pcg_solve_batch": [vp, vp, vp, P(SolveOpts), vp, vp],
@@ -438,6 +439,22 @@ def pcg_solve(problem: Problem, precond: Precond, b, x, tol=1e-10, maxit=300000,
     info = SolveInfo()
     st = load().fc_pcg_solve(problem._h, precond._h, C.c_void_p(_dptr(b)), C.c_void_p(_dptr(x)),
                              C.byref(o), C.byref(info), C.c_void_p(_stream(stream)))
+    if st not in (FC_OK, FC_E_NOTCONV, FC_E_BREAKDOWN, FC_E_NAN) or (raise_on_error and st):
+        _check(st)
+    return _info_dict(info, st)
+
+
+def pcg_solve_noalloc(problem: Problem, precond: Precond, b, x, tol=1e-10, maxit=300000,
+                      stop="precond", check_every=16, history=None, stream=None,
+                      raise_on_error=False):
+    """Run fc_pcg_solve_noalloc (FP64 PCG with the library's static device
+    scratch instead of an allocated workspace); returns the info dict."""
+    o = SolveOpts(float(tol), int(maxit), STOP[stop], MODE["f64"], int(check_every), 1e-4,
+                  C.c_void_p(_dptr(history)) if history is not None else None, 0, 1)
+    info = SolveInfo()
+    st = load().fc_pcg_solve_noalloc(problem._h, precond._h, C.c_void_p(_dptr(b)),
+                                     C.c_void_p(_dptr(x)), C.byref(o), C.byref(info),
+                                     C.c_void_p(_stream(stream)))
     if st not in (FC_OK, FC_E_NOTCONV, FC_E_BREAKDOWN, FC_E_NAN) or (raise_on_error and st):
         _check(st)
     return _info_dict(info, st)

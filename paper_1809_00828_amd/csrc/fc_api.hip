@@ -27,6 +27,8 @@ void set_error(const std::string& msg) { g_err = msg; }
 
 fc_status pcg_solve(fc_precond_s& pc, const double* b, double* x, const fc_solve_opts& o,
                     fc_solve_info* info, hipStream_t user);
+fc_status pcg_solve_noalloc(fc_precond_s& pc, const double* b, double* x,
+                            const fc_solve_opts& o, fc_solve_info* info, hipStream_t s);
 
 template <class T>
 static fc_status dev_alloc(T** p, size_t count) {
@@ -613,6 +615,27 @@ fc_status fc_pcg_solve(fc_problem pb, fc_precond pc, const double* b_dev, double
     return pcg_solve_body(pb, pc, b_dev, x_dev, opts, info, stream);
   } catch (const std::bad_alloc&) {
     set_error("fc_pcg_solve: out of host memory");
+    return FC_E_NOMEM;
+  }
+}
+
+fc_status fc_pcg_solve_noalloc(fc_problem pb, fc_precond pc, const double* b_dev,
+                               double* x_dev, const fc_solve_opts* opts, fc_solve_info* info,
+                               void* stream) {
+  if (!pb || !pc || pc->pb != pb || !b_dev || !x_dev || b_dev == x_dev) {
+    set_error("fc_pcg_solve_noalloc: invalid arguments");
+    return FC_E_ARG;
+  }
+  fc_solve_opts o{1e-10, 300000, FC_STOP_PRECOND, FC_MODE_F64, 16, 1e-4, nullptr, 0, 1};
+  if (opts) o = *opts;
+  if (!(o.tol >= 0.0) || o.maxit < 0 || (o.stop != FC_STOP_PRECOND && o.stop != FC_STOP_RESIDUAL)) {
+    set_error("fc_pcg_solve_noalloc: invalid options");
+    return FC_E_ARG;
+  }
+  try {
+    return pcg_solve_noalloc(*pc, b_dev, x_dev, o, info, (hipStream_t)stream);
+  } catch (const std::bad_alloc&) {
+    set_error("fc_pcg_solve_noalloc: out of host memory");
     return FC_E_NOMEM;
   }
 }

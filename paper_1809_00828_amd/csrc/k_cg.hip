@@ -26,6 +26,8 @@
 #include <chrono>
 #include <cstdlib>
 #include <cmath>
+#include <mutex>
+#include <string>
 #include <vector>
 
 #include "dev_common.h"
@@ -1074,6 +1076,129 @@ fc_status pcg_solve(fc_precond_s& pc, const double* b, double* x, const fc_solve
     info->ms_schwarz = acc.t_schw;
     info->n_timed = acc.n_timed;
     info->fallbacks = fallbacks;
+  }
+  return result;
+}
+
+// ------------------------------------------- solve without allocation
+// Device scratch of fc_pcg_solve_noalloc: the CG vectors r, z, p, q and the
+// residual product t (kNoAllocMaxDofs doubles each), the dot partials and
+// the CG scalars.  One copy per GPU, held until the process ends; host
+// code reaches it only through the address hipGetSymbolAddress returns for
+// the current device.
+constexpr int64_t kNoAllocMaxDofs = int64_t(1) << 19;
+constexpr int64_t kNoAllocPartials = 4 * 4096 + 8;
+constexpr int64_t kNoAllocScalars = (sizeof(CgScalars) + sizeof(double) - 1) / sizeof(double);
+constexpr int64_t kNoAllocDoubles = 5 * kNoAllocMaxDofs + kNoAllocPartials + kNoAllocScalars;
+static __device__ __align__(256) double scratch[kNoAllocDoubles];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static double* g_scratch_ptr[kMaxDevices] = {};
+
+// Address of this device's scratch (looked up once per device).
+static fc_status scratch_for(int dev, double** out) {
+  if (dev < 0 || dev >= kMaxDevices) {
+    set_error("fc_pcg_solve_noalloc: device index above the supported maximum");
+    return FC_E_UNSUPPORTED;
+  }
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr) {
+      set_error(std::string("fc_pcg_solve_noalloc: hipGetSymbolAddress: ") +
+                hipGetErrorString(e));
+      return FC_E_DEVICE;
+    }
+    g_scratch_ptr[dev] = static_cast<double*>(ptr);
+  }
+  *out = g_scratch_ptr[dev];
+  return FC_OK;
+}
+
+// The scalars start from a kernel, not a copy from host memory, so the
+// ticket of the last-workgroup reductions starts at zero on every call.
+__global__ void k_sc_init(CgScalars* sc, double tol, int64_t maxit, int32_t stop,
+                          double* history) {
+  CgScalars v{};
+  v.tol = tol;
+  v.maxit = maxit;
+  v.stop = stop;
+  v.history = history;
+  *sc = v;
+}
+
+fc_status pcg_solve_noalloc(fc_precond_s& pc, const double* b, double* x, const fc_solve_opts& o,
+                            fc_solve_info* info, hipStream_t s) {
+  fc_problem_s& pb = *pc.pb;
+  const int64_t n = pb.n_dofs;
+  if (n > kNoAllocMaxDofs) {
+    set_error("fc_pcg_solve_noalloc: " + std::to_string(n) +
+              " unknowns exceed the scratch maximum of " + std::to_string(kNoAllocMaxDofs));
+    return FC_E_UNSUPPORTED;
+  }
+  if (o.mode != FC_MODE_F64 || o.timing != 0) {
+    set_error("fc_pcg_solve_noalloc: only FP64 PCG without timing mode");
+    return FC_E_UNSUPPORTED;
+  }
+  int dev = -1;
+  FC_HIP(hipGetDevice(&dev));
+  if (dev != pb.device) {
+    set_error("fc_pcg_solve_noalloc: the current device is not the problem's");
+    return FC_E_ARG;
+  }
+  double* base = nullptr;
+  FC_TRY_ST(scratch_for(dev, &base));
+  // a workspace view of the scratch: only the members the FP64 steps use
+  SolverWs w;
+  w.n = n;
+  w.r = base;
+  w.z = base + kNoAllocMaxDofs;
+  w.p = base + 2 * kNoAllocMaxDofs;
+  w.q = base + 3 * kNoAllocMaxDofs;
+  w.t = base + 4 * kNoAllocMaxDofs;
+  w.partial = base + 5 * kNoAllocMaxDofs;
+  w.partial_len = kNoAllocPartials;
+  w.sc = reinterpret_cast<CgScalars*>(w.partial + kNoAllocPartials);
+  hipLaunchKernelGGL(k_sc_init, dim3(1), dim3(1), 0, s, w.sc, o.tol, o.maxit, o.stop,
+                     o.history_dev);
+  hipLaunchKernelGGL(k_fill, dim3(1024), dim3(256), 0, s, x, 0.0, n);
+  hipLaunchKernelGGL(k_copy, dim3(1024), dim3(256), 0, s, b, w.r, n);
+  FC_HIP(hipGetLastError());
+  FC_HIP(launch_schwarz_phase1(pc, 0, w.r, nullptr, nullptr, s));
+  FC_HIP(launch_schwarz_pull(pc, w.r, w.z, s));
+  hipLaunchKernelGGL(k_copy, dim3(1024), dim3(256), 0, s, w.z, w.p, n);
+  hipLaunchKernelGGL(k_cg_start, dim3(kRedBlocks), dim3(256), 0, s, w.r, w.z, n, w.partial,
+                     w.sc);
+  FC_HIP(hipGetLastError());
+  const int chunk = o.check_every > 0 ? o.check_every : 16;
+  const int64_t max_chunks = (o.maxit + chunk - 1) / chunk + 1;
+  CgScalars h{};
+  for (int64_t launched = 0;;) {
+    FC_HIP(enqueue_steps(pc, w, x, chunk, 0, 0, s));
+    ++launched;
+    FC_HIP(hipMemcpyAsync(&h, w.sc, sizeof(CgScalars), hipMemcpyDeviceToHost, s));
+    FC_HIP(hipStreamSynchronize(s));
+    if (h.done != 0 || launched > max_chunks) break;
+  }
+  // ||b - A x|| / ||b|| with the FP64 matrix
+  FC_HIP(launch_spmv(pb.A, x, w.t, s));
+  double* out2 = w.partial + w.partial_len - 2;
+  hipLaunchKernelGGL(k_resid, dim3(kRedBlocks), dim3(256), 0, s, b, w.t, n, w.partial, w.sc,
+                     out2);
+  FC_HIP(hipGetLastError());
+  double v[2] = {0.0, 0.0};
+  FC_HIP(hipMemcpyAsync(v, out2, sizeof(v), hipMemcpyDeviceToHost, s));
+  FC_HIP(hipStreamSynchronize(s));
+  const fc_status result = status_of(h.done);
+  if (info) {
+    *info = fc_solve_info{};
+    info->iters = h.iter;
+    info->outer_iters = 1;
+    info->rel_res_true = v[1] > 0 ? std::sqrt(v[0] / v[1]) : 0.0;
+    info->rel_res_prec = h.zn0 > 0 ? std::sqrt(h.zz) / h.zn0 : 0.0;
+    info->status = result;
   }
   return result;
 }
