@@ -156,7 +156,8 @@ fc_status fc_apply_A(fc_problem pb, const double* x_dev, double* y_dev,
                      void* stream);
 
 /* Preconditioner options (Algorithm 1 and Sec. 3.2).
- *   eta_bar    blocks only for elements with eta_T <= eta_bar (1.0: all)
+ *   eta_bar    blocks only for elements with eta_T <= eta_bar (1.0: all);
+ *              vertex patches: only patches with a cell of eta_T <= eta_bar
  *   eps        pseudo-inverse threshold: eigenvalues <= eps*max are dropped
  *   stabilize  1 = pseudo-inverse of Eqs. 10-11, 0 = plain inverse (S*)
  *   store_mask FC_STORE_* bits: extra low-precision copies of the block
@@ -164,19 +165,32 @@ fc_status fc_apply_A(fc_problem pb, const double* x_dev, double* y_dev,
  *              scaled inverse with an FP64 list for blocks it would leave
  *              indefinite (fc_precond_lowprec_info), FC_STORE_BF16 the
  *              scaled Cholesky factor (positive semi-definite however
- *              rounded) */
+ *              rounded)
+ *   block_kind FC_BLOCK_ELEMENT: one block per element, all functions
+ *              supported on the cell (Sec. 3.1, the paper's blocks);
+ *              FC_BLOCK_VERTEX_PATCH: one block per vertex of the cell grid,
+ *              all functions supported on the (up to 2^dim) cells around it,
+ *              so every element block lies inside a patch (problems set up
+ *              from a description only; FP64 copy only; at most 192
+ *              unknowns per patch, i.e. (2p+1)^dim * ncomp <= 192; patches
+ *              at the boundary are padded to that size with rows and
+ *              columns of zeros, whose eigenvalues the threshold drops and
+ *              fc_precond_block_dropped does not count) */
 enum { FC_STORE_F64 = 1, FC_STORE_F32 = 2, FC_STORE_BF16 = 4 };
+enum { FC_BLOCK_ELEMENT = 0, FC_BLOCK_VERTEX_PATCH = 1 };
 typedef struct {
   double eta_bar;
   double eps;
   int32_t stabilize;
   uint32_t store_mask;
+  int32_t block_kind;
 } fc_precond_opts;
 
 /* Algorithm 1 on the device: select blocks, extract A_B = R_B A R_B^T,
  * compute the stabilised local inverses in FP64, then the diagonal
  * fallback 1/A_ll for every unknown whose diagonal in S is zero and
- * A_ll > 0.  opts NULL means {1.0, 1e-13, 1, FC_STORE_F64}.
+ * A_ll > 0.  opts NULL means {1.0, 1e-13, 1, FC_STORE_F64,
+ * FC_BLOCK_ELEMENT}.
  * Errors: FC_E_ARG, FC_E_UNSUPPORTED, FC_E_NOMEM, FC_E_DEVICE. */
 fc_status fc_precond_build(fc_problem pb, const fc_precond_opts* opts,
                            void* stream, fc_precond* out);
@@ -203,6 +217,11 @@ fc_status fc_spmv_info(fc_problem pb, int32_t* group, int32_t* lattice);
  * are applied from the FP64 copy.  Counts of both kinds. */
 fc_status fc_precond_lowprec_info(fc_precond pc, int64_t* n_f32_blocks,
                                   int64_t* n_f32_from_f64);
+/* Unknowns per block m (element blocks: the problem's m; vertex patches:
+ * (2p+1)^dim * ncomp, the padded size) and the block kind (FC_BLOCK_*) of a
+ * built preconditioner; either pointer may be NULL. */
+fc_status fc_precond_shape(fc_precond pc, int32_t* m, int32_t* block_kind);
+
 /* Eigenvalues dropped by the threshold of Eq. 11 (lambda <= eps * max
  * lambda, negative ones included) in every block, in block order
  * (dropped_host receives n_blocks values; 0 for a block whose certified

@@ -16,6 +16,8 @@ prolongates each local inverse into S.
 """
 from __future__ import annotations
 
+import itertools
+
 import numpy as np
 import scipy.sparse as sp
 
@@ -23,6 +25,26 @@ import scipy.sparse as sp
 def select_blocks(elem_dofs, eta, eta_bar=1.0):
     """Element blocks of the cells whose eta_T <= eta_bar."""
     return [elem_dofs[i] for i in range(len(eta)) if eta[i] <= eta_bar]
+
+
+def vertex_patch_blocks(desc, elem_dofs, eta, eta_bar=1.0):
+    """Vertex-patch blocks: one per vertex of the cell grid (vertices in
+    order of the first direction fastest), the union of the element blocks
+    of the (up to 2^dim) cells that share the vertex, i.e. every function
+    supported on those cells, in ascending unknown order.  A patch is kept
+    when one of its cells has eta_T <= eta_bar.  Every element block lies
+    inside the patch of each of its vertices, so the functions a cut cell
+    makes nearly dependent stay together, as Sec. 3.1 asks of a block."""
+    n, d = desc["n"], desc["dim"]
+    blocks = []
+    for vid in range((n + 1) ** d):
+        vc = [(vid // (n + 1) ** k) % (n + 1) for k in range(d)]
+        ranges = [range(max(0, c - 1), min(n - 1, c) + 1) for c in vc]
+        cells = [sum(cc[k] * n ** k for k in range(d)) for cc in itertools.product(*ranges)]
+        if min(eta[c] for c in cells) > eta_bar:
+            continue
+        blocks.append(np.unique(np.concatenate([elem_dofs[c] for c in cells])))
+    return blocks
 
 
 def extract_submatrix(A, B):

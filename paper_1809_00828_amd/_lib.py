@@ -24,6 +24,7 @@ DOMAIN = {"voids": 0, "inclusions": 1}
 STORE_F64, STORE_F32, STORE_BF16 = 1, 2, 4
 STOP = {"precond": 0, "residual": 1}
 MODE = {"f64": 0, "ir_f32": 1, "ir_bf16": 2, "s_f32": 3, "s_bf16": 4, "learned": 5}
+BLOCK_KIND = {"element": 0, "vertex_patch": 1}
 
 # every symbol include/fc.h declares
 EXPORTS = [
@@ -38,7 +39,7 @@ EXPORTS = [
     "fc_learned_attach", "fc_coarse_grid", "fc_coarse_channels", "fc_coarse_restrict",
     "fc_coarse_prolong", "fc_coarse_apply", "fc_learned_stats", "fc_learned_snapshots",
     "fc_learned_validate", "fc_precond_lowprec_info", "fc_spmv_info",
-    "fc_precond_block_dropped", "fc_pcg_solve_noalloc",
+    "fc_precond_block_dropped", "fc_pcg_solve_noalloc", "fc_precond_shape",
 ]
 
 
@@ -61,7 +62,7 @@ class ProblemDesc(C.Structure):
 
 class PrecondOpts(C.Structure):
     _fields_ = [("eta_bar", C.c_double), ("eps", C.c_double), ("stabilize", C.c_int32),
-                ("store_mask", C.c_uint32)]
+                ("store_mask", C.c_uint32), ("block_kind", C.c_int32)]
 
 
 class SolveOpts(C.Structure):
@@ -114,6 +115,7 @@ def load():
         "fc_spmv_info": [vp, P(i32), P(i32)],
         "fc_get_block_inverse": [vp, i64, vp],
         "fc_precond_block_dropped": [vp, vp],
+        "fc_precond_shape": [vp, P(i32), P(i32)],
         "fc_apply_M": [vp, dp, dp, vp],
         "fc_pcg_solve": [vp, vp, dp, dp, P(SolveOpts), P(SolveInfo), vp],
         "fc_pcg_solve_noalloc": [vp, vp, dp, dp, P(SolveOpts), P(SolveInfo), vp],
@@ -334,14 +336,18 @@ class Problem:
 
 class Precond:
     def __init__(self, problem: Problem, eta_bar=1.0, eps=1e-13, stabilize=True,
-                 store=STORE_F64, stream=None):
-        o = PrecondOpts(float(eta_bar), float(eps), 1 if stabilize else 0, int(store))
+                 store=STORE_F64, block_kind="element", stream=None):
+        o = PrecondOpts(float(eta_bar), float(eps), 1 if stabilize else 0, int(store),
+                        BLOCK_KIND[block_kind])
         h = C.c_void_p()
         _check(load().fc_precond_build(problem._h, C.byref(o), C.c_void_p(_stream(stream)),
                                        C.byref(h)))
         self._h = h
         self.problem = problem     # keeps the problem alive as long as this
-        self.m = problem.info()["m"]
+        self.block_kind = block_kind
+        m, kind = C.c_int32(), C.c_int32()
+        _check(load().fc_precond_shape(h, C.byref(m), C.byref(kind)))
+        self.m = m.value
 
     def info(self):
         a, b, c, d = C.c_int64(), C.c_int64(), C.c_int64(), C.c_int64()

@@ -216,6 +216,15 @@ __device__ __forceinline__ double pull_lattice_sum(const double* __restrict__ y,
   return s;
 }
 
+// Unknown of row i of a block whose node list starts at nodes[e * nn]
+// (element blocks, or vertex patches whose lists are padded with -1 at the
+// boundary): -1 for a padding row.
+__device__ __forceinline__ int64_t block_dof(const int32_t* __restrict__ nodes, int64_t e, int nn,
+                                             int bd, int i) {
+  const int32_t nd = nodes[e * nn + i / bd];
+  return nd < 0 ? int64_t(-1) : (int64_t)nd * bd + (i % bd);
+}
+
 __device__ __forceinline__ float bf16_to_f32(uint16_t v) {
   return __uint_as_float(((uint32_t)v) << 16);
 }

@@ -71,7 +71,8 @@ static void free_precond(fc_precond_s* pc) {
   if (!pc) return;
   solver_ws_destroy(pc->ws);
   coarse_destroy(pc->coarse);
-  for (void* p : {(void*)pc->block_elem, (void*)pc->P, (void*)pc->Q, (void*)pc->Q32,
+  for (void* p : {(void*)pc->block_elem, (void*)pc->bnodes, (void*)pc->P, (void*)pc->Q,
+                  (void*)pc->Q32,
                   (void*)pc->unsafe32, (void*)pc->unsafe_flag32, (void*)pc->Lbf, (void*)pc->isd,
                   (void*)pc->inv_ptr, (void*)pc->inv_idx, (void*)pc->fallback, (void*)pc->y})
     if (p) (void)hipFree(p);
@@ -341,14 +342,31 @@ static fc_status precond_build_body(fc_problem pb, const fc_precond_opts* opts, 
     return FC_E_ARG;
   }
   *out = nullptr;
-  fc_precond_opts o{1.0, 1e-13, 1, FC_STORE_F64};
+  fc_precond_opts o{1.0, 1e-13, 1, FC_STORE_F64, FC_BLOCK_ELEMENT};
   if (opts) o = *opts;
-  if (!(o.eps >= 0.0) || !(o.eta_bar == o.eta_bar)) {
+  if (!(o.eps >= 0.0) || !(o.eta_bar == o.eta_bar) ||
+      (o.block_kind != FC_BLOCK_ELEMENT && o.block_kind != FC_BLOCK_VERTEX_PATCH)) {
     set_error("fc_precond_build: invalid options");
     return FC_E_ARG;
   }
-  if (pb->m > 192) {
-    set_error("fc_precond_build: element blocks above 192 unknowns are not supported");
+  const bool patch = o.block_kind == FC_BLOCK_VERTEX_PATCH;
+  int pm = pb->m, pnn = pb->nn;
+  if (patch) {
+    if (pb->dim < 1 || pb->n < 1 || pb->p < 1) {
+      set_error("fc_precond_build: vertex patches need a problem set up from a description");
+      return FC_E_UNSUPPORTED;
+    }
+    if (o.store_mask & (FC_STORE_F32 | FC_STORE_BF16)) {
+      set_error("fc_precond_build: vertex patches are built in FP64 only");
+      return FC_E_UNSUPPORTED;
+    }
+    pnn = 1;
+    for (int k = 0; k < pb->dim; ++k) pnn *= 2 * pb->p + 1;
+    pm = pnn * pb->bdim;
+  }
+  if (pm > 192) {
+    set_error(std::string("fc_precond_build: ") + (patch ? "vertex patches" : "element blocks") +
+              " above 192 unknowns are not supported");
     return FC_E_UNSUPPORTED;
   }
   hipStream_t s = (hipStream_t)stream;
@@ -356,17 +374,58 @@ static fc_status precond_build_body(fc_problem pb, const fc_precond_opts* opts, 
                                                            free_precond);
   if (!pc) return FC_E_NOMEM;
   pc->pb = pb;
-  pc->m = pb->m;
-  pc->nn = pb->nn;
+  pc->m = pm;
+  pc->nn = pnn;
   pc->bdim = pb->bdim;
   pc->eps = o.eps;
   pc->stabilize = o.stabilize ? 1 : 0;
+  pc->block_kind = o.block_kind;
   const int m = pc->m, nn = pc->nn, bd = pc->bdim;
 
-  // blocks: elements with eta_T <= eta_bar (Sec. 3.2), element order
-  std::vector<int32_t> blocks;
-  for (int64_t e = 0; e < pb->n_el; ++e)
-    if (pb->eta[e] <= o.eta_bar) blocks.push_back((int32_t)e);
+  // blocks: elements with eta_T <= eta_bar (Sec. 3.2), element order; or
+  // the vertex patches with a cell of eta_T <= eta_bar, vertex order (first
+  // direction fastest), each listing the nodes of its box in lattice order
+  // and padded with -1
+  std::vector<int32_t> blocks, pnodes, pad;
+  if (!patch) {
+    for (int64_t e = 0; e < pb->n_el; ++e)
+      if (pb->eta[e] <= o.eta_bar) blocks.push_back((int32_t)e);
+  } else {
+    const int d = pb->dim, n = pb->n, p = pb->p, n1 = p * n + 1;
+    int64_t nv = 1;
+    for (int k = 0; k < d; ++k) nv *= n + 1;
+    for (int64_t v = 0; v < nv; ++v) {
+      int vc[3] = {0, 0, 0}, clo[3] = {0, 0, 0}, chi[3] = {0, 0, 0};
+      int64_t t = v;
+      for (int k = 0; k < d; ++k) {
+        vc[k] = (int)(t % (n + 1));
+        t /= n + 1;
+        clo[k] = std::max(0, vc[k] - 1);
+        chi[k] = std::min(n - 1, vc[k]);
+      }
+      double emin = 2.0;
+      for (int cz = clo[2]; cz <= chi[2]; ++cz)
+        for (int cy = clo[1]; cy <= chi[1]; ++cy)
+          for (int cx = clo[0]; cx <= chi[0]; ++cx)
+            emin = std::min(emin, pb->eta[cx + (int64_t)n * (cy + (int64_t)n * cz)]);
+      if (!(emin <= o.eta_bar)) continue;
+      int glo[3] = {0, 0, 0}, ghi[3] = {0, 0, 0};
+      for (int k = 0; k < d; ++k) {
+        glo[k] = std::max(0, p * vc[k] - p);
+        ghi[k] = std::min(n1 - 1, p * vc[k] + p);
+      }
+      const size_t start = pnodes.size();
+      for (int gz = glo[2]; gz <= ghi[2]; ++gz)
+        for (int gy = glo[1]; gy <= ghi[1]; ++gy)
+          for (int gx = glo[0]; gx <= ghi[0]; ++gx)
+            pnodes.push_back((int32_t)(gx + (int64_t)n1 * (gy + (int64_t)n1 * gz)));
+      const int used = (int)(pnodes.size() - start);
+      pad.push_back(nn - used);
+      pnodes.resize(start + nn, -1);
+      blocks.push_back((int32_t)(blocks.size()));
+    }
+  }
+  const std::vector<int32_t>& bn = patch ? pnodes : pb->elem_nodes_host;
   pc->n_blocks = (int64_t)blocks.size();
   const int64_t nb = pc->n_blocks;
   if (nb * (int64_t)m >= (int64_t(1) << 31)) {
@@ -375,17 +434,26 @@ static fc_status precond_build_body(fc_problem pb, const fc_precond_opts* opts, 
   }
   // node -> (block, local node) map, blocks in increasing order
   std::vector<int32_t> ptr(pb->n_nodes + 1, 0), idx((size_t)nb * nn);
+  int64_t n_entries = 0;
   for (int64_t k = 0; k < nb; ++k)
-    for (int a = 0; a < nn; ++a) ptr[pb->elem_nodes_host[(int64_t)blocks[k] * nn + a] + 1]++;
+    for (int a = 0; a < nn; ++a) {
+      const int32_t node = bn[(int64_t)blocks[k] * nn + a];
+      if (node >= 0) {
+        ptr[node + 1]++;
+        ++n_entries;
+      }
+    }
   for (int64_t i = 0; i < pb->n_nodes; ++i) ptr[i + 1] += ptr[i];
+  idx.resize((size_t)n_entries);
   {
     std::vector<int32_t> fill(ptr.begin(), ptr.end() - 1);
     for (int64_t k = 0; k < nb; ++k)
       for (int a = 0; a < nn; ++a) {
-        const int32_t node = pb->elem_nodes_host[(int64_t)blocks[k] * nn + a];
-        idx[fill[node]++] = (int32_t)(k * m + a * bd);
+        const int32_t node = bn[(int64_t)blocks[k] * nn + a];
+        if (node >= 0) idx[fill[node]++] = (int32_t)(k * m + a * bd);
       }
   }
+  if (patch) FC_TRY(upload(&pc->bnodes, pnodes.data(), pnodes.size()));
   FC_TRY(upload(&pc->block_elem, blocks.data(), blocks.size()));
   FC_TRY(upload(&pc->inv_ptr, ptr.data(), ptr.size()));
   FC_TRY(upload(&pc->inv_idx, idx.data(), idx.size()));
@@ -512,8 +580,8 @@ static fc_status precond_build_body(fc_problem pb, const fc_precond_opts* opts, 
   {
     const char* env = std::getenv("FC_PULL_LATTICE");
     const bool allowed = !(env && std::atoi(env) == 0);
-    if (allowed && pb->bdim == 1 && pb->dim >= 2 && pb->dim <= 3 && pb->n > 0 && pb->p > 0 &&
-        nb == pb->n_el &&
+    if (allowed && !patch && pb->bdim == 1 && pb->dim >= 2 && pb->dim <= 3 && pb->n > 0 &&
+        pb->p > 0 && nb == pb->n_el &&
         nb == std::pow((double)pb->n, pb->dim) && pb->nn == (int)std::pow(pb->p + 1.0, pb->dim))
       pc->lat = PullLattice{pb->dim, pb->n, pb->p, pb->p * pb->n + 1};
   }
@@ -521,6 +589,16 @@ static fc_status precond_build_body(fc_problem pb, const fc_precond_opts* opts, 
   for (int64_t k = 0; k < nb; ++k) nd += drop[k];
   pc->n_dropped = nd;
   drop.resize((size_t)nb);
+  // the zero rows and columns padding a boundary patch give exactly zero
+  // eigenvalues, which the threshold drops; they are not counted
+  if (patch) {
+    nd = 0;
+    for (int64_t k = 0; k < nb; ++k) {
+      drop[k] -= pad[k] * bd;
+      nd += drop[k];
+    }
+    pc->n_dropped = nd;
+  }
   pc->dropped.swap(drop);
   *out = pc.release();
   return FC_OK;
@@ -548,6 +626,13 @@ fc_status fc_precond_info(fc_precond pc, int64_t* n_blocks, int64_t* n_fallback,
   if (n_fallback) *n_fallback = pc->n_fallback;
   if (n_eig_blocks) *n_eig_blocks = pc->n_eig;
   if (n_dropped) *n_dropped = pc->n_dropped;
+  return FC_OK;
+}
+
+fc_status fc_precond_shape(fc_precond pc, int32_t* m, int32_t* block_kind) {
+  if (!pc) return FC_E_ARG;
+  if (m) *m = pc->m;
+  if (block_kind) *block_kind = pc->block_kind;
   return FC_OK;
 }
 

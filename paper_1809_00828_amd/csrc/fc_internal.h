@@ -102,7 +102,9 @@ struct fc_precond_s {
   fc_problem pb = nullptr;
   int32_t m = 0, nn = 0, bdim = 1;
   int64_t n_blocks = 0;
-  int32_t* block_elem = nullptr;   // [n_blocks] element of each block
+  int32_t block_kind = FC_BLOCK_ELEMENT;
+  int32_t* block_elem = nullptr;   // [n_blocks] element of each block (patch: its index)
+  int32_t* bnodes = nullptr;       // vertex patches: [n_blocks][nn] node lists, -1 padding
   double* P = nullptr;             // [n_blocks*m*m] FP64 local inverses (dense)
   double* Q = nullptr;             // wrapped-diagonal symmetric copy, FP64
   float* Q32 = nullptr;            // optional FP32 wrapped-diagonal copy of D^1/2 P D^1/2
@@ -125,6 +127,12 @@ struct fc_precond_s {
 };
 
 namespace fc {
+
+// Node lists of the preconditioner's blocks: the element lists of the
+// problem, or the patch lists of a vertex-patch preconditioner.
+inline const int32_t* block_nodes(const fc_precond_s& pc) {
+  return pc.bnodes ? pc.bnodes : pc.pb->elem_nodes;
+}
 
 // ---- launchers (each returns hipSuccess or the first launch error) ----
 // y = A x  (and optionally partial dots (x, y) per workgroup)

@@ -576,6 +576,10 @@ extern "C" fc_status fc_batch_create(int32_t nprob, const fc_problem* problems,
       set_error("fc_batch_create: preconditioner without symmetric copy");
       return FC_E_ARG;
     }
+    if (pc->bnodes) {
+      set_error("fc_batch_create: vertex-patch preconditioners are not batched");
+      return FC_E_UNSUPPORTED;
+    }
     BProb& P = B.host[k];
     std::memset(&P, 0, sizeof(P));
     P.rowptr = pb->A.rowptr;

@@ -53,16 +53,16 @@ __global__ __launch_bounds__(256) void k_schwarz_large(
   const double alpha = (sc && q) ? sc->alpha : 0.0;
   const int i = threadIdx.x;
   const int64_t e = block_elem[blk];
-  int64_t dof = 0;
+  int64_t dof = -1;
   if (i < m) {
-    dof = (int64_t)elem_nodes[e * nn + i / bd] * bd + (i % bd);
-    rB[i] = gather_r(r, q, alpha, dof) * (isd ? isd[dof] : 1.0);
+    dof = block_dof(elem_nodes, e, nn, bd, i);
+    rB[i] = dof >= 0 ? gather_r(r, q, alpha, dof) * (isd ? isd[dof] : 1.0) : 0.0;
   }
   __syncthreads();
   if (i >= m) return;
   const T* Pb = P + blk * block_stride;
   const double v = kSym ? sym_row<T>(Pb, rB, m, i) : dense_row<T>(Pb, rB, m, i);
-  y[blk * m + i] = isd ? v * isd[dof] : v;
+  y[blk * m + i] = dof < 0 ? 0.0 : isd ? v * isd[dof] : v;
 }
 
 // m > 64, symmetric layout staged through LDS (sym_block_staged).
@@ -90,14 +90,14 @@ __global__ __launch_bounds__(256) void k_schwarz_sym_staged(
   const int i = threadIdx.x;
   const bool act = i < m;
   const int64_t e = block_elem[blk];
-  int64_t dof = 0;
+  int64_t dof = -1;
   if (act) {
-    dof = (int64_t)elem_nodes[e * nn + i / bd] * bd + (i % bd);
-    rB[i] = (A)(gather_r(r, q, alpha, dof) * (isd ? isd[dof] : 1.0));
+    dof = block_dof(elem_nodes, e, nn, bd, i);
+    rB[i] = dof >= 0 ? (A)(gather_r(r, q, alpha, dof) * (isd ? isd[dof] : 1.0)) : A(0);
   }
   const T* Qb = P + blk * block_stride;
   const double v = sym_block_staged<T, A>(Qb, rB, m, i, tile);
-  if (act) y[blk * m + i] = isd ? v * isd[dof] : v;
+  if (act) y[blk * m + i] = dof < 0 ? 0.0 : isd ? v * isd[dof] : v;
 }
 
 // m <= 64: each wave handles floor(64/m) blocks, one lane per output row.
@@ -116,18 +116,18 @@ __global__ __launch_bounds__(256) void k_schwarz_small(
   const int64_t tile = xcd_remap(blockIdx.x, gridDim.x);
   const int64_t blk = (tile * 4 + w) * bpw + lb;
   const bool active = lb < bpw && blk < n_blocks;
-  int64_t dof = 0;
+  int64_t dof = -1;
   if (active) {
     const int64_t e = block_elem[blk];
-    dof = (int64_t)elem_nodes[e * nn + i / bd] * bd + (i % bd);
-    rB[w][l] = gather_r(r, q, alpha, dof) * (isd ? isd[dof] : 1.0);
+    dof = block_dof(elem_nodes, e, nn, bd, i);
+    rB[w][l] = dof >= 0 ? gather_r(r, q, alpha, dof) * (isd ? isd[dof] : 1.0) : 0.0;
   }
   __syncthreads();
   if (!active) return;
   const double* rb = &rB[w][lb * m];
   const T* Pb = P + blk * block_stride;
   const double v = kSym ? sym_row<T>(Pb, rb, m, i) : dense_row<T>(Pb, rb, m, i);
-  y[blk * m + i] = isd ? v * isd[dof] : v;
+  y[blk * m + i] = dof < 0 ? 0.0 : isd ? v * isd[dof] : v;
 }
 
 // Factored low-precision product y_B = D^{-1/2} Lt (Lt^T (D^{-1/2} r_B)) with
@@ -276,7 +276,7 @@ static hipError_t phase1_chol(const fc_precond_s& pc, const T* L, const double* 
     (void)hipFuncSetAttribute((const void*)k_schwarz_chol_large<T>,
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     hipLaunchKernelGGL(k_schwarz_chol_large<T>, dim3((unsigned)pc.n_blocks), dim3(threads), lds,
-                       s, L, pb.elem_nodes, pc.block_elem, pc.nn, pc.bdim, m, r, q, pc.isd, sc,
+                       s, L, block_nodes(pc), pc.block_elem, pc.nn, pc.bdim, m, r, q, pc.isd, sc,
                        pc.y, pc.n_blocks);
   } else {
     const int bpw = 64 / m;
@@ -286,7 +286,7 @@ static hipError_t phase1_chol(const fc_precond_s& pc, const T* L, const double* 
     (void)hipFuncSetAttribute((const void*)k_schwarz_chol_small<T>,
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     hipLaunchKernelGGL(k_schwarz_chol_small<T>, dim3((unsigned)nwg), dim3(256), lds, s, L,
-                       pb.elem_nodes, pc.block_elem, pc.nn, pc.bdim, m, r, q, pc.isd, sc, pc.y,
+                       block_nodes(pc), pc.block_elem, pc.nn, pc.bdim, m, r, q, pc.isd, sc, pc.y,
                        pc.n_blocks);
   }
   return hipGetLastError();
@@ -329,9 +329,9 @@ __global__ void k_pack_sym(const double* __restrict__ P, T* __restrict__ Q, int 
     double v = P[blk * (int64_t)m * m + (int64_t)i * m + j];
     if (isd) {
       const int64_t e = block_elem[blk];
-      const int64_t di = (int64_t)elem_nodes[e * nn + i / bd] * bd + (i % bd);
-      const int64_t dj = (int64_t)elem_nodes[e * nn + j / bd] * bd + (j % bd);
-      v = v / (isd[di] * isd[dj]);
+      const int64_t di = block_dof(elem_nodes, e, nn, bd, i);
+      const int64_t dj = block_dof(elem_nodes, e, nn, bd, j);
+      v = (di < 0 || dj < 0) ? 0.0 : v / (isd[di] * isd[dj]);
     }
     if constexpr (sizeof(T) == 8) {
       Q[t] = v;
@@ -353,7 +353,7 @@ hipError_t launch_pack_sym(const fc_precond_s& pc, void* Q, int precision, hipSt
   const int m = pc.m;
   if (nb == 0) return hipSuccess;
   dim3 g(8192), b(256);
-  const int32_t* en = pc.pb->elem_nodes;
+  const int32_t* en = block_nodes(pc);
   switch (precision) {
     case 0:
       hipLaunchKernelGGL(k_pack_sym<double>, g, b, 0, s, pc.P, (double*)Q, m, nb, nullptr, en,
@@ -398,19 +398,19 @@ static hipError_t phase1(const fc_precond_s& pc, const T* P, const double* r, co
     const int threads = 64 * ((pc.m + 63) / 64);
     if (kSym && variant)
       hipLaunchKernelGGL((k_schwarz_sym_staged<T>), dim3((unsigned)pc.n_blocks), dim3(threads),
-                         0, s, P, stride, pb.elem_nodes, pc.block_elem, pc.nn, pc.bdim, pc.m, r,
+                         0, s, P, stride, block_nodes(pc), pc.block_elem, pc.nn, pc.bdim, pc.m, r,
                          q, isd, sc, pc.y, pc.n_blocks, nullptr,
                          sizeof(T) == 4 ? pc.unsafe_flag32 : nullptr);
     else
       hipLaunchKernelGGL((k_schwarz_large<T, kSym>), dim3((unsigned)pc.n_blocks), dim3(threads),
-                         0, s, P, stride, pb.elem_nodes, pc.block_elem, pc.nn, pc.bdim, pc.m, r,
+                         0, s, P, stride, block_nodes(pc), pc.block_elem, pc.nn, pc.bdim, pc.m, r,
                          q, isd, sc, pc.y, pc.n_blocks);
   } else {
     const int bpw = 64 / pc.m;
     const int64_t per_wg = 4 * (int64_t)bpw;
     const int64_t nwg = (pc.n_blocks + per_wg - 1) / per_wg;
     hipLaunchKernelGGL((k_schwarz_small<T, kSym>), dim3((unsigned)nwg), dim3(256), 0, s, P, stride,
-                       pb.elem_nodes, pc.block_elem, pc.nn, pc.bdim, pc.m, r, q, isd, sc, pc.y,
+                       block_nodes(pc), pc.block_elem, pc.nn, pc.bdim, pc.m, r, q, isd, sc, pc.y,
                        pc.n_blocks);
   }
   return hipGetLastError();
@@ -430,8 +430,8 @@ __global__ __launch_bounds__(256) void k_schwarz_sym_list(
   const int i = threadIdx.x;
   if (i < m) {
     const int64_t e = block_elem[blk];
-    const int64_t dof = (int64_t)elem_nodes[e * nn + i / bd] * bd + (i % bd);
-    rB[i] = gather_r(r, q, alpha, dof);
+    const int64_t dof = block_dof(elem_nodes, e, nn, bd, i);
+    rB[i] = dof >= 0 ? gather_r(r, q, alpha, dof) : 0.0;
   }
   __syncthreads();
   if (i < m) y[blk * m + i] = sym_row<double>(Q + blk * stride, rB, m, i);
@@ -451,12 +451,12 @@ hipError_t launch_schwarz_phase1(const fc_precond_s& pc, int precision, const do
       if (pc.m > 64)
         hipLaunchKernelGGL((k_schwarz_sym_staged<double>), dim3((unsigned)pc.n_unsafe32),
                            dim3(64 * ((pc.m + 63) / 64)), 0, s, pc.Q, sym_block_stride(pc.m),
-                           pb.elem_nodes, pc.block_elem, pc.nn, pc.bdim, pc.m, r, q, nullptr, sc,
+                           block_nodes(pc), pc.block_elem, pc.nn, pc.bdim, pc.m, r, q, nullptr, sc,
                            pc.y, pc.n_blocks, pc.unsafe32, nullptr);
       else
         hipLaunchKernelGGL(k_schwarz_sym_list, dim3((unsigned)pc.n_unsafe32),
                            dim3(64 * ((pc.m + 63) / 64)), 0, s, pc.Q, sym_block_stride(pc.m),
-                           pc.unsafe32, pb.elem_nodes, pc.block_elem, pc.nn, pc.bdim, pc.m, r, q,
+                           pc.unsafe32, block_nodes(pc), pc.block_elem, pc.nn, pc.bdim, pc.m, r, q,
                            sc, pc.y);
       return hipGetLastError();
     }

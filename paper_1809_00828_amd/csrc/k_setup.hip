@@ -37,6 +37,13 @@ __global__ __launch_bounds__(256) void k_block_extract(
   for (int t = threadIdx.x; t < nn * nn; t += blockDim.x) {
     const int a = t / nn, b = t % nn;
     const int32_t na = en[a], nb = en[b];
+    if (na < 0 || nb < 0) {
+      // padding of a boundary vertex patch: zero rows and columns, whose
+      // zero eigenvalues the threshold of Eq. 11 drops
+      for (int i = 0; i < bd; ++i)
+        for (int j = 0; j < bd; ++j) Ab[(int64_t)(a * bd + i) * m + (b * bd + j)] = 0.0;
+      continue;
+    }
     const int32_t lo = rowptr[na], hi = rowptr[na + 1];
     int32_t l = lo, h = hi - 1, found = -1;
     while (l <= h) {
@@ -415,10 +422,10 @@ hipError_t launch_chol_pack(fc_precond_s& pc, hipStream_t s, int32_t* unsafe) {
 #define FC_CHOL(GR, TT)                                                                     \
   if (unsafe)                                                                               \
     hipLaunchKernelGGL((k_chol_pack<GR, TT, true>), g, dim3(GR * GR), 0, s, pc.P, m, pc.isd, \
-                       pb.elem_nodes, pc.block_elem, pc.nn, pc.bdim, nullptr, unsafe);          \
+                       block_nodes(pc), pc.block_elem, pc.nn, pc.bdim, nullptr, unsafe);       \
   else                                                                                      \
     hipLaunchKernelGGL((k_chol_pack<GR, TT, false>), g, dim3(GR * GR), 0, s, pc.P, m,        \
-                       pc.isd, pb.elem_nodes, pc.block_elem, pc.nn, pc.bdim, pc.Lbf, nullptr)
+                       pc.isd, block_nodes(pc), pc.block_elem, pc.nn, pc.bdim, pc.Lbf, nullptr)
   if (m <= 8) FC_CHOL(8, 1);
   else if (m <= 16) FC_CHOL(8, 2);
   else if (m <= 32) FC_CHOL(8, 4);
@@ -488,7 +495,7 @@ hipError_t launch_block_extract(const fc_problem_s& pb, const fc_precond_s& pc,
                                 hipStream_t s) {
   if (pc.n_blocks == 0) return hipSuccess;
   hipLaunchKernelGGL(k_block_extract, dim3((unsigned)pc.n_blocks), dim3(256), 0, s,
-                     pb.A.rowptr, pb.A.col, pb.A.val, pb.elem_nodes, pc.block_elem,
+                     pb.A.rowptr, pb.A.col, pb.A.val, block_nodes(pc), pc.block_elem,
                      pc.nn, pc.bdim, pc.m, pc.P);
   return hipGetLastError();
 }

@@ -9,6 +9,7 @@ direct solves, CG's conjugacy and monotone energy error, and the paper's
 robustness claim: Schwarz iterations stay bounded as a cut cell shrinks
 while Jacobi's grow (Sec. 3.1, remark; Sec. 5.2).
 """
+import itertools
 import json
 import os
 
@@ -208,3 +209,60 @@ def test_schwarz_robust_where_jacobi_is_not():
     assert max(it_s) <= 1.25 * min(it_s), it_s
     assert it_j[-1] > 3 * it_j[0], it_j
     assert it_j[-1] > 10 * it_s[-1], (it_j, it_s)
+
+
+# ------------------------------------------------------ vertex patches
+def _patch_case(name):
+    import fcgen
+    from oracle import assemble
+    d = {"disk": lambda: fcgen.disk_poisson_2d(0),
+         "cube": lambda: fcgen.porous_poisson_3d(seed=1, n=3, p=2, n_voids=2, rmin=0.1,
+                                                  rmax=0.2)}[name]()
+    return d, assemble.assemble(d)
+
+
+@pytest.mark.parametrize("name", ["disk", "cube"])
+def test_vertex_patches_contain_every_element_block(name):
+    """Every element block lies inside the patch of each of its cell's
+    vertices; interior patches hold (2p+1)^dim functions; a vertex function
+    belongs to 3^dim patches away from the boundary, an interior function
+    of a cell edge or face to fewer (2 per direction where it is not a
+    vertex index): counted here by brute force over the lattice."""
+    d, s = _patch_case(name)
+    n, p, dim = d["n"], d["p"], d["dim"]
+    patches = schwarz.vertex_patch_blocks(d, s["elem_dofs"], s["eta"], 1.0)
+    assert len(patches) == (n + 1) ** dim
+    sets = [set(b.tolist()) for b in patches]
+    for e, B in enumerate(s["elem_dofs"]):
+        cell = [(e // n ** k) % n for k in range(dim)]
+        for corner in itertools.product((0, 1), repeat=dim):
+            vid = sum((cell[k] + corner[k]) * (n + 1) ** k for k in range(dim))
+            assert set(B.tolist()) <= sets[vid]
+    assert max(len(b) for b in patches) == (2 * p + 1) ** dim
+    n1 = p * n + 1
+    count = schwarz.block_overlap(patches, s["A"].shape[0])
+    for node in range(n1 ** dim):
+        g = [(node // n1 ** k) % n1 for k in range(dim)]
+        expect = 1
+        for gk in g:
+            lo, hi = -((-(gk - p)) // p), (gk + p) // p    # vertices v with |gk - p v| <= p
+            expect *= min(hi, n) - max(lo, 0) + 1
+        assert count[node] == expect, (node, g)
+
+
+def test_vertex_patch_pcg_solves_config_1():
+    """Schwarz-PCG with vertex patches on the 16^2-cell disk reaches the
+    direct solution, and, its blocks containing the element blocks, needs
+    no more iterations than element blocks."""
+    d, s = _patch_case("disk")
+    A, b = s["A"], s["b"]
+    Sp, fp = schwarz.compute_preconditioner(A, schwarz.vertex_patch_blocks(
+        d, s["elem_dofs"], s["eta"], 1.0))
+    Se, _ = schwarz.compute_preconditioner(A, schwarz.select_blocks(s["elem_dofs"], s["eta"]))
+    assert fp.size == 0
+    xp, ip = pcg.pcg(A, b, Sp, tol=1e-12)
+    _, ie = pcg.pcg(A, b, Se, tol=1e-12)
+    xr = pcg.direct_solve(A, b)
+    assert ip["status"] == pcg.OK
+    assert pcg.energy_error(A, xr, xp) <= 1e-8
+    assert ip["iters"] <= ie["iters"]
