@@ -250,6 +250,40 @@ def copy_calibration(torch):
     del a, b
 
 
+def net_timing(fc, reps=200):
+    """Network kernels alone: the forward pass the solver runs per iteration
+    (batch 1 on the 33^3 coarse grid of the 64^3-cell problem) and one
+    training step's loss and gradient (batch 8 on the 25^3 coarse grid of
+    the 48^3-cell training problems), widths (8, 16, 32, 32), random
+    weights.  Mean wall time per call over reps calls after a warm-up."""
+    import torch
+    import fcgen
+    ch = (8, 16, 32, 32)
+    model = fc.Model(fcgen.unet_init(ch, 2, seed=1), ch)
+    gen = torch.Generator(device="cuda").manual_seed(5)
+    out = {"widths": list(ch)}
+    for key, B, g in (("forward_b1_33", 1, 33), ("train_b8_25", 8, 25)):
+        x = torch.randn((B, 2, g, g, g), device="cuda", generator=gen)
+        y = torch.empty((B, 1, g, g, g), device="cuda")
+        t = torch.randn((B, 1, g, g, g), device="cuda", generator=gen)
+        n = reps if key.startswith("forward") else reps // 4
+
+        def call():
+            if key.startswith("forward"):
+                model.forward(x, y)
+            else:
+                model.loss_grad(x, t)
+        for _ in range(3):
+            call()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(n):
+            call()
+        torch.cuda.synchronize()
+        out[key + "_ms"] = (time.perf_counter() - t0) / n * 1e3
+    return out
+
+
 def learned_bench(fc, args):
     """Learned coarse correction: a U-Net trained on solver-generated pairs
     from 48^3-cell, p=2 porous Poisson cubes, evaluated inside flexible CG
@@ -259,7 +293,8 @@ def learned_bench(fc, args):
     import fcgen
     from paper_1809_00828_amd import learned as LR
     ch = (8, 16, 32, 32)
-    m = args.learned_fcg_m
+    ms = args.learned_fcg_m
+    m = ms[0]
     t0 = time.perf_counter()
     descs = [fcgen.porous_poisson_3d(1000 + i, n=48, p=2) for i in range(args.learned_train)]
     xin, t, G = LR.training_set(descs, args.learned_pairs // args.learned_train,
@@ -296,6 +331,17 @@ def learned_bench(fc, args):
                       "rel_res_true": info["rel_res_true"]}
         log(f"learned: {name} {info['iters']} iterations, {wall:.0f} ms")
     st = pc.learned_stats()
+    sweep = []
+    for mm in ms[1:]:
+        fc.pcg_solve(pb, pc, b, x, tol=args.tol, stop="residual", mode="learned", fcg_m=mm)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        info = fc.pcg_solve(pb, pc, b, x, tol=args.tol, stop="residual", mode="learned", fcg_m=mm)
+        torch.cuda.synchronize()
+        wall = (time.perf_counter() - t0) * 1e3
+        sweep.append({"fcg_directions": mm, "iters": info["iters"], "time_to_tol_ms": wall,
+                      "ms_per_iter": wall / max(1, info["iters"]), "status": info["status"]})
+        log(f"learned: FCG({mm}) {info['iters']} iterations, {wall:.0f} ms")
     use, ip, il = pc.validate(b, tol=args.tol, fcg_m=m)
     x.zero_()
     torch.cuda.synchronize()
@@ -317,6 +363,8 @@ def learned_bench(fc, args):
                   "loss_first": float(hist[0]), "loss_last": float(hist[-1]),
                   "data_s": t_data, "train_s": t_train},
         "plain": runs["plain"], "learned": runs["learned"],
+        "fcg_sweep": sweep,
+        "network": net_timing(fc),
         "corrections": st,
         "speedup_vs_plain": runs["plain"]["time_to_tol_ms"] / runs["learned"]["time_to_tol_ms"],
         "iteration_ratio": runs["learned"]["iters"] / max(1, runs["plain"]["iters"]),
@@ -526,8 +574,9 @@ def main():
     ap.add_argument("--learned-target", default="coarse", choices=["coarse", "e-Sr", "e"],
                     help="training target: the coarse Galerkin projection of the error, the "
                          "error left by the Schwarz apply, or the error")
-    ap.add_argument("--learned-fcg-m", type=int, default=64,
-                    help="directions kept by the learned flexible CG")
+    ap.add_argument("--learned-fcg-m", type=int, nargs="+", default=[32],
+                    help="directions kept by the learned flexible CG (the first is the "
+                         "reported run; further values are solved too)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first copy 4 GiB three times with a plain copy kernel, the reference "
                          "for scaling hardware byte counters")
@@ -540,6 +589,8 @@ def main():
                     default=[1.0, 0.9, 0.8, 0.7, 0.6, 0.4, 0.2, 0.0, -1.0])
     ap.add_argument("--learned-only", action="store_true",
                     help="instead: only the learned coarse-correction comparison")
+    ap.add_argument("--net-only", action="store_true",
+                    help="instead: only the network kernels (forward and training step)")
     ap.add_argument("--compare", action="store_true",
                     help="instead: DA, S* and S on the elasticity geometry at small alpha")
     ap.add_argument("--compare-alpha", type=float, nargs="+", default=[1e-12, 1e-16, 0.0])
@@ -564,6 +615,9 @@ def main():
         return
     if args.learned_only:
         print(json.dumps(learned_bench(fc, args)), flush=True)
+        return
+    if args.net_only:
+        print(json.dumps(net_timing(fc)), flush=True)
         return
     if args.eta_sweep:
         print(json.dumps(eta_sweep_bench(fc, args)), flush=True)

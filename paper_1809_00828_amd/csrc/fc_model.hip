@@ -72,7 +72,7 @@ fc_status fc_model_create(const int32_t* ch, int32_t in_ch, const float* params,
   net.init(ch, in_ch);
   const size_t n = (size_t)net.nparam;
   FC_HIP(hipMalloc(&net.p, n * sizeof(float)));
-  FC_HIP(hipMalloc(&net.wpk, (size_t)net.nwpk * sizeof(uint32_t)));
+  FC_HIP(hipMalloc(&net.wpk, (size_t)net.nwpk * sizeof(uint16_t)));
   FC_HIP(hipMalloc(&net.g, n * sizeof(float)));
   FC_HIP(hipMalloc(&net.m, n * sizeof(float)));
   FC_HIP(hipMalloc(&net.v, n * sizeof(float)));

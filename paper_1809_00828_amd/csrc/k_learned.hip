@@ -13,11 +13,14 @@
 // then b[co]; tap = dz*9 + dy*3 + dx), a BF16 copy used by every
 // convolution, FP32 activations and FP32 accumulation.
 //
-// Convolution kernels: every lane owns one output voxel and 8 output
-// channels, with the BF16 weights arriving through wave-uniform loads.
-// The data gradient is the same kernel with the weights transposed and the
-// taps mirrored; the weight gradient is one workgroup per (co, ci) pair
-// reducing over voxels (fixed order, no atomics).
+// Convolution kernels: implicit GEMMs on the BF16 matrix cores (MFMA) with
+// FP32 accumulation.  A workgroup stages a 4x4x4 brick of its input with a
+// one-voxel halo in LDS, split into BF16 terms (three for the forward and
+// data-gradient passes, which keeps FP32 accuracy with BF16 weights; two
+// for the weight gradient), and runs the 27 taps from there.  The data
+// gradient is the forward kernel on weights packed transposed with the taps
+// mirrored; the weight gradient sums brick ranges into partials that a
+// second kernel adds in a fixed order (no atomics).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -31,8 +34,7 @@
 
 namespace fc {
 
-constexpr int kConvT = 64;   // lanes per workgroup (one wave)
-constexpr int kWgradSlots = 4096;   // (co, ci, chunk) partials of the weight gradient
+constexpr int kWgradRanges = 512;   // brick ranges of one weight-gradient launch, at most
 
 __device__ __forceinline__ uint16_t f2bf(float f) {
   uint32_t u = __float_as_uint(f);
@@ -40,133 +42,392 @@ __device__ __forceinline__ uint16_t f2bf(float f) {
   return (uint16_t)(u >> 16);
 }
 
-// y[b][o][v] = act(bias[o] + sum_{i,t} w(o,i,t) x[b][i][v + off_t])
-// One wave per workgroup, one voxel and CoT output channels per lane (CoT
-// shrinks on the coarse levels so that the launch still spans the chip).  The
-// weights are read at wave-uniform addresses from rows of 14 dwords (27
-// BF16 taps and one pad per (co, ci) pair), so they arrive through scalar
-// loads and feed the FMAs as scalar operands; the 27 neighbour values of
-// an input channel are loaded once and reused for all CoT outputs.
-// kTrans: w(o,i,t) = W[i][o][26-t] (data gradient of a convolution whose
-// input width is this kernel's Co), no bias, no activation.
-template <bool kTrans, int kCoT>
-__global__ __launch_bounds__(kConvT) void k_conv3d(const float* __restrict__ x, int Ci,
-                                                   const uint32_t* __restrict__ W,
-                                                   const float* __restrict__ bias,
-                                                   float* __restrict__ y, int Co, int N,
-                                                   int relu) {
+// ---------------------------------------------------------- MFMA convolutions
+// Every convolution is an implicit GEMM on the 16x16x16 BF16 matrix cores
+// with FP32 accumulation.  Operand layouts of v_mfma_f32_16x16x16_bf16 (one
+// wave): lane l supplies A[l % 16][4 (l / 16) + j] and B[4 (l / 16) + j]
+// [l % 16], j = 0..3, and holds D[4 (l / 16) + j][l % 16].
+//
+// A workgroup owns a brick of 4x4x4 voxels; its input, with a one-voxel
+// halo (6x6x6), is staged once in LDS, already split into BF16 terms, and
+// every tap of the stencil reads it there.  A 16-voxel row tile of the GEMM
+// is one 4x4 (y, x) plane of the brick.
+typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int kHaloVox = 216;   // 6^3 halo voxels of a 4^3 brick
+
+// v = h0 + h1 + h2 in BF16 with |v - (h0 + h1 + h2)| <= 2^-24 |v| (each
+// term the BF16 rounding of what the earlier ones leave; the remainders are
+// exact in FP32).  Products of BF16 numbers are exact in FP32, so three
+// MFMAs over the three terms give the FP32-accurate product with a BF16
+// weight.  Two terms leave 2^-16 |v|.
+struct Split3 {
+  uint16_t h[3];
+};
+
+__device__ __forceinline__ Split3 split3(float v) {
+  Split3 r;
+  r.h[0] = f2bf(v);
+  const float ra = v - __uint_as_float((uint32_t)r.h[0] << 16);
+  r.h[1] = f2bf(ra);
+  const float rb = ra - __uint_as_float((uint32_t)r.h[1] << 16);
+  r.h[2] = f2bf(rb);
+  return r;
+}
+
+__device__ __forceinline__ void split2(float v, uint16_t& h0, uint16_t& h1) {
+  h0 = f2bf(v);
+  h1 = f2bf(v - __uint_as_float((uint32_t)h0 << 16));
+}
+
+// offset of tap t = dz*9 + dy*3 + dx in a 6x6x6 halo (taps past 26 are
+// padding with zero weight and read the corner)
+__device__ __forceinline__ int halo_tap_offset(int t) {
+  if (t >= 27) return 0;
+  const int dz = t / 9, r = t - 9 * dz, dy = r / 3;
+  return dz * 36 + dy * 6 + (r - 3 * dy);
+}
+
+// Reduction layout of a convolution with cin input channels: chunks of cc
+// channels (4, 8 or 16), each chunk a run of ksteps * 16 reduction indices
+// k = tap * cc + c (c the channel within the chunk), zero weights past
+// 27 * cc.
+struct ConvK {
+  int cc, nchunk, ksteps, krow;
+};
+
+inline ConvK conv_k(int cin) {
+  ConvK g;
+  g.cc = cin <= 4 ? 4 : cin <= 8 ? 8 : 16;
+  g.nchunk = (cin + g.cc - 1) / g.cc;
+  g.ksteps = (27 * g.cc + 15) / 16;
+  g.krow = g.nchunk * g.ksteps * 16;
+  return g;
+}
+
+// y[b][o][v] = act(bias[o] + sum_{i,t} w(o,i,t) x[b][i][v + off_t]) with the
+// weights packed by k_pack_conv (rows o of krow BF16 values, chunks of kCc
+// input channels) and the input split into three BF16 terms.  Workgroup:
+// brick blockIdx.x (nb^3 per sample), output channels 16 blockIdx.y .. + 15
+// (one column tile), sample blockIdx.z; wave w computes plane z = w of the
+// brick.  Per chunk, the halo input and the tile's weights are staged in
+// LDS, the loads of a thread all issued before the first is used.
+template <int kCc>
+__global__ __launch_bounds__(256) void k_conv3d(const float* __restrict__ x, int Ci, int nchunk,
+                                                const uint16_t* __restrict__ W, int krow,
+                                                const float* __restrict__ bias,
+                                                float* __restrict__ y, int Co, int N, int nb,
+                                                int relu) {
+  constexpr int kRs = kCc + 4;                   // LDS row of a halo voxel (pad: banks)
+  constexpr int kSteps = (27 * kCc + 15) / 16;
+  constexpr int kWRow = kSteps * 16 + 4;         // LDS row of one output channel
+  constexpr int kItems = kHaloVox * kCc / 4;     // (halo voxel, 4 channels) items
+  constexpr int kIter = (kItems + 255) / 256;
+  constexpr int kWItems = 16 * kSteps * 2;       // 8 weights per item
+  constexpr int kWIter = (kWItems + 255) / 256;
+  __shared__ __align__(16) uint16_t xs[3][kHaloVox * kRs];   // [term][voxel][channel]
+  __shared__ __align__(16) uint16_t wl[16 * kWRow];          // [column][k]
   const int V = N * N * N;
-  const int b = blockIdx.z;
-  const int o0 = blockIdx.y * kCoT;
-  const int v = blockIdx.x * kConvT + threadIdx.x;
-  const bool active = v < V;
-  const int vv = active ? v : 0;
-  const int xx = vv % N, yy = (vv / N) % N, zz = vv / (N * N);
-  float acc[kCoT];
+  const int brick = blockIdx.x, b = blockIdx.z, o0 = blockIdx.y * 16;
+  const int bx = brick % nb, by = (brick / nb) % nb, bz = brick / (nb * nb);
+  const int x0 = 4 * bx - 1, y0 = 4 * by - 1, z0 = 4 * bz - 1;   // halo corner
+  const int tid = threadIdx.x, w = tid >> 6, l = tid & 63, r16 = l & 15, kg = l >> 4;
+  const int hv0 = (w * 6 + (r16 >> 2)) * 6 + (r16 & 3);   // this lane's A row, tap 0
+  // one accumulator per input term (independent MFMA chains), added
+  // smallest term first at the end
+  f32x4 acc[3];
 #pragma unroll
-  for (int o = 0; o < kCoT; ++o) acc[o] = (!kTrans && bias && o0 + o < Co) ? bias[o0 + o] : 0.f;
+  for (int s = 0; s < 3; ++s) acc[s] = f32x4{0.f, 0.f, 0.f, 0.f};
   const float* xb = x + (int64_t)b * Ci * V;
-  for (int i = 0; i < Ci; ++i) {
-    const float* xi = xb + (int64_t)i * V;
-    float xv[27];
+  for (int ch = 0; ch < nchunk; ++ch) {
+    const int c0 = ch * kCc;
+    float v[kIter][4];
+    int dst[kIter];
 #pragma unroll
-    for (int k = 0; k < 27; ++k) {
-      const int z2 = zz + k / 9 - 1, y2 = yy + (k / 3) % 3 - 1, x2 = xx + k % 3 - 1;
-      const bool in = z2 >= 0 && z2 < N && y2 >= 0 && y2 < N && x2 >= 0 && x2 < N;
-      xv[k] = in ? xi[(z2 * N + y2) * N + x2] : 0.f;
+    for (int it = 0; it < kIter; ++it) {
+      const int e = tid + 256 * it;
+      const int q = e / kHaloVox, hv = e - q * kHaloVox;
+      const int hz = hv / 36, hr = hv - 36 * hz, hy = hr / 6, hx = hr - 6 * hy;
+      const int gz = z0 + hz, gy = y0 + hy, gx = x0 + hx;
+      const bool in = e < kItems && gz >= 0 && gz < N && gy >= 0 && gy < N && gx >= 0 && gx < N;
+      const float* src = xb + (int64_t)(c0 + 4 * q) * V + (in ? (gz * N + gy) * N + gx : 0);
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        v[it][j] = (in && c0 + 4 * q + j < Ci) ? src[(int64_t)j * V] : 0.f;
+      dst[it] = e < kItems ? hv * kRs + 4 * q : -1;
+    }
+    uint4 wv[kWIter];
+    int wdst[kWIter];
+#pragma unroll
+    for (int it = 0; it < kWIter; ++it) {
+      const int e = tid + 256 * it;
+      const int r = e / (2 * kSteps), q = e - r * 2 * kSteps;
+      wv[it] = uint4{0u, 0u, 0u, 0u};
+      if (e < kWItems && o0 + r < Co)
+        wv[it] = *reinterpret_cast<const uint4*>(W + (int64_t)(o0 + r) * krow +
+                                                 (int64_t)ch * kSteps * 16 + 8 * q);
+      wdst[it] = e < kWItems ? r * kWRow + 8 * q : -1;
+    }
+    __syncthreads();   // the previous chunk's reads are done
+#pragma unroll
+    for (int it = 0; it < kIter; ++it) {
+      if (dst[it] < 0) continue;
+      uint16_t h[3][4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const Split3 sp = split3(v[it][j]);
+        h[0][j] = sp.h[0];
+        h[1][j] = sp.h[1];
+        h[2][j] = sp.h[2];
+      }
+#pragma unroll
+      for (int s = 0; s < 3; ++s) {
+        uint2 pk;
+        pk.x = (uint32_t)h[s][0] | ((uint32_t)h[s][1] << 16);
+        pk.y = (uint32_t)h[s][2] | ((uint32_t)h[s][3] << 16);
+        *reinterpret_cast<uint2*>(&xs[s][dst[it]]) = pk;
+      }
     }
 #pragma unroll
-    for (int o = 0; o < kCoT; ++o) {
-      if (o0 + o >= Co) break;
-      const int64_t row = kTrans ? ((int64_t)i * Co + (o0 + o)) : ((int64_t)(o0 + o) * Ci + i);
-      const uint32_t* wr = W + row * kRowDw;
+    for (int it = 0; it < kWIter; ++it) {
+      if (wdst[it] < 0) continue;
+      *reinterpret_cast<uint2*>(&wl[wdst[it]]) = uint2{wv[it].x, wv[it].y};
+      *reinterpret_cast<uint2*>(&wl[wdst[it] + 4]) = uint2{wv[it].z, wv[it].w};
+    }
+    __syncthreads();
 #pragma unroll
-      for (int j = 0; j < kRowDw; ++j) {
-        const uint32_t pr = wr[j];
-        const float wlo = __uint_as_float(pr << 16), whi = __uint_as_float(pr & 0xffff0000u);
-        const int k0 = 2 * j, k1 = 2 * j + 1;
-        acc[o] = fmaf(wlo, xv[kTrans ? 26 - k0 : k0], acc[o]);
-        if (k1 < 27) acc[o] = fmaf(whi, xv[kTrans ? 26 - k1 : k1], acc[o]);
+    for (int s = 0; s < kSteps; ++s) {
+      const int k = 16 * s + 4 * kg;
+      const int t = k / kCc, c = k - t * kCc;
+      const int a = (hv0 + halo_tap_offset(t)) * kRs + c;
+      const bf16x4 bw = *reinterpret_cast<const bf16x4*>(&wl[r16 * kWRow + k]);
+#pragma unroll
+      for (int h = 0; h < 3; ++h) {
+        const bf16x4 av = *reinterpret_cast<const bf16x4*>(&xs[h][a]);
+        acc[h] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bw, acc[h], 0, 0, 0);
       }
     }
   }
-  if (!active) return;
-  float* yb = y + (int64_t)b * Co * V;
+  // D[4 kg + j][r16]: voxel (y = kg, x = j) of plane w, channel o0 + r16
+  const int gz = z0 + 1 + w, gy = y0 + 1 + kg, o = o0 + r16;
+  if (gz >= N || gy >= N || o >= Co) return;
+  const float bo = bias ? bias[o] : 0.f;
+  float* yo = y + ((int64_t)b * Co + o) * V + (gz * N + gy) * N;
 #pragma unroll
-  for (int o = 0; o < kCoT; ++o)
-    if (o0 + o < Co) yb[(int64_t)(o0 + o) * V + v] = relu ? fmaxf(acc[o], 0.f) : acc[o];
-}
-
-// BF16 rows of 14 dwords from the FP32 weights W[rows][27]
-__global__ void k_pack_w(const float* __restrict__ w, uint32_t* __restrict__ out, int64_t rows) {
-  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < rows * kRowDw;
-       t += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t row = t / kRowDw;
-    const int j = (int)(t % kRowDw);
-    const uint32_t lo = f2bf(w[row * 27 + 2 * j]);
-    const uint32_t hi = 2 * j + 1 < 27 ? f2bf(w[row * 27 + 2 * j + 1]) : 0u;
-    out[t] = lo | (hi << 16);
-  }
-}
-
-// Weight gradient, gw[co][ci][t] = sum_{b,v} g[b][co][v] x[b][ci][v + off_t]
-// and gb[co] = sum g, in two deterministic passes: workgroup (ci, co, c)
-// sums chunk c of the (b, v) range into 28 partials, then one thread per
-// (co, ci, t) adds the chunks in order.
-__global__ __launch_bounds__(256) void k_conv3d_wgrad(const float* __restrict__ x, int Ci,
-                                                      const float* __restrict__ g, int Co, int B,
-                                                      int D, int H, int Wd, int nchunk,
-                                                      float* __restrict__ part) {
-  __shared__ float red[16];
-  const int ci = blockIdx.x, co = blockIdx.y, c = blockIdx.z;
-  const int V = D * H * Wd;
-  const int64_t total = (int64_t)B * V;
-  const int64_t len = (total + nchunk - 1) / nchunk;
-  const int64_t lo = (int64_t)c * len, hi = lo + len < total ? lo + len : total;
-  float acc[27];
-#pragma unroll
-  for (int k = 0; k < 27; ++k) acc[k] = 0.f;
-  float accb = 0.f;
-  for (int64_t idx = lo + threadIdx.x; idx < hi; idx += blockDim.x) {
-    const int b = (int)(idx / V), v = (int)(idx % V);
-    const float gv = g[((int64_t)b * Co + co) * V + v];
-    accb += gv;
-    if (gv == 0.f) continue;
-    const int xx = v % Wd, yy = (v / Wd) % H, zz = v / (Wd * H);
-    const float* xi = x + ((int64_t)b * Ci + ci) * V;
-#pragma unroll
-    for (int k = 0; k < 27; ++k) {
-      const int dz = k / 9 - 1, dy = (k / 3) % 3 - 1, dx = k % 3 - 1;
-      const int z2 = zz + dz, y2 = yy + dy, x2 = xx + dx;
-      if (z2 >= 0 && z2 < D && y2 >= 0 && y2 < H && x2 >= 0 && x2 < Wd)
-        acc[k] = fmaf(gv, xi[(z2 * H + y2) * Wd + x2], acc[k]);
+  for (int j = 0; j < 4; ++j) {
+    const int gx = x0 + 1 + j;
+    if (gx < N) {
+      const float val = (acc[2][j] + acc[1][j]) + acc[0][j] + bo;
+      yo[gx] = relu ? fmaxf(val, 0.f) : val;
     }
   }
-  float* out = part + (((int64_t)co * Ci + ci) * nchunk + c) * 28;
-  for (int k = 0; k < 27; ++k) {
-    const float s = block_sum(acc[k], red);
-    if (threadIdx.x == 0) out[k] = s;
-  }
-  const float sb = block_sum(accb, red);
-  if (threadIdx.x == 0) out[27] = sb;
 }
 
-__global__ void k_wgrad_reduce(const float* __restrict__ part, int Ci, int Co, int nchunk,
-                               float* __restrict__ gw, float* __restrict__ gb) {
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t rows = (int64_t)Co * Ci;
-  if (t >= rows * 28) return;
-  const int64_t row = t / 28;
-  const int k = (int)(t % 28);
-  const float* p = part + row * nchunk * 28 + k;
-  float s = 0.f;
-  for (int c = 0; c < nchunk; ++c) s += p[(int64_t)c * 28];
-  const int co = (int)(row / Ci), ci = (int)(row % Ci);
-  if (k < 27) gw[row * 27 + k] = s;
-  else if (ci == 0) {
-    // the bias gradient is the same sum for every ci; keep ci = 0's
-    gb[co] = s;
+// Packed BF16 weights of one layer for k_conv3d.  Forward (trans = 0): row
+// o of Co rows, reduction over the Ci input channels, value W[o][i][t].
+// Data gradient (trans = 1): row i of Ci rows, reduction over the Co output
+// channels with the taps mirrored, value W[o][i][26 - t] (the adjoint of a
+// 'same' convolution is the convolution with the mirrored stencil).
+__global__ void k_pack_conv(const float* __restrict__ w, int Co, int Ci, int trans, int cc,
+                            int ksteps, int krow, uint16_t* __restrict__ out) {
+  const int rows = trans ? Ci : Co, cin = trans ? Co : Ci;
+  const int64_t total = (int64_t)rows * krow;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int r = (int)(e / krow), k = (int)(e - (int64_t)r * krow);
+    const int chunk = k / (ksteps * 16), kk = k - chunk * ksteps * 16;
+    const int t = kk / cc, c = chunk * cc + kk % cc;
+    float v = 0.f;
+    if (t < 27 && c < cin)
+      v = trans ? w[((int64_t)c * Ci + r) * 27 + 26 - t] : w[((int64_t)r * Ci + c) * 27 + t];
+    out[e] = f2bf(v);
   }
+}
+
+// Weight gradient gw[o][i][t] = sum_{b,v} g[b][o][v] x[b][i][v + off_t] and
+// gb[o] = sum g[b][o][v], on the matrix cores: rows o, columns the 16
+// input channels i of one chunk per tap, reduction over the voxels of a
+// brick (16 per step: one 4x4 plane), both operands split into two BF16
+// terms and the three products above 2^-16 summed.  Workgroup: input
+// channels 16 blockIdx.x .., output channels 32 blockIdx.y .., a range of
+// bricks (over samples and space) blockIdx.z; wave w owns taps w, w + 4, ..
+// (wave 3 also the bias, as a column of ones).  Each workgroup writes its
+// sums to part[z][o][i][28] (slot 27 of i = 0: bias); k_wgrad_reduce adds
+// the ranges in order (deterministic, no atomics).
+__global__ __launch_bounds__(256, 2) void k_conv3d_wgrad(const float* __restrict__ x, int Ci,
+                                                      const float* __restrict__ g, int Co,
+                                                      int N, int nb, int64_t nbricks,
+                                                      int64_t per, int Cip,
+                                                      float* __restrict__ part) {
+  // input terms by x shift: xs[term][dx][i][row (z, y) of the halo][4]
+  // holds x at halo x = dx .. dx + 3, so each shifted 4-voxel run is one
+  // aligned 8-byte read; rows of 148 values per channel spread the banks
+  constexpr int kXRow = 148;
+  constexpr int kGRow = 68;
+  constexpr int kXItems = 16 * kHaloVox;
+  constexpr int kXIter = (kXItems + 255) / 256;
+  constexpr int kGIter = 32 * 64 / 256;
+  __shared__ __align__(16) uint16_t xs[2][3][16 * kXRow];
+  __shared__ __align__(16) uint16_t gs[2][32 * kGRow];   // [term][o][voxel]
+  const int V = N * N * N, nb3 = nb * nb * nb;
+  const int i0 = blockIdx.x * 16, o0 = blockIdx.y * 32;
+  const int tid = threadIdx.x, w = tid >> 6, l = tid & 63, r16 = l & 15, kg = l >> 4;
+  const bool two = o0 + 16 < Co;
+  const bool with_bias = w == 3 && blockIdx.x == 0;
+  f32x4 acc[7][2];
+#pragma unroll
+  for (int q = 0; q < 7; ++q) acc[q][0] = acc[q][1] = f32x4{0.f, 0.f, 0.f, 0.f};
+  const int64_t lo = (int64_t)blockIdx.z * per;
+  const int64_t hi = lo + per < nbricks ? lo + per : nbricks;
+  // the raw values of one brick, loaded one brick ahead of the compute
+  float xv[kXIter], gv[kGIter];
+  auto load = [&](int64_t bi) {
+    const int b = (int)(bi / nb3), brick = (int)(bi - (int64_t)b * nb3);
+    const int bx = brick % nb, by = (brick / nb) % nb, bz = brick / (nb * nb);
+    const int x0 = 4 * bx - 1, y0 = 4 * by - 1, z0 = 4 * bz - 1;
+    const float* xb = x + (int64_t)b * Ci * V;
+#pragma unroll
+    for (int it = 0; it < kXIter; ++it) {
+      const int e = tid + 256 * it;
+      const int i = e / kHaloVox, hv = e - i * kHaloVox;
+      const int hz = hv / 36, hr = hv - 36 * hz, hy = hr / 6, hx = hr - 6 * hy;
+      const int gz = z0 + hz, gy = y0 + hy, gx = x0 + hx;
+      xv[it] = (e < kXItems && i0 + i < Ci && gz >= 0 && gz < N && gy >= 0 && gy < N &&
+                gx >= 0 && gx < N)
+                   ? xb[(int64_t)(i0 + i) * V + (gz * N + gy) * N + gx]
+                   : 0.f;
+    }
+    const float* gb = g + (int64_t)b * Co * V;
+#pragma unroll
+    for (int it = 0; it < kGIter; ++it) {
+      const int e = tid + 256 * it;
+      const int o = e >> 6, v = e & 63;
+      const int gz = z0 + 1 + (v >> 4), gy = y0 + 1 + ((v >> 2) & 3), gx = x0 + 1 + (v & 3);
+      gv[it] = (o0 + o < Co && gz < N && gy < N && gx < N)
+                   ? gb[(int64_t)(o0 + o) * V + (gz * N + gy) * N + gx]
+                   : 0.f;
+    }
+  };
+  if (lo < hi) load(lo);
+  for (int64_t bi = lo; bi < hi; ++bi) {
+    __syncthreads();   // the previous brick's reads are done
+#pragma unroll
+    for (int it = 0; it < kXIter; ++it) {
+      const int e = tid + 256 * it;
+      if (e >= kXItems) continue;
+      const int i = e / kHaloVox, hv = e - i * kHaloVox;
+      const int hz = hv / 36, hr = hv - 36 * hz, hy = hr / 6, hx = hr - 6 * hy;
+      uint16_t h0, h1;
+      split2(xv[it], h0, h1);
+      const int base = i * kXRow + (hz * 6 + hy) * 4 + hx;
+#pragma unroll
+      for (int dx = 0; dx < 3; ++dx) {
+        const int xq = hx - dx;
+        if (xq >= 0 && xq < 4) {
+          xs[0][dx][base - dx] = h0;
+          xs[1][dx][base - dx] = h1;
+        }
+      }
+    }
+#pragma unroll
+    for (int it = 0; it < kGIter; ++it) {
+      const int e = tid + 256 * it;
+      const int o = e >> 6, v = e & 63;
+      uint16_t h0, h1;
+      split2(gv[it], h0, h1);
+      gs[0][o * kGRow + v] = h0;
+      gs[1][o * kGRow + v] = h1;
+    }
+    __syncthreads();
+    if (bi + 1 < hi) load(bi + 1);   // in flight during the products below
+#pragma unroll 1
+    for (int pz = 0; pz < 4; ++pz) {
+      // A: g[o][voxels (y = kg, x = 0..3) of plane pz]
+      const int ga = r16 * kGRow + 16 * pz + 4 * kg;
+      const bf16x4 g0a = *reinterpret_cast<const bf16x4*>(&gs[0][ga]);
+      const bf16x4 g1a = *reinterpret_cast<const bf16x4*>(&gs[1][ga]);
+      const bf16x4 g0b = *reinterpret_cast<const bf16x4*>(&gs[0][ga + 16 * kGRow]);
+      const bf16x4 g1b = *reinterpret_cast<const bf16x4*>(&gs[1][ga + 16 * kGRow]);
+#pragma unroll
+      for (int q = 0; q < 7; ++q) {
+        const int t = w + 4 * q;
+        if (t < 27) {
+          const int dz = t / 9, dy = (t / 3) % 3, dx = t % 3;
+          const int xa = r16 * kXRow + ((pz + dz) * 6 + kg + dy) * 4;
+          const bf16x4 x0v = *reinterpret_cast<const bf16x4*>(&xs[0][dx][xa]);
+          const bf16x4 x1v = *reinterpret_cast<const bf16x4*>(&xs[1][dx][xa]);
+          acc[q][0] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(g1a, x0v, acc[q][0], 0, 0, 0);
+          acc[q][0] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(g0a, x1v, acc[q][0], 0, 0, 0);
+          acc[q][0] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(g0a, x0v, acc[q][0], 0, 0, 0);
+          if (two) {
+            acc[q][1] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(g1b, x0v, acc[q][1], 0, 0, 0);
+            acc[q][1] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(g0b, x1v, acc[q][1], 0, 0, 0);
+            acc[q][1] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(g0b, x0v, acc[q][1], 0, 0, 0);
+          }
+        } else if (with_bias) {
+          const short one = (short)0x3f80;   // BF16 1.0
+          const bf16x4 ones = {one, one, one, one};
+          acc[q][0] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(g1a, ones, acc[q][0], 0, 0, 0);
+          acc[q][0] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(g0a, ones, acc[q][0], 0, 0, 0);
+          if (two) {
+            acc[q][1] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(g1b, ones, acc[q][1], 0, 0, 0);
+            acc[q][1] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(g0b, ones, acc[q][1], 0, 0, 0);
+          }
+        }
+      }
+    }
+  }
+  // D[4 kg + j][r16]: output channel o0 + 16 ct + 4 kg + j, input channel
+  // i0 + r16
+  float* pz = part + (int64_t)blockIdx.z * Co * Cip * 28;
+#pragma unroll
+  for (int q = 0; q < 7; ++q) {
+    const int t = w + 4 * q;
+    if (t >= 27 && !with_bias) continue;
+    if (t >= 27 && r16 != 0) continue;
+    const int tt = t < 27 ? t : 27;
+#pragma unroll
+    for (int ct = 0; ct < 2; ++ct) {
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int o = o0 + 16 * ct + 4 * kg + j;
+        if (o < Co && (ct == 0 || two))
+          pz[((int64_t)o * Cip + i0 + r16) * 28 + tt] = acc[q][ct][j];
+      }
+    }
+  }
+}
+
+// gw[o][i][t] and gb[o] from the per-range sums: 16 outputs per workgroup
+// of 256 threads, thread (slice, output) adds ranges slice, slice + 16, ..
+// in order, then the 16 slice sums are added in order (deterministic).
+__global__ __launch_bounds__(256) void k_wgrad_reduce(const float* __restrict__ part, int Ci,
+                                                      int Co, int Cip, int nrange,
+                                                      float* __restrict__ gw,
+                                                      float* __restrict__ gb) {
+  __shared__ float sums[16][17];
+  const int lane = threadIdx.x & 15, slice = threadIdx.x >> 4;
+  const int64_t e = (int64_t)blockIdx.x * 16 + lane;
+  const int64_t nout = (int64_t)Co * Ci * 28;
+  int o = 0, i = 0, t = 0;
+  float s = 0.f;
+  if (e < nout) {
+    o = (int)(e / (Ci * 28));
+    const int r = (int)(e - (int64_t)o * Ci * 28);
+    i = r / 28;
+    t = r - 28 * i;
+    const int64_t stride = (int64_t)Co * Cip * 28;
+    const float* p = part + ((int64_t)o * Cip + i) * 28 + t;
+    for (int c = slice; c < nrange; c += 16) s += p[c * stride];
+  }
+  sums[slice][lane] = s;
+  __syncthreads();
+  if (slice != 0 || e >= nout || (t == 27 && i != 0)) return;
+  float tot = 0.f;
+  for (int k = 0; k < 16; ++k) tot += sums[k][lane];
+  if (t < 27) gw[((int64_t)o * Ci + i) * 27 + t] = tot;
+  else gb[o] = tot;
 }
 
 // average over the existing children: (D,H,W) -> ceil halves
@@ -322,12 +583,14 @@ void Net::init(const int32_t* c, int32_t in_channels) {
     off += co[l];
   }
   nparam = off;
-  int64_t dw = 0;
+  int64_t e = 0;
   for (int l = 0; l < 15; ++l) {
-    wpoff[l] = dw;
-    dw += (int64_t)ci[l] * co[l] * kRowDw;
+    wfoff[l] = e;
+    e += (int64_t)co[l] * conv_k(ci[l]).krow;
+    wtoff[l] = e;
+    e += (int64_t)ci[l] * conv_k(co[l]).krow;
   }
-  nwpk = dw;
+  nwpk = e;
 }
 
 int64_t net_param_count(const int32_t* c, int32_t in_channels) {
@@ -336,61 +599,62 @@ int64_t net_param_count(const int32_t* c, int32_t in_channels) {
   return n.nparam;
 }
 
-// Output channels per lane: the largest of 8, 4, 2, 1 that still gives at
-// least 1024 workgroups (the coarse levels hold few voxels).
-template <bool kTrans>
-static hipError_t launch_conv(const float* x, int cin, const uint32_t* W, const float* bias,
+// One workgroup per 4^3 brick and 16 output channels; cin input channels
+// with weights packed for that width.
+static hipError_t launch_conv(const float* x, int cin, const uint16_t* W, const float* bias,
                               float* y, int cout, int N, int B, int relu, hipStream_t s) {
-  const int V = N * N * N;
-  const int64_t vb = (V + kConvT - 1) / kConvT;
-  int cot = 8;
-  while (cot > 1 && vb * ((cout + cot - 1) / cot) * B < 1024) cot /= 2;
-  dim3 g((unsigned)vb, (unsigned)((cout + cot - 1) / cot), (unsigned)B);
-  switch (cot) {
-    case 8:
-      hipLaunchKernelGGL((k_conv3d<kTrans, 8>), g, dim3(kConvT), 0, s, x, cin, W, bias, y, cout,
-                         N, relu);
-      break;
-    case 4:
-      hipLaunchKernelGGL((k_conv3d<kTrans, 4>), g, dim3(kConvT), 0, s, x, cin, W, bias, y, cout,
-                         N, relu);
-      break;
-    case 2:
-      hipLaunchKernelGGL((k_conv3d<kTrans, 2>), g, dim3(kConvT), 0, s, x, cin, W, bias, y, cout,
-                         N, relu);
-      break;
-    default:
-      hipLaunchKernelGGL((k_conv3d<kTrans, 1>), g, dim3(kConvT), 0, s, x, cin, W, bias, y, cout,
-                         N, relu);
-  }
+  const ConvK k = conv_k(cin);
+  const int nb = (N + 3) / 4;
+  dim3 g((unsigned)(nb * nb * nb), (unsigned)((cout + 15) / 16), (unsigned)B);
+  if (k.cc == 4)
+    hipLaunchKernelGGL(k_conv3d<4>, g, dim3(256), 0, s, x, cin, k.nchunk, W, k.krow, bias, y,
+                       cout, N, nb, relu);
+  else if (k.cc == 8)
+    hipLaunchKernelGGL(k_conv3d<8>, g, dim3(256), 0, s, x, cin, k.nchunk, W, k.krow, bias, y,
+                       cout, N, nb, relu);
+  else
+    hipLaunchKernelGGL(k_conv3d<16>, g, dim3(256), 0, s, x, cin, k.nchunk, W, k.krow, bias, y,
+                       cout, N, nb, relu);
   return hipGetLastError();
 }
 
 static hipError_t conv_fwd(const Net& net, int l, const float* x, float* y, int B, int N, bool relu,
                            hipStream_t s) {
-  return launch_conv<false>(x, net.ci[l], net.wpk + net.wpoff[l], net.p + net.boff[l], y,
-                            net.co[l], N, B, relu ? 1 : 0, s);
+  return launch_conv(x, net.ci[l], net.wpk + net.wfoff[l], net.p + net.boff[l], y, net.co[l], N,
+                     B, relu ? 1 : 0, s);
 }
 
 // data gradient of layer l: gx (Ci channels) from gy (Co channels)
 static hipError_t conv_bwd_data(const Net& net, int l, const float* gy, float* gx, int B, int N,
                                 hipStream_t s) {
-  return launch_conv<true>(gy, net.co[l], net.wpk + net.wpoff[l], nullptr, gx, net.ci[l], N, B,
-                           0, s);
+  return launch_conv(gy, net.co[l], net.wpk + net.wtoff[l], nullptr, gx, net.ci[l], N, B, 0, s);
+}
+
+static int64_t wgrad_row_floats(int Ci, int Co) {
+  return (int64_t)Co * ((Ci + 15) / 16 * 16) * 28;
+}
+
+// brick ranges of a weight-gradient launch: about 1024 workgroups
+static int64_t wgrad_max_ranges(int Ci, int Co) {
+  const int64_t tiles = (int64_t)((Ci + 15) / 16) * ((Co + 31) / 32);
+  return std::min<int64_t>(kWgradRanges, std::max<int64_t>(1, 1024 / tiles));
 }
 
 static hipError_t conv_bwd_weight(Net& net, NetWs& ws, int l, const float* x, const float* gy,
                                   int B, int N, hipStream_t s) {
   const int Ci = net.ci[l], Co = net.co[l];
-  const int64_t total = (int64_t)B * N * N * N;
-  const int64_t pairs = (int64_t)Ci * Co;
-  // chunks of at least 1024 (b, v) points, at most ws.wslots partial rows
-  int64_t nchunk = std::max<int64_t>(1, std::min<int64_t>(ws.wslots / pairs, total / 1024));
-  hipLaunchKernelGGL(k_conv3d_wgrad, dim3(Ci, Co, (unsigned)nchunk), dim3(256), 0, s, x, Ci, gy,
-                     Co, B, N, N, N, (int)nchunk, ws.wpart);
-  const int64_t nt = pairs * 28;
-  hipLaunchKernelGGL(k_wgrad_reduce, dim3((unsigned)((nt + 255) / 256)), dim3(256), 0, s, ws.wpart,
-                     Ci, Co, (int)nchunk, net.g + net.woff[l], net.g + net.boff[l]);
+  const int nb = (N + 3) / 4;
+  const int64_t nbricks = (int64_t)B * nb * nb * nb;
+  const int nic = (Ci + 15) / 16, nop = (Co + 31) / 32;
+  int64_t nrange = std::min<int64_t>(wgrad_max_ranges(Ci, Co), nbricks);
+  const int64_t per = (nbricks + nrange - 1) / nrange;
+  nrange = (nbricks + per - 1) / per;
+  dim3 g((unsigned)nic, (unsigned)nop, (unsigned)nrange);
+  hipLaunchKernelGGL(k_conv3d_wgrad, g, dim3(256), 0, s, x, Ci, gy, Co, N, nb, nbricks, per,
+                     nic * 16, ws.wpart);
+  const int64_t nt = (int64_t)Co * Ci * 28;
+  hipLaunchKernelGGL(k_wgrad_reduce, dim3((unsigned)((nt + 15) / 16)), dim3(256), 0, s, ws.wpart,
+                     Ci, Co, nic * 16, (int)nrange, net.g + net.woff[l], net.g + net.boff[l]);
   return hipGetLastError();
 }
 
@@ -425,10 +689,12 @@ fc_status NetWs::ensure(const Net& net, int B_, int N0) {
     return FC_E_NOMEM;
   }
   if (hipMalloc(&partial, 1024 * sizeof(double)) != hipSuccess) return FC_E_NOMEM;
-  // partial rows of the weight gradient: at least one per (co, ci) pair
-  wslots = kWgradSlots;
-  for (int l = 0; l < 15; ++l) wslots = std::max<int64_t>(wslots, (int64_t)net.ci[l] * net.co[l]);
-  if (hipMalloc(&wpart, (size_t)wslots * 28 * sizeof(float)) != hipSuccess) return FC_E_NOMEM;
+  // weight-gradient partials of the largest layer
+  wslots = 0;
+  for (int l = 0; l < 15; ++l)
+    wslots = std::max<int64_t>(wslots, wgrad_max_ranges(net.ci[l], net.co[l]) *
+                                           wgrad_row_floats(net.ci[l], net.co[l]));
+  if (hipMalloc(&wpart, (size_t)wslots * sizeof(float)) != hipSuccess) return FC_E_NOMEM;
   return FC_OK;
 }
 
@@ -570,9 +836,14 @@ hipError_t net_adam(Net& net, float lr, int64_t step, hipStream_t s) {
 
 hipError_t net_sync_bf16(Net& net, hipStream_t s) {
   for (int l = 0; l < 15; ++l) {
-    const int64_t rows = (int64_t)net.ci[l] * net.co[l];
-    hipLaunchKernelGGL(k_pack_w, grid1(rows * kRowDw), dim3(256), 0, s, net.p + net.woff[l],
-                       net.wpk + net.wpoff[l], rows);
+    const int ci = net.ci[l], co = net.co[l];
+    const ConvK kf = conv_k(ci), kt = conv_k(co);
+    hipLaunchKernelGGL(k_pack_conv, grid1((int64_t)co * kf.krow), dim3(256), 0, s,
+                       net.p + net.woff[l], co, ci, 0, kf.cc, kf.ksteps, kf.krow,
+                       net.wpk + net.wfoff[l]);
+    hipLaunchKernelGGL(k_pack_conv, grid1((int64_t)ci * kt.krow), dim3(256), 0, s,
+                       net.p + net.woff[l], co, ci, 1, kt.cc, kt.ksteps, kt.krow,
+                       net.wpk + net.wtoff[l]);
   }
   return hipGetLastError();
 }

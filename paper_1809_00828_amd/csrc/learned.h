@@ -9,19 +9,18 @@
 
 namespace fc {
 
-constexpr int kRowDw = 14;   // dwords per packed BF16 weight row (27 taps + pad)
-
 // Parameters and optimiser state of the 4-level U-Net (device memory).
 struct Net {
   int ch[4] = {0, 0, 0, 0};
   int in_ch = 2;
   int ci[15], co[15];
   int64_t woff[15], boff[15];
-  int64_t wpoff[15];       // dword offset of each layer's packed BF16 rows
+  int64_t wfoff[15];       // offsets in wpk of each layer's forward and
+  int64_t wtoff[15];       // data-gradient (transposed) BF16 weights
   int64_t nparam = 0, nwpk = 0;
   float* p = nullptr;      // FP32 master parameters
-  uint32_t* wpk = nullptr; // BF16 weights used by the convolutions: per
-                           // (co, ci) a row of 14 dwords, 27 taps + pad
+  uint16_t* wpk = nullptr; // BF16 weights packed for the matrix-core
+                           // convolutions (rows of (tap, channel) runs)
   float* g = nullptr;      // gradient
   float* m = nullptr;      // Adam first moment
   float* v = nullptr;      // Adam second moment
@@ -39,7 +38,7 @@ struct NetWs {
   int64_t off_y = 0;
   float* buf = nullptr;
   double* partial = nullptr;
-  float* wpart = nullptr;   // weight-gradient partials, wslots rows of 28
+  float* wpart = nullptr;   // weight-gradient partials (wslots floats)
   int64_t wslots = 0;
   float* t(int l, int k) const { return buf + off[l][k]; }
   int64_t vox(int l) const { return (int64_t)N[l] * N[l] * N[l]; }
