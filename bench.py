@@ -34,7 +34,7 @@ HBM_PEAK_GBS = 8000.0
 # counter passes (FETCH_SIZE, WRITE_SIZE), scaled by what the same counters
 # read for a plain 4 GiB copy (profiles/pcg_fp64_elastic32_p3_hbm_counters.md);
 # to be re-measured whenever one of these kernels changes.
-TRAFFIC = {"spmv": 8.3640e9, "schwarz": 4.6881e9}
+TRAFFIC = {"spmv": 8.9031e9, "schwarz": 4.9988e9}
 METRIC = "DOF·iter/s and time-to-1e-8 residual: mixed/learned vs plain FP64 PCG"
 
 
@@ -141,19 +141,19 @@ def cpu_baseline(gpu_iters=None, full_nnz=None, full_n=None):
             f"{info['iters']} iterations")
     entries = A.nnz + S.nnz
     out = {
-        "value": runs["all_threads"]["dof_iter_per_s"], "unit": "DOF·iter/s",
-        "cores": blas or 1, "kind": "oracle",
+        "value": runs["one_thread"]["dof_iter_per_s"], "unit": "DOF·iter/s",
+        "cores": 1, "kind": "oracle",
         "sample": (f"oracle (python/scipy, FP64) on the 4^3-cell, p=3 instance of the "
                    f"benchmark's generator ({n} DOFs): assembly once, then Algorithm 1 and "
-                   f"PCG to ||r||/||b|| <= 1e-8 with every BLAS thread and with one; the CSR "
-                   f"products of the solve are single-threaded in scipy, the eigen-"
-                   f"decompositions of the build use the BLAS threads"),
+                   f"PCG to ||r||/||b|| <= 1e-8 with every BLAS thread and with one; value and "
+                   f"cores are the one-thread solve (scipy's CSR products are single-threaded "
+                   f"either way; the eigen-decompositions of the build use the BLAS threads)"),
         "cpu_model": _cpu_model(), "host_cpus": os.cpu_count(), "blas_threads": blas,
         "assembly_s": t_asm, "runs": runs,
         "sample_entries_A_plus_S": int(entries),
     }
     if gpu_iters and full_nnz and full_n:
-        per_entry = runs["all_threads"]["ms_per_iter"] * 1e-3 / entries
+        per_entry = runs["one_thread"]["ms_per_iter"] * 1e-3 / entries
         per_iter = per_entry * 2 * full_nnz
         out["extrapolated_full"] = {
             "label": "extrapolated",
