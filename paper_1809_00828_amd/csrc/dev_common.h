@@ -77,40 +77,122 @@ __device__ __forceinline__ double sum_partials(const double* part, int n,
   return block_sum(t, lds);
 }
 
-// Lattice box of row node `row`: for every direction the range of lattice
-// indices of the functions whose support meets the row's support (a vertex
-// index reaches one cell to each side, an interior index only its cell).
+// n / d with the multiplier of make_fastdiv
+__device__ __forceinline__ uint32_t fdiv(uint32_t n, const FastDiv f) {
+  const uint32_t t = __umulhi(n, f.m);
+  return (t + ((n - t) >> f.s1)) >> f.s2;
+}
+
+// Lattice indices of row node `row` (fewer than 2^31 rows: the row
+// pointers are 32-bit), first direction fastest.
+__device__ __forceinline__ void lattice_coords(int64_t row, const LatticeInfo& lat, int c[3]) {
+  uint32_t r = (uint32_t)row;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    c[k] = 0;
+    if (k < lat.dim) {
+      const uint32_t q = fdiv(r, lat.dn1);
+      c[k] = (int)(r - q * (uint32_t)lat.n1);
+      r = q;
+    }
+  }
+}
+
 struct RowBox {
   int lo[3], len[3];
+  float inv[2];   // 1 / len[0], 1 / len[1] (approximate, see lattice_col)
 };
 
-__device__ __forceinline__ RowBox row_box(int64_t row, const LatticeInfo lat) {
+__device__ __forceinline__ RowBox row_box_at(const int c[3], const LatticeInfo& lat) {
   RowBox b;
-  int64_t r = row;
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
     b.lo[k] = 0;
     b.len[k] = 1;
     if (k < lat.dim) {
-      const int g = (int)(r % lat.n1);
-      r /= lat.n1;
-      if (g % lat.p == 0) {
+      const int g = c[k];
+      const int q = (int)fdiv((uint32_t)g, lat.dp);
+      if (g == q * lat.p) {
         const int lo = max(0, g - lat.p), hi = min(lat.n1 - 1, g + lat.p);
         b.lo[k] = lo;
         b.len[k] = hi - lo + 1;
       } else {
-        b.lo[k] = (g / lat.p) * lat.p;
+        b.lo[k] = q * lat.p;
         b.len[k] = lat.p + 1;
       }
     }
   }
+  b.inv[0] = __builtin_amdgcn_rcpf((float)b.len[0]);
+  b.inv[1] = __builtin_amdgcn_rcpf((float)b.len[1]);
   return b;
 }
 
-// column of the k-th block of the row (first direction fastest)
+// Lattice box of row node `row`: for every direction the range of lattice
+// indices of the functions whose support meets the row's support (a vertex
+// index reaches one cell to each side, an interior index only its cell).
+__device__ __forceinline__ RowBox row_box(int64_t row, const LatticeInfo& lat) {
+  int c[3];
+  lattice_coords(row, lat, c);
+  return row_box_at(c, lat);
+}
+
+// Row start of a node in a matrix whose rows are the lattice nodes in order
+// and hold exactly their lattice boxes (the layout the SpMV checks before it
+// computes columns).  Along one direction, node g reaches len(g) nodes:
+// 2p + 1 for an inner vertex index, p + 1 for a boundary vertex or any
+// other index.  The box of node (x, y, z) holds len(x) len(y) len(z)
+// entries, so with S(g) = sum_{j<g} len(j) and T = S(n1) the entries before
+// it number S(z) T^2 + len(z) S(y) T + len(z) len(y) S(x).
+__device__ __forceinline__ int64_t lattice_len(int g, const LatticeInfo& lat) {
+  if (g != (int)fdiv((uint32_t)g, lat.dp) * lat.p) return lat.p + 1;
+  return (g == 0 || g == lat.n1 - 1) ? lat.p + 1 : 2 * lat.p + 1;
+}
+
+__device__ __forceinline__ int64_t lattice_prefix(int g, const LatticeInfo& lat) {
+  // every period of p indices holds one vertex and p - 1 other indices; the
+  // boundary vertices 0 and n1 - 1 reach p fewer nodes (the last one lies
+  // in a whole period only when p = 1)
+  const int p = lat.p;
+  const int q = (int)fdiv((uint32_t)g, lat.dp), rm = g - q * p;
+  int64_t s = (int64_t)q * (2 * p + 1 + (int64_t)(p - 1) * (p + 1));
+  if (q > 0) s -= p;
+  if ((int64_t)q * p > lat.n1 - 1) s -= p;
+  if (rm > 0) s += lattice_len(q * p, lat) + (int64_t)(rm - 1) * (p + 1);
+  return s;
+}
+
+__device__ __forceinline__ int64_t lattice_row_start_at(const int c[3], const RowBox& b,
+                                                        const LatticeInfo& lat) {
+  const int64_t T = lattice_prefix(lat.n1, lat);
+  // from the last direction down: S(c_k) T^k times the box lengths above k
+  int64_t base = 0, outer = 1;
+  if (lat.dim == 3) {
+    base += lattice_prefix(c[2], lat) * T * T;
+    outer = b.len[2];
+  }
+  if (lat.dim >= 2) {
+    base += lattice_prefix(c[1], lat) * T * outer;
+    outer *= b.len[1];
+  }
+  base += lattice_prefix(c[0], lat) * outer;
+  return base;
+}
+
+__device__ __forceinline__ int64_t lattice_row_start(int64_t row, const LatticeInfo& lat) {
+  int c[3];
+  lattice_coords(row, lat, c);
+  return lattice_row_start_at(c, row_box_at(c, lat), lat);
+}
+
+// column of the k-th block of the row (first direction fastest).  k < 2^12
+// and the lengths are small, so floor((k + 1/2) / len) from the approximate
+// reciprocal is exact: the quotient lies at least 1/(2 len) from an integer,
+// far beyond the reciprocal's relative error of about 2^-22.
 __device__ __forceinline__ int lattice_col(const RowBox& b, int k, int n1) {
-  const int kx = k % b.len[0], r = k / b.len[0];
-  const int ky = r % b.len[1], kz = r / b.len[1];
+  const int r = (int)(((float)k + 0.5f) * b.inv[0]);
+  const int kx = k - r * b.len[0];
+  const int kz = (int)(((float)r + 0.5f) * b.inv[1]);
+  const int ky = r - kz * b.len[1];
   return (b.lo[0] + kx) + n1 * ((b.lo[1] + ky) + n1 * (b.lo[2] + kz));
 }
 
@@ -214,6 +296,28 @@ __device__ __forceinline__ double pull_lattice_sum(const double* __restrict__ y,
     if (ix < cx.cnt && iy < cy.cnt && iz < cz.cnt) s += v[k];
   }
   return s;
+}
+
+// Node of local function loc of cell e on a lattice whose cells are the
+// blocks, in order (the inverse of cells_of: local index 0 is a cell's
+// left vertex, 1 its right vertex, 2 .. p its interior indices, tensor
+// order with the first direction fastest).
+__device__ __forceinline__ int64_t lattice_cell_node(const PullLattice L, int e, int loc) {
+  const int p1 = L.p + 1;
+  int64_t node = 0, stride = 1;
+  int ee = e, ll = loc;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    if (k < L.dim) {
+      const int c = ee % L.n, l = ll % p1;
+      ee /= L.n;
+      ll /= p1;
+      const int g = c * L.p + (l == 0 ? 0 : l == 1 ? L.p : l - 1);
+      node += g * stride;
+      stride *= L.n1;
+    }
+  }
+  return node;
 }
 
 // Unknown of row i of a block whose node list starts at nodes[e * nn]

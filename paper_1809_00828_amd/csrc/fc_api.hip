@@ -573,17 +573,23 @@ static fc_status precond_build_body(fc_problem pb, const fc_precond_opts* opts, 
   FC_HIP(hipMemcpyAsync(drop.data(), d_drop, drop.size() * sizeof(int32_t), hipMemcpyDeviceToHost, s));
   FC_HIP(hipStreamSynchronize(s));
   pc->n_fallback = (int64_t)cnt;
-  // scalar lattice problem with every cell a block, in cell order: the pull
-  // finds a node's blocks from its lattice indices (FC_PULL_LATTICE=0 keeps
-  // the node-to-block map).  With three components per node the mapped pull
-  // is faster (46 against 57 us at 32^3 cells, p = 3), so it stays there.
+  // scalar lattice problem with every cell a block, in cell order (checked
+  // row by row on the device): the block products find a row's unknown and
+  // the pull a node's blocks from lattice indices (FC_PULL_LATTICE=0 keeps
+  // the node lists and the node-to-block map).  With three components per
+  // node the mapped pull is faster (46 against 57 us at 32^3 cells, p = 3),
+  // so it stays there.
   {
     const char* env = std::getenv("FC_PULL_LATTICE");
     const bool allowed = !(env && std::atoi(env) == 0);
     if (allowed && !patch && pb->bdim == 1 && pb->dim >= 2 && pb->dim <= 3 && pb->n > 0 &&
         pb->p > 0 && nb == pb->n_el &&
-        nb == std::pow((double)pb->n, pb->dim) && pb->nn == (int)std::pow(pb->p + 1.0, pb->dim))
-      pc->lat = PullLattice{pb->dim, pb->n, pb->p, pb->p * pb->n + 1};
+        nb == std::pow((double)pb->n, pb->dim) && pb->nn == (int)std::pow(pb->p + 1.0, pb->dim)) {
+      const PullLattice L{pb->dim, pb->n, pb->p, pb->p * pb->n + 1};
+      bool ok = false;
+      FC_HIP(schwarz_check_lattice(*pc, L, &ok, s));
+      if (ok) pc->lat = L;
+    }
   }
   int64_t nd = 0;
   for (int64_t k = 0; k < nb; ++k) nd += drop[k];

@@ -48,9 +48,39 @@ struct CgScalars {
 // description (dim = 0 otherwise): the block columns of every row are the
 // lattice box spanned by the supports through the row's node, so they can
 // be computed instead of read.
+// Division of 32-bit unsigned numbers by an invariant d (Granlund and
+// Montgomery, division by invariant integers using multiplication): with
+// l = ceil(log2 d) and m = floor(2^32 (2^l - d) / d) + 1, the quotient is
+// (t + ((n - t) >> min(l, 1))) >> max(l - 1, 0), t = (m n) >> 32.
+struct FastDiv {
+  uint32_t d = 1, m = 1, s1 = 0, s2 = 0;
+};
+
+inline FastDiv make_fastdiv(uint32_t d) {
+  FastDiv f;
+  f.d = d;
+  uint32_t l = 0;
+  while ((uint64_t(1) << l) < d) ++l;
+  f.m = (uint32_t)(((uint64_t(1) << 32) * ((uint64_t(1) << l) - d)) / d + 1);
+  f.s1 = l > 0 ? 1u : 0u;
+  f.s2 = l > 0 ? l - 1 : 0u;
+  return f;
+}
+
 struct LatticeInfo {
   int32_t dim = 0, n1 = 0, p = 0;
+  FastDiv dn1, dp;   // division by n1 and by p
 };
+
+inline LatticeInfo make_lattice_info(int32_t dim, int32_t n1, int32_t p) {
+  LatticeInfo l;
+  l.dim = dim;
+  l.n1 = n1;
+  l.p = p;
+  l.dn1 = make_fastdiv((uint32_t)n1);
+  l.dp = make_fastdiv((uint32_t)p);
+  return l;
+}
 
 // Lattice of the element blocks when every cell of a problem set up from a
 // description is a block, in cell order (dim = 0 otherwise): the pull then

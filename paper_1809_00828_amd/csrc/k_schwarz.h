@@ -16,6 +16,11 @@ int64_t sym_block_stride(int m);
 // Q = wrapped-diagonal copy of the dense FP64 local inverses pc.P in FP64
 // (0), or diagonally scaled in FP32 (1) or BF16 (2) (needs pc.isd).
 hipError_t launch_pack_sym(const fc_precond_s& pc, void* Q, int precision, hipStream_t s);
+// Whether every row of every block of pc names the unknown the lattice L
+// gives it (block b = cell b, rows in the cells' local tensor order);
+// synchronises s.
+hipError_t schwarz_check_lattice(const fc_precond_s& pc, const PullLattice L, bool* ok,
+                                 hipStream_t s);
 // isd = 1/sqrt(diag(A)) (1 where the diagonal is not positive).
 hipError_t launch_inv_sqrt_diag(const fc_problem_s& pb, double* isd, hipStream_t s);
 }  // namespace fc

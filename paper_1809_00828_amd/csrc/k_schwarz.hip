@@ -101,14 +101,25 @@ __global__ __launch_bounds__(256) void k_schwarz_sym_staged(
 }
 
 // m <= 64: each wave handles floor(64/m) blocks, one lane per output row.
-template <typename T, bool kSym>
+// kM > 0 (symmetric layout, m = kM known at compile time): lane i loads its
+// column of the stored rows (Q_B[k][i] = P_B[i][(i + k) mod m], k = 0 ..
+// m/2) into registers before it gathers r_B, so the block's stream is in
+// flight during the gather; the entries P_B[i][(i - k) mod m] =
+// Q_B[k][(i - k) mod m] are then read from the lane that loaded them (a
+// cross-lane read within the wave).  kM = 0: any m, the stored rows read
+// after the gather (sym_row / dense_row).  kLat: the blocks are the cells of
+// a lattice in order, so a row's unknown follows from the block and row
+// indices and the gather of r_B is issued together with the stored rows.
+template <typename T, bool kSym, int kM, bool kLat>
 __global__ __launch_bounds__(256) void k_schwarz_small(
     const T* __restrict__ P, int64_t block_stride, const int32_t* __restrict__ elem_nodes,
-    const int32_t* __restrict__ block_elem, int nn, int bd, int m,
+    const int32_t* __restrict__ block_elem, int nn, int bd, int m_arg,
     const double* __restrict__ r, const double* __restrict__ q, const double* __restrict__ isd,
-    const CgScalars* __restrict__ sc, double* __restrict__ y, int64_t n_blocks) {
+    const CgScalars* __restrict__ sc, double* __restrict__ y, int64_t n_blocks,
+    const PullLattice lat) {
   __shared__ double rB[4][64];
   if (sc && sc->done) return;
+  const int m = kM > 0 ? kM : m_arg;
   const double alpha = (sc && q) ? sc->alpha : 0.0;
   const int bpw = 64 / m;
   const int w = threadIdx.x / 64, l = threadIdx.x % 64;
@@ -116,18 +127,60 @@ __global__ __launch_bounds__(256) void k_schwarz_small(
   const int64_t tile = xcd_remap(blockIdx.x, gridDim.x);
   const int64_t blk = (tile * 4 + w) * bpw + lb;
   const bool active = lb < bpw && blk < n_blocks;
+  // lanes without a block read block 0 (always present) and store nothing
+  const T* Pb = P + (active ? blk : 0) * block_stride;
+  using A = typename Acc<T>::type;
+  constexpr int kH = kM / 2;
+  T v[kH + 1];
   int64_t dof = -1;
-  if (active) {
-    const int64_t e = block_elem[blk];
-    dof = block_dof(elem_nodes, e, nn, bd, i);
-    rB[w][l] = dof >= 0 ? gather_r(r, q, alpha, dof) * (isd ? isd[dof] : 1.0) : 0.0;
+  double rv = 0.0;
+  double g_r = 0.0, g_q = 0.0, g_s = 1.0;
+  if constexpr (kLat) {
+    // the gathered entries are loaded first and the stored rows next, all
+    // without branches (a lane without a block reads unknown 0), and only
+    // then combined: the wait for the gather does not wait for the rows
+    dof = active ? lattice_cell_node(lat, (int)blk, i / bd) * bd + i % bd : 0;
+    g_r = r[dof];
+    g_q = (q ? q : r)[dof];
+    g_s = (isd ? isd : r)[dof];
   }
+  if constexpr (kSym && kM > 0) {
+#pragma unroll
+    for (int k = 0; k <= kH; ++k) v[k] = Pb[k * kM + i];
+  }
+  if constexpr (kLat) {
+    rv = (q ? fma(-alpha, g_q, g_r) : g_r) * (isd ? g_s : 1.0);
+  } else {
+    if (active) {
+      dof = block_dof(elem_nodes, block_elem[blk], nn, bd, i);
+      rv = dof >= 0 ? gather_r(r, q, alpha, dof) * (isd ? isd[dof] : 1.0) : 0.0;
+    }
+  }
+  if (active) rB[w][l] = rv;
   __syncthreads();
+  double out;
+  if constexpr (kSym && kM > 0) {
+    // every lane takes part in the cross-lane reads; a lane without a block
+    // reads its own group's entries and discards the result
+    const int g0 = (active ? lb : 0) * kM;
+    const double* rb = &rB[w][g0];
+    A acc0 = madd<A>(v[0], rb[i], A(0)), acc1 = 0;
+#pragma unroll
+    for (int k = 1; k <= kH; ++k) {
+      const int ip = i + k < kM ? i + k : i + k - kM;   // (i + k) mod m
+      const int im = i >= k ? i - k : i - k + kM;       // (i - k) mod m
+      const T vr = __shfl(v[k], g0 + im, 64);
+      acc0 = madd<A>(v[k], rb[ip], acc0);
+      if (!((kM & 1) == 0 && k == kH)) acc1 = madd<A>(vr, rb[im], acc1);
+    }
+    out = (double)acc0 + (double)acc1;
+  } else {
+    if (!active) return;
+    const double* rb = &rB[w][lb * m];
+    out = kSym ? sym_row<T>(Pb, rb, m, i) : dense_row<T>(Pb, rb, m, i);
+  }
   if (!active) return;
-  const double* rb = &rB[w][lb * m];
-  const T* Pb = P + blk * block_stride;
-  const double v = kSym ? sym_row<T>(Pb, rb, m, i) : dense_row<T>(Pb, rb, m, i);
-  y[blk * m + i] = dof < 0 ? 0.0 : isd ? v * isd[dof] : v;
+  y[blk * m + i] = dof < 0 ? 0.0 : isd ? out * isd[dof] : out;
 }
 
 // Factored low-precision product y_B = D^{-1/2} Lt (Lt^T (D^{-1/2} r_B)) with
@@ -372,6 +425,42 @@ hipError_t launch_pack_sym(const fc_precond_s& pc, void* Q, int precision, hipSt
   return hipGetLastError();
 }
 
+// rows whose unknown differs from the lattice's (counted with an atomic only
+// where one occurs)
+__global__ void k_check_cell_lattice(const int32_t* __restrict__ nodes,
+                                     const int32_t* __restrict__ block_elem, int nn, int bd,
+                                     int m, int64_t n_blocks, const PullLattice L,
+                                     unsigned long long* __restrict__ bad) {
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n_blocks * m;
+       t += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t b = t / m;
+    const int i = (int)(t - b * m);
+    const int64_t want = lattice_cell_node(L, (int)b, i / bd) * bd + i % bd;
+    if (block_elem[b] != b || block_dof(nodes, b, nn, bd, i) != want) atomicAdd(bad, 1ull);
+  }
+}
+
+hipError_t schwarz_check_lattice(const fc_precond_s& pc, const PullLattice L, bool* ok,
+                                 hipStream_t s) {
+  *ok = false;
+  if (pc.n_blocks == 0) return hipSuccess;
+  unsigned long long* bad = nullptr;
+  hipError_t e = hipMalloc(&bad, sizeof(*bad));
+  if (e != hipSuccess) return e;
+  unsigned long long hbad = 1;
+  e = hipMemsetAsync(bad, 0, sizeof(*bad), s);
+  if (e == hipSuccess) {
+    hipLaunchKernelGGL(k_check_cell_lattice, dim3(2048), dim3(256), 0, s, block_nodes(pc),
+                       pc.block_elem, pc.nn, pc.bdim, pc.m, pc.n_blocks, L, bad);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) e = hipMemcpyAsync(&hbad, bad, sizeof(hbad), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  (void)hipFree(bad);
+  *ok = e == hipSuccess && hbad == 0;
+  return e;
+}
+
 __global__ void k_inv_sqrt_diag(const double* __restrict__ d, double* __restrict__ isd, int64_t n) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x)
@@ -409,9 +498,36 @@ static hipError_t phase1(const fc_precond_s& pc, const T* P, const double* r, co
     const int bpw = 64 / pc.m;
     const int64_t per_wg = 4 * (int64_t)bpw;
     const int64_t nwg = (pc.n_blocks + per_wg - 1) / per_wg;
-    hipLaunchKernelGGL((k_schwarz_small<T, kSym>), dim3((unsigned)nwg), dim3(256), 0, s, P, stride,
-                       block_nodes(pc), pc.block_elem, pc.nn, pc.bdim, pc.m, r, q, isd, sc, pc.y,
-                       pc.n_blocks);
+    // the block sizes of scalar and vector problems at p = 1..3 (2-D and
+    // 3-D) have their own compiled kernels
+    const bool lat = pc.lat.dim > 0;
+#define FC_SMALL_LAUNCH(KM)                                                                    \
+  do {                                                                                         \
+    if (lat && KM > 0)                                                                         \
+      hipLaunchKernelGGL((k_schwarz_small<T, kSym, KM, true>), dim3((unsigned)nwg), dim3(256), \
+                         0, s, P, stride, block_nodes(pc), pc.block_elem, pc.nn, pc.bdim, pc.m, \
+                         r, q, isd, sc, pc.y, pc.n_blocks, pc.lat);                            \
+    else                                                                                       \
+      hipLaunchKernelGGL((k_schwarz_small<T, kSym, KM, false>), dim3((unsigned)nwg),           \
+                         dim3(256), 0, s, P, stride, block_nodes(pc), pc.block_elem, pc.nn,    \
+                         pc.bdim, pc.m, r, q, isd, sc, pc.y, pc.n_blocks, pc.lat);             \
+  } while (0)
+    switch (kSym ? pc.m : 0) {
+      case 8: FC_SMALL_LAUNCH(8); break;
+      case 9: FC_SMALL_LAUNCH(9); break;
+      case 16: FC_SMALL_LAUNCH(16); break;
+      case 18: FC_SMALL_LAUNCH(18); break;
+      case 24: FC_SMALL_LAUNCH(24); break;
+      case 25: FC_SMALL_LAUNCH(25); break;
+      case 27: FC_SMALL_LAUNCH(27); break;
+      case 32: FC_SMALL_LAUNCH(32); break;
+      case 36: FC_SMALL_LAUNCH(36); break;
+      case 49: FC_SMALL_LAUNCH(49); break;
+      case 50: FC_SMALL_LAUNCH(50); break;
+      case 64: FC_SMALL_LAUNCH(64); break;
+      default: FC_SMALL_LAUNCH(0); break;
+    }
+#undef FC_SMALL_LAUNCH
   }
   return hipGetLastError();
 }

@@ -65,11 +65,22 @@ __global__ __launch_bounds__(256) void k_spmv_bsr(
     const int64_t idx = tile * RPW + threadIdx.x / G;
     if (idx >= n_rows) continue;
     const int64_t row = rows ? (int64_t)rows[idx] : idx;
-    const int64_t base = rowptr[row];
-    const int L = rowptr[row + 1] - (int32_t)base;
-    const T* v = val + base * BB;
+    // on the lattice the row's start and length follow from its indices,
+    // so the value stream does not wait for a row-pointer load
     RowBox box;
-    if constexpr (kLat) box = row_box(row, lat);
+    int64_t base;
+    int L;
+    if constexpr (kLat) {
+      int c[3];
+      lattice_coords(row, lat, c);
+      box = row_box_at(c, lat);
+      base = lattice_row_start_at(c, box, lat);
+      L = box.len[0] * box.len[1] * box.len[2];
+    } else {
+      base = rowptr[row];
+      L = rowptr[row + 1] - (int32_t)base;
+    }
+    const T* v = val + base * BB;
     double acc[B];
     float accf[B];
 #pragma unroll
@@ -222,8 +233,8 @@ hipError_t launch_spmv(const DeviceBsr& A, const double* x, double* y, hipStream
 
 int spmv_num_blocks(const DeviceBsr& A) { return (int)fused_grid(A); }
 
-// mismatches between stored columns and lattice boxes (counted with an
-// atomic only where one occurs)
+// mismatches between stored rows and lattice boxes: length, start and
+// columns (counted with an atomic only where one occurs)
 __global__ void k_check_lattice(const int32_t* __restrict__ rowptr, const int32_t* __restrict__ col,
                                 int64_t n_rows, const LatticeInfo lat,
                                 unsigned long long* __restrict__ bad) {
@@ -232,7 +243,7 @@ __global__ void k_check_lattice(const int32_t* __restrict__ rowptr, const int32_
     const RowBox b = row_box(row, lat);
     const int64_t base = rowptr[row];
     const int L = rowptr[row + 1] - (int32_t)base;
-    int miss = L != b.len[0] * b.len[1] * b.len[2];
+    int miss = L != b.len[0] * b.len[1] * b.len[2] || base != lattice_row_start(row, lat);
     for (int k = 0; k < L && !miss; ++k) miss = col[base + k] != lattice_col(b, k, lat.n1);
     if (miss) atomicAdd(bad, 1ull);
   }
@@ -248,7 +259,7 @@ hipError_t spmv_enable_lattice(DeviceBsr& A, int dim, int n1, int p, hipStream_t
   hipError_t e = hipMalloc(&bad, sizeof(*bad));
   if (e != hipSuccess) return e;
   unsigned long long hbad = 1;
-  const LatticeInfo lat{dim, n1, p};
+  const LatticeInfo lat = make_lattice_info(dim, n1, p);
   e = hipMemsetAsync(bad, 0, sizeof(*bad), s);
   if (e == hipSuccess) {
     hipLaunchKernelGGL(k_check_lattice, dim3(2048), dim3(256), 0, s, A.rowptr, A.col, A.n_rows,
