@@ -17,4 +17,6 @@ schwarz   additive Schwarz blocks (Eq. 6), pseudo-inverses (Eqs. 9-11),
           Algorithm 1 with its diagonal-scaling fallback
 pcg       preconditioned CG, the stopping criterion (Eq. 12), the energy
           error (Eq. 13) and a direct reference solve
+ebe       element-by-element forms of A and S (no global matrix), for the
+          CPU timing of the full benchmark problem
 """

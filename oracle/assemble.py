@@ -252,11 +252,12 @@ def clamped_dofs(desc):
     return (nc * nodes[:, None] + np.arange(nc)[None, :]).ravel()
 
 
-def assemble(desc, keep_cells=None):
+def assemble(desc, keep_cells=None, keep_elements=False):
     """Assemble the global system.
 
     Returns a dict with A (scipy CSR), b, eta (per cell, cell index order),
-    elem_dofs (n_cells, m) and the list of cells.
+    elem_dofs (n_cells, m) and the list of cells; with keep_elements also
+    Ke, the element stiffness matrices (n_cells, m, m) in cell order.
     """
     ndof = n_dofs(desc)
     rows, cols, vals = [], [], []
@@ -264,8 +265,11 @@ def assemble(desc, keep_cells=None):
     cl = list(cells(desc))
     eta = np.zeros(len(cl))
     edofs = []
+    kes = []
     for ci, cell in enumerate(cl):
         Ke, fe, et = element_system(desc, cell)
+        if keep_elements:
+            kes.append(Ke)
         fe = fe + traction_load(desc, cell)
         dofs = element_dofs(desc, cell)
         edofs.append(dofs)
@@ -281,8 +285,10 @@ def assemble(desc, keep_cells=None):
     A, b = apply_clamp(desc, A, b)
     if desc.get("discard_fictitious"):
         A, b = remove_dofs(A, b, fictitious_dofs(np.array(edofs), eta, ndof))
-    return {"A": A, "b": b, "eta": eta, "elem_dofs": np.array(edofs),
-            "cells": cl}
+    out = {"A": A, "b": b, "eta": eta, "elem_dofs": np.array(edofs), "cells": cl}
+    if keep_elements:
+        out["Ke"] = np.array(kes)
+    return out
 
 
 def fictitious_dofs(elem_dofs, eta, ndof):

@@ -43,13 +43,14 @@ __device__ __forceinline__ T stream_load(const T* p) {
 // kLat: columns computed from the lattice box (col is not read).
 // XT: type of x (FP32 for the FP32 rows of the mixed product, which round
 // x to FP32 before every product anyway).
-template <int B, int G, typename T, bool kLat, typename XT>
+// U: blocks per lane per pass (all loads of a pass are in flight together).
+// kNT: stream the matrix values non-temporally.
+template <int B, int G, typename T, bool kLat, typename XT, int U, bool kNT>
 __global__ __launch_bounds__(256) void k_spmv_bsr(
     const int32_t* __restrict__ rowptr, const int32_t* __restrict__ col,
     const T* __restrict__ val, const XT* __restrict__ x,
     double* __restrict__ y, int64_t n_rows, const CgScalars* __restrict__ sc,
     double* __restrict__ partial, const int32_t* __restrict__ rows, const LatticeInfo lat) {
-  constexpr bool kNT = B != 1 && sizeof(T) == 8;
   constexpr int BB = B * B;
   constexpr int RPW = 256 / G;   // rows per tile
   __shared__ double lds[16];
@@ -88,10 +89,6 @@ __global__ __launch_bounds__(256) void k_spmv_bsr(
       acc[i] = 0.0;
       accf[i] = 0.0f;
     }
-    // U blocks per lane per pass: all loads of a pass are in flight
-    // together (scalar rows: eight, which on 64^3-cell p = 2 rows is 6 %
-    // faster than four; 3x3 blocks carry nine values each, so two)
-    constexpr int U = B == 1 ? 8 : 2;
     for (int k = lane; k < L; k += U * G) {
       int c[U];
       T a[U][BB];
@@ -196,14 +193,31 @@ static hipError_t spmv_dispatch(const DeviceBsr& A, const T* val, const XT* x,
   static const bool lat_allowed = env_int("FC_SPMV_LATTICE", 1) != 0;
   const bool lat = lat_allowed && A.lat.dim > 0;
   dim3 grid((unsigned)nb), block(256);
-#define FC_SPMV_CASE(GG)                                                                   \
-  case GG:                                                                                 \
-    if (lat)                                                                               \
-      hipLaunchKernelGGL((k_spmv_bsr<B, GG, T, true, XT>), grid, block, 0, s, A.rowptr,     \
-                         A.col, val, x, y, n_rows, sc, partial, rows, A.lat);              \
-    else                                                                                   \
-      hipLaunchKernelGGL((k_spmv_bsr<B, GG, T, false, XT>), grid, block, 0, s, A.rowptr,    \
-                         A.col, val, x, y, n_rows, sc, partial, rows, A.lat);              \
+  // 3x3 blocks: two per lane per pass (nine values each), FP64 values
+  // non-temporal.  Scalar rows: eight per lane per pass through the caches
+  // (FC_SPMV_PASS=16 and FC_SPMV_NT=1 select sixteen and the non-temporal
+  // stream for FP64 scalar rows on the lattice).
+  static const int pass16 = env_int("FC_SPMV_PASS", 8) == 16;
+  static const int nt1 = env_int("FC_SPMV_NT", 0) == 1;
+  constexpr bool kNT3 = B != 1 && sizeof(T) == 8;
+  constexpr int kU = B == 1 ? 8 : 2;
+#define FC_SPMV_LAUNCH(GG, LAT, UU, NT)                                                      \
+  hipLaunchKernelGGL((k_spmv_bsr<B, GG, T, LAT, XT, UU, NT>), grid, block, 0, s, A.rowptr,   \
+                     A.col, val, x, y, n_rows, sc, partial, rows, A.lat)
+#define FC_SPMV_CASE(GG)                                                                     \
+  case GG:                                                                                   \
+    if (lat) {                                                                               \
+      if constexpr (B == 1 && sizeof(T) == 8) {                                              \
+        if (pass16 && nt1) FC_SPMV_LAUNCH(GG, true, 16, true);                               \
+        else if (pass16) FC_SPMV_LAUNCH(GG, true, 16, false);                                \
+        else if (nt1) FC_SPMV_LAUNCH(GG, true, 8, true);                                     \
+        else FC_SPMV_LAUNCH(GG, true, 8, false);                                             \
+      } else {                                                                               \
+        FC_SPMV_LAUNCH(GG, true, kU, kNT3);                                                  \
+      }                                                                                      \
+    } else {                                                                                 \
+      FC_SPMV_LAUNCH(GG, false, kU, kNT3);                                                   \
+    }                                                                                        \
     break;
   switch (G) {
     FC_SPMV_CASE(8)
@@ -212,6 +226,7 @@ static hipError_t spmv_dispatch(const DeviceBsr& A, const T* val, const XT* x,
     FC_SPMV_CASE(64)
   }
 #undef FC_SPMV_CASE
+#undef FC_SPMV_LAUNCH
   return hipGetLastError();
 }
 
