@@ -21,6 +21,26 @@ __device__ __forceinline__ uint32_t xcd_remap(uint32_t bid, uint32_t nwg) {
   return (x < r) ? x * (q + 1) + j : r * (q + 1) + (x - r) * q + j;
 }
 
+// Contiguous tile range [t0, t1) of the XCD of workgroup bid, walked by
+// that XCD's workgroups from j with stride per.  Workgroups are dealt out
+// round-robin over min(nwg, kNumXcd) XCDs, so a grid with fewer workgroups
+// than XCDs still covers every tile.
+struct XcdRange {
+  int64_t t0, t1;
+  uint32_t j, per;
+};
+
+__device__ __forceinline__ XcdRange xcd_range(uint32_t bid, uint32_t nwg, int64_t ntiles) {
+  const uint32_t nx = nwg < (uint32_t)kNumXcd ? nwg : (uint32_t)kNumXcd;
+  const uint32_t x = bid % nx;
+  XcdRange r;
+  r.j = bid / nx;
+  r.per = nwg / nx + (x < nwg % nx ? 1u : 0u);
+  r.t0 = ntiles * x / nx;
+  r.t1 = ntiles * (x + 1) / nx;
+  return r;
+}
+
 template <int W, typename T>
 __device__ __forceinline__ T group_sum(T v) {
 #pragma unroll

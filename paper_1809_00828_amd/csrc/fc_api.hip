@@ -61,7 +61,8 @@ static fc_status upload(T** p, const T* src, size_t count) {
 static void free_problem(fc_problem_s* pb) {
   if (!pb) return;
   for (void* p : {(void*)pb->A.rowptr, (void*)pb->A.col, (void*)pb->A.val, (void*)pb->A.val32,
-                  (void*)pb->A.rows_hi, (void*)pb->A.rows_lo, (void*)pb->rhs,
+                  (void*)pb->A.rows_hi, (void*)pb->A.rows_lo, (void*)pb->A.sell_val,
+                  (void*)pb->A.sell_off, (void*)pb->A.sell_rest, (void*)pb->rhs,
                   (void*)pb->elem_nodes, (void*)pb->diag})
     if (p) (void)hipFree(p);
   delete pb;

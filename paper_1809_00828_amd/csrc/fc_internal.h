@@ -106,6 +106,19 @@ struct DeviceBsr {
   int32_t* rows_hi = nullptr;
   int32_t* rows_lo = nullptr;
   int64_t n_hi = 0, n_lo = 0;
+  // Sliced copy of a scalar lattice matrix (degree p <= 4): the rows of one
+  // lattice line (fixed y, z) and one x class, interior vertex indices
+  // (x = p, 2p, ..) or the other interior indices, in slices of 64 rows
+  // whose boxes have equal shape; entry k of lane l of slice s at
+  // sell_val[sell_off[s] + 64 k + l] (zero for lanes past the class's end).
+  // The boundary vertex rows (x = 0 and x = n1 - 1) are listed in sell_rest
+  // and use the row layout.
+  double* sell_val = nullptr;
+  int64_t* sell_off = nullptr;   // [n_slices + 1]
+  int64_t n_slices = 0;
+  int32_t sell_cv = 0, sell_nv = 0, sell_nn = 0;   // vertex slices per line, rows per class
+  int32_t* sell_rest = nullptr;
+  int64_t n_rest = 0;
 };
 
 struct SolverWs;

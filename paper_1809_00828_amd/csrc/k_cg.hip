@@ -1148,6 +1148,12 @@ fc_status pcg_solve_noalloc(fc_precond_s& pc, const double* b, double* x, const 
     set_error("fc_pcg_solve_noalloc: the current device is not the problem's");
     return FC_E_ARG;
   }
+  // the SpMV with its fused dot (FC_CG_SPLIT_DOT=0) leaves one partial per
+  // workgroup, which must fit the scratch's partial sums
+  if (!split_dot() && (int64_t)spmv_num_blocks(pb.A) > (kNoAllocPartials - 8) / 4) {
+    set_error("fc_pcg_solve_noalloc: too many SpMV partials for the fused dot");
+    return FC_E_UNSUPPORTED;
+  }
   double* base = nullptr;
   FC_TRY_ST(scratch_for(dev, &base));
   // a workspace view of the scratch: only the members the FP64 steps use

@@ -21,6 +21,7 @@
 // per workgroup; a one-workgroup kernel of the solver sums them in a fixed
 // order (no atomics).
 #include <cstdlib>
+#include <vector>
 
 #include "dev_common.h"
 #include "k_spmv.h"
@@ -57,9 +58,9 @@ __global__ __launch_bounds__(256) void k_spmv_bsr(
   if (sc && sc->done) return;
   const int64_t ntiles = (n_rows + RPW - 1) / RPW;
   // XCD-contiguous tile ranges
-  const uint32_t nwg = gridDim.x, xcd = blockIdx.x % kNumXcd, j = blockIdx.x / kNumXcd;
-  const uint32_t per = nwg / kNumXcd + (xcd < nwg % kNumXcd ? 1u : 0u);
-  const int64_t t0 = ntiles * xcd / kNumXcd, t1 = ntiles * (xcd + 1) / kNumXcd;
+  const XcdRange xr_ = xcd_range(blockIdx.x, gridDim.x, ntiles);
+  const uint32_t j = xr_.j, per = xr_.per;
+  const int64_t t0 = xr_.t0, t1 = xr_.t1;
   const int lane = threadIdx.x % G;
   double dot = 0.0;
   for (int64_t tile = t0 + j; tile < t1; tile += per) {
@@ -141,6 +142,326 @@ __global__ __launch_bounds__(256) void k_spmv_bsr(
   if (threadIdx.x == 0) partial[blockIdx.x] = dot;
 }
 
+// Scalar rows on the lattice of a degree-P problem.  The box of a row is a
+// set of x-pencils, runs of len[0] <= 2P + 1 consecutive columns whose
+// values are consecutive too (the first direction runs fastest), so a lane
+// takes whole pencils: one column computation per pencil, then loads at
+// fixed offsets and one FMA per entry.  The pencil count len[1] len[2]
+// depends only on the row's y and z indices, which the consecutive rows of
+// a wave share, so the lanes of a wave run the same number of pencils.
+template <int G, typename T, typename XT, int P>
+__global__ __launch_bounds__(256) void k_spmv_pencil(
+    const T* __restrict__ val, const XT* __restrict__ x, double* __restrict__ y, int64_t n_rows,
+    const CgScalars* __restrict__ sc, double* __restrict__ partial,
+    const int32_t* __restrict__ rows, const LatticeInfo lat) {
+  constexpr int RPW = 256 / G;
+  constexpr int KX = 2 * P + 1;
+  __shared__ double lds[16];
+  if (sc && sc->done) return;
+  const int64_t ntiles = (n_rows + RPW - 1) / RPW;
+  const XcdRange xr_ = xcd_range(blockIdx.x, gridDim.x, ntiles);
+  const uint32_t j0 = xr_.j, per = xr_.per;
+  const int64_t t0 = xr_.t0, t1 = xr_.t1;
+  const int lane = threadIdx.x % G;
+  const int64_t n1 = lat.n1;
+  double dot = 0.0;
+  for (int64_t tile = t0 + j0; tile < t1; tile += per) {
+    const int64_t idx = tile * RPW + threadIdx.x / G;
+    if (idx >= n_rows) continue;
+    const int64_t row = rows ? (int64_t)rows[idx] : idx;
+    int c[3];
+    lattice_coords(row, lat, c);
+    const RowBox box = row_box_at(c, lat);
+    const int64_t base = lattice_row_start_at(c, box, lat);
+    const int len0 = box.len[0], np = box.len[1] * box.len[2];
+    double acc = 0.0;
+    float accf = 0.0f;
+    // two pencils per round, all their loads issued before the first is
+    // used: entries past a pencil's end, and the second pencil past the
+    // last, read a valid neighbour and are multiplied as zero
+    for (int j = lane; j < np; j += 2 * G) {
+      T va[2][KX];
+      XT xa[2][KX];
+      bool on[2];
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int jj = j + h * G;
+        on[h] = jj < np;
+        const int jc = on[h] ? jj : j;
+        // pencil jc = jy + len[1] jz (the float quotient is exact, as in
+        // lattice_col)
+        const int jz = (int)(((float)jc + 0.5f) * box.inv[1]);
+        const int jy = jc - jz * box.len[1];
+        const T* vp = val + base + (int64_t)jc * len0;
+        const XT* xp = x + box.lo[0] + n1 * ((box.lo[1] + jy) + n1 * (box.lo[2] + jz));
+#pragma unroll
+        for (int kx = 0; kx < KX; ++kx) {
+          const int kc = kx <= P ? kx : min(kx, len0 - 1);   // every pencil holds P + 1
+          va[h][kx] = vp[kc];
+          xa[h][kx] = xp[kc];
+        }
+      }
+#pragma unroll
+      for (int h = 0; h < 2; ++h)
+#pragma unroll
+        for (int kx = 0; kx < KX; ++kx) {
+          const bool use = on[h] && (kx <= P || kx < len0);
+          if constexpr (sizeof(T) == 8)
+            acc = fma(use ? (double)va[h][kx] : 0.0, (double)xa[h][kx], acc);
+          else
+            accf = fmaf(use ? (float)va[h][kx] : 0.0f, (float)xa[h][kx], accf);
+        }
+    }
+    if constexpr (sizeof(T) == 8)
+      acc = group_sum<G>(acc);
+    else
+      acc = (double)group_sum<G>(accf);
+    if (lane == 0) {
+      y[row] = acc;
+      if (partial) dot = fma((double)x[row], acc, dot);
+    }
+  }
+  if (!partial) return;
+  dot = block_sum(dot, lds);
+  if (threadIdx.x == 0) partial[blockIdx.x] = dot;
+}
+
+// Scalar rows on the lattice of a degree-P problem, one workgroup per run
+// of at most 32 consecutive rows of one lattice line (fixed y and z).  The
+// boxes of those rows share their y and z ranges, so the x entries they
+// gather form a window of len[1] len[2] pencil lines of at most 32 + 2P
+// nodes, which the workgroup stages in LDS with coalesced loads; then the
+// eight lanes of each row stream its values (contiguous) and read x from
+// LDS.  Only the value stream and the staging go through the vector memory
+// address unit, not one scattered gather per entry.
+template <typename T, typename XT, int P>
+__global__ __launch_bounds__(256) void k_spmv_line(const T* __restrict__ val,
+                                                   const XT* __restrict__ x,
+                                                   double* __restrict__ y,
+                                                   const CgScalars* __restrict__ sc,
+                                                   const LatticeInfo lat, int nseg) {
+  constexpr int G = 8, RPW = 256 / G;
+  constexpr int WMAX = RPW + 2 * P;           // window width
+  constexpr int NPMAX = (2 * P + 1) * (2 * P + 1);
+  __shared__ XT xs[NPMAX * WMAX];
+  if (sc && sc->done) return;
+  const int n1 = lat.n1;
+  const int64_t nlines = lat.dim == 3 ? (int64_t)n1 * n1 : lat.dim == 2 ? n1 : 1;
+  const int64_t ntiles = nlines * nseg;
+  // XCD-contiguous tile ranges: consecutive lines share an XCD's L2
+  const XcdRange xr_ = xcd_range(blockIdx.x, gridDim.x, ntiles);
+  const uint32_t j0 = xr_.j, per = xr_.per;
+  const int64_t t0 = xr_.t0, t1 = xr_.t1;
+  const int lane = threadIdx.x % G, r = threadIdx.x / G;
+  for (int64_t tile = t0 + j0; tile < t1; tile += per) {
+    const int64_t line = tile / nseg;
+    const int seg = (int)(tile - line * nseg);
+    const int y0 = lat.dim >= 2 ? (int)(line % n1) : 0;
+    const int z0 = lat.dim == 3 ? (int)(line / n1) : 0;
+    const int xa = (int)((int64_t)seg * n1 / nseg), xb = (int)((int64_t)(seg + 1) * n1 / nseg);
+    // the line's box in y and z (every row of the run shares it)
+    const int cl[3] = {xa, y0, z0};
+    const RowBox lb = row_box_at(cl, lat);
+    const int wx0 = max(0, xa - P), wx1 = min(n1 - 1, xb - 1 + P);
+    const int W = wx1 - wx0 + 1;
+    const int np = lb.len[1] * lb.len[2];
+    __syncthreads();   // the previous run's reads of the window are done
+    for (int e = threadIdx.x; e < np * W; e += 256) {
+      const int q = e / W, xo = e - q * W;
+      const int jz = q / lb.len[1], jy = q - jz * lb.len[1];
+      xs[q * WMAX + xo] =
+          x[(int64_t)(wx0 + xo) + (int64_t)n1 * ((lb.lo[1] + jy) + (int64_t)n1 * (lb.lo[2] + jz))];
+    }
+    __syncthreads();
+    const int xr = xa + r;
+    if (xr >= xb) continue;
+    const int c[3] = {xr, y0, z0};
+    const RowBox box = row_box_at(c, lat);
+    const int64_t base = lattice_row_start_at(c, box, lat);
+    const int64_t row = xr + (int64_t)n1 * (y0 + (int64_t)n1 * z0);
+    const int len0 = box.len[0], L = len0 * np;
+    const int off = box.lo[0] - wx0;
+    const T* v = val + base;
+    double acc = 0.0;
+    float accf = 0.0f;
+    constexpr int U = 8;
+    for (int k = lane; k < L; k += U * G) {
+      T a[U];
+      XT xv[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int ku = k + u * G;
+        const bool on = ku < L;
+        a[u] = on ? v[ku] : T(0);
+        // entry ku = kx + len0 q (the float quotient is exact, as in
+        // lattice_col)
+        const int q = (int)(((float)ku + 0.5f) * box.inv[0]);
+        const int kx = ku - q * len0;
+        xv[u] = on ? xs[q * WMAX + off + kx] : XT(0);
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        if constexpr (sizeof(T) == 8)
+          acc = fma((double)a[u], (double)xv[u], acc);
+        else
+          accf = fmaf((float)a[u], (float)xv[u], accf);
+      }
+    }
+    if constexpr (sizeof(T) == 8)
+      acc = group_sum<G>(acc);
+    else
+      acc = (double)group_sum<G>(accf);
+    if (lane == 0) y[row] = acc;
+  }
+}
+
+// ---------------------------------------------------------------- sliced
+// Lattice range of the functions whose support meets that of index g along
+// one direction (as in row_box_at).
+__device__ __forceinline__ void dir_box(int g, const LatticeInfo& lat, int* lo, int* len) {
+  const int p = lat.p;
+  if (g % p == 0) {
+    const int a = max(0, g - p), b = min(lat.n1 - 1, g + p);
+    *lo = a;
+    *len = b - a + 1;
+  } else {
+    *lo = (g / p) * p;
+    *len = p + 1;
+  }
+}
+
+// x index of lane row i of a class: interior vertices x = p (i + 1), other
+// interior indices in ascending order (p - 1 per cell; none when p = 1)
+__device__ __forceinline__ int sell_x(bool vertex, int i, int p) {
+  if (vertex || p == 1) return p * (i + 1);
+  return (i / (p - 1)) * p + 1 + i % (p - 1);
+}
+
+template <int P>
+__device__ __forceinline__ int sell_x_p(bool vertex, int i) {
+  if constexpr (P == 1) {
+    return i + 1;
+  } else {
+    return vertex ? P * (i + 1) : (i / (P - 1)) * P + 1 + i % (P - 1);
+  }
+}
+
+struct SellSlice {
+  int64_t line;
+  bool vertex;
+  int chunk;
+};
+
+__device__ __forceinline__ SellSlice sell_slice(int64_t s, int cv, int cn) {
+  SellSlice r;
+  const int spl = cv + cn;
+  r.line = s / spl;
+  const int loc = (int)(s - r.line * spl);
+  r.vertex = loc < cv;
+  r.chunk = r.vertex ? loc : loc - cv;
+  return r;
+}
+
+// sell_val from the row layout, one workgroup per slice
+__global__ __launch_bounds__(256) void k_sell_build(const double* __restrict__ val,
+                                                    const int64_t* __restrict__ off,
+                                                    int64_t n_slices, int cv, int cn, int nv,
+                                                    int nn, const LatticeInfo lat,
+                                                    double* __restrict__ sv) {
+  for (int64_t s = blockIdx.x; s < n_slices; s += gridDim.x) {
+    const SellSlice sl = sell_slice(s, cv, cn);
+    const int n1 = lat.n1;
+    const int y0 = lat.dim >= 2 ? (int)(sl.line % n1) : 0;
+    const int z0 = lat.dim == 3 ? (int)(sl.line / n1) : 0;
+    const int64_t len = (off[s + 1] - off[s]) / 64;
+    for (int64_t e = threadIdx.x; e < 64 * len; e += blockDim.x) {
+      const int k = (int)(e / 64), l = (int)(e % 64);
+      const int i = sl.chunk * 64 + l;
+      double v = 0.0;
+      if (i < (sl.vertex ? nv : nn)) {
+        const int c[3] = {sell_x(sl.vertex, i, lat.p), y0, z0};
+        v = val[lattice_row_start_at(c, row_box_at(c, lat), lat) + k];
+      }
+      sv[off[s] + e] = v;
+    }
+  }
+}
+
+// y = A x on the sliced rows: one wave per slice, one row per lane.  The
+// box entries run x-pencil by x-pencil (kx fastest); every lane of a slice
+// has the same pencil count and length, so the pencil's column offset in y
+// and z is the same for all lanes and each entry is two loads (the value
+// run of the slice is 512 contiguous bytes per entry) and one FMA.
+// Pencils of one slice, four per round, all their loads issued before the
+// first FMA; a pencil index past the last reads the round's first pencil and
+// its products are skipped (a wave-uniform test).  kNT: the values (read
+// once) are streamed non-temporally.
+template <int K, bool kNT>
+__device__ __forceinline__ double sell_pencils(const double* __restrict__ vs,
+                                               const double* __restrict__ xb, int len1,
+                                               int npen, int64_t n1) {
+  constexpr int R = 4;
+  double acc = 0.0;
+  for (int q = 0; q < npen; q += R) {
+    double a[R][K], b[R][K];
+#pragma unroll
+    for (int u = 0; u < R; ++u) {
+      const int qq = q + u < npen ? q + u : q;
+      const int qz = qq / len1, qy = qq - qz * len1;
+      const double* xp = xb + n1 * (qy + n1 * qz);
+      const double* vp = vs + (int64_t)64 * K * qq;
+#pragma unroll
+      for (int kx = 0; kx < K; ++kx) {
+        a[u][kx] = kNT ? __builtin_nontemporal_load(vp + 64 * kx) : vp[64 * kx];
+        b[u][kx] = xp[kx];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < R; ++u) {
+      if (q + u < npen) {
+#pragma unroll
+        for (int kx = 0; kx < K; ++kx) acc = fma(a[u][kx], b[u][kx], acc);
+      }
+    }
+  }
+  return acc;
+}
+
+template <int P, bool kNT>
+__global__ __launch_bounds__(256) void k_spmv_sell(const double* __restrict__ sv,
+                                                   const int64_t* __restrict__ off,
+                                                   int64_t n_slices, int cv, int cn, int nv,
+                                                   int nn, const double* __restrict__ x,
+                                                   double* __restrict__ y,
+                                                   const CgScalars* __restrict__ sc,
+                                                   const LatticeInfo lat) {
+  if (sc && sc->done) return;
+  // the slice of this wave (wave-uniform, so everything derived from it
+  // stays in scalar registers)
+  const int64_t s = xcd_remap(blockIdx.x, gridDim.x) * 4 +
+                    __builtin_amdgcn_readfirstlane(threadIdx.x / 64);
+  if (s >= n_slices) return;
+  const int l = threadIdx.x % 64;
+  const SellSlice sl = sell_slice(s, cv, cn);
+  const int n1 = lat.n1;
+  const int y0 = lat.dim >= 2 ? (int)(sl.line % n1) : 0;
+  const int z0 = lat.dim == 3 ? (int)(sl.line / n1) : 0;
+  int lo1 = 0, len1 = 1, lo2 = 0, len2 = 1;
+  if (lat.dim >= 2) dir_box(y0, lat, &lo1, &len1);
+  if (lat.dim == 3) dir_box(z0, lat, &lo2, &len2);
+  const int count = sl.vertex ? nv : nn;
+  const int i = sl.chunk * 64 + l;
+  const bool valid = i < count;
+  const int xr = sell_x_p<P>(sl.vertex, valid ? i : count - 1);
+  const int lo0 = sl.vertex ? xr - P : (xr / P) * P;
+  const double* vs = sv + off[s] + l;
+  const double* xb = x + lo0 + (int64_t)n1 * (lo1 + (int64_t)n1 * lo2);
+  const int npen = len1 * len2;
+  const double acc = sl.vertex ? sell_pencils<2 * P + 1, kNT>(vs, xb, len1, npen, n1)
+                               : sell_pencils<P + 1, kNT>(vs, xb, len1, npen, n1);
+  if (valid) y[xr + (int64_t)n1 * (y0 + (int64_t)n1 * z0)] = acc;
+}
+
 // Launch shape.  G lanes per block row: enough lanes that one pass of U
 // blocks per lane (eight scalar blocks, two 3x3 blocks) covers the mean row,
 // rounded up to 8, 16, 32 or 64 (FC_SPMV_GROUP overrides it).  Measured on
@@ -192,11 +513,74 @@ static hipError_t spmv_dispatch(const DeviceBsr& A, const T* val, const XT* x,
   const int64_t nb = (partial && !rows) ? fused_grid(A) : nt;
   static const bool lat_allowed = env_int("FC_SPMV_LATTICE", 1) != 0;
   const bool lat = lat_allowed && A.lat.dim > 0;
+  // the whole scalar matrix with its sliced copy, no fused dot: the sliced
+  // rows, then the boundary vertex rows from the row layout
+  if constexpr (B == 1 && sizeof(T) == 8 && sizeof(XT) == 8) {
+    if (lat && A.sell_val && !rows && !partial) {
+      const int cn = A.sell_nn > 0 ? (A.sell_nn + 63) / 64 : 0;
+      dim3 g((unsigned)((A.n_slices + 3) / 4)), b(256);
+      // values streamed non-temporally (3 % faster at 64^3 cells, p = 2;
+      // FC_SPMV_SELL_NT=0 reads them through the caches)
+      static const bool sell_nt = env_int("FC_SPMV_SELL_NT", 1) != 0;
+#define FC_SELL(PP)                                                                           \
+  do {                                                                                        \
+    if (sell_nt)                                                                              \
+      hipLaunchKernelGGL((k_spmv_sell<PP, true>), g, b, 0, s, A.sell_val, A.sell_off,         \
+                         A.n_slices, A.sell_cv, cn, A.sell_nv, A.sell_nn, (const double*)x, y, \
+                         sc, A.lat);                                                          \
+    else                                                                                      \
+      hipLaunchKernelGGL((k_spmv_sell<PP, false>), g, b, 0, s, A.sell_val, A.sell_off,        \
+                         A.n_slices, A.sell_cv, cn, A.sell_nv, A.sell_nn, (const double*)x, y, \
+                         sc, A.lat);                                                          \
+  } while (0)
+      switch (A.lat.p) {
+        case 1: FC_SELL(1); break;
+        case 2: FC_SELL(2); break;
+        case 3: FC_SELL(3); break;
+        default: FC_SELL(4); break;
+      }
+#undef FC_SELL
+      hipError_t e = hipGetLastError();
+      if (e != hipSuccess || A.n_rest == 0) return e;
+      return spmv_dispatch<B, T, XT>(A, val, x, y, s, sc, nullptr, A.sell_rest, A.n_rest);
+    }
+  }
+  // scalar lattice rows of degree p <= 4, the whole matrix, no fused dot:
+  // one workgroup per run of a lattice line with its x window in LDS
+  // (FC_SPMV_LINE=1 selects it; the default is the row-tile kernels)
+  static const bool line_allowed = env_int("FC_SPMV_LINE", 0) != 0;
+  if constexpr (B == 1) {
+    if (lat && line_allowed && !rows && !partial && A.lat.p >= 1 && A.lat.p <= 4) {
+      const int n1 = A.lat.n1;
+      const int nseg = (n1 + 31) / 32;
+      const int64_t nlines = A.lat.dim == 3 ? (int64_t)n1 * n1 : A.lat.dim == 2 ? n1 : 1;
+      const int64_t ntl = nlines * nseg;
+      dim3 g((unsigned)ntl), b(256);
+      switch (A.lat.p) {
+        case 1:
+          hipLaunchKernelGGL((k_spmv_line<T, XT, 1>), g, b, 0, s, val, x, y, sc, A.lat, nseg);
+          break;
+        case 2:
+          hipLaunchKernelGGL((k_spmv_line<T, XT, 2>), g, b, 0, s, val, x, y, sc, A.lat, nseg);
+          break;
+        case 3:
+          hipLaunchKernelGGL((k_spmv_line<T, XT, 3>), g, b, 0, s, val, x, y, sc, A.lat, nseg);
+          break;
+        default:
+          hipLaunchKernelGGL((k_spmv_line<T, XT, 4>), g, b, 0, s, val, x, y, sc, A.lat, nseg);
+          break;
+      }
+      return hipGetLastError();
+    }
+  }
   dim3 grid((unsigned)nb), block(256);
   // 3x3 blocks: two per lane per pass (nine values each), FP64 values
   // non-temporal.  Scalar rows: eight per lane per pass through the caches
   // (FC_SPMV_PASS=16 and FC_SPMV_NT=1 select sixteen and the non-temporal
   // stream for FP64 scalar rows on the lattice).
+  // scalar rows of degree p <= 4 on the lattice: whole x-pencils per lane
+  // with FC_SPMV_PENCIL=1 (the entry-per-lane kernel is the default)
+  static const bool pencil = env_int("FC_SPMV_PENCIL", 0) != 0;
   static const int pass16 = env_int("FC_SPMV_PASS", 8) == 16;
   static const int nt1 = env_int("FC_SPMV_NT", 0) == 1;
   constexpr bool kNT3 = B != 1 && sizeof(T) == 8;
@@ -204,13 +588,20 @@ static hipError_t spmv_dispatch(const DeviceBsr& A, const T* val, const XT* x,
 #define FC_SPMV_LAUNCH(GG, LAT, UU, NT)                                                      \
   hipLaunchKernelGGL((k_spmv_bsr<B, GG, T, LAT, XT, UU, NT>), grid, block, 0, s, A.rowptr,   \
                      A.col, val, x, y, n_rows, sc, partial, rows, A.lat)
+#define FC_SPMV_PENCIL(GG, PP)                                                               \
+  hipLaunchKernelGGL((k_spmv_pencil<GG, T, XT, PP>), grid, block, 0, s, val, x, y, n_rows, sc, \
+                     partial, rows, A.lat)
 #define FC_SPMV_CASE(GG)                                                                     \
   case GG:                                                                                   \
     if (lat) {                                                                               \
-      if constexpr (B == 1 && sizeof(T) == 8) {                                              \
-        if (pass16 && nt1) FC_SPMV_LAUNCH(GG, true, 16, true);                               \
-        else if (pass16) FC_SPMV_LAUNCH(GG, true, 16, false);                                \
-        else if (nt1) FC_SPMV_LAUNCH(GG, true, 8, true);                                     \
+      if constexpr (B == 1) {                                                                \
+        if (pencil && A.lat.p == 1) FC_SPMV_PENCIL(GG, 1);                                   \
+        else if (pencil && A.lat.p == 2) FC_SPMV_PENCIL(GG, 2);                              \
+        else if (pencil && A.lat.p == 3) FC_SPMV_PENCIL(GG, 3);                              \
+        else if (pencil && A.lat.p == 4) FC_SPMV_PENCIL(GG, 4);                              \
+        else if (sizeof(T) == 8 && pass16 && nt1) FC_SPMV_LAUNCH(GG, true, 16, true);        \
+        else if (sizeof(T) == 8 && pass16) FC_SPMV_LAUNCH(GG, true, 16, false);              \
+        else if (sizeof(T) == 8 && nt1) FC_SPMV_LAUNCH(GG, true, 8, true);                   \
         else FC_SPMV_LAUNCH(GG, true, 8, false);                                             \
       } else {                                                                               \
         FC_SPMV_LAUNCH(GG, true, kU, kNT3);                                                  \
@@ -227,6 +618,7 @@ static hipError_t spmv_dispatch(const DeviceBsr& A, const T* val, const XT* x,
   }
 #undef FC_SPMV_CASE
 #undef FC_SPMV_LAUNCH
+#undef FC_SPMV_PENCIL
   return hipGetLastError();
 }
 
@@ -247,6 +639,64 @@ hipError_t launch_spmv(const DeviceBsr& A, const double* x, double* y, hipStream
 }
 
 int spmv_num_blocks(const DeviceBsr& A) { return (int)fused_grid(A); }
+
+// Host side of the sliced copy: slice offsets (each slice holds 64 lanes of
+// its box size), the boundary vertex rows, then the copy on the device.
+static hipError_t spmv_build_sell(DeviceBsr& A, hipStream_t s) {
+  const LatticeInfo lat = A.lat;
+  const int n1 = lat.n1, p = lat.p, n = (n1 - 1) / p;
+  const int nv = n - 1, nn = n * (p - 1);
+  const int cv = nv > 0 ? (nv + 63) / 64 : 0, cn = nn > 0 ? (nn + 63) / 64 : 0;
+  const int64_t lines = lat.dim == 3 ? (int64_t)n1 * n1 : n1;
+  if (cv + cn == 0) return hipSuccess;
+  auto len = [&](int g) {
+    if (g % p != 0) return p + 1;
+    return std::min(n1 - 1, g + p) - std::max(0, g - p) + 1;
+  };
+  std::vector<int64_t> off;
+  off.reserve((size_t)(lines * (cv + cn) + 1));
+  off.push_back(0);
+  std::vector<int32_t> rest;
+  for (int64_t line = 0; line < lines; ++line) {
+    const int y0 = (int)(line % n1), z0 = lat.dim == 3 ? (int)(line / n1) : 0;
+    const int64_t yz = (int64_t)len(y0) * (lat.dim == 3 ? len(z0) : 1);
+    for (int k = 0; k < cv; ++k) off.push_back(off.back() + 64 * yz * (2 * p + 1));
+    for (int k = 0; k < cn; ++k) off.push_back(off.back() + 64 * yz * (p + 1));
+    const int64_t r0 = (int64_t)n1 * (y0 + (int64_t)n1 * z0);
+    rest.push_back((int32_t)r0);
+    if (n1 > 1) rest.push_back((int32_t)(r0 + n1 - 1));
+  }
+  const int64_t ns = (int64_t)off.size() - 1;
+  hipError_t e = hipMalloc(&A.sell_val, (size_t)off.back() * sizeof(double));
+  if (e == hipSuccess) e = hipMalloc(&A.sell_off, off.size() * sizeof(int64_t));
+  if (e == hipSuccess) e = hipMalloc(&A.sell_rest, rest.size() * sizeof(int32_t));
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(A.sell_off, off.data(), off.size() * sizeof(int64_t),
+                       hipMemcpyHostToDevice, s);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(A.sell_rest, rest.data(), rest.size() * sizeof(int32_t),
+                       hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) {
+    hipLaunchKernelGGL(k_sell_build, dim3(4096), dim3(256), 0, s, A.val, A.sell_off, ns, cv, cn,
+                       nv, nn, lat, A.sell_val);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(s);   // the host vectors die here
+  if (e != hipSuccess) {
+    for (void* q : {(void*)A.sell_val, (void*)A.sell_off, (void*)A.sell_rest})
+      if (q) (void)hipFree(q);
+    A.sell_val = nullptr;
+    A.sell_off = nullptr;
+    A.sell_rest = nullptr;
+    return e;
+  }
+  A.n_slices = ns;
+  A.sell_cv = cv;
+  A.sell_nv = nv;
+  A.sell_nn = nn;
+  A.n_rest = (int64_t)rest.size();
+  return hipSuccess;
+}
 
 // mismatches between stored rows and lattice boxes: length, start and
 // columns (counted with an atomic only where one occurs)
@@ -285,6 +735,8 @@ hipError_t spmv_enable_lattice(DeviceBsr& A, int dim, int n1, int p, hipStream_t
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   (void)hipFree(bad);
   if (e == hipSuccess && hbad == 0) A.lat = lat;
+  if (e == hipSuccess && A.lat.dim >= 2 && A.bdim == 1 && p <= 4 && env_int("FC_SPMV_SELL", 1))
+    e = spmv_build_sell(A, s);
   return e;
 }
 
