@@ -208,7 +208,9 @@ fc_status fc_precond_info(fc_precond pc, int64_t* n_blocks,
  * the same in every process), and whether the block columns are computed
  * from the lattice (1: the matrix came from a problem description and its
  * columns were verified to be each row's lattice box, so the column array
- * is not read) or read (0). */
+ * is not read; 2: as 1, and the scalar rows are also held in the sliced
+ * layout, slices of 64 rows of one lattice line with equal boxes, which
+ * the whole-matrix product reads) or read (0). */
 fc_status fc_spmv_info(fc_problem pb, int32_t* group, int32_t* lattice);
 /* FP32 copy (FC_STORE_F32): the diagonally scaled inverse D^1/2 P_B D^1/2
  * (D = diag(A) on the block) rounded to FP32, kept for the blocks where a

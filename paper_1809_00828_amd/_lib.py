@@ -296,7 +296,7 @@ class Problem:
             _check(load().fc_spmv_info(self._h, C.byref(g), C.byref(lat)))
             self._info = {"n_dofs": n.value, "nnzb": nnzb.value, "n_el": nel.value,
                           "m": m.value, "bsr_dim": bd.value, "spmv_group": g.value,
-                          "lattice_columns": bool(lat.value)}
+                          "lattice_columns": lat.value >= 1, "sliced": lat.value == 2}
         return self._info
 
     @property

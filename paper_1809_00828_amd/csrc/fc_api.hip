@@ -614,7 +614,7 @@ static fc_status precond_build_body(fc_problem pb, const fc_precond_opts* opts, 
 fc_status fc_spmv_info(fc_problem pb, int32_t* group, int32_t* lattice) {
   if (!pb) return FC_E_ARG;
   if (group) *group = pb->A.group;
-  if (lattice) *lattice = pb->A.lat.dim > 0 ? 1 : 0;
+  if (lattice) *lattice = pb->A.lat.dim > 0 ? (pb->A.sell_val ? 2 : 1) : 0;
   return FC_OK;
 }
 

@@ -160,6 +160,7 @@ def test_scalar_lattice_spmv_matches_oracle(torch, monkeypatch, dim, p, n):
         monkeypatch.setenv("FC_SPMV_SELL", sell)
         pb = fc.Problem.setup(d)
         assert pb.info()["lattice_columns"]
+        assert pb.info()["sliced"] == (sell == "1")
         y = torch.empty(pb.n, dtype=torch.float64, device="cuda")
         pb.apply_A(torch.as_tensor(x, device="cuda"), y)
         torch.cuda.synchronize()
