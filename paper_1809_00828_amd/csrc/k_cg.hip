@@ -236,7 +236,10 @@ __global__ __launch_bounds__(256) void k_cg_pull_lat(
   const PullTiles T = pull_tiles(L);
   const int64_t ntiles = (int64_t)T.ntx * T.nty * T.ntz;
   double a = 0.0, b = 0.0, c = 0.0, d = 0.0;
-  for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+  // XCD-contiguous tile ranges: the block outputs of the cells on a tile's
+  // faces, which the neighbouring tiles read too, stay in one XCD's L2
+  const XcdRange xr = xcd_range(blockIdx.x, gridDim.x, ntiles);
+  for (int64_t tile = xr.t0 + xr.j; tile < xr.t1; tile += xr.per) {
 #pragma unroll
     for (int j = 0; j < BD; ++j) {
       int gx, gy, gz, cc;
@@ -567,12 +570,14 @@ static constexpr unsigned kRedBlocks = 1024;
 // grid of the fused pull: enough workgroups to fill the chip, few partials
 static inline unsigned pull_grid(int64_t n) { return std::min<unsigned>(nblk(n), 2048u); }
 // grid of the pull actually launched for this preconditioner (the lattice
-// pull walks node tiles; never more workgroups than partial slots)
+// pull walks node tiles, one workgroup per tile up to 16,384 workgroups,
+// which at 64^3 cells, p = 2 is 6 % faster than 4,096; never more
+// workgroups than partial slots)
 static inline unsigned pull_grid_for(const fc_precond_s& pc, int64_t n, int64_t partial_len) {
   if (pc.lat.dim == 0) return pull_grid(n);
   static const int cap = [] {
     const char* e = std::getenv("FC_PULL_GRID");
-    return e ? std::max(64, std::atoi(e)) : 4096;
+    return e ? std::max(64, std::atoi(e)) : 16384;
   }();
   const PullTiles T = pull_tiles(pc.lat);
   const int64_t nt = (int64_t)T.ntx * T.nty * T.ntz;
