@@ -142,179 +142,6 @@ __global__ __launch_bounds__(256) void k_spmv_bsr(
   if (threadIdx.x == 0) partial[blockIdx.x] = dot;
 }
 
-// Scalar rows on the lattice of a degree-P problem.  The box of a row is a
-// set of x-pencils, runs of len[0] <= 2P + 1 consecutive columns whose
-// values are consecutive too (the first direction runs fastest), so a lane
-// takes whole pencils: one column computation per pencil, then loads at
-// fixed offsets and one FMA per entry.  The pencil count len[1] len[2]
-// depends only on the row's y and z indices, which the consecutive rows of
-// a wave share, so the lanes of a wave run the same number of pencils.
-template <int G, typename T, typename XT, int P>
-__global__ __launch_bounds__(256) void k_spmv_pencil(
-    const T* __restrict__ val, const XT* __restrict__ x, double* __restrict__ y, int64_t n_rows,
-    const CgScalars* __restrict__ sc, double* __restrict__ partial,
-    const int32_t* __restrict__ rows, const LatticeInfo lat) {
-  constexpr int RPW = 256 / G;
-  constexpr int KX = 2 * P + 1;
-  __shared__ double lds[16];
-  if (sc && sc->done) return;
-  const int64_t ntiles = (n_rows + RPW - 1) / RPW;
-  const XcdRange xr_ = xcd_range(blockIdx.x, gridDim.x, ntiles);
-  const uint32_t j0 = xr_.j, per = xr_.per;
-  const int64_t t0 = xr_.t0, t1 = xr_.t1;
-  const int lane = threadIdx.x % G;
-  const int64_t n1 = lat.n1;
-  double dot = 0.0;
-  for (int64_t tile = t0 + j0; tile < t1; tile += per) {
-    const int64_t idx = tile * RPW + threadIdx.x / G;
-    if (idx >= n_rows) continue;
-    const int64_t row = rows ? (int64_t)rows[idx] : idx;
-    int c[3];
-    lattice_coords(row, lat, c);
-    const RowBox box = row_box_at(c, lat);
-    const int64_t base = lattice_row_start_at(c, box, lat);
-    const int len0 = box.len[0], np = box.len[1] * box.len[2];
-    double acc = 0.0;
-    float accf = 0.0f;
-    // two pencils per round, all their loads issued before the first is
-    // used: entries past a pencil's end, and the second pencil past the
-    // last, read a valid neighbour and are multiplied as zero
-    for (int j = lane; j < np; j += 2 * G) {
-      T va[2][KX];
-      XT xa[2][KX];
-      bool on[2];
-#pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        const int jj = j + h * G;
-        on[h] = jj < np;
-        const int jc = on[h] ? jj : j;
-        // pencil jc = jy + len[1] jz (the float quotient is exact, as in
-        // lattice_col)
-        const int jz = (int)(((float)jc + 0.5f) * box.inv[1]);
-        const int jy = jc - jz * box.len[1];
-        const T* vp = val + base + (int64_t)jc * len0;
-        const XT* xp = x + box.lo[0] + n1 * ((box.lo[1] + jy) + n1 * (box.lo[2] + jz));
-#pragma unroll
-        for (int kx = 0; kx < KX; ++kx) {
-          const int kc = kx <= P ? kx : min(kx, len0 - 1);   // every pencil holds P + 1
-          va[h][kx] = vp[kc];
-          xa[h][kx] = xp[kc];
-        }
-      }
-#pragma unroll
-      for (int h = 0; h < 2; ++h)
-#pragma unroll
-        for (int kx = 0; kx < KX; ++kx) {
-          const bool use = on[h] && (kx <= P || kx < len0);
-          if constexpr (sizeof(T) == 8)
-            acc = fma(use ? (double)va[h][kx] : 0.0, (double)xa[h][kx], acc);
-          else
-            accf = fmaf(use ? (float)va[h][kx] : 0.0f, (float)xa[h][kx], accf);
-        }
-    }
-    if constexpr (sizeof(T) == 8)
-      acc = group_sum<G>(acc);
-    else
-      acc = (double)group_sum<G>(accf);
-    if (lane == 0) {
-      y[row] = acc;
-      if (partial) dot = fma((double)x[row], acc, dot);
-    }
-  }
-  if (!partial) return;
-  dot = block_sum(dot, lds);
-  if (threadIdx.x == 0) partial[blockIdx.x] = dot;
-}
-
-// Scalar rows on the lattice of a degree-P problem, one workgroup per run
-// of at most 32 consecutive rows of one lattice line (fixed y and z).  The
-// boxes of those rows share their y and z ranges, so the x entries they
-// gather form a window of len[1] len[2] pencil lines of at most 32 + 2P
-// nodes, which the workgroup stages in LDS with coalesced loads; then the
-// eight lanes of each row stream its values (contiguous) and read x from
-// LDS.  Only the value stream and the staging go through the vector memory
-// address unit, not one scattered gather per entry.
-template <typename T, typename XT, int P>
-__global__ __launch_bounds__(256) void k_spmv_line(const T* __restrict__ val,
-                                                   const XT* __restrict__ x,
-                                                   double* __restrict__ y,
-                                                   const CgScalars* __restrict__ sc,
-                                                   const LatticeInfo lat, int nseg) {
-  constexpr int G = 8, RPW = 256 / G;
-  constexpr int WMAX = RPW + 2 * P;           // window width
-  constexpr int NPMAX = (2 * P + 1) * (2 * P + 1);
-  __shared__ XT xs[NPMAX * WMAX];
-  if (sc && sc->done) return;
-  const int n1 = lat.n1;
-  const int64_t nlines = lat.dim == 3 ? (int64_t)n1 * n1 : lat.dim == 2 ? n1 : 1;
-  const int64_t ntiles = nlines * nseg;
-  // XCD-contiguous tile ranges: consecutive lines share an XCD's L2
-  const XcdRange xr_ = xcd_range(blockIdx.x, gridDim.x, ntiles);
-  const uint32_t j0 = xr_.j, per = xr_.per;
-  const int64_t t0 = xr_.t0, t1 = xr_.t1;
-  const int lane = threadIdx.x % G, r = threadIdx.x / G;
-  for (int64_t tile = t0 + j0; tile < t1; tile += per) {
-    const int64_t line = tile / nseg;
-    const int seg = (int)(tile - line * nseg);
-    const int y0 = lat.dim >= 2 ? (int)(line % n1) : 0;
-    const int z0 = lat.dim == 3 ? (int)(line / n1) : 0;
-    const int xa = (int)((int64_t)seg * n1 / nseg), xb = (int)((int64_t)(seg + 1) * n1 / nseg);
-    // the line's box in y and z (every row of the run shares it)
-    const int cl[3] = {xa, y0, z0};
-    const RowBox lb = row_box_at(cl, lat);
-    const int wx0 = max(0, xa - P), wx1 = min(n1 - 1, xb - 1 + P);
-    const int W = wx1 - wx0 + 1;
-    const int np = lb.len[1] * lb.len[2];
-    __syncthreads();   // the previous run's reads of the window are done
-    for (int e = threadIdx.x; e < np * W; e += 256) {
-      const int q = e / W, xo = e - q * W;
-      const int jz = q / lb.len[1], jy = q - jz * lb.len[1];
-      xs[q * WMAX + xo] =
-          x[(int64_t)(wx0 + xo) + (int64_t)n1 * ((lb.lo[1] + jy) + (int64_t)n1 * (lb.lo[2] + jz))];
-    }
-    __syncthreads();
-    const int xr = xa + r;
-    if (xr >= xb) continue;
-    const int c[3] = {xr, y0, z0};
-    const RowBox box = row_box_at(c, lat);
-    const int64_t base = lattice_row_start_at(c, box, lat);
-    const int64_t row = xr + (int64_t)n1 * (y0 + (int64_t)n1 * z0);
-    const int len0 = box.len[0], L = len0 * np;
-    const int off = box.lo[0] - wx0;
-    const T* v = val + base;
-    double acc = 0.0;
-    float accf = 0.0f;
-    constexpr int U = 8;
-    for (int k = lane; k < L; k += U * G) {
-      T a[U];
-      XT xv[U];
-#pragma unroll
-      for (int u = 0; u < U; ++u) {
-        const int ku = k + u * G;
-        const bool on = ku < L;
-        a[u] = on ? v[ku] : T(0);
-        // entry ku = kx + len0 q (the float quotient is exact, as in
-        // lattice_col)
-        const int q = (int)(((float)ku + 0.5f) * box.inv[0]);
-        const int kx = ku - q * len0;
-        xv[u] = on ? xs[q * WMAX + off + kx] : XT(0);
-      }
-#pragma unroll
-      for (int u = 0; u < U; ++u) {
-        if constexpr (sizeof(T) == 8)
-          acc = fma((double)a[u], (double)xv[u], acc);
-        else
-          accf = fmaf((float)a[u], (float)xv[u], accf);
-      }
-    }
-    if constexpr (sizeof(T) == 8)
-      acc = group_sum<G>(acc);
-    else
-      acc = (double)group_sum<G>(accf);
-    if (lane == 0) y[row] = acc;
-  }
-}
-
 // ---------------------------------------------------------------- sliced
 // Lattice range of the functions whose support meets that of index g along
 // one direction (as in row_box_at).
@@ -545,70 +372,19 @@ static hipError_t spmv_dispatch(const DeviceBsr& A, const T* val, const XT* x,
       return spmv_dispatch<B, T, XT>(A, val, x, y, s, sc, nullptr, A.sell_rest, A.n_rest);
     }
   }
-  // scalar lattice rows of degree p <= 4, the whole matrix, no fused dot:
-  // one workgroup per run of a lattice line with its x window in LDS
-  // (FC_SPMV_LINE=1 selects it; the default is the row-tile kernels)
-  static const bool line_allowed = env_int("FC_SPMV_LINE", 0) != 0;
-  if constexpr (B == 1) {
-    if (lat && line_allowed && !rows && !partial && A.lat.p >= 1 && A.lat.p <= 4) {
-      const int n1 = A.lat.n1;
-      const int nseg = (n1 + 31) / 32;
-      const int64_t nlines = A.lat.dim == 3 ? (int64_t)n1 * n1 : A.lat.dim == 2 ? n1 : 1;
-      const int64_t ntl = nlines * nseg;
-      dim3 g((unsigned)ntl), b(256);
-      switch (A.lat.p) {
-        case 1:
-          hipLaunchKernelGGL((k_spmv_line<T, XT, 1>), g, b, 0, s, val, x, y, sc, A.lat, nseg);
-          break;
-        case 2:
-          hipLaunchKernelGGL((k_spmv_line<T, XT, 2>), g, b, 0, s, val, x, y, sc, A.lat, nseg);
-          break;
-        case 3:
-          hipLaunchKernelGGL((k_spmv_line<T, XT, 3>), g, b, 0, s, val, x, y, sc, A.lat, nseg);
-          break;
-        default:
-          hipLaunchKernelGGL((k_spmv_line<T, XT, 4>), g, b, 0, s, val, x, y, sc, A.lat, nseg);
-          break;
-      }
-      return hipGetLastError();
-    }
-  }
   dim3 grid((unsigned)nb), block(256);
   // 3x3 blocks: two per lane per pass (nine values each), FP64 values
-  // non-temporal.  Scalar rows: eight per lane per pass through the caches
-  // (FC_SPMV_PASS=16 and FC_SPMV_NT=1 select sixteen and the non-temporal
-  // stream for FP64 scalar rows on the lattice).
-  // scalar rows of degree p <= 4 on the lattice: whole x-pencils per lane
-  // with FC_SPMV_PENCIL=1 (the entry-per-lane kernel is the default)
-  static const bool pencil = env_int("FC_SPMV_PENCIL", 0) != 0;
-  static const int pass16 = env_int("FC_SPMV_PASS", 8) == 16;
-  static const int nt1 = env_int("FC_SPMV_NT", 0) == 1;
-  constexpr bool kNT3 = B != 1 && sizeof(T) == 8;
+  // non-temporal; scalar rows: eight per lane per pass through the caches
+  constexpr bool kNT = B != 1 && sizeof(T) == 8;
   constexpr int kU = B == 1 ? 8 : 2;
-#define FC_SPMV_LAUNCH(GG, LAT, UU, NT)                                                      \
-  hipLaunchKernelGGL((k_spmv_bsr<B, GG, T, LAT, XT, UU, NT>), grid, block, 0, s, A.rowptr,   \
-                     A.col, val, x, y, n_rows, sc, partial, rows, A.lat)
-#define FC_SPMV_PENCIL(GG, PP)                                                               \
-  hipLaunchKernelGGL((k_spmv_pencil<GG, T, XT, PP>), grid, block, 0, s, val, x, y, n_rows, sc, \
-                     partial, rows, A.lat)
 #define FC_SPMV_CASE(GG)                                                                     \
   case GG:                                                                                   \
-    if (lat) {                                                                               \
-      if constexpr (B == 1) {                                                                \
-        if (pencil && A.lat.p == 1) FC_SPMV_PENCIL(GG, 1);                                   \
-        else if (pencil && A.lat.p == 2) FC_SPMV_PENCIL(GG, 2);                              \
-        else if (pencil && A.lat.p == 3) FC_SPMV_PENCIL(GG, 3);                              \
-        else if (pencil && A.lat.p == 4) FC_SPMV_PENCIL(GG, 4);                              \
-        else if (sizeof(T) == 8 && pass16 && nt1) FC_SPMV_LAUNCH(GG, true, 16, true);        \
-        else if (sizeof(T) == 8 && pass16) FC_SPMV_LAUNCH(GG, true, 16, false);              \
-        else if (sizeof(T) == 8 && nt1) FC_SPMV_LAUNCH(GG, true, 8, true);                   \
-        else FC_SPMV_LAUNCH(GG, true, 8, false);                                             \
-      } else {                                                                               \
-        FC_SPMV_LAUNCH(GG, true, kU, kNT3);                                                  \
-      }                                                                                      \
-    } else {                                                                                 \
-      FC_SPMV_LAUNCH(GG, false, kU, kNT3);                                                   \
-    }                                                                                        \
+    if (lat)                                                                                 \
+      hipLaunchKernelGGL((k_spmv_bsr<B, GG, T, true, XT, kU, kNT>), grid, block, 0, s,       \
+                         A.rowptr, A.col, val, x, y, n_rows, sc, partial, rows, A.lat);      \
+    else                                                                                     \
+      hipLaunchKernelGGL((k_spmv_bsr<B, GG, T, false, XT, kU, kNT>), grid, block, 0, s,      \
+                         A.rowptr, A.col, val, x, y, n_rows, sc, partial, rows, A.lat);      \
     break;
   switch (G) {
     FC_SPMV_CASE(8)
@@ -617,8 +393,6 @@ static hipError_t spmv_dispatch(const DeviceBsr& A, const T* val, const XT* x,
     FC_SPMV_CASE(64)
   }
 #undef FC_SPMV_CASE
-#undef FC_SPMV_LAUNCH
-#undef FC_SPMV_PENCIL
   return hipGetLastError();
 }
 
