@@ -92,7 +92,7 @@ def _cpu_model():
     return platform.processor() or platform.machine()
 
 
-def cpu_baseline(full_desc, gpu_iters, cpu_iters=10):
+def cpu_baseline(full_desc, gpu_iters, cpu_iters=50):
     """The FP64 oracle timed on the host, in two parts.
 
     Full size (the reported value): cpu_iters oracle PCG iterations on the
@@ -590,7 +590,7 @@ def main():
                     help="the FP64 PCG workload: 32^3-cell p=3 elasticity (the benchmark) or "
                          "64^3-cell p=2 Poisson (the learned form's problem)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-iters", type=int, default=10,
+    ap.add_argument("--cpu-iters", type=int, default=50,
                     help="full-size oracle PCG iterations of the CPU baseline")
     ap.add_argument("--no-forms", action="store_true",
                     help="skip the mixed-precision forms comparison")
