@@ -20,6 +20,12 @@
 // share that XCD's L2 for x.  The PCG variant leaves one partial (x, y)
 // per workgroup; a one-workgroup kernel of the solver sums them in a fixed
 // order (no atomics).
+//
+// Matrices assembled from a problem description have lattice rows: the
+// columns and the start of each row follow from the row's lattice indices
+// and are computed, not read.  Scalar ones (degree p <= 4) also keep a
+// sliced copy, 64 rows of one lattice line with equal boxes per slice, for
+// the whole-matrix product (k_spmv_sell below).
 #include <cstdlib>
 #include <vector>
 
