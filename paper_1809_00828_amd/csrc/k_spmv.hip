@@ -468,6 +468,11 @@ static hipError_t spmv_build_sell(DeviceBsr& A, hipStream_t s) {
     A.sell_val = nullptr;
     A.sell_off = nullptr;
     A.sell_rest = nullptr;
+    // without room for the copy the row layout serves every product
+    if (e == hipErrorOutOfMemory) {
+      (void)hipGetLastError();
+      return hipSuccess;
+    }
     return e;
   }
   A.n_slices = ns;
