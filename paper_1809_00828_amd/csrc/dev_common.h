@@ -36,8 +36,15 @@ __device__ __forceinline__ XcdRange xcd_range(uint32_t bid, uint32_t nwg, int64_
   XcdRange r;
   r.j = bid / nx;
   r.per = nwg / nx + (x < nwg % nx ? 1u : 0u);
-  r.t0 = ntiles * x / nx;
-  r.t1 = ntiles * (x + 1) / nx;
+  // eight XCDs (every grid of eight workgroups or more): a shift instead of
+  // a 64-bit division, which costs hundreds of scalar instructions per wave
+  if (nx == (uint32_t)kNumXcd) {
+    r.t0 = (ntiles * x) >> 3;
+    r.t1 = (ntiles * (x + 1)) >> 3;
+  } else {
+    r.t0 = ntiles * x / nx;
+    r.t1 = ntiles * (x + 1) / nx;
+  }
   return r;
 }
 
@@ -225,11 +232,11 @@ struct CellsOf {
   int cell[2], loc[2];
 };
 
-__device__ __forceinline__ CellsOf cells_of(int g, int n, int p) {
+__device__ __forceinline__ CellsOf cells_of(int g, int n, int p, const FastDiv dp) {
   CellsOf c;
   c.cnt = 0;
-  if (g % p == 0) {
-    const int e = g / p;
+  const int e = (int)fdiv((uint32_t)g, dp), rem = g - e * p;
+  if (rem == 0) {
     if (e >= 1) {
       c.cell[c.cnt] = e - 1;
       c.loc[c.cnt] = 1;
@@ -241,8 +248,8 @@ __device__ __forceinline__ CellsOf cells_of(int g, int n, int p) {
       ++c.cnt;
     }
   } else {
-    c.cell[0] = g / p;
-    c.loc[0] = g % p + 1;
+    c.cell[0] = e;
+    c.loc[0] = rem + 1;
     c.cnt = 1;
   }
   return c;
@@ -250,51 +257,42 @@ __device__ __forceinline__ CellsOf cells_of(int g, int n, int p) {
 
 // Node tiles of the lattice pull: 16 x 4 x 4 nodes (3-D) or 32 x 8 (2-D)
 // per 256-thread workgroup, so the cells whose block outputs a workgroup
-// sums are mostly summed by that workgroup alone.
-struct PullTiles {
-  int TX, TY, TZ, ntx, nty, ntz;
-};
-
-__host__ __device__ __forceinline__ PullTiles pull_tiles(const PullLattice L) {
-  PullTiles t;
-  t.TX = L.dim == 3 ? 16 : 32;
-  t.TY = L.dim == 3 ? 4 : 8;
-  t.TZ = L.dim == 3 ? 4 : 1;
-  t.ntx = (L.n1 + t.TX - 1) / t.TX;
-  t.nty = (L.n1 + t.TY - 1) / t.TY;
-  t.ntz = L.dim == 3 ? (L.n1 + t.TZ - 1) / t.TZ : 1;
-  return t;
+// sums are mostly summed by that workgroup alone.  The tile counts along the
+// first two directions are the divisors of L.dtx and L.dty.
+__host__ __device__ __forceinline__ int64_t pull_num_tiles(const PullLattice L) {
+  const int64_t ntz = L.dim == 3 ? (L.n1 + 3) / 4 : 1;
+  return (int64_t)L.dtx.d * L.dty.d * ntz;
 }
 
-// Unknown of slot `slot` (0 .. TX*TY*TZ*BD - 1) of tile `tile`: a tile's
-// unknowns are taken row by row (TX consecutive nodes, components
-// interleaved, so each row is one contiguous run of TX*BD unknowns), which
-// keeps the vector accesses of consecutive lanes contiguous.  False when the
-// node lies outside the lattice.
-template <int BD>
-__device__ __forceinline__ bool pull_dof(const PullLattice L, const PullTiles T, int64_t tile,
-                                         int slot, int* gx, int* gy, int* gz, int* c) {
-  const int t = (int)tile;   // fewer than 2^31 tiles: n1 <= 2^21 nodes per direction
-  const int bx = t % T.ntx, by = (t / T.ntx) % T.nty;
-  const int bz = t / (T.ntx * T.nty);
-  const int row = slot / (T.TX * BD), o = slot - row * (T.TX * BD);
-  *gx = bx * T.TX + o / BD;
-  *c = o % BD;
-  *gy = by * T.TY + row % T.TY;
-  *gz = bz * T.TZ + row / T.TY;
+// Node of slot `slot` (0 .. 255) of tile `tile` (one unknown per node: the
+// lattice pull serves scalar problems): a tile's nodes are taken row by row
+// (TX consecutive nodes), which keeps the vector accesses of consecutive
+// lanes contiguous.  The tile sizes are powers of two and the tile counts
+// are divided by multiply-shift.  False when the node lies outside the
+// lattice.
+__device__ __forceinline__ bool pull_node(const PullLattice L, int64_t tile, int slot, int* gx,
+                                          int* gy, int* gz) {
+  const uint32_t t = (uint32_t)tile;   // fewer than 2^31 tiles
+  const uint32_t tyz = fdiv(t, L.dtx), bz = fdiv(tyz, L.dty);
+  const int bx = (int)(t - tyz * L.dtx.d), by = (int)(tyz - bz * L.dty.d);
+  const int sx = L.dim == 3 ? 4 : 5, sy = L.dim == 3 ? 2 : 3;   // log2 TX, log2 TY
+  const int row = slot >> sx;
+  *gx = (bx << sx) + (slot & ((1 << sx) - 1));
+  *gy = (by << sy) + (row & ((1 << sy) - 1));
+  *gz = L.dim == 3 ? (int)(bz << 2) + (row >> sy) : (int)bz + (row >> sy);
   return *gx < L.n1 && *gy < L.n1 && (L.dim < 3 ? *gz == 0 : *gz < L.n1);
 }
 
-// Sum of the block outputs y_B holding component c of node (gx, gy, gz), in
-// ascending block (= cell) order, as the node-to-block map lists them.  All
-// (at most eight) loads are issued before the ordered sum.
+// Sum of the block outputs y_B holding node (gx, gy, gz), in ascending
+// block (= cell) order, as the node-to-block map lists them.  All (at most
+// eight) loads are issued before the ordered sum.
 __device__ __forceinline__ double pull_lattice_sum(const double* __restrict__ y,
-                                                   const PullLattice L, int m, int bd, int gx,
-                                                   int gy, int gz, int c) {
-  const CellsOf cx = cells_of(gx, L.n, L.p);
+                                                   const PullLattice L, int m, int gx, int gy,
+                                                   int gz) {
+  const CellsOf cx = cells_of(gx, L.n, L.p, L.dp);
   CellsOf cy{1, {0, 0}, {0, 0}}, cz{1, {0, 0}, {0, 0}};
-  if (L.dim >= 2) cy = cells_of(gy, L.n, L.p);
-  if (L.dim >= 3) cz = cells_of(gz, L.n, L.p);
+  if (L.dim >= 2) cy = cells_of(gy, L.n, L.p, L.dp);
+  if (L.dim >= 3) cz = cells_of(gz, L.n, L.p, L.dp);
   const int p1 = L.p + 1;
   double v[8];
 #pragma unroll
@@ -306,7 +304,7 @@ __device__ __forceinline__ double pull_lattice_sum(const double* __restrict__ y,
       const int64_t e =
           cx.cell[ix] + (int64_t)L.n * (cy.cell[iy] + (int64_t)L.n * cz.cell[iz]);
       const int loc = cx.loc[ix] + p1 * (cy.loc[iy] + p1 * cz.loc[iz]);
-      v[k] = y[e * m + (int64_t)loc * bd + c];
+      v[k] = y[e * m + loc];
     }
   }
   double s = 0.0;
@@ -323,15 +321,15 @@ __device__ __forceinline__ double pull_lattice_sum(const double* __restrict__ y,
 // left vertex, 1 its right vertex, 2 .. p its interior indices, tensor
 // order with the first direction fastest).
 __device__ __forceinline__ int64_t lattice_cell_node(const PullLattice L, int e, int loc) {
-  const int p1 = L.p + 1;
   int64_t node = 0, stride = 1;
-  int ee = e, ll = loc;
+  uint32_t ee = (uint32_t)e, ll = (uint32_t)loc;
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
     if (k < L.dim) {
-      const int c = ee % L.n, l = ll % p1;
-      ee /= L.n;
-      ll /= p1;
+      const uint32_t eq = fdiv(ee, L.dn), lq = fdiv(ll, L.dp1);
+      const int c = (int)(ee - eq * (uint32_t)L.n), l = (int)(ll - lq * (uint32_t)(L.p + 1));
+      ee = eq;
+      ll = lq;
       const int g = c * L.p + (l == 0 ? 0 : l == 1 ? L.p : l - 1);
       node += g * stride;
       stride *= L.n1;

@@ -586,7 +586,7 @@ static fc_status precond_build_body(fc_problem pb, const fc_precond_opts* opts, 
     if (allowed && !patch && pb->bdim == 1 && pb->dim >= 2 && pb->dim <= 3 && pb->n > 0 &&
         pb->p > 0 && nb == pb->n_el &&
         nb == std::pow((double)pb->n, pb->dim) && pb->nn == (int)std::pow(pb->p + 1.0, pb->dim)) {
-      const PullLattice L{pb->dim, pb->n, pb->p, pb->p * pb->n + 1};
+      const PullLattice L = make_pull_lattice(pb->dim, pb->n, pb->p);
       bool ok = false;
       FC_HIP(schwarz_check_lattice(*pc, L, &ok, s));
       if (ok) pc->lat = L;

@@ -88,7 +88,25 @@ inline LatticeInfo make_lattice_info(int32_t dim, int32_t n1, int32_t p) {
 // node-to-block map.
 struct PullLattice {
   int32_t dim = 0, n = 0, p = 0, n1 = 0;
+  // division by n, p and p + 1, and by the node-tile counts along the
+  // first two directions (16 x 4 x 4 node tiles in 3-D, 32 x 8 in 2-D)
+  FastDiv dn, dp, dp1, dtx, dty;
 };
+
+inline PullLattice make_pull_lattice(int32_t dim, int32_t n, int32_t p) {
+  PullLattice l;
+  l.dim = dim;
+  l.n = n;
+  l.p = p;
+  l.n1 = p * n + 1;
+  l.dn = make_fastdiv((uint32_t)n);
+  l.dp = make_fastdiv((uint32_t)p);
+  l.dp1 = make_fastdiv((uint32_t)(p + 1));
+  const int tx = dim == 3 ? 16 : 32, ty = dim == 3 ? 4 : 8;
+  l.dtx = make_fastdiv((uint32_t)((l.n1 + tx - 1) / tx));
+  l.dty = make_fastdiv((uint32_t)((l.n1 + ty - 1) / ty));
+  return l;
+}
 
 struct DeviceBsr {
   int32_t bdim = 1;
@@ -109,8 +127,10 @@ struct DeviceBsr {
   // Sliced copy of a scalar lattice matrix (degree p <= 4): the rows of one
   // lattice line (fixed y, z) and one x class, interior vertex indices
   // (x = p, 2p, ..) or the other interior indices, in slices of 64 rows
-  // whose boxes have equal shape; entry k of lane l of slice s at
-  // sell_val[sell_off[s] + 64 k + l] (zero for lanes past the class's end).
+  // whose boxes have equal shape.  A slice's entries are stored in pairs:
+  // entries 2j and 2j + 1 of lane l at sell_val[sell_off[s] + 128 j + 2 l]
+  // and the next word, an odd last entry alone at sell_off[s] + 128 j + l
+  // (zero for lanes past the class's end).
   // The boundary vertex rows (x = 0 and x = n1 - 1) are listed in sell_rest
   // and use the row layout.
   double* sell_val = nullptr;

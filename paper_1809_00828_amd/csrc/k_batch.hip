@@ -194,7 +194,7 @@ __global__ __launch_bounds__(256) void kb_schwarz(const BProb* __restrict__ prob
     P.y[blk * m + i] = sym_row<double>(P.Q + blk * stride, &rB[w * 64 + lb * m], m, i);
   } else {
     // one block per workgroup, its stored rows staged through LDS
-    __shared__ double tile[StageRows<double>::value][256];
+    __shared__ __align__(16) double tile[StageRows<double>::value * 256];
     const int64_t blk = it.tile;
     const int i = threadIdx.x;
     if (i < m) {

@@ -219,54 +219,53 @@ __global__ __launch_bounds__(256) void k_cg_pull(
   }
 }
 
-// The same pull where every cell is a block: the workgroups walk node tiles
-// of the lattice and find each node's blocks from its lattice indices (no
-// node-to-block map is read), summing them in the same ascending order, so
-// z is bitwise the mapped pull's.  fb may be null (no unknown needs the
-// diagonal scaling).
-template <bool kFlex, int BD>
+// The same pull where every cell is a block (scalar problems): the
+// workgroups walk node tiles of the lattice and find each node's blocks
+// from its lattice indices (no node-to-block map is read), summing them in
+// the same ascending order, so z is bitwise the mapped pull's.  fb may be
+// null (no unknown needs the diagonal scaling).  The partial sums of a
+// workgroup are reduced together, with one barrier.
+template <bool kFlex>
 __global__ __launch_bounds__(256) void k_cg_pull_lat(
     const double* __restrict__ y, const PullLattice L, int m, const double* __restrict__ fb,
     double* __restrict__ x, double* __restrict__ r, const double* __restrict__ p,
     const double* __restrict__ q, double* __restrict__ z, double* __restrict__ partial,
     const CgScalars* __restrict__ sc) {
-  __shared__ double lds[16];
+  constexpr int kN = kFlex ? 4 : 3;
+  __shared__ double lds[4][kN];
   if (sc->done) return;
   const double alpha = sc->alpha;
-  const PullTiles T = pull_tiles(L);
-  const int64_t ntiles = (int64_t)T.ntx * T.nty * T.ntz;
-  double a = 0.0, b = 0.0, c = 0.0, d = 0.0;
+  const int64_t ntiles = pull_num_tiles(L);
+  double v[kN] = {};
   // XCD-contiguous tile ranges: the block outputs of the cells on a tile's
   // faces, which the neighbouring tiles read too, stay in one XCD's L2
   const XcdRange xr = xcd_range(blockIdx.x, gridDim.x, ntiles);
   for (int64_t tile = xr.t0 + xr.j; tile < xr.t1; tile += xr.per) {
-#pragma unroll
-    for (int j = 0; j < BD; ++j) {
-      int gx, gy, gz, cc;
-      if (!pull_dof<BD>(L, T, tile, threadIdx.x + 256 * j, &gx, &gy, &gz, &cc)) continue;
-      const double sv = pull_lattice_sum(y, L, m, BD, gx, gy, gz, cc);
-      const int64_t i = (gx + (int64_t)L.n1 * (gy + (int64_t)L.n1 * gz)) * BD + cc;
-      const double qi = q[i];
-      const double ri = fma(-alpha, qi, r[i]);
-      x[i] = fma(alpha, p[i], x[i]);
-      r[i] = ri;
-      const double zi = fb ? fma(fb[i], ri, sv) : sv;
-      z[i] = zi;
-      a = fma(ri, zi, a);
-      b = fma(zi, zi, b);
-      c = fma(ri, ri, c);
-      if (kFlex) d = fma(zi, qi, d);
-    }
+    int gx, gy, gz;
+    if (!pull_node(L, tile, threadIdx.x, &gx, &gy, &gz)) continue;
+    const double sv = pull_lattice_sum(y, L, m, gx, gy, gz);
+    const int64_t i = gx + (int64_t)L.n1 * (gy + (int64_t)L.n1 * gz);
+    const double qi = q[i];
+    const double ri = fma(-alpha, qi, r[i]);
+    x[i] = fma(alpha, p[i], x[i]);
+    r[i] = ri;
+    const double zi = fb ? fma(fb[i], ri, sv) : sv;
+    z[i] = zi;
+    v[0] = fma(ri, zi, v[0]);
+    v[1] = fma(zi, zi, v[1]);
+    v[2] = fma(ri, ri, v[2]);
+    if constexpr (kFlex) v[3] = fma(zi, qi, v[3]);
   }
-  a = block_sum(a, lds);
-  b = block_sum(b, lds);
-  c = block_sum(c, lds);
-  if (kFlex) d = block_sum(d, lds);
-  if (threadIdx.x == 0) {
-    partial[blockIdx.x] = a;
-    partial[gridDim.x + blockIdx.x] = b;
-    partial[2 * gridDim.x + blockIdx.x] = c;
-    if (kFlex) partial[3 * gridDim.x + blockIdx.x] = d;
+  const int w = threadIdx.x / kWave;
+#pragma unroll
+  for (int k = 0; k < kN; ++k) {
+    v[k] = group_sum<kWave>(v[k]);
+    if (threadIdx.x % kWave == 0) lds[w][k] = v[k];
+  }
+  __syncthreads();
+  if (threadIdx.x < kN) {
+    const int k = threadIdx.x;
+    partial[k * gridDim.x + blockIdx.x] = ((lds[0][k] + lds[1][k]) + lds[2][k]) + lds[3][k];
   }
 }
 
@@ -579,8 +578,7 @@ static inline unsigned pull_grid_for(const fc_precond_s& pc, int64_t n, int64_t 
     const char* e = std::getenv("FC_PULL_GRID");
     return e ? std::max(64, std::atoi(e)) : 16384;
   }();
-  const PullTiles T = pull_tiles(pc.lat);
-  const int64_t nt = (int64_t)T.ntx * T.nty * T.ntz;
+  const int64_t nt = pull_num_tiles(pc.lat);
   // at most one partial set (four values) per workgroup fits in `partial`
   return (unsigned)std::min<int64_t>({nt, (int64_t)cap, (partial_len - 8) / 4});
 }
@@ -597,26 +595,15 @@ static hipError_t launch_cg_pull(const fc_precond_s& pc, unsigned pg, double* x,
                        pc.inv_idx, pc.fallback, pc.bdim, n, x, r, p, q, z, partial, sc);
     return hipGetLastError();
   }
+  // the lattice is set for scalar problems only
+  if (pc.bdim != 1) return hipErrorInvalidValue;
   const double* fb = pc.n_fallback ? pc.fallback : nullptr;
-  switch (pc.bdim) {
-    case 1:
-      hipLaunchKernelGGL((k_cg_pull_lat<kFlex, 1>), dim3(pg), dim3(256), 0, s, pc.y, pc.lat,
-                         pc.m, fb, x, r, p, q, z, partial, sc);
-      break;
-    case 2:
-      hipLaunchKernelGGL((k_cg_pull_lat<kFlex, 2>), dim3(pg), dim3(256), 0, s, pc.y, pc.lat,
-                         pc.m, fb, x, r, p, q, z, partial, sc);
-      break;
-    case 3:
-      hipLaunchKernelGGL((k_cg_pull_lat<kFlex, 3>), dim3(pg), dim3(256), 0, s, pc.y, pc.lat,
-                         pc.m, fb, x, r, p, q, z, partial, sc);
-      break;
-    default: return hipErrorInvalidValue;
-  }
+  hipLaunchKernelGGL(k_cg_pull_lat<kFlex>, dim3(pg), dim3(256), 0, s, pc.y, pc.lat, pc.m, fb, x,
+                     r, p, q, z, partial, sc);
   return hipGetLastError();
 }
 
-// grid of a two-vector dot: a few elements per lane keep enough loads in// grid of a two-vector dot: a few elements per lane keep enough loads in
+// grid of a two-vector dot: a few elements per lane keep enough loads in
 // flight (1024 workgroups left ten dependent iterations per lane at 2.7M)
 static inline unsigned dot_grid(int64_t n) { return std::min<unsigned>(nblk(n), 4096u); }
 

@@ -79,7 +79,7 @@ __global__ __launch_bounds__(256) void k_schwarz_sym_staged(
   // rounds it to FP32 at every use anyway, and half-width entries halve the
   // LDS traffic of the rotated reads
   __shared__ A rB[256];
-  __shared__ T tile[kStageRows][256];
+  __shared__ __align__(16) T tile[kStageRows * 256];
   if (sc && sc->done) return;
   // list: the workgroups handle only the listed blocks; skip: blocks
   // flagged there are left to another launch
@@ -139,7 +139,8 @@ __global__ __launch_bounds__(256) void k_schwarz_small(
     // the gathered entries are loaded first and the stored rows next, all
     // without branches (a lane without a block reads unknown 0), and only
     // then combined: the wait for the gather does not wait for the rows
-    dof = active ? lattice_cell_node(lat, (int)blk, i / bd) * bd + i % bd : 0;
+    // (the lattice is set for scalar problems only: one unknown per node)
+    dof = active ? lattice_cell_node(lat, (int)blk, i) : 0;
     g_r = r[dof];
     g_q = (q ? q : r)[dof];
     g_s = (isd ? isd : r)[dof];
@@ -583,24 +584,20 @@ hipError_t launch_schwarz_phase1(const fc_precond_s& pc, int precision, const do
   return hipErrorInvalidValue;
 }
 
-// The same where every cell is a block (lattice pull, see k_cg_pull_lat).
-template <int BD>
+// The same where every cell is a block (lattice pull, see k_cg_pull_lat;
+// scalar problems only).
 __global__ __launch_bounds__(256) void k_schwarz_pull_lat(const double* __restrict__ y,
                                                           const PullLattice L, int m,
                                                           const double* __restrict__ fb,
                                                           const double* __restrict__ r,
                                                           double* __restrict__ z) {
-  const PullTiles T = pull_tiles(L);
-  const int64_t ntiles = (int64_t)T.ntx * T.nty * T.ntz;
+  const int64_t ntiles = pull_num_tiles(L);
   for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
-#pragma unroll
-    for (int j = 0; j < BD; ++j) {
-      int gx, gy, gz, c;
-      if (!pull_dof<BD>(L, T, tile, threadIdx.x + 256 * j, &gx, &gy, &gz, &c)) continue;
-      const double sv = pull_lattice_sum(y, L, m, BD, gx, gy, gz, c);
-      const int64_t i = (gx + (int64_t)L.n1 * (gy + (int64_t)L.n1 * gz)) * BD + c;
-      z[i] = fb ? fma(fb[i], r[i], sv) : sv;
-    }
+    int gx, gy, gz;
+    if (!pull_node(L, tile, threadIdx.x, &gx, &gy, &gz)) continue;
+    const double sv = pull_lattice_sum(y, L, m, gx, gy, gz);
+    const int64_t i = gx + (int64_t)L.n1 * (gy + (int64_t)L.n1 * gz);
+    z[i] = fb ? fma(fb[i], r[i], sv) : sv;
   }
 }
 
@@ -609,16 +606,10 @@ hipError_t launch_schwarz_pull(const fc_precond_s& pc, const double* r, double* 
   const int64_t n = pc.pb->n_dofs;
   if (n == 0) return hipSuccess;
   if (pc.lat.dim > 0) {
-    const PullTiles T = pull_tiles(pc.lat);
-    const int64_t nt = (int64_t)T.ntx * T.nty * T.ntz;
-    const dim3 g((unsigned)std::min<int64_t>(nt, 4096)), b(256);
+    if (pc.bdim != 1) return hipErrorInvalidValue;
+    const dim3 g((unsigned)std::min<int64_t>(pull_num_tiles(pc.lat), 4096)), b(256);
     const double* fb = pc.n_fallback ? pc.fallback : nullptr;
-    switch (pc.bdim) {
-      case 1: hipLaunchKernelGGL(k_schwarz_pull_lat<1>, g, b, 0, s, pc.y, pc.lat, pc.m, fb, r, z); break;
-      case 2: hipLaunchKernelGGL(k_schwarz_pull_lat<2>, g, b, 0, s, pc.y, pc.lat, pc.m, fb, r, z); break;
-      case 3: hipLaunchKernelGGL(k_schwarz_pull_lat<3>, g, b, 0, s, pc.y, pc.lat, pc.m, fb, r, z); break;
-      default: return hipErrorInvalidValue;
-    }
+    hipLaunchKernelGGL(k_schwarz_pull_lat, g, b, 0, s, pc.y, pc.lat, pc.m, fb, r, z);
     return hipGetLastError();
   }
   hipLaunchKernelGGL(k_schwarz_pull, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, pc.y,

@@ -6,8 +6,9 @@
 // Layout (row-SoA BSR): the values of block row i are stored entry-major,
 // val[rowptr[i]*B*B + e*L + k] for entry e of the k-th block of the row,
 // so G lanes sweeping the blocks of one row read G consecutive values per
-// entry.  A group of G lanes owns one block row; its partial sums are
-// combined with a butterfly reduction.  Every block row reads its own
+// entry (two adjacent blocks per lane for 2x2 and 3x3 blocks, so each entry
+// of a lane is one 16-byte load).  A group of G lanes owns one block row;
+// its partial sums are combined with a butterfly reduction.  Every block row reads its own
 // stored values once per product; FP64 3x3 values and column indices are
 // streamed with non-temporal loads, which leaves the cache to the gathered x
 // entries (neighbouring rows of the lattice share most of their columns).
@@ -50,10 +51,15 @@ __device__ __forceinline__ T stream_load(const T* p) {
 // kLat: columns computed from the lattice box (col is not read).
 // XT: type of x (FP32 for the FP32 rows of the mixed product, which round
 // x to FP32 before every product anyway).
-// U: blocks per lane per pass (all loads of a pass are in flight together).
+// U: blocks per lane per pass (all loads of a pass are in flight together);
+// U = 2 takes two adjacent blocks, so each entry is one two-wide load (half
+// the load instructions of two separate blocks: 5.5 % faster for the 3x3
+// rows of 32^3-cell p = 3 elasticity).
 // kNT: stream the matrix values non-temporally.
+// At most 96 VGPRs, five waves per SIMD: the paired loads otherwise take 105
+// VGPRs and four waves, which is 3 % slower.
 template <int B, int G, typename T, bool kLat, typename XT, int U, bool kNT>
-__global__ __launch_bounds__(256) void k_spmv_bsr(
+__global__ __launch_bounds__(256, 5) void k_spmv_bsr(
     const int32_t* __restrict__ rowptr, const int32_t* __restrict__ col,
     const T* __restrict__ val, const XT* __restrict__ x,
     double* __restrict__ y, int64_t n_rows, const CgScalars* __restrict__ sc,
@@ -96,26 +102,69 @@ __global__ __launch_bounds__(256) void k_spmv_bsr(
       acc[i] = 0.0;
       accf[i] = 0.0f;
     }
-    for (int k = lane; k < L; k += U * G) {
+    // U == 2: a lane takes two adjacent blocks, so each entry of the pair
+    // is one 2-wide load (16 bytes for FP64; 8-byte aligned, which the
+    // hardware loads as one access)
+    constexpr bool kPair = U == 2;
+    const int k0 = kPair ? 2 * lane : lane;
+    for (int k = k0; k < L; k += U * G) {
       int c[U];
       T a[U][BB];
+      if constexpr (kPair) {
+        typedef T t2 __attribute__((ext_vector_type(2), aligned(sizeof(T))));
 #pragma unroll
-      for (int u = 0; u < U; ++u) {
-        const int ku = k + u * G;
-        const bool on = ku < L;
-        if constexpr (kLat)
-          c[u] = on ? lattice_col(box, ku, lat.n1) : -1;
-        else
-          c[u] = on ? stream_load<kNT>(col + base + ku) : -1;
+        for (int u = 0; u < 2; ++u) {
+          const bool on = k + u < L;
+          if constexpr (kLat)
+            c[u] = on ? lattice_col(box, k + u, lat.n1) : -1;
+          else
+            c[u] = on ? stream_load<kNT>(col + base + k + u) : -1;
+        }
+        if (k + 1 < L) {
 #pragma unroll
-        for (int e = 0; e < BB; ++e)
-          a[u][e] = on ? stream_load<kNT>(v + (int64_t)e * L + ku) : T(0);
+          for (int e = 0; e < BB; ++e) {
+            const t2* p = reinterpret_cast<const t2*>(v + (int64_t)e * L + k);
+            const t2 t = kNT ? __builtin_nontemporal_load(p) : *p;
+            a[0][e] = t.x;
+            a[1][e] = t.y;
+          }
+        } else {
+#pragma unroll
+          for (int e = 0; e < BB; ++e) {
+            a[0][e] = stream_load<kNT>(v + (int64_t)e * L + k);
+            a[1][e] = T(0);
+          }
+        }
+      } else {
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const int ku = k + u * G;
+          const bool on = ku < L;
+          if constexpr (kLat)
+            c[u] = on ? lattice_col(box, ku, lat.n1) : -1;
+          else
+            c[u] = on ? stream_load<kNT>(col + base + ku) : -1;
+#pragma unroll
+          for (int e = 0; e < BB; ++e)
+            a[u][e] = on ? stream_load<kNT>(v + (int64_t)e * L + ku) : T(0);
+        }
       }
       XT xv[U][B];
 #pragma unroll
-      for (int u = 0; u < U; ++u)
+      for (int u = 0; u < U; ++u) {
+        if constexpr (B == 3) {
+          typedef XT x2 __attribute__((ext_vector_type(2), aligned(sizeof(XT))));
+          const int64_t cc = c[u] >= 0 ? (int64_t)c[u] * B : 0;
+          const x2 t = *reinterpret_cast<const x2*>(x + cc);
+          const XT t2 = x[cc + 2];
+          xv[u][0] = c[u] >= 0 ? t.x : XT(0);
+          xv[u][1] = c[u] >= 0 ? t.y : XT(0);
+          xv[u][2] = c[u] >= 0 ? t2 : XT(0);
+        } else {
 #pragma unroll
-        for (int jj = 0; jj < B; ++jj) xv[u][jj] = c[u] >= 0 ? x[(int64_t)c[u] * B + jj] : XT(0);
+          for (int jj = 0; jj < B; ++jj) xv[u][jj] = c[u] >= 0 ? x[(int64_t)c[u] * B + jj] : XT(0);
+        }
+      }
 #pragma unroll
       for (int u = 0; u < U; ++u)
 #pragma unroll
@@ -149,20 +198,6 @@ __global__ __launch_bounds__(256) void k_spmv_bsr(
 }
 
 // ---------------------------------------------------------------- sliced
-// Lattice range of the functions whose support meets that of index g along
-// one direction (as in row_box_at).
-__device__ __forceinline__ void dir_box(int g, const LatticeInfo& lat, int* lo, int* len) {
-  const int p = lat.p;
-  if (g % p == 0) {
-    const int a = max(0, g - p), b = min(lat.n1 - 1, g + p);
-    *lo = a;
-    *len = b - a + 1;
-  } else {
-    *lo = (g / p) * p;
-    *len = p + 1;
-  }
-}
-
 // x index of lane row i of a class: interior vertices x = p (i + 1), other
 // interior indices in ascending order (p - 1 per cell; none when p = 1)
 __device__ __forceinline__ int sell_x(bool vertex, int i, int p) {
@@ -179,6 +214,20 @@ __device__ __forceinline__ int sell_x_p(bool vertex, int i) {
   }
 }
 
+// Lattice range of the functions whose support meets that of index g along
+// one direction (as in row_box_at), for degree P.
+template <int P>
+__device__ __forceinline__ void dir_box_p(int g, int n1, int* lo, int* len) {
+  if (g % P == 0) {
+    const int a = max(0, g - P), b = min(n1 - 1, g + P);
+    *lo = a;
+    *len = b - a + 1;
+  } else {
+    *lo = (g / P) * P;
+    *len = P + 1;
+  }
+}
+
 struct SellSlice {
   int64_t line;
   bool vertex;
@@ -190,6 +239,18 @@ __device__ __forceinline__ SellSlice sell_slice(int64_t s, int cv, int cn) {
   const int spl = cv + cn;
   r.line = s / spl;
   const int loc = (int)(s - r.line * spl);
+  r.vertex = loc < cv;
+  r.chunk = r.vertex ? loc : loc - cv;
+  return r;
+}
+
+// The same for the product kernel: fewer than 2^31 slices, and the slices
+// per line divided by multiply-shift.
+__device__ __forceinline__ SellSlice sell_slice_fast(uint32_t s, int cv, const FastDiv dspl) {
+  SellSlice r;
+  const uint32_t line = fdiv(s, dspl);
+  const int loc = (int)(s - line * dspl.d);
+  r.line = line;
   r.vertex = loc < cv;
   r.chunk = r.vertex ? loc : loc - cv;
   return r;
@@ -215,7 +276,11 @@ __global__ __launch_bounds__(256) void k_sell_build(const double* __restrict__ v
         const int c[3] = {sell_x(sl.vertex, i, lat.p), y0, z0};
         v = val[lattice_row_start_at(c, row_box_at(c, lat), lat) + k];
       }
-      sv[off[s] + e] = v;
+      // entries in pairs: lane l holds entries 2j, 2j + 1 at 128 j + 2 l + 0/1;
+      // an odd last entry alone at 128 j + l
+      const int64_t dst = (k == len - 1 && (len & 1)) ? (int64_t)(k / 2) * 128 + l
+                                                      : (int64_t)(k / 2) * 128 + 2 * l + (k & 1);
+      sv[off[s] + dst] = v;
     }
   }
 }
@@ -223,37 +288,80 @@ __global__ __launch_bounds__(256) void k_sell_build(const double* __restrict__ v
 // y = A x on the sliced rows: one wave per slice, one row per lane.  The
 // box entries run x-pencil by x-pencil (kx fastest); every lane of a slice
 // has the same pencil count and length, so the pencil's column offset in y
-// and z is the same for all lanes and each entry is two loads (the value
-// run of the slice is 512 contiguous bytes per entry) and one FMA.
-// Pencils of one slice, R per round, all their loads issued before the
-// first FMA; a pencil index past the last reads the round's first pencil and
-// its products are skipped (a wave-uniform test).  kNT: the values (read
-// once) are streamed non-temporally.
-template <int K, bool kNT, int R>
-__device__ __forceinline__ double sell_pencils(const double* __restrict__ vs,
+// and z is the same for all lanes.  Pencils go two per round, all their
+// loads issued before the first FMA: a round's 2K entries are K paired
+// values per lane (one 16-byte load each, 1 KB contiguous per wave; 8 %
+// faster than one 8-byte load per entry at 64^3 cells, p = 2), and each
+// pencil's x run is read two entries per load.  A last round with one
+// pencil reads its odd last entry alone.  kNT: the values (read once) are
+// streamed non-temporally.  The pencil's (y, z) offsets are stepped, not
+// divided out of its index.
+template <int K, bool kNT>
+__device__ __forceinline__ double sell_pencils(const double* __restrict__ vs, int l,
                                                const double* __restrict__ xb, int len1,
                                                int npen, int64_t n1) {
+  typedef double d2 __attribute__((ext_vector_type(2)));
+  typedef double d2a8 __attribute__((ext_vector_type(2), aligned(8)));
   double acc = 0.0;
-  for (int q = 0; q < npen; q += R) {
-    double a[R][K], b[R][K];
-#pragma unroll
-    for (int u = 0; u < R; ++u) {
-      const int qq = q + u < npen ? q + u : q;
-      const int qz = qq / len1, qy = qq - qz * len1;
-      const double* xp = xb + n1 * (qy + n1 * qz);
-      const double* vp = vs + (int64_t)64 * K * qq;
-#pragma unroll
-      for (int kx = 0; kx < K; ++kx) {
-        a[u][kx] = kNT ? __builtin_nontemporal_load(vp + 64 * kx) : vp[64 * kx];
-        b[u][kx] = xp[kx];
-      }
+  int qy = 0, qz = 0;   // offsets of pencil q
+  for (int q = 0; q < npen; q += 2) {
+    const double* vr = vs + (int64_t)128 * K * (q / 2) + 2 * l;
+    const double* xp0 = xb + n1 * (qy + n1 * qz);
+    if (++qy == len1) {
+      qy = 0;
+      ++qz;
     }
-#pragma unroll
-    for (int u = 0; u < R; ++u) {
-      if (q + u < npen) {
-#pragma unroll
-        for (int kx = 0; kx < K; ++kx) acc = fma(a[u][kx], b[u][kx], acc);
+    if (q + 1 < npen) {
+      const double* xp1 = xb + n1 * (qy + n1 * qz);
+      if (++qy == len1) {
+        qy = 0;
+        ++qz;
       }
+      double a[2 * K], b[2 * K];
+#pragma unroll
+      for (int j = 0; j < K; ++j) {
+        const d2* p = reinterpret_cast<const d2*>(vr + 128 * j);
+        const d2 t = kNT ? __builtin_nontemporal_load(p) : *p;
+        a[2 * j] = t.x;
+        a[2 * j + 1] = t.y;
+      }
+#pragma unroll
+      for (int kx = 0; kx + 1 < K; kx += 2) {
+        const d2a8 t0 = *reinterpret_cast<const d2a8*>(xp0 + kx);
+        const d2a8 t1 = *reinterpret_cast<const d2a8*>(xp1 + kx);
+        b[kx] = t0.x;
+        b[kx + 1] = t0.y;
+        b[K + kx] = t1.x;
+        b[K + kx + 1] = t1.y;
+      }
+      if (K & 1) {
+        b[K - 1] = xp0[K - 1];
+        b[2 * K - 1] = xp1[K - 1];
+      }
+#pragma unroll
+      for (int e = 0; e < 2 * K; ++e) acc = fma(a[e], b[e], acc);
+    } else {
+      double a[K], b[K];
+#pragma unroll
+      for (int j = 0; j < K / 2; ++j) {
+        const d2* p = reinterpret_cast<const d2*>(vr + 128 * j);
+        const d2 t = kNT ? __builtin_nontemporal_load(p) : *p;
+        a[2 * j] = t.x;
+        a[2 * j + 1] = t.y;
+      }
+      if (K & 1) {
+        const double* p = vr - l + 128 * (K / 2);   // the odd last entry, alone
+        a[K - 1] = kNT ? __builtin_nontemporal_load(p) : *p;
+      }
+#pragma unroll
+      for (int kx = 0; kx + 1 < K; kx += 2) {
+        const d2a8 t0 = *reinterpret_cast<const d2a8*>(xp0 + kx);
+        b[kx] = t0.x;
+        b[kx + 1] = t0.y;
+      }
+      if (K & 1) b[K - 1] = xp0[K - 1];
+#pragma unroll
+      for (int e = 0; e < K; ++e) acc = fma(a[e], b[e], acc);
     }
   }
   return acc;
@@ -262,37 +370,38 @@ __device__ __forceinline__ double sell_pencils(const double* __restrict__ vs,
 template <int P, bool kNT>
 __global__ __launch_bounds__(256) void k_spmv_sell(const double* __restrict__ sv,
                                                    const int64_t* __restrict__ off,
-                                                   int64_t n_slices, int cv, int cn, int nv,
-                                                   int nn, const double* __restrict__ x,
+                                                   int64_t n_slices, int cv, const FastDiv dspl,
+                                                   int nv, int nn, const double* __restrict__ x,
                                                    double* __restrict__ y,
                                                    const CgScalars* __restrict__ sc,
                                                    const LatticeInfo lat) {
   if (sc && sc->done) return;
   // the slice of this wave (wave-uniform, so everything derived from it
-  // stays in scalar registers)
+  // stays in scalar registers; no division by a run-time value)
   const int64_t s = xcd_remap(blockIdx.x, gridDim.x) * 4 +
                     __builtin_amdgcn_readfirstlane(threadIdx.x / 64);
   if (s >= n_slices) return;
   const int l = threadIdx.x % 64;
-  const SellSlice sl = sell_slice(s, cv, cn);
+  const SellSlice sl = sell_slice_fast((uint32_t)s, cv, dspl);
   const int n1 = lat.n1;
-  const int y0 = lat.dim >= 2 ? (int)(sl.line % n1) : 0;
-  const int z0 = lat.dim == 3 ? (int)(sl.line / n1) : 0;
+  const uint32_t lz = fdiv((uint32_t)sl.line, lat.dn1);
+  const int y0 = lat.dim >= 2 ? (int)((uint32_t)sl.line - lz * (uint32_t)n1) : 0;
+  const int z0 = lat.dim == 3 ? (int)lz : 0;
   int lo1 = 0, len1 = 1, lo2 = 0, len2 = 1;
-  if (lat.dim >= 2) dir_box(y0, lat, &lo1, &len1);
-  if (lat.dim == 3) dir_box(z0, lat, &lo2, &len2);
+  if (lat.dim >= 2) dir_box_p<P>(y0, n1, &lo1, &len1);
+  if (lat.dim == 3) dir_box_p<P>(z0, n1, &lo2, &len2);
   const int count = sl.vertex ? nv : nn;
   const int i = sl.chunk * 64 + l;
   const bool valid = i < count;
   const int xr = sell_x_p<P>(sl.vertex, valid ? i : count - 1);
   const int lo0 = sl.vertex ? xr - P : (xr / P) * P;
-  const double* vs = sv + off[s] + l;
+  const double* vs = sv + off[s];
   const double* xb = x + lo0 + (int64_t)n1 * (lo1 + (int64_t)n1 * lo2);
   const int npen = len1 * len2;
   // two pencils per round: 1 % faster than four and 3 % faster than eight
   // at 64^3 cells, p = 2
-  const double acc = sl.vertex ? sell_pencils<2 * P + 1, kNT, 2>(vs, xb, len1, npen, n1)
-                               : sell_pencils<P + 1, kNT, 2>(vs, xb, len1, npen, n1);
+  const double acc = sl.vertex ? sell_pencils<2 * P + 1, kNT>(vs, l, xb, len1, npen, n1)
+                               : sell_pencils<P + 1, kNT>(vs, l, xb, len1, npen, n1);
   if (valid) y[xr + (int64_t)n1 * (y0 + (int64_t)n1 * z0)] = acc;
 }
 
@@ -352,6 +461,7 @@ static hipError_t spmv_dispatch(const DeviceBsr& A, const T* val, const XT* x,
   if constexpr (B == 1 && sizeof(T) == 8 && sizeof(XT) == 8) {
     if (lat && A.sell_val && !rows && !partial) {
       const int cn = A.sell_nn > 0 ? (A.sell_nn + 63) / 64 : 0;
+      const FastDiv dspl = make_fastdiv((uint32_t)(A.sell_cv + cn));
       dim3 g((unsigned)((A.n_slices + 3) / 4)), b(256);
       // values streamed non-temporally (3 % faster at 64^3 cells, p = 2;
       // FC_SPMV_SELL_NT=0 reads them through the caches)
@@ -360,11 +470,11 @@ static hipError_t spmv_dispatch(const DeviceBsr& A, const T* val, const XT* x,
   do {                                                                                        \
     if (sell_nt)                                                                              \
       hipLaunchKernelGGL((k_spmv_sell<PP, true>), g, b, 0, s, A.sell_val, A.sell_off,         \
-                         A.n_slices, A.sell_cv, cn, A.sell_nv, A.sell_nn, (const double*)x, y, \
+                         A.n_slices, A.sell_cv, dspl, A.sell_nv, A.sell_nn, (const double*)x, y, \
                          sc, A.lat);                                                          \
     else                                                                                      \
       hipLaunchKernelGGL((k_spmv_sell<PP, false>), g, b, 0, s, A.sell_val, A.sell_off,        \
-                         A.n_slices, A.sell_cv, cn, A.sell_nv, A.sell_nn, (const double*)x, y, \
+                         A.n_slices, A.sell_cv, dspl, A.sell_nv, A.sell_nn, (const double*)x, y, \
                          sc, A.lat);                                                          \
   } while (0)
       switch (A.lat.p) {

@@ -60,49 +60,67 @@ struct StageRows {
   static constexpr int value = sizeof(T) == 8 ? 8 : 16;
 };
 
-// Symmetric product of one block (m > 64) by a whole workgroup, one output
-// row i per thread (threads with i >= m take part in the barriers only):
-// chunks of stored rows are loaded with coalesced non-temporal loads, every
-// thread its own entry, written to LDS, and the rotated entries are read
-// back from LDS, so HBM and L2 see each stored entry exactly once.  rB holds
-// the block's gathered right-hand side (m entries, in LDS).  The stored
-// entries are streamed non-temporally (each is read once per product).
+// Symmetric product of one block (m > 64) by a whole workgroup of
+// 64 ceil(m/64) threads, one output row i per thread (threads with i >= m
+// take part in the loads and barriers only).  A chunk of stored rows is one
+// contiguous run of the block; every thread loads 16-byte pieces of it
+// (half the load instructions of one entry per thread, and no idle lanes),
+// non-temporally, into LDS, and each thread then reads its own entry and
+// the rotated one back from LDS, so HBM and L2 see each stored entry exactly
+// once.  rB holds the block's gathered right-hand side (m entries, in LDS).
+// tile (16-byte aligned) holds kStageRows * m <= kStageRows * 256 entries,
+// as tile[kk * m + j] for stored row k0 + kk.
 template <typename T, typename RB>
 __device__ __forceinline__ double sym_block_staged(const T* __restrict__ Qb, const RB* rB,
-                                                   int m, int i,
-                                                   T (*tile)[256]) {
+                                                   int m, int i, T* tile) {
   using A = typename Acc<T>::type;
   constexpr int kStageRows = StageRows<T>::value;
+  constexpr int V = 16 / sizeof(T);                // entries per 16-byte piece
+  constexpr int kPer = kStageRows / V;             // pieces per thread per chunk (m <= threads)
+  typedef T tv __attribute__((ext_vector_type(V), aligned(sizeof(T))));
+  typedef T tva __attribute__((ext_vector_type(V), aligned(16)));
+  const int nt = blockDim.x, t = threadIdx.x;
   const bool act = i < m;
   const int h = m / 2;
   const bool even = (m & 1) == 0;
   A acc0 = 0, acc1 = 0;
   int ip = i, im = i;
   for (int k0 = 0; k0 <= h; k0 += kStageRows) {
-    T v[kStageRows];
+    const int rows = min(kStageRows, h + 1 - k0);
+    const int cnt = rows * m;                      // entries of this chunk
+    const T* src = Qb + (int64_t)k0 * m;
+    tv v[kPer];
 #pragma unroll
-    for (int kk = 0; kk < kStageRows; ++kk) {
-      const int k = k0 + kk;
-      const T* src = Qb + (int64_t)k * m + i;
-      v[kk] = (act && k <= h) ? __builtin_nontemporal_load(src) : T(0);
+    for (int u = 0; u < kPer; ++u) {
+      const int e = (t + nt * u) * V;
+      if (e + V <= cnt) {
+        v[u] = __builtin_nontemporal_load(reinterpret_cast<const tv*>(src + e));
+      } else {
+#pragma unroll
+        for (int c = 0; c < V; ++c) v[u][c] = e + c < cnt ? __builtin_nontemporal_load(src + e + c) : T(0);
+      }
     }
-    __syncthreads();   // previous chunk's rotated reads are done
+    __syncthreads();   // previous chunk's reads are done
 #pragma unroll
-    for (int kk = 0; kk < kStageRows; ++kk) tile[kk][i] = v[kk];
+    for (int u = 0; u < kPer; ++u) {
+      const int e = (t + nt * u) * V;
+      if (e < cnt) *reinterpret_cast<tva*>(tile + e) = v[u];   // the pad past cnt is never read
+    }
     __syncthreads();
     if (act) {
 #pragma unroll
       for (int kk = 0; kk < kStageRows; ++kk) {
         const int k = k0 + kk;
         if (k > h) break;
+        const T* row = tile + kk * m;
         if (k == 0) {
-          acc0 = madd<A>(v[kk], rB[i], acc0);
+          acc0 = madd<A>(row[i], rB[i], acc0);
           continue;
         }
         ip = (ip + 1 == m) ? 0 : ip + 1;
         im = (im == 0) ? m - 1 : im - 1;
-        acc0 = madd<A>(v[kk], rB[ip], acc0);
-        if (!(even && k == h)) acc1 = madd<A>(tile[kk][im], rB[im], acc1);
+        acc0 = madd<A>(row[i], rB[ip], acc0);
+        if (!(even && k == h)) acc1 = madd<A>(row[im], rB[im], acc1);
       }
     }
   }
