@@ -16,7 +16,10 @@
 //     load is a contiguous segment, no cross-lane reduction is needed, and
 //     HBM delivers each stored entry once (the rotated read hits the cache
 //     line the direct read of a neighbouring thread brought in).  When m is
-//     even the row k = m/2 holds every pair twice and is used once.
+//     even the row k = m/2 holds every pair twice and is used once.  For
+//     m <= 64 (one lane per column) the stored rows are kept in pairs,
+//     rows 2j and 2j + 1 interleaved column by column, so a lane reads two
+//     of its entries with one load (sym_offset).
 //   * Dense layout: lane i accumulates sum_j P_B[j][i] r_B[j] (row j of a
 //     symmetric matrix is its column j) reading P_B row by row.
 //   * FP32: the same wrapped diagonals of the diagonally scaled inverse
@@ -103,7 +106,8 @@ __global__ __launch_bounds__(256) void k_schwarz_sym_staged(
 // m <= 64: each wave handles floor(64/m) blocks, one lane per output row.
 // kM > 0 (symmetric layout, m = kM known at compile time): lane i loads its
 // column of the stored rows (Q_B[k][i] = P_B[i][(i + k) mod m], k = 0 ..
-// m/2) into registers before it gathers r_B, so the block's stream is in
+// m/2; two rows per load, as sym_offset pairs them) into registers before
+// it gathers r_B, so the block's stream is in
 // flight during the gather; the entries P_B[i][(i - k) mod m] =
 // Q_B[k][(i - k) mod m] are then read from the lane that loaded them (a
 // cross-lane read within the wave).  kM = 0: any m, the stored rows read
@@ -146,8 +150,16 @@ __global__ __launch_bounds__(256) void k_schwarz_small(
     g_s = (isd ? isd : r)[dof];
   }
   if constexpr (kSym && kM > 0) {
+    // stored rows in pairs (sym_offset, m <= 64): one two-wide load each
+    constexpr int kNP = (kH + 1) & ~1;
+    typedef T t2 __attribute__((ext_vector_type(2), aligned(sizeof(T))));
 #pragma unroll
-    for (int k = 0; k <= kH; ++k) v[k] = Pb[k * kM + i];
+    for (int k = 0; k < kNP; k += 2) {
+      const t2 t = *reinterpret_cast<const t2*>(Pb + k * kM + 2 * i);
+      v[k] = t.x;
+      v[k + 1] = t.y;
+    }
+    if constexpr (kNP < kH + 1) v[kH] = Pb[kH * kM + i];
   }
   if constexpr (kLat) {
     rv = (q ? fma(-alpha, g_q, g_r) : g_r) * (isd ? g_s : 1.0);
@@ -360,7 +372,8 @@ __global__ __launch_bounds__(256) void k_schwarz_pull(
   z[i] = fma(fb[i], r[i], s);
 }
 
-// Wrapped-diagonal copy: Q[blk][k][i] = P[blk][i][(i+k) mod m], k <= m/2.
+// Wrapped-diagonal copy: entry (k, i) of block blk, P[blk][i][(i+k) mod m]
+// for k <= m/2, at Q[blk * (m/2 + 1) m + sym_offset(k, i, m)].
 // With isd (low-precision copies) the stored block is the diagonally
 // scaled D^{1/2} P_B D^{1/2} (D = diag(A) on the block's unknowns, isd =
 // D^{-1/2}), which removes the 1/alpha dynamic range of fictitious
@@ -387,15 +400,16 @@ __global__ void k_pack_sym(const double* __restrict__ P, T* __restrict__ Q, int 
       const int64_t dj = block_dof(elem_nodes, e, nn, bd, j);
       v = (di < 0 || dj < 0) ? 0.0 : v / (isd[di] * isd[dj]);
     }
+    const int64_t dst = blk * per + sym_offset(k, i, m);
     if constexpr (sizeof(T) == 8) {
-      Q[t] = v;
+      Q[dst] = v;
     } else if constexpr (sizeof(T) == 4) {
-      Q[t] = (float)v;
+      Q[dst] = (float)v;
     } else {
       // FP64 -> BF16 through FP32, round to nearest even
       uint32_t u = __float_as_uint((float)v);
       u += 0x7fffu + ((u >> 16) & 1u);
-      Q[t] = (T)(u >> 16);
+      Q[dst] = (T)(u >> 16);
     }
   }
 }

@@ -10,6 +10,17 @@ __host__ __device__ __forceinline__ int64_t sym_block_stride_dev(int m) {
   return (int64_t)(m / 2 + 1) * m;
 }
 
+// Offset of stored entry (k, i) = P_B[i][(i + k) mod m] of a block in the
+// wrapped-diagonal layout.  m > 64 (one block per workgroup): stored row by
+// stored row.  m <= 64 (one lane per column i): stored rows 2j and 2j + 1
+// interleaved column by column, so a lane's two entries are adjacent and
+// one two-wide load; an odd last stored row follows alone.
+__host__ __device__ __forceinline__ int64_t sym_offset(int k, int i, int m) {
+  if (m > 64) return (int64_t)k * m + i;
+  const int npair = (m / 2 + 1) & ~1;   // stored rows that come in pairs
+  return k < npair ? (int64_t)(k & ~1) * m + 2 * i + (k & 1) : (int64_t)k * m + i;
+}
+
 template <typename T>
 __device__ __forceinline__ double to_f64(T v);
 template <>
@@ -127,7 +138,8 @@ __device__ __forceinline__ double sym_block_staged(const T* __restrict__ Qb, con
   return (double)acc0 + (double)acc1;
 }
 
-// Wrapped-diagonal symmetric product for one block row i (0 <= i < m).
+// Wrapped-diagonal symmetric product for one block row i (0 <= i < m), in
+// either layout of sym_offset.
 template <typename T>
 __device__ __forceinline__ double sym_row(const T* __restrict__ Qb, const double* rb, int m,
                                           int i) {
@@ -135,15 +147,14 @@ __device__ __forceinline__ double sym_row(const T* __restrict__ Qb, const double
   const int h = m / 2;
   const bool even = (m & 1) == 0;
   A acc0 = 0, acc1 = 0;
-  acc0 = madd<A>(Qb[i], rb[i], acc0);
+  acc0 = madd<A>(Qb[sym_offset(0, i, m)], rb[i], acc0);
   int ip = i, im = i;
 #pragma unroll 4
   for (int k = 1; k <= h; ++k) {
     ip = (ip + 1 == m) ? 0 : ip + 1;   // (i + k) mod m
     im = (im == 0) ? m - 1 : im - 1;   // (i - k) mod m
-    const T* row = Qb + (int64_t)k * m;
-    acc0 = madd<A>(row[i], rb[ip], acc0);
-    if (!(even && k == h)) acc1 = madd<A>(row[im], rb[im], acc1);
+    acc0 = madd<A>(Qb[sym_offset(k, i, m)], rb[ip], acc0);
+    if (!(even && k == h)) acc1 = madd<A>(Qb[sym_offset(k, im, m)], rb[im], acc1);
   }
   return (double)acc0 + (double)acc1;
 }
