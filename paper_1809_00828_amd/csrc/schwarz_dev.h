@@ -82,7 +82,7 @@ struct StageRows {
 // tile (16-byte aligned) holds kStageRows * m <= kStageRows * 256 entries,
 // as tile[kk * m + j] for stored row k0 + kk.
 template <typename T, typename RB>
-__device__ __forceinline__ double sym_block_staged(const T* __restrict__ Qb, const RB* rB,
+__device__ __forceinline__ double sym_block_staged_runs(const T* __restrict__ Qb, const RB* rB,
                                                    int m, int i, T* tile) {
   using A = typename Acc<T>::type;
   constexpr int kStageRows = StageRows<T>::value;
@@ -132,6 +132,50 @@ __device__ __forceinline__ double sym_block_staged(const T* __restrict__ Qb, con
         im = (im == 0) ? m - 1 : im - 1;
         acc0 = madd<A>(row[i], rB[ip], acc0);
         if (!(even && k == h)) acc1 = madd<A>(row[im], rB[im], acc1);
+      }
+    }
+  }
+  return (double)acc0 + (double)acc1;
+}
+
+// The same with every thread loading its own entry of each stored row of
+// the chunk (8-byte loads) and keeping it in a register; only the rotated
+// entries are read back from LDS (tile[kk * 256 + j]).
+template <typename T, typename RB>
+__device__ __forceinline__ double sym_block_staged_rows(const T* __restrict__ Qb, const RB* rB,
+                                                        int m, int i, T* tile) {
+  using A = typename Acc<T>::type;
+  constexpr int kStageRows = StageRows<T>::value;
+  const bool act = i < m;
+  const int h = m / 2;
+  const bool even = (m & 1) == 0;
+  A acc0 = 0, acc1 = 0;
+  int ip = i, im = i;
+  for (int k0 = 0; k0 <= h; k0 += kStageRows) {
+    T v[kStageRows];
+#pragma unroll
+    for (int kk = 0; kk < kStageRows; ++kk) {
+      const int k = k0 + kk;
+      const T* src = Qb + (int64_t)k * m + i;
+      v[kk] = (act && k <= h) ? __builtin_nontemporal_load(src) : T(0);
+    }
+    __syncthreads();   // previous chunk's rotated reads are done
+#pragma unroll
+    for (int kk = 0; kk < kStageRows; ++kk) tile[kk * 256 + i] = v[kk];
+    __syncthreads();
+    if (act) {
+#pragma unroll
+      for (int kk = 0; kk < kStageRows; ++kk) {
+        const int k = k0 + kk;
+        if (k > h) break;
+        if (k == 0) {
+          acc0 = madd<A>(v[kk], rB[i], acc0);
+          continue;
+        }
+        ip = (ip + 1 == m) ? 0 : ip + 1;
+        im = (im == 0) ? m - 1 : im - 1;
+        acc0 = madd<A>(v[kk], rB[ip], acc0);
+        if (!(even && k == h)) acc1 = madd<A>(tile[kk * 256 + im], rB[im], acc1);
       }
     }
   }
