@@ -34,7 +34,7 @@ HBM_PEAK_GBS = 8000.0
 # counter passes (FETCH_SIZE, WRITE_SIZE), scaled by what the same counters
 # read for a plain 4 GiB copy (profiles/pcg_fp64_elastic32_p3_hbm_counters.md);
 # to be re-measured whenever one of these kernels changes.
-TRAFFIC = {"spmv": 8.5189e9, "schwarz": 4.9989e9}
+TRAFFIC = {"spmv": 8.5187e9, "schwarz": 4.9989e9}
 METRIC = "DOF·iter/s and time-to-1e-8 residual: mixed/learned vs plain FP64 PCG"
 
 
@@ -724,7 +724,8 @@ def main():
     if info.get("lattice_columns"):
         # the same product with the 4-byte block columns read from memory
         k_spmv["bytes_per_launch_with_columns"] = spmv_b + info["nnzb"] * 4
-    schw_name = "k_schwarz_sym_staged<double>" if m > 64 else "k_schwarz_small<double,sym>"
+    schw_name = ("k_schwarz_sym_staged<double,%s>" % ("true" if m > 128 else "false")
+                 if m > 64 else "k_schwarz_small<double,sym>")
     k_schw = {"bound": "hbm", "kernel": schw_name + " (block products)",
               "achieved": gbs_schw, "peak": HBM_PEAK_GBS, "unit": "GB/s",
               "frac": gbs_schw / HBM_PEAK_GBS,
