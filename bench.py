@@ -564,6 +564,15 @@ def batch_bench(fc, args, count=None, line=True):
     torch.cuda.synchronize()
     wall = (time.perf_counter() - t0) / steps
     dof_iters = sum(p.n * r["iters"] for p, r in zip(pbs, res))
+    # HBM fraction against the summed algorithmic bytes: every member's
+    # iterations times the bytes of one of its iterations (the batch reads
+    # its block columns; symmetric storage of the local inverses)
+    moved = 0
+    for p, c, r in zip(pbs, pcs, res):
+        inf = dict(p.info(), lattice_columns=False)
+        moved += r["iters"] * iteration_bytes(inf, c.m, c.info()["n_blocks"],
+                                              c.m // inf["bsr_dim"])
+    gbs = moved / wall / 1e9
     return {
         "metric": METRIC + " (batched form)", "value": dof_iters / wall, "unit": "DOF·iter/s",
         "n_gpus": 1, "steps": steps, "warmup": warmup, "ms_per_step": wall * 1e3,
@@ -572,6 +581,10 @@ def batch_bench(fc, args, count=None, line=True):
         "config": {"workload": f"{len(descs)} uneven 2D/3D finite cell Poisson problems, "
                                f"p=1..4, alpha=1e-10, one batch",
                    "total_dofs": info["total_dofs"], "tol": args.tol},
+        "roofline": {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": gbs / HBM_PEAK_GBS, "bytes_per_solve": moved,
+                     "basis": "sum over members of iterations x bytes of one PCG iteration "
+                              "(matrix with block columns, symmetric local inverses, vectors)"},
         "converged": sum(r["status"] == "OK" for r in res),
         "iters_min": min(r["iters"] for r in res), "iters_max": max(r["iters"] for r in res),
         "setup_s": t_setup, "batch_create_autotune_s": t_tune,
