@@ -105,8 +105,8 @@ __device__ __forceinline__ double sum_partials(const double* part, int n,
 }
 
 // n / d with the multiplier of make_fastdiv
-__device__ __forceinline__ uint32_t fdiv(uint32_t n, const FastDiv f) {
-  const uint32_t t = __umulhi(n, f.m);
+__host__ __device__ __forceinline__ uint32_t fdiv(uint32_t n, const FastDiv f) {
+  const uint32_t t = (uint32_t)(((uint64_t)n * f.m) >> 32);   // v_mul_hi_u32 on the device
   return (t + ((n - t) >> f.s1)) >> f.s2;
 }
 
