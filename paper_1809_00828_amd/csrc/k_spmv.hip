@@ -76,7 +76,10 @@ __global__ __launch_bounds__(256, 5) void k_spmv_bsr(
   const int lane = threadIdx.x % G;
   double dot = 0.0;
   for (int64_t tile = t0 + j; tile < t1; tile += per) {
-    const int64_t idx = tile * RPW + threadIdx.x / G;
+    // one row per wave (G = 64): the row and everything derived from it are
+    // wave-uniform, so they are computed once per wave in scalar registers
+    const int64_t idx = tile * RPW + (G == 64 ? (int)__builtin_amdgcn_readfirstlane(threadIdx.x / G)
+                                              : (int)(threadIdx.x / G));
     if (idx >= n_rows) continue;
     const int64_t row = rows ? (int64_t)rows[idx] : idx;
     // on the lattice the row's start and length follow from its indices,
