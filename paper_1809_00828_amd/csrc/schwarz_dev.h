@@ -78,8 +78,9 @@ struct StageRows {
 // (half the load instructions of one entry per thread, and no idle lanes),
 // non-temporally, into LDS, and each thread then reads its own entry and
 // the rotated one back from LDS, so HBM and L2 see each stored entry exactly
-// once.  rB holds the block's gathered right-hand side (m entries, in LDS).
-// tile (16-byte aligned) holds kStageRows * m <= kStageRows * 256 entries,
+// once.  The next chunk's loads are issued before the current chunk is
+// summed.  rB holds the block's gathered right-hand side (m entries, in
+// LDS).  tile (16-byte aligned) holds kStageRows * m <= kStageRows * 256 entries,
 // as tile[kk * m + j] for stored row k0 + kk.
 template <typename T, typename RB>
 __device__ __forceinline__ double sym_block_staged_runs(const T* __restrict__ Qb, const RB* rB,
@@ -96,11 +97,10 @@ __device__ __forceinline__ double sym_block_staged_runs(const T* __restrict__ Qb
   const bool even = (m & 1) == 0;
   A acc0 = 0, acc1 = 0;
   int ip = i, im = i;
-  for (int k0 = 0; k0 <= h; k0 += kStageRows) {
-    const int rows = min(kStageRows, h + 1 - k0);
-    const int cnt = rows * m;                      // entries of this chunk
+  // chunk k0's pieces are loaded while chunk k0 - kStageRows is summed
+  auto load_chunk = [&](int k0, tv* v) {
+    const int cnt = min(kStageRows, h + 1 - k0) * m;
     const T* src = Qb + (int64_t)k0 * m;
-    tv v[kPer];
 #pragma unroll
     for (int u = 0; u < kPer; ++u) {
       const int e = (t + nt * u) * V;
@@ -111,6 +111,11 @@ __device__ __forceinline__ double sym_block_staged_runs(const T* __restrict__ Qb
         for (int c = 0; c < V; ++c) v[u][c] = e + c < cnt ? __builtin_nontemporal_load(src + e + c) : T(0);
       }
     }
+  };
+  tv v[kPer];
+  load_chunk(0, v);
+  for (int k0 = 0; k0 <= h; k0 += kStageRows) {
+    const int cnt = min(kStageRows, h + 1 - k0) * m;   // entries of this chunk
     __syncthreads();   // previous chunk's reads are done
 #pragma unroll
     for (int u = 0; u < kPer; ++u) {
@@ -118,6 +123,7 @@ __device__ __forceinline__ double sym_block_staged_runs(const T* __restrict__ Qb
       if (e < cnt) *reinterpret_cast<tva*>(tile + e) = v[u];   // the pad past cnt is never read
     }
     __syncthreads();
+    if (k0 + kStageRows <= h) load_chunk(k0 + kStageRows, v);
     if (act) {
 #pragma unroll
       for (int kk = 0; kk < kStageRows; ++kk) {
