@@ -452,6 +452,53 @@ def eta_sweep_bench(fc, args):
             "n_dofs": pb.n, "maxit": args.maxit, "sweep": rows}
 
 
+def small_bench(fc, seeds=range(10), reps=5):
+    """Config 1 (2-D disk Poisson, 16^2 cells, p = 2, about 1k unknowns) with
+    vertex-patch and element blocks, and config 3 (its precision forms), to
+    ||b - Ax|| / ||b|| <= 1e-10: latency-bound, so the record is microseconds
+    per iteration, from hipGraph-captured chunks and from direct launches
+    (the timing mode, with events), medians over the seeds."""
+    import statistics
+    import torch
+    import fcgen
+    rows = {}
+    for seed in seeds:
+        d = fcgen.disk_poisson_2d(seed)
+        pb = fc.Problem.setup(d)
+        b = torch.empty(pb.n, dtype=torch.float64, device="cuda")
+        pb.rhs(b)
+        x = torch.zeros_like(b)
+        runs = [("vertex_patch", "f64", False), ("vertex_patch", "f64", True),
+                ("element", "f64", False), ("element", "f64", True),
+                ("element", "ir_f32", False), ("element", "s_f32", False)]
+        pcs = {}
+        for kind, mode, timing in runs:
+            if kind not in pcs:
+                pcs[kind] = fc.Precond(pb, block_kind=kind,
+                                       store=fc.STORE_F64 | fc.STORE_F32 if kind == "element"
+                                       else fc.STORE_F64)
+            pc = pcs[kind]
+            best = None
+            for _ in range(reps + 1):
+                x.zero_()
+                info = fc.pcg_solve(pb, pc, b, x, tol=1e-10, stop="residual", mode=mode,
+                                    timing=timing)
+                us = info["ms_solve"] * 1e3 / max(1, info["iters"])
+                if best is None or us < best[0]:
+                    best = (us, info["iters"], info["status"])
+            key = f"{kind}/{mode}/{'direct' if timing else 'graph'}"
+            rows.setdefault(key, []).append(best)
+        del pcs, pb
+    out = {"workload": "2D finite cell Poisson, disk r=0.37 on 16^2 cells, p=2, alpha=1e-10 "
+                       "(1,089 unknowns), seeds 0-9, tol 1e-10",
+           "runs": {}}
+    for key, v in rows.items():
+        out["runs"][key] = {"us_per_iter_median": statistics.median(r[0] for r in v),
+                            "iters_median": statistics.median(r[1] for r in v),
+                            "all_ok": all(r[2] == "OK" for r in v)}
+    return out
+
+
 def eta_pair(fc, pb, b, args, t_f64, it_f64):
     """The paper's study of preconditioning only cut cells, at one point:
     blocks only for elements with eta_T <= 0.8 and diagonal scaling for
@@ -609,6 +656,8 @@ def main():
                     help="skip the mixed-precision forms comparison")
     ap.add_argument("--no-learned", action="store_true",
                     help="skip the learned coarse-correction comparison")
+    ap.add_argument("--small-configs", action="store_true",
+                    help="only the 2-D disk (configs 1 and 3) microseconds-per-iteration record")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the block-threshold, DA/S*/S and 32-member batch extras")
     ap.add_argument("--learned-train", type=int, default=8, help="training problems (48^3)")
@@ -662,6 +711,9 @@ def main():
         return
     if args.net_only:
         print(json.dumps(net_timing(fc)), flush=True)
+        return
+    if args.small_configs:
+        print(json.dumps(small_bench(fc)), flush=True)
         return
     if args.eta_sweep:
         print(json.dumps(eta_sweep_bench(fc, args)), flush=True)
@@ -783,6 +835,7 @@ def main():
         del pb
         out["compare"] = compare_bench(fc, args, alphas=[0.0], maxit=1500)
         out["batch"] = batch_bench(fc, args, count=32, line=False)
+        out["small"] = small_bench(fc)
     if not args.no_learned and not args.small:
         out["learned"] = learned_bench(fc, args)
     if not args.no_cpu_baseline:
