@@ -46,7 +46,26 @@ __device__ __forceinline__ T stream_load(const T* p) {
   else return *p;
 }
 
-// rows (may be null): the launch covers only these n_rows block rows
+// Sum over a wave with DPP moves (row shifts within rows of 16 lanes, then
+// row broadcasts): the total lands in lane 63, in a fixed order.
+template <int C, int RM>
+__device__ __forceinline__ double dpp64(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)b, C, RM, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), C, RM, 0xf, false);
+  return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+__device__ __forceinline__ double wave_sum_last(double v) {
+  v += dpp64<0x111, 0xf>(v);   // row_shr:1
+  v += dpp64<0x112, 0xf>(v);   // row_shr:2
+  v += dpp64<0x114, 0xf>(v);   // row_shr:4
+  v += dpp64<0x118, 0xf>(v);   // row_shr:8
+  v += dpp64<0x142, 0xa>(v);   // row_bcast:15 into rows 1 and 3
+  v += dpp64<0x143, 0xc>(v);   // row_bcast:31 into rows 2 and 3
+  return v;
+}
+
+// rows (may be null): the launch covers only these n_rows block rows// rows (may be null): the launch covers only these n_rows block rows
 // (ascending), the others of y are left alone.
 // kLat: columns computed from the lattice box (col is not read).
 // XT: type of x (FP32 for the FP32 rows of the mixed product, which round
@@ -180,14 +199,17 @@ __global__ __launch_bounds__(256, 5) void k_spmv_bsr(
               accf[i] = fmaf((float)a[u][i * B + jj], (float)xv[u][jj], accf[i]);
           }
     }
+    constexpr int kOut = G == 64 ? 63 : 0;   // the lane that holds the row's sums
 #pragma unroll
     for (int i = 0; i < B; ++i) {
-      if constexpr (sizeof(T) == 8)
+      if constexpr (G == 64)
+        acc[i] = wave_sum_last(sizeof(T) == 8 ? acc[i] : (double)accf[i]);
+      else if constexpr (sizeof(T) == 8)
         acc[i] = group_sum<G>(acc[i]);
       else
         acc[i] = (double)group_sum<G>(accf[i]);
     }
-    if (lane == 0) {
+    if (lane == kOut) {
 #pragma unroll
       for (int i = 0; i < B; ++i) {
         y[row * B + i] = acc[i];
