@@ -65,7 +65,7 @@ __device__ __forceinline__ double wave_sum_last(double v) {
   return v;
 }
 
-// rows (may be null): the launch covers only these n_rows block rows// rows (may be null): the launch covers only these n_rows block rows
+// rows (may be null): the launch covers only these n_rows block rows
 // (ascending), the others of y are left alone.
 // kLat: columns computed from the lattice box (col is not read).
 // XT: type of x (FP32 for the FP32 rows of the mixed product, which round
@@ -97,8 +97,9 @@ __global__ __launch_bounds__(256, 5) void k_spmv_bsr(
   for (int64_t tile = t0 + j; tile < t1; tile += per) {
     // one row per wave (G = 64): the row and everything derived from it are
     // wave-uniform, so they are computed once per wave in scalar registers
-    const int64_t idx = tile * RPW + (G == 64 ? (int)__builtin_amdgcn_readfirstlane(threadIdx.x / G)
-                                              : (int)(threadIdx.x / G));
+    const int wrow = G == 64 ? (int)__builtin_amdgcn_readfirstlane(threadIdx.x / G)
+                             : (int)(threadIdx.x / G);
+    const int64_t idx = tile * RPW + wrow;
     if (idx >= n_rows) continue;
     const int64_t row = rows ? (int64_t)rows[idx] : idx;
     // on the lattice the row's start and length follow from its indices,
