@@ -483,8 +483,9 @@ static fc_status precond_build_body(fc_problem pb, const fc_precond_opts* opts, 
 
   if (nb > 0) {
     FC_HIP(launch_block_extract(*pb, *pc, s));
-    if (m <= 64) {
-      // every block by the eigen-decomposition; in LDS when it fits
+    if (m <= 64 && !pc->stabilize) {
+      // the plain inverse (S*): every block by the eigen-decomposition with
+      // every nonzero eigenvalue inverted; in LDS when it fits
       const int64_t chunk = jacobi_needs_work(m) ? 16384 : nb;
       double* work = nullptr;
       if (jacobi_needs_work(m)) FC_TRY(dev_alloc(&work, (size_t)std::min(chunk, nb) * 2 * m * m));
@@ -503,7 +504,13 @@ static fc_status precond_build_body(fc_problem pb, const fc_precond_opts* opts, 
       FC_HIP(e2);
       pc->n_eig = nb;
     } else {
-      FC_HIP(launch_sweep(*pc, d_flag, s));
+      // certified direct inverses; the blocks whose certificate fails (some
+      // eigenvalue may be near the threshold of Eq. 11) keep A_B and are
+      // eigen-decomposed below
+      if (m <= 64)
+        FC_HIP(launch_sweep_small(*pc, d_flag, s));
+      else
+        FC_HIP(launch_sweep(*pc, d_flag, s));
       std::vector<int32_t> flag(nb);
       FC_HIP(hipMemcpyAsync(flag.data(), d_flag, nb * sizeof(int32_t), hipMemcpyDeviceToHost, s));
       FC_HIP(hipStreamSynchronize(s));

@@ -8,6 +8,8 @@ hipError_t launch_jacobi(fc_precond_s& pc, const int32_t* sel, int64_t count,
 // true when the Jacobi eigen path keeps its blocks in global memory
 bool jacobi_needs_work(int m);
 hipError_t launch_sweep(fc_precond_s& pc, int32_t* need_eig, hipStream_t s);
+// the same certified sweep for m <= 64 (one wave per block)
+hipError_t launch_sweep_small(fc_precond_s& pc, int32_t* need_eig, hipStream_t s);
 // Scaled Cholesky factors of the local inverses in BF16 into pc.Lbf (needs
 // pc.isd); with `unsafe` instead only flag the blocks whose FP32-rounded
 // scaled inverse is not safely positive definite

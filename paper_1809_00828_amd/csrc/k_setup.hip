@@ -7,17 +7,20 @@
 //   diagonal scaling      1/A_ll for every unknown whose entry S_ll is zero
 //
 // Local inverses are computed in one of two ways, both FP64:
-//  * m <= 64: cyclic two-sided Jacobi eigen-decomposition with the block
-//    and its eigenvectors resident in LDS (parallel round-robin ordering,
-//    m/2 disjoint rotations per step), then P_B = V diag(1/lambda_+) V^T.
-//  * 64 < m <= 192: a certified direct inverse.  The block lives in the
-//    registers of a 1024-thread workgroup (a 32 x 32 grid of tiles) and is
-//    inverted by the symmetric sweep operator; the result is accepted only
-//    when every pivot is positive and trace(P) * ||A_B||_inf * eps * 4 < 1.
-//    Since lambda_min >= 1/trace(A_B^-1) and lambda_max <= ||A_B||_inf,
-//    that certificate proves no eigenvalue lies within a factor 4 of the
-//    threshold, so the pseudo-inverse equals the inverse.  Blocks that fail
-//    it take the Jacobi eigen-decomposition with the block in global memory.
+//  * a certified direct inverse.  The block is inverted by the symmetric
+//    sweep operator in registers: one wave per block with a column per
+//    lane for m <= 64, a 1024-thread workgroup (a 32 x 32 grid of tiles)
+//    for 64 < m <= 192.  The result is accepted only when every pivot is
+//    positive and trace(P) * ||A_B||_inf * eps * 4 < 1.  Since
+//    lambda_min >= 1/trace(A_B^-1) and lambda_max <= ||A_B||_inf, that
+//    certificate proves no eigenvalue lies within a factor 4 of the
+//    threshold, so the pseudo-inverse equals the inverse.
+//  * cyclic two-sided Jacobi eigen-decomposition (parallel round-robin
+//    ordering, m/2 disjoint rotations per step), then
+//    P_B = V diag(1/lambda_+) V^T: for the blocks that fail the
+//    certificate, and for every block of the unstabilised inverse when
+//    m <= 64.  The block and its eigenvectors stay in LDS when they fit,
+//    else in global memory.
 #include "dev_common.h"
 #include "k_setup.h"
 
@@ -298,6 +301,80 @@ __global__ __launch_bounds__(1024) void k_sweep_inverse(
   if (tid == 0) need_eig[blk] = 0;
 }
 
+// The same certified sweep for small blocks (m <= KM <= 64), one wave per
+// block, four blocks per workgroup: lane j holds column j of the block in
+// registers, and the pivot row (by symmetry the pivot column) is read
+// across lanes with readlane, so no LDS and no barrier is needed.  Blocks
+// that fail a pivot or the certificate are flagged in need_eig and left
+// unchanged (they still hold A_B) for the eigen-decomposition.
+__device__ __forceinline__ double readlane_f64(double v, int lane) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)b, lane);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
+  return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
+template <int KM>
+__global__ __launch_bounds__(256) void k_sweep_small(double* __restrict__ P, int m,
+                                                     int64_t n_blocks, double eps,
+                                                     int32_t* __restrict__ need_eig) {
+  const int64_t blk = (int64_t)blockIdx.x * 4 + threadIdx.x / 64;
+  if (blk >= n_blocks) return;   // the whole wave
+  const int j = threadIdx.x % 64;
+  double* Ab = P + blk * (int64_t)m * m;
+  double a[KM];
+#pragma unroll
+  for (int i = 0; i < KM; ++i) a[i] = (i < m && j < m) ? Ab[(int64_t)i * m + j] : 0.0;
+  // ||A_B||_inf: the column sums equal the row sums of the symmetric block
+  double cs = 0.0;
+#pragma unroll
+  for (int i = 0; i < KM; ++i) cs += fabs(a[i]);
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) cs = fmax(cs, __shfl_xor(cs, o, 64));
+  const double anorm = cs;
+  // fully unrolled (guards instead of breaks), so a[] stays in registers
+  bool bad = false;
+#pragma unroll
+  for (int k = 0; k < KM; ++k) {
+    if (k < m && !bad) {
+      const double d = readlane_f64(a[k], k);
+      bad = !(d > 0.0);   // uniform: every lane read the same pivot
+      if (!bad) {
+        const double rinv = 1.0 / d;
+        const double bj = a[k];   // row k, column j
+#pragma unroll
+        for (int i = 0; i < KM; ++i) {
+          if (i != k && i < m) {
+            const double bi = readlane_f64(a[k], i);   // row k, column i = column k, row i
+            a[i] = (j == k) ? bi * rinv : a[i] - (bi * bj) * rinv;
+          }
+        }
+        a[k] = (j == k) ? -rinv : bj * rinv;
+      }
+    }
+  }
+  if (!bad) {
+    // trace of A_B^-1 = minus the trace of the swept block
+    double tr = 0.0;
+#pragma unroll
+    for (int i = 0; i < KM; ++i)
+      if (i == j && i < m) tr = -a[i];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) tr += __shfl_xor(tr, o, 64);
+    bad = !(tr > 0.0 && tr * anorm * eps * 4.0 < 1.0);
+  }
+  if (bad) {
+    if (j == 0) need_eig[blk] = 1;
+    return;
+  }
+  if (j < m) {
+#pragma unroll
+    for (int i = 0; i < KM; ++i)
+      if (i < m) Ab[(int64_t)i * m + j] = -a[i];
+  }
+  if (j == 0) need_eig[blk] = 0;
+}
+
 // ------------------------------------------- factored low-precision copy
 // P_B = L L^T (lower Cholesky factor of the FP64 local inverse; a pivot at
 // or below 1e-14 * max diag(P_B) zeroes its column, which is exact for the
@@ -545,6 +622,20 @@ hipError_t launch_sweep(fc_precond_s& pc, int32_t* need_eig, hipStream_t s) {
     hipLaunchKernelGGL(k_sweep_inverse<5>, g, b, 0, s, pc.P, m, pc.eps, pc.stabilize, need_eig);
   else
     hipLaunchKernelGGL(k_sweep_inverse<6>, g, b, 0, s, pc.P, m, pc.eps, pc.stabilize, need_eig);
+  return hipGetLastError();
+}
+
+hipError_t launch_sweep_small(fc_precond_s& pc, int32_t* need_eig, hipStream_t s) {
+  const int m = pc.m;
+  const dim3 g((unsigned)((pc.n_blocks + 3) / 4)), b(256);
+  if (m <= 16)
+    hipLaunchKernelGGL(k_sweep_small<16>, g, b, 0, s, pc.P, m, pc.n_blocks, pc.eps, need_eig);
+  else if (m <= 32)
+    hipLaunchKernelGGL(k_sweep_small<32>, g, b, 0, s, pc.P, m, pc.n_blocks, pc.eps, need_eig);
+  else if (m <= 64)
+    hipLaunchKernelGGL(k_sweep_small<64>, g, b, 0, s, pc.P, m, pc.n_blocks, pc.eps, need_eig);
+  else
+    return hipErrorInvalidValue;
   return hipGetLastError();
 }
 
