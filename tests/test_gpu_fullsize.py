@@ -108,6 +108,8 @@ def test_spmv_sampled_rows(torch, lib):
     N1 = wl.n1
     nodes = [tuple(int(v) for v in rng.integers(0, N1, size=3)) for _ in range(12)]
     nodes += [(0, 0, 0), (N1 - 1, N1 - 1, N1 - 1), (N1 // 2, N1 // 2, 0), (5, 7, N1 - 1)]
+    # rows interior to a cell along every direction (4 x 4 x 4 blocks each)
+    nodes += [(1, 1, 1), (2, 1, 1), (49, 50, 52), (50, 50, 52), (N1 - 3, N1 - 2, N1 - 2)]
     for g in nodes:
         node = g[0] + N1 * (g[1] + N1 * g[2])
         dofs = [wl.bd * node + c for c in range(wl.bd)]
