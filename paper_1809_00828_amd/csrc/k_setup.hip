@@ -9,7 +9,7 @@
 // Local inverses are computed in one of two ways, both FP64:
 //  * a certified direct inverse.  The block is inverted by the symmetric
 //    sweep operator in registers: one wave per block with a column per
-//    lane for m <= 64, a 1024-thread workgroup (a 32 x 32 grid of tiles)
+//    lane for m <= 64, a 512-thread workgroup (a 16 x 32 grid of tiles)
 //    for 64 < m <= 192.  The result is accepted only when every pivot is
 //    positive and trace(P) * ||A_B||_inf * eps * 4 < 1.  Since
 //    lambda_min >= 1/trace(A_B^-1) and lambda_max <= ||A_B||_inf, that
@@ -198,29 +198,32 @@ __global__ __launch_bounds__(256) void k_jacobi_pinv(
 
 // ------------------------------------------------- certified sweep inverse
 // Sweep operator on a symmetric matrix: sweeping every pivot turns A into
-// -A^{-1}.  Thread (ti, tj) of a 32 x 32 grid holds the T x T tile at rows
-// ti*T.., columns tj*T..; pivot row k is broadcast through LDS.
+// -A^{-1}.  Thread (ti, tj) of a 16 x 32 grid holds the 2T x T tile at rows
+// ti*2T.., columns tj*T..; pivot row k is broadcast through LDS.  512
+// threads leave each wave 256 registers: a 12 x 6 FP64 tile (m = 192) then
+// stays in registers, where the 6 x 6 tiles of a 1024-thread grid spilled.
 template <int T>
-__global__ __launch_bounds__(1024) void k_sweep_inverse(
+__global__ __launch_bounds__(512) void k_sweep_inverse(
     double* __restrict__ P, int m, double eps, int stabilize,
     int32_t* __restrict__ need_eig) {
   __shared__ double rowbuf[2][32 * T];
   __shared__ double red[16];
   const int64_t blk = blockIdx.x;
   double* Ab = P + blk * (int64_t)m * m;
+  constexpr int TR = 2 * T;   // rows per thread
   const int tid = threadIdx.x, ti = tid / 32, tj = tid % 32;
-  double a[T][T];
+  double a[TR][T];
 #pragma unroll
-  for (int r = 0; r < T; ++r)
+  for (int r = 0; r < TR; ++r)
 #pragma unroll
     for (int c = 0; c < T; ++c) {
-      const int i = ti * T + r, j = tj * T + c;
+      const int i = ti * TR + r, j = tj * T + c;
       a[r][c] = (i < m && j < m) ? Ab[(int64_t)i * m + j] : 0.0;
     }
   // ||A_B||_inf: row sums over the 32 threads of a tile row, then max
   double rmax = 0.0;
 #pragma unroll
-  for (int r = 0; r < T; ++r) {
+  for (int r = 0; r < TR; ++r) {
     double s = 0.0;
 #pragma unroll
     for (int c = 0; c < T; ++c) s += fabs(a[r][c]);
@@ -234,7 +237,7 @@ __global__ __launch_bounds__(1024) void k_sweep_inverse(
     if (tid % 64 == 0) red[tid / 64] = v;
     __syncthreads();
     v = 0.0;
-    for (int w = 0; w < 16; ++w) v = fmax(v, red[w]);
+    for (int w = 0; w < (int)(blockDim.x / 64); ++w) v = fmax(v, red[w]);
     rmax = v;
     __syncthreads();
   }
@@ -242,10 +245,10 @@ __global__ __launch_bounds__(1024) void k_sweep_inverse(
   bool bad = false;
   for (int k = 0; k < m; ++k) {
     double* buf = rowbuf[k & 1];
-    if (ti == k / T) {
-      const int r = k % T;
+    if (ti == k / TR) {
+      const int r = k % TR;
 #pragma unroll
-      for (int rr = 0; rr < T; ++rr)
+      for (int rr = 0; rr < TR; ++rr)
         if (rr == r) {
 #pragma unroll
           for (int c = 0; c < T; ++c) buf[tj * T + c] = a[rr][c];
@@ -258,19 +261,40 @@ __global__ __launch_bounds__(1024) void k_sweep_inverse(
       break;
     }
     const double rinv = 1.0 / d;
+    // rank-one update with u = column k / pivot, then row k and column k
+    // of the swept matrix overwrite their entries
+    double u[TR], bj[T];
 #pragma unroll
-    for (int r = 0; r < T; ++r) {
-      const int i = ti * T + r;
-      const double bi = buf[i < m ? i : 0];
+    for (int r = 0; r < TR; ++r) {
+      const int i = ti * TR + r;
+      u[r] = buf[i < m ? i : 0] * rinv;
+    }
 #pragma unroll
-      for (int c = 0; c < T; ++c) {
-        const int j = tj * T + c;
-        const double bj = buf[j < m ? j : 0];
-        if (i == k && j == k) a[r][c] = -rinv;
-        else if (i == k) a[r][c] = bj * rinv;
-        else if (j == k) a[r][c] = bi * rinv;
-        else a[r][c] -= (bi * bj) * rinv;
-      }
+    for (int c = 0; c < T; ++c) {
+      const int j = tj * T + c;
+      bj[c] = buf[j < m ? j : 0];
+    }
+#pragma unroll
+    for (int r = 0; r < TR; ++r)
+#pragma unroll
+      for (int c = 0; c < T; ++c) a[r][c] = fma(-u[r], bj[c], a[r][c]);
+    if (ti == k / TR) {
+      const int rk = k % TR;
+#pragma unroll
+      for (int r = 0; r < TR; ++r)
+        if (r == rk) {
+#pragma unroll
+          for (int c = 0; c < T; ++c) a[r][c] = bj[c] * rinv;
+        }
+    }
+    if (tj == k / T) {
+      const int ck = k % T;
+#pragma unroll
+      for (int c = 0; c < T; ++c)
+        if (c == ck) {
+#pragma unroll
+          for (int r = 0; r < TR; ++r) a[r][c] = (ti * TR + r == k) ? -rinv : u[r];
+        }
     }
   }
   if (bad) {
@@ -279,10 +303,10 @@ __global__ __launch_bounds__(1024) void k_sweep_inverse(
   }
   double tr = 0.0;
 #pragma unroll
-  for (int r = 0; r < T; ++r)
+  for (int r = 0; r < TR; ++r)
 #pragma unroll
     for (int c = 0; c < T; ++c) {
-      const int i = ti * T + r, j = tj * T + c;
+      const int i = ti * TR + r, j = tj * T + c;
       if (i == j && i < m) tr -= a[r][c];
     }
   tr = block_sum(tr, red);
@@ -292,10 +316,10 @@ __global__ __launch_bounds__(1024) void k_sweep_inverse(
     return;
   }
 #pragma unroll
-  for (int r = 0; r < T; ++r)
+  for (int r = 0; r < TR; ++r)
 #pragma unroll
     for (int c = 0; c < T; ++c) {
-      const int i = ti * T + r, j = tj * T + c;
+      const int i = ti * TR + r, j = tj * T + c;
       if (i < m && j < m) Ab[(int64_t)i * m + j] = -a[r][c];
     }
   if (tid == 0) need_eig[blk] = 0;
@@ -613,7 +637,7 @@ bool jacobi_needs_work(int m) {
 
 hipError_t launch_sweep(fc_precond_s& pc, int32_t* need_eig, hipStream_t s) {
   const int m = pc.m;
-  dim3 g((unsigned)pc.n_blocks), b(1024);
+  dim3 g((unsigned)pc.n_blocks), b(512);
   if (m <= 96)
     hipLaunchKernelGGL(k_sweep_inverse<3>, g, b, 0, s, pc.P, m, pc.eps, pc.stabilize, need_eig);
   else if (m <= 128)
