@@ -200,8 +200,9 @@ __global__ __launch_bounds__(256) void k_jacobi_pinv(
 // Sweep operator on a symmetric matrix: sweeping every pivot turns A into
 // -A^{-1}.  Thread (ti, tj) of a 16 x 32 grid holds the 2T x T tile at rows
 // ti*2T.., columns tj*T..; pivot row k is broadcast through LDS.  512
-// threads leave each wave 256 registers: a 12 x 6 FP64 tile (m = 192) then
-// stays in registers, where the 6 x 6 tiles of a 1024-thread grid spilled.
+// threads leave each wave 256 registers, so a 12 x 6 FP64 tile (m = 192)
+// stays in registers (with 1024 threads, 128 registers per wave, the 6 x 6
+// tiles of the same block spill).
 template <int T>
 __global__ __launch_bounds__(512) void k_sweep_inverse(
     double* __restrict__ P, int m, double eps, int stabilize,
