@@ -478,21 +478,32 @@ __global__ __launch_bounds__(GRID * GRID) void k_chol_pack(
     bad = bad || !live;
     const double lkk = live ? sqrt(d) : 0.0;
     const double rl = live ? 1.0 / lkk : 0.0;
+    // L[i][k] below the pivot (zero elsewhere, so the rank-one update below
+    // leaves every entry outside the trailing block as it is), then column
+    // k of L.  Entries above the diagonal are never stored or read again.
+    double li[T], lj[T];
 #pragma unroll
     for (int r = 0; r < T; ++r) {
       const int i = ti * T + r;
-      if (i < k || i >= m) continue;
-      const double li = (i == k) ? lkk : buf[i] * rl;
+      li[r] = (i > k && i < m) ? buf[i] * rl : 0.0;
+    }
 #pragma unroll
-      for (int c = 0; c < T; ++c) {
-        const int j = tj * T + c;
-        if (j < k || j >= m) continue;
-        if (j == k) {
-          a[r][c] = li;                       // L[i][k]
-        } else if (i > k) {
-          a[r][c] -= li * (buf[j] * rl);      // trailing update with L[j][k]
+    for (int c = 0; c < T; ++c) {
+      const int j = tj * T + c;
+      lj[c] = (j > k && j < m) ? buf[j] * rl : 0.0;
+    }
+#pragma unroll
+    for (int r = 0; r < T; ++r)
+#pragma unroll
+      for (int c = 0; c < T; ++c) a[r][c] = fma(-li[r], lj[c], a[r][c]);
+    if (tj == k / T) {
+      const int ck = k % T;
+#pragma unroll
+      for (int c = 0; c < T; ++c)
+        if (c == ck) {
+#pragma unroll
+          for (int r = 0; r < T; ++r) a[r][c] = (ti * T + r == k) ? lkk : li[r];
         }
-      }
     }
   }
   __syncthreads();
